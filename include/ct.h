@@ -1,0 +1,205 @@
+/*
+ * ct.h -- C ABI of the MI355X Compact-Table (CT) propagation library.
+ *
+ * Method: Compact-Table propagation for the positive table constraint,
+ * after E. Santi, F. Tardivo, A. Dovier, A. Formisano, "GPU Accelerated
+ * Compact-Table Propagation" (arXiv 2507.18413).  Definitions of supports,
+ * currTable and valid tuples: Sec. 2; enforceGAC / updateTable /
+ * filterDomains: Alg. 1-3; constructor check and indexing: Sec. 3.
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * Tables.  A table has `arity` columns x_0..x_{n-1} and `n_tuples` rows; the
+ * tuples are int32, row-major (`tuples[j * arity + i]` = tau_j[i]).  Column i
+ * has the initial domain [dom_lo[i], dom_lo[i] + dom_size[i]).  Duplicate
+ * tuples are kept (each has its own currTable bit); a tuple holding a value
+ * outside an initial domain is never valid.
+ *
+ * Domain bitmaps.  Variable i owns ceil(dom_size[i] / 64) consecutive uint64
+ * words starting at word dom_off[i] = sum of the word counts of variables
+ * 0..i-1; value v is bit (v - dom_lo[i]) % 64 of word
+ * dom_off[i] + (v - dom_lo[i]) / 64, least significant bit first, 1 = present.
+ * Bits at or beyond dom_size[i] must be zero ("stray bits").  D is the total
+ * word count.
+ *
+ * currTable.  ceil(n_tuples / 64) uint64 words; tuple j is bit j % 64 of word
+ * j / 64; bit set = the tuple is valid under the current domains (Sec. 2).
+ * Tail bits past n_tuples are zero.
+ *
+ * Slots.  A table owns one or more independent reversible propagator states
+ * ("slots", e.g. one per search or search node).  Slot 0 exists after
+ * ct_create; every slot starts as a copy of the root state (the state after
+ * the root propagation in ct_create).
+ *
+ * Status codes: CT_OK, CT_FAIL (domain wipe-out: no valid tuple, Alg. 1 line
+ * 5), or a negative error.  No call throws; after an error ct_last_error()
+ * returns a message for the calling thread.  A ct_table may be used by one
+ * thread at a time; distinct tables are independent.
+ */
+#ifndef CT_H
+#define CT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define CT_OK 0
+#define CT_FAIL 1
+#define CT_E_INVALID (-1)    /* malformed argument or stray domain bits */
+#define CT_E_NOT_SUBSET (-2) /* dom_in holds a value the slot's domains lack */
+#define CT_E_STATE (-3)      /* slot failed (only pop allowed) / pop at depth 0 */
+#define CT_E_NOMEM (-4)      /* device or host allocation, trail or depth capacity */
+#define CT_E_DEVICE (-5)     /* HIP error or device-side timeout; handle is poisoned */
+
+/* update branch policy (Alg. 2 line 3): AUTO takes the incremental branch
+ * (OR over the removed values, complemented) iff |Delta_i| < |dom(x_i)|,
+ * else the reset branch (OR over the remaining values).  Both give the same
+ * currTable; the forced modes exist for testing and ablation. */
+#define CT_BRANCH_AUTO 0
+#define CT_BRANCH_RESET 1
+#define CT_BRANCH_INCREMENTAL 2
+
+typedef struct ct_table ct_table;
+
+typedef struct {
+    int32_t branch_policy; /* CT_BRANCH_*; default AUTO */
+    int32_t max_depth;     /* push levels per slot; default 256 */
+} ct_config;
+
+typedef struct {
+    int32_t n_vars;
+    int32_t D;          /* domain bitmap words */
+    int64_t W;          /* currTable words = ceil(n_tuples / 64) */
+    int64_t n_tuples;
+    int32_t rows;       /* support rows = sum of dom_size */
+    int32_t n_slots;
+    int32_t granules;   /* 64-word groups of currTable tracked by the sparse index */
+    int32_t root_failed;/* 1 if the root propagation found no valid tuple */
+} ct_layout_info;
+
+/* Cumulative per-slot work counters (never reset; take differences). */
+typedef struct {
+    int64_t jobs;             /* propagate jobs executed */
+    int64_t granules_in;      /* sum over jobs of active granules at entry */
+    int64_t rows_or;          /* support rows OR-ed by updateTable (sum of k_i) */
+    int64_t granule_rows;     /* granule x row loads issued by updateTable */
+    int64_t trail_granules;   /* granules saved on the trail */
+    int64_t residue_checks;   /* values tested by filterDomains */
+    int64_t residue_misses;   /* of those, residue word no longer intersecting */
+    int64_t scan_granules;    /* granules scanned after residue misses */
+} ct_stats;
+
+/*
+ * ct_create -- copy the tuples to the device, build the support bitsets
+ * (supports[x_i, v] bit j = 1 iff tau_j[i] = v, Sec. 2) and run the root
+ * propagation: every variable takes the reset branch over its initial domain,
+ * then every non-singleton variable is filtered (the constructor's check of
+ * Sec. 3, read as root GAC).  init_dom (host, nullable) restricts the initial
+ * domains; NULL = full intervals.  cfg is nullable.  All inputs are host
+ * pointers owned by the caller and not retained.
+ * Returns CT_OK, or CT_FAIL with *out valid but its root state failed, or
+ * CT_E_INVALID (arity < 1 or > 256, n_tuples < 0, dom_size < 1, more than
+ * 16384 support rows, stray init_dom bits), CT_E_NOMEM, CT_E_DEVICE with
+ * *out = NULL.
+ */
+int ct_create(const int32_t *tuples, int64_t n_tuples, int32_t arity, const int32_t *dom_lo,
+              const int32_t *dom_size, const uint64_t *init_dom, const ct_config *cfg,
+              ct_table **out);
+
+/* Frees every device and host resource of the table; NULL is ignored. */
+void ct_destroy(ct_table *t);
+
+/* Sizes of the table; dom_off (host, nullable, n_vars entries) receives the
+ * first bitmap word of every variable. */
+int ct_layout(const ct_table *t, ct_layout_info *info, int32_t *dom_off);
+
+/* Copies n_rows support rows starting at row_begin (row of value v of x_i =
+ * sum_{k<i} dom_size[k] + v - dom_lo[i], the supportJmp / variablesOffsets
+ * indexing of Sec. 3) to host memory, W words each. */
+int ct_get_supports(ct_table *t, int32_t row_begin, int32_t n_rows, uint64_t *out);
+
+/*
+ * ct_propagate / ct_propagate_slot -- one call of enforceGAC (Alg. 1): Delta
+ * and s_val from the slot's last domains, updateTable (Alg. 2) on the device,
+ * fail if currTable = 0, filterDomains (Alg. 3) with residues.  Host pointers,
+ * synchronous.  dom_in (D words) must be a subset of the slot's current
+ * domains (the dom_out of its previous call, or the root domains); dom_out
+ * (D words, may alias dom_in) receives the pruned domains; ct_out (nullable,
+ * W words) receives currTable; st (nullable) receives the slot's cumulative
+ * counters after the call.
+ * CT_OK: dom_out = GAC domains, ct_out = exactly the tuples valid under them.
+ * CT_FAIL: no valid tuple; dom_out untouched, ct_out zeros; the slot is
+ *   failed until popped.
+ * CT_E_NOT_SUBSET / CT_E_INVALID (stray bits) / CT_E_STATE (failed slot):
+ *   nothing changes.  CT_E_DEVICE: the handle is poisoned.
+ */
+int ct_propagate(ct_table *t, const uint64_t *dom_in, uint64_t *dom_out, uint64_t *ct_out,
+                 ct_stats *st);
+int ct_propagate_slot(ct_table *t, int32_t slot, const uint64_t *dom_in, uint64_t *dom_out,
+                      uint64_t *ct_out, ct_stats *st);
+
+/*
+ * ct_push / ct_pop -- backtracking.  push records a level; pop restores the
+ * slot's currTable, domains and failed flag exactly as they were at the
+ * matching push.  push on a failed slot -> CT_E_STATE; push beyond max_depth
+ * -> CT_E_NOMEM; pop at depth 0 -> CT_E_STATE.  Both are cheap host calls;
+ * the device work is folded into the slot's next device operation.
+ */
+int ct_push(ct_table *t);
+int ct_pop(ct_table *t);
+int ct_push_slot(ct_table *t, int32_t slot);
+int ct_pop_slot(ct_table *t, int32_t slot);
+
+/* Current domains (D words) and currTable (W words) of a slot, host
+ * pointers, both nullable. */
+int ct_get_state(ct_table *t, int32_t slot, uint64_t *dom_out, uint64_t *ct_out);
+
+/* Adds n slots, each a copy of the root state with room for max_depth push
+ * levels (negative = the table's default; 0 = no levels, for slots that are
+ * only reset by CT_JOB_FROM_ROOT jobs or never pushed).  Synchronous.
+ * *first_slot receives the first new id. */
+int ct_slots_alloc(ct_table *t, int32_t n, int32_t max_depth, int32_t *first_slot);
+
+/* Cumulative counters of a slot (host pointer). */
+int ct_slot_stats(ct_table *t, int32_t slot, ct_stats *st);
+
+/* ------------------------------------------------------------------------
+ * Batched propagation (device pointers, asynchronous)
+ * --------------------------------------------------------------------- */
+#define CT_JOB_PROPAGATE 1u /* run enforceGAC after the pops and pushes */
+#define CT_JOB_FROM_ROOT 2u /* reset the slot to the root state (depth 0) first */
+
+typedef struct {
+    ct_table *table;
+    int32_t slot;
+    uint32_t flags;      /* CT_JOB_* */
+    int32_t n_pop;       /* levels popped first (<= the slot's depth) */
+    int32_t n_push;      /* levels pushed after the pops */
+    const uint64_t *dom_in; /* device, D words of the table (PROPAGATE) */
+    uint64_t *dom_out;      /* device, D words (PROPAGATE; may alias dom_in) */
+    uint64_t *ct_out;       /* device, W words, nullable */
+} ct_job;
+
+/*
+ * ct_propagate_batch -- runs every job in one persistent launch on `stream`
+ * (a hipStream_t; NULL = the null stream) driven by a device work queue.
+ * Each job's result equals that of the same pops, pushes and ct_propagate on
+ * its slot alone.  status_dev (device, n_jobs int32) receives each job's
+ * status (CT_OK, CT_FAIL, CT_E_NOT_SUBSET, CT_E_INVALID, CT_E_STATE,
+ * CT_E_NOMEM).  Returns immediately after queueing; CT_E_INVALID for a
+ * malformed batch (two jobs on one slot, pop below depth 0, FROM_ROOT with
+ * pops or pushes), CT_E_NOMEM (push beyond max_depth).  In a batch a push on
+ * a failed slot is allowed (the level records the failed flag).  The tables
+ * must not be used from another stream until the batch completes.
+ */
+int ct_propagate_batch(const ct_job *jobs, int32_t n_jobs, void *stream, int32_t *status_dev);
+
+/* Thread-local message of the last error ("" if none). */
+const char *ct_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CT_H */

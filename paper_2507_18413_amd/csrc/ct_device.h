@@ -1,0 +1,128 @@
+// ct_device.h -- device-side data layout of the CT library (internal).
+//
+// Shared by the kernels (ct_kernels.hip) and the host runtime (ct_runtime.cpp);
+// never by the oracle.
+//
+// Reversible sparse bitset for currTable, MI355X form.  The paper keeps a
+// dense currTable (Sec. 3); the CT algorithm it builds on tracks the non-zero
+// words in an index list so that zero words are skipped.  Here the unit of the
+// index is a *granule* of 64 consecutive uint64 words -- one word per lane of
+// a 64-wide wavefront -- so that every load of a granule is one coalesced
+// 512-byte access:
+//   ct[stride]             dense words, exact: words of inactive granules are 0
+//   idx[2][nGran]          two permutations of the granule ids (ping-pong);
+//                          idx[cur][0..limit) are the granules with a non-zero
+//                          word.  A propagation writes the stable partition of
+//                          idx[cur][0..limit) (survivors first) into the other
+//                          buffer and copies the tail, so idx[cur][0..L) holds
+//                          the same *set* for every earlier limit L: restoring
+//                          `limit` on backtrack restores the set.
+//   stamp[nGran]           serial of the level in which the granule was last
+//                          saved on the trail (first write per level only)
+//   trail                  (granule, old stamp) headers + 64 old words each
+//   levels[maxDepth]       trail top, limit, failed, serial at each push
+#pragma once
+#include <stdint.h>
+
+namespace ctk {
+
+constexpr int WAVE = 64;
+constexpr int GW = 64;             // words per granule
+constexpr int BLOCK = 256;         // threads per workgroup of the propagate kernel
+constexpr int WAVES = BLOCK / WAVE;
+constexpr int MAX_ARITY = 256;
+constexpr int MAX_ROWS = 16384;    // support rows per table (row lists kept in LDS)
+constexpr int MAX_D = 1024;        // domain words per table kept in LDS
+constexpr int MAX_GRAN = 8192;     // granules per table (partition done in LDS)
+constexpr int INLINE_WORDS = 64;   // dom_in words carried in kernel arguments
+
+// status codes (same values as the public header)
+constexpr int ST_OK = 0, ST_FAIL = 1, ST_INVALID = -1, ST_NOT_SUBSET = -2, ST_STATE = -3,
+              ST_NOMEM = -4;
+
+// job flags
+constexpr uint32_t JF_PROPAGATE = 1u;
+constexpr uint32_t JF_FROM_ROOT = 2u;
+constexpr uint32_t JF_ROOT = 4u;      // creation: every variable takes the reset branch
+constexpr uint32_t JF_INLINE_DOM = 8u;
+
+struct VarDesc {
+  int32_t rowStart, dsize, domOff, domWords;
+};
+
+struct TabDesc {
+  int32_t n, rows, D, nGran;
+  int64_t W, stride;          // stride = nGran * 64 words per support row
+  const uint64_t* S;          // rows x stride
+  const VarDesc* vars;        // n
+  const int32_t* wordVar;     // D: variable owning each domain word
+  // root state, read-only after creation
+  const uint64_t* ct0;
+  const int32_t* idx0;
+  const uint64_t* dom0;
+  int32_t limit0, rootFailed;
+  int32_t policy, pad;
+};
+
+struct TrailHdr {
+  int32_t gran, oldStamp;
+};
+
+struct Level {
+  int64_t trailTop;
+  int32_t limit, failed, serial, pad;
+};
+
+enum StatIdx { S_JOBS = 0, S_GRAN_IN, S_ROWS, S_GRAN_ROWS, S_TRAIL, S_RES_CHECK, S_RES_MISS, S_SCAN };
+
+struct SlotDesc {
+  // arrays
+  uint64_t* ct;
+  int32_t* idx[2];
+  int32_t* stamp;
+  uint64_t* lastDom;
+  int32_t* res;           // residue word per support row
+  TrailHdr* trailHdr;
+  uint64_t* trailWords;   // trailCap x 64
+  Level* levels;          // maxDepth
+  uint64_t* levelDom;     // maxDepth x D
+  int32_t* nzFlag;        // nGran: granule non-zero after the running job
+  int64_t trailCap;
+  int32_t maxDepth, pad0;
+  // mutable state
+  int64_t trailTop;
+  int32_t cur, limit, failed, depth, serial, pad1;
+  // per-job scratch
+  int32_t updCount, filtCount, jobTrail, prepDone, updDone, status, newLimit, pad2;
+  unsigned long long stats[8];
+};
+
+struct DevJob {
+  const TabDesc* tab;
+  SlotDesc* slot;
+  const uint64_t* dom_in;  // device pointer, or unused with JF_INLINE_DOM
+  uint64_t* dom_out;
+  uint64_t* ct_out;
+  int32_t* status_out;
+  uint32_t flags;
+  int32_t nPop, nPush;
+  int32_t serialBase;      // serial of the k-th pushed level = serialBase + k
+  int32_t nUpd, nFilt;     // item counts of this job
+  int32_t depthAfter;      // slot depth once the pops and pushes are applied
+  int32_t pad;
+};
+
+// Kernel argument block of the persistent propagate kernel.
+struct KArgs {
+  const DevJob* jobs;      // nullptr: single job in `job`
+  const int32_t* updOff;   // nJobs + 1 prefix sums of update items (nullptr for one job)
+  const int32_t* filtOff;  // nJobs + 1 prefix sums of filter items
+  const int32_t* prepList; // jobs that need a prep item (pops/pushes)
+  int32_t nJobs, nPrep, nUpd, nFilt;
+  int32_t* queue;          // [0] head, [1] exit count, [2] launches, [3] error
+  int32_t* hostErr;        // nullable: error word copied here by the last block
+  DevJob job;
+  uint64_t inl[INLINE_WORDS];
+};
+
+}  // namespace ctk

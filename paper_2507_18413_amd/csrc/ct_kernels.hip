@@ -1,0 +1,702 @@
+// ct_kernels.hip -- HIP kernels of the CT library for gfx950 (CDNA4).
+//
+// Work is exact bitwise integer arithmetic on uint64 words; nothing here is
+// a dense contraction, so there is no MFMA: the kernels are built around
+// coalesced 512-byte granule loads (one word per lane of a wave64), wave
+// ballots and LDS.
+//
+// One persistent kernel executes a batch of propagation jobs from a device
+// work queue.  Queue items, in dequeue order:
+//   prep   (one per job that pops or pushes)  backtrack restore / level push
+//   update (nUpd per job)   updateTable (Alg. 2) over 8 granules each, with the
+//                           Delta / s_val / s_sup prologue of Alg. 1 recomputed
+//                           per item in LDS; the last update item of a job
+//                           partitions the sparse index and decides FAIL
+//   filter (nFilt per job)  filterDomains (Alg. 3), one domain word per wave,
+//                           residue word first, then a scan of active granules
+// An item only waits for items of its own job that precede it in the queue
+// (update waits for prep when the job pops; filter waits for the job's last
+// update item).  Every dequeued item belongs to a running workgroup, so every
+// wait ends; waits are also bounded and report a device error on expiry.
+#include <hip/hip_runtime.h>
+
+#include "ct_device.h"
+
+namespace ctk {
+
+constexpr int NGW = 2;                 // granules per wave processed together
+constexpr int GPI = WAVES * NGW;       // granules per update item
+constexpr int ROW_UNROLL = 8;          // support rows loaded per batch
+constexpr uint32_t SPIN_LIMIT = 1u << 22;
+
+__device__ __forceinline__ int lane_id() { return threadIdx.x & (WAVE - 1); }
+__device__ __forceinline__ int wave_id() { return threadIdx.x / WAVE; }
+
+__device__ __forceinline__ int ld_acquire(int32_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_release(int32_t* p, int32_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ int ld_relaxed(int32_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+struct Shared {
+  int32_t item, ok, isLast, status, noop, nseg, nrows, limit, serial, depth, bad_stray, bad_sub;
+  int64_t trailTop;
+  int32_t size[MAX_ARITY];
+  int32_t dcnt[MAX_ARITY];
+  int32_t segOf[MAX_ARITY];   // var -> segment, -1 if not in s_val
+  int32_t segEnd[MAX_ARITY];  // exclusive end of segment rows
+  int32_t segInc[MAX_ARITY];
+  int32_t segVar[MAX_ARITY];
+  int32_t scan[BLOCK];
+  uint64_t din[MAX_D];
+  union {
+    uint16_t rows[MAX_ROWS];
+    int32_t part[MAX_GRAN];
+  } u;
+};
+
+// Thread 0 spins until *flag == want; the result is broadcast to the block.
+__device__ bool block_wait(int32_t* flag, int32_t want, int32_t* err, Shared& sh) {
+  if (threadIdx.x == 0) {
+    int ok = 1;
+    for (uint32_t it = 0;; ++it) {
+      if (ld_acquire(flag) == want) break;
+      if (ld_relaxed(err)) { ok = 0; break; }
+      if (it > SPIN_LIMIT) { atomicExch(err, 1); ok = 0; break; }
+      __builtin_amdgcn_s_sleep(2);
+    }
+    sh.ok = ok;
+  }
+  __syncthreads();
+  int ok = sh.ok;
+  __syncthreads();
+  return ok != 0;
+}
+
+__device__ __forceinline__ const DevJob& job_of(const KArgs& a, int j) {
+  return a.jobs ? a.jobs[j] : a.job;
+}
+
+__device__ __forceinline__ uint64_t job_din(const KArgs& a, const DevJob& J, int k) {
+  return (J.flags & JF_INLINE_DOM) ? a.inl[k] : J.dom_in[k];
+}
+
+// largest j with off[j] <= x  (off has n + 1 entries, off[0] = 0)
+__device__ int find_job(const int32_t* off, int n, int x) {
+  int lo = 0, hi = n;  // off[lo] <= x < off[hi]
+  while (hi - lo > 1) {
+    int mid = (lo + hi) >> 1;
+    if (off[mid] <= x) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
+// ---------------------------------------------------------------------------
+// prep: pops then pushes (whole block)
+// ---------------------------------------------------------------------------
+__device__ void do_prep(const KArgs& a, const DevJob& J, Shared& sh) {
+  SlotDesc* s = J.slot;
+  const TabDesc* T = J.tab;
+  const int D = T->D;
+  for (int p = 0; p < J.nPop; ++p) {
+    if (threadIdx.x == 0) {
+      sh.depth = s->depth - 1;
+      sh.trailTop = s->trailTop;
+    }
+    __syncthreads();
+    const int d = sh.depth;
+    const Level L = s->levels[d];
+    const int64_t top = sh.trailTop;
+    for (int64_t e = L.trailTop + wave_id(); e < top; e += WAVES) {
+      const TrailHdr h = s->trailHdr[e];
+      s->ct[(int64_t)h.gran * GW + lane_id()] = s->trailWords[e * GW + lane_id()];
+      if (lane_id() == 0) s->stamp[h.gran] = h.oldStamp;
+    }
+    for (int q = threadIdx.x; q < D; q += BLOCK) s->lastDom[q] = s->levelDom[(int64_t)d * D + q];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      s->trailTop = L.trailTop;
+      s->limit = L.limit;
+      s->failed = L.failed;
+      s->serial = L.serial;
+      s->depth = d;
+    }
+    __syncthreads();
+  }
+  for (int k = 0; k < J.nPush; ++k) {
+    if (threadIdx.x == 0) sh.depth = s->depth;
+    __syncthreads();
+    const int d = sh.depth;
+    for (int q = threadIdx.x; q < D; q += BLOCK) s->levelDom[(int64_t)d * D + q] = s->lastDom[q];
+    if (threadIdx.x == 0) {
+      Level L;
+      L.trailTop = s->trailTop;
+      L.limit = s->limit;
+      L.failed = s->failed;
+      L.serial = s->serial;
+      L.pad = 0;
+      s->levels[d] = L;
+      s->depth = d + 1;
+      s->serial = J.serialBase + k;
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    __threadfence();
+    if (!(J.flags & JF_PROPAGATE)) {
+      if (J.status_out) *J.status_out = ST_OK;
+    } else {
+      st_release(&s->prepDone, 1);  // consumed (and reset) by the job's last update item
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// prologue of Alg. 1 for one job (every update item recomputes it in LDS)
+// ---------------------------------------------------------------------------
+__device__ void prologue(const KArgs& a, const DevJob& J, Shared& sh) {
+  const TabDesc* T = J.tab;
+  SlotDesc* s = J.slot;
+  const bool fromRoot = J.flags & JF_FROM_ROOT;
+  const bool root = J.flags & JF_ROOT;
+  const int n = T->n, D = T->D;
+  const uint64_t* last = fromRoot ? T->dom0 : s->lastDom;
+  if (threadIdx.x == 0) {
+    sh.bad_stray = 0;
+    sh.bad_sub = 0;
+    if (fromRoot) {
+      sh.limit = T->limit0;
+      sh.status = T->rootFailed ? ST_STATE : ST_OK;
+    } else {
+      sh.limit = s->limit;
+      sh.status = s->failed ? ST_STATE : ST_OK;
+    }
+    sh.trailTop = s->trailTop;
+    sh.serial = J.nPush > 0 ? J.serialBase + J.nPush - 1 : s->serial;
+  }
+  for (int i = threadIdx.x; i < n; i += BLOCK) {
+    sh.size[i] = 0;
+    sh.dcnt[i] = 0;
+  }
+  __syncthreads();
+  for (int q = threadIdx.x; q < D; q += BLOCK) {
+    const uint64_t din = job_din(a, J, q);
+    const int i = T->wordVar[q];
+    const VarDesc v = T->vars[i];
+    const int used = v.dsize - 64 * (q - v.domOff);
+    if (used < 64 && (din >> used) != 0) sh.bad_stray = 1;
+    uint64_t dl = 0;
+    if (!root) {
+      const uint64_t ld = last[q];
+      if (din & ~ld) sh.bad_sub = 1;
+      dl = ld & ~din;
+    }
+    sh.din[q] = din;
+    atomicAdd(&sh.size[i], __popcll(din));
+    atomicAdd(&sh.dcnt[i], __popcll(dl));
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    if (sh.status == ST_OK) {
+      if (sh.bad_stray) sh.status = ST_INVALID;
+      else if (sh.bad_sub) sh.status = ST_NOT_SUBSET;
+    }
+    const int policy = T->policy;
+    int nseg = 0, nrows = 0;
+    for (int i = 0; i < n; ++i) {
+      const bool inSval = root || sh.dcnt[i] > 0;  // |dom| changed since the last call
+      if (!inSval) { sh.segOf[i] = -1; continue; }
+      const int inc = root ? 0
+                           : (policy == 2 ? 1 : policy == 1 ? 0 : (sh.dcnt[i] < sh.size[i] ? 1 : 0));
+      nrows += inc ? sh.dcnt[i] : sh.size[i];
+      sh.segOf[i] = nseg;
+      sh.segInc[nseg] = inc;
+      sh.segVar[nseg] = i;
+      sh.segEnd[nseg] = nrows;
+      ++nseg;
+    }
+    sh.nseg = nseg;
+    sh.nrows = nrows;
+    sh.noop = (nseg == 0) && !fromRoot;
+  }
+  __syncthreads();
+  if (sh.status != ST_OK || sh.noop) return;
+  // list the selected rows of every segment: word q of variable i contributes
+  // the set bits of (Delta word or domain word) in ascending order
+  for (int q = threadIdx.x; q < D; q += BLOCK) {
+    const int i = T->wordVar[q];
+    const int sg = sh.segOf[i];
+    if (sg < 0) continue;
+    const VarDesc v = T->vars[i];
+    const int inc = sh.segInc[sg];
+    int off = sg == 0 ? 0 : sh.segEnd[sg - 1];
+    for (int k = v.domOff; k < q; ++k) {
+      const uint64_t dk = sh.din[k];
+      off += __popcll(inc ? (last[k] & ~dk) : dk);
+    }
+    uint64_t bits = inc ? (last[q] & ~sh.din[q]) : sh.din[q];
+    const int base = v.rowStart + (q - v.domOff) * 64;
+    while (bits) {
+      const int b = __ffsll((unsigned long long)bits) - 1;
+      bits &= bits - 1;
+      sh.u.rows[off++] = (uint16_t)(base + b);
+    }
+  }
+  __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
+// update: updateTable (Alg. 2) over the granules of one item
+// ---------------------------------------------------------------------------
+__device__ void do_update(const KArgs& a, const DevJob& J, int chunk, Shared& sh) {
+  const TabDesc* T = J.tab;
+  SlotDesc* s = J.slot;
+  const bool fromRoot = J.flags & JF_FROM_ROOT;
+  const bool root = J.flags & JF_ROOT;
+  // levels exist only above depth 0: nothing is saved at depth 0
+  const bool trailOn = !fromRoot && !root && J.depthAfter > 0;
+
+  if (J.nPop > 0) {
+    if (!block_wait(&s->prepDone, 1, &a.queue[3], sh)) return;
+  }
+  prologue(a, J, sh);
+
+  const int nGran = T->nGran;
+  const int64_t stride = T->stride;
+  const int64_t W = T->W;
+  const int limit = sh.limit;
+  const int status = sh.status;
+  const int noop = sh.noop;
+  const int nseg = sh.nseg, nrows = sh.nrows;
+  const int serial = sh.serial;
+  const int lane = lane_id();
+  const uint64_t* srcCt = fromRoot ? T->ct0 : s->ct;
+  const int32_t* srcIdx = fromRoot ? T->idx0 : s->idx[s->cur];
+  // the slot's depth after this job's pushes/pops decides whether to trail
+  const int64_t trailTop = sh.trailTop;
+
+  unsigned long long nAct = 0, nTrail = 0;
+  const int p0 = chunk * GPI + wave_id() * NGW;
+  int pos[NGW], g[NGW];
+  bool act[NGW];
+  uint64_t old[NGW], m[NGW], acc[NGW];
+#pragma unroll
+  for (int u = 0; u < NGW; ++u) {
+    pos[u] = p0 + u;
+    g[u] = pos[u] < nGran ? srcIdx[pos[u]] : -1;
+    act[u] = pos[u] < limit && status == ST_OK;
+    old[u] = act[u] ? srcCt[(int64_t)g[u] * GW + lane] : 0ull;
+    m[u] = ~0ull;
+    acc[u] = 0ull;
+    nAct += act[u] ? 1 : 0;
+  }
+  if (status == ST_OK && !noop) {
+    int seg = 0;
+    int segEnd = nseg > 0 ? sh.segEnd[0] : 0;
+    for (int k0 = 0; k0 < nrows; k0 += ROW_UNROLL) {
+      uint64_t v[ROW_UNROLL][NGW];
+#pragma unroll
+      for (int j = 0; j < ROW_UNROLL; ++j) {
+        const int k = k0 + j;
+        const int r = k < nrows ? (int)sh.u.rows[k] : -1;
+#pragma unroll
+        for (int u = 0; u < NGW; ++u)
+          v[j][u] = (r >= 0 && act[u]) ? T->S[(int64_t)r * stride + (int64_t)g[u] * GW + lane] : 0ull;
+      }
+#pragma unroll
+      for (int j = 0; j < ROW_UNROLL; ++j) {
+        const int k = k0 + j;
+        if (k >= nrows) break;
+        while (k >= segEnd) {
+          const int inc = sh.segInc[seg];
+#pragma unroll
+          for (int u = 0; u < NGW; ++u) {
+            m[u] &= inc ? ~acc[u] : acc[u];
+            acc[u] = 0ull;
+          }
+          ++seg;
+          segEnd = sh.segEnd[seg];
+        }
+#pragma unroll
+        for (int u = 0; u < NGW; ++u) acc[u] |= v[j][u];
+      }
+    }
+    while (seg < nseg) {  // remaining segments (an empty reset segment gives 0)
+      const int inc = sh.segInc[seg];
+#pragma unroll
+      for (int u = 0; u < NGW; ++u) {
+        m[u] &= inc ? ~acc[u] : acc[u];
+        acc[u] = 0ull;
+      }
+      ++seg;
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < NGW; ++u) {
+    if (pos[u] >= nGran) continue;
+    const int64_t w = (int64_t)g[u] * GW + lane;
+    if (!act[u]) {
+      if (status != ST_OK) continue;
+      // inactive granule (all zero by invariant)
+      if (fromRoot) s->ct[w] = 0ull;
+      if (J.ct_out && w < W) J.ct_out[w] = 0ull;
+      continue;
+    }
+    const uint64_t nw = noop ? old[u] : (old[u] & m[u]);
+    const bool changed = __ballot(nw != old[u]) != 0ull;
+    if (fromRoot || root) {
+      s->ct[w] = nw;
+    } else if (changed) {
+      if (trailOn) {
+        const int st = s->stamp[g[u]];
+        if (st != serial) {
+          int e = 0;
+          if (lane == 0) e = atomicAdd(&s->jobTrail, 1);
+          e = __shfl(e, 0);
+          const int64_t tp = trailTop + e;
+          if (tp < s->trailCap) {
+            s->trailWords[tp * GW + lane] = old[u];
+            if (lane == 0) {
+              TrailHdr h;
+              h.gran = g[u];
+              h.oldStamp = st;
+              s->trailHdr[tp] = h;
+              s->stamp[g[u]] = serial;
+            }
+          } else if (lane == 0) {
+            atomicExch(&a.queue[3], 2);  // capacity is sized so this cannot happen
+          }
+          ++nTrail;
+        }
+      }
+      s->ct[w] = nw;
+    }
+    if (J.ct_out && w < W) J.ct_out[w] = nw;
+    const bool nz = __ballot(nw != 0ull) != 0ull;
+    if (lane == 0) s->nzFlag[pos[u]] = nz ? 1 : 0;
+  }
+  if (lane == 0 && status == ST_OK) {
+    atomicAdd(&s->stats[S_GRAN_ROWS], nAct * (unsigned long long)(noop ? 0 : nrows));
+    if (nTrail) atomicAdd(&s->stats[S_TRAIL], nTrail);
+  }
+
+  // count finished items; the last one finalizes the job
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __threadfence();
+    const int prev = atomicAdd(&s->updCount, 1);
+    sh.isLast = prev == J.nUpd - 1;
+    if (sh.isLast) {
+      s->updCount = 0;
+      __threadfence();
+    }
+  }
+  __syncthreads();
+  if (!sh.isLast) return;
+
+  if (J.nPush > 0 && J.nPop == 0) {
+    if (!block_wait(&s->prepDone, 1, &a.queue[3], sh)) return;
+  }
+  if (threadIdx.x == 0 && (J.nPush > 0 || J.nPop > 0)) s->prepDone = 0;
+  int st = status;
+  if (st == ST_OK && !noop) {
+    // stable partition of the active granule list: survivors first
+    const int32_t* src = srcIdx;
+    const int dstBuf = fromRoot ? 0 : 1 - s->cur;
+    int32_t* dst = s->idx[dstBuf];
+    const int per = (limit + BLOCK - 1) / BLOCK;
+    const int b = threadIdx.x * per;
+    const int e = min(b + per, limit);
+    int cnt = 0;
+    for (int p = b; p < e; ++p) cnt += s->nzFlag[p];
+    sh.scan[threadIdx.x] = cnt;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      int acc = 0;
+      for (int t = 0; t < BLOCK; ++t) {
+        const int c = sh.scan[t];
+        sh.scan[t] = acc;
+        acc += c;
+      }
+      sh.item = acc;  // survivors
+    }
+    __syncthreads();
+    const int nSurv = sh.item;
+    int sv = sh.scan[threadIdx.x];
+    int zr = nSurv + (b - sv);
+    for (int p = b; p < e; ++p) {
+      const int gid = src[p];
+      if (s->nzFlag[p]) dst[sv++] = gid; else dst[zr++] = gid;
+    }
+    for (int p = limit + threadIdx.x; p < nGran; p += BLOCK) dst[p] = src[p];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      s->cur = dstBuf;
+      s->limit = nSurv;
+      if (fromRoot) {
+        s->depth = 0;
+        s->trailTop = 0;
+        s->serial = J.serialBase;
+        s->failed = 0;
+      } else {
+        s->trailTop = trailTop + s->jobTrail;
+      }
+      s->jobTrail = 0;
+      if (nSurv == 0) {
+        st = ST_FAIL;
+        s->failed = 1;
+      }
+    }
+  }
+  if (threadIdx.x == 0) {
+    s->status = st;
+    s->pad2 = noop;
+    if (st != ST_OK && J.status_out) *J.status_out = st;
+    if (st == ST_OK || st == ST_FAIL) {
+      atomicAdd(&s->stats[S_JOBS], 1ull);
+      atomicAdd(&s->stats[S_GRAN_IN], (unsigned long long)limit);
+      atomicAdd(&s->stats[S_ROWS], (unsigned long long)(noop ? 0 : sh.nrows));
+    }
+    __threadfence();
+    st_release(&s->updDone, 1);  // consumed (and reset) by the job's last filter item
+  }
+}
+
+// ---------------------------------------------------------------------------
+// filter: filterDomains (Alg. 3) for one domain word per wave
+// ---------------------------------------------------------------------------
+__device__ void do_filter(const KArgs& a, const DevJob& J, int chunk, Shared& sh) {
+  const TabDesc* T = J.tab;
+  SlotDesc* s = J.slot;
+  if (!block_wait(&s->updDone, 1, &a.queue[3], sh)) return;
+  const int jobStatus = s->status;
+  const int noop = s->pad2;
+  const int q = chunk * WAVES + wave_id();
+  const int D = T->D;
+  const int lane = lane_id();
+  unsigned long long nChk = 0, nMiss = 0, nScan = 0;
+  if (q < D && jobStatus == ST_OK) {
+    const int i = T->wordVar[q];
+    const VarDesc v = T->vars[i];
+    const uint64_t din = job_din(a, J, q);
+    int size = 0;
+    for (int k = v.domOff; k < v.domOff + v.domWords; ++k) size += __popcll(job_din(a, J, k));
+    uint64_t dout = din;
+    if (!noop && size > 1) {  // s_sup: non-singleton variables
+      const int64_t stride = T->stride;
+      const int rowBase = v.rowStart + (q - v.domOff) * 64;
+      const bool present = (din >> lane) & 1ull;
+      bool hit = false;
+      if (present) {
+        const int r = rowBase + lane;
+        const int rw = s->res[r];
+        hit = (s->ct[rw] & T->S[(int64_t)r * stride + rw]) != 0ull;
+      }
+      unsigned long long miss = __ballot(present && !hit);
+      nChk = __popcll(__ballot(present));
+      nMiss = __popcll(miss);
+      uint64_t unsup = 0;
+      const int lim = s->limit;
+      const int32_t* idx = s->idx[s->cur];
+      while (miss) {
+        const int l = __ffsll(miss) - 1;
+        miss &= miss - 1;
+        const int r = rowBase + l;
+        const uint64_t* row = T->S + (int64_t)r * stride;
+        int found = -1;
+        for (int p = 0; p < lim && found < 0; p += 4) {
+          uint64_t x[4];
+          int gg[4];
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            gg[j] = (p + j < lim) ? idx[p + j] : -1;
+            const int64_t w = (int64_t)gg[j] * GW + lane;
+            x[j] = gg[j] >= 0 ? (s->ct[w] & row[w]) : 0ull;
+          }
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            const unsigned long long bm = __ballot(x[j] != 0ull);
+            if (found < 0 && bm) found = gg[j] * GW + (__ffsll(bm) - 1);
+          }
+          nScan += min(4, lim - p);
+        }
+        if (found >= 0) {
+          if (lane == 0) s->res[r] = found;
+        } else {
+          unsup |= 1ull << l;
+        }
+      }
+      dout = din & ~unsup;
+    }
+    if (lane == 0) {
+      J.dom_out[q] = dout;
+      s->lastDom[q] = dout;
+    }
+  }
+  if (lane == 0 && (nChk | nMiss | nScan)) {
+    atomicAdd(&s->stats[S_RES_CHECK], nChk);
+    atomicAdd(&s->stats[S_RES_MISS], nMiss);
+    atomicAdd(&s->stats[S_SCAN], nScan);
+  }
+  // the last filter item of the job reports OK
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __threadfence();
+    const int prev = atomicAdd(&s->filtCount, 1);
+    if (prev == J.nFilt - 1) {
+      s->filtCount = 0;
+      s->updDone = 0;
+      if (jobStatus == ST_OK && J.status_out) *J.status_out = ST_OK;
+    }
+  }
+}
+
+__global__ void __launch_bounds__(BLOCK) propagate_kernel(KArgs a) {
+  __shared__ Shared sh;
+  int32_t* q = a.queue;
+  const int total = a.nPrep + a.nUpd + a.nFilt;
+  for (;;) {
+    if (threadIdx.x == 0) sh.item = atomicAdd(&q[0], 1);
+    __syncthreads();
+    const int item = sh.item;
+    __syncthreads();
+    if (item >= total) break;
+    if (ld_relaxed(&q[3])) continue;  // a device error: drain the queue
+    if (item < a.nPrep) {
+      const int j = a.jobs ? a.prepList[item] : 0;
+      do_prep(a, job_of(a, j), sh);
+    } else if (item < a.nPrep + a.nUpd) {
+      const int x = item - a.nPrep;
+      const int j = a.jobs ? find_job(a.updOff, a.nJobs, x) : 0;
+      const int c = a.jobs ? x - a.updOff[j] : x;
+      do_update(a, job_of(a, j), c, sh);
+    } else {
+      const int x = item - a.nPrep - a.nUpd;
+      const int j = a.jobs ? find_job(a.filtOff, a.nJobs, x) : 0;
+      const int c = a.jobs ? x - a.filtOff[j] : x;
+      do_filter(a, job_of(a, j), c, sh);
+    }
+    __syncthreads();
+  }
+  // the last workgroup out resets the queue for the next launch
+  if (threadIdx.x == 0) {
+    __threadfence();
+    const int prev = atomicAdd(&q[1], 1);
+    if (prev == (int)gridDim.x - 1) {
+      const int err = ld_relaxed(&q[3]);
+      if (a.hostErr) *(volatile int32_t*)a.hostErr = err;
+      q[0] = 0;
+      q[1] = 0;
+      q[3] = 0;
+      q[2] += 1;  // launches completed (diagnostics)
+      __threadfence();
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// support bitset builder: one wave per 64 tuples (one word column); for each
+// column of the table every distinct row among the wave's lanes is written
+// once with the ballot of the lanes holding that value (no atomics, each
+// (row, word) has exactly one writer).  S must be zeroed beforehand.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(BLOCK) build_supports_kernel(const int32_t* tuples, int64_t t,
+                                                               int n, const VarDesc* vars,
+                                                               const int32_t* lo, uint64_t* S,
+                                                               int64_t stride, int64_t W) {
+  const int64_t w = (int64_t)blockIdx.x * WAVES + wave_id();
+  if (w >= W) return;
+  const int lane = lane_id();
+  const int64_t j = w * 64 + lane;
+  for (int i = 0; i < n; ++i) {
+    const VarDesc v = vars[i];
+    int r = -1;
+    if (j < t) {
+      const int64_t val = (int64_t)tuples[j * n + i] - lo[i];
+      if (val >= 0 && val < v.dsize) r = v.rowStart + (int)val;
+    }
+    bool pending = r >= 0;
+    for (;;) {
+      const unsigned long long act = __ballot(pending);
+      if (!act) break;
+      const int leader = __ffsll(act) - 1;
+      const int rl = __shfl(r, leader);
+      const unsigned long long mask = __ballot(pending && r == rl);
+      if (lane == leader) S[(int64_t)rl * stride + w] = mask;
+      if (r == rl) pending = false;
+    }
+  }
+}
+
+// copy the root state into n fresh slots (one workgroup per slot)
+__global__ void __launch_bounds__(BLOCK) init_slots_kernel(const TabDesc* T, SlotDesc* slots,
+                                                           int n, const int32_t* rootRes) {
+  const int k = blockIdx.x;
+  if (k >= n) return;
+  SlotDesc* s = slots + k;
+  const int64_t words = T->stride;
+  for (int64_t w = threadIdx.x; w < words; w += BLOCK) s->ct[w] = T->ct0[w];
+  for (int p = threadIdx.x; p < T->nGran; p += BLOCK) {
+    s->idx[0][p] = T->idx0[p];
+    s->idx[1][p] = T->idx0[p];
+    s->stamp[p] = 0;
+    s->nzFlag[p] = 0;
+  }
+  for (int q = threadIdx.x; q < T->D; q += BLOCK) s->lastDom[q] = T->dom0[q];
+  for (int r = threadIdx.x; r < T->rows; r += BLOCK) s->res[r] = rootRes[r];
+  if (threadIdx.x == 0) {
+    s->trailTop = 0;
+    s->cur = 0;
+    s->limit = T->limit0;
+    s->failed = T->rootFailed;
+    s->depth = 0;
+    s->serial = 0;
+    s->updCount = 0;
+    s->filtCount = 0;
+    s->jobTrail = 0;
+    s->prepDone = 0;
+    s->updDone = 0;
+    s->status = 0;
+    s->newLimit = 0;
+    s->pad2 = 0;
+    for (int x = 0; x < 8; ++x) s->stats[x] = 0;
+  }
+}
+
+}  // namespace ctk
+
+// ---------------------------------------------------------------------------
+// launch wrappers used by the host runtime
+// ---------------------------------------------------------------------------
+namespace ctk {
+
+int propagate_items_per_job_update(int nGran) { return (nGran + GPI - 1) / GPI; }
+int propagate_items_per_job_filter(int D) { return (D + WAVES - 1) / WAVES; }
+
+hipError_t launch_propagate(const KArgs& a, int grid, hipStream_t stream) {
+  hipLaunchKernelGGL(propagate_kernel, dim3(grid), dim3(BLOCK), 0, stream, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_build_supports(const int32_t* tuples, int64_t t, int n, const VarDesc* vars,
+                                 const int32_t* lo, uint64_t* S, int64_t stride, int64_t W,
+                                 hipStream_t stream) {
+  if (W <= 0) return hipSuccess;
+  const int64_t blocks = (W + WAVES - 1) / WAVES;
+  hipLaunchKernelGGL(build_supports_kernel, dim3((unsigned)blocks), dim3(BLOCK), 0, stream, tuples,
+                     t, n, vars, lo, S, stride, W);
+  return hipGetLastError();
+}
+
+hipError_t launch_init_slots(const TabDesc* T, SlotDesc* slots, int n, const int32_t* rootRes,
+                             hipStream_t stream) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(init_slots_kernel, dim3(n), dim3(BLOCK), 0, stream, T, slots, n, rootRes);
+  return hipGetLastError();
+}
+
+}  // namespace ctk

@@ -1,0 +1,806 @@
+// ct_runtime.cpp -- host runtime and C ABI of the CT library (include/ct.h).
+//
+// Owns device memory, streams and the host-side mirror of each slot's depth.
+// Every step of propagation runs in the HIP kernels of ct_kernels.hip; the
+// host only validates arguments, lays out job descriptors and moves the
+// domain bitmaps across the boundary.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <set>
+#include <string>
+#include <vector>
+
+#include "ct.h"
+#include "ct_device.h"
+
+using namespace ctk;
+
+namespace ctk {
+int propagate_items_per_job_update(int nGran);
+int propagate_items_per_job_filter(int D);
+hipError_t launch_propagate(const KArgs& a, int grid, hipStream_t stream);
+hipError_t launch_build_supports(const int32_t* tuples, int64_t t, int n, const VarDesc* vars,
+                                 const int32_t* lo, uint64_t* S, int64_t stride, int64_t W,
+                                 hipStream_t stream);
+hipError_t launch_init_slots(const TabDesc* T, SlotDesc* slots, int n, const int32_t* rootRes,
+                             hipStream_t stream);
+}  // namespace ctk
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+#define HIPCHK(expr)                                                                        \
+  do {                                                                                      \
+    hipError_t e_ = (expr);                                                                 \
+    if (e_ != hipSuccess)                                                                   \
+      return fail(CT_E_DEVICE, "%s failed: %s (%s:%d)", #expr, hipGetErrorString(e_),       \
+                  __FILE__, __LINE__);                                                      \
+  } while (0)
+
+constexpr int MAX_GRID = 768;  // 256 CUs x 3 workgroups (LDS bound)
+
+// failed flag as known on the host: 0 no, 1 yes, 2 unknown (after batches)
+struct SlotHost {
+  SlotDesc* dev = nullptr;
+  int maxDepth = 0;
+  int depth = 0;           // depth including pending operations
+  int pendPop = 0, pendPush = 0;
+  int8_t failed = 0;
+  std::vector<int8_t> failedAt;  // failed flag recorded by each push
+};
+
+struct DevBlock {
+  void* ptr = nullptr;
+};
+
+// Device queue + staging for one stream.
+struct QueueCtx {
+  int32_t* queue = nullptr;   // 4 ints on the device
+  int32_t* hostErr = nullptr; // pinned
+  // batch staging
+  DevJob* dJobs = nullptr;
+  int32_t* dOff = nullptr;    // updOff | filtOff | prepList
+  size_t capJobs = 0;
+  std::vector<DevJob> hJobs;
+  std::vector<int32_t> hOff;
+  DevJob* pJobs = nullptr;    // pinned staging
+  int32_t* pOff = nullptr;
+  size_t capPinned = 0;
+  hipEvent_t staged = nullptr;
+};
+
+int queue_init(QueueCtx& q) {
+  HIPCHK(hipMalloc(&q.queue, 4 * sizeof(int32_t)));
+  HIPCHK(hipMemset(q.queue, 0, 4 * sizeof(int32_t)));
+  HIPCHK(hipHostMalloc((void**)&q.hostErr, sizeof(int32_t), hipHostMallocDefault));
+  *q.hostErr = 0;
+  HIPCHK(hipEventCreateWithFlags(&q.staged, hipEventDisableTiming));
+  return CT_OK;
+}
+
+void queue_free(QueueCtx& q) {
+  if (q.queue) (void)hipFree(q.queue);
+  if (q.hostErr) (void)hipHostFree(q.hostErr);
+  if (q.dJobs) (void)hipFree(q.dJobs);
+  if (q.dOff) (void)hipFree(q.dOff);
+  if (q.pJobs) (void)hipHostFree(q.pJobs);
+  if (q.pOff) (void)hipHostFree(q.pOff);
+  if (q.staged) (void)hipEventDestroy(q.staged);
+  q = QueueCtx();
+}
+
+std::mutex g_qmu;
+std::map<hipStream_t, QueueCtx*> g_queues;
+
+}  // namespace
+
+struct ct_table {
+  int n = 0;
+  int64_t t = 0, W = 0, stride = 0;
+  int rows = 0, D = 0, nGran = 0;
+  ct_config cfg{};
+  std::vector<int32_t> lo, dsz, domOff;
+  std::vector<VarDesc> vars;
+  std::vector<int32_t> wordVar;
+  // device
+  uint64_t* dS = nullptr;
+  VarDesc* dVars = nullptr;
+  int32_t* dWordVar = nullptr;
+  int32_t* dLo = nullptr;
+  TabDesc* dTab = nullptr;
+  TabDesc hTab{};
+  SlotDesc* dRoot = nullptr;
+  SlotDesc hRoot{};
+  std::vector<void*> blocks;  // device allocations to free
+  std::vector<SlotHost> slots;
+  int32_t serialCounter = 1;
+  bool poisoned = false;
+  int rootFailed = 0;
+  hipStream_t stream = nullptr;
+  QueueCtx q;
+  // pinned staging of the synchronous calls
+  uint64_t* pDomOut = nullptr;  // D words
+  uint64_t* pDomIn = nullptr;   // D words (used when D > INLINE_WORDS)
+  uint64_t* pCt = nullptr;      // W words (lazily)
+  int32_t* pStatus = nullptr;
+};
+
+namespace {
+
+int dev_alloc(ct_table* T, void** p, size_t bytes) {
+  if (bytes == 0) bytes = 8;
+  hipError_t e = hipMalloc(p, bytes);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(CT_E_NOMEM, "hipMalloc(%zu) failed: %s", bytes, hipGetErrorString(e));
+  }
+  T->blocks.push_back(*p);
+  return CT_OK;
+}
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+// Allocate n slot descriptors and their arrays in one device block.
+int alloc_slots(ct_table* T, int n, int maxDepth, SlotDesc** dSlots, std::vector<SlotDesc>& h) {
+  const size_t ctB = align256(sizeof(uint64_t) * T->stride);
+  const size_t idxB = align256(sizeof(int32_t) * T->nGran);
+  const size_t domB = align256(sizeof(uint64_t) * T->D);
+  const size_t resB = align256(sizeof(int32_t) * T->rows);
+  const int64_t trailCap = (int64_t)maxDepth * T->nGran;
+  const size_t thB = align256(sizeof(TrailHdr) * std::max<int64_t>(trailCap, 1));
+  const size_t twB = align256(sizeof(uint64_t) * GW * std::max<int64_t>(trailCap, 1));
+  const size_t lvB = align256(sizeof(Level) * std::max(maxDepth, 1));
+  const size_t ldB = align256(sizeof(uint64_t) * T->D * std::max(maxDepth, 1));
+  const size_t per = ctB + 4 * idxB + domB + resB + thB + twB + lvB + ldB;
+  const size_t descB = align256(sizeof(SlotDesc) * n);
+  char* base = nullptr;
+  int rc = dev_alloc(T, (void**)&base, descB + per * (size_t)n);
+  if (rc != CT_OK) return rc;
+  *dSlots = (SlotDesc*)base;
+  h.assign(n, SlotDesc{});
+  char* p = base + descB;
+  for (int k = 0; k < n; ++k) {
+    SlotDesc& s = h[k];
+    s.ct = (uint64_t*)p; p += ctB;
+    s.idx[0] = (int32_t*)p; p += idxB;
+    s.idx[1] = (int32_t*)p; p += idxB;
+    s.stamp = (int32_t*)p; p += idxB;
+    s.nzFlag = (int32_t*)p; p += idxB;
+    s.lastDom = (uint64_t*)p; p += domB;
+    s.res = (int32_t*)p; p += resB;
+    s.trailHdr = (TrailHdr*)p; p += thB;
+    s.trailWords = (uint64_t*)p; p += twB;
+    s.levels = (Level*)p; p += lvB;
+    s.levelDom = (uint64_t*)p; p += ldB;
+    s.trailCap = trailCap;
+    s.maxDepth = maxDepth;
+  }
+  HIPCHK(hipMemcpy(base, h.data(), sizeof(SlotDesc) * n, hipMemcpyHostToDevice));
+  return CT_OK;
+}
+
+int check_poison(const ct_table* T) {
+  if (!T) return fail(CT_E_INVALID, "null table");
+  if (T->poisoned) return fail(CT_E_DEVICE, "table handle poisoned by an earlier device error");
+  return CT_OK;
+}
+
+// Fill item counts of a propagate job.
+void job_counts(const ct_table* T, DevJob& J) {
+  if (J.flags & JF_PROPAGATE) {
+    J.nUpd = propagate_items_per_job_update(T->nGran);
+    J.nFilt = propagate_items_per_job_filter(T->D);
+  } else {
+    J.nUpd = 0;
+    J.nFilt = 0;
+  }
+}
+
+// Run one job synchronously on the table's stream.
+int run_single(ct_table* T, DevJob& J, const uint64_t* dom_in_host) {
+  KArgs a{};
+  a.jobs = nullptr;
+  a.nJobs = 1;
+  job_counts(T, J);
+  const bool needPrep = J.nPop > 0 || J.nPush > 0;
+  a.nPrep = needPrep ? 1 : 0;
+  a.nUpd = J.nUpd;
+  a.nFilt = J.nFilt;
+  a.queue = T->q.queue;
+  a.hostErr = T->q.hostErr;
+  if (dom_in_host) {
+    if (T->D <= INLINE_WORDS) {
+      memcpy(a.inl, dom_in_host, sizeof(uint64_t) * T->D);
+      J.flags |= JF_INLINE_DOM;
+    } else {
+      memcpy(T->pDomIn, dom_in_host, sizeof(uint64_t) * T->D);
+      uint64_t* dp = nullptr;
+      HIPCHK(hipHostGetDevicePointer((void**)&dp, T->pDomIn, 0));
+      J.dom_in = dp;
+    }
+  }
+  a.job = J;
+  const int total = a.nPrep + a.nUpd + a.nFilt;
+  if (total == 0) return CT_OK;
+  *T->q.hostErr = 0;
+  *T->pStatus = 99;
+  HIPCHK(launch_propagate(a, std::min(total, MAX_GRID), T->stream));
+  hipError_t e = hipStreamSynchronize(T->stream);
+  if (e != hipSuccess) {
+    T->poisoned = true;
+    return fail(CT_E_DEVICE, "kernel failed: %s", hipGetErrorString(e));
+  }
+  if (*T->q.hostErr) {
+    T->poisoned = true;
+    return fail(CT_E_DEVICE, "device-side error %d (wait timeout or trail overflow)", *T->q.hostErr);
+  }
+  return CT_OK;
+}
+
+int32_t* pinned_dev(ct_table* T, int32_t* host) {
+  int32_t* d = nullptr;
+  if (hipHostGetDevicePointer((void**)&d, host, 0) != hipSuccess) return nullptr;
+  return d;
+}
+uint64_t* pinned_dev64(ct_table* T, uint64_t* host) {
+  uint64_t* d = nullptr;
+  if (hipHostGetDevicePointer((void**)&d, host, 0) != hipSuccess) return nullptr;
+  return d;
+}
+
+// Apply pending pushes/pops of a slot (device work) without propagating.
+int flush_slot(ct_table* T, int slot) {
+  SlotHost& S = T->slots[slot];
+  if (S.pendPop == 0 && S.pendPush == 0) return CT_OK;
+  DevJob J{};
+  J.tab = T->dTab;
+  J.slot = S.dev;
+  J.flags = 0;
+  J.nPop = S.pendPop;
+  J.nPush = S.pendPush;
+  J.serialBase = T->serialCounter;
+  T->serialCounter += S.pendPush;
+  J.depthAfter = S.depth;
+  J.status_out = pinned_dev(T, T->pStatus);
+  S.pendPop = S.pendPush = 0;
+  return run_single(T, J, nullptr);
+}
+
+int ensure_pinned_ct(ct_table* T) {
+  if (T->pCt) return CT_OK;
+  HIPCHK(hipHostMalloc((void**)&T->pCt, sizeof(uint64_t) * std::max<int64_t>(T->W, 1),
+                       hipHostMallocDefault));
+  return CT_OK;
+}
+
+int check_slot(const ct_table* T, int slot) {
+  if (slot < 0 || slot >= (int)T->slots.size())
+    return fail(CT_E_INVALID, "slot %d out of range (%zu slots)", slot, T->slots.size());
+  return CT_OK;
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+extern "C" {
+
+const char* ct_last_error(void) { return g_err.c_str(); }
+
+void ct_destroy(ct_table* T) {
+  if (!T) return;
+  if (T->stream) (void)hipStreamSynchronize(T->stream);
+  for (void* p : T->blocks) (void)hipFree(p);
+  queue_free(T->q);
+  if (T->pDomOut) (void)hipHostFree(T->pDomOut);
+  if (T->pDomIn) (void)hipHostFree(T->pDomIn);
+  if (T->pCt) (void)hipHostFree(T->pCt);
+  if (T->pStatus) (void)hipHostFree(T->pStatus);
+  if (T->stream) (void)hipStreamDestroy(T->stream);
+  delete T;
+}
+
+static int create_impl(ct_table* T, const int32_t* tuples, int64_t t, int32_t n,
+                       const int32_t* lo, const int32_t* dsz, const uint64_t* init_dom) {
+  T->n = n;
+  T->t = t;
+  T->W = (t + 63) / 64;
+  T->nGran = (int)std::max<int64_t>(1, (T->W + GW - 1) / GW);
+  T->stride = (int64_t)T->nGran * GW;
+  T->lo.assign(lo, lo + n);
+  T->dsz.assign(dsz, dsz + n);
+  int rows = 0, D = 0;
+  for (int i = 0; i < n; ++i) {
+    VarDesc v;
+    v.rowStart = rows;
+    v.dsize = dsz[i];
+    v.domOff = D;
+    v.domWords = (dsz[i] + 63) / 64;
+    T->vars.push_back(v);
+    T->domOff.push_back(D);
+    for (int k = 0; k < v.domWords; ++k) T->wordVar.push_back(i);
+    rows += dsz[i];
+    D += v.domWords;
+  }
+  T->rows = rows;
+  T->D = D;
+  if (rows > MAX_ROWS) return fail(CT_E_INVALID, "%d support rows exceed the limit %d", rows, MAX_ROWS);
+  if (D > MAX_D) return fail(CT_E_INVALID, "%d domain words exceed the limit %d", D, MAX_D);
+  if (T->nGran > MAX_GRAN)
+    return fail(CT_E_INVALID, "%lld tuples exceed the limit %lld", (long long)t,
+                (long long)MAX_GRAN * GW * 64);
+  // initial domains (validated on the host, before any device work)
+  std::vector<uint64_t> dom0(D, 0);
+  for (int i = 0; i < n; ++i) {
+    const VarDesc& v = T->vars[i];
+    for (int k = 0; k < v.domWords; ++k) {
+      const int used = std::min(64, v.dsize - 64 * k);
+      const uint64_t full = used == 64 ? ~0ull : ((1ull << used) - 1);
+      if (init_dom) {
+        if (init_dom[v.domOff + k] & ~full)
+          return fail(CT_E_INVALID, "init_dom has stray bits in variable %d", i);
+        dom0[v.domOff + k] = init_dom[v.domOff + k];
+      } else {
+        dom0[v.domOff + k] = full;
+      }
+    }
+  }
+  HIPCHK(hipStreamCreateWithFlags(&T->stream, hipStreamNonBlocking));
+  int rc = queue_init(T->q);
+  if (rc) return rc;
+  HIPCHK(hipHostMalloc((void**)&T->pDomOut, sizeof(uint64_t) * D, hipHostMallocDefault));
+  HIPCHK(hipHostMalloc((void**)&T->pDomIn, sizeof(uint64_t) * D, hipHostMallocDefault));
+  HIPCHK(hipHostMalloc((void**)&T->pStatus, sizeof(int32_t) * 4, hipHostMallocDefault));
+
+  // static data
+  if ((rc = dev_alloc(T, (void**)&T->dS, sizeof(uint64_t) * (size_t)rows * T->stride))) return rc;
+  if ((rc = dev_alloc(T, (void**)&T->dVars, sizeof(VarDesc) * n))) return rc;
+  if ((rc = dev_alloc(T, (void**)&T->dWordVar, sizeof(int32_t) * D))) return rc;
+  if ((rc = dev_alloc(T, (void**)&T->dLo, sizeof(int32_t) * n))) return rc;
+  if ((rc = dev_alloc(T, (void**)&T->dTab, sizeof(TabDesc)))) return rc;
+  HIPCHK(hipMemcpy(T->dVars, T->vars.data(), sizeof(VarDesc) * n, hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(T->dWordVar, T->wordVar.data(), sizeof(int32_t) * D, hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(T->dLo, lo, sizeof(int32_t) * n, hipMemcpyHostToDevice));
+  HIPCHK(hipMemsetAsync(T->dS, 0, sizeof(uint64_t) * (size_t)rows * T->stride, T->stream));
+  if (t > 0) {
+    int32_t* dTup = nullptr;
+    HIPCHK(hipMalloc(&dTup, sizeof(int32_t) * (size_t)t * n));
+    hipError_t e = hipMemcpyAsync(dTup, tuples, sizeof(int32_t) * (size_t)t * n,
+                                  hipMemcpyHostToDevice, T->stream);
+    if (e == hipSuccess)
+      e = launch_build_supports(dTup, t, n, T->dVars, T->dLo, T->dS, T->stride, T->W, T->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(T->stream);
+    (void)hipFree(dTup);
+    if (e != hipSuccess) return fail(CT_E_DEVICE, "support build failed: %s", hipGetErrorString(e));
+  }
+
+  // root slot: currTable = all t tuples, every granule active, domains dom0
+  std::vector<SlotDesc> hs;
+  if ((rc = alloc_slots(T, 1, 0, &T->dRoot, hs))) return rc;
+  T->hRoot = hs[0];
+  {
+    std::vector<uint64_t> ones(T->stride, 0);
+    for (int64_t j = 0; j < T->W; ++j) {
+      const int64_t left = t - 64 * j;
+      ones[j] = left >= 64 ? ~0ull : ((1ull << left) - 1);
+    }
+    std::vector<int32_t> iota(T->nGran);
+    for (int g = 0; g < T->nGran; ++g) iota[g] = g;
+    std::vector<int32_t> zeros(std::max(rows, T->nGran), 0);
+    HIPCHK(hipMemcpy(T->hRoot.ct, ones.data(), sizeof(uint64_t) * T->stride, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(T->hRoot.idx[0], iota.data(), sizeof(int32_t) * T->nGran, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(T->hRoot.idx[1], iota.data(), sizeof(int32_t) * T->nGran, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(T->hRoot.stamp, zeros.data(), sizeof(int32_t) * T->nGran, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(T->hRoot.nzFlag, zeros.data(), sizeof(int32_t) * T->nGran, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(T->hRoot.res, zeros.data(), sizeof(int32_t) * rows, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(T->hRoot.lastDom, dom0.data(), sizeof(uint64_t) * D, hipMemcpyHostToDevice));
+    SlotDesc r = T->hRoot;
+    r.limit = T->nGran;
+    HIPCHK(hipMemcpy(T->dRoot, &r, sizeof(SlotDesc), hipMemcpyHostToDevice));
+  }
+  // TabDesc (root pointers filled after the root propagation)
+  TabDesc& tb = T->hTab;
+  tb.n = n;
+  tb.rows = rows;
+  tb.D = D;
+  tb.nGran = T->nGran;
+  tb.W = T->W;
+  tb.stride = T->stride;
+  tb.S = T->dS;
+  tb.vars = T->dVars;
+  tb.wordVar = T->dWordVar;
+  tb.policy = T->cfg.branch_policy;
+  HIPCHK(hipMemcpy(T->dTab, &tb, sizeof(TabDesc), hipMemcpyHostToDevice));
+
+  // root propagation: every variable takes the reset branch over dom0
+  DevJob J{};
+  J.tab = T->dTab;
+  J.slot = T->dRoot;
+  J.flags = JF_PROPAGATE | JF_ROOT;
+  J.dom_out = pinned_dev64(T, T->pDomOut);
+  J.status_out = pinned_dev(T, T->pStatus);
+  J.depthAfter = 0;
+  if ((rc = run_single(T, J, dom0.data()))) return rc;
+  const int st = *T->pStatus;
+  SlotDesc r{};
+  HIPCHK(hipMemcpy(&r, T->dRoot, sizeof(SlotDesc), hipMemcpyDeviceToHost));
+  if (st != CT_OK && st != CT_FAIL) return fail(CT_E_DEVICE, "root propagation returned %d", st);
+  T->rootFailed = st == CT_FAIL;
+  tb.ct0 = T->hRoot.ct;
+  tb.idx0 = r.idx[r.cur];
+  tb.dom0 = T->hRoot.lastDom;
+  tb.limit0 = r.limit;
+  tb.rootFailed = T->rootFailed;
+  if (T->rootFailed) {
+    // the failed root keeps dom0 as its domains and no valid tuple
+    HIPCHK(hipMemcpy(T->hRoot.lastDom, dom0.data(), sizeof(uint64_t) * D, hipMemcpyHostToDevice));
+    HIPCHK(hipMemset(T->hRoot.ct, 0, sizeof(uint64_t) * T->stride));
+    tb.limit0 = 0;
+  }
+  HIPCHK(hipMemcpy(T->dTab, &tb, sizeof(TabDesc), hipMemcpyHostToDevice));
+  int first = 0;
+  return ct_slots_alloc(T, 1, -1, &first);
+}
+
+int ct_create(const int32_t* tuples, int64_t n_tuples, int32_t arity, const int32_t* dom_lo,
+              const int32_t* dom_size, const uint64_t* init_dom, const ct_config* cfg,
+              ct_table** out) {
+  if (!out) return fail(CT_E_INVALID, "out is NULL");
+  *out = nullptr;
+  if (arity < 1 || arity > MAX_ARITY) return fail(CT_E_INVALID, "arity %d not in [1, %d]", arity, MAX_ARITY);
+  if (n_tuples < 0) return fail(CT_E_INVALID, "n_tuples < 0");
+  if (n_tuples > 0 && !tuples) return fail(CT_E_INVALID, "tuples is NULL");
+  if (!dom_lo || !dom_size) return fail(CT_E_INVALID, "dom_lo / dom_size is NULL");
+  for (int i = 0; i < arity; ++i)
+    if (dom_size[i] < 1) return fail(CT_E_INVALID, "dom_size[%d] < 1", i);
+  ct_table* T = new (std::nothrow) ct_table();
+  if (!T) return fail(CT_E_NOMEM, "host allocation failed");
+  T->cfg.branch_policy = CT_BRANCH_AUTO;
+  T->cfg.max_depth = 256;
+  if (cfg) {
+    if (cfg->branch_policy < 0 || cfg->branch_policy > 2) {
+      delete T;
+      return fail(CT_E_INVALID, "branch_policy %d", cfg->branch_policy);
+    }
+    T->cfg.branch_policy = cfg->branch_policy;
+    if (cfg->max_depth < 0) {
+      delete T;
+      return fail(CT_E_INVALID, "max_depth < 0");
+    }
+    T->cfg.max_depth = cfg->max_depth;
+  }
+  int rc = create_impl(T, tuples, n_tuples, arity, dom_lo, dom_size, init_dom);
+  if (rc != CT_OK) {
+    std::string msg = g_err;
+    ct_destroy(T);
+    g_err = msg;
+    return rc;
+  }
+  *out = T;
+  return T->rootFailed ? CT_FAIL : CT_OK;
+}
+
+int ct_layout(const ct_table* T, ct_layout_info* info, int32_t* dom_off) {
+  if (!T) return fail(CT_E_INVALID, "null table");
+  if (info) {
+    info->n_vars = T->n;
+    info->D = T->D;
+    info->W = T->W;
+    info->n_tuples = T->t;
+    info->rows = T->rows;
+    info->n_slots = (int32_t)T->slots.size();
+    info->granules = T->nGran;
+    info->root_failed = T->rootFailed;
+  }
+  if (dom_off) memcpy(dom_off, T->domOff.data(), sizeof(int32_t) * T->n);
+  return CT_OK;
+}
+
+int ct_get_supports(ct_table* T, int32_t row_begin, int32_t n_rows, uint64_t* out) {
+  int rc = check_poison(T);
+  if (rc) return rc;
+  if (row_begin < 0 || n_rows < 0 || row_begin + n_rows > T->rows || (!out && n_rows))
+    return fail(CT_E_INVALID, "rows [%d, %d) out of range", row_begin, row_begin + n_rows);
+  if (T->W == 0) return CT_OK;
+  HIPCHK(hipMemcpy2D(out, sizeof(uint64_t) * T->W, T->dS + (size_t)row_begin * T->stride,
+                     sizeof(uint64_t) * T->stride, sizeof(uint64_t) * T->W, n_rows,
+                     hipMemcpyDeviceToHost));
+  return CT_OK;
+}
+
+int ct_slots_alloc(ct_table* T, int32_t n, int32_t max_depth, int32_t* first_slot) {
+  int rc = check_poison(T);
+  if (rc) return rc;
+  if (n < 1) return fail(CT_E_INVALID, "n < 1");
+  if (max_depth < 0) max_depth = T->cfg.max_depth;
+  SlotDesc* d = nullptr;
+  std::vector<SlotDesc> h;
+  if ((rc = alloc_slots(T, n, max_depth, &d, h))) return rc;
+  HIPCHK(launch_init_slots(T->dTab, d, n, T->hRoot.res, T->stream));
+  HIPCHK(hipStreamSynchronize(T->stream));
+  if (first_slot) *first_slot = (int32_t)T->slots.size();
+  for (int k = 0; k < n; ++k) {
+    SlotHost s;
+    s.dev = d + k;
+    s.maxDepth = max_depth;
+    s.failed = T->rootFailed ? 1 : 0;
+    T->slots.push_back(s);
+  }
+  return CT_OK;
+}
+
+int ct_push_slot(ct_table* T, int32_t slot) {
+  int rc = check_poison(T);
+  if (rc) return rc;
+  if ((rc = check_slot(T, slot))) return rc;
+  SlotHost& S = T->slots[slot];
+  if (S.failed == 1) return fail(CT_E_STATE, "push on a failed slot");
+  if (S.depth >= S.maxDepth) return fail(CT_E_NOMEM, "depth %d reaches max_depth", S.depth);
+  S.failedAt.push_back(S.failed);
+  S.depth++;
+  S.pendPush++;
+  return CT_OK;
+}
+
+int ct_pop_slot(ct_table* T, int32_t slot) {
+  int rc = check_poison(T);
+  if (rc) return rc;
+  if ((rc = check_slot(T, slot))) return rc;
+  SlotHost& S = T->slots[slot];
+  if (S.depth == 0) return fail(CT_E_STATE, "pop at depth 0");
+  S.depth--;
+  S.failed = S.failedAt.back();
+  S.failedAt.pop_back();
+  if (S.pendPush > 0) S.pendPush--;
+  else S.pendPop++;
+  return CT_OK;
+}
+
+int ct_push(ct_table* T) { return ct_push_slot(T, 0); }
+int ct_pop(ct_table* T) { return ct_pop_slot(T, 0); }
+
+int ct_propagate_slot(ct_table* T, int32_t slot, const uint64_t* dom_in, uint64_t* dom_out,
+                      uint64_t* ct_out, ct_stats* st) {
+  int rc = check_poison(T);
+  if (rc) return rc;
+  if ((rc = check_slot(T, slot))) return rc;
+  if (!dom_in || !dom_out) return fail(CT_E_INVALID, "dom_in / dom_out is NULL");
+  SlotHost& S = T->slots[slot];
+  DevJob J{};
+  J.tab = T->dTab;
+  J.slot = S.dev;
+  J.flags = JF_PROPAGATE;
+  J.nPop = S.pendPop;
+  J.nPush = S.pendPush;
+  J.serialBase = T->serialCounter;
+  T->serialCounter += S.pendPush;
+  J.depthAfter = S.depth;
+  J.dom_out = pinned_dev64(T, T->pDomOut);
+  J.status_out = pinned_dev(T, T->pStatus);
+  if (ct_out) {
+    if ((rc = ensure_pinned_ct(T))) return rc;
+    J.ct_out = pinned_dev64(T, T->pCt);
+  }
+  S.pendPop = S.pendPush = 0;
+  if ((rc = run_single(T, J, dom_in))) return rc;
+  const int status = *T->pStatus;
+  if (status == CT_OK) {
+    memcpy(dom_out, T->pDomOut, sizeof(uint64_t) * T->D);
+    if (ct_out) memcpy(ct_out, T->pCt, sizeof(uint64_t) * T->W);
+  } else if (status == CT_FAIL) {
+    S.failed = 1;
+    if (ct_out) memset(ct_out, 0, sizeof(uint64_t) * T->W);
+  }
+  if (st) {
+    if ((rc = ct_slot_stats(T, slot, st))) return rc;
+  }
+  switch (status) {
+    case CT_OK:
+    case CT_FAIL:
+      return status;
+    case CT_E_NOT_SUBSET:
+      return fail(status, "dom_in is not a subset of the slot's domains");
+    case CT_E_INVALID:
+      return fail(status, "dom_in has stray bits");
+    case CT_E_STATE:
+      return fail(status, "slot is failed; only pop is allowed");
+    default:
+      T->poisoned = true;
+      return fail(CT_E_DEVICE, "unexpected device status %d", status);
+  }
+}
+
+int ct_propagate(ct_table* T, const uint64_t* dom_in, uint64_t* dom_out, uint64_t* ct_out,
+                 ct_stats* st) {
+  return ct_propagate_slot(T, 0, dom_in, dom_out, ct_out, st);
+}
+
+int ct_get_state(ct_table* T, int32_t slot, uint64_t* dom_out, uint64_t* ct_out) {
+  int rc = check_poison(T);
+  if (rc) return rc;
+  if ((rc = check_slot(T, slot))) return rc;
+  if ((rc = flush_slot(T, slot))) return rc;
+  SlotDesc s{};
+  HIPCHK(hipMemcpy(&s, T->slots[slot].dev, sizeof(SlotDesc), hipMemcpyDeviceToHost));
+  if (dom_out) HIPCHK(hipMemcpy(dom_out, s.lastDom, sizeof(uint64_t) * T->D, hipMemcpyDeviceToHost));
+  if (ct_out && T->W > 0) {
+    if (s.failed) {
+      memset(ct_out, 0, sizeof(uint64_t) * T->W);
+    } else {
+      HIPCHK(hipMemcpy(ct_out, s.ct, sizeof(uint64_t) * T->W, hipMemcpyDeviceToHost));
+    }
+  }
+  return CT_OK;
+}
+
+int ct_slot_stats(ct_table* T, int32_t slot, ct_stats* st) {
+  int rc = check_poison(T);
+  if (rc) return rc;
+  if ((rc = check_slot(T, slot))) return rc;
+  if (!st) return fail(CT_E_INVALID, "st is NULL");
+  SlotDesc s{};
+  HIPCHK(hipMemcpy(&s, T->slots[slot].dev, sizeof(SlotDesc), hipMemcpyDeviceToHost));
+  st->jobs = (int64_t)s.stats[S_JOBS];
+  st->granules_in = (int64_t)s.stats[S_GRAN_IN];
+  st->rows_or = (int64_t)s.stats[S_ROWS];
+  st->granule_rows = (int64_t)s.stats[S_GRAN_ROWS];
+  st->trail_granules = (int64_t)s.stats[S_TRAIL];
+  st->residue_checks = (int64_t)s.stats[S_RES_CHECK];
+  st->residue_misses = (int64_t)s.stats[S_RES_MISS];
+  st->scan_granules = (int64_t)s.stats[S_SCAN];
+  return CT_OK;
+}
+
+int ct_propagate_batch(const ct_job* jobs, int32_t n_jobs, void* stream_v, int32_t* status_dev) {
+  if (n_jobs < 0 || (n_jobs > 0 && (!jobs || !status_dev)))
+    return fail(CT_E_INVALID, "bad batch arguments");
+  if (n_jobs == 0) return CT_OK;
+  hipStream_t stream = (hipStream_t)stream_v;
+  // validate (no state is touched before every job passes)
+  std::set<std::pair<const ct_table*, int>> seen;
+  for (int j = 0; j < n_jobs; ++j) {
+    const ct_job& cj = jobs[j];
+    ct_table* T = cj.table;
+    int rc = check_poison(T);
+    if (rc) return rc;
+    if ((rc = check_slot(T, cj.slot))) return rc;
+    if (!seen.insert({T, cj.slot}).second)
+      return fail(CT_E_INVALID, "job %d: slot %d appears twice in the batch", j, cj.slot);
+    if (cj.flags & ~(CT_JOB_PROPAGATE | CT_JOB_FROM_ROOT))
+      return fail(CT_E_INVALID, "job %d: unknown flags", j);
+    if (cj.n_pop < 0 || cj.n_push < 0) return fail(CT_E_INVALID, "job %d: negative pops/pushes", j);
+    const SlotHost& S = T->slots[cj.slot];
+    if (cj.flags & CT_JOB_FROM_ROOT) {
+      if (cj.n_pop || cj.n_push) return fail(CT_E_INVALID, "job %d: FROM_ROOT with pops/pushes", j);
+      if (!(cj.flags & CT_JOB_PROPAGATE)) return fail(CT_E_INVALID, "job %d: FROM_ROOT needs PROPAGATE", j);
+    } else {
+      if (cj.n_pop > S.depth) return fail(CT_E_INVALID, "job %d: pop below depth 0", j);
+      if (S.depth - cj.n_pop + cj.n_push > S.maxDepth)
+        return fail(CT_E_NOMEM, "job %d: depth beyond max_depth", j);
+    }
+    if ((cj.flags & CT_JOB_PROPAGATE) && (!cj.dom_in || !cj.dom_out))
+      return fail(CT_E_INVALID, "job %d: dom_in / dom_out is NULL", j);
+  }
+  QueueCtx* q = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(g_qmu);
+    auto it = g_queues.find(stream);
+    if (it == g_queues.end()) {
+      q = new QueueCtx();
+      int rc = queue_init(*q);
+      if (rc) {
+        delete q;
+        return rc;
+      }
+      g_queues[stream] = q;
+    } else {
+      q = it->second;
+    }
+  }
+  // job descriptors
+  q->hJobs.resize(n_jobs);
+  std::vector<int32_t> updOff(n_jobs + 1, 0), filtOff(n_jobs + 1, 0), prep;
+  for (int j = 0; j < n_jobs; ++j) {
+    const ct_job& cj = jobs[j];
+    ct_table* T = cj.table;
+    SlotHost& S = T->slots[cj.slot];
+    DevJob& J = q->hJobs[j];
+    J = DevJob{};
+    J.tab = T->dTab;
+    J.slot = S.dev;
+    J.dom_in = cj.dom_in;
+    J.dom_out = cj.dom_out;
+    J.ct_out = cj.ct_out;
+    J.status_out = status_dev + j;
+    J.flags = ((cj.flags & CT_JOB_PROPAGATE) ? JF_PROPAGATE : 0u) |
+              ((cj.flags & CT_JOB_FROM_ROOT) ? JF_FROM_ROOT : 0u);
+    if (cj.flags & CT_JOB_FROM_ROOT) {
+      S.pendPop = S.pendPush = 0;
+      S.depth = 0;
+      S.failedAt.clear();
+      J.serialBase = T->serialCounter++;
+      J.depthAfter = 0;
+    } else {
+      // pending single-call operations (pops P then pushes Q) come first
+      int P = S.pendPop, Q = S.pendPush;
+      if (cj.n_pop <= Q) {
+        Q = Q - cj.n_pop + cj.n_push;
+      } else {
+        P += cj.n_pop - Q;
+        Q = cj.n_push;
+      }
+      S.pendPop = S.pendPush = 0;
+      J.nPop = P;
+      J.nPush = Q;
+      J.serialBase = T->serialCounter;
+      T->serialCounter += Q;
+      for (int k = 0; k < cj.n_pop; ++k) S.failedAt.pop_back();
+      for (int k = 0; k < cj.n_push; ++k) S.failedAt.push_back(2);
+      S.depth = S.depth - cj.n_pop + cj.n_push;
+      J.depthAfter = S.depth;
+    }
+    S.failed = 2;
+    job_counts(T, J);
+    updOff[j + 1] = updOff[j] + J.nUpd;
+    filtOff[j + 1] = filtOff[j] + J.nFilt;
+    if (J.nPop > 0 || J.nPush > 0) prep.push_back(j);
+  }
+  // stage to the device
+  const size_t nOff = 2 * (size_t)(n_jobs + 1) + prep.size() + 1;
+  if (q->capJobs < (size_t)n_jobs || q->capPinned < nOff) {
+    HIPCHK(hipStreamSynchronize(stream));
+    if (q->dJobs) (void)hipFree(q->dJobs);
+    if (q->dOff) (void)hipFree(q->dOff);
+    if (q->pJobs) (void)hipHostFree(q->pJobs);
+    if (q->pOff) (void)hipHostFree(q->pOff);
+    q->capJobs = std::max<size_t>(n_jobs, 2 * q->capJobs);
+    q->capPinned = std::max<size_t>(nOff, 2 * (q->capJobs + 1) + q->capJobs + 1);
+    HIPCHK(hipMalloc(&q->dJobs, sizeof(DevJob) * q->capJobs));
+    HIPCHK(hipMalloc(&q->dOff, sizeof(int32_t) * q->capPinned));
+    HIPCHK(hipHostMalloc((void**)&q->pJobs, sizeof(DevJob) * q->capJobs, hipHostMallocDefault));
+    HIPCHK(hipHostMalloc((void**)&q->pOff, sizeof(int32_t) * q->capPinned, hipHostMallocDefault));
+  } else {
+    HIPCHK(hipEventSynchronize(q->staged));  // previous staging copy has left the pinned buffers
+  }
+  memcpy(q->pJobs, q->hJobs.data(), sizeof(DevJob) * n_jobs);
+  memcpy(q->pOff, updOff.data(), sizeof(int32_t) * (n_jobs + 1));
+  memcpy(q->pOff + (n_jobs + 1), filtOff.data(), sizeof(int32_t) * (n_jobs + 1));
+  if (!prep.empty()) memcpy(q->pOff + 2 * (n_jobs + 1), prep.data(), sizeof(int32_t) * prep.size());
+  HIPCHK(hipMemcpyAsync(q->dJobs, q->pJobs, sizeof(DevJob) * n_jobs, hipMemcpyHostToDevice, stream));
+  HIPCHK(hipMemcpyAsync(q->dOff, q->pOff, sizeof(int32_t) * nOff, hipMemcpyHostToDevice, stream));
+  HIPCHK(hipEventRecord(q->staged, stream));
+  KArgs a{};
+  a.jobs = q->dJobs;
+  a.updOff = q->dOff;
+  a.filtOff = q->dOff + (n_jobs + 1);
+  a.prepList = q->dOff + 2 * (n_jobs + 1);
+  a.nJobs = n_jobs;
+  a.nPrep = (int32_t)prep.size();
+  a.nUpd = updOff[n_jobs];
+  a.nFilt = filtOff[n_jobs];
+  a.queue = q->queue;
+  a.hostErr = nullptr;
+  const int total = a.nPrep + a.nUpd + a.nFilt;
+  if (total > 0) HIPCHK(launch_propagate(a, std::min(total, MAX_GRID), stream));
+  return CT_OK;
+}
+
+}  // extern "C"

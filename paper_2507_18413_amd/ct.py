@@ -1,0 +1,234 @@
+"""Thin Python binding of libct.so (argument marshalling only).
+
+Every step of propagation runs in the library's HIP kernels; this module only
+converts numpy arrays / torch tensors to pointers and back.  If the library
+is missing it raises: there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import re
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+LIB_PATH = os.path.join(HERE, "libct.so")
+HEADER = os.path.join(ROOT, "include", "ct.h")
+
+OK, FAIL = 0, 1
+E_INVALID, E_NOT_SUBSET, E_STATE, E_NOMEM, E_DEVICE = -1, -2, -3, -4, -5
+BRANCH_AUTO, BRANCH_RESET, BRANCH_INCREMENTAL = 0, 1, 2
+JOB_PROPAGATE, JOB_FROM_ROOT = 1, 2
+
+
+class CTError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"CT error {code}: {msg}")
+        self.code = code
+
+
+class ct_config(C.Structure):
+    _fields_ = [("branch_policy", C.c_int32), ("max_depth", C.c_int32)]
+
+
+class ct_layout_info(C.Structure):
+    _fields_ = [("n_vars", C.c_int32), ("D", C.c_int32), ("W", C.c_int64), ("n_tuples", C.c_int64),
+                ("rows", C.c_int32), ("n_slots", C.c_int32), ("granules", C.c_int32),
+                ("root_failed", C.c_int32)]
+
+
+class ct_stats(C.Structure):
+    _fields_ = [(k, C.c_int64) for k in ("jobs", "granules_in", "rows_or", "granule_rows",
+                                         "trail_granules", "residue_checks", "residue_misses",
+                                         "scan_granules")]
+
+    def as_dict(self):
+        return {k: int(getattr(self, k)) for k, _ in self._fields_}
+
+
+class ct_job(C.Structure):
+    _fields_ = [("table", C.c_void_p), ("slot", C.c_int32), ("flags", C.c_uint32),
+                ("n_pop", C.c_int32), ("n_push", C.c_int32), ("dom_in", C.c_void_p),
+                ("dom_out", C.c_void_p), ("ct_out", C.c_void_p)]
+
+
+_lib = None
+
+
+def exported_names():
+    """Function names declared in include/ct.h."""
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"^(?:int|void|const char \*)\s*(ct_\w+)\s*\(", text, re.M)))
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"HIP library {LIB_PATH} is not built; run __graft_entry__.build()")
+        L = C.CDLL(LIB_PATH)
+        P, I32, I64 = C.c_void_p, C.c_int32, C.c_int64
+        sig = {
+            "ct_create": ([P, I64, I32, P, P, P, P, C.POINTER(P)], C.c_int),
+            "ct_destroy": ([P], None),
+            "ct_layout": ([P, C.POINTER(ct_layout_info), P], C.c_int),
+            "ct_get_supports": ([P, I32, I32, P], C.c_int),
+            "ct_propagate": ([P, P, P, P, P], C.c_int),
+            "ct_propagate_slot": ([P, I32, P, P, P, P], C.c_int),
+            "ct_push": ([P], C.c_int),
+            "ct_pop": ([P], C.c_int),
+            "ct_push_slot": ([P, I32], C.c_int),
+            "ct_pop_slot": ([P, I32], C.c_int),
+            "ct_get_state": ([P, I32, P, P], C.c_int),
+            "ct_slots_alloc": ([P, I32, I32, C.POINTER(I32)], C.c_int),
+            "ct_slot_stats": ([P, I32, C.POINTER(ct_stats)], C.c_int),
+            "ct_propagate_batch": ([P, I32, P, P], C.c_int),
+            "ct_last_error": ([], C.c_char_p),
+        }
+        for name, (args, res) in sig.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = res
+        _lib = L
+    return _lib
+
+
+def last_error() -> str:
+    return lib().ct_last_error().decode()
+
+
+def _p(a):
+    return None if a is None else a.ctypes.data_as(C.c_void_p)
+
+
+def _ptr(x):
+    """Device pointer of a torch tensor, or an int address."""
+    if x is None:
+        return None
+    if isinstance(x, int):
+        return x
+    return x.data_ptr()
+
+
+class Table:
+    """One table constraint on the GPU with its slots (reversible states)."""
+
+    def __init__(self, tuples, lo, dsizes, init_dom=None, branch_policy=BRANCH_AUTO, max_depth=256):
+        L = lib()
+        tuples = np.ascontiguousarray(tuples, dtype=np.int32)
+        lo = np.ascontiguousarray(lo, dtype=np.int32)
+        ds = np.ascontiguousarray(dsizes, dtype=np.int32)
+        t = int(tuples.shape[0]) if tuples.ndim == 2 and tuples.size else 0
+        if init_dom is not None:
+            init_dom = np.ascontiguousarray(init_dom, dtype=np.uint64)
+        cfg = ct_config(int(branch_policy), int(max_depth))
+        h = C.c_void_p()
+        st = L.ct_create(_p(tuples) if t else None, t, int(ds.shape[0]), _p(lo), _p(ds), _p(init_dom),
+                         C.byref(cfg), C.byref(h))
+        if st < 0:
+            raise CTError(st, last_error())
+        self.h = h
+        self.create_status = st
+        info = ct_layout_info()
+        off = np.zeros(ds.shape[0], np.int32)
+        L.ct_layout(h, C.byref(info), _p(off))
+        self.n, self.D, self.W, self.t = info.n_vars, info.D, info.W, info.n_tuples
+        self.rows, self.granules, self.root_failed = info.rows, info.granules, bool(info.root_failed)
+        self.dom_off = off
+
+    @property
+    def n_slots(self):
+        info = ct_layout_info()
+        lib().ct_layout(self.h, C.byref(info), None)
+        return info.n_slots
+
+    def close(self):
+        if getattr(self, "h", None) is not None and self.h.value is not None:
+            lib().ct_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def propagate(self, dom_in, slot=0, want_ct=False, want_stats=False):
+        dom_in = np.ascontiguousarray(dom_in, dtype=np.uint64)
+        assert dom_in.shape[0] == self.D
+        dom_out = dom_in.copy()
+        ct = np.zeros(max(self.W, 1), np.uint64) if want_ct else None
+        stats = ct_stats() if want_stats else None
+        st = lib().ct_propagate_slot(self.h, int(slot), _p(dom_in), _p(dom_out), _p(ct),
+                                     C.byref(stats) if stats is not None else None)
+        if st == E_DEVICE:
+            raise CTError(st, last_error())
+        out = [st, dom_out]
+        if want_ct:
+            out.append(ct[: self.W])
+        if want_stats:
+            out.append(stats.as_dict())
+        return tuple(out)
+
+    def push(self, slot=0):
+        return lib().ct_push_slot(self.h, int(slot))
+
+    def pop(self, slot=0):
+        return lib().ct_pop_slot(self.h, int(slot))
+
+    def state(self, slot=0):
+        dom = np.zeros(self.D, np.uint64)
+        ct = np.zeros(max(self.W, 1), np.uint64)
+        st = lib().ct_get_state(self.h, int(slot), _p(dom), _p(ct))
+        if st < 0:
+            raise CTError(st, last_error())
+        return dom, ct[: self.W]
+
+    def domains(self, slot=0):
+        return self.state(slot)[0]
+
+    def supports(self, row_begin=0, n_rows=None):
+        n_rows = self.rows - row_begin if n_rows is None else n_rows
+        out = np.zeros((n_rows, max(self.W, 1)), np.uint64)
+        st = lib().ct_get_supports(self.h, int(row_begin), int(n_rows), _p(out))
+        if st < 0:
+            raise CTError(st, last_error())
+        return out[:, : self.W]
+
+    def slots_alloc(self, n, max_depth=-1):
+        first = C.c_int32()
+        st = lib().ct_slots_alloc(self.h, int(n), int(max_depth), C.byref(first))
+        if st < 0:
+            raise CTError(st, last_error())
+        return first.value
+
+    def stats(self, slot=0):
+        s = ct_stats()
+        st = lib().ct_slot_stats(self.h, int(slot), C.byref(s))
+        if st < 0:
+            raise CTError(st, last_error())
+        return s.as_dict()
+
+
+def propagate_batch(jobs, status_dev, stream=None):
+    """jobs: iterable of dicts with keys table, slot, flags, n_pop, n_push,
+    dom_in, dom_out, ct_out (torch tensors or device addresses).
+    status_dev: int32 device tensor (or address) with one entry per job."""
+    jobs = list(jobs)
+    arr = (ct_job * max(1, len(jobs)))()
+    for k, j in enumerate(jobs):
+        arr[k].table = j["table"].h.value
+        arr[k].slot = int(j.get("slot", 0))
+        arr[k].flags = int(j.get("flags", JOB_PROPAGATE))
+        arr[k].n_pop = int(j.get("n_pop", 0))
+        arr[k].n_push = int(j.get("n_push", 0))
+        arr[k].dom_in = _ptr(j.get("dom_in"))
+        arr[k].dom_out = _ptr(j.get("dom_out"))
+        arr[k].ct_out = _ptr(j.get("ct_out"))
+    s = None if stream is None else (stream if isinstance(stream, int) else stream.cuda_stream)
+    st = lib().ct_propagate_batch(C.cast(arr, C.c_void_p), len(jobs), s, _ptr(status_dev))
+    if st < 0:
+        raise CTError(st, last_error())
+    return st

@@ -1,0 +1,73 @@
+"""The C-ABI library loads and exports every function include/ct.h declares
+(no compute calls: this runs without a GPU)."""
+import ctypes
+import os
+import subprocess
+
+import pytest
+
+from paper_2507_18413_amd import ct
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def libpath():
+    if not os.path.exists(ct.LIB_PATH):
+        from paper_2507_18413_amd import build
+        build.build()
+    return ct.LIB_PATH
+
+
+def test_header_declares_the_boundary():
+    names = ct.exported_names()
+    for need in ["ct_create", "ct_destroy", "ct_layout", "ct_get_supports", "ct_propagate",
+                 "ct_propagate_slot", "ct_push", "ct_pop", "ct_push_slot", "ct_pop_slot",
+                 "ct_get_state", "ct_slots_alloc", "ct_slot_stats", "ct_propagate_batch",
+                 "ct_last_error"]:
+        assert need in names
+
+
+def test_library_exports_every_declared_symbol(libpath):
+    L = ctypes.CDLL(libpath)
+    for name in ct.exported_names():
+        assert hasattr(L, name), name
+    out = subprocess.run(["nm", "-D", "--defined-only", libpath], capture_output=True, text=True).stdout
+    exported = {ln.split()[-1] for ln in out.splitlines() if " T " in ln}
+    for name in ct.exported_names():
+        assert name in exported, name
+
+
+def test_binding_signatures_cover_header(libpath):
+    L = ct.lib()
+    for name in ct.exported_names():
+        assert getattr(L, name).argtypes is not None or name == "ct_last_error", name
+
+
+def test_host_side_errors_without_device(libpath):
+    # argument validation happens before any HIP call
+    L = ct.lib()
+    h = ctypes.c_void_p()
+    lo = (ctypes.c_int32 * 1)(0)
+    ds = (ctypes.c_int32 * 1)(0)
+    assert L.ct_create(None, 0, 1, lo, ds, None, None, ctypes.byref(h)) == ct.E_INVALID
+    assert L.ct_create(None, 0, 0, lo, ds, None, None, ctypes.byref(h)) == ct.E_INVALID
+    assert L.ct_create(None, -1, 1, lo, ds, None, None, ctypes.byref(h)) == ct.E_INVALID
+    assert "arity" in ct.last_error() or "n_tuples" in ct.last_error()
+    assert L.ct_propagate_batch(None, -1, None, None) == ct.E_INVALID
+
+
+def test_no_oracle_in_product_path():
+    """The package neither imports nor links the oracle."""
+    import re
+    pkg = os.path.join(ROOT, "paper_2507_18413_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for f in files:
+            path = os.path.join(dirpath, f)
+            if f.endswith(".py"):
+                text = open(path).read()
+                assert not re.search(r"^\s*(from|import)\s+oracle", text, re.M), path
+                assert "libct_oracle" not in text and "cto_" not in text, path
+            elif f.endswith((".cpp", ".hip", ".h")):
+                text = open(path).read()
+                assert "cto_" not in text and "ct_oracle" not in text, path

@@ -1,0 +1,341 @@
+"""Parity of the HIP library with the CPU oracle, call by call, bit-exact.
+
+Every case drives the GPU (through the C ABI) and the oracle with the same
+seeded inputs and compares statuses, domains and currTable after every
+operation.  The work is exact integer bit manipulation, so the tolerance is
+zero.
+"""
+import json
+import os
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2507_18413_amd import ct
+from paper_2507_18413_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "table1.json")
+
+
+def say(*a):
+    print("[gpu-case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+def bits_of(words, t):
+    return [int((int(words[j // 64]) >> (j % 64)) & 1) for j in range(t)]
+
+
+def pair(tup, lo, ds, init=None, policy=ct.BRANCH_AUTO, max_depth=256):
+    say("create", f"t={len(tup)}", f"n={len(ds)}", f"policy={policy}")
+    g = ct.Table(tup, lo, ds, init_dom=init, branch_policy=policy, max_depth=max_depth)
+    o = O.OracleTable(tup, lo, ds, init_dom=init)
+    return g, o
+
+
+def same_state(g, o, slot=0, where=""):
+    gd, gc = g.state(slot)
+    od, oc, of = o.state()
+    assert (gd == od).all(), f"domains differ {where}"
+    if not of:
+        assert (gc == oc).all(), f"currTable differs {where}"
+
+
+def random_subset(rng, lay, dom, p_keep):
+    out = dom.copy()
+    for i in range(lay.n):
+        for a in lay.values(dom, i):
+            if rng.random() > p_keep:
+                lay.clear(out, i, int(a))
+    return out
+
+
+# --------------------------------------------------------------------------
+def test_table1_on_gpu():
+    g = json.load(open(GOLDEN))
+    tup = np.array(g["tuples"], np.int32)
+    G, Ot = pair(tup, g["lo"], g["dsizes"])
+    S = G.supports()
+    for name, want in g["printed_support_rows"].items():
+        if name == "comment":
+            continue
+        i = {"x1": 0, "x2": 1, "x3": 2}[name.split("=")[0]]
+        row = 4 * i + int(name.split("=")[1]) - 1
+        assert bits_of(S[row], 5) == want, name
+    same_state(G, Ot, where="root")
+    lay = W.DomLayout(g["dsizes"], g["lo"])
+    dom_in = lay.from_sets([[v - 1 for v in s] for s in g["derived"]["dom_giving_printed_currtable"]])
+    st, dom_out, c = G.propagate(dom_in, want_ct=True)
+    assert st == ct.OK
+    assert bits_of(c, 5) == g["printed_currtable"]
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_support_builder_bit_exact(seed):
+    rng = W.rng_for(seed, 200, 0)
+    n = int(rng.integers(1, 6))
+    ds = rng.integers(1, 140, size=n).astype(np.int32)
+    lo = rng.integers(-50, 50, size=n).astype(np.int32)
+    t = int(rng.integers(1, 64 * 64 * 3 + 50))
+    tup = np.stack([rng.integers(lo[i] - 2, lo[i] + ds[i] + 2, size=t) for i in range(n)], 1).astype(np.int32)
+    G, Ot = pair(tup, lo, ds)
+    S = G.supports()
+    for r in range(G.rows):
+        assert (S[r] == Ot.support_row(r)).all(), r
+    same_state(G, Ot, where="root")
+
+
+def random_case(rng):
+    n = int(rng.integers(1, 6))
+    ds = rng.integers(1, 12, size=n).astype(np.int32)
+    lo = rng.integers(-3, 4, size=n).astype(np.int32)
+    t = int(rng.choice([0, 1, 5, 63, 64, 65, 300, 4096, 4097, 9000]))
+    tup = np.stack([rng.integers(lo[i] - 1, lo[i] + ds[i] + 1, size=t) for i in range(n)], 1).astype(np.int32) \
+        if t else np.zeros((0, n), np.int32)
+    if t and rng.random() < 0.3:
+        tup = np.concatenate([tup, tup[: max(1, t // 3)]])
+    return tup, lo, ds
+
+
+@pytest.mark.parametrize("chunk", range(6))
+def test_random_sequences_vs_oracle(chunk):
+    rng = W.rng_for(chunk, 201, 0)
+    for case in range(12):
+        tup, lo, ds = random_case(rng)
+        lay = W.DomLayout(ds, lo)
+        init = random_subset(rng, lay, lay.full(), 0.8) if rng.random() < 0.3 else None
+        policy = int(rng.integers(0, 3))
+        say(f"chunk={chunk} case={case}")
+        G, Ot = pair(tup, lo, ds, init=init, policy=policy)
+        assert (G.create_status == ct.FAIL) == (Ot.create_status == O.FAIL)
+        if Ot.create_status == O.FAIL:
+            st, _ = G.propagate(lay.full() if init is None else init)
+            assert st == ct.E_STATE
+            continue
+        same_state(G, Ot, where="root")
+        for step in range(25):
+            r = rng.random()
+            if r < 0.25 and Ot.depth > 0:
+                assert G.pop() == O.OK and Ot.pop() == O.OK
+                same_state(G, Ot, where=f"pop step {step}")
+                continue
+            if r < 0.6:
+                a, b = G.push(), Ot.push()
+                assert a == b, (a, b)
+            dom = Ot.domains()
+            dom_in = random_subset(rng, lay, dom, float(rng.uniform(0.5, 1.0)))
+            if rng.random() < 0.05:         # a value that is not present any more
+                dom_in = lay.full()
+            gs, gd, gc = G.propagate(dom_in, want_ct=True)
+            os_, od, oc = Ot.propagate(dom_in, want_ct=True)
+            assert gs == os_, (step, gs, os_)
+            if os_ == O.OK:
+                assert (gd == od).all(), step
+                assert (gc == oc).all(), step
+            if os_ == O.FAIL:
+                assert not gc.any()
+                if Ot.depth > 0:
+                    assert G.pop() == O.OK and Ot.pop() == O.OK
+                else:
+                    assert G.push() == ct.E_STATE and Ot.push() == O.E_STATE
+                    break
+            same_state(G, Ot, where=f"step {step}")
+
+
+def run_plain(spec, n_calls, picker, config, check_every=1):
+    G, Ot = pair(spec.tuples, spec.lo, spec.dsizes)
+    lay = spec.layout()
+    same_state(G, Ot, where="root")
+    rng = W.rng_for(W.DEFAULT_SEED, config, 9)
+    bt = W.Backtracker(rng)
+    depth = 0
+    for call in range(n_calls):
+        dom_in = picker(rng, lay, Ot.domains())
+        assert G.push() == ct.OK and Ot.push() == O.OK
+        depth += 1
+        gs, gd, gc = G.propagate(dom_in, want_ct=True)
+        os_, od, oc = Ot.propagate(dom_in, want_ct=True)
+        assert gs == os_, (call, gs, os_)
+        if os_ == O.OK and call % check_every == 0:
+            assert (gd == od).all(), call
+            assert (gc == oc).all(), call
+        for _ in range(bt.pops_after(os_ == O.FAIL, depth)):
+            assert G.pop() == ct.OK and Ot.pop() == O.OK
+            depth -= 1
+            if call % check_every == 0:
+                same_state(G, Ot, where=f"after pop at call {call}")
+    return G, Ot
+
+
+def test_config1_full():
+    say("config1: arity 3, d=8, 200 tuples, 100 calls")
+    run_plain(W.config1_table(), 100, W.pick_small_removal, 1)
+
+
+def test_config2_scaled():
+    say("config2 scaled: arity 5, d=50, 20,000 tuples, 300 calls")
+    spec = W.config2_table(t=20_000)
+    run_plain(spec, 300, W.pick_fraction_removal, 2)
+
+
+def test_config2_full():
+    say("config2 full: arity 5, d=50, 200,000 tuples, 1,000 calls")
+    spec = W.config2_table()
+    G, Ot = run_plain(spec, 1000, W.pick_fraction_removal, 2)
+    assert G.W == 3125
+
+
+def test_errors_match_oracle():
+    g = json.load(open(GOLDEN))
+    tup = np.array(g["tuples"], np.int32)
+    G, Ot = pair(tup, g["lo"], g["dsizes"])
+    lay = W.DomLayout(g["dsizes"], g["lo"])
+    root = Ot.domains()
+    stray = root.copy()
+    stray[0] |= np.uint64(1 << 5)
+    assert G.propagate(stray)[0] == ct.E_INVALID
+    grow = root.copy()
+    grow[2] |= np.uint64(1 << 1)
+    assert G.propagate(grow)[0] == ct.E_NOT_SUBSET
+    assert G.pop() == ct.E_STATE
+    same_state(G, Ot, where="after errors")
+    assert G.push() == ct.OK
+    empty = lay.from_sets([[], [0, 1, 2, 3], [0, 2]])
+    assert G.propagate(empty)[0] == ct.FAIL
+    assert G.propagate(root)[0] == ct.E_STATE
+    assert G.push() == ct.E_STATE
+    assert G.pop() == ct.OK
+    same_state(G, Ot, where="after fail + pop")
+
+
+def test_depth_limit():
+    spec = W.config1_table()
+    G = ct.Table(spec.tuples, spec.lo, spec.dsizes, max_depth=3)
+    for _ in range(3):
+        assert G.push() == ct.OK
+    assert G.push() == ct.E_NOMEM
+    for _ in range(3):
+        assert G.pop() == ct.OK
+    assert G.pop() == ct.E_STATE
+
+
+def test_multiword_domains_and_ragged_tail():
+    rng = W.rng_for(5, 202, 0)
+    ds = np.array([130, 3, 65, 1], np.int32)
+    lo = np.array([-7, 0, 100, 5], np.int32)
+    t = 64 * 64 * 2 + 17
+    tup = np.stack([rng.integers(lo[i], lo[i] + ds[i], size=t) for i in range(4)], 1).astype(np.int32)
+    G, Ot = pair(tup, lo, ds)
+    lay = W.DomLayout(ds, lo)
+    same_state(G, Ot, where="root")
+    for step in range(40):
+        G.push(); Ot.push()
+        dom_in = random_subset(rng, lay, Ot.domains(), 0.93)
+        gs, gd, gc = G.propagate(dom_in, want_ct=True)
+        os_, od, oc = Ot.propagate(dom_in, want_ct=True)
+        assert gs == os_
+        if os_ == O.OK:
+            assert (gd == od).all() and (gc == oc).all()
+        if os_ == O.FAIL or rng.random() < 0.2:
+            G.pop(); Ot.pop()
+            same_state(G, Ot, where=f"pop {step}")
+
+
+# --------------------------------------------------------------------------
+# batched jobs
+# --------------------------------------------------------------------------
+def to_dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a).view(np.int64)).cuda()
+
+
+def from_dev(t):
+    return t.cpu().numpy().view(np.uint64)
+
+
+def test_batch_from_root_nodes_vs_oracle():
+    import torch
+    say("batch: FROM_ROOT search nodes, Zipf table 60k tuples, 256 nodes")
+    spec = W.config4_table(t=60_000)
+    lay = spec.layout()
+    G, Ot = pair(spec.tuples, spec.lo, spec.dsizes)
+    root = Ot.domains()
+    nodes = W.config4_nodes(lay, root, 256)
+    first = G.slots_alloc(256, max_depth=0)
+    din = to_dev(nodes)
+    dout = torch.zeros_like(din)
+    cts = torch.zeros((256, G.W), dtype=torch.int64, device="cuda")
+    status = torch.full((256,), 99, dtype=torch.int32, device="cuda")
+    jobs = [dict(table=G, slot=first + k, flags=ct.JOB_PROPAGATE | ct.JOB_FROM_ROOT,
+                 dom_in=din[k], dom_out=dout[k], ct_out=cts[k]) for k in range(256)]
+    ct.propagate_batch(jobs, status)
+    torch.cuda.synchronize()
+    st = status.cpu().numpy()
+    got_dom = from_dev(dout)
+    got_ct = from_dev(cts)
+    for k in range(256):
+        Ot.push()
+        os_, od, oc = Ot.propagate(nodes[k], want_ct=True)
+        Ot.pop()
+        assert st[k] == os_, k
+        if os_ == O.OK:
+            assert (got_dom[k] == od).all(), k
+            assert (got_ct[k] == oc).all(), k
+            gd, gc = G.state(first + k)
+            assert (gd == od).all() and (gc == oc).all(), k
+    # a second batch reuses the slots from the root again
+    ct.propagate_batch(jobs[:64], status[:64])
+    torch.cuda.synchronize()
+    assert (from_dev(dout[:64]) == got_dom[:64]).all()
+
+
+def test_batch_with_backtracking_equals_sequential():
+    import torch
+    say("batch: 32 slots with pops/pushes vs single calls")
+    spec = W.config2_table(t=30_000, d=20, n=4)
+    lay = spec.layout()
+    Gb = ct.Table(spec.tuples, spec.lo, spec.dsizes)          # batched
+    Gs = ct.Table(spec.tuples, spec.lo, spec.dsizes)          # single calls
+    nsl = 32
+    fb = Gb.slots_alloc(nsl)
+    fs = Gs.slots_alloc(nsl)
+    rng = W.rng_for(1, 203, 0)
+    depth = np.zeros(nsl, int)
+    for rnd in range(12):
+        jobs, doms = [], []
+        for k in range(nsl):
+            n_pop = int(rng.integers(0, depth[k] + 1)) if rng.random() < 0.3 else 0
+            for _ in range(n_pop):
+                assert Gs.pop(fs + k) == ct.OK
+            n_push = int(rng.integers(0, 2))
+            for _ in range(n_push):
+                assert Gs.push(fs + k) == ct.OK
+            depth[k] += n_push - n_pop
+            dom_in = random_subset(rng, lay, Gs.domains(fs + k), 0.9)
+            doms.append(dom_in)
+            jobs.append(dict(slot=fb + k, n_pop=n_pop, n_push=n_push))
+        din = to_dev(np.stack(doms))
+        dout = torch.zeros_like(din)
+        status = torch.full((nsl,), 99, dtype=torch.int32, device="cuda")
+        bj = [dict(table=Gb, slot=j["slot"], flags=ct.JOB_PROPAGATE, n_pop=j["n_pop"],
+                   n_push=j["n_push"], dom_in=din[k], dom_out=dout[k]) for k, j in enumerate(jobs)]
+        ct.propagate_batch(bj, status)
+        torch.cuda.synchronize()
+        st = status.cpu().numpy()
+        gd = from_dev(dout)
+        for k in range(nsl):
+            ss, sd, sc = Gs.propagate(doms[k], slot=fs + k, want_ct=True)
+            assert st[k] == ss, (rnd, k, st[k], ss)
+            if ss == ct.OK:
+                assert (gd[k] == sd).all()
+                bd, bc = Gb.state(fb + k)
+                assert (bd == sd).all() and (bc == sc).all()
+            if ss == ct.FAIL:
+                # both pop one level so the slot is usable again
+                if depth[k] > 0:
+                    Gs.pop(fs + k)
+                    Gb.pop(fb + k)
+                    depth[k] -= 1
