@@ -196,6 +196,14 @@ typedef struct {
  */
 int ct_propagate_batch(const ct_job *jobs, int32_t n_jobs, void *stream, int32_t *status_dev);
 
+/* Kernel timing of the synchronous calls (ct_propagate*, flushes of
+ * ct_push/ct_pop): when on, each launch on the table's internal stream is
+ * bracketed by two HIP events and the elapsed time is accumulated.
+ * ct_get_timing returns the cumulative kernel milliseconds and launch count
+ * since timing was last switched on. */
+int ct_set_timing(ct_table *t, int32_t on);
+int ct_get_timing(ct_table *t, double *kernel_ms, int64_t *launches);
+
 /* Thread-local message of the last error ("" if none). */
 const char *ct_last_error(void);
 

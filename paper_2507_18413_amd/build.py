@@ -1,4 +1,12 @@
-"""Build the HIP library libct.so for gfx950 in-tree (hipcc, no JIT cache)."""
+"""Build the HIP library libct.so for gfx950 in-tree (hipcc, no JIT cache).
+
+Device code is compiled by hipcc for gfx950.  The shared library is linked
+against the HIP runtime that PyTorch loads (torch/lib/libamdhip64.so) when
+PyTorch is installed: streams and device pointers handed over by torch are
+then objects of the same runtime instance, and a process holds one HIP
+runtime only.
+"""
+import glob
 import os
 import subprocess
 import sys
@@ -7,21 +15,54 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libct.so")
+BUILD = os.path.join(ROOT, "_build")
 SOURCES = [os.path.join(CSRC, "ct_kernels.hip"), os.path.join(CSRC, "ct_runtime.cpp")]
 ARCH = os.environ.get("CT_OFFLOAD_ARCH", "gfx950")
+HIPCC = "/opt/rocm/bin/hipcc"
 
 
-def command(out):
-    return ["/opt/rocm/bin/hipcc", f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-shared",
+def torch_hip_runtime():
+    try:
+        import importlib.util
+        spec = importlib.util.find_spec("torch")
+        if spec is None or not spec.origin:
+            return None
+        libdir = os.path.join(os.path.dirname(spec.origin), "lib")
+        if glob.glob(os.path.join(libdir, "libamdhip64.so*")):
+            return libdir
+    except Exception:
+        pass
+    return None
+
+
+def compile_cmd(src, obj):
+    return [HIPCC, f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-c",
             "-Wall", "-Wno-unused-function",
             # packed fp32 instructions stay off in every device pass
             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-            "-I", os.path.join(ROOT, "include"), "-I", CSRC, *SOURCES, "-o", out]
+            "-I", os.path.join(ROOT, "include"), "-I", CSRC, src, "-o", obj]
+
+
+def link_cmd(objs, out):
+    libdir = torch_hip_runtime()
+    if libdir:
+        return ["g++", "-shared", "-o", out, *objs, "-L", libdir, "-l:libamdhip64.so",
+                f"-Wl,-rpath,{libdir}", "-Wl,--no-undefined"]
+    return [HIPCC, "-shared", f"--offload-arch={ARCH}", "-o", out, *objs]
 
 
 def build(verbose: bool = False) -> str:
+    os.makedirs(BUILD, exist_ok=True)
+    objs = []
+    for src in SOURCES:
+        obj = os.path.join(BUILD, os.path.basename(src) + ".o")
+        cmd = compile_cmd(src, obj)
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        subprocess.run(cmd, check=True)
+        objs.append(obj)
     tmp = LIB + ".tmp"
-    cmd = command(tmp)
+    cmd = link_cmd(objs, tmp)
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)

@@ -140,6 +140,11 @@ struct ct_table {
   uint64_t* pDomIn = nullptr;   // D words (used when D > INLINE_WORDS)
   uint64_t* pCt = nullptr;      // W words (lazily)
   int32_t* pStatus = nullptr;
+  // optional kernel timing of synchronous launches
+  bool timing = false;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  double kernelMs = 0.0;
+  int64_t launches = 0;
 };
 
 namespace {
@@ -241,8 +246,16 @@ int run_single(ct_table* T, DevJob& J, const uint64_t* dom_in_host) {
   if (total == 0) return CT_OK;
   *T->q.hostErr = 0;
   *T->pStatus = 99;
+  if (T->timing) HIPCHK(hipEventRecord(T->ev0, T->stream));
   HIPCHK(launch_propagate(a, std::min(total, MAX_GRID), T->stream));
+  if (T->timing) HIPCHK(hipEventRecord(T->ev1, T->stream));
   hipError_t e = hipStreamSynchronize(T->stream);
+  if (e == hipSuccess && T->timing) {
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, T->ev0, T->ev1));
+    T->kernelMs += ms;
+    T->launches++;
+  }
   if (e != hipSuccess) {
     T->poisoned = true;
     return fail(CT_E_DEVICE, "kernel failed: %s", hipGetErrorString(e));
@@ -314,6 +327,8 @@ void ct_destroy(ct_table* T) {
   if (T->pDomIn) (void)hipHostFree(T->pDomIn);
   if (T->pCt) (void)hipHostFree(T->pCt);
   if (T->pStatus) (void)hipHostFree(T->pStatus);
+  if (T->ev0) (void)hipEventDestroy(T->ev0);
+  if (T->ev1) (void)hipEventDestroy(T->ev1);
   if (T->stream) (void)hipStreamDestroy(T->stream);
   delete T;
 }
@@ -666,6 +681,26 @@ int ct_slot_stats(ct_table* T, int32_t slot, ct_stats* st) {
   st->residue_checks = (int64_t)s.stats[S_RES_CHECK];
   st->residue_misses = (int64_t)s.stats[S_RES_MISS];
   st->scan_granules = (int64_t)s.stats[S_SCAN];
+  return CT_OK;
+}
+
+int ct_set_timing(ct_table* T, int32_t on) {
+  int rc = check_poison(T);
+  if (rc) return rc;
+  if (on && !T->ev0) {
+    HIPCHK(hipEventCreate(&T->ev0));
+    HIPCHK(hipEventCreate(&T->ev1));
+  }
+  T->timing = on != 0;
+  T->kernelMs = 0.0;
+  T->launches = 0;
+  return CT_OK;
+}
+
+int ct_get_timing(ct_table* T, double* kernel_ms, int64_t* launches) {
+  if (!T) return fail(CT_E_INVALID, "null table");
+  if (kernel_ms) *kernel_ms = T->kernelMs;
+  if (launches) *launches = T->launches;
   return CT_OK;
 }
 

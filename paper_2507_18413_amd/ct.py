@@ -63,11 +63,26 @@ def exported_names():
     return sorted(set(re.findall(r"^(?:int|void|const char \*)\s*(ct_\w+)\s*\(", text, re.M)))
 
 
+def _preload_shared_hip_runtime():
+    """Load the HIP runtime PyTorch ships before libct.so, so that the
+    library, torch's streams and torch's allocations share one runtime
+    (the library's libamdhip64.so.7 dependency resolves to the loaded copy,
+    and a later `import torch` maps the same file again)."""
+    import importlib.util
+    spec = importlib.util.find_spec("torch")
+    if spec is None or not spec.origin:
+        return
+    path = os.path.join(os.path.dirname(spec.origin), "lib", "libamdhip64.so")
+    if os.path.exists(path):
+        C.CDLL(path, mode=C.RTLD_GLOBAL)
+
+
 def lib():
     global _lib
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"HIP library {LIB_PATH} is not built; run __graft_entry__.build()")
+        _preload_shared_hip_runtime()
         L = C.CDLL(LIB_PATH)
         P, I32, I64 = C.c_void_p, C.c_int32, C.c_int64
         sig = {
@@ -85,6 +100,8 @@ def lib():
             "ct_slots_alloc": ([P, I32, I32, C.POINTER(I32)], C.c_int),
             "ct_slot_stats": ([P, I32, C.POINTER(ct_stats)], C.c_int),
             "ct_propagate_batch": ([P, I32, P, P], C.c_int),
+            "ct_set_timing": ([P, I32], C.c_int),
+            "ct_get_timing": ([P, C.POINTER(C.c_double), C.POINTER(I64)], C.c_int),
             "ct_last_error": ([], C.c_char_p),
         }
         for name, (args, res) in sig.items():
@@ -203,6 +220,17 @@ class Table:
         if st < 0:
             raise CTError(st, last_error())
         return first.value
+
+    def set_timing(self, on=True):
+        st = lib().ct_set_timing(self.h, 1 if on else 0)
+        if st < 0:
+            raise CTError(st, last_error())
+
+    def timing(self):
+        """(cumulative kernel milliseconds, launches) since set_timing(True)."""
+        ms, n = C.c_double(), C.c_int64()
+        lib().ct_get_timing(self.h, C.byref(ms), C.byref(n))
+        return ms.value, n.value
 
     def stats(self, slot=0):
         s = ct_stats()
