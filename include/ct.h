@@ -196,6 +196,11 @@ typedef struct {
  */
 int ct_propagate_batch(const ct_job *jobs, int32_t n_jobs, void *stream, int32_t *status_dev);
 
+/* Synchronizes `stream` and reports whether a batch launched on it hit a
+ * device-side error (a bounded wait that expired): CT_OK or CT_E_DEVICE (the
+ * error is cleared; the slots of the affected jobs are undefined). */
+int ct_batch_status(void *stream);
+
 /* Kernel timing of the synchronous calls (ct_propagate*, flushes of
  * ct_push/ct_pop): when on, each launch on the table's internal stream is
  * bracketed by two HIP events and the elapsed time is accumulated.

@@ -45,6 +45,7 @@ constexpr uint32_t JF_PROPAGATE = 1u;
 constexpr uint32_t JF_FROM_ROOT = 2u;
 constexpr uint32_t JF_ROOT = 4u;      // creation: every variable takes the reset branch
 constexpr uint32_t JF_INLINE_DOM = 8u;
+constexpr uint32_t JF_HOST_OUT = 16u;   // status / outputs in host memory: system-scope release
 
 struct VarDesc {
   int32_t rowStart, dsize, domOff, domWords;
@@ -117,7 +118,7 @@ struct KArgs {
   const DevJob* jobs;      // nullptr: single job in `job`
   const int32_t* updOff;   // nJobs + 1 prefix sums of update items (nullptr for one job)
   const int32_t* filtOff;  // nJobs + 1 prefix sums of filter items
-  const int32_t* prepList; // jobs that need a prep item (pops/pushes)
+  const int32_t* prepList; // jobs that need a prep item (pops, or only pushes/pops)
   int32_t nJobs, nPrep, nUpd, nFilt;
   int32_t* queue;          // [0] head, [1] exit count, [2] launches, [3] error
   int32_t* hostErr;        // nullable: error word copied here by the last block

@@ -5,19 +5,22 @@
 // coalesced 512-byte granule loads (one word per lane of a wave64), wave
 // ballots and LDS.
 //
-// One persistent kernel executes a batch of propagation jobs from a device
-// work queue.  Queue items, in dequeue order:
-//   prep   (one per job that pops or pushes)  backtrack restore / level push
+// One persistent kernel executes a batch of propagation jobs as a list of
+// work items, in this order:
+//   prep   (jobs that pop, and pure push/pop jobs)  backtrack restore, pushes
 //   update (nUpd per job)   updateTable (Alg. 2) over 8 granules each, with the
 //                           Delta / s_val / s_sup prologue of Alg. 1 recomputed
 //                           per item in LDS; the last update item of a job
-//                           partitions the sparse index and decides FAIL
+//                           records the job's pushes, partitions the sparse
+//                           index and decides FAIL (Alg. 1 line 5)
 //   filter (nFilt per job)  filterDomains (Alg. 3), one domain word per wave,
 //                           residue word first, then a scan of active granules
-// An item only waits for items of its own job that precede it in the queue
-// (update waits for prep when the job pops; filter waits for the job's last
-// update item).  Every dequeued item belongs to a running workgroup, so every
-// wait ends; waits are also bounded and report a device error on expiry.
+// Workgroup b starts with item b; when the grid is smaller than the item
+// count the remaining items are taken from a device queue in increasing
+// order.  An item only waits for earlier items of its own job (update waits
+// for prep when the job pops; filter waits for the job's last update item).
+// Waits are bounded: on expiry the kernel records a device error and the
+// remaining work of the launch is skipped.
 #include <hip/hip_runtime.h>
 
 #include "ct_device.h"
@@ -50,31 +53,59 @@ struct Shared {
   int32_t segOf[MAX_ARITY];   // var -> segment, -1 if not in s_val
   int32_t segEnd[MAX_ARITY];  // exclusive end of segment rows
   int32_t segInc[MAX_ARITY];
-  int32_t segVar[MAX_ARITY];
-  int32_t scan[BLOCK];
+  int32_t wsum[WAVES];
   uint64_t din[MAX_D];
-  union {
-    uint16_t rows[MAX_ROWS];
-    int32_t part[MAX_GRAN];
-  } u;
+  uint16_t rows[MAX_ROWS];
 };
 
+// Record a device error: the host sees it through hostErr (pinned) and the
+// other workgroups of the launch stop waiting.
+__device__ void raise_error(const KArgs& a, int code) {
+  atomicExch(&a.queue[3], code);
+  if (a.hostErr) {
+    __hip_atomic_store(a.hostErr, code, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+  }
+}
+
 // Thread 0 spins until *flag == want; the result is broadcast to the block.
-__device__ bool block_wait(int32_t* flag, int32_t want, int32_t* err, Shared& sh) {
+__device__ bool block_wait(const KArgs& a, int32_t* flag, int32_t want, Shared& sh) {
   if (threadIdx.x == 0) {
     int ok = 1;
     for (uint32_t it = 0;; ++it) {
       if (ld_acquire(flag) == want) break;
-      if (ld_relaxed(err)) { ok = 0; break; }
-      if (it > SPIN_LIMIT) { atomicExch(err, 1); ok = 0; break; }
-      __builtin_amdgcn_s_sleep(2);
+      if (ld_relaxed(&a.queue[3])) { ok = 0; break; }
+      if (it > SPIN_LIMIT) { raise_error(a, 1); ok = 0; break; }
+      __builtin_amdgcn_s_sleep(1);
     }
     sh.ok = ok;
   }
   __syncthreads();
-  int ok = sh.ok;
+  const int ok = sh.ok;
   __syncthreads();
   return ok != 0;
+}
+
+// Exclusive prefix sum over the block; *total receives the sum.
+__device__ int block_scan_excl(int v, int* total, Shared& sh) {
+  const int lane = lane_id(), w = wave_id();
+  int x = v;
+#pragma unroll
+  for (int d = 1; d < WAVE; d <<= 1) {
+    const int y = __shfl_up(x, d);
+    if (lane >= d) x += y;
+  }
+  if (lane == WAVE - 1) sh.wsum[w] = x;
+  __syncthreads();
+  int off = 0, tot = 0;
+#pragma unroll
+  for (int k = 0; k < WAVES; ++k) {
+    const int s = sh.wsum[k];
+    if (k < w) off += s;
+    tot += s;
+  }
+  __syncthreads();
+  *total = tot;
+  return off + x - v;
 }
 
 __device__ __forceinline__ const DevJob& job_of(const KArgs& a, int j) {
@@ -85,18 +116,55 @@ __device__ __forceinline__ uint64_t job_din(const KArgs& a, const DevJob& J, int
   return (J.flags & JF_INLINE_DOM) ? a.inl[k] : J.dom_in[k];
 }
 
+// Job status for the caller.  Outputs in host memory are published with a
+// system-scope release after a system-scope fence, so a host that sees the
+// status also sees the domain words written before it.
+__device__ void publish_status(const DevJob& J, int st) {
+  if (!J.status_out) return;
+  if (J.flags & JF_HOST_OUT) {
+    __threadfence_system();
+    __hip_atomic_store(J.status_out, st, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+  } else {
+    *J.status_out = st;
+  }
+}
+
+__device__ __forceinline__ void item_fence(const DevJob& J) {
+  if (J.flags & JF_HOST_OUT) __threadfence_system();
+  else __threadfence();
+}
+
 // largest j with off[j] <= x  (off has n + 1 entries, off[0] = 0)
 __device__ int find_job(const int32_t* off, int n, int x) {
   int lo = 0, hi = n;  // off[lo] <= x < off[hi]
   while (hi - lo > 1) {
-    int mid = (lo + hi) >> 1;
+    const int mid = (lo + hi) >> 1;
     if (off[mid] <= x) lo = mid; else hi = mid;
   }
   return lo;
 }
 
+// Push nPush levels recording (trailTop, limit, failed, serial, domains);
+// the k-th new level continues with serial serialBase + k.  Whole block.
+__device__ void push_levels(const DevJob& J, SlotDesc* s, int depth0, int64_t trailTop, int limit,
+                            int failed, int serial0, int D) {
+  for (int k = 0; k < J.nPush; ++k) {
+    const int d = depth0 + k;
+    for (int q = threadIdx.x; q < D; q += BLOCK) s->levelDom[(int64_t)d * D + q] = s->lastDom[q];
+    if (threadIdx.x == 0) {
+      Level L;
+      L.trailTop = trailTop;
+      L.limit = limit;
+      L.failed = failed;
+      L.serial = k == 0 ? serial0 : J.serialBase + k - 1;
+      L.pad = 0;
+      s->levels[d] = L;
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------
-// prep: pops then pushes (whole block)
+// prep: pops then pushes (whole block), for jobs that pop or only push/pop
 // ---------------------------------------------------------------------------
 __device__ void do_prep(const KArgs& a, const DevJob& J, Shared& sh) {
   SlotDesc* s = J.slot;
@@ -127,29 +195,28 @@ __device__ void do_prep(const KArgs& a, const DevJob& J, Shared& sh) {
     }
     __syncthreads();
   }
-  for (int k = 0; k < J.nPush; ++k) {
-    if (threadIdx.x == 0) sh.depth = s->depth;
-    __syncthreads();
-    const int d = sh.depth;
-    for (int q = threadIdx.x; q < D; q += BLOCK) s->levelDom[(int64_t)d * D + q] = s->lastDom[q];
+  if (J.nPush > 0) {
     if (threadIdx.x == 0) {
-      Level L;
-      L.trailTop = s->trailTop;
-      L.limit = s->limit;
-      L.failed = s->failed;
-      L.serial = s->serial;
-      L.pad = 0;
-      s->levels[d] = L;
-      s->depth = d + 1;
-      s->serial = J.serialBase + k;
+      sh.depth = s->depth;
+      sh.trailTop = s->trailTop;
+      sh.limit = s->limit;
+      sh.status = s->failed;
+      sh.serial = s->serial;
     }
     __syncthreads();
+    push_levels(J, s, sh.depth, sh.trailTop, sh.limit, sh.status, sh.serial, D);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      s->depth = sh.depth + J.nPush;
+      s->serial = J.serialBase + J.nPush - 1;
+    }
   }
   if (threadIdx.x == 0) {
-    __threadfence();
     if (!(J.flags & JF_PROPAGATE)) {
-      if (J.status_out) *J.status_out = ST_OK;
+      item_fence(J);
+      publish_status(J, ST_OK);
     } else {
+      __threadfence();
       st_release(&s->prepDone, 1);  // consumed (and reset) by the job's last update item
     }
   }
@@ -215,7 +282,6 @@ __device__ void prologue(const KArgs& a, const DevJob& J, Shared& sh) {
       nrows += inc ? sh.dcnt[i] : sh.size[i];
       sh.segOf[i] = nseg;
       sh.segInc[nseg] = inc;
-      sh.segVar[nseg] = i;
       sh.segEnd[nseg] = nrows;
       ++nseg;
     }
@@ -243,7 +309,7 @@ __device__ void prologue(const KArgs& a, const DevJob& J, Shared& sh) {
     while (bits) {
       const int b = __ffsll((unsigned long long)bits) - 1;
       bits &= bits - 1;
-      sh.u.rows[off++] = (uint16_t)(base + b);
+      sh.rows[off++] = (uint16_t)(base + b);
     }
   }
   __syncthreads();
@@ -261,7 +327,7 @@ __device__ void do_update(const KArgs& a, const DevJob& J, int chunk, Shared& sh
   const bool trailOn = !fromRoot && !root && J.depthAfter > 0;
 
   if (J.nPop > 0) {
-    if (!block_wait(&s->prepDone, 1, &a.queue[3], sh)) return;
+    if (!block_wait(a, &s->prepDone, 1, sh)) return;
   }
   prologue(a, J, sh);
 
@@ -276,12 +342,11 @@ __device__ void do_update(const KArgs& a, const DevJob& J, int chunk, Shared& sh
   const int lane = lane_id();
   const uint64_t* srcCt = fromRoot ? T->ct0 : s->ct;
   const int32_t* srcIdx = fromRoot ? T->idx0 : s->idx[s->cur];
-  // the slot's depth after this job's pushes/pops decides whether to trail
   const int64_t trailTop = sh.trailTop;
 
-  unsigned long long nAct = 0, nTrail = 0;
+  unsigned long long nAct = 0;
   const int p0 = chunk * GPI + wave_id() * NGW;
-  int pos[NGW], g[NGW];
+  int pos[NGW], g[NGW], stv[NGW];
   bool act[NGW];
   uint64_t old[NGW], m[NGW], acc[NGW];
 #pragma unroll
@@ -290,6 +355,7 @@ __device__ void do_update(const KArgs& a, const DevJob& J, int chunk, Shared& sh
     g[u] = pos[u] < nGran ? srcIdx[pos[u]] : -1;
     act[u] = pos[u] < limit && status == ST_OK;
     old[u] = act[u] ? srcCt[(int64_t)g[u] * GW + lane] : 0ull;
+    stv[u] = (act[u] && trailOn && !noop) ? s->stamp[g[u]] : serial;
     m[u] = ~0ull;
     acc[u] = 0ull;
     nAct += act[u] ? 1 : 0;
@@ -302,7 +368,7 @@ __device__ void do_update(const KArgs& a, const DevJob& J, int chunk, Shared& sh
 #pragma unroll
       for (int j = 0; j < ROW_UNROLL; ++j) {
         const int k = k0 + j;
-        const int r = k < nrows ? (int)sh.u.rows[k] : -1;
+        const int r = k < nrows ? (int)sh.rows[k] : -1;
 #pragma unroll
         for (int u = 0; u < NGW; ++u)
           v[j][u] = (r >= 0 && act[u]) ? T->S[(int64_t)r * stride + (int64_t)g[u] * GW + lane] : 0ull;
@@ -335,59 +401,66 @@ __device__ void do_update(const KArgs& a, const DevJob& J, int chunk, Shared& sh
       ++seg;
     }
   }
+  // new words, and which granules need saving on the trail (first change in
+  // this level); one trail allocation per wave
+  uint64_t nw[NGW];
+  bool need[NGW];
+  int nNeed = 0;
+#pragma unroll
+  for (int u = 0; u < NGW; ++u) {
+    nw[u] = noop ? old[u] : (old[u] & m[u]);
+    const bool changed = act[u] && (__ballot(nw[u] != old[u]) != 0ull);
+    need[u] = changed && trailOn && stv[u] != serial;
+    nNeed += need[u] ? 1 : 0;
+    if (!changed) need[u] = false;
+    act[u] = act[u] && (changed || fromRoot || root);  // act now means "write ct"
+  }
+  int tbase = 0;
+  if (nNeed) {
+    if (lane == 0) tbase = atomicAdd(&s->jobTrail, nNeed);
+    tbase = __shfl(tbase, 0);
+  }
 #pragma unroll
   for (int u = 0; u < NGW; ++u) {
     if (pos[u] >= nGran) continue;
     const int64_t w = (int64_t)g[u] * GW + lane;
-    if (!act[u]) {
+    if (pos[u] >= limit) {
       if (status != ST_OK) continue;
       // inactive granule (all zero by invariant)
       if (fromRoot) s->ct[w] = 0ull;
       if (J.ct_out && w < W) J.ct_out[w] = 0ull;
       continue;
     }
-    const uint64_t nw = noop ? old[u] : (old[u] & m[u]);
-    const bool changed = __ballot(nw != old[u]) != 0ull;
-    if (fromRoot || root) {
-      s->ct[w] = nw;
-    } else if (changed) {
-      if (trailOn) {
-        const int st = s->stamp[g[u]];
-        if (st != serial) {
-          int e = 0;
-          if (lane == 0) e = atomicAdd(&s->jobTrail, 1);
-          e = __shfl(e, 0);
-          const int64_t tp = trailTop + e;
-          if (tp < s->trailCap) {
-            s->trailWords[tp * GW + lane] = old[u];
-            if (lane == 0) {
-              TrailHdr h;
-              h.gran = g[u];
-              h.oldStamp = st;
-              s->trailHdr[tp] = h;
-              s->stamp[g[u]] = serial;
-            }
-          } else if (lane == 0) {
-            atomicExch(&a.queue[3], 2);  // capacity is sized so this cannot happen
-          }
-          ++nTrail;
+    if (status != ST_OK) continue;
+    if (need[u]) {
+      const int64_t tp = trailTop + tbase++;
+      if (tp < s->trailCap) {
+        s->trailWords[tp * GW + lane] = old[u];
+        if (lane == 0) {
+          TrailHdr h;
+          h.gran = g[u];
+          h.oldStamp = stv[u];
+          s->trailHdr[tp] = h;
+          s->stamp[g[u]] = serial;
         }
+      } else if (lane == 0) {
+        raise_error(a, 2);  // capacity is sized so that this cannot happen
       }
-      s->ct[w] = nw;
     }
-    if (J.ct_out && w < W) J.ct_out[w] = nw;
-    const bool nz = __ballot(nw != 0ull) != 0ull;
+    if (act[u]) s->ct[w] = nw[u];
+    if (J.ct_out && w < W) J.ct_out[w] = nw[u];
+    const bool nz = __ballot(nw[u] != 0ull) != 0ull;
     if (lane == 0) s->nzFlag[pos[u]] = nz ? 1 : 0;
   }
   if (lane == 0 && status == ST_OK) {
     atomicAdd(&s->stats[S_GRAN_ROWS], nAct * (unsigned long long)(noop ? 0 : nrows));
-    if (nTrail) atomicAdd(&s->stats[S_TRAIL], nTrail);
+    if (nNeed) atomicAdd(&s->stats[S_TRAIL], (unsigned long long)nNeed);
   }
 
   // count finished items; the last one finalizes the job
   __syncthreads();
   if (threadIdx.x == 0) {
-    __threadfence();
+    item_fence(J);
     const int prev = atomicAdd(&s->updCount, 1);
     sh.isLast = prev == J.nUpd - 1;
     if (sh.isLast) {
@@ -398,35 +471,33 @@ __device__ void do_update(const KArgs& a, const DevJob& J, int chunk, Shared& sh
   __syncthreads();
   if (!sh.isLast) return;
 
-  if (J.nPush > 0 && J.nPop == 0) {
-    if (!block_wait(&s->prepDone, 1, &a.queue[3], sh)) return;
+  // --- finalize the job (one workgroup) ---
+  if (J.nPop > 0) {
+    if (threadIdx.x == 0) s->prepDone = 0;  // the prep item also did the pushes
+  } else if (J.nPush > 0) {
+    // pushes record the state before this job
+    if (threadIdx.x == 0) {
+      sh.depth = s->depth;
+      sh.bad_sub = s->failed;
+      sh.item = s->serial;
+    }
+    __syncthreads();
+    push_levels(J, s, sh.depth, trailTop, limit, sh.bad_sub, sh.item, T->D);
+    __syncthreads();
   }
-  if (threadIdx.x == 0 && (J.nPush > 0 || J.nPop > 0)) s->prepDone = 0;
   int st = status;
+  int nSurv = limit;
   if (st == ST_OK && !noop) {
     // stable partition of the active granule list: survivors first
     const int32_t* src = srcIdx;
     const int dstBuf = fromRoot ? 0 : 1 - s->cur;
     int32_t* dst = s->idx[dstBuf];
     const int per = (limit + BLOCK - 1) / BLOCK;
-    const int b = threadIdx.x * per;
+    const int b = min((int)threadIdx.x * per, limit);
     const int e = min(b + per, limit);
     int cnt = 0;
     for (int p = b; p < e; ++p) cnt += s->nzFlag[p];
-    sh.scan[threadIdx.x] = cnt;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      int acc = 0;
-      for (int t = 0; t < BLOCK; ++t) {
-        const int c = sh.scan[t];
-        sh.scan[t] = acc;
-        acc += c;
-      }
-      sh.item = acc;  // survivors
-    }
-    __syncthreads();
-    const int nSurv = sh.item;
-    int sv = sh.scan[threadIdx.x];
+    int sv = block_scan_excl(cnt, &nSurv, sh);
     int zr = nSurv + (b - sv);
     for (int p = b; p < e; ++p) {
       const int gid = src[p];
@@ -453,14 +524,18 @@ __device__ void do_update(const KArgs& a, const DevJob& J, int chunk, Shared& sh
     }
   }
   if (threadIdx.x == 0) {
+    if (J.nPop == 0 && J.nPush > 0) {
+      s->depth = s->depth + J.nPush;
+      s->serial = J.serialBase + J.nPush - 1;
+    }
     s->status = st;
     s->pad2 = noop;
-    if (st != ST_OK && J.status_out) *J.status_out = st;
     if (st == ST_OK || st == ST_FAIL) {
       atomicAdd(&s->stats[S_JOBS], 1ull);
       atomicAdd(&s->stats[S_GRAN_IN], (unsigned long long)limit);
-      atomicAdd(&s->stats[S_ROWS], (unsigned long long)(noop ? 0 : sh.nrows));
+      atomicAdd(&s->stats[S_ROWS], (unsigned long long)(noop ? 0 : nrows));
     }
+    if (st != ST_OK) publish_status(J, st);
     __threadfence();
     st_release(&s->updDone, 1);  // consumed (and reset) by the job's last filter item
   }
@@ -472,7 +547,7 @@ __device__ void do_update(const KArgs& a, const DevJob& J, int chunk, Shared& sh
 __device__ void do_filter(const KArgs& a, const DevJob& J, int chunk, Shared& sh) {
   const TabDesc* T = J.tab;
   SlotDesc* s = J.slot;
-  if (!block_wait(&s->updDone, 1, &a.queue[3], sh)) return;
+  if (!block_wait(a, &s->updDone, 1, sh)) return;
   const int jobStatus = s->status;
   const int noop = s->pad2;
   const int q = chunk * WAVES + wave_id();
@@ -545,12 +620,12 @@ __device__ void do_filter(const KArgs& a, const DevJob& J, int chunk, Shared& sh
   // the last filter item of the job reports OK
   __syncthreads();
   if (threadIdx.x == 0) {
-    __threadfence();
+    item_fence(J);
     const int prev = atomicAdd(&s->filtCount, 1);
     if (prev == J.nFilt - 1) {
       s->filtCount = 0;
       s->updDone = 0;
-      if (jobStatus == ST_OK && J.status_out) *J.status_out = ST_OK;
+      if (jobStatus == ST_OK) publish_status(J, ST_OK);
     }
   }
 }
@@ -559,13 +634,9 @@ __global__ void __launch_bounds__(BLOCK) propagate_kernel(KArgs a) {
   __shared__ Shared sh;
   int32_t* q = a.queue;
   const int total = a.nPrep + a.nUpd + a.nFilt;
-  for (;;) {
-    if (threadIdx.x == 0) sh.item = atomicAdd(&q[0], 1);
-    __syncthreads();
-    const int item = sh.item;
-    __syncthreads();
-    if (item >= total) break;
-    if (ld_relaxed(&q[3])) continue;  // a device error: drain the queue
+  const bool dynamic = (int)gridDim.x < total;
+  int item = blockIdx.x;
+  while (item < total) {
     if (item < a.nPrep) {
       const int j = a.jobs ? a.prepList[item] : 0;
       do_prep(a, job_of(a, j), sh);
@@ -580,23 +651,26 @@ __global__ void __launch_bounds__(BLOCK) propagate_kernel(KArgs a) {
       const int c = a.jobs ? x - a.filtOff[j] : x;
       do_filter(a, job_of(a, j), c, sh);
     }
+    if (!dynamic) break;
     __syncthreads();
+    if (threadIdx.x == 0) sh.item = (int)gridDim.x + atomicAdd(&q[0], 1);
+    __syncthreads();
+    item = sh.item;
   }
+  if (!dynamic) return;
   // the last workgroup out resets the queue for the next launch
   if (threadIdx.x == 0) {
     __threadfence();
     const int prev = atomicAdd(&q[1], 1);
     if (prev == (int)gridDim.x - 1) {
-      const int err = ld_relaxed(&q[3]);
-      if (a.hostErr) *(volatile int32_t*)a.hostErr = err;
       q[0] = 0;
       q[1] = 0;
-      q[3] = 0;
-      q[2] += 1;  // launches completed (diagnostics)
+      q[2] += 1;  // dynamic launches completed (diagnostics)
       __threadfence();
     }
   }
 }
+
 
 // ---------------------------------------------------------------------------
 // support bitset builder: one wave per 64 tuples (one word column); for each

@@ -7,6 +7,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -55,6 +56,7 @@ int fail(int code, const char* fmt, ...) {
   } while (0)
 
 constexpr int MAX_GRID = 768;  // 256 CUs x 3 workgroups (LDS bound)
+constexpr int32_t kStatusPending = 0x7fff0001;
 
 // failed flag as known on the host: 0 no, 1 yes, 2 unknown (after batches)
 struct SlotHost {
@@ -89,7 +91,7 @@ struct QueueCtx {
 int queue_init(QueueCtx& q) {
   HIPCHK(hipMalloc(&q.queue, 4 * sizeof(int32_t)));
   HIPCHK(hipMemset(q.queue, 0, 4 * sizeof(int32_t)));
-  HIPCHK(hipHostMalloc((void**)&q.hostErr, sizeof(int32_t), hipHostMallocDefault));
+  HIPCHK(hipHostMalloc((void**)&q.hostErr, sizeof(int32_t), hipHostMallocMapped | hipHostMallocCoherent));
   *q.hostErr = 0;
   HIPCHK(hipEventCreateWithFlags(&q.staged, hipEventDisableTiming));
   return CT_OK;
@@ -140,9 +142,10 @@ struct ct_table {
   uint64_t* pDomIn = nullptr;   // D words (used when D > INLINE_WORDS)
   uint64_t* pCt = nullptr;      // W words (lazily)
   int32_t* pStatus = nullptr;
-  // optional kernel timing of synchronous launches
+  // optional kernel timing of synchronous launches: event pairs are read
+  // back lazily so that timing adds no synchronization to a call
   bool timing = false;
-  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> evPool, evPending;
   double kernelMs = 0.0;
   int64_t launches = 0;
 };
@@ -224,8 +227,9 @@ int run_single(ct_table* T, DevJob& J, const uint64_t* dom_in_host) {
   a.jobs = nullptr;
   a.nJobs = 1;
   job_counts(T, J);
-  const bool needPrep = J.nPop > 0 || J.nPush > 0;
+  const bool needPrep = J.nPop > 0 || !(J.flags & JF_PROPAGATE);
   a.nPrep = needPrep ? 1 : 0;
+  J.flags |= JF_HOST_OUT;
   a.nUpd = J.nUpd;
   a.nFilt = J.nFilt;
   a.queue = T->q.queue;
@@ -244,21 +248,42 @@ int run_single(ct_table* T, DevJob& J, const uint64_t* dom_in_host) {
   a.job = J;
   const int total = a.nPrep + a.nUpd + a.nFilt;
   if (total == 0) return CT_OK;
-  *T->q.hostErr = 0;
-  *T->pStatus = 99;
-  if (T->timing) HIPCHK(hipEventRecord(T->ev0, T->stream));
-  HIPCHK(launch_propagate(a, std::min(total, MAX_GRID), T->stream));
-  if (T->timing) HIPCHK(hipEventRecord(T->ev1, T->stream));
-  hipError_t e = hipStreamSynchronize(T->stream);
-  if (e == hipSuccess && T->timing) {
-    float ms = 0.f;
-    HIPCHK(hipEventElapsedTime(&ms, T->ev0, T->ev1));
-    T->kernelMs += ms;
-    T->launches++;
+  volatile int32_t* status = T->pStatus;
+  *status = kStatusPending;
+  std::pair<hipEvent_t, hipEvent_t> ev{nullptr, nullptr};
+  if (T->timing) {
+    if (T->evPool.empty()) {
+      HIPCHK(hipEventCreate(&ev.first));
+      HIPCHK(hipEventCreate(&ev.second));
+    } else {
+      ev = T->evPool.back();
+      T->evPool.pop_back();
+    }
+    HIPCHK(hipEventRecord(ev.first, T->stream));
   }
-  if (e != hipSuccess) {
-    T->poisoned = true;
-    return fail(CT_E_DEVICE, "kernel failed: %s", hipGetErrorString(e));
+  HIPCHK(launch_propagate(a, std::min(total, MAX_GRID), T->stream));
+  if (T->timing) {
+    HIPCHK(hipEventRecord(ev.second, T->stream));
+    T->evPending.push_back(ev);
+  }
+  // The job publishes its status (and its outputs before it) to coherent
+  // host memory with a system-scope release: wait for that word instead of
+  // the whole kernel.  The kernel's tail finishes on the stream, which
+  // orders it before the next launch.
+  const auto t0 = std::chrono::steady_clock::now();
+  for (uint32_t spin = 0; *status == kStatusPending; ++spin) {
+    if ((spin & 1023) == 1023 &&
+        std::chrono::steady_clock::now() - t0 > std::chrono::seconds(2)) {
+      hipError_t e = hipStreamSynchronize(T->stream);
+      if (e != hipSuccess) {
+        T->poisoned = true;
+        return fail(CT_E_DEVICE, "kernel failed: %s", hipGetErrorString(e));
+      }
+      if (*status == kStatusPending) {
+        T->poisoned = true;
+        return fail(CT_E_DEVICE, "kernel finished without a status (device error %d)", *T->q.hostErr);
+      }
+    }
   }
   if (*T->q.hostErr) {
     T->poisoned = true;
@@ -299,7 +324,7 @@ int flush_slot(ct_table* T, int slot) {
 int ensure_pinned_ct(ct_table* T) {
   if (T->pCt) return CT_OK;
   HIPCHK(hipHostMalloc((void**)&T->pCt, sizeof(uint64_t) * std::max<int64_t>(T->W, 1),
-                       hipHostMallocDefault));
+                       hipHostMallocMapped | hipHostMallocCoherent));
   return CT_OK;
 }
 
@@ -327,8 +352,14 @@ void ct_destroy(ct_table* T) {
   if (T->pDomIn) (void)hipHostFree(T->pDomIn);
   if (T->pCt) (void)hipHostFree(T->pCt);
   if (T->pStatus) (void)hipHostFree(T->pStatus);
-  if (T->ev0) (void)hipEventDestroy(T->ev0);
-  if (T->ev1) (void)hipEventDestroy(T->ev1);
+  for (auto& e : T->evPool) {
+    (void)hipEventDestroy(e.first);
+    (void)hipEventDestroy(e.second);
+  }
+  for (auto& e : T->evPending) {
+    (void)hipEventDestroy(e.first);
+    (void)hipEventDestroy(e.second);
+  }
   if (T->stream) (void)hipStreamDestroy(T->stream);
   delete T;
 }
@@ -381,9 +412,12 @@ static int create_impl(ct_table* T, const int32_t* tuples, int64_t t, int32_t n,
   HIPCHK(hipStreamCreateWithFlags(&T->stream, hipStreamNonBlocking));
   int rc = queue_init(T->q);
   if (rc) return rc;
-  HIPCHK(hipHostMalloc((void**)&T->pDomOut, sizeof(uint64_t) * D, hipHostMallocDefault));
-  HIPCHK(hipHostMalloc((void**)&T->pDomIn, sizeof(uint64_t) * D, hipHostMallocDefault));
-  HIPCHK(hipHostMalloc((void**)&T->pStatus, sizeof(int32_t) * 4, hipHostMallocDefault));
+  // coherent (fine-grained) pinned buffers: the kernel's writes reach host
+  // memory without waiting for the end of the kernel
+  const unsigned kCoherent = hipHostMallocMapped | hipHostMallocCoherent;
+  HIPCHK(hipHostMalloc((void**)&T->pDomOut, sizeof(uint64_t) * D, kCoherent));
+  HIPCHK(hipHostMalloc((void**)&T->pDomIn, sizeof(uint64_t) * D, kCoherent));
+  HIPCHK(hipHostMalloc((void**)&T->pStatus, sizeof(int32_t) * 4, kCoherent));
 
   // static data
   if ((rc = dev_alloc(T, (void**)&T->dS, sizeof(uint64_t) * (size_t)rows * T->stride))) return rc;
@@ -454,6 +488,7 @@ static int create_impl(ct_table* T, const int32_t* tuples, int64_t t, int32_t n,
   J.status_out = pinned_dev(T, T->pStatus);
   J.depthAfter = 0;
   if ((rc = run_single(T, J, dom0.data()))) return rc;
+  HIPCHK(hipStreamSynchronize(T->stream));
   const int st = *T->pStatus;
   SlotDesc r{};
   HIPCHK(hipMemcpy(&r, T->dRoot, sizeof(SlotDesc), hipMemcpyDeviceToHost));
@@ -653,6 +688,7 @@ int ct_get_state(ct_table* T, int32_t slot, uint64_t* dom_out, uint64_t* ct_out)
   if (rc) return rc;
   if ((rc = check_slot(T, slot))) return rc;
   if ((rc = flush_slot(T, slot))) return rc;
+  HIPCHK(hipStreamSynchronize(T->stream));
   SlotDesc s{};
   HIPCHK(hipMemcpy(&s, T->slots[slot].dev, sizeof(SlotDesc), hipMemcpyDeviceToHost));
   if (dom_out) HIPCHK(hipMemcpy(dom_out, s.lastDom, sizeof(uint64_t) * T->D, hipMemcpyDeviceToHost));
@@ -671,6 +707,7 @@ int ct_slot_stats(ct_table* T, int32_t slot, ct_stats* st) {
   if (rc) return rc;
   if ((rc = check_slot(T, slot))) return rc;
   if (!st) return fail(CT_E_INVALID, "st is NULL");
+  HIPCHK(hipStreamSynchronize(T->stream));
   SlotDesc s{};
   HIPCHK(hipMemcpy(&s, T->slots[slot].dev, sizeof(SlotDesc), hipMemcpyDeviceToHost));
   st->jobs = (int64_t)s.stats[S_JOBS];
@@ -684,13 +721,42 @@ int ct_slot_stats(ct_table* T, int32_t slot, ct_stats* st) {
   return CT_OK;
 }
 
+static int drain_timing(ct_table* T) {
+  for (auto& e : T->evPending) {
+    HIPCHK(hipEventSynchronize(e.second));
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, e.first, e.second));
+    T->kernelMs += ms;
+    T->launches++;
+    T->evPool.push_back(e);
+  }
+  T->evPending.clear();
+  return CT_OK;
+}
+
+int ct_batch_status(void* stream_v) {
+  hipStream_t stream = (hipStream_t)stream_v;
+  QueueCtx* q = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(g_qmu);
+    auto it = g_queues.find(stream);
+    if (it == g_queues.end()) return CT_OK;
+    q = it->second;
+  }
+  HIPCHK(hipStreamSynchronize(stream));
+  const int32_t err = *(volatile int32_t*)q->hostErr;
+  if (!err) return CT_OK;
+  *q->hostErr = 0;
+  HIPCHK(hipMemsetAsync(q->queue + 3, 0, sizeof(int32_t), stream));
+  HIPCHK(hipStreamSynchronize(stream));
+  return fail(CT_E_DEVICE, "device-side error %d in a batch on this stream (wait timeout or trail "
+              "overflow); the slots of that batch are undefined", err);
+}
+
 int ct_set_timing(ct_table* T, int32_t on) {
   int rc = check_poison(T);
   if (rc) return rc;
-  if (on && !T->ev0) {
-    HIPCHK(hipEventCreate(&T->ev0));
-    HIPCHK(hipEventCreate(&T->ev1));
-  }
+  if ((rc = drain_timing(T))) return rc;
   T->timing = on != 0;
   T->kernelMs = 0.0;
   T->launches = 0;
@@ -699,6 +765,8 @@ int ct_set_timing(ct_table* T, int32_t on) {
 
 int ct_get_timing(ct_table* T, double* kernel_ms, int64_t* launches) {
   if (!T) return fail(CT_E_INVALID, "null table");
+  int rc = drain_timing(T);
+  if (rc) return rc;
   if (kernel_ms) *kernel_ms = T->kernelMs;
   if (launches) *launches = T->launches;
   return CT_OK;
@@ -733,6 +801,12 @@ int ct_propagate_batch(const ct_job* jobs, int32_t n_jobs, void* stream_v, int32
     }
     if ((cj.flags & CT_JOB_PROPAGATE) && (!cj.dom_in || !cj.dom_out))
       return fail(CT_E_INVALID, "job %d: dom_in / dom_out is NULL", j);
+  }
+  // the synchronous calls of these tables may still be finishing their tail
+  {
+    std::set<ct_table*> tabs;
+    for (int j = 0; j < n_jobs; ++j) tabs.insert(jobs[j].table);
+    for (ct_table* T : tabs) HIPCHK(hipStreamSynchronize(T->stream));
   }
   QueueCtx* q = nullptr;
   {
@@ -796,7 +870,7 @@ int ct_propagate_batch(const ct_job* jobs, int32_t n_jobs, void* stream_v, int32
     job_counts(T, J);
     updOff[j + 1] = updOff[j] + J.nUpd;
     filtOff[j + 1] = filtOff[j] + J.nFilt;
-    if (J.nPop > 0 || J.nPush > 0) prep.push_back(j);
+    if (J.nPop > 0 || !(J.flags & JF_PROPAGATE)) prep.push_back(j);
   }
   // stage to the device
   const size_t nOff = 2 * (size_t)(n_jobs + 1) + prep.size() + 1;
@@ -832,7 +906,7 @@ int ct_propagate_batch(const ct_job* jobs, int32_t n_jobs, void* stream_v, int32
   a.nUpd = updOff[n_jobs];
   a.nFilt = filtOff[n_jobs];
   a.queue = q->queue;
-  a.hostErr = nullptr;
+  a.hostErr = q->hostErr;
   const int total = a.nPrep + a.nUpd + a.nFilt;
   if (total > 0) HIPCHK(launch_propagate(a, std::min(total, MAX_GRID), stream));
   return CT_OK;

@@ -100,6 +100,7 @@ def lib():
             "ct_slots_alloc": ([P, I32, I32, C.POINTER(I32)], C.c_int),
             "ct_slot_stats": ([P, I32, C.POINTER(ct_stats)], C.c_int),
             "ct_propagate_batch": ([P, I32, P, P], C.c_int),
+            "ct_batch_status": ([P], C.c_int),
             "ct_set_timing": ([P, I32], C.c_int),
             "ct_get_timing": ([P, C.POINTER(C.c_double), C.POINTER(I64)], C.c_int),
             "ct_last_error": ([], C.c_char_p),
@@ -238,6 +239,14 @@ class Table:
         if st < 0:
             raise CTError(st, last_error())
         return s.as_dict()
+
+
+def batch_status(stream=None):
+    """Synchronize `stream`; raise if a batch on it hit a device-side error."""
+    s = None if stream is None else (stream if isinstance(stream, int) else stream.cuda_stream)
+    st = lib().ct_batch_status(s)
+    if st < 0:
+        raise CTError(st, last_error())
 
 
 def propagate_batch(jobs, status_dev, stream=None):
