@@ -63,9 +63,20 @@ extern "C" {
 
 typedef struct ct_table ct_table;
 
+/* How a propagation is spread over the GPU: SOLO runs a whole call in one
+ * workgroup (no hand-off between workgroups; best for small tables and for
+ * batches of many jobs), SPLIT spreads updateTable over workgroups of 8
+ * granules and filterDomains over workgroups of 4 domain words.  AUTO picks
+ * SOLO for tables of at most 64 granules (262,144 tuples) and for batches of
+ * at least 256 jobs.  Results are identical. */
+#define CT_SCHED_AUTO 0
+#define CT_SCHED_SOLO 1
+#define CT_SCHED_SPLIT 2
+
 typedef struct {
     int32_t branch_policy; /* CT_BRANCH_*; default AUTO */
     int32_t max_depth;     /* push levels per slot; default 256 */
+    int32_t schedule;      /* CT_SCHED_*; default AUTO */
 } ct_config;
 
 typedef struct {

@@ -46,6 +46,7 @@ constexpr uint32_t JF_FROM_ROOT = 2u;
 constexpr uint32_t JF_ROOT = 4u;      // creation: every variable takes the reset branch
 constexpr uint32_t JF_INLINE_DOM = 8u;
 constexpr uint32_t JF_HOST_OUT = 16u;   // status / outputs in host memory: system-scope release
+constexpr uint32_t JF_SOLO = 32u;       // whole job in one workgroup
 
 struct VarDesc {
   int32_t rowStart, dsize, domOff, domWords;

@@ -6,7 +6,9 @@
 // ballots and LDS.
 //
 // One persistent kernel executes a batch of propagation jobs as a list of
-// work items, in this order:
+// work items.  A job runs either in solo mode -- one item, one workgroup,
+// the whole of Alg. 1-3 with no hand-off between workgroups (small tables,
+// large batches) -- or in split mode, as items in this order:
 //   prep   (jobs that pop, and pure push/pop jobs)  backtrack restore, pushes
 //   update (nUpd per job)   updateTable (Alg. 2) over 8 granules each, with the
 //                           Delta / s_val / s_sup prologue of Alg. 1 recomputed
@@ -27,8 +29,9 @@
 
 namespace ctk {
 
-constexpr int NGW = 2;                 // granules per wave processed together
-constexpr int GPI = WAVES * NGW;       // granules per update item
+constexpr int NGW = 2;                 // granules per wave per update item (split mode)
+constexpr int GPI = WAVES * NGW;       // granules per update item (split mode)
+constexpr int NGS = 4;                 // granules per wave per step (solo mode)
 constexpr int ROW_UNROLL = 8;          // support rows loaded per batch
 constexpr uint32_t SPIN_LIMIT = 1u << 22;
 
@@ -54,8 +57,10 @@ struct Shared {
   int32_t segEnd[MAX_ARITY];  // exclusive end of segment rows
   int32_t segInc[MAX_ARITY];
   int32_t wsum[WAVES];
+  int32_t trailCount;          // trail entries of a job run by one workgroup
   uint64_t din[MAX_D];
   uint16_t rows[MAX_ROWS];
+  uint8_t nz[MAX_GRAN];        // granule non-zero flags of a job run by one workgroup
 };
 
 // Record a device error: the host sees it through hostErr (pinned) and the
@@ -166,10 +171,9 @@ __device__ void push_levels(const DevJob& J, SlotDesc* s, int depth0, int64_t tr
 // ---------------------------------------------------------------------------
 // prep: pops then pushes (whole block), for jobs that pop or only push/pop
 // ---------------------------------------------------------------------------
-__device__ void do_prep(const KArgs& a, const DevJob& J, Shared& sh) {
+__device__ void apply_pops_pushes(const DevJob& J, Shared& sh) {
   SlotDesc* s = J.slot;
-  const TabDesc* T = J.tab;
-  const int D = T->D;
+  const int D = J.tab->D;
   for (int p = 0; p < J.nPop; ++p) {
     if (threadIdx.x == 0) {
       sh.depth = s->depth - 1;
@@ -210,14 +214,19 @@ __device__ void do_prep(const KArgs& a, const DevJob& J, Shared& sh) {
       s->depth = sh.depth + J.nPush;
       s->serial = J.serialBase + J.nPush - 1;
     }
+    __syncthreads();
   }
+}
+
+__device__ void do_prep(const KArgs& a, const DevJob& J, Shared& sh) {
+  apply_pops_pushes(J, sh);
   if (threadIdx.x == 0) {
     if (!(J.flags & JF_PROPAGATE)) {
       item_fence(J);
       publish_status(J, ST_OK);
     } else {
       __threadfence();
-      st_release(&s->prepDone, 1);  // consumed (and reset) by the job's last update item
+      st_release(&J.slot->prepDone, 1);  // consumed (and reset) by the job's last update item
     }
   }
 }
@@ -316,21 +325,18 @@ __device__ void prologue(const KArgs& a, const DevJob& J, Shared& sh) {
 }
 
 // ---------------------------------------------------------------------------
-// update: updateTable (Alg. 2) over the granules of one item
+// updateTable (Alg. 2) for NG granules per wave starting at position p0.
+// Granule flags go to LDS (whole job in one workgroup) or to global memory.
 // ---------------------------------------------------------------------------
-__device__ void do_update(const KArgs& a, const DevJob& J, int chunk, Shared& sh) {
+template <int NG>
+__device__ void update_granules(const KArgs& a, const DevJob& J, Shared& sh, int p0, bool ldsFlags,
+                                int* trailCounter) {
   const TabDesc* T = J.tab;
   SlotDesc* s = J.slot;
   const bool fromRoot = J.flags & JF_FROM_ROOT;
   const bool root = J.flags & JF_ROOT;
   // levels exist only above depth 0: nothing is saved at depth 0
   const bool trailOn = !fromRoot && !root && J.depthAfter > 0;
-
-  if (J.nPop > 0) {
-    if (!block_wait(a, &s->prepDone, 1, sh)) return;
-  }
-  prologue(a, J, sh);
-
   const int nGran = T->nGran;
   const int64_t stride = T->stride;
   const int64_t W = T->W;
@@ -345,12 +351,11 @@ __device__ void do_update(const KArgs& a, const DevJob& J, int chunk, Shared& sh
   const int64_t trailTop = sh.trailTop;
 
   unsigned long long nAct = 0;
-  const int p0 = chunk * GPI + wave_id() * NGW;
-  int pos[NGW], g[NGW], stv[NGW];
-  bool act[NGW];
-  uint64_t old[NGW], m[NGW], acc[NGW];
+  int pos[NG], g[NG], stv[NG];
+  bool act[NG];
+  uint64_t old[NG], m[NG], acc[NG];
 #pragma unroll
-  for (int u = 0; u < NGW; ++u) {
+  for (int u = 0; u < NG; ++u) {
     pos[u] = p0 + u;
     g[u] = pos[u] < nGran ? srcIdx[pos[u]] : -1;
     act[u] = pos[u] < limit && status == ST_OK;
@@ -360,17 +365,17 @@ __device__ void do_update(const KArgs& a, const DevJob& J, int chunk, Shared& sh
     acc[u] = 0ull;
     nAct += act[u] ? 1 : 0;
   }
-  if (status == ST_OK && !noop) {
+  if (status == ST_OK && !noop && nAct > 0) {
     int seg = 0;
     int segEnd = nseg > 0 ? sh.segEnd[0] : 0;
     for (int k0 = 0; k0 < nrows; k0 += ROW_UNROLL) {
-      uint64_t v[ROW_UNROLL][NGW];
+      uint64_t v[ROW_UNROLL][NG];
 #pragma unroll
       for (int j = 0; j < ROW_UNROLL; ++j) {
         const int k = k0 + j;
         const int r = k < nrows ? (int)sh.rows[k] : -1;
 #pragma unroll
-        for (int u = 0; u < NGW; ++u)
+        for (int u = 0; u < NG; ++u)
           v[j][u] = (r >= 0 && act[u]) ? T->S[(int64_t)r * stride + (int64_t)g[u] * GW + lane] : 0ull;
       }
 #pragma unroll
@@ -380,7 +385,7 @@ __device__ void do_update(const KArgs& a, const DevJob& J, int chunk, Shared& sh
         while (k >= segEnd) {
           const int inc = sh.segInc[seg];
 #pragma unroll
-          for (int u = 0; u < NGW; ++u) {
+          for (int u = 0; u < NG; ++u) {
             m[u] &= inc ? ~acc[u] : acc[u];
             acc[u] = 0ull;
           }
@@ -388,13 +393,13 @@ __device__ void do_update(const KArgs& a, const DevJob& J, int chunk, Shared& sh
           segEnd = sh.segEnd[seg];
         }
 #pragma unroll
-        for (int u = 0; u < NGW; ++u) acc[u] |= v[j][u];
+        for (int u = 0; u < NG; ++u) acc[u] |= v[j][u];
       }
     }
     while (seg < nseg) {  // remaining segments (an empty reset segment gives 0)
       const int inc = sh.segInc[seg];
 #pragma unroll
-      for (int u = 0; u < NGW; ++u) {
+      for (int u = 0; u < NG; ++u) {
         m[u] &= inc ? ~acc[u] : acc[u];
         acc[u] = 0ull;
       }
@@ -403,35 +408,32 @@ __device__ void do_update(const KArgs& a, const DevJob& J, int chunk, Shared& sh
   }
   // new words, and which granules need saving on the trail (first change in
   // this level); one trail allocation per wave
-  uint64_t nw[NGW];
-  bool need[NGW];
+  uint64_t nw[NG];
+  bool need[NG], wr[NG];
   int nNeed = 0;
 #pragma unroll
-  for (int u = 0; u < NGW; ++u) {
+  for (int u = 0; u < NG; ++u) {
     nw[u] = noop ? old[u] : (old[u] & m[u]);
     const bool changed = act[u] && (__ballot(nw[u] != old[u]) != 0ull);
     need[u] = changed && trailOn && stv[u] != serial;
     nNeed += need[u] ? 1 : 0;
-    if (!changed) need[u] = false;
-    act[u] = act[u] && (changed || fromRoot || root);  // act now means "write ct"
+    wr[u] = act[u] && (changed || fromRoot || root);
   }
   int tbase = 0;
   if (nNeed) {
-    if (lane == 0) tbase = atomicAdd(&s->jobTrail, nNeed);
+    if (lane == 0) tbase = atomicAdd(trailCounter, nNeed);
     tbase = __shfl(tbase, 0);
   }
 #pragma unroll
-  for (int u = 0; u < NGW; ++u) {
-    if (pos[u] >= nGran) continue;
+  for (int u = 0; u < NG; ++u) {
+    if (pos[u] >= nGran || status != ST_OK) continue;
     const int64_t w = (int64_t)g[u] * GW + lane;
     if (pos[u] >= limit) {
-      if (status != ST_OK) continue;
       // inactive granule (all zero by invariant)
       if (fromRoot) s->ct[w] = 0ull;
       if (J.ct_out && w < W) J.ct_out[w] = 0ull;
       continue;
     }
-    if (status != ST_OK) continue;
     if (need[u]) {
       const int64_t tp = trailTop + tbase++;
       if (tp < s->trailCap) {
@@ -447,15 +449,161 @@ __device__ void do_update(const KArgs& a, const DevJob& J, int chunk, Shared& sh
         raise_error(a, 2);  // capacity is sized so that this cannot happen
       }
     }
-    if (act[u]) s->ct[w] = nw[u];
+    if (wr[u]) s->ct[w] = nw[u];
     if (J.ct_out && w < W) J.ct_out[w] = nw[u];
     const bool nz = __ballot(nw[u] != 0ull) != 0ull;
-    if (lane == 0) s->nzFlag[pos[u]] = nz ? 1 : 0;
+    if (lane == 0) {
+      if (ldsFlags) sh.nz[pos[u]] = nz ? 1 : 0;
+      else s->nzFlag[pos[u]] = nz ? 1 : 0;
+    }
   }
   if (lane == 0 && status == ST_OK) {
-    atomicAdd(&s->stats[S_GRAN_ROWS], nAct * (unsigned long long)(noop ? 0 : nrows));
+    if (nAct && !noop) atomicAdd(&s->stats[S_GRAN_ROWS], nAct * (unsigned long long)nrows);
     if (nNeed) atomicAdd(&s->stats[S_TRAIL], (unsigned long long)nNeed);
   }
+}
+
+// ---------------------------------------------------------------------------
+// End of updateTable for a job (one workgroup): stable partition of the
+// active granule list (survivors first), new limit, trail top, FAIL when no
+// granule survives (Alg. 1 line 5).  Returns the job status.
+// ---------------------------------------------------------------------------
+__device__ int finalize_update(const DevJob& J, Shared& sh, bool ldsFlags, int jobTrail) {
+  const TabDesc* T = J.tab;
+  SlotDesc* s = J.slot;
+  const bool fromRoot = J.flags & JF_FROM_ROOT;
+  const int limit = sh.limit;
+  const int nGran = T->nGran;
+  int st = sh.status;
+  if (st == ST_OK && !sh.noop) {
+    const int32_t* src = fromRoot ? T->idx0 : s->idx[s->cur];
+    const int dstBuf = fromRoot ? 0 : 1 - s->cur;
+    int32_t* dst = s->idx[dstBuf];
+    const int per = (limit + BLOCK - 1) / BLOCK;
+    const int b = min((int)threadIdx.x * per, limit);
+    const int e = min(b + per, limit);
+    int cnt = 0;
+    for (int p = b; p < e; ++p) cnt += ldsFlags ? sh.nz[p] : s->nzFlag[p];
+    int nSurv = 0;
+    int sv = block_scan_excl(cnt, &nSurv, sh);
+    int zr = nSurv + (b - sv);
+    for (int p = b; p < e; ++p) {
+      const int gid = src[p];
+      const int f = ldsFlags ? sh.nz[p] : s->nzFlag[p];
+      if (f) dst[sv++] = gid; else dst[zr++] = gid;
+    }
+    for (int p = limit + threadIdx.x; p < nGran; p += BLOCK) dst[p] = src[p];
+    if (nSurv == 0) st = ST_FAIL;
+    if (threadIdx.x == 0) {
+      s->cur = dstBuf;
+      s->limit = nSurv;
+      if (fromRoot) {
+        s->depth = 0;
+        s->trailTop = 0;
+        s->serial = J.serialBase;
+        s->failed = 0;
+      } else {
+        s->trailTop = sh.trailTop + jobTrail;
+      }
+      if (nSurv == 0) s->failed = 1;
+    }
+  }
+  if (threadIdx.x == 0) {
+    s->status = st;
+    s->pad2 = sh.noop;
+    if (st == ST_OK || st == ST_FAIL) {
+      atomicAdd(&s->stats[S_JOBS], 1ull);
+      atomicAdd(&s->stats[S_GRAN_IN], (unsigned long long)limit);
+      atomicAdd(&s->stats[S_ROWS], (unsigned long long)(sh.noop ? 0 : sh.nrows));
+    }
+  }
+  __syncthreads();
+  return st;
+}
+
+// ---------------------------------------------------------------------------
+// filterDomains (Alg. 3) for domain word q, by one wave: residue word first,
+// then the active granules in index order until a support is found.
+// ---------------------------------------------------------------------------
+__device__ void filter_word(const KArgs& a, const DevJob& J, int q, int noop, int lim,
+                            const int32_t* idx, unsigned long long* cnt) {
+  const TabDesc* T = J.tab;
+  SlotDesc* s = J.slot;
+  const int lane = lane_id();
+  const int i = T->wordVar[q];
+  const VarDesc v = T->vars[i];
+  const uint64_t din = job_din(a, J, q);
+  int size = 0;
+  for (int k = v.domOff; k < v.domOff + v.domWords; ++k) size += __popcll(job_din(a, J, k));
+  uint64_t dout = din;
+  if (!noop && size > 1) {  // s_sup: non-singleton variables
+    const int64_t stride = T->stride;
+    const int rowBase = v.rowStart + (q - v.domOff) * 64;
+    const bool present = (din >> lane) & 1ull;
+    bool hit = false;
+    if (present) {
+      const int r = rowBase + lane;
+      const int rw = s->res[r];
+      hit = (s->ct[rw] & T->S[(int64_t)r * stride + rw]) != 0ull;
+    }
+    unsigned long long miss = __ballot(present && !hit);
+    cnt[0] += __popcll(__ballot(present));
+    cnt[1] += __popcll(miss);
+    uint64_t unsup = 0;
+    while (miss) {
+      const int l = __ffsll(miss) - 1;
+      miss &= miss - 1;
+      const int r = rowBase + l;
+      const uint64_t* row = T->S + (int64_t)r * stride;
+      int found = -1;
+      for (int p = 0; p < lim && found < 0; p += 4) {
+        uint64_t x[4];
+        int gg[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          gg[j] = (p + j < lim) ? idx[p + j] : -1;
+          const int64_t w = (int64_t)gg[j] * GW + lane;
+          x[j] = gg[j] >= 0 ? (s->ct[w] & row[w]) : 0ull;
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const unsigned long long bm = __ballot(x[j] != 0ull);
+          if (found < 0 && bm) found = gg[j] * GW + (__ffsll(bm) - 1);
+        }
+        cnt[2] += min(4, lim - p);
+      }
+      if (found >= 0) {
+        if (lane == 0) s->res[r] = found;
+      } else {
+        unsup |= 1ull << l;
+      }
+    }
+    dout = din & ~unsup;
+  }
+  if (lane == 0) {
+    J.dom_out[q] = dout;
+    s->lastDom[q] = dout;
+  }
+}
+
+__device__ void add_filter_stats(SlotDesc* s, const unsigned long long* cnt) {
+  if (lane_id() == 0 && (cnt[0] | cnt[1] | cnt[2])) {
+    atomicAdd(&s->stats[S_RES_CHECK], cnt[0]);
+    atomicAdd(&s->stats[S_RES_MISS], cnt[1]);
+    atomicAdd(&s->stats[S_SCAN], cnt[2]);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// split mode: one update item of a job (the last one finalizes the job)
+// ---------------------------------------------------------------------------
+__device__ void do_update(const KArgs& a, const DevJob& J, int chunk, Shared& sh) {
+  SlotDesc* s = J.slot;
+  if (J.nPop > 0) {
+    if (!block_wait(a, &s->prepDone, 1, sh)) return;
+  }
+  prologue(a, J, sh);
+  update_granules<NGW>(a, J, sh, chunk * GPI + wave_id() * NGW, false, &s->jobTrail);
 
   // count finished items; the last one finalizes the job
   __syncthreads();
@@ -471,7 +619,6 @@ __device__ void do_update(const KArgs& a, const DevJob& J, int chunk, Shared& sh
   __syncthreads();
   if (!sh.isLast) return;
 
-  // --- finalize the job (one workgroup) ---
   if (J.nPop > 0) {
     if (threadIdx.x == 0) s->prepDone = 0;  // the prep item also did the pushes
   } else if (J.nPush > 0) {
@@ -482,141 +629,35 @@ __device__ void do_update(const KArgs& a, const DevJob& J, int chunk, Shared& sh
       sh.item = s->serial;
     }
     __syncthreads();
-    push_levels(J, s, sh.depth, trailTop, limit, sh.bad_sub, sh.item, T->D);
-    __syncthreads();
-  }
-  int st = status;
-  int nSurv = limit;
-  if (st == ST_OK && !noop) {
-    // stable partition of the active granule list: survivors first
-    const int32_t* src = srcIdx;
-    const int dstBuf = fromRoot ? 0 : 1 - s->cur;
-    int32_t* dst = s->idx[dstBuf];
-    const int per = (limit + BLOCK - 1) / BLOCK;
-    const int b = min((int)threadIdx.x * per, limit);
-    const int e = min(b + per, limit);
-    int cnt = 0;
-    for (int p = b; p < e; ++p) cnt += s->nzFlag[p];
-    int sv = block_scan_excl(cnt, &nSurv, sh);
-    int zr = nSurv + (b - sv);
-    for (int p = b; p < e; ++p) {
-      const int gid = src[p];
-      if (s->nzFlag[p]) dst[sv++] = gid; else dst[zr++] = gid;
-    }
-    for (int p = limit + threadIdx.x; p < nGran; p += BLOCK) dst[p] = src[p];
+    push_levels(J, s, sh.depth, sh.trailTop, sh.limit, sh.bad_sub, sh.item, J.tab->D);
     __syncthreads();
     if (threadIdx.x == 0) {
-      s->cur = dstBuf;
-      s->limit = nSurv;
-      if (fromRoot) {
-        s->depth = 0;
-        s->trailTop = 0;
-        s->serial = J.serialBase;
-        s->failed = 0;
-      } else {
-        s->trailTop = trailTop + s->jobTrail;
-      }
-      s->jobTrail = 0;
-      if (nSurv == 0) {
-        st = ST_FAIL;
-        s->failed = 1;
-      }
-    }
-  }
-  if (threadIdx.x == 0) {
-    if (J.nPop == 0 && J.nPush > 0) {
-      s->depth = s->depth + J.nPush;
+      s->depth = sh.depth + J.nPush;
       s->serial = J.serialBase + J.nPush - 1;
     }
-    s->status = st;
-    s->pad2 = noop;
-    if (st == ST_OK || st == ST_FAIL) {
-      atomicAdd(&s->stats[S_JOBS], 1ull);
-      atomicAdd(&s->stats[S_GRAN_IN], (unsigned long long)limit);
-      atomicAdd(&s->stats[S_ROWS], (unsigned long long)(noop ? 0 : nrows));
-    }
+  }
+  if (threadIdx.x == 0) sh.trailCount = s->jobTrail;
+  __syncthreads();
+  const int st = finalize_update(J, sh, false, sh.trailCount);
+  if (threadIdx.x == 0) {
+    s->jobTrail = 0;
     if (st != ST_OK) publish_status(J, st);
     __threadfence();
     st_release(&s->updDone, 1);  // consumed (and reset) by the job's last filter item
   }
 }
 
-// ---------------------------------------------------------------------------
-// filter: filterDomains (Alg. 3) for one domain word per wave
-// ---------------------------------------------------------------------------
+// split mode: one filter item (one domain word per wave)
 __device__ void do_filter(const KArgs& a, const DevJob& J, int chunk, Shared& sh) {
-  const TabDesc* T = J.tab;
   SlotDesc* s = J.slot;
   if (!block_wait(a, &s->updDone, 1, sh)) return;
   const int jobStatus = s->status;
-  const int noop = s->pad2;
   const int q = chunk * WAVES + wave_id();
-  const int D = T->D;
-  const int lane = lane_id();
-  unsigned long long nChk = 0, nMiss = 0, nScan = 0;
-  if (q < D && jobStatus == ST_OK) {
-    const int i = T->wordVar[q];
-    const VarDesc v = T->vars[i];
-    const uint64_t din = job_din(a, J, q);
-    int size = 0;
-    for (int k = v.domOff; k < v.domOff + v.domWords; ++k) size += __popcll(job_din(a, J, k));
-    uint64_t dout = din;
-    if (!noop && size > 1) {  // s_sup: non-singleton variables
-      const int64_t stride = T->stride;
-      const int rowBase = v.rowStart + (q - v.domOff) * 64;
-      const bool present = (din >> lane) & 1ull;
-      bool hit = false;
-      if (present) {
-        const int r = rowBase + lane;
-        const int rw = s->res[r];
-        hit = (s->ct[rw] & T->S[(int64_t)r * stride + rw]) != 0ull;
-      }
-      unsigned long long miss = __ballot(present && !hit);
-      nChk = __popcll(__ballot(present));
-      nMiss = __popcll(miss);
-      uint64_t unsup = 0;
-      const int lim = s->limit;
-      const int32_t* idx = s->idx[s->cur];
-      while (miss) {
-        const int l = __ffsll(miss) - 1;
-        miss &= miss - 1;
-        const int r = rowBase + l;
-        const uint64_t* row = T->S + (int64_t)r * stride;
-        int found = -1;
-        for (int p = 0; p < lim && found < 0; p += 4) {
-          uint64_t x[4];
-          int gg[4];
-#pragma unroll
-          for (int j = 0; j < 4; ++j) {
-            gg[j] = (p + j < lim) ? idx[p + j] : -1;
-            const int64_t w = (int64_t)gg[j] * GW + lane;
-            x[j] = gg[j] >= 0 ? (s->ct[w] & row[w]) : 0ull;
-          }
-#pragma unroll
-          for (int j = 0; j < 4; ++j) {
-            const unsigned long long bm = __ballot(x[j] != 0ull);
-            if (found < 0 && bm) found = gg[j] * GW + (__ffsll(bm) - 1);
-          }
-          nScan += min(4, lim - p);
-        }
-        if (found >= 0) {
-          if (lane == 0) s->res[r] = found;
-        } else {
-          unsup |= 1ull << l;
-        }
-      }
-      dout = din & ~unsup;
-    }
-    if (lane == 0) {
-      J.dom_out[q] = dout;
-      s->lastDom[q] = dout;
-    }
+  unsigned long long cnt[3] = {0, 0, 0};
+  if (q < J.tab->D && jobStatus == ST_OK) {
+    filter_word(a, J, q, s->pad2, s->limit, s->idx[s->cur], cnt);
   }
-  if (lane == 0 && (nChk | nMiss | nScan)) {
-    atomicAdd(&s->stats[S_RES_CHECK], nChk);
-    atomicAdd(&s->stats[S_RES_MISS], nMiss);
-    atomicAdd(&s->stats[S_SCAN], nScan);
-  }
+  add_filter_stats(s, cnt);
   // the last filter item of the job reports OK
   __syncthreads();
   if (threadIdx.x == 0) {
@@ -627,6 +668,38 @@ __device__ void do_filter(const KArgs& a, const DevJob& J, int chunk, Shared& sh
       s->updDone = 0;
       if (jobStatus == ST_OK) publish_status(J, ST_OK);
     }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// solo mode: the whole job in one workgroup -- pops/pushes, prologue, all
+// granules, partition, filter -- with no hand-off between workgroups.
+// ---------------------------------------------------------------------------
+__device__ void do_solo(const KArgs& a, const DevJob& J, Shared& sh) {
+  SlotDesc* s = J.slot;
+  apply_pops_pushes(J, sh);
+  prologue(a, J, sh);
+  if (threadIdx.x == 0) sh.trailCount = 0;
+  __syncthreads();
+  const int nGran = J.tab->nGran;
+  const int span = sh.status == ST_OK ? nGran : 0;
+  for (int c = 0; c < span; c += WAVES * NGS) {
+    update_granules<NGS>(a, J, sh, c + wave_id() * NGS, true, &sh.trailCount);
+  }
+  __syncthreads();
+  const int st = finalize_update(J, sh, true, sh.trailCount);
+  if (st == ST_OK) {
+    unsigned long long cnt[3] = {0, 0, 0};
+    const int lim = s->limit;
+    const int32_t* idx = s->idx[s->cur];
+    const int noop = sh.noop;
+    for (int q = wave_id(); q < J.tab->D; q += WAVES) filter_word(a, J, q, noop, lim, idx, cnt);
+    add_filter_stats(s, cnt);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    item_fence(J);
+    publish_status(J, st);
   }
 }
 
@@ -643,8 +716,13 @@ __global__ void __launch_bounds__(BLOCK) propagate_kernel(KArgs a) {
     } else if (item < a.nPrep + a.nUpd) {
       const int x = item - a.nPrep;
       const int j = a.jobs ? find_job(a.updOff, a.nJobs, x) : 0;
-      const int c = a.jobs ? x - a.updOff[j] : x;
-      do_update(a, job_of(a, j), c, sh);
+      const DevJob& J = job_of(a, j);
+      if (J.flags & JF_SOLO) {
+        do_solo(a, J, sh);
+      } else {
+        const int c = a.jobs ? x - a.updOff[j] : x;
+        do_update(a, J, c, sh);
+      }
     } else {
       const int x = item - a.nPrep - a.nUpd;
       const int j = a.jobs ? find_job(a.filtOff, a.nJobs, x) : 0;
@@ -670,7 +748,6 @@ __global__ void __launch_bounds__(BLOCK) propagate_kernel(KArgs a) {
     }
   }
 }
-
 
 // ---------------------------------------------------------------------------
 // support bitset builder: one wave per 64 tuples (one word column); for each
@@ -750,6 +827,22 @@ namespace ctk {
 
 int propagate_items_per_job_update(int nGran) { return (nGran + GPI - 1) / GPI; }
 int propagate_items_per_job_filter(int D) { return (D + WAVES - 1) / WAVES; }
+
+// Workgroups of the propagate kernel that are resident at once on the whole
+// device: the grid never exceeds it, so every workgroup that holds an item
+// is running and every wait in the kernel can end.
+int propagate_max_grid() {
+  static int cached = 0;
+  if (cached) return cached;
+  int dev = 0, cus = 0, perCu = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 256;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 256;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&perCu, propagate_kernel, BLOCK, 0) != hipSuccess ||
+      perCu < 1)
+    perCu = 1;
+  cached = cus * perCu;
+  return cached;
+}
 
 hipError_t launch_propagate(const KArgs& a, int grid, hipStream_t stream) {
   hipLaunchKernelGGL(propagate_kernel, dim3(grid), dim3(BLOCK), 0, stream, a);

@@ -25,6 +25,7 @@ using namespace ctk;
 namespace ctk {
 int propagate_items_per_job_update(int nGran);
 int propagate_items_per_job_filter(int D);
+int propagate_max_grid();
 hipError_t launch_propagate(const KArgs& a, int grid, hipStream_t stream);
 hipError_t launch_build_supports(const int32_t* tuples, int64_t t, int n, const VarDesc* vars,
                                  const int32_t* lo, uint64_t* S, int64_t stride, int64_t W,
@@ -55,7 +56,6 @@ int fail(int code, const char* fmt, ...) {
                   __FILE__, __LINE__);                                                      \
   } while (0)
 
-constexpr int MAX_GRID = 768;  // 256 CUs x 3 workgroups (LDS bound)
 constexpr int32_t kStatusPending = 0x7fff0001;
 
 // failed flag as known on the host: 0 no, 1 yes, 2 unknown (after batches)
@@ -210,15 +210,32 @@ int check_poison(const ct_table* T) {
   return CT_OK;
 }
 
-// Fill item counts of a propagate job.
+constexpr int SOLO_MAX_GRAN = 64;     // tables up to 262,144 tuples run solo
+constexpr int SOLO_MIN_BATCH = 256;   // batches this large run every job solo
+
+bool use_solo(const ct_table* T, int nJobs) {
+  if (T->cfg.schedule == CT_SCHED_SOLO) return true;
+  if (T->cfg.schedule == CT_SCHED_SPLIT) return false;
+  return T->nGran <= SOLO_MAX_GRAN || nJobs >= SOLO_MIN_BATCH;
+}
+
+// Fill item counts of a job: solo = one update item that does everything.
 void job_counts(const ct_table* T, DevJob& J) {
-  if (J.flags & JF_PROPAGATE) {
-    J.nUpd = propagate_items_per_job_update(T->nGran);
-    J.nFilt = propagate_items_per_job_filter(T->D);
-  } else {
+  if (!(J.flags & JF_PROPAGATE)) {
     J.nUpd = 0;
     J.nFilt = 0;
+  } else if (J.flags & JF_SOLO) {
+    J.nUpd = 1;
+    J.nFilt = 0;
+  } else {
+    J.nUpd = propagate_items_per_job_update(T->nGran);
+    J.nFilt = propagate_items_per_job_filter(T->D);
   }
+}
+
+bool needs_prep(const DevJob& J) {
+  if (!(J.flags & JF_PROPAGATE)) return true;
+  return !(J.flags & JF_SOLO) && J.nPop > 0;
 }
 
 // Run one job synchronously on the table's stream.
@@ -226,9 +243,9 @@ int run_single(ct_table* T, DevJob& J, const uint64_t* dom_in_host) {
   KArgs a{};
   a.jobs = nullptr;
   a.nJobs = 1;
+  if ((J.flags & JF_PROPAGATE) && use_solo(T, 1)) J.flags |= JF_SOLO;
   job_counts(T, J);
-  const bool needPrep = J.nPop > 0 || !(J.flags & JF_PROPAGATE);
-  a.nPrep = needPrep ? 1 : 0;
+  a.nPrep = needs_prep(J) ? 1 : 0;
   J.flags |= JF_HOST_OUT;
   a.nUpd = J.nUpd;
   a.nFilt = J.nFilt;
@@ -261,7 +278,7 @@ int run_single(ct_table* T, DevJob& J, const uint64_t* dom_in_host) {
     }
     HIPCHK(hipEventRecord(ev.first, T->stream));
   }
-  HIPCHK(launch_propagate(a, std::min(total, MAX_GRID), T->stream));
+  HIPCHK(launch_propagate(a, std::min(total, propagate_max_grid()), T->stream));
   if (T->timing) {
     HIPCHK(hipEventRecord(ev.second, T->stream));
     T->evPending.push_back(ev);
@@ -525,7 +542,13 @@ int ct_create(const int32_t* tuples, int64_t n_tuples, int32_t arity, const int3
   if (!T) return fail(CT_E_NOMEM, "host allocation failed");
   T->cfg.branch_policy = CT_BRANCH_AUTO;
   T->cfg.max_depth = 256;
+  T->cfg.schedule = CT_SCHED_AUTO;
   if (cfg) {
+    if (cfg->schedule < 0 || cfg->schedule > 2) {
+      delete T;
+      return fail(CT_E_INVALID, "schedule %d", cfg->schedule);
+    }
+    T->cfg.schedule = cfg->schedule;
     if (cfg->branch_policy < 0 || cfg->branch_policy > 2) {
       delete T;
       return fail(CT_E_INVALID, "branch_policy %d", cfg->branch_policy);
@@ -867,10 +890,11 @@ int ct_propagate_batch(const ct_job* jobs, int32_t n_jobs, void* stream_v, int32
       J.depthAfter = S.depth;
     }
     S.failed = 2;
+    if ((J.flags & JF_PROPAGATE) && use_solo(T, n_jobs)) J.flags |= JF_SOLO;
     job_counts(T, J);
     updOff[j + 1] = updOff[j] + J.nUpd;
     filtOff[j + 1] = filtOff[j] + J.nFilt;
-    if (J.nPop > 0 || !(J.flags & JF_PROPAGATE)) prep.push_back(j);
+    if (needs_prep(J)) prep.push_back(j);
   }
   // stage to the device
   const size_t nOff = 2 * (size_t)(n_jobs + 1) + prep.size() + 1;
@@ -908,7 +932,7 @@ int ct_propagate_batch(const ct_job* jobs, int32_t n_jobs, void* stream_v, int32
   a.queue = q->queue;
   a.hostErr = q->hostErr;
   const int total = a.nPrep + a.nUpd + a.nFilt;
-  if (total > 0) HIPCHK(launch_propagate(a, std::min(total, MAX_GRID), stream));
+  if (total > 0) HIPCHK(launch_propagate(a, std::min(total, propagate_max_grid()), stream));
   return CT_OK;
 }
 

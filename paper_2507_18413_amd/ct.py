@@ -20,6 +20,7 @@ HEADER = os.path.join(ROOT, "include", "ct.h")
 OK, FAIL = 0, 1
 E_INVALID, E_NOT_SUBSET, E_STATE, E_NOMEM, E_DEVICE = -1, -2, -3, -4, -5
 BRANCH_AUTO, BRANCH_RESET, BRANCH_INCREMENTAL = 0, 1, 2
+SCHED_AUTO, SCHED_SOLO, SCHED_SPLIT = 0, 1, 2
 JOB_PROPAGATE, JOB_FROM_ROOT = 1, 2
 
 
@@ -30,7 +31,7 @@ class CTError(RuntimeError):
 
 
 class ct_config(C.Structure):
-    _fields_ = [("branch_policy", C.c_int32), ("max_depth", C.c_int32)]
+    _fields_ = [("branch_policy", C.c_int32), ("max_depth", C.c_int32), ("schedule", C.c_int32)]
 
 
 class ct_layout_info(C.Structure):
@@ -133,7 +134,8 @@ def _ptr(x):
 class Table:
     """One table constraint on the GPU with its slots (reversible states)."""
 
-    def __init__(self, tuples, lo, dsizes, init_dom=None, branch_policy=BRANCH_AUTO, max_depth=256):
+    def __init__(self, tuples, lo, dsizes, init_dom=None, branch_policy=BRANCH_AUTO, max_depth=256,
+                 schedule=SCHED_AUTO):
         L = lib()
         tuples = np.ascontiguousarray(tuples, dtype=np.int32)
         lo = np.ascontiguousarray(lo, dtype=np.int32)
@@ -141,7 +143,7 @@ class Table:
         t = int(tuples.shape[0]) if tuples.ndim == 2 and tuples.size else 0
         if init_dom is not None:
             init_dom = np.ascontiguousarray(init_dom, dtype=np.uint64)
-        cfg = ct_config(int(branch_policy), int(max_depth))
+        cfg = ct_config(int(branch_policy), int(max_depth), int(schedule))
         h = C.c_void_p()
         st = L.ct_create(_p(tuples) if t else None, t, int(ds.shape[0]), _p(lo), _p(ds), _p(init_dom),
                          C.byref(cfg), C.byref(h))

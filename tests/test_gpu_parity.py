@@ -29,9 +29,9 @@ def bits_of(words, t):
     return [int((int(words[j // 64]) >> (j % 64)) & 1) for j in range(t)]
 
 
-def pair(tup, lo, ds, init=None, policy=ct.BRANCH_AUTO, max_depth=256):
-    say("create", f"t={len(tup)}", f"n={len(ds)}", f"policy={policy}")
-    g = ct.Table(tup, lo, ds, init_dom=init, branch_policy=policy, max_depth=max_depth)
+def pair(tup, lo, ds, init=None, policy=ct.BRANCH_AUTO, max_depth=256, schedule=ct.SCHED_AUTO):
+    say("create", f"t={len(tup)}", f"n={len(ds)}", f"policy={policy}", f"schedule={schedule}")
+    g = ct.Table(tup, lo, ds, init_dom=init, branch_policy=policy, max_depth=max_depth, schedule=schedule)
     o = O.OracleTable(tup, lo, ds, init_dom=init)
     return g, o
 
@@ -108,8 +108,9 @@ def test_random_sequences_vs_oracle(chunk):
         lay = W.DomLayout(ds, lo)
         init = random_subset(rng, lay, lay.full(), 0.8) if rng.random() < 0.3 else None
         policy = int(rng.integers(0, 3))
+        schedule = (ct.SCHED_SOLO, ct.SCHED_SPLIT)[case % 2]
         say(f"chunk={chunk} case={case}")
-        G, Ot = pair(tup, lo, ds, init=init, policy=policy)
+        G, Ot = pair(tup, lo, ds, init=init, policy=policy, schedule=schedule)
         assert (G.create_status == ct.FAIL) == (Ot.create_status == O.FAIL)
         if Ot.create_status == O.FAIL:
             st, _ = G.propagate(lay.full() if init is None else init)
@@ -145,8 +146,8 @@ def test_random_sequences_vs_oracle(chunk):
             same_state(G, Ot, where=f"step {step}")
 
 
-def run_plain(spec, n_calls, picker, config, check_every=1):
-    G, Ot = pair(spec.tuples, spec.lo, spec.dsizes)
+def run_plain(spec, n_calls, picker, config, check_every=1, schedule=ct.SCHED_AUTO):
+    G, Ot = pair(spec.tuples, spec.lo, spec.dsizes, schedule=schedule)
     lay = spec.layout()
     same_state(G, Ot, where="root")
     rng = W.rng_for(W.DEFAULT_SEED, config, 9)
@@ -175,16 +176,18 @@ def test_config1_full():
     run_plain(W.config1_table(), 100, W.pick_small_removal, 1)
 
 
-def test_config2_scaled():
-    say("config2 scaled: arity 5, d=50, 20,000 tuples, 300 calls")
+@pytest.mark.parametrize("schedule", [ct.SCHED_SOLO, ct.SCHED_SPLIT])
+def test_config2_scaled(schedule):
+    say("config2 scaled: arity 5, d=50, 20,000 tuples, 300 calls, schedule", schedule)
     spec = W.config2_table(t=20_000)
-    run_plain(spec, 300, W.pick_fraction_removal, 2)
+    run_plain(spec, 300, W.pick_fraction_removal, 2, schedule=schedule)
 
 
-def test_config2_full():
-    say("config2 full: arity 5, d=50, 200,000 tuples, 1,000 calls")
+@pytest.mark.parametrize("schedule", [ct.SCHED_AUTO, ct.SCHED_SPLIT])
+def test_config2_full(schedule):
+    say("config2 full: arity 5, d=50, 200,000 tuples, 1,000 calls, schedule", schedule)
     spec = W.config2_table()
-    G, Ot = run_plain(spec, 1000, W.pick_fraction_removal, 2)
+    G, Ot = run_plain(spec, 1000, W.pick_fraction_removal, 2, schedule=schedule)
     assert G.W == 3125
 
 
@@ -256,12 +259,13 @@ def from_dev(t):
     return t.cpu().numpy().view(np.uint64)
 
 
-def test_batch_from_root_nodes_vs_oracle():
+@pytest.mark.parametrize("schedule", [ct.SCHED_AUTO, ct.SCHED_SPLIT])
+def test_batch_from_root_nodes_vs_oracle(schedule):
     import torch
-    say("batch: FROM_ROOT search nodes, Zipf table 60k tuples, 256 nodes")
+    say("batch: FROM_ROOT search nodes, Zipf table 60k tuples, 256 nodes, schedule", schedule)
     spec = W.config4_table(t=60_000)
     lay = spec.layout()
-    G, Ot = pair(spec.tuples, spec.lo, spec.dsizes)
+    G, Ot = pair(spec.tuples, spec.lo, spec.dsizes, schedule=schedule)
     root = Ot.domains()
     nodes = W.config4_nodes(lay, root, 256)
     first = G.slots_alloc(256, max_depth=0)
@@ -292,13 +296,15 @@ def test_batch_from_root_nodes_vs_oracle():
     assert (from_dev(dout[:64]) == got_dom[:64]).all()
 
 
-def test_batch_with_backtracking_equals_sequential():
+@pytest.mark.parametrize("schedule", [ct.SCHED_SOLO, ct.SCHED_SPLIT])
+def test_batch_with_backtracking_equals_sequential(schedule):
     import torch
-    say("batch: 32 slots with pops/pushes vs single calls")
+    say("batch: 32 slots with pops/pushes vs single calls, schedule", schedule)
     spec = W.config2_table(t=30_000, d=20, n=4)
     lay = spec.layout()
-    Gb = ct.Table(spec.tuples, spec.lo, spec.dsizes)          # batched
-    Gs = ct.Table(spec.tuples, spec.lo, spec.dsizes)          # single calls
+    Gb = ct.Table(spec.tuples, spec.lo, spec.dsizes, schedule=schedule)   # batched
+    Gs = ct.Table(spec.tuples, spec.lo, spec.dsizes,             # single calls, other schedule
+                  schedule=ct.SCHED_SPLIT if schedule == ct.SCHED_SOLO else ct.SCHED_SOLO)
     nsl = 32
     fb = Gb.slots_alloc(nsl)
     fs = Gs.slots_alloc(nsl)
