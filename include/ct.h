@@ -213,10 +213,12 @@ int ct_propagate_batch(const ct_job *jobs, int32_t n_jobs, void *stream, int32_t
 int ct_batch_status(void *stream);
 
 /* Kernel timing of the synchronous calls (ct_propagate*, flushes of
- * ct_push/ct_pop): when on, each launch on the table's internal stream is
- * bracketed by two HIP events and the elapsed time is accumulated.
- * ct_get_timing returns the cumulative kernel milliseconds and launch count
- * since timing was last switched on. */
+ * ct_push/ct_pop): when on, every launch measures itself on the GPU's
+ * constant-rate wall clock (earliest workgroup start to latest workgroup
+ * end) and adds the duration to a device counter; no host events are
+ * inserted into the stream.  ct_get_timing synchronizes the table's stream
+ * and returns the cumulative kernel milliseconds and launch count since
+ * timing was last switched on. */
 int ct_set_timing(ct_table *t, int32_t on);
 int ct_get_timing(ct_table *t, double *kernel_ms, int64_t *launches);
 

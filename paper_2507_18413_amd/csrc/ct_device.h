@@ -123,6 +123,10 @@ struct KArgs {
   int32_t nJobs, nPrep, nUpd, nFilt;
   int32_t* queue;          // [0] head, [1] exit count, [2] launches, [3] error
   int32_t* hostErr;        // nullable: error word copied here by the last block
+  // nullable: kernel timing on the device clock (wall_clock64): [0] earliest
+  // workgroup start, [1] latest end, [2] workgroups done, [3] summed
+  // durations, [4] timed launches
+  unsigned long long* clock;
   DevJob job;
   uint64_t inl[INLINE_WORDS];
 };

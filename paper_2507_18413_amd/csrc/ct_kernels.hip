@@ -234,7 +234,7 @@ __device__ void do_prep(const KArgs& a, const DevJob& J, Shared& sh) {
 // ---------------------------------------------------------------------------
 // prologue of Alg. 1 for one job (every update item recomputes it in LDS)
 // ---------------------------------------------------------------------------
-__device__ void prologue(const KArgs& a, const DevJob& J, Shared& sh) {
+__device__ void prologue(const KArgs& a, const DevJob& J, Shared& sh, bool pushHere) {
   const TabDesc* T = J.tab;
   SlotDesc* s = J.slot;
   const bool fromRoot = J.flags & JF_FROM_ROOT;
@@ -253,6 +253,23 @@ __device__ void prologue(const KArgs& a, const DevJob& J, Shared& sh) {
     }
     sh.trailTop = s->trailTop;
     sh.serial = J.nPush > 0 ? J.serialBase + J.nPush - 1 : s->serial;
+    if (pushHere) {
+      // this job's pushes record the state before it (levels of push_levels)
+      const int d0 = s->depth;
+      const int failed = s->failed;
+      for (int k = 0; k < J.nPush; ++k) {
+        Level L;
+        L.trailTop = sh.trailTop;
+        L.limit = sh.limit;
+        L.failed = failed;
+        L.serial = k == 0 ? s->serial : J.serialBase + k - 1;
+        L.pad = 0;
+        s->levels[d0 + k] = L;
+      }
+      sh.depth = d0;
+      s->depth = d0 + J.nPush;
+      s->serial = J.serialBase + J.nPush - 1;
+    }
   }
   for (int i = threadIdx.x; i < n; i += BLOCK) {
     sh.size[i] = 0;
@@ -270,6 +287,8 @@ __device__ void prologue(const KArgs& a, const DevJob& J, Shared& sh) {
       const uint64_t ld = last[q];
       if (din & ~ld) sh.bad_sub = 1;
       dl = ld & ~din;
+      if (pushHere)
+        for (int k = 0; k < J.nPush; ++k) s->levelDom[(int64_t)(sh.depth + k) * D + q] = ld;
     }
     sh.din[q] = din;
     atomicAdd(&sh.size[i], __popcll(din));
@@ -602,7 +621,7 @@ __device__ void do_update(const KArgs& a, const DevJob& J, int chunk, Shared& sh
   if (J.nPop > 0) {
     if (!block_wait(a, &s->prepDone, 1, sh)) return;
   }
-  prologue(a, J, sh);
+  prologue(a, J, sh, false);
   update_granules<NGW>(a, J, sh, chunk * GPI + wave_id() * NGW, false, &s->jobTrail);
 
   // count finished items; the last one finalizes the job
@@ -677,8 +696,9 @@ __device__ void do_filter(const KArgs& a, const DevJob& J, int chunk, Shared& sh
 // ---------------------------------------------------------------------------
 __device__ void do_solo(const KArgs& a, const DevJob& J, Shared& sh) {
   SlotDesc* s = J.slot;
-  apply_pops_pushes(J, sh);
-  prologue(a, J, sh);
+  const bool pushHere = J.nPop == 0 && J.nPush > 0;
+  if (!pushHere) apply_pops_pushes(J, sh);
+  prologue(a, J, sh, pushHere);
   if (threadIdx.x == 0) sh.trailCount = 0;
   __syncthreads();
   const int nGran = J.tab->nGran;
@@ -703,11 +723,35 @@ __device__ void do_solo(const KArgs& a, const DevJob& J, Shared& sh) {
   }
 }
 
+// Device-clock duration of a launch: first workgroup start to last end.
+__device__ void clock_begin(const KArgs& a) {
+  if (a.clock && threadIdx.x == 0) atomicMin(&a.clock[0], wall_clock64());
+}
+
+__device__ void clock_end(const KArgs& a) {
+  if (!a.clock || threadIdx.x != 0) return;
+  const unsigned long long now = wall_clock64();
+  atomicMax(&a.clock[1], now);
+  __threadfence();
+  const unsigned long long prev = atomicAdd(&a.clock[2], 1ull);
+  if (prev == gridDim.x - 1) {
+    const unsigned long long t0 = atomicOr(&a.clock[0], 0ull);
+    const unsigned long long t1 = atomicOr(&a.clock[1], 0ull);
+    atomicAdd(&a.clock[3], t1 > t0 ? t1 - t0 : 0ull);
+    atomicAdd(&a.clock[4], 1ull);
+    a.clock[0] = ~0ull;
+    a.clock[1] = 0ull;
+    a.clock[2] = 0ull;
+    __threadfence();
+  }
+}
+
 __global__ void __launch_bounds__(BLOCK) propagate_kernel(KArgs a) {
   __shared__ Shared sh;
   int32_t* q = a.queue;
   const int total = a.nPrep + a.nUpd + a.nFilt;
   const bool dynamic = (int)gridDim.x < total;
+  clock_begin(a);
   int item = blockIdx.x;
   while (item < total) {
     if (item < a.nPrep) {
@@ -735,6 +779,8 @@ __global__ void __launch_bounds__(BLOCK) propagate_kernel(KArgs a) {
     __syncthreads();
     item = sh.item;
   }
+  __syncthreads();
+  clock_end(a);
   if (!dynamic) return;
   // the last workgroup out resets the queue for the next launch
   if (threadIdx.x == 0) {

@@ -142,12 +142,10 @@ struct ct_table {
   uint64_t* pDomIn = nullptr;   // D words (used when D > INLINE_WORDS)
   uint64_t* pCt = nullptr;      // W words (lazily)
   int32_t* pStatus = nullptr;
-  // optional kernel timing of synchronous launches: event pairs are read
-  // back lazily so that timing adds no synchronization to a call
+  // optional kernel timing of synchronous launches, on the device clock
+  // (no host events: they would add dispatch packets to every call)
+  unsigned long long* dClock = nullptr;  // 5 words, see KArgs::clock
   bool timing = false;
-  std::vector<std::pair<hipEvent_t, hipEvent_t>> evPool, evPending;
-  double kernelMs = 0.0;
-  int64_t launches = 0;
 };
 
 namespace {
@@ -267,22 +265,8 @@ int run_single(ct_table* T, DevJob& J, const uint64_t* dom_in_host) {
   if (total == 0) return CT_OK;
   volatile int32_t* status = T->pStatus;
   *status = kStatusPending;
-  std::pair<hipEvent_t, hipEvent_t> ev{nullptr, nullptr};
-  if (T->timing) {
-    if (T->evPool.empty()) {
-      HIPCHK(hipEventCreate(&ev.first));
-      HIPCHK(hipEventCreate(&ev.second));
-    } else {
-      ev = T->evPool.back();
-      T->evPool.pop_back();
-    }
-    HIPCHK(hipEventRecord(ev.first, T->stream));
-  }
+  a.clock = T->timing ? T->dClock : nullptr;
   HIPCHK(launch_propagate(a, std::min(total, propagate_max_grid()), T->stream));
-  if (T->timing) {
-    HIPCHK(hipEventRecord(ev.second, T->stream));
-    T->evPending.push_back(ev);
-  }
   // The job publishes its status (and its outputs before it) to coherent
   // host memory with a system-scope release: wait for that word instead of
   // the whole kernel.  The kernel's tail finishes on the stream, which
@@ -369,14 +353,6 @@ void ct_destroy(ct_table* T) {
   if (T->pDomIn) (void)hipHostFree(T->pDomIn);
   if (T->pCt) (void)hipHostFree(T->pCt);
   if (T->pStatus) (void)hipHostFree(T->pStatus);
-  for (auto& e : T->evPool) {
-    (void)hipEventDestroy(e.first);
-    (void)hipEventDestroy(e.second);
-  }
-  for (auto& e : T->evPending) {
-    (void)hipEventDestroy(e.first);
-    (void)hipEventDestroy(e.second);
-  }
   if (T->stream) (void)hipStreamDestroy(T->stream);
   delete T;
 }
@@ -744,54 +720,32 @@ int ct_slot_stats(ct_table* T, int32_t slot, ct_stats* st) {
   return CT_OK;
 }
 
-static int drain_timing(ct_table* T) {
-  for (auto& e : T->evPending) {
-    HIPCHK(hipEventSynchronize(e.second));
-    float ms = 0.f;
-    HIPCHK(hipEventElapsedTime(&ms, e.first, e.second));
-    T->kernelMs += ms;
-    T->launches++;
-    T->evPool.push_back(e);
-  }
-  T->evPending.clear();
-  return CT_OK;
-}
-
-int ct_batch_status(void* stream_v) {
-  hipStream_t stream = (hipStream_t)stream_v;
-  QueueCtx* q = nullptr;
-  {
-    std::lock_guard<std::mutex> lk(g_qmu);
-    auto it = g_queues.find(stream);
-    if (it == g_queues.end()) return CT_OK;
-    q = it->second;
-  }
-  HIPCHK(hipStreamSynchronize(stream));
-  const int32_t err = *(volatile int32_t*)q->hostErr;
-  if (!err) return CT_OK;
-  *q->hostErr = 0;
-  HIPCHK(hipMemsetAsync(q->queue + 3, 0, sizeof(int32_t), stream));
-  HIPCHK(hipStreamSynchronize(stream));
-  return fail(CT_E_DEVICE, "device-side error %d in a batch on this stream (wait timeout or trail "
-              "overflow); the slots of that batch are undefined", err);
-}
+static const unsigned long long kClockInit[5] = {~0ull, 0ull, 0ull, 0ull, 0ull};
 
 int ct_set_timing(ct_table* T, int32_t on) {
   int rc = check_poison(T);
   if (rc) return rc;
-  if ((rc = drain_timing(T))) return rc;
+  HIPCHK(hipStreamSynchronize(T->stream));
+  if (on && !T->dClock) {
+    if ((rc = dev_alloc(T, (void**)&T->dClock, sizeof(kClockInit)))) return rc;
+  }
+  if (T->dClock) HIPCHK(hipMemcpy(T->dClock, kClockInit, sizeof(kClockInit), hipMemcpyHostToDevice));
   T->timing = on != 0;
-  T->kernelMs = 0.0;
-  T->launches = 0;
   return CT_OK;
 }
 
 int ct_get_timing(ct_table* T, double* kernel_ms, int64_t* launches) {
   if (!T) return fail(CT_E_INVALID, "null table");
-  int rc = drain_timing(T);
-  if (rc) return rc;
-  if (kernel_ms) *kernel_ms = T->kernelMs;
-  if (launches) *launches = T->launches;
+  unsigned long long c[5] = {0, 0, 0, 0, 0};
+  if (T->dClock) {
+    HIPCHK(hipStreamSynchronize(T->stream));
+    HIPCHK(hipMemcpy(c, T->dClock, sizeof(c), hipMemcpyDeviceToHost));
+  }
+  int dev = 0, khz = 0;
+  HIPCHK(hipGetDevice(&dev));
+  HIPCHK(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev));
+  if (kernel_ms) *kernel_ms = khz > 0 ? (double)c[3] / (double)khz : 0.0;
+  if (launches) *launches = (int64_t)c[4];
   return CT_OK;
 }
 
