@@ -720,6 +720,25 @@ int ct_slot_stats(ct_table* T, int32_t slot, ct_stats* st) {
   return CT_OK;
 }
 
+int ct_batch_status(void* stream_v) {
+  hipStream_t stream = (hipStream_t)stream_v;
+  QueueCtx* q = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(g_qmu);
+    auto it = g_queues.find(stream);
+    if (it == g_queues.end()) return CT_OK;
+    q = it->second;
+  }
+  HIPCHK(hipStreamSynchronize(stream));
+  const int32_t err = *(volatile int32_t*)q->hostErr;
+  if (!err) return CT_OK;
+  *q->hostErr = 0;
+  HIPCHK(hipMemsetAsync(q->queue + 3, 0, sizeof(int32_t), stream));
+  HIPCHK(hipStreamSynchronize(stream));
+  return fail(CT_E_DEVICE, "device-side error %d in a batch on this stream (wait timeout or trail "
+              "overflow); the slots of that batch are undefined", err);
+}
+
 static const unsigned long long kClockInit[5] = {~0ull, 0ull, 0ull, 0ull, 0ull};
 
 int ct_set_timing(ct_table* T, int32_t on) {
