@@ -37,6 +37,8 @@ def parse():
     p.add_argument("--calls", type=int, default=1000)
     p.add_argument("--cpu-seconds", type=float, default=10.0)
     p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--nodes", type=int, default=4096)
+    p.add_argument("--no-nodes", action="store_true")
     return p.parse_args()
 
 
@@ -111,6 +113,57 @@ def cpu_baseline(spec, script, seconds):
     while o.depth > 0:
         o.pop()
     return props / el, props, el, passes
+
+
+def nodes_leg(seed, n_nodes, reps, warmup, schedule=0):
+    """Batched CT across search nodes: one arity-6 table with 1,000,000 Zipf
+    tuples, n_nodes independent domain states (each removes a random 0-60 %
+    of every variable's values), all propagated from the root state in one
+    launch with per-node currTable copies in HBM."""
+    import numpy as np
+    import torch
+    from paper_2507_18413_amd import ct
+    from paper_2507_18413_amd import workloads as W
+    spec = W.config4_table(seed)
+    lay = spec.layout()
+    table = ct.Table(spec.tuples, spec.lo, spec.dsizes, max_depth=0, schedule=schedule)
+    root = table.domains()
+    nodes = W.config4_nodes(lay, root, n_nodes, seed)
+    first = table.slots_alloc(n_nodes, max_depth=0)
+    din = torch.from_numpy(nodes.view(np.int64)).cuda()
+    dout = torch.zeros_like(din)
+    status = torch.zeros(n_nodes, dtype=torch.int32, device="cuda")
+    jobs = [dict(table=table, slot=first + k, flags=ct.JOB_PROPAGATE | ct.JOB_FROM_ROOT,
+                 dom_in=din[k], dom_out=dout[k]) for k in range(n_nodes)]
+    stream = torch.cuda.current_stream()
+    for _ in range(warmup):
+        ct.propagate_batch(jobs, status, stream)
+    torch.cuda.synchronize()
+    s0 = [table.stats(first + k) for k in (0,)]
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record(stream)
+    for _ in range(reps):
+        ct.propagate_batch(jobs, status, stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ct.batch_status(stream)
+    gpu_ms = e0.elapsed_time(e1) / reps
+    st = status.cpu().numpy()
+    # algorithmic bytes of one batch: compulsory traffic = supports once +
+    # root currTable once + per node currTable write + domains
+    W_words = table.W
+    comp = 8 * table.rows * W_words + 8 * W_words + n_nodes * (8 * W_words + 16 * lay.D)
+    return {
+        "nodes": n_nodes, "tuples": spec.t, "ms_per_batch": round(gpu_ms, 3),
+        "node_props_per_s": round(n_nodes / (gpu_ms / 1e3), 1),
+        "wall_ms_per_batch": round(wall / reps * 1e3, 3),
+        "status_counts": {int(k): int(v) for k, v in zip(*np.unique(st, return_counts=True))},
+        "compulsory_bytes": comp,
+        "compulsory_GBps": round(comp / (gpu_ms / 1e3) / 1e9, 1),
+        "frac_of_hbm_peak": round(comp / (gpu_ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
+    }
 
 
 def main():
@@ -191,6 +244,8 @@ def main():
                      "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": None,
                      "bytes_per_launch": round(per_launch_bytes, 1)},
     }
+    if not args.no_nodes:
+        out["batched_nodes"] = nodes_leg(seed, args.nodes, max(1, args.steps), 1)
     if not args.no_cpu_baseline:
         cps, cprops, cel, passes = cpu_baseline(spec, script, args.cpu_seconds)
         out["cpu_baseline"] = {"value": round(cps, 1), "unit": "propagations/s", "cores": 1, "kind": "oracle",

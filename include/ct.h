@@ -67,7 +67,7 @@ typedef struct ct_table ct_table;
  * workgroup (no hand-off between workgroups; best for small tables and for
  * batches of many jobs), SPLIT spreads updateTable over workgroups of 8
  * granules and filterDomains over workgroups of 4 domain words.  AUTO picks
- * SOLO for tables of at most 64 granules (262,144 tuples) and for batches of
+ * SOLO for tables of at most 4 granules (16,384 tuples) and for batches of
  * at least 256 jobs.  Results are identical. */
 #define CT_SCHED_AUTO 0
 #define CT_SCHED_SOLO 1

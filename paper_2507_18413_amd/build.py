@@ -36,6 +36,10 @@ def torch_hip_runtime():
 
 
 def compile_cmd(src, obj):
+    if src.endswith(".cpp"):
+        # host-only runtime: HIP runtime API, no device code
+        return ["g++", "-O2", "-std=c++17", "-fPIC", "-c", "-Wall", "-D__HIP_PLATFORM_AMD__=1",
+                "-I", "/opt/rocm/include", "-I", os.path.join(ROOT, "include"), "-I", CSRC, src, "-o", obj]
     return [HIPCC, f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-c",
             "-Wall", "-Wno-unused-function",
             # packed fp32 instructions stay off in every device pass

@@ -24,6 +24,18 @@
 #pragma once
 #include <stdint.h>
 
+// Pointers inside the descriptors address global memory (device HBM or
+// pinned host memory).  The device pass types them as address space 1 so
+// that the compiler emits global_load/global_store rather than flat
+// accesses, which would share the LDS wait counter and serialize the
+// support-row loads behind every LDS read.  The host pass sees plain
+// pointers; the layout is the same.
+#if defined(__HIP_DEVICE_COMPILE__)
+#define CT_G __attribute__((address_space(1)))
+#else
+#define CT_G
+#endif
+
 namespace ctk {
 
 constexpr int WAVE = 64;
@@ -55,13 +67,13 @@ struct VarDesc {
 struct TabDesc {
   int32_t n, rows, D, nGran;
   int64_t W, stride;          // stride = nGran * 64 words per support row
-  const uint64_t* S;          // rows x stride
-  const VarDesc* vars;        // n
-  const int32_t* wordVar;     // D: variable owning each domain word
+  const CT_G uint64_t* S;          // rows x stride
+  const CT_G VarDesc* vars;        // n
+  const CT_G int32_t* wordVar;     // D: variable owning each domain word
   // root state, read-only after creation
-  const uint64_t* ct0;
-  const int32_t* idx0;
-  const uint64_t* dom0;
+  const CT_G uint64_t* ct0;
+  const CT_G int32_t* idx0;
+  const CT_G uint64_t* dom0;
   int32_t limit0, rootFailed;
   int32_t policy, pad;
 };
@@ -79,16 +91,16 @@ enum StatIdx { S_JOBS = 0, S_GRAN_IN, S_ROWS, S_GRAN_ROWS, S_TRAIL, S_RES_CHECK,
 
 struct SlotDesc {
   // arrays
-  uint64_t* ct;
-  int32_t* idx[2];
-  int32_t* stamp;
-  uint64_t* lastDom;
-  int32_t* res;           // residue word per support row
-  TrailHdr* trailHdr;
-  uint64_t* trailWords;   // trailCap x 64
-  Level* levels;          // maxDepth
-  uint64_t* levelDom;     // maxDepth x D
-  int32_t* nzFlag;        // nGran: granule non-zero after the running job
+  CT_G uint64_t* ct;
+  CT_G int32_t* idx[2];
+  CT_G int32_t* stamp;
+  CT_G uint64_t* lastDom;
+  CT_G int32_t* res;           // residue word per support row
+  CT_G TrailHdr* trailHdr;
+  CT_G uint64_t* trailWords;   // trailCap x 64
+  CT_G Level* levels;          // maxDepth
+  CT_G uint64_t* levelDom;     // maxDepth x D
+  CT_G int32_t* nzFlag;        // nGran: granule non-zero after the running job
   int64_t trailCap;
   int32_t maxDepth, pad0;
   // mutable state
@@ -100,12 +112,12 @@ struct SlotDesc {
 };
 
 struct DevJob {
-  const TabDesc* tab;
-  SlotDesc* slot;
-  const uint64_t* dom_in;  // device pointer, or unused with JF_INLINE_DOM
-  uint64_t* dom_out;
-  uint64_t* ct_out;
-  int32_t* status_out;
+  const CT_G TabDesc* tab;
+  CT_G SlotDesc* slot;
+  const CT_G uint64_t* dom_in;  // device pointer, or unused with JF_INLINE_DOM
+  CT_G uint64_t* dom_out;
+  CT_G uint64_t* ct_out;
+  CT_G int32_t* status_out;
   uint32_t flags;
   int32_t nPop, nPush;
   int32_t serialBase;      // serial of the k-th pushed level = serialBase + k
@@ -116,10 +128,10 @@ struct DevJob {
 
 // Kernel argument block of the persistent propagate kernel.
 struct KArgs {
-  const DevJob* jobs;      // nullptr: single job in `job`
-  const int32_t* updOff;   // nJobs + 1 prefix sums of update items (nullptr for one job)
-  const int32_t* filtOff;  // nJobs + 1 prefix sums of filter items
-  const int32_t* prepList; // jobs that need a prep item (pops, or only pushes/pops)
+  const CT_G DevJob* jobs;      // nullptr: single job in `job`
+  const CT_G int32_t* updOff;   // nJobs + 1 prefix sums of update items (nullptr for one job)
+  const CT_G int32_t* filtOff;  // nJobs + 1 prefix sums of filter items
+  const CT_G int32_t* prepList; // jobs that need a prep item (pops, or only pushes/pops)
   int32_t nJobs, nPrep, nUpd, nFilt;
   int32_t* queue;          // [0] head, [1] exit count, [2] launches, [3] error
   int32_t* hostErr;        // nullable: error word copied here by the last block

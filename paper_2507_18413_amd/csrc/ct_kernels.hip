@@ -32,6 +32,7 @@ namespace ctk {
 constexpr int NGW = 2;                 // granules per wave per update item (split mode)
 constexpr int GPI = WAVES * NGW;       // granules per update item (split mode)
 constexpr int NGS = 4;                 // granules per wave per step (solo mode)
+constexpr int LANE_SCAN = 16;          // words each missing lane checks before the wave scan
 constexpr int ROW_UNROLL = 8;          // support rows loaded per batch
 constexpr uint32_t SPIN_LIMIT = 1u << 22;
 
@@ -61,6 +62,7 @@ struct Shared {
   uint64_t din[MAX_D];
   uint16_t rows[MAX_ROWS];
   uint8_t nz[MAX_GRAN];        // granule non-zero flags of a job run by one workgroup
+  uint16_t gidx[MAX_GRAN];     // granule list of a job run by one workgroup
 };
 
 // Record a device error: the host sees it through hostErr (pinned) and the
@@ -113,8 +115,14 @@ __device__ int block_scan_excl(int v, int* total, Shared& sh) {
   return off + x - v;
 }
 
-__device__ __forceinline__ const DevJob& job_of(const KArgs& a, int j) {
-  return a.jobs ? a.jobs[j] : a.job;
+// The job descriptor by value: from the batch array (global memory) or from
+// the kernel arguments; a reference chosen between the two would be a flat
+// pointer and turn every field access into a flat load.
+__device__ __forceinline__ DevJob job_of(const KArgs& a, int j) {
+  DevJob J;
+  if (a.jobs) J = a.jobs[j];
+  else J = a.job;
+  return J;
 }
 
 __device__ __forceinline__ uint64_t job_din(const KArgs& a, const DevJob& J, int k) {
@@ -140,7 +148,7 @@ __device__ __forceinline__ void item_fence(const DevJob& J) {
 }
 
 // largest j with off[j] <= x  (off has n + 1 entries, off[0] = 0)
-__device__ int find_job(const int32_t* off, int n, int x) {
+__device__ int find_job(const CT_G int32_t* off, int n, int x) {
   int lo = 0, hi = n;  // off[lo] <= x < off[hi]
   while (hi - lo > 1) {
     const int mid = (lo + hi) >> 1;
@@ -183,10 +191,25 @@ __device__ void apply_pops_pushes(const DevJob& J, Shared& sh) {
     const int d = sh.depth;
     const Level L = s->levels[d];
     const int64_t top = sh.trailTop;
-    for (int64_t e = L.trailTop + wave_id(); e < top; e += WAVES) {
-      const TrailHdr h = s->trailHdr[e];
-      s->ct[(int64_t)h.gran * GW + lane_id()] = s->trailWords[e * GW + lane_id()];
-      if (lane_id() == 0) s->stamp[h.gran] = h.oldStamp;
+    // entries of one level name distinct granules: restore 4 per wave at once
+    for (int64_t e0 = L.trailTop + 4 * wave_id(); e0 < top; e0 += 4 * WAVES) {
+      TrailHdr h[4];
+      uint64_t w[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int64_t e = e0 + j;
+        if (e < top) {
+          h[j] = s->trailHdr[e];
+          w[j] = s->trailWords[e * GW + lane_id()];
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        if (e0 + j < top) {
+          s->ct[(int64_t)h[j].gran * GW + lane_id()] = w[j];
+          if (lane_id() == 0) s->stamp[h[j].gran] = h[j].oldStamp;
+        }
+      }
     }
     for (int q = threadIdx.x; q < D; q += BLOCK) s->lastDom[q] = s->levelDom[(int64_t)d * D + q];
     __syncthreads();
@@ -240,7 +263,7 @@ __device__ void prologue(const KArgs& a, const DevJob& J, Shared& sh, bool pushH
   const bool fromRoot = J.flags & JF_FROM_ROOT;
   const bool root = J.flags & JF_ROOT;
   const int n = T->n, D = T->D;
-  const uint64_t* last = fromRoot ? T->dom0 : s->lastDom;
+  const CT_G uint64_t* last = fromRoot ? T->dom0 : s->lastDom;
   if (threadIdx.x == 0) {
     sh.bad_stray = 0;
     sh.bad_sub = 0;
@@ -348,7 +371,7 @@ __device__ void prologue(const KArgs& a, const DevJob& J, Shared& sh, bool pushH
 // Granule flags go to LDS (whole job in one workgroup) or to global memory.
 // ---------------------------------------------------------------------------
 template <int NG>
-__device__ void update_granules(const KArgs& a, const DevJob& J, Shared& sh, int p0, bool ldsFlags,
+__device__ void update_granules(const KArgs& a, const DevJob& J, Shared& sh, int p0, bool lds,
                                 int* trailCounter) {
   const TabDesc* T = J.tab;
   SlotDesc* s = J.slot;
@@ -365,8 +388,8 @@ __device__ void update_granules(const KArgs& a, const DevJob& J, Shared& sh, int
   const int nseg = sh.nseg, nrows = sh.nrows;
   const int serial = sh.serial;
   const int lane = lane_id();
-  const uint64_t* srcCt = fromRoot ? T->ct0 : s->ct;
-  const int32_t* srcIdx = fromRoot ? T->idx0 : s->idx[s->cur];
+  const CT_G uint64_t* srcCt = fromRoot ? T->ct0 : s->ct;
+  const CT_G int32_t* srcIdx = fromRoot ? T->idx0 : s->idx[s->cur];
   const int64_t trailTop = sh.trailTop;
 
   unsigned long long nAct = 0;
@@ -376,7 +399,7 @@ __device__ void update_granules(const KArgs& a, const DevJob& J, Shared& sh, int
 #pragma unroll
   for (int u = 0; u < NG; ++u) {
     pos[u] = p0 + u;
-    g[u] = pos[u] < nGran ? srcIdx[pos[u]] : -1;
+    g[u] = pos[u] < nGran ? (lds ? (int)sh.gidx[pos[u]] : srcIdx[pos[u]]) : -1;
     act[u] = pos[u] < limit && status == ST_OK;
     old[u] = act[u] ? srcCt[(int64_t)g[u] * GW + lane] : 0ull;
     stv[u] = (act[u] && trailOn && !noop) ? s->stamp[g[u]] : serial;
@@ -472,7 +495,7 @@ __device__ void update_granules(const KArgs& a, const DevJob& J, Shared& sh, int
     if (J.ct_out && w < W) J.ct_out[w] = nw[u];
     const bool nz = __ballot(nw[u] != 0ull) != 0ull;
     if (lane == 0) {
-      if (ldsFlags) sh.nz[pos[u]] = nz ? 1 : 0;
+      if (lds) sh.nz[pos[u]] = nz ? 1 : 0;
       else s->nzFlag[pos[u]] = nz ? 1 : 0;
     }
   }
@@ -495,9 +518,9 @@ __device__ int finalize_update(const DevJob& J, Shared& sh, bool ldsFlags, int j
   const int nGran = T->nGran;
   int st = sh.status;
   if (st == ST_OK && !sh.noop) {
-    const int32_t* src = fromRoot ? T->idx0 : s->idx[s->cur];
+    const CT_G int32_t* src = fromRoot ? T->idx0 : s->idx[s->cur];
     const int dstBuf = fromRoot ? 0 : 1 - s->cur;
-    int32_t* dst = s->idx[dstBuf];
+    CT_G int32_t* dst = s->idx[dstBuf];
     const int per = (limit + BLOCK - 1) / BLOCK;
     const int b = min((int)threadIdx.x * per, limit);
     const int e = min(b + per, limit);
@@ -507,7 +530,7 @@ __device__ int finalize_update(const DevJob& J, Shared& sh, bool ldsFlags, int j
     int sv = block_scan_excl(cnt, &nSurv, sh);
     int zr = nSurv + (b - sv);
     for (int p = b; p < e; ++p) {
-      const int gid = src[p];
+      const int gid = ldsFlags ? (int)sh.gidx[p] : src[p];
       const int f = ldsFlags ? sh.nz[p] : s->nzFlag[p];
       if (f) dst[sv++] = gid; else dst[zr++] = gid;
     }
@@ -545,7 +568,7 @@ __device__ int finalize_update(const DevJob& J, Shared& sh, bool ldsFlags, int j
 // then the active granules in index order until a support is found.
 // ---------------------------------------------------------------------------
 __device__ void filter_word(const KArgs& a, const DevJob& J, int q, int noop, int lim,
-                            const int32_t* idx, unsigned long long* cnt) {
+                            const CT_G int32_t* idx, unsigned long long* cnt) {
   const TabDesc* T = J.tab;
   SlotDesc* s = J.slot;
   const int lane = lane_id();
@@ -569,11 +592,42 @@ __device__ void filter_word(const KArgs& a, const DevJob& J, int q, int noop, in
     cnt[0] += __popcll(__ballot(present));
     cnt[1] += __popcll(miss);
     uint64_t unsup = 0;
+    if (miss) {
+      // every missing lane first walks the words after its old residue
+      // (wrapping at the end of the table): a value's supports are spread
+      // over the whole table, so a nearby word usually still holds one
+      const bool mine = (miss >> lane) & 1ull;
+      const int r = rowBase + lane;
+      const int64_t words = (int64_t)T->nGran * GW;
+      int64_t w = mine ? (int64_t)s->res[r] : 0;
+      bool found = false;
+#pragma unroll 1
+      for (int step = 0; step < LANE_SCAN; step += 4) {
+        uint64_t x[4];
+        int64_t ww[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          ww[j] = w + 1 + step + j;
+          if (ww[j] >= words) ww[j] -= words;
+          x[j] = (mine && !found) ? (s->ct[ww[j]] & T->S[(int64_t)r * stride + ww[j]]) : 0ull;
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          if (!found && x[j]) {
+            found = true;
+            s->res[r] = (int)ww[j];
+          }
+        }
+        if (!__ballot(mine && !found)) break;
+      }
+      cnt[2] += __popcll(__ballot(mine));
+      miss = __ballot(mine && !found);
+    }
     while (miss) {
       const int l = __ffsll(miss) - 1;
       miss &= miss - 1;
       const int r = rowBase + l;
-      const uint64_t* row = T->S + (int64_t)r * stride;
+      const CT_G uint64_t* row = T->S + (int64_t)r * stride;
       int found = -1;
       for (int p = 0; p < lim && found < 0; p += 4) {
         uint64_t x[4];
@@ -700,9 +754,15 @@ __device__ void do_solo(const KArgs& a, const DevJob& J, Shared& sh) {
   if (!pushHere) apply_pops_pushes(J, sh);
   prologue(a, J, sh, pushHere);
   if (threadIdx.x == 0) sh.trailCount = 0;
-  __syncthreads();
   const int nGran = J.tab->nGran;
   const int span = sh.status == ST_OK ? nGran : 0;
+  {
+    // the job's granule list, read once (each update step is then a single
+    // round of independent loads)
+    const CT_G int32_t* src = (J.flags & JF_FROM_ROOT) ? J.tab->idx0 : s->idx[s->cur];
+    for (int p = threadIdx.x; p < span; p += BLOCK) sh.gidx[p] = (uint16_t)src[p];
+  }
+  __syncthreads();
   for (int c = 0; c < span; c += WAVES * NGS) {
     update_granules<NGS>(a, J, sh, c + wave_id() * NGS, true, &sh.trailCount);
   }
@@ -711,7 +771,7 @@ __device__ void do_solo(const KArgs& a, const DevJob& J, Shared& sh) {
   if (st == ST_OK) {
     unsigned long long cnt[3] = {0, 0, 0};
     const int lim = s->limit;
-    const int32_t* idx = s->idx[s->cur];
+    const CT_G int32_t* idx = s->idx[s->cur];
     const int noop = sh.noop;
     for (int q = wave_id(); q < J.tab->D; q += WAVES) filter_word(a, J, q, noop, lim, idx, cnt);
     add_filter_stats(s, cnt);
@@ -760,7 +820,7 @@ __global__ void __launch_bounds__(BLOCK) propagate_kernel(KArgs a) {
     } else if (item < a.nPrep + a.nUpd) {
       const int x = item - a.nPrep;
       const int j = a.jobs ? find_job(a.updOff, a.nJobs, x) : 0;
-      const DevJob& J = job_of(a, j);
+      const DevJob J = job_of(a, j);
       if (J.flags & JF_SOLO) {
         do_solo(a, J, sh);
       } else {

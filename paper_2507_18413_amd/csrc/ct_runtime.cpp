@@ -4,7 +4,7 @@
 // Every step of propagation runs in the HIP kernels of ct_kernels.hip; the
 // host only validates arguments, lays out job descriptors and moves the
 // domain bitmaps across the boundary.
-#include <hip/hip_runtime.h>
+#include <hip/hip_runtime_api.h>
 
 #include <algorithm>
 #include <chrono>
@@ -208,7 +208,7 @@ int check_poison(const ct_table* T) {
   return CT_OK;
 }
 
-constexpr int SOLO_MAX_GRAN = 64;     // tables up to 262,144 tuples run solo
+constexpr int SOLO_MAX_GRAN = 4;      // tables up to 16,384 tuples run solo
 constexpr int SOLO_MIN_BATCH = 256;   // batches this large run every job solo
 
 bool use_solo(const ct_table* T, int nJobs) {
