@@ -207,6 +207,64 @@ typedef struct {
  */
 int ct_propagate_batch(const ct_job *jobs, int32_t n_jobs, void *stream, int32_t *status_dev);
 
+/* ------------------------------------------------------------------------
+ * Many tables sharing variables: propagation to a fixpoint
+ * --------------------------------------------------------------------- */
+/*
+ * A model is a pool of variables plus tables whose columns are pool
+ * variables (a CSP whose constraints are table constraints, Sec. 2).  Its
+ * fixpoint is the largest set of sub-domains of the pool that is GAC for
+ * every table (propagation repeated until nothing changes, Sec. 2), or a
+ * failure.  Each table takes part through its slot 0; a table may belong to
+ * one model.  The pool bitmap uses the per-variable 64-bit segments of the
+ * domain bitmaps above, over all pool variables.  A table column must have
+ * the same dom_lo and dom_size as its pool variable.
+ */
+typedef struct ct_model ct_model;
+
+/* n_vars pool variables with initial domains [dom_lo[i], dom_lo[i] + dom_size[i]). */
+int ct_model_create(int32_t n_vars, const int32_t *dom_lo, const int32_t *dom_size, ct_model **out);
+void ct_model_destroy(ct_model *m);
+
+/* Adds a table; scope (host, arity entries) names the pool variable of each
+ * column, all distinct.  *index (nullable) receives the table's index. */
+int ct_model_add(ct_model *m, ct_table *t, const int32_t *scope, int32_t *index);
+
+/* Word offset of each pool variable in the pool bitmap (host, n_vars) and the
+ * total word count. */
+int ct_model_layout(const ct_model *m, int32_t *pool_off, int32_t *pool_words);
+
+/*
+ * Runs propagation rounds from pool_in (device, pool words) until no domain
+ * changes: every round propagates, in one persistent launch, each table one
+ * of whose variables changed in the previous round (all tables in the first
+ * round) on the pool intersected with its own last domains, and ANDs the
+ * results into the pool.  Rounds are captured in a hipGraph, `rounds_per_graph`
+ * at a time, and replayed until the device reports convergence or failure.
+ * Synchronous on `stream` (NULL = the model's own stream).  pool_out (device)
+ * receives the fixpoint (undefined after CT_FAIL).  n_props (nullable)
+ * receives the number of table propagations, n_rounds (nullable) the rounds.
+ * Returns CT_OK or CT_FAIL.  After CT_FAIL the failed tables must be popped
+ * (ct_model_pop) before the next fixpoint.
+ */
+int ct_model_fixpoint(ct_model *m, const uint64_t *pool_in, uint64_t *pool_out, void *stream,
+                      int64_t *n_props, int64_t *n_rounds);
+
+/* Push / pop one level on slot 0 of every table of the model (one launch). */
+int ct_model_push(ct_model *m);
+int ct_model_pop(ct_model *m);
+
+/* Scheduling knob of the model's rounds: tables of at most solo_max_granules
+ * granules run in one workgroup each, larger ones are split over workgroups
+ * (see CT_SCHED_*); rounds_per_graph rounds are captured per graph.  The
+ * default is chosen by ct_model_autotune or is (4, 8). */
+int ct_model_set_schedule(ct_model *m, int32_t solo_max_granules, int32_t rounds_per_graph);
+
+/* Autotuner: times one fixpoint from pool_in for each candidate threshold
+ * (1, 4, 16, 64, 256 granules), restoring every table between trials with a
+ * push / pop, keeps the fastest and returns it in *best (nullable). */
+int ct_model_autotune(ct_model *m, const uint64_t *pool_in, int32_t *best);
+
 /* Synchronizes `stream` and reports whether a batch launched on it hit a
  * device-side error (a bounded wait that expired): CT_OK or CT_E_DEVICE (the
  * error is cleared; the slots of the affected jobs are undefined). */

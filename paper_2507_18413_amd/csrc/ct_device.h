@@ -124,6 +124,30 @@ struct DevJob {
   int32_t nUpd, nFilt;     // item counts of this job
   int32_t depthAfter;      // slot depth once the pops and pushes are applied
   int32_t pad;
+  const CT_G int32_t* active;  // nullable: the job is skipped when *active == 0
+};
+
+// Multi-table model: pool variables shared by tables (device side of a
+// propagation round).  Scope entry e links column tabCol[e] of table
+// scopeTab[e] to pool variable scopeVar[e].
+struct ModelDesc {
+  int32_t nTables, nPool, poolWords, nEntries;
+  const CT_G int32_t* poolOff;    // nPool: first pool word of each variable
+  const CT_G int32_t* poolNW;     // nPool: words of each variable
+  const CT_G int32_t* scopeTab;   // nEntries
+  const CT_G int32_t* scopeVar;   // nEntries
+  const CT_G int32_t* entDomOff;  // nEntries: word offset of the column in its table's bitmap
+  const CT_G int32_t* tabScope;   // nTables + 1: entries of table c are [tabScope[c], tabScope[c+1])
+  const CT_G int32_t* bufOff;     // nTables: offset of table c's words in domIn / domOut
+  const CT_G uint64_t* const CT_G* lastDom;  // nTables: slot-0 domains of each table
+  CT_G uint64_t* domIn;
+  CT_G uint64_t* domOut;
+  CT_G int32_t* status;           // nTables: job status of the round
+  CT_G int32_t* dirty;            // nTables: table runs in the round
+  CT_G uint64_t* pool;            // poolWords
+  CT_G uint64_t* poolNext;        // poolWords
+  CT_G int32_t* changed;          // nPool
+  CT_G int32_t* flags;            // [0] some table dirty, [1] failed, [2] rounds, [3] table runs
 };
 
 // Kernel argument block of the persistent propagate kernel.

@@ -816,12 +816,15 @@ __global__ void __launch_bounds__(BLOCK) propagate_kernel(KArgs a) {
   while (item < total) {
     if (item < a.nPrep) {
       const int j = a.jobs ? a.prepList[item] : 0;
-      do_prep(a, job_of(a, j), sh);
+      const DevJob J = job_of(a, j);
+      if (!J.active || *J.active) do_prep(a, J, sh);
     } else if (item < a.nPrep + a.nUpd) {
       const int x = item - a.nPrep;
       const int j = a.jobs ? find_job(a.updOff, a.nJobs, x) : 0;
       const DevJob J = job_of(a, j);
-      if (J.flags & JF_SOLO) {
+      if (J.active && !*J.active) {
+        // a clean job of a model round: nothing to do
+      } else if (J.flags & JF_SOLO) {
         do_solo(a, J, sh);
       } else {
         const int c = a.jobs ? x - a.updOff[j] : x;
@@ -831,7 +834,8 @@ __global__ void __launch_bounds__(BLOCK) propagate_kernel(KArgs a) {
       const int x = item - a.nPrep - a.nUpd;
       const int j = a.jobs ? find_job(a.filtOff, a.nJobs, x) : 0;
       const int c = a.jobs ? x - a.filtOff[j] : x;
-      do_filter(a, job_of(a, j), c, sh);
+      const DevJob J = job_of(a, j);
+      if (!J.active || *J.active) do_filter(a, J, c, sh);
     }
     if (!dynamic) break;
     __syncthreads();
@@ -924,6 +928,82 @@ __global__ void __launch_bounds__(BLOCK) init_slots_kernel(const TabDesc* T, Slo
   }
 }
 
+// ---------------------------------------------------------------------------
+// Propagation rounds of a multi-table model.  One round = gather -> propagate
+// (every dirty table, one persistent launch) -> merge -> changed -> mark.
+// All state lives on the device, so rounds can be captured in a graph; once
+// nothing is dirty (or a table failed) the remaining rounds do no work.
+// ---------------------------------------------------------------------------
+// input of every dirty table: pool restricted to its scope, intersected with
+// the domains the table returned last; poolNext starts as a copy of pool
+__global__ void __launch_bounds__(BLOCK) model_gather_kernel(ModelDesc M) {
+  const int stride = gridDim.x * BLOCK;
+  for (int w = blockIdx.x * BLOCK + threadIdx.x; w < M.poolWords; w += stride) M.poolNext[w] = M.pool[w];
+  if (M.flags[1]) return;
+  for (int e = blockIdx.x * BLOCK + threadIdx.x; e < M.nEntries; e += stride) {
+    const int c = M.scopeTab[e];
+    if (!M.dirty[c]) continue;
+    const int v = M.scopeVar[e];
+    const int po = M.poolOff[v], nw = M.poolNW[v];
+    const int to = M.entDomOff[e];
+    const CT_G uint64_t* last = M.lastDom[c];
+    CT_G uint64_t* din = M.domIn + M.bufOff[c];
+    for (int q = 0; q < nw; ++q) din[to + q] = M.pool[po + q] & last[to + q];
+  }
+}
+
+// AND every successful table's output into poolNext; a failure stops the model
+__global__ void __launch_bounds__(BLOCK) model_merge_kernel(ModelDesc M) {
+  const int stride = gridDim.x * BLOCK;
+  for (int e = blockIdx.x * BLOCK + threadIdx.x; e < M.nEntries; e += stride) {
+    const int c = M.scopeTab[e];
+    if (!M.dirty[c]) continue;
+    const int st = M.status[c];
+    if (st != ST_OK) {
+      if (e == M.tabScope[c]) atomicExch(&M.flags[1], st == ST_FAIL ? 1 : 2);
+      continue;
+    }
+    const int v = M.scopeVar[e];
+    const int po = M.poolOff[v], nw = M.poolNW[v];
+    const CT_G uint64_t* dout = M.domOut + M.bufOff[c] + M.entDomOff[e];
+    for (int q = 0; q < nw; ++q) atomicAnd((unsigned long long*)&M.poolNext[po + q], (unsigned long long)dout[q]);
+  }
+}
+
+// variables whose pool domain shrank in this round; pool <- poolNext
+__global__ void __launch_bounds__(BLOCK) model_changed_kernel(ModelDesc M) {
+  const int stride = gridDim.x * BLOCK;
+  if (blockIdx.x == 0 && threadIdx.x == 0) M.flags[0] = 0;
+  for (int v = blockIdx.x * BLOCK + threadIdx.x; v < M.nPool; v += stride) {
+    const int po = M.poolOff[v], nw = M.poolNW[v];
+    int ch = 0;
+    for (int q = 0; q < nw; ++q) {
+      const uint64_t nx = M.poolNext[po + q];
+      if (nx != M.pool[po + q]) ch = 1;
+      M.pool[po + q] = nx;
+    }
+    M.changed[v] = ch;
+  }
+}
+
+// a table is dirty in the next round iff a variable of its scope changed
+__global__ void __launch_bounds__(BLOCK) model_mark_kernel(ModelDesc M) {
+  const int stride = gridDim.x * BLOCK;
+  const bool failed = M.flags[1] != 0;
+  int any = 0, cnt = 0;
+  for (int c = blockIdx.x * BLOCK + threadIdx.x; c < M.nTables; c += stride) {
+    int d = 0;
+    if (!failed)
+      for (int e = M.tabScope[c]; e < M.tabScope[c + 1]; ++e) d |= M.changed[M.scopeVar[e]];
+    M.dirty[c] = d;
+    any |= d;
+    cnt += d;
+  }
+  if (any) atomicOr(&M.flags[0], 1);
+  if (cnt) atomicAdd(&M.flags[3], cnt);
+  if (blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(&M.flags[2], 1);
+}
+
 }  // namespace ctk
 
 // ---------------------------------------------------------------------------
@@ -962,6 +1042,16 @@ hipError_t launch_build_supports(const int32_t* tuples, int64_t t, int n, const 
   const int64_t blocks = (W + WAVES - 1) / WAVES;
   hipLaunchKernelGGL(build_supports_kernel, dim3((unsigned)blocks), dim3(BLOCK), 0, stream, tuples,
                      t, n, vars, lo, S, stride, W);
+  return hipGetLastError();
+}
+
+hipError_t launch_model_round(const ModelDesc& M, const KArgs& a, int grid, hipStream_t stream) {
+  const int gb = 256;
+  hipLaunchKernelGGL(model_gather_kernel, dim3(gb), dim3(BLOCK), 0, stream, M);
+  hipLaunchKernelGGL(propagate_kernel, dim3(grid), dim3(BLOCK), 0, stream, a);
+  hipLaunchKernelGGL(model_merge_kernel, dim3(gb), dim3(BLOCK), 0, stream, M);
+  hipLaunchKernelGGL(model_changed_kernel, dim3(gb), dim3(BLOCK), 0, stream, M);
+  hipLaunchKernelGGL(model_mark_kernel, dim3(gb), dim3(BLOCK), 0, stream, M);
   return hipGetLastError();
 }
 

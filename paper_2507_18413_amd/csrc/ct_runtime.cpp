@@ -910,3 +910,417 @@ int ct_propagate_batch(const ct_job* jobs, int32_t n_jobs, void* stream_v, int32
 }
 
 }  // extern "C"
+
+// ===========================================================================
+// Multi-table model: propagation rounds captured in a hipGraph
+// ===========================================================================
+namespace ctk {
+hipError_t launch_model_round(const ModelDesc& M, const KArgs& a, int grid, hipStream_t stream);
+}
+
+struct ct_model {
+  int nPool = 0, poolWords = 0;
+  std::vector<int32_t> lo, dsz, poolOff, poolNW;
+  std::vector<ct_table*> tabs;
+  std::vector<std::vector<int32_t>> scopes;
+  hipStream_t stream = nullptr;
+  QueueCtx q;
+  int soloMax = 4, roundsPerGraph = 8;
+  // device state, rebuilt when the table set or the schedule changes
+  bool built = false;
+  std::vector<void*> blocks;
+  ModelDesc M{};
+  DevJob* dJobs = nullptr;
+  int32_t* dOff = nullptr;
+  std::vector<DevJob> hJobs;
+  KArgs a{};
+  int grid = 1;
+  hipGraphExec_t exec = nullptr;
+  int32_t* pFlags = nullptr;   // pinned copy of M.flags
+  int32_t* dStatus = nullptr;  // statuses of push/pop batches
+};
+
+namespace {
+
+int model_alloc(ct_model* m, void** p, size_t bytes) {
+  hipError_t e = hipMalloc(p, bytes ? bytes : 8);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(CT_E_NOMEM, "hipMalloc(%zu) failed: %s", bytes, hipGetErrorString(e));
+  }
+  m->blocks.push_back(*p);
+  return CT_OK;
+}
+
+void model_free_device(ct_model* m) {
+  if (m->stream) (void)hipStreamSynchronize(m->stream);
+  if (m->exec) (void)hipGraphExecDestroy(m->exec);
+  m->exec = nullptr;
+  for (void* p : m->blocks) (void)hipFree(p);
+  m->blocks.clear();
+  m->built = false;
+}
+
+template <class T>
+int model_upload(ct_model* m, T** dst, const std::vector<T>& src) {
+  int rc = model_alloc(m, (void**)dst, sizeof(T) * std::max<size_t>(src.size(), 1));
+  if (rc) return rc;
+  if (!src.empty()) HIPCHK(hipMemcpy(*dst, src.data(), sizeof(T) * src.size(), hipMemcpyHostToDevice));
+  return CT_OK;
+}
+
+// Device arrays, one propagate job per table, and the graph of K rounds.
+int model_build(ct_model* m) {
+  model_free_device(m);
+  const int nT = (int)m->tabs.size();
+  std::vector<int32_t> scopeTab, scopeVar, entDomOff, tabScope(nT + 1, 0), bufOff(nT, 0);
+  std::vector<const uint64_t*> lastDom(nT);
+  int64_t words = 0;
+  for (int c = 0; c < nT; ++c) {
+    ct_table* T = m->tabs[c];
+    for (int k = 0; k < T->n; ++k) {
+      scopeTab.push_back(c);
+      scopeVar.push_back(m->scopes[c][k]);
+      entDomOff.push_back(T->domOff[k]);
+    }
+    tabScope[c + 1] = (int32_t)scopeTab.size();
+    bufOff[c] = (int32_t)words;
+    words += T->D;
+    SlotDesc sd{};
+    HIPCHK(hipMemcpy(&sd, T->slots[0].dev, sizeof(SlotDesc), hipMemcpyDeviceToHost));
+    lastDom[c] = (const uint64_t*)sd.lastDom;
+  }
+  ModelDesc& M = m->M;
+  M = ModelDesc{};
+  M.nTables = nT;
+  M.nPool = m->nPool;
+  M.poolWords = m->poolWords;
+  M.nEntries = (int32_t)scopeTab.size();
+  int rc;
+  int32_t* p32 = nullptr;
+  if ((rc = model_upload(m, &p32, m->poolOff))) return rc;
+  M.poolOff = p32;
+  if ((rc = model_upload(m, &p32, m->poolNW))) return rc;
+  M.poolNW = p32;
+  if ((rc = model_upload(m, &p32, scopeTab))) return rc;
+  M.scopeTab = p32;
+  if ((rc = model_upload(m, &p32, scopeVar))) return rc;
+  M.scopeVar = p32;
+  if ((rc = model_upload(m, &p32, entDomOff))) return rc;
+  M.entDomOff = p32;
+  if ((rc = model_upload(m, &p32, tabScope))) return rc;
+  M.tabScope = p32;
+  if ((rc = model_upload(m, &p32, bufOff))) return rc;
+  M.bufOff = p32;
+  const uint64_t** pld = nullptr;
+  if ((rc = model_upload(m, &pld, lastDom))) return rc;
+  M.lastDom = pld;
+  uint64_t* p64 = nullptr;
+  if ((rc = model_alloc(m, (void**)&p64, sizeof(uint64_t) * std::max<int64_t>(words, 1)))) return rc;
+  M.domIn = p64;
+  if ((rc = model_alloc(m, (void**)&p64, sizeof(uint64_t) * std::max<int64_t>(words, 1)))) return rc;
+  M.domOut = p64;
+  if ((rc = model_alloc(m, (void**)&p64, sizeof(uint64_t) * m->poolWords))) return rc;
+  M.pool = p64;
+  if ((rc = model_alloc(m, (void**)&p64, sizeof(uint64_t) * m->poolWords))) return rc;
+  M.poolNext = p64;
+  if ((rc = model_alloc(m, (void**)&p32, sizeof(int32_t) * std::max(nT, 1)))) return rc;
+  M.status = p32;
+  if ((rc = model_alloc(m, (void**)&p32, sizeof(int32_t) * std::max(nT, 1)))) return rc;
+  M.dirty = p32;
+  if ((rc = model_alloc(m, (void**)&p32, sizeof(int32_t) * std::max(m->nPool, 1)))) return rc;
+  M.changed = p32;
+  if ((rc = model_alloc(m, (void**)&p32, sizeof(int32_t) * 8))) return rc;
+  M.flags = p32;
+  if ((rc = model_alloc(m, (void**)&m->dStatus, sizeof(int32_t) * std::max(nT, 1)))) return rc;
+  // jobs: table c propagates slot 0 from domIn to domOut when dirty[c]
+  m->hJobs.assign(nT, DevJob{});
+  std::vector<int32_t> off(2 * (nT + 1) + 1, 0);
+  for (int c = 0; c < nT; ++c) {
+    ct_table* T = m->tabs[c];
+    DevJob& J = m->hJobs[c];
+    J.tab = T->dTab;
+    J.slot = T->slots[0].dev;
+    J.dom_in = M.domIn + bufOff[c];
+    J.dom_out = M.domOut + bufOff[c];
+    J.status_out = M.status + c;
+    J.flags = JF_PROPAGATE | (T->nGran <= m->soloMax ? JF_SOLO : 0u);
+    J.depthAfter = T->slots[0].depth;
+    J.active = M.dirty + c;
+    job_counts(T, J);
+    off[c + 1] = off[c] + J.nUpd;
+    off[(nT + 1) + c + 1] = off[(nT + 1) + c] + J.nFilt;
+  }
+  if ((rc = model_upload(m, &m->dJobs, m->hJobs))) return rc;
+  if ((rc = model_upload(m, &m->dOff, off))) return rc;
+  KArgs& a = m->a;
+  a = KArgs{};
+  a.jobs = m->dJobs;
+  a.updOff = m->dOff;
+  a.filtOff = m->dOff + (nT + 1);
+  a.prepList = m->dOff + 2 * (nT + 1);
+  a.nJobs = nT;
+  a.nPrep = 0;
+  a.nUpd = off[nT];
+  a.nFilt = off[(nT + 1) + nT];
+  a.queue = m->q.queue;
+  a.hostErr = m->q.hostErr;
+  const int total = a.nUpd + a.nFilt;
+  m->grid = std::max(1, std::min(total, propagate_max_grid()));
+  // capture rounds_per_graph rounds
+  hipGraph_t g = nullptr;
+  HIPCHK(hipStreamBeginCapture(m->stream, hipStreamCaptureModeThreadLocal));
+  for (int r = 0; r < m->roundsPerGraph; ++r) {
+    hipError_t e = launch_model_round(M, a, m->grid, m->stream);
+    if (e != hipSuccess) {
+      hipGraph_t dummy = nullptr;
+      (void)hipStreamEndCapture(m->stream, &dummy);
+      if (dummy) (void)hipGraphDestroy(dummy);
+      return fail(CT_E_DEVICE, "model round capture failed: %s", hipGetErrorString(e));
+    }
+  }
+  HIPCHK(hipStreamEndCapture(m->stream, &g));
+  hipError_t e = hipGraphInstantiate(&m->exec, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (e != hipSuccess) return fail(CT_E_DEVICE, "hipGraphInstantiate failed: %s", hipGetErrorString(e));
+  m->built = true;
+  return CT_OK;
+}
+
+// Bring every table's slot 0 up to date (pending pushes/pops) and refresh the
+// depth each job trails at.
+int model_sync_tables(ct_model* m) {
+  bool changed = false;
+  for (size_t c = 0; c < m->tabs.size(); ++c) {
+    ct_table* T = m->tabs[c];
+    int rc = check_poison(T);
+    if (rc) return rc;
+    if ((rc = flush_slot(T, 0))) return rc;
+    HIPCHK(hipStreamSynchronize(T->stream));
+    if (m->built && m->hJobs[c].depthAfter != T->slots[0].depth) {
+      m->hJobs[c].depthAfter = T->slots[0].depth;
+      changed = true;
+    }
+  }
+  if (changed)
+    HIPCHK(hipMemcpy(m->dJobs, m->hJobs.data(), sizeof(DevJob) * m->hJobs.size(), hipMemcpyHostToDevice));
+  return CT_OK;
+}
+
+int model_push_pop(ct_model* m, bool push) {
+  const int nT = (int)m->tabs.size();
+  if (nT == 0) return CT_OK;
+  if (!m->dStatus) {
+    int rc = model_alloc(m, (void**)&m->dStatus, sizeof(int32_t) * nT);
+    if (rc) return rc;
+  }
+  std::vector<ct_job> jobs(nT);
+  for (int c = 0; c < nT; ++c) {
+    jobs[c] = ct_job{};
+    jobs[c].table = m->tabs[c];
+    jobs[c].slot = 0;
+    jobs[c].flags = 0;
+    jobs[c].n_pop = push ? 0 : 1;
+    jobs[c].n_push = push ? 1 : 0;
+  }
+  int rc = ct_propagate_batch(jobs.data(), nT, m->stream, m->dStatus);
+  if (rc) return rc;
+  HIPCHK(hipStreamSynchronize(m->stream));
+  return ct_batch_status(m->stream);
+}
+
+}  // namespace
+
+extern "C" {
+
+int ct_model_create(int32_t n_vars, const int32_t* dom_lo, const int32_t* dom_size, ct_model** out) {
+  if (!out) return fail(CT_E_INVALID, "out is NULL");
+  *out = nullptr;
+  if (n_vars < 1 || !dom_lo || !dom_size) return fail(CT_E_INVALID, "bad model arguments");
+  ct_model* m = new (std::nothrow) ct_model();
+  if (!m) return fail(CT_E_NOMEM, "host allocation failed");
+  m->nPool = n_vars;
+  int w = 0;
+  for (int i = 0; i < n_vars; ++i) {
+    if (dom_size[i] < 1) {
+      delete m;
+      return fail(CT_E_INVALID, "dom_size[%d] < 1", i);
+    }
+    m->lo.push_back(dom_lo[i]);
+    m->dsz.push_back(dom_size[i]);
+    m->poolOff.push_back(w);
+    m->poolNW.push_back((dom_size[i] + 63) / 64);
+    w += (dom_size[i] + 63) / 64;
+  }
+  m->poolWords = w;
+  hipError_t e = hipStreamCreateWithFlags(&m->stream, hipStreamNonBlocking);
+  if (e != hipSuccess) {
+    delete m;
+    return fail(CT_E_DEVICE, "hipStreamCreate failed: %s", hipGetErrorString(e));
+  }
+  int rc = queue_init(m->q);
+  if (rc == CT_OK) {
+    e = hipHostMalloc((void**)&m->pFlags, sizeof(int32_t) * 8, hipHostMallocDefault);
+    if (e != hipSuccess) rc = fail(CT_E_NOMEM, "pinned allocation failed");
+  }
+  if (rc) {
+    ct_model_destroy(m);
+    return rc;
+  }
+  *out = m;
+  return CT_OK;
+}
+
+void ct_model_destroy(ct_model* m) {
+  if (!m) return;
+  model_free_device(m);
+  queue_free(m->q);
+  if (m->pFlags) (void)hipHostFree(m->pFlags);
+  if (m->stream) (void)hipStreamDestroy(m->stream);
+  delete m;
+}
+
+int ct_model_add(ct_model* m, ct_table* T, const int32_t* scope, int32_t* index) {
+  if (!m || !scope) return fail(CT_E_INVALID, "bad arguments");
+  int rc = check_poison(T);
+  if (rc) return rc;
+  std::vector<int32_t> sc(scope, scope + T->n);
+  std::set<int32_t> seen;
+  for (int k = 0; k < T->n; ++k) {
+    const int v = sc[k];
+    if (v < 0 || v >= m->nPool) return fail(CT_E_INVALID, "scope[%d] = %d out of range", k, v);
+    if (!seen.insert(v).second) return fail(CT_E_INVALID, "variable %d twice in a scope", v);
+    if (m->lo[v] != T->lo[k] || m->dsz[v] != T->dsz[k])
+      return fail(CT_E_INVALID, "column %d does not match pool variable %d", k, v);
+  }
+  for (ct_table* u : m->tabs)
+    if (u == T) return fail(CT_E_INVALID, "table already in the model");
+  if (index) *index = (int32_t)m->tabs.size();
+  m->tabs.push_back(T);
+  m->scopes.push_back(sc);
+  model_free_device(m);
+  return CT_OK;
+}
+
+int ct_model_layout(const ct_model* m, int32_t* pool_off, int32_t* pool_words) {
+  if (!m) return fail(CT_E_INVALID, "null model");
+  if (pool_off) memcpy(pool_off, m->poolOff.data(), sizeof(int32_t) * m->nPool);
+  if (pool_words) *pool_words = m->poolWords;
+  return CT_OK;
+}
+
+int ct_model_set_schedule(ct_model* m, int32_t solo_max_granules, int32_t rounds_per_graph) {
+  if (!m || solo_max_granules < 0 || rounds_per_graph < 1 || rounds_per_graph > 256)
+    return fail(CT_E_INVALID, "bad schedule");
+  if (solo_max_granules != m->soloMax || rounds_per_graph != m->roundsPerGraph) {
+    m->soloMax = solo_max_granules;
+    m->roundsPerGraph = rounds_per_graph;
+    model_free_device(m);
+  }
+  return CT_OK;
+}
+
+int ct_model_fixpoint(ct_model* m, const uint64_t* pool_in, uint64_t* pool_out, void* stream_v,
+                      int64_t* n_props, int64_t* n_rounds) {
+  if (!m || !pool_in || !pool_out) return fail(CT_E_INVALID, "bad arguments");
+  hipStream_t user = (hipStream_t)stream_v;
+  if (user) HIPCHK(hipStreamSynchronize(user));
+  int rc = model_sync_tables(m);
+  if (rc) return rc;
+  if (!m->built && (rc = model_build(m))) return rc;
+  const int nT = (int)m->tabs.size();
+  ModelDesc& M = m->M;
+  HIPCHK(hipMemcpyAsync(M.pool, pool_in, sizeof(uint64_t) * m->poolWords, hipMemcpyDeviceToDevice, m->stream));
+  {
+    std::vector<int32_t> ones(std::max(nT, 1), 1);
+    int32_t fl[8] = {nT > 0 ? 1 : 0, 0, 0, nT, 0, 0, 0, 0};
+    HIPCHK(hipMemcpyAsync(M.dirty, ones.data(), sizeof(int32_t) * nT, hipMemcpyHostToDevice, m->stream));
+    HIPCHK(hipMemcpyAsync(M.flags, fl, sizeof(fl), hipMemcpyHostToDevice, m->stream));
+    HIPCHK(hipStreamSynchronize(m->stream));
+  }
+  for (int replays = 0;; ++replays) {
+    if (replays > 100000) return fail(CT_E_DEVICE, "fixpoint did not converge");
+    HIPCHK(hipGraphLaunch(m->exec, m->stream));
+    HIPCHK(hipMemcpyAsync(m->pFlags, M.flags, sizeof(int32_t) * 8, hipMemcpyDeviceToHost, m->stream));
+    hipError_t e = hipStreamSynchronize(m->stream);
+    if (e != hipSuccess) {
+      for (ct_table* T : m->tabs) T->poisoned = true;
+      return fail(CT_E_DEVICE, "model round failed: %s", hipGetErrorString(e));
+    }
+    if (*(volatile int32_t*)m->q.hostErr) {
+      for (ct_table* T : m->tabs) T->poisoned = true;
+      return fail(CT_E_DEVICE, "device-side error %d in a model round", *m->q.hostErr);
+    }
+    if (m->pFlags[1] || !m->pFlags[0]) break;
+  }
+  for (ct_table* T : m->tabs) T->slots[0].failed = 2;
+  if (n_props) *n_props = m->pFlags[3];
+  if (n_rounds) *n_rounds = m->pFlags[2];
+  if (m->pFlags[1] == 2)
+    return fail(CT_E_STATE, "a table of the model is in the failed state (pop it first)");
+  if (m->pFlags[1]) return CT_FAIL;
+  HIPCHK(hipMemcpyAsync(pool_out, M.pool, sizeof(uint64_t) * m->poolWords, hipMemcpyDeviceToDevice, m->stream));
+  HIPCHK(hipStreamSynchronize(m->stream));
+  return CT_OK;
+}
+
+int ct_model_push(ct_model* m) {
+  if (!m) return fail(CT_E_INVALID, "null model");
+  return model_push_pop(m, true);
+}
+
+int ct_model_pop(ct_model* m) {
+  if (!m) return fail(CT_E_INVALID, "null model");
+  for (ct_table* T : m->tabs)
+    if (T->slots[0].depth == 0) return fail(CT_E_STATE, "pop at depth 0");
+  return model_push_pop(m, false);
+}
+
+int ct_model_autotune(ct_model* m, const uint64_t* pool_in, int32_t* best) {
+  if (!m || !pool_in) return fail(CT_E_INVALID, "bad arguments");
+  static const int cands[] = {1, 4, 16, 64, 256};
+  uint64_t* scratch = nullptr;
+  HIPCHK(hipMalloc(&scratch, sizeof(uint64_t) * m->poolWords));
+  std::vector<uint64_t> ref(m->poolWords), got(m->poolWords);
+  double bestT = 1e30;
+  int bestC = m->soloMax, refSt = -100;
+  int rc = CT_OK;
+  for (int ci = 0; ci < 5 && rc == CT_OK; ++ci) {
+    if ((rc = ct_model_set_schedule(m, cands[ci], m->roundsPerGraph))) break;
+    if ((rc = ct_model_push(m))) break;
+    if ((rc = model_sync_tables(m))) break;
+    if (!m->built && (rc = model_build(m))) break;
+    const auto t0 = std::chrono::steady_clock::now();
+    const int st = ct_model_fixpoint(m, pool_in, scratch, nullptr, nullptr, nullptr);
+    const double el = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    if (st != CT_OK && st != CT_FAIL) {
+      rc = st;
+      break;
+    }
+    if (st == CT_OK) {
+      hipError_t e = hipMemcpy(got.data(), scratch, sizeof(uint64_t) * m->poolWords, hipMemcpyDeviceToHost);
+      if (e != hipSuccess) {
+        rc = fail(CT_E_DEVICE, "copy failed");
+        break;
+      }
+    }
+    if (refSt == -100) {
+      refSt = st;
+      ref = got;
+    } else if (st != refSt || (st == CT_OK && got != ref)) {
+      rc = fail(CT_E_DEVICE, "schedules disagree on the fixpoint");
+      break;
+    }
+    if ((rc = ct_model_pop(m))) break;
+    if (el < bestT) {
+      bestT = el;
+      bestC = cands[ci];
+    }
+  }
+  (void)hipFree(scratch);
+  if (rc) return rc;
+  if (best) *best = bestC;
+  return ct_model_set_schedule(m, bestC, m->roundsPerGraph);
+}
+
+}  // extern "C"

@@ -104,6 +104,15 @@ def lib():
             "ct_batch_status": ([P], C.c_int),
             "ct_set_timing": ([P, I32], C.c_int),
             "ct_get_timing": ([P, C.POINTER(C.c_double), C.POINTER(I64)], C.c_int),
+            "ct_model_create": ([I32, P, P, C.POINTER(P)], C.c_int),
+            "ct_model_destroy": ([P], None),
+            "ct_model_add": ([P, P, P, C.POINTER(I32)], C.c_int),
+            "ct_model_layout": ([P, P, C.POINTER(I32)], C.c_int),
+            "ct_model_fixpoint": ([P, P, P, P, C.POINTER(I64), C.POINTER(I64)], C.c_int),
+            "ct_model_push": ([P], C.c_int),
+            "ct_model_pop": ([P], C.c_int),
+            "ct_model_set_schedule": ([P, I32, I32], C.c_int),
+            "ct_model_autotune": ([P, P, C.POINTER(I32)], C.c_int),
             "ct_last_error": ([], C.c_char_p),
         }
         for name, (args, res) in sig.items():
@@ -271,3 +280,76 @@ def propagate_batch(jobs, status_dev, stream=None):
     if st < 0:
         raise CTError(st, last_error())
     return st
+
+
+class Model:
+    """Tables sharing a pool of variables; fixpoint propagation on the GPU."""
+
+    def __init__(self, lo, dsizes):
+        L = lib()
+        lo = np.ascontiguousarray(lo, dtype=np.int32)
+        ds = np.ascontiguousarray(dsizes, dtype=np.int32)
+        h = C.c_void_p()
+        st = L.ct_model_create(int(ds.shape[0]), _p(lo), _p(ds), C.byref(h))
+        if st < 0:
+            raise CTError(st, last_error())
+        self.h = h
+        self.n = int(ds.shape[0])
+        self.tables = []
+        off = np.zeros(self.n, np.int32)
+        w = C.c_int32()
+        L.ct_model_layout(h, _p(off), C.byref(w))
+        self.pool_off, self.pool_words = off, w.value
+
+    def close(self):
+        if getattr(self, "h", None) is not None and self.h.value is not None:
+            lib().ct_model_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def add(self, table, scope):
+        scope = np.ascontiguousarray(scope, dtype=np.int32)
+        idx = C.c_int32()
+        st = lib().ct_model_add(self.h, table.h, _p(scope), C.byref(idx))
+        if st < 0:
+            raise CTError(st, last_error())
+        self.tables.append(table)
+        return idx.value
+
+    def fixpoint(self, pool_in, pool_out, stream=None):
+        """pool_in / pool_out: device tensors of pool_words int64 (bit patterns).
+        Returns (status, propagations, rounds)."""
+        s = None if stream is None else (stream if isinstance(stream, int) else stream.cuda_stream)
+        props, rounds = C.c_int64(), C.c_int64()
+        st = lib().ct_model_fixpoint(self.h, _ptr(pool_in), _ptr(pool_out), s, C.byref(props),
+                                     C.byref(rounds))
+        if st < 0:
+            raise CTError(st, last_error())
+        return st, props.value, rounds.value
+
+    def push(self):
+        st = lib().ct_model_push(self.h)
+        if st < 0:
+            raise CTError(st, last_error())
+
+    def pop(self):
+        st = lib().ct_model_pop(self.h)
+        if st < 0:
+            raise CTError(st, last_error())
+
+    def set_schedule(self, solo_max_granules, rounds_per_graph=8):
+        st = lib().ct_model_set_schedule(self.h, int(solo_max_granules), int(rounds_per_graph))
+        if st < 0:
+            raise CTError(st, last_error())
+
+    def autotune(self, pool_in):
+        best = C.c_int32()
+        st = lib().ct_model_autotune(self.h, _ptr(pool_in), C.byref(best))
+        if st < 0:
+            raise CTError(st, last_error())
+        return best.value
