@@ -958,6 +958,10 @@ void model_free_device(ct_model* m) {
   m->exec = nullptr;
   for (void* p : m->blocks) (void)hipFree(p);
   m->blocks.clear();
+  m->dStatus = nullptr;
+  m->dJobs = nullptr;
+  m->dOff = nullptr;
+  m->M = ModelDesc{};
   m->built = false;
 }
 

@@ -239,12 +239,16 @@ class ModelSpec:
 
 
 def config3_model(seed: int = DEFAULT_SEED, n_pool: int = 5000, n_tables: int = 2000,
-                  arity=(2, 8), dom=(4, 64), tuples=(100, 500_000)) -> ModelSpec:
+                  arity=(2, 8), dom=(4, 64), tuples=(100, 500_000), plant: bool = True) -> ModelSpec:
     """Pool of variables with d ~ U{dom}, tables of arity ~ U{arity} over distinct
     pool variables, tuple counts log-uniform in ``tuples`` capped at half the
-    domain product, distinct uniform tuples."""
+    domain product, distinct uniform tuples.  With ``plant`` a hidden
+    assignment of every pool variable is drawn and each table holds its
+    projection (replacing the first tuple when absent), so the model has a
+    solution and the root fixpoint never fails."""
     rng = rng_for(seed, 3, 0)
     pool = rng.integers(dom[0], dom[1] + 1, size=n_pool).astype(np.int32)
+    hidden = (rng.random(n_pool) * pool).astype(np.int64)
     tables, scopes = [], []
     for c in range(n_tables):
         n = int(rng.integers(arity[0], arity[1] + 1))
@@ -255,6 +259,10 @@ def config3_model(seed: int = DEFAULT_SEED, n_pool: int = 5000, n_tables: int = 
         t = max(1, min(t, space // 2))
         trng = rng_for(seed, 3, 1 + c)
         tup = distinct_uniform_tuples(trng, ds, t)
+        if plant:
+            sol = hidden[scope].astype(np.int32)
+            if not (tup == sol).all(axis=1).any():
+                tup[0] = sol
         tables.append(TableSpec(tup, np.zeros(n, np.int32), ds.astype(np.int32)))
         scopes.append(scope)
     return ModelSpec(pool, tables, scopes)
