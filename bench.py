@@ -39,6 +39,8 @@ def parse():
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--nodes", type=int, default=4096)
     p.add_argument("--no-nodes", action="store_true")
+    p.add_argument("--model-steps", type=int, default=100)
+    p.add_argument("--no-model", action="store_true")
     return p.parse_args()
 
 
@@ -166,6 +168,189 @@ def nodes_leg(seed, n_nodes, reps, warmup, schedule=0):
     }
 
 
+class PlainModel:
+    """AC-3 over the tables on the host, one synchronous GPU call per table
+    propagation (the one-constraint-per-launch baseline)."""
+
+    def __init__(self, tables, scopes, lay):
+        import numpy as np
+        self.t, self.sc, self.lay = tables, scopes, lay
+        self.last = [t.domains() for t in tables]
+        self.stack = []
+        self.nbr = {}
+        for c, sc in enumerate(scopes):
+            for v in sc:
+                self.nbr.setdefault(int(v), []).append(c)
+
+    def push(self):
+        for t in self.t:
+            t.push()
+        self.stack.append([x.copy() for x in self.last])
+
+    def pop(self):
+        for t in self.t:
+            t.pop()
+        self.last = self.stack.pop()
+
+    def fixpoint(self, pool):
+        import numpy as np
+        from collections import deque
+        lay = self.lay
+        pool = pool.copy()
+        q = deque(range(len(self.t)))
+        inq = [True] * len(self.t)
+        props = 0
+        while q:
+            c = q.popleft()
+            inq[c] = False
+            tb, sc, last = self.t[c], self.sc[c], self.last[c]
+            din = np.concatenate([pool[lay.off[v]: lay.off[v] + lay.words[v]] for v in sc]) & last
+            st, dout = tb.propagate(din)
+            props += 1
+            if st != 0:
+                return st, pool, props
+            self.last[c] = dout
+            o = 0
+            for v in sc:
+                nw = int(lay.words[v])
+                seg = dout[o: o + nw]
+                if (pool[lay.off[v]: lay.off[v] + nw] != seg).any():
+                    pool[lay.off[v]: lay.off[v] + nw] = seg
+                    for c2 in self.nbr[int(v)]:
+                        if c2 != c and not inq[c2]:
+                            q.append(c2)
+                            inq[c2] = True
+                o += nw
+        return 0, pool, props
+
+
+def model_leg(seed, steps, plain_steps, cpu):
+    """Batched CT across constraints: 2,000 tables over a pool of 5,000
+    variables, root fixpoint then `steps` search steps (push, remove 5 % of
+    the values of 1-3 pool variables, fixpoint; every 10 steps pop
+    U{1..depth}, one level after a failure)."""
+    import numpy as np
+    import torch
+    from paper_2507_18413_amd import ct
+    from paper_2507_18413_amd import workloads as W
+    t0 = time.perf_counter()
+    spec = W.config3_model(seed)
+    lay = spec.pool_layout()
+    gen_s = time.perf_counter() - t0
+    tabs = [ct.Table(tb.tuples, tb.lo, tb.dsizes) for tb in spec.tables]
+    M = ct.Model(np.zeros(lay.n, np.int32), spec.pool_dsizes)
+    for tb, sc in zip(tabs, spec.scopes):
+        M.add(tb, sc)
+    build_s = time.perf_counter() - t0 - gen_s
+    full = lay.full()
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a).view(np.int64)).cuda()
+    pin, pout = dev(full), dev(full)
+    # root fixpoint (phase 1): every table streams its supports once
+    M.push()
+    torch.cuda.synchronize()
+    r0 = time.perf_counter()
+    st, props, rounds = M.fixpoint(pin, pout)
+    root_s = time.perf_counter() - r0
+    M.pop()
+    best = M.autotune(pin)
+    r0 = time.perf_counter()
+    st, props, rounds = M.fixpoint(pin, pout)
+    root_tuned_s = time.perf_counter() - r0
+    root = pout.cpu().numpy().view(np.uint64).copy()
+    supports_bytes = sum(8 * int(tb.dsizes.sum()) * ((tb.t + 63) // 64) for tb in spec.tables)
+    # the search script, drawn from the batched results (untimed), then timed
+    rng = W.rng_for(seed, 3, 99)
+    bt = W.Backtracker(rng)
+    stack, pool, script = [], root.copy(), []
+    for k in range(steps):
+        new = W.pick_fraction_removal(rng, lay, pool)
+        M.push()
+        stack.append(pool)
+        out = dev(new)
+        st2, p2, r2 = M.fixpoint(dev(new), out)
+        script.append(("step", new))
+        pool = out.cpu().numpy().view(np.uint64).copy() if st2 == 0 else pool
+        for _ in range(bt.pops_after(st2 != 0, len(stack))):
+            M.pop()
+            pool = stack.pop()
+            script.append(("pop", None))
+    while stack:
+        M.pop()
+        stack.pop()
+        script.append(("pop", None))
+    ins = [dev(x) if k == "step" else None for k, x in script]
+    torch.cuda.synchronize()
+    b0 = time.perf_counter()
+    bprops = 0
+    for (kind, _), din in zip(script, ins):
+        if kind == "step":
+            M.push()
+            stt, p2, _ = M.fixpoint(din, pout)
+            bprops += p2
+        else:
+            M.pop()
+    torch.cuda.synchronize()
+    batched_s = time.perf_counter() - b0
+    out = {"tables": len(spec.tables), "pool_vars": lay.n, "tuples": int(sum(tb.t for tb in spec.tables)),
+           "support_bytes": supports_bytes, "generate_s": round(gen_s, 1), "build_s": round(build_s, 1),
+           "root_fixpoint_ms": round(root_s * 1e3, 3), "root_fixpoint_tuned_ms": round(root_tuned_s * 1e3, 3),
+           "autotuned_solo_max_granules": best, "root_props": props, "root_rounds": rounds,
+           "root_support_GBps": round(supports_bytes / root_tuned_s / 1e9, 1),
+           "steps": steps, "batched_props": bprops, "batched_step_props_per_s": round(bprops / batched_s, 1),
+           "batched_ms_per_step": round(batched_s / steps * 1e3, 3)}
+    # plain GPU baseline (one launch per table propagation) on the first steps
+    pm = PlainModel(tabs, spec.scopes, lay)
+    pm.push()
+    p0 = time.perf_counter()
+    _, _, rprops = pm.fixpoint(full)
+    out["plain_root_ms"] = round((time.perf_counter() - p0) * 1e3, 3)
+    pm.pop()
+    pcnt, pstep = 0, 0
+    p0 = time.perf_counter()
+    for kind, x in script:
+        if pstep >= plain_steps and kind == "step":
+            break
+        if kind == "step":
+            pm.push()
+            st3, _, pp = pm.fixpoint(x)
+            pcnt += pp
+            pstep += 1
+        else:
+            pm.pop()
+    plain_s = time.perf_counter() - p0
+    while pm.stack:
+        pm.pop()
+    out["plain_steps"] = pstep
+    out["plain_step_props_per_s"] = round(pcnt / plain_s, 1)
+    if cpu:
+        from oracle import oracle as O
+        ots = [O.OracleTable(tb.tuples, tb.lo, tb.dsizes) for tb in spec.tables]
+        c0 = time.perf_counter()
+        for o in ots:
+            o.push()
+        ost, opool, oprops = O.fixpoint(ots, spec.scopes, lay, full)
+        out["oracle_root_ms"] = round((time.perf_counter() - c0) * 1e3, 3)
+        out["root_matches_oracle"] = bool(ost == st and (ost != 0 or (opool == root).all()))
+        for o in ots:
+            o.pop()
+        ocnt, ostep = 0, 0
+        c0 = time.perf_counter()
+        for kind, x in script:
+            if kind == "step":
+                if ostep >= plain_steps:
+                    break
+                for o in ots:
+                    o.push()
+                _, _, pp = O.fixpoint(ots, spec.scopes, lay, x)
+                ocnt += pp
+                ostep += 1
+            else:
+                for o in ots:
+                    o.pop()
+        out["oracle_step_props_per_s"] = round(ocnt / (time.perf_counter() - c0), 1)
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -246,6 +431,8 @@ def main():
     }
     if not args.no_nodes:
         out["batched_nodes"] = nodes_leg(seed, args.nodes, max(1, args.steps), 1)
+    if not args.no_model:
+        out["batched_model"] = model_leg(seed, args.model_steps, 20, not args.no_cpu_baseline)
     if not args.no_cpu_baseline:
         cps, cprops, cel, passes = cpu_baseline(spec, script, args.cpu_seconds)
         out["cpu_baseline"] = {"value": round(cps, 1), "unit": "propagations/s", "cores": 1, "kind": "oracle",
