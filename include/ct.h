@@ -237,9 +237,10 @@ int ct_model_layout(const ct_model *m, int32_t *pool_off, int32_t *pool_words);
 /*
  * Runs propagation rounds from pool_in (device, pool words) until no domain
  * changes: every round propagates, in one persistent launch, each table one
- * of whose variables changed in the previous round (all tables in the first
- * round) on the pool intersected with its own last domains, and ANDs the
- * results into the pool.  Rounds are captured in a hipGraph, `rounds_per_graph`
+ * of whose variables changed in the previous round (in the first round: each
+ * table from whose last domains pool_in removes a value) on the pool
+ * intersected with its own last domains, and ANDs the results into the
+ * pool.  Rounds are captured in a hipGraph, `rounds_per_graph`
  * at a time, and replayed until the device reports convergence or failure.
  * Synchronous on `stream` (NULL = the model's own stream).  pool_out (device)
  * receives the fixpoint (undefined after CT_FAIL).  n_props (nullable)

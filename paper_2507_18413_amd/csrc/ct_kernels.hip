@@ -952,6 +952,28 @@ __global__ void __launch_bounds__(BLOCK) model_gather_kernel(ModelDesc M) {
   }
 }
 
+// first round: a table runs iff the input pool removes a value from the
+// domains it returned last (some variable of its scope changed)
+__global__ void __launch_bounds__(BLOCK) model_seed_kernel(ModelDesc M) {
+  const int stride = gridDim.x * BLOCK;
+  int any = 0, cnt = 0;
+  for (int c = blockIdx.x * BLOCK + threadIdx.x; c < M.nTables; c += stride) {
+    const CT_G uint64_t* last = M.lastDom[c];
+    int d = 0;
+    for (int e = M.tabScope[c]; e < M.tabScope[c + 1] && !d; ++e) {
+      const int v = M.scopeVar[e];
+      const int po = M.poolOff[v], nw = M.poolNW[v], to = M.entDomOff[e];
+      for (int q = 0; q < nw; ++q)
+        if (last[to + q] & ~M.pool[po + q]) d = 1;
+    }
+    M.dirty[c] = d;
+    any |= d;
+    cnt += d;
+  }
+  if (any) atomicOr(&M.flags[0], 1);
+  if (cnt) atomicAdd(&M.flags[3], cnt);
+}
+
 // AND every successful table's output into poolNext; a failure stops the model
 __global__ void __launch_bounds__(BLOCK) model_merge_kernel(ModelDesc M) {
   const int stride = gridDim.x * BLOCK;
@@ -1052,6 +1074,11 @@ hipError_t launch_model_round(const ModelDesc& M, const KArgs& a, int grid, hipS
   hipLaunchKernelGGL(model_merge_kernel, dim3(gb), dim3(BLOCK), 0, stream, M);
   hipLaunchKernelGGL(model_changed_kernel, dim3(gb), dim3(BLOCK), 0, stream, M);
   hipLaunchKernelGGL(model_mark_kernel, dim3(gb), dim3(BLOCK), 0, stream, M);
+  return hipGetLastError();
+}
+
+hipError_t launch_model_seed(const ModelDesc& M, hipStream_t stream) {
+  hipLaunchKernelGGL(model_seed_kernel, dim3(64), dim3(BLOCK), 0, stream, M);
   return hipGetLastError();
 }
 

@@ -916,6 +916,7 @@ int ct_propagate_batch(const ct_job* jobs, int32_t n_jobs, void* stream_v, int32
 // ===========================================================================
 namespace ctk {
 hipError_t launch_model_round(const ModelDesc& M, const KArgs& a, int grid, hipStream_t stream);
+hipError_t launch_model_seed(const ModelDesc& M, hipStream_t stream);
 }
 
 struct ct_model {
@@ -1236,10 +1237,9 @@ int ct_model_fixpoint(ct_model* m, const uint64_t* pool_in, uint64_t* pool_out, 
   ModelDesc& M = m->M;
   HIPCHK(hipMemcpyAsync(M.pool, pool_in, sizeof(uint64_t) * m->poolWords, hipMemcpyDeviceToDevice, m->stream));
   {
-    std::vector<int32_t> ones(std::max(nT, 1), 1);
-    int32_t fl[8] = {nT > 0 ? 1 : 0, 0, 0, nT, 0, 0, 0, 0};
-    HIPCHK(hipMemcpyAsync(M.dirty, ones.data(), sizeof(int32_t) * nT, hipMemcpyHostToDevice, m->stream));
+    int32_t fl[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     HIPCHK(hipMemcpyAsync(M.flags, fl, sizeof(fl), hipMemcpyHostToDevice, m->stream));
+    HIPCHK(launch_model_seed(M, m->stream));
     HIPCHK(hipStreamSynchronize(m->stream));
   }
   for (int replays = 0;; ++replays) {
