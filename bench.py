@@ -295,7 +295,6 @@ def model_leg(seed, steps, plain_steps, cpu):
            "support_bytes": supports_bytes, "generate_s": round(gen_s, 1), "build_s": round(build_s, 1),
            "root_fixpoint_ms": round(root_s * 1e3, 3), "root_fixpoint_tuned_ms": round(root_tuned_s * 1e3, 3),
            "autotuned_solo_max_granules": best, "root_props": props, "root_rounds": rounds,
-           "root_support_GBps": round(supports_bytes / root_tuned_s / 1e9, 1),
            "steps": steps, "batched_props": bprops, "batched_step_props_per_s": round(bprops / batched_s, 1),
            "batched_ms_per_step": round(batched_s / steps * 1e3, 3)}
     # plain GPU baseline (one launch per table propagation) on the first steps
@@ -322,6 +321,7 @@ def model_leg(seed, steps, plain_steps, cpu):
         pm.pop()
     out["plain_steps"] = pstep
     out["plain_step_props_per_s"] = round(pcnt / plain_s, 1)
+    out["plain_ms_per_step"] = round(plain_s / max(pstep, 1) * 1e3, 3)
     if cpu:
         from oracle import oracle as O
         ots = [O.OracleTable(tb.tuples, tb.lo, tb.dsizes) for tb in spec.tables]
@@ -347,7 +347,9 @@ def model_leg(seed, steps, plain_steps, cpu):
             else:
                 for o in ots:
                     o.pop()
-        out["oracle_step_props_per_s"] = round(ocnt / (time.perf_counter() - c0), 1)
+        oel = time.perf_counter() - c0
+        out["oracle_step_props_per_s"] = round(ocnt / oel, 1)
+        out["oracle_ms_per_step"] = round(oel / max(ostep, 1) * 1e3, 3)
     return out
 
 
