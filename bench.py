@@ -12,8 +12,10 @@ state through the C ABI (push, propagate, pop), so every propagate is a
 synchronous host call with its domain bitmaps crossing the boundary.
 
 Printed: one JSON line with propagations/s (`value`), p50/p99 call latency,
-the propagate kernel's HIP-event duration against the HBM roofline, and the
-CPU oracle timed on a bounded sample of the same script.
+the propagate kernel's device-clock duration against the HBM roofline, the
+batched legs (4,096 search nodes in one launch; a 2,000-table model solved to
+a fixpoint per search step, batched vs one launch per table vs the CPU
+oracle), and the CPU oracle timed on a bounded sample of the same script.
 """
 import argparse
 import json
@@ -40,6 +42,8 @@ def parse():
     p.add_argument("--nodes", type=int, default=4096)
     p.add_argument("--no-nodes", action="store_true")
     p.add_argument("--model-steps", type=int, default=100)
+    p.add_argument("--calibration-copy", type=int, default=0,
+                   help="MiB copied once by torch before the timed run (counter calibration)")
     p.add_argument("--no-model", action="store_true")
     return p.parse_args()
 
@@ -366,6 +370,14 @@ def main():
 
     seed = W.DEFAULT_SEED if args.seed is None else args.seed
     torch.cuda.set_device(0)
+    if args.calibration_copy:
+        n = args.calibration_copy * (1 << 20) // 8
+        src = torch.ones(n, dtype=torch.int64, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     spec = W.config2_table(seed)
     lay = spec.layout()
     table = ct.Table(spec.tuples, spec.lo, spec.dsizes)
@@ -402,6 +414,9 @@ def main():
     avg_kernel_s = kernel_ms / 1e3 / max(launches, 1)
     achieved = per_launch_bytes / avg_kernel_s / 1e9 if avg_kernel_s > 0 else 0.0
 
+    from paper_2507_18413_amd import profiling
+    prof = profiling.read_summary(os.path.join(ROOT, "profiles", "propagate_config2.md"))
+    traffic = prof.get("hbm_bytes_per_launch") if prof else None
     out = {
         "metric": "CT propagations/sec (plain calls, one large table)",
         "value": round(value, 1),
@@ -428,7 +443,7 @@ def main():
                    "avg_us": round(avg_kernel_s * 1e6, 3),
                    "support_words_per_s": round(d["granule_rows"] * 64 / elapsed, 1)},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": None,
+                     "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": traffic,
                      "bytes_per_launch": round(per_launch_bytes, 1)},
     }
     if not args.no_nodes:
