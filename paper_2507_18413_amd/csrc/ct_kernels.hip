@@ -952,9 +952,22 @@ __global__ void __launch_bounds__(BLOCK) model_gather_kernel(ModelDesc M) {
   }
 }
 
-// first round: a table runs iff the input pool removes a value from the
-// domains it returned last (some variable of its scope changed)
-__global__ void __launch_bounds__(BLOCK) model_seed_kernel(ModelDesc M) {
+// Seeding the first round.  Every table's earlier pruning holds under the
+// (smaller) input pool, so the pool is first ANDed with the domains each
+// table returned last; a table then runs iff that pool removes a value from
+// its domains.
+__global__ void __launch_bounds__(BLOCK) model_seed_and_kernel(ModelDesc M) {
+  const int stride = gridDim.x * BLOCK;
+  for (int e = blockIdx.x * BLOCK + threadIdx.x; e < M.nEntries; e += stride) {
+    const int c = M.scopeTab[e];
+    const int v = M.scopeVar[e];
+    const int po = M.poolOff[v], nw = M.poolNW[v], to = M.entDomOff[e];
+    const CT_G uint64_t* last = M.lastDom[c];
+    for (int q = 0; q < nw; ++q) atomicAnd((unsigned long long*)&M.poolNext[po + q], (unsigned long long)last[to + q]);
+  }
+}
+
+__global__ void __launch_bounds__(BLOCK) model_seed_mark_kernel(ModelDesc M) {
   const int stride = gridDim.x * BLOCK;
   int any = 0, cnt = 0;
   for (int c = blockIdx.x * BLOCK + threadIdx.x; c < M.nTables; c += stride) {
@@ -964,7 +977,7 @@ __global__ void __launch_bounds__(BLOCK) model_seed_kernel(ModelDesc M) {
       const int v = M.scopeVar[e];
       const int po = M.poolOff[v], nw = M.poolNW[v], to = M.entDomOff[e];
       for (int q = 0; q < nw; ++q)
-        if (last[to + q] & ~M.pool[po + q]) d = 1;
+        if (last[to + q] & ~M.poolNext[po + q]) d = 1;
     }
     M.dirty[c] = d;
     any |= d;
@@ -972,6 +985,10 @@ __global__ void __launch_bounds__(BLOCK) model_seed_kernel(ModelDesc M) {
   }
   if (any) atomicOr(&M.flags[0], 1);
   if (cnt) atomicAdd(&M.flags[3], cnt);
+}
+
+__global__ void __launch_bounds__(BLOCK) model_copy_kernel(CT_G uint64_t* dst, const CT_G uint64_t* src, int n) {
+  for (int w = blockIdx.x * BLOCK + threadIdx.x; w < n; w += gridDim.x * BLOCK) dst[w] = src[w];
 }
 
 // AND every successful table's output into poolNext; a failure stops the model
@@ -1077,8 +1094,13 @@ hipError_t launch_model_round(const ModelDesc& M, const KArgs& a, int grid, hipS
   return hipGetLastError();
 }
 
+// M.pool holds the input; leaves pool = input AND every table's domains and
+// the dirty flags of the first round.
 hipError_t launch_model_seed(const ModelDesc& M, hipStream_t stream) {
-  hipLaunchKernelGGL(model_seed_kernel, dim3(64), dim3(BLOCK), 0, stream, M);
+  hipLaunchKernelGGL(model_copy_kernel, dim3(64), dim3(BLOCK), 0, stream, M.poolNext, M.pool, M.poolWords);
+  hipLaunchKernelGGL(model_seed_and_kernel, dim3(64), dim3(BLOCK), 0, stream, M);
+  hipLaunchKernelGGL(model_seed_mark_kernel, dim3(64), dim3(BLOCK), 0, stream, M);
+  hipLaunchKernelGGL(model_copy_kernel, dim3(64), dim3(BLOCK), 0, stream, M.pool, M.poolNext, M.poolWords);
   return hipGetLastError();
 }
 
