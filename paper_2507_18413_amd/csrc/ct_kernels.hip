@@ -987,8 +987,12 @@ __global__ void __launch_bounds__(BLOCK) model_seed_mark_kernel(ModelDesc M) {
   if (cnt) atomicAdd(&M.flags[3], cnt);
 }
 
-__global__ void __launch_bounds__(BLOCK) model_copy_kernel(CT_G uint64_t* dst, const CT_G uint64_t* src, int n) {
-  for (int w = blockIdx.x * BLOCK + threadIdx.x; w < n; w += gridDim.x * BLOCK) dst[w] = src[w];
+// (kernel parameters never carry the address-space qualifier: host and device
+// passes must mangle the kernel's name identically)
+__global__ void __launch_bounds__(BLOCK) model_copy_kernel(uint64_t* dst, const uint64_t* src, int n) {
+  CT_G uint64_t* d = (CT_G uint64_t*)dst;
+  const CT_G uint64_t* sc = (const CT_G uint64_t*)src;
+  for (int w = blockIdx.x * BLOCK + threadIdx.x; w < n; w += gridDim.x * BLOCK) d[w] = sc[w];
 }
 
 // AND every successful table's output into poolNext; a failure stops the model
@@ -1097,10 +1101,12 @@ hipError_t launch_model_round(const ModelDesc& M, const KArgs& a, int grid, hipS
 // M.pool holds the input; leaves pool = input AND every table's domains and
 // the dirty flags of the first round.
 hipError_t launch_model_seed(const ModelDesc& M, hipStream_t stream) {
-  hipLaunchKernelGGL(model_copy_kernel, dim3(64), dim3(BLOCK), 0, stream, M.poolNext, M.pool, M.poolWords);
+  hipLaunchKernelGGL(model_copy_kernel, dim3(64), dim3(BLOCK), 0, stream, (uint64_t*)M.poolNext,
+                     (const uint64_t*)M.pool, M.poolWords);
   hipLaunchKernelGGL(model_seed_and_kernel, dim3(64), dim3(BLOCK), 0, stream, M);
   hipLaunchKernelGGL(model_seed_mark_kernel, dim3(64), dim3(BLOCK), 0, stream, M);
-  hipLaunchKernelGGL(model_copy_kernel, dim3(64), dim3(BLOCK), 0, stream, M.pool, M.poolNext, M.poolWords);
+  hipLaunchKernelGGL(model_copy_kernel, dim3(64), dim3(BLOCK), 0, stream, (uint64_t*)M.pool,
+                     (const uint64_t*)M.poolNext, M.poolWords);
   return hipGetLastError();
 }
 

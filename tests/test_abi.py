@@ -71,3 +71,28 @@ def test_no_oracle_in_product_path():
             elif f.endswith((".cpp", ".hip", ".h")):
                 text = open(path).read()
                 assert "cto_" not in text and "ct_oracle" not in text, path
+
+
+def test_kernel_signatures_have_no_address_space_qualifier():
+    """A __global__ parameter typed with the device-only address space would
+    mangle the kernel's name differently in the host and device passes, and
+    its launch would name a kernel that does not exist on the device."""
+    import re
+    src = open(os.path.join(ROOT, "paper_2507_18413_amd", "csrc", "ct_kernels.hip")).read()
+    for m in re.finditer(r"__global__[^{]*\(([^)]*)\)\s*\{", src):
+        assert "CT_G" not in m.group(1), m.group(0)[:120]
+
+
+def test_host_and_device_kernel_names_match(tmp_path):
+    """Every kernel the host stubs launch is defined in the gfx950 code."""
+    import re
+    src = os.path.join(ROOT, "paper_2507_18413_amd", "csrc", "ct_kernels.hip")
+    cmd = ["/opt/rocm/bin/hipcc", "--offload-arch=gfx950", "-O1", "-std=c++17", "-c", "--save-temps",
+           "-I", os.path.join(ROOT, "include"), "-I", os.path.dirname(src), src, "-o", str(tmp_path / "k.o")]
+    subprocess.run(cmd, check=True, capture_output=True, cwd=tmp_path)
+    dev = open(next(tmp_path.glob("*amdgcn*gfx950.s"))).read()
+    host = open(next(tmp_path.glob("*host-x86_64*.s"))).read()
+    dev_k = set(re.findall(r"^(_ZN3ctk\w*kernel\w*):", dev, re.M))
+    host_k = {k for k in re.findall(r"(_ZN3ctk\w*kernel\w*)", host) if "__device_stub__" not in k}
+    assert dev_k and host_k
+    assert host_k <= dev_k, host_k - dev_k
