@@ -8,7 +8,8 @@
 The kernel-trace statistics give the propagate kernel's average duration.
 The two counter runs (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch) are
 scaled by what the same counter reads for a plain copy kernel of known size
-(torch's copy of `--copy-bytes` bytes, run by `bench.py --calibration-copy`)
+(the runtime's device-to-device copyBuffer kernel of `--copy-bytes` bytes,
+run by `bench.py --calibration-copy`)
 and give HBM bytes per launch.  The summary ends with a JSON line that
 bench.py reads back, keyed by the SHA-256 of the kernel source, so the
 traffic figure is dropped as soon as the kernel changes.
@@ -37,8 +38,8 @@ def _rows(path):
         return list(csv.DictReader(f))
 
 
-def counter_by_kernel(path, counter):
-    """Mean counter value per dispatch, per kernel name."""
+def counter_by_kernel(path, counter, largest=False):
+    """Mean (or largest) counter value per dispatch, per kernel name."""
     vals = {}
     for r in _rows(path):
         name = r.get("Kernel_Name", "")
@@ -47,7 +48,8 @@ def counter_by_kernel(path, counter):
         v = float(r.get("Counter_Value", "nan"))
         vals.setdefault(name, {}).setdefault(r.get("Dispatch_Id", len(vals)), 0.0)
         vals[name][r.get("Dispatch_Id")] += v
-    return {k: (statistics.mean(d.values()), len(d)) for k, d in vals.items()}
+    agg = max if largest else statistics.mean
+    return {k: (agg(d.values()), len(d)) for k, d in vals.items()}
 
 
 def pick(d, pattern):
@@ -75,8 +77,9 @@ def summarize(args):
         w = counter_by_kernel(args.write, "WRITE_SIZE")
         _, (kf, nf) = pick(f, KERNEL)
         _, (kw, nw) = pick(w, KERNEL)
-        cname, (cf, _) = pick(f, r"copy|Copy|elementwise|Elementwise")
-        _, (cw, _) = pick(w, r"copy|Copy|elementwise|Elementwise")
+        # the calibration copy is the largest copyBuffer dispatch of the run
+        cname, (cf, _) = pick(counter_by_kernel(args.fetch, "FETCH_SIZE", largest=True), r"copyBuffer")
+        _, (cw, _) = pick(counter_by_kernel(args.write, "WRITE_SIZE", largest=True), r"copyBuffer")
         kib = args.copy_bytes / 1024.0
         ffac, wfac = cf / kib, cw / kib
         traffic = kf / ffac * 1024 + kw / wfac * 1024
