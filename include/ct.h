@@ -266,6 +266,75 @@ int ct_model_set_schedule(ct_model *m, int32_t solo_max_granules, int32_t rounds
  * push / pop, keeps the fastest and returns it in *best (nullable). */
 int ct_model_autotune(ct_model *m, const uint64_t *pool_in, int32_t *best);
 
+/* ------------------------------------------------------------------------
+ * Serving: continuous batching of propagate requests from many searches
+ * --------------------------------------------------------------------- */
+/*
+ * A server owns a thread that takes requests from many concurrent searches
+ * (each bound to one table), batches the requests of searches that have no
+ * request in flight into one ct_propagate_batch launch per free stream, and
+ * returns completions while later requests are already being batched: a
+ * request that arrives while others run on the GPU joins the next launch.
+ * Requests of one search run in submission order, one at a time.
+ * A search holds a slot of its table from its first request to its finishing
+ * request; slots are admitted against a device-memory budget (bytes of slot
+ * state; one search is always admitted), and a search waits, queued, while
+ * the budget is exhausted.  The
+ * server keeps each search's domain stack on the host, so a request names
+ * only the values to remove.  Results do not depend on what else is in the
+ * batch.  The tables must not be used by anything else while the server runs.
+ */
+typedef struct ct_server ct_server;
+
+typedef struct {
+    int64_t mem_budget;  /* bytes of slot state admitted at once; <= 0: unlimited */
+    int32_t max_batch;   /* requests per launch; <= 0: 1024 */
+    int32_t streams;     /* launches in flight; <= 0: 2 */
+} ct_server_cfg;
+
+#define CT_REQ_FINISH 1u /* the search ends after this request; its slot is released */
+
+typedef struct {
+    int32_t search;          /* id from ct_server_add_search */
+    uint32_t flags;          /* CT_REQ_* */
+    int32_t n_pop;           /* levels popped first */
+    int32_t push;            /* 1: push a level after the pops */
+    const uint64_t *remove;  /* host, D words of the search's table: values removed
+                                from the current domains (NULL: none); copied */
+    uint64_t *dom_out;       /* host, D words, written before completion (nullable) */
+    uint64_t tag;            /* returned in the completion */
+} ct_request;
+
+typedef struct {
+    uint64_t tag;
+    int32_t search;
+    int32_t status;          /* as ct_propagate; CT_E_NOMEM if the search's depth
+                                would exceed its max_depth */
+    double t_submit, t_launch, t_done;  /* seconds, steady clock of the process */
+} ct_completion;
+
+int ct_server_create(const ct_server_cfg *cfg, ct_server **out);
+/* Stops the thread after the requests in flight, frees the server's slots'
+ * bookkeeping (the tables keep their memory). */
+void ct_server_destroy(ct_server *s);
+/* Registers a search on table t with room for max_depth levels (all searches
+ * of one table use the same max_depth); it starts at the table's root state
+ * when its first request is admitted.  Searches are registered before the
+ * first ct_server_submit (CT_E_STATE afterwards).  The first request of a
+ * search (and the first after a CT_REQ_FINISH) has n_pop = 0 and push = 0. */
+int ct_server_add_search(ct_server *s, ct_table *t, int32_t max_depth, int32_t *search);
+/* Thread-safe. */
+int ct_server_submit(ct_server *s, const ct_request *req);
+/* Up to max completions, waiting up to wait_us microseconds for the first;
+ * returns the number written (>= 0) or a negative error. */
+int ct_server_poll(ct_server *s, ct_completion *out, int32_t max, int32_t wait_us);
+/* Counters: [0] requests done, [1] launches, [2] admission waits (times a
+ * ready request could not get a slot), [3] slot bytes in use, [4] peak slot
+ * bytes, [5] slots allocated. */
+int ct_server_stats(ct_server *s, int64_t *out6);
+/* The steady clock the timestamps use (seconds). */
+double ct_server_now(void);
+
 /* Synchronizes `stream` and reports whether a batch launched on it hit a
  * device-side error (a bounded wait that expired): CT_OK or CT_E_DEVICE (the
  * error is cleared; the slots of the affected jobs are undefined). */

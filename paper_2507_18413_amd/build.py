@@ -16,7 +16,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libct.so")
 BUILD = os.path.join(ROOT, "_build")
-SOURCES = [os.path.join(CSRC, "ct_kernels.hip"), os.path.join(CSRC, "ct_runtime.cpp")]
+SOURCES = [os.path.join(CSRC, "ct_kernels.hip"), os.path.join(CSRC, "ct_runtime.cpp"),
+           os.path.join(CSRC, "ct_server.cpp")]
 ARCH = os.environ.get("CT_OFFLOAD_ARCH", "gfx950")
 HIPCC = "/opt/rocm/bin/hipcc"
 
@@ -38,7 +39,7 @@ def torch_hip_runtime():
 def compile_cmd(src, obj):
     if src.endswith(".cpp"):
         # host-only runtime: HIP runtime API, no device code
-        return ["g++", "-O2", "-std=c++17", "-fPIC", "-c", "-Wall", "-D__HIP_PLATFORM_AMD__=1",
+        return ["g++", "-O2", "-std=c++17", "-fPIC", "-pthread", "-c", "-Wall", "-D__HIP_PLATFORM_AMD__=1",
                 "-I", "/opt/rocm/include", "-I", os.path.join(ROOT, "include"), "-I", CSRC, src, "-o", obj]
     return [HIPCC, f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-c",
             "-Wall", "-Wno-unused-function",
@@ -50,7 +51,7 @@ def compile_cmd(src, obj):
 def link_cmd(objs, out):
     libdir = torch_hip_runtime()
     if libdir:
-        return ["g++", "-shared", "-o", out, *objs, "-L", libdir, "-l:libamdhip64.so",
+        return ["g++", "-shared", "-pthread", "-o", out, *objs, "-L", libdir, "-l:libamdhip64.so",
                 f"-Wl,-rpath,{libdir}", "-Wl,--no-undefined"]
     return [HIPCC, "-shared", f"--offload-arch={ARCH}", "-o", out, *objs]
 

@@ -142,6 +142,7 @@ struct ct_table {
   uint64_t* pDomIn = nullptr;   // D words (used when D > INLINE_WORDS)
   uint64_t* pCt = nullptr;      // W words (lazily)
   int32_t* pStatus = nullptr;
+  bool tailPending = false;  // a synchronous call returned before its kernel ended
   // optional kernel timing of synchronous launches, on the device clock
   // (no host events: they would add dispatch packets to every call)
   unsigned long long* dClock = nullptr;  // 5 words, see KArgs::clock
@@ -267,6 +268,7 @@ int run_single(ct_table* T, DevJob& J, const uint64_t* dom_in_host) {
   *status = kStatusPending;
   a.clock = T->timing ? T->dClock : nullptr;
   HIPCHK(launch_propagate(a, std::min(total, propagate_max_grid()), T->stream));
+  T->tailPending = true;
   // The job publishes its status (and its outputs before it) to coherent
   // host memory with a system-scope release: wait for that word instead of
   // the whole kernel.  The kernel's tail finishes on the stream, which
@@ -802,7 +804,11 @@ int ct_propagate_batch(const ct_job* jobs, int32_t n_jobs, void* stream_v, int32
   {
     std::set<ct_table*> tabs;
     for (int j = 0; j < n_jobs; ++j) tabs.insert(jobs[j].table);
-    for (ct_table* T : tabs) HIPCHK(hipStreamSynchronize(T->stream));
+    for (ct_table* T : tabs)
+      if (T->tailPending) {
+        HIPCHK(hipStreamSynchronize(T->stream));
+        T->tailPending = false;
+      }
   }
   QueueCtx* q = nullptr;
   {
@@ -910,6 +916,26 @@ int ct_propagate_batch(const ct_job* jobs, int32_t n_jobs, void* stream_v, int32
 }
 
 }  // extern "C"
+
+// internal accessors used by the serving loop (ct_server.cpp)
+namespace ctk {
+int64_t slot_footprint(const ct_table* T, int maxDepth) {
+  const int64_t trailCap = (int64_t)maxDepth * T->nGran;
+  return (int64_t)(align256(sizeof(uint64_t) * T->stride) + 4 * align256(sizeof(int32_t) * T->nGran) +
+                   align256(sizeof(uint64_t) * T->D) + align256(sizeof(int32_t) * T->rows) +
+                   align256(sizeof(TrailHdr) * std::max<int64_t>(trailCap, 1)) +
+                   align256(sizeof(uint64_t) * GW * std::max<int64_t>(trailCap, 1)) +
+                   align256(sizeof(Level) * std::max(maxDepth, 1)) +
+                   align256(sizeof(uint64_t) * T->D * std::max(maxDepth, 1)) + sizeof(SlotDesc));
+}
+
+int root_domains(ct_table* T, uint64_t* out) {
+  HIPCHK(hipMemcpy(out, T->hRoot.lastDom, sizeof(uint64_t) * T->D, hipMemcpyDeviceToHost));
+  return CT_OK;
+}
+
+void set_error(const char* msg) { g_err = msg; }
+}  // namespace ctk
 
 // ===========================================================================
 // Multi-table model: propagation rounds captured in a hipGraph
@@ -1233,7 +1259,6 @@ int ct_model_fixpoint(ct_model* m, const uint64_t* pool_in, uint64_t* pool_out, 
   int rc = model_sync_tables(m);
   if (rc) return rc;
   if (!m->built && (rc = model_build(m))) return rc;
-  const int nT = (int)m->tabs.size();
   ModelDesc& M = m->M;
   HIPCHK(hipMemcpyAsync(M.pool, pool_in, sizeof(uint64_t) * m->poolWords, hipMemcpyDeviceToDevice, m->stream));
   {

@@ -55,6 +55,22 @@ class ct_job(C.Structure):
                 ("dom_out", C.c_void_p), ("ct_out", C.c_void_p)]
 
 
+class ct_server_cfg(C.Structure):
+    _fields_ = [("mem_budget", C.c_int64), ("max_batch", C.c_int32), ("streams", C.c_int32)]
+
+
+class ct_request(C.Structure):
+    _fields_ = [("search", C.c_int32), ("flags", C.c_uint32), ("n_pop", C.c_int32), ("push", C.c_int32),
+                ("remove", C.c_void_p), ("dom_out", C.c_void_p), ("tag", C.c_uint64)]
+
+
+class ct_completion(C.Structure):
+    _fields_ = [("tag", C.c_uint64), ("search", C.c_int32), ("status", C.c_int32),
+                ("t_submit", C.c_double), ("t_launch", C.c_double), ("t_done", C.c_double)]
+
+
+REQ_FINISH = 1
+
 _lib = None
 
 
@@ -113,6 +129,13 @@ def lib():
             "ct_model_pop": ([P], C.c_int),
             "ct_model_set_schedule": ([P, I32, I32], C.c_int),
             "ct_model_autotune": ([P, P, C.POINTER(I32)], C.c_int),
+            "ct_server_create": ([C.POINTER(ct_server_cfg), C.POINTER(P)], C.c_int),
+            "ct_server_destroy": ([P], None),
+            "ct_server_add_search": ([P, P, I32, C.POINTER(I32)], C.c_int),
+            "ct_server_submit": ([P, C.POINTER(ct_request)], C.c_int),
+            "ct_server_poll": ([P, P, I32, I32], C.c_int),
+            "ct_server_stats": ([P, P], C.c_int),
+            "ct_server_now": ([], C.c_double),
             "ct_last_error": ([], C.c_char_p),
         }
         for name, (args, res) in sig.items():
@@ -353,3 +376,69 @@ class Model:
         if st < 0:
             raise CTError(st, last_error())
         return best.value
+
+
+class Server:
+    """Continuous-batching serving loop over many searches (one thread in the
+    library).  Requests name values to remove; completions carry status and
+    timestamps; dom_out is written into the caller's buffer."""
+
+    def __init__(self, mem_budget=0, max_batch=1024, streams=2):
+        cfg = ct_server_cfg(int(mem_budget), int(max_batch), int(streams))
+        h = C.c_void_p()
+        st = lib().ct_server_create(C.byref(cfg), C.byref(h))
+        if st < 0:
+            raise CTError(st, last_error())
+        self.h = h
+        self._keep = {}
+
+    def close(self):
+        if getattr(self, "h", None) is not None and self.h.value is not None:
+            lib().ct_server_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def add_search(self, table, max_depth=64):
+        sid = C.c_int32()
+        st = lib().ct_server_add_search(self.h, table.h, int(max_depth), C.byref(sid))
+        if st < 0:
+            raise CTError(st, last_error())
+        return sid.value
+
+    def submit(self, search, remove=None, n_pop=0, push=0, finish=False, dom_out=None, tag=0):
+        """remove / dom_out: numpy uint64 arrays (dom_out must stay alive until
+        the completion is polled)."""
+        r = ct_request(int(search), REQ_FINISH if finish else 0, int(n_pop), int(push),
+                       _p(remove), _p(dom_out), int(tag))
+        if dom_out is not None:
+            self._keep[int(tag)] = dom_out
+        st = lib().ct_server_submit(self.h, C.byref(r))
+        if st < 0:
+            raise CTError(st, last_error())
+
+    def poll(self, max_n=4096, wait_us=1000):
+        arr = (ct_completion * max_n)()
+        n = lib().ct_server_poll(self.h, C.cast(arr, C.c_void_p), int(max_n), int(wait_us))
+        if n < 0:
+            raise CTError(n, last_error())
+        out = []
+        for k in range(n):
+            c = arr[k]
+            self._keep.pop(int(c.tag), None)
+            out.append((int(c.tag), int(c.search), int(c.status), c.t_submit, c.t_launch, c.t_done))
+        return out
+
+    def stats(self):
+        a = np.zeros(6, np.int64)
+        lib().ct_server_stats(self.h, _p(a))
+        return dict(done=int(a[0]), launches=int(a[1]), admission_waits=int(a[2]),
+                    slot_bytes_in_use=int(a[3]), peak_slot_bytes=int(a[4]), slots_allocated=int(a[5]))
+
+    @staticmethod
+    def now():
+        return lib().ct_server_now()

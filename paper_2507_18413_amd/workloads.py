@@ -398,3 +398,62 @@ def run_plain_script(sut, layout: DomLayout, n_calls: int, seed: int, config: in
             if on_step:
                 on_step("pop", None)
     return script
+
+
+class SimSearch:
+    """A simulated depth-first search over one table, as a stream of requests.
+
+    Request k: pops (one after a failure; U{1..depth} every ``every``-th
+    request), a push (except the first request), then the values to remove:
+    ceil(``frac`` x |dom|) present values of U{nvars} distinct variables.  The
+    search keeps the domains it was given back, so the choices follow the
+    results; ``log`` records (n_pop, push, remove) for replay.
+    """
+
+    def __init__(self, layout: DomLayout, root: np.ndarray, rng, length: int, every: int = 10,
+                 frac: float = 0.05, nvars=(1, 4)):
+        self.lay, self.rng, self.length = layout, rng, length
+        self.every, self.frac, self.nvars = every, frac, nvars
+        self.dom = root.copy()
+        self.stack = []
+        self.failed = False
+        self.k = 0
+        self.log = []
+
+    def done(self) -> bool:
+        return self.k >= self.length
+
+    def next_request(self):
+        """(n_pop, push, remove, finish) of the next request."""
+        n_pop = 0
+        if self.k > 0:
+            if self.failed:
+                n_pop = 1
+            elif self.k % self.every == 0 and self.stack:
+                n_pop = int(self.rng.integers(1, len(self.stack) + 1))
+        for _ in range(n_pop):
+            self.dom = self.stack.pop()
+        self.failed = False
+        push = 1 if self.k > 0 else 0
+        if push:
+            self.stack.append(self.dom.copy())
+        new = pick_fraction_removal(self.rng, self.lay, self.dom, self.frac, self.nvars)
+        remove = self.dom & ~new
+        self.pending = new
+        self.k += 1
+        finish = self.k >= self.length
+        self.log.append((n_pop, push, remove))
+        return n_pop, push, remove, finish
+
+    def on_result(self, status: int, dom_out):
+        if status == 0:
+            self.dom = np.asarray(dom_out, dtype=np.uint64).copy()
+        elif status == 1:
+            self.failed = True
+        else:
+            raise RuntimeError(f"unexpected status {status}")
+
+
+def poisson_arrivals(rng, rate: float, n: int) -> np.ndarray:
+    """Arrival times (seconds from 0) of a Poisson process of the given rate."""
+    return np.cumsum(rng.exponential(1.0 / rate, size=n))
