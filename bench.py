@@ -42,6 +42,10 @@ def parse():
     p.add_argument("--nodes", type=int, default=4096)
     p.add_argument("--no-nodes", action="store_true")
     p.add_argument("--model-steps", type=int, default=100)
+    p.add_argument("--no-serve", action="store_true")
+    p.add_argument("--serve-requests", type=int, default=200_000)
+    p.add_argument("--serve-rate", type=float, default=20_000.0)
+    p.add_argument("--serve-budget", type=int, default=0)
     p.add_argument("--calibration-copy", type=int, default=0,
                    help="MiB copied once by torch before the timed run (counter calibration)")
     p.add_argument("--no-model", action="store_true")
@@ -357,6 +361,137 @@ def model_leg(seed, steps, plain_steps, cpu):
     return out
 
 
+def serve_leg(tables_spec, seed, rate, n_requests, n_searches, budget, sample_check):
+    """Serving loop: Poisson arrivals at `rate` requests/s, each given to a
+    random idle search among `n_searches` simulated DFS searches bound to
+    uniformly drawn tables of the 300-table mix; latency = completion time -
+    arrival time (arrivals wait while no search is idle)."""
+    import collections
+    import numpy as np
+    import torch
+    from paper_2507_18413_amd import ct
+    from paper_2507_18413_amd import workloads as W
+    t0 = time.perf_counter()
+    tabs = [ct.Table(sp.tuples, sp.lo, sp.dsizes, max_depth=64) for sp in tables_spec]
+    build_s = time.perf_counter() - t0
+    rng = W.rng_for(seed, 5, 777)
+    # per-table pools of deltas: U{1..4} variables, ceil(5 %) of each one's
+    # initial values (values already gone make no difference)
+    pools = []
+    for sp in tables_spec:
+        lay = sp.layout()
+        pool = np.zeros((256, lay.D), np.uint64)
+        for k in range(256):
+            for v in rng.choice(lay.n, size=min(lay.n, int(rng.integers(1, 5))), replace=False):
+                d = int(lay.dsizes[v])
+                for a in rng.choice(d, size=int(np.ceil(0.05 * d)), replace=False):
+                    pool[k, lay.off[v] + a // 64] |= np.uint64(1 << (int(a) % 64))
+        pools.append(pool)
+    srv = ct.Server(mem_budget=budget, max_batch=1024, streams=2)
+    search_tab = rng.integers(0, len(tabs), size=n_searches)
+    sids = [srv.add_search(tabs[int(c)], max_depth=64) for c in search_tab]
+    depth = np.zeros(n_searches, np.int64)
+    count = np.zeros(n_searches, np.int64)
+    length = rng.integers(50, 201, size=n_searches)
+    failed = np.zeros(n_searches, bool)
+    arrivals = W.poisson_arrivals(rng, rate, n_requests)
+    idle = list(range(n_searches))
+    waiting = collections.deque()
+    t_arr, t_launch, t_done, sreq = {}, [], [], {}
+    sample = set(range(min(sample_check, n_searches)))
+    logs = {s: [] for s in sample}
+    outs = {}
+    issued = completed = 0
+    start = srv.now() + 0.05
+    arrivals = arrivals + start
+    nxt = 0
+    while completed < n_requests:
+        now = srv.now()
+        while nxt < n_requests and arrivals[nxt] <= now:
+            waiting.append(arrivals[nxt])
+            nxt += 1
+        while waiting and idle:
+            ta = waiting.popleft()
+            j = int(rng.integers(0, len(idle)))
+            s = idle[j]
+            idle[j] = idle[-1]
+            idle.pop()
+            c = int(search_tab[s])
+            if count[s] == 0:
+                n_pop, push = 0, 0
+            else:
+                n_pop = 1 if failed[s] else (int(rng.integers(1, depth[s] + 1)) if count[s] % 10 == 0 and depth[s] else 0)
+                push = 1
+            depth[s] += push - n_pop
+            failed[s] = False
+            rem = pools[c][int(rng.integers(0, 256))]
+            count[s] += 1
+            finish = count[s] >= length[s]
+            out = np.empty(tabs[c].D, np.uint64) if s in sample else None
+            srv.submit(sids[s], remove=rem, n_pop=n_pop, push=push, finish=finish, dom_out=out, tag=issued)
+            t_arr[issued] = ta
+            sreq[issued] = (s, finish)
+            if s in sample:
+                logs[s].append((n_pop, push, rem, out))
+            issued += 1
+        res = srv.poll(wait_us=50 if not waiting else 0)
+        for (tg, sid, status, ts, tl, td) in res:
+            s, finish = sreq.pop(tg)
+            t_done.append(td - t_arr.pop(tg))
+            t_launch.append(tl)
+            if status == 1:
+                failed[s] = True
+            elif status != 0:
+                raise RuntimeError(f"serving status {status}")
+            if finish:
+                count[s] = 0
+                depth[s] = 0
+                failed[s] = False
+            if s in sample:
+                logs[s][-1] = logs[s][-1] + (status,) if len(logs[s][-1]) == 4 else logs[s][-1]
+            idle.append(s)
+            completed += 1
+    wall = srv.now() - start
+    st = srv.stats()
+    srv.close()
+    lat = np.array(t_done) * 1e6
+    out = {"tables": len(tabs), "searches": n_searches, "requests": n_requests, "offered_rate": rate,
+           "build_s": round(build_s, 1), "throughput_req_per_s": round(n_requests / wall, 1),
+           "latency_us": {"p50": round(float(np.percentile(lat, 50)), 1),
+                          "p99": round(float(np.percentile(lat, 99)), 1),
+                          "mean": round(float(lat.mean()), 1)},
+           "launches": st["launches"], "mean_batch": round(n_requests / max(st["launches"], 1), 2),
+           "admission_waits": st["admission_waits"], "peak_slot_bytes": st["peak_slot_bytes"],
+           "slots_allocated": st["slots_allocated"], "mem_budget": budget}
+    # the sampled searches replayed alone on the oracle must give the same results
+    if sample_check:
+        from oracle import oracle as O
+        ok = True
+        for s in sample:
+            sp = tables_spec[int(search_tab[s])]
+            o = None
+            dom, stack = None, []
+            for (n_pop, push, rem, outv, *stl) in logs[s]:
+                if o is None or (n_pop == 0 and push == 0):
+                    o = O.OracleTable(sp.tuples, sp.lo, sp.dsizes)
+                    dom, stack = o.domains(), []
+                for _ in range(n_pop):
+                    o.pop()
+                    dom = stack.pop()
+                if push:
+                    o.push()
+                    stack.append(dom.copy())
+                sto, od = o.propagate(dom & ~rem)
+                if stl and sto != stl[0]:
+                    ok = False
+                if sto == 0:
+                    if not (od == outv).all():
+                        ok = False
+                    dom = od
+        out["sampled_searches_equal_alone"] = ok
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -369,6 +504,11 @@ def main():
     from paper_2507_18413_amd import workloads as W
 
     seed = W.DEFAULT_SEED if args.seed is None else args.seed
+    serve_spec = None
+    if not args.no_serve:
+        # generated before the GPU is initialised: the pool's workers are
+        # fresh interpreters
+        serve_spec = W.config5_tables(seed, workers=min(16, os.cpu_count() or 1))
     torch.cuda.set_device(0)
     if args.calibration_copy:
         n = args.calibration_copy * (1 << 20) // 8
@@ -450,6 +590,10 @@ def main():
         out["batched_nodes"] = nodes_leg(seed, args.nodes, max(1, args.steps), 1)
     if not args.no_model:
         out["batched_model"] = model_leg(seed, args.model_steps, 20, not args.no_cpu_baseline)
+    if serve_spec is not None:
+        out["serving"] = serve_leg(serve_spec, seed, args.serve_rate, args.serve_requests, 512,
+                                   args.serve_budget, 0 if args.no_cpu_baseline else 8)
+        del serve_spec
     if not args.no_cpu_baseline:
         cps, cprops, cel, passes = cpu_baseline(spec, script, args.cpu_seconds)
         out["cpu_baseline"] = {"value": round(cps, 1), "unit": "propagations/s", "cores": 1, "kind": "oracle",

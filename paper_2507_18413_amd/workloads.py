@@ -110,6 +110,39 @@ def _first_occurrence_distinct(codes: np.ndarray, t: int) -> np.ndarray:
     return codes[first[:t]]
 
 
+_CODE_LIMIT = 1 << 62
+
+
+def _row_hash(tup: np.ndarray) -> np.ndarray:
+    """64-bit hash of each row (equal rows, equal hashes)."""
+    h = np.zeros(tup.shape[0], dtype=np.uint64)
+    with np.errstate(over="ignore"):
+        for i in range(tup.shape[1]):
+            h = (h ^ tup[:, i].astype(np.uint64)) * np.uint64(0x9E3779B97F4A7C15)
+            h ^= h >> np.uint64(29)
+    return h
+
+
+def _distinct_rows(draw_rows, t: int, n: int) -> np.ndarray:
+    """First ``t`` distinct rows of the stream ``draw_rows(m)`` (int64 [m, n]),
+    in draw order.  Rows whose hashes coincide count as one, so the kept rows
+    are always distinct (a collision only costs an extra draw)."""
+    rows = np.zeros((0, n), dtype=np.int64)
+    want, rate = t, 1.0
+    while True:
+        m = int(want / max(rate, 0.02) * 1.15) + 64
+        new = draw_rows(m)
+        before = rows.shape[0]
+        rows = np.concatenate([rows, new])
+        _, first = np.unique(_row_hash(rows), return_index=True)
+        first.sort()
+        if first.shape[0] >= t:
+            return rows[first[:t]].astype(np.int32)
+        rows = rows[first]
+        rate = max((rows.shape[0] - before) / m, 1e-3)
+        want = t - rows.shape[0]
+
+
 def distinct_uniform_tuples(rng: np.random.Generator, dsizes, t: int) -> np.ndarray:
     """``t`` distinct tuples, each column uniform over ``[0, d_i)``, in draw order."""
     dsizes = np.asarray(dsizes, dtype=np.int64)
@@ -118,6 +151,9 @@ def distinct_uniform_tuples(rng: np.random.Generator, dsizes, t: int) -> np.ndar
         raise ValueError("more distinct tuples requested than the domain product holds")
     if t == 0:
         return np.zeros((0, dsizes.shape[0]), dtype=np.int32)
+    if space >= _CODE_LIMIT:
+        n = dsizes.shape[0]
+        return _distinct_rows(lambda m: np.stack([rng.integers(0, d, size=m) for d in dsizes], 1), t, n)
     if 2 * t >= space:
         codes = rng.permutation(space)[:t].astype(np.int64)
         return _codes_to_tuples(codes, dsizes)
@@ -268,24 +304,36 @@ def config3_model(seed: int = DEFAULT_SEED, n_pool: int = 5000, n_tables: int = 
     return ModelSpec(pool, tables, scopes)
 
 
+def _config5_one(args):
+    seed, c, ds, t, s = args
+    trng = rng_for(seed, 5, 1 + c)
+    if c % 2 == 0:
+        tup = distinct_uniform_tuples(trng, ds, t)
+    else:
+        tup = _distinct_zipf_mixed(trng, ds, s, t)
+    return TableSpec(tup, np.zeros(ds.shape[0], np.int32), ds.astype(np.int32))
+
+
 def config5_tables(seed: int = DEFAULT_SEED, n_tables: int = 300, arity=(3, 10), dom=(8, 128),
-                   tuples=(1_000, 2_000_000), s: float = 1.1):
-    """Serving mix: even-index tables uniform, odd-index Zipf(s) columns."""
+                   tuples=(1_000, 2_000_000), s: float = 1.1, workers: int = 0):
+    """Serving mix: even-index tables uniform, odd-index Zipf(s) columns.
+
+    Each table's tuples come from its own stream, so the result does not
+    depend on ``workers`` (> 1: a pool of fresh interpreter processes)."""
     rng = rng_for(seed, 5, 0)
-    out = []
+    jobs = []
     for c in range(n_tables):
         n = int(rng.integers(arity[0], arity[1] + 1))
         ds = rng.integers(dom[0], dom[1] + 1, size=n).astype(np.int64)
         t = int(round(math.exp(rng.uniform(math.log(tuples[0]), math.log(tuples[1])))))
         space = int(np.prod([int(x) for x in ds], dtype=object))
         t = max(1, min(t, space // 2))
-        trng = rng_for(seed, 5, 1 + c)
-        if c % 2 == 0:
-            tup = distinct_uniform_tuples(trng, ds, t)
-        else:
-            tup = _distinct_zipf_mixed(trng, ds, s, t)
-        out.append(TableSpec(tup, np.zeros(n, np.int32), ds.astype(np.int32)))
-    return out
+        jobs.append((seed, c, ds, t, s))
+    if workers and workers > 1:
+        import multiprocessing as mp
+        with mp.get_context("spawn").Pool(workers) as pool:
+            return pool.map(_config5_one, jobs, chunksize=1)
+    return [_config5_one(j) for j in jobs]
 
 
 def _distinct_zipf_mixed(rng, dsizes, s, t):
@@ -295,19 +343,28 @@ def _distinct_zipf_mixed(rng, dsizes, s, t):
         c = np.cumsum(zipf_probs(int(d), s))
         c[-1] = 1.0
         cdfs.append(c)
+    space = int(np.prod([int(x) for x in dsizes], dtype=object))
+    if space >= _CODE_LIMIT:
+        def draw(m):
+            u = rng.random((m, n))
+            return np.stack([np.minimum(np.searchsorted(cdfs[i], u[:, i], side="right"), dsizes[i] - 1)
+                             for i in range(n)], 1).astype(np.int64)
+        return _distinct_rows(draw, t, n)
     got = np.zeros(0, dtype=np.int64)
-    draw = int(t * 1.9) + 64
+    draw, rate = int(t * 1.9) + 64, 1.0
     while True:
         codes = np.zeros(draw, dtype=np.int64)
         u = rng.random((draw, n))
         for i in range(n):
             v = np.minimum(np.searchsorted(cdfs[i], u[:, i], side="right"), dsizes[i] - 1)
             codes = codes * dsizes[i] + v
-        got = np.concatenate([got, codes])
-        dist = _first_occurrence_distinct(got, t)
-        if dist.shape[0] >= t:
-            return _codes_to_tuples(dist, dsizes)
-        draw = max(1024, int((t - dist.shape[0]) * 3))
+        before = got.shape[0]
+        got = _first_occurrence_distinct(np.concatenate([got, codes]), 1 << 62)
+        if got.shape[0] >= t:
+            return _codes_to_tuples(got[:t], dsizes)
+        # keep only distinct codes; size the next round from the distinct rate
+        rate = max((got.shape[0] - before) / draw, 1e-3)
+        draw = int((t - got.shape[0]) / rate * 1.15) + 1024
 
 
 # ---------------------------------------------------------------------------
