@@ -66,12 +66,19 @@ typedef struct ct_table ct_table;
 /* How a propagation is spread over the GPU: SOLO runs a whole call in one
  * workgroup (no hand-off between workgroups; best for small tables and for
  * batches of many jobs), SPLIT spreads updateTable over workgroups of 8
- * granules and filterDomains over workgroups of 4 domain words.  AUTO picks
- * SOLO for tables of at most 4 granules (16,384 tuples) and for batches of
- * at least 256 jobs.  Results are identical. */
+ * granules and filterDomains over workgroups of 4 domain words.  NODES is the
+ * search-node schedule of ct_propagate_batch: when every job of a batch is a
+ * CT_JOB_FROM_ROOT propagation of the same table of at most 256 support rows
+ * (sum of the domain sizes), one workgroup per (granule, 64 jobs) stages that
+ * granule of every support row in LDS and evaluates updateTable for its jobs
+ * from there, so the supports are read once per 64 jobs; other batches and
+ * single calls fall back to AUTO.  AUTO picks SOLO for tables of at most 4
+ * granules (16,384 tuples) and for batches of at least 256 jobs, and NODES
+ * for eligible batches of at least 64 jobs.  Results are identical. */
 #define CT_SCHED_AUTO 0
 #define CT_SCHED_SOLO 1
 #define CT_SCHED_SPLIT 2
+#define CT_SCHED_NODES 3
 
 typedef struct {
     int32_t branch_policy; /* CT_BRANCH_*; default AUTO */

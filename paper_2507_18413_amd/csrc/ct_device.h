@@ -127,6 +127,25 @@ struct DevJob {
   const CT_G int32_t* active;  // nullable: the job is skipped when *active == 0
 };
 
+// Granule-major schedule of a batch of search nodes (jobs that all propagate
+// one table from its root state): per node the Alg. 1 prologue's outcome and
+// its row list, encoded for the update kernel, and per (node, granule) a
+// non-zero flag of the new currTable granule.
+struct NodeInfo {
+  int32_t status, nrows;
+  CT_G uint64_t* ct;       // the node's slot currTable
+  CT_G uint64_t* ct_out;   // optional copy (W words), may be null
+  int64_t pad;
+};
+
+struct NodesDesc {
+  int32_t nJobs, rowsCap, groups, pad;
+  const CT_G DevJob* jobs;
+  CT_G NodeInfo* info;     // nJobs
+  CT_G uint16_t* rows;     // nJobs x rowsCap: row | 0x8000 (segment start) | 0x4000 (incremental)
+  CT_G uint8_t* nz;        // nJobs x nGran
+};
+
 // Multi-table model: pool variables shared by tables (device side of a
 // propagation round).  Scope entry e links column tabCol[e] of table
 // scopeTab[e] to pool variable scopeVar[e].

@@ -783,6 +783,162 @@ __device__ void do_solo(const KArgs& a, const DevJob& J, Shared& sh) {
   }
 }
 
+// ---------------------------------------------------------------------------
+// Granule-major schedule of search nodes (jobs that all propagate one table
+// from its root state).  The per-job schedules read every selected support
+// row of a node from memory; here a workgroup stages one granule of every
+// support row in LDS once and evaluates a group of nodes against it, so the
+// supports cross the memory hierarchy once per group and HBM mostly sees the
+// nodes' currTable writes.
+//   nodes_prep:   one workgroup per node: Alg. 1 prologue -> encoded row list
+//   nodes_update: one workgroup per (granule, node group): Alg. 2 from LDS
+//   nodes_finish: one workgroup per node: partition, FAIL, Alg. 3, status
+// ---------------------------------------------------------------------------
+constexpr int NODES_PER_GROUP = 64;
+constexpr int NODES_MAX_ROWS = 256;  // LDS tile of the update kernel: rows x 512 B
+constexpr int XCDS = 8;
+
+__global__ void __launch_bounds__(BLOCK) nodes_prep_kernel(KArgs a, NodesDesc N) {
+  __shared__ Shared sh;
+  const int j = blockIdx.x;
+  const DevJob J = N.jobs[j];
+  prologue(a, J, sh, false);
+  int st = sh.status;
+  // an empty reset segment is an empty domain: no tuple stays valid
+  if (st == ST_OK)
+    for (int g = 0; g < sh.nseg; ++g)
+      if (sh.segEnd[g] == (g ? sh.segEnd[g - 1] : 0)) st = ST_FAIL;
+  const int nrows = (st == ST_OK || st == ST_FAIL) ? sh.nrows : 0;
+  if (st == ST_OK) {
+    CT_G uint16_t* out = N.rows + (int64_t)j * N.rowsCap;
+    for (int k = threadIdx.x; k < nrows; k += BLOCK) {
+      // mark the first row of each segment (segments are a few hundred rows
+      // at most: a linear search in LDS)
+      int g = 0;
+      while (sh.segEnd[g] <= k) ++g;
+      const int b = g ? sh.segEnd[g - 1] : 0;
+      uint32_t e = sh.rows[k];
+      if (k == b) e |= 0x8000u | (sh.segInc[g] ? 0x4000u : 0u);
+      out[k] = (uint16_t)e;
+    }
+  }
+  if (threadIdx.x == 0) {
+    NodeInfo I;
+    I.status = st;
+    I.nrows = nrows;
+    I.ct = J.slot->ct;
+    I.ct_out = J.ct_out;
+    I.pad = 0;
+    N.info[j] = I;
+  }
+}
+
+// Block b of the launch runs on XCD b % 8 (round-robin dispatch); the blocks
+// of one granule are mapped to one XCD so that its L2 serves the tile to all
+// node groups after one fetch from HBM.
+__global__ void __launch_bounds__(BLOCK) nodes_update_kernel(KArgs a, NodesDesc N) {
+  extern __shared__ uint64_t tile[];
+  const int b = blockIdx.x;
+  const int xcd = b % XCDS, k = b / XCDS;
+  const int g = (k / N.groups) * XCDS + xcd;
+  const int group = k % N.groups;
+  const TabDesc* T = N.jobs[0].tab;
+  if (g >= T->nGran) return;
+  const int rows = T->rows;
+  const int64_t stride = T->stride, W = T->W;
+  const int lane = lane_id();
+  const CT_G uint64_t* S = T->S + (int64_t)g * GW;
+  for (int i = threadIdx.x; i < rows * GW; i += BLOCK) tile[i] = S[(int64_t)(i / GW) * stride + (i % GW)];
+  const int64_t w = (int64_t)g * GW + lane;
+  const uint64_t root = T->ct0[w];
+  __syncthreads();
+  const int node0 = group * NODES_PER_GROUP;
+  const int nEnd = min(node0 + NODES_PER_GROUP, N.nJobs);
+  const int wv = __builtin_amdgcn_readfirstlane(wave_id());
+  for (int p = node0 + wv; p < nEnd; p += WAVES) {
+    const NodeInfo I = N.info[p];
+    if (I.status != ST_OK && I.status != ST_FAIL) continue;  // rejected input: nothing changes
+    uint64_t m = 0ull;
+    if (I.status == ST_OK) {
+      const CT_G uint16_t* rl = N.rows + (int64_t)p * N.rowsCap;
+      uint64_t acc = 0ull;
+      bool inc = false, open = false;
+      m = ~0ull;
+      for (int k0 = 0; k0 < I.nrows; k0 += WAVE) {
+        // 64 entries of the row list, one per lane, then read lane by lane
+        const int mine = (k0 + lane < I.nrows) ? (int)rl[k0 + lane] : 0;
+        const int cnt = min(WAVE, I.nrows - k0);
+        for (int u0 = 0; u0 < cnt; u0 += ROW_UNROLL) {
+          int e[ROW_UNROLL];
+          uint64_t v[ROW_UNROLL];
+#pragma unroll
+          for (int u = 0; u < ROW_UNROLL; ++u) {
+            e[u] = __builtin_amdgcn_readlane(mine, u0 + u);
+            v[u] = tile[(e[u] & 0x3FFF) * GW + lane];
+          }
+#pragma unroll
+          for (int u = 0; u < ROW_UNROLL; ++u) {
+            if (u0 + u >= cnt) break;
+            if (e[u] & 0x8000) {
+              if (open) m &= inc ? ~acc : acc;
+              acc = 0ull;
+              inc = (e[u] & 0x4000) != 0;
+              open = true;
+            }
+            acc |= v[u];
+          }
+        }
+      }
+      if (open) m &= inc ? ~acc : acc;
+    }
+    const uint64_t nw = root & m;
+    I.ct[w] = nw;
+    if (I.ct_out && w < W) I.ct_out[w] = nw;
+    const bool nz = __ballot(nw != 0ull) != 0ull;
+    if (lane == 0) N.nz[(int64_t)p * T->nGran + g] = nz ? 1 : 0;
+  }
+}
+
+__global__ void __launch_bounds__(BLOCK) nodes_finish_kernel(KArgs a, NodesDesc N) {
+  __shared__ Shared sh;
+  const int j = blockIdx.x;
+  const DevJob J = N.jobs[j];
+  const TabDesc* T = J.tab;
+  SlotDesc* s = J.slot;
+  const NodeInfo I = N.info[j];
+  const int limit0 = T->limit0;
+  if (threadIdx.x == 0) {
+    // the prologue's FAIL (an empty domain) shows up as no surviving granule
+    sh.status = I.status == ST_FAIL ? ST_OK : I.status;
+    sh.noop = 0;
+    sh.limit = limit0;
+    sh.nrows = I.nrows;
+    sh.trailTop = 0;
+  }
+  const CT_G uint8_t* nz = N.nz + (int64_t)j * T->nGran;
+  for (int p = threadIdx.x; p < limit0; p += BLOCK) {
+    const int gid = T->idx0[p];
+    sh.gidx[p] = (uint16_t)gid;
+    sh.nz[p] = nz[gid];
+  }
+  __syncthreads();
+  const int st = finalize_update(J, sh, true, 0);
+  if (st == ST_OK) {
+    unsigned long long cnt[3] = {0, 0, 0};
+    const int lim = s->limit;
+    const CT_G int32_t* idx = s->idx[s->cur];
+    for (int q = wave_id(); q < T->D; q += WAVES) filter_word(a, J, q, 0, lim, idx, cnt);
+    add_filter_stats(s, cnt);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    if (I.nrows && (I.status == ST_OK || I.status == ST_FAIL))
+      atomicAdd(&s->stats[S_GRAN_ROWS], (unsigned long long)limit0 * (unsigned long long)I.nrows);
+    item_fence(J);
+    publish_status(J, st);
+  }
+}
+
 // Device-clock duration of a launch: first workgroup start to last end.
 __device__ void clock_begin(const KArgs& a) {
   if (a.clock && threadIdx.x == 0) atomicMin(&a.clock[0], wall_clock64());
@@ -1100,6 +1256,18 @@ hipError_t launch_model_round(const ModelDesc& M, const KArgs& a, int grid, hipS
 
 // M.pool holds the input; leaves pool = input AND every table's domains and
 // the dirty flags of the first round.
+int nodes_max_rows() { return NODES_MAX_ROWS; }
+int nodes_per_group() { return NODES_PER_GROUP; }
+
+hipError_t launch_nodes(const KArgs& a, const NodesDesc& N, int nGran, int rows, hipStream_t stream) {
+  hipLaunchKernelGGL(nodes_prep_kernel, dim3(N.nJobs), dim3(BLOCK), 0, stream, a, N);
+  const int blocks = (nGran + XCDS - 1) / XCDS * XCDS * N.groups;
+  hipLaunchKernelGGL(nodes_update_kernel, dim3(blocks), dim3(BLOCK), (size_t)rows * GW * sizeof(uint64_t),
+                     stream, a, N);
+  hipLaunchKernelGGL(nodes_finish_kernel, dim3(N.nJobs), dim3(BLOCK), 0, stream, a, N);
+  return hipGetLastError();
+}
+
 hipError_t launch_model_seed(const ModelDesc& M, hipStream_t stream) {
   hipLaunchKernelGGL(model_copy_kernel, dim3(64), dim3(BLOCK), 0, stream, (uint64_t*)M.poolNext,
                      (const uint64_t*)M.pool, M.poolWords);

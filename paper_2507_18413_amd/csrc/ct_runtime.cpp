@@ -27,6 +27,9 @@ int propagate_items_per_job_update(int nGran);
 int propagate_items_per_job_filter(int D);
 int propagate_max_grid();
 hipError_t launch_propagate(const KArgs& a, int grid, hipStream_t stream);
+int nodes_max_rows();
+int nodes_per_group();
+hipError_t launch_nodes(const KArgs& a, const NodesDesc& N, int nGran, int rows, hipStream_t stream);
 hipError_t launch_build_supports(const int32_t* tuples, int64_t t, int n, const VarDesc* vars,
                                  const int32_t* lo, uint64_t* S, int64_t stride, int64_t W,
                                  hipStream_t stream);
@@ -86,6 +89,9 @@ struct QueueCtx {
   int32_t* pOff = nullptr;
   size_t capPinned = 0;
   hipEvent_t staged = nullptr;
+  // search-node schedule scratch (NodeInfo | row lists | granule flags)
+  void* dNodes = nullptr;
+  size_t capNodes = 0;
 };
 
 int queue_init(QueueCtx& q) {
@@ -104,6 +110,7 @@ void queue_free(QueueCtx& q) {
   if (q.dOff) (void)hipFree(q.dOff);
   if (q.pJobs) (void)hipHostFree(q.pJobs);
   if (q.pOff) (void)hipHostFree(q.pOff);
+  if (q.dNodes) (void)hipFree(q.dNodes);
   if (q.staged) (void)hipEventDestroy(q.staged);
   q = QueueCtx();
 }
@@ -212,10 +219,30 @@ int check_poison(const ct_table* T) {
 constexpr int SOLO_MAX_GRAN = 4;      // tables up to 16,384 tuples run solo
 constexpr int SOLO_MIN_BATCH = 256;   // batches this large run every job solo
 
+constexpr int NODES_MIN_BATCH = 64;   // AUTO: batches of root resets this large run granule-major
+
 bool use_solo(const ct_table* T, int nJobs) {
   if (T->cfg.schedule == CT_SCHED_SOLO) return true;
   if (T->cfg.schedule == CT_SCHED_SPLIT) return false;
   return T->nGran <= SOLO_MAX_GRAN || nJobs >= SOLO_MIN_BATCH;
+}
+
+// The search-node schedule takes a batch whose jobs all reset slots of one
+// table to the root and propagate (the slots are distinct: checked before).
+bool use_nodes(const ct_job* jobs, int n) {
+  const ct_table* T = jobs[0].table;
+  if (T->cfg.schedule != CT_SCHED_NODES && (T->cfg.schedule != CT_SCHED_AUTO || n < NODES_MIN_BATCH))
+    return false;
+  if (T->rows > nodes_max_rows() || T->nGran > MAX_GRAN) return false;
+  // the update kernel's LDS tile holds one granule of every support row
+  int dev = 0, lds = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+    return false;
+  if ((size_t)T->rows * GW * sizeof(uint64_t) > (size_t)lds) return false;
+  for (int j = 0; j < n; ++j)
+    if (jobs[j].table != T || jobs[j].flags != (CT_JOB_PROPAGATE | CT_JOB_FROM_ROOT)) return false;
+  return true;
 }
 
 // Fill item counts of a job: solo = one update item that does everything.
@@ -522,7 +549,7 @@ int ct_create(const int32_t* tuples, int64_t n_tuples, int32_t arity, const int3
   T->cfg.max_depth = 256;
   T->cfg.schedule = CT_SCHED_AUTO;
   if (cfg) {
-    if (cfg->schedule < 0 || cfg->schedule > 2) {
+    if (cfg->schedule < 0 || cfg->schedule > 3) {
       delete T;
       return fail(CT_E_INVALID, "schedule %d", cfg->schedule);
     }
@@ -826,6 +853,21 @@ int ct_propagate_batch(const ct_job* jobs, int32_t n_jobs, void* stream_v, int32
       q = it->second;
     }
   }
+  const bool nodes = use_nodes(jobs, n_jobs);
+  if (nodes) {
+    const ct_table* T = jobs[0].table;
+    const size_t need = align256(sizeof(NodeInfo) * n_jobs) +
+                        align256(sizeof(uint16_t) * (size_t)n_jobs * T->rows) +
+                        align256((size_t)n_jobs * T->nGran);
+    if (q->capNodes < need) {
+      HIPCHK(hipStreamSynchronize(stream));
+      if (q->dNodes) (void)hipFree(q->dNodes);
+      q->dNodes = nullptr;
+      q->capNodes = 0;
+      HIPCHK(hipMalloc(&q->dNodes, need));
+      q->capNodes = need;
+    }
+  }
   // job descriptors
   q->hJobs.resize(n_jobs);
   std::vector<int32_t> updOff(n_jobs + 1, 0), filtOff(n_jobs + 1, 0), prep;
@@ -869,7 +911,7 @@ int ct_propagate_batch(const ct_job* jobs, int32_t n_jobs, void* stream_v, int32
       J.depthAfter = S.depth;
     }
     S.failed = 2;
-    if ((J.flags & JF_PROPAGATE) && use_solo(T, n_jobs)) J.flags |= JF_SOLO;
+    if ((J.flags & JF_PROPAGATE) && !nodes && use_solo(T, n_jobs)) J.flags |= JF_SOLO;
     job_counts(T, J);
     updOff[j + 1] = updOff[j] + J.nUpd;
     filtOff[j + 1] = filtOff[j] + J.nFilt;
@@ -910,6 +952,19 @@ int ct_propagate_batch(const ct_job* jobs, int32_t n_jobs, void* stream_v, int32
   a.nFilt = filtOff[n_jobs];
   a.queue = q->queue;
   a.hostErr = q->hostErr;
+  if (nodes) {
+    const ct_table* T = jobs[0].table;
+    NodesDesc N{};
+    N.nJobs = n_jobs;
+    N.rowsCap = T->rows;
+    N.groups = (n_jobs + nodes_per_group() - 1) / nodes_per_group();
+    N.jobs = q->dJobs;
+    N.info = (NodeInfo*)q->dNodes;
+    N.rows = (uint16_t*)((char*)q->dNodes + align256(sizeof(NodeInfo) * n_jobs));
+    N.nz = (uint8_t*)((char*)N.rows + align256(sizeof(uint16_t) * (size_t)n_jobs * T->rows));
+    HIPCHK(launch_nodes(a, N, T->nGran, T->rows, stream));
+    return CT_OK;
+  }
   const int total = a.nPrep + a.nUpd + a.nFilt;
   if (total > 0) HIPCHK(launch_propagate(a, std::min(total, propagate_max_grid()), stream));
   return CT_OK;

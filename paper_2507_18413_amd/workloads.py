@@ -344,6 +344,8 @@ def _distinct_zipf_mixed(rng, dsizes, s, t):
         c[-1] = 1.0
         cdfs.append(c)
     space = int(np.prod([int(x) for x in dsizes], dtype=object))
+    if t > space:
+        raise ValueError("more distinct tuples requested than the domain product holds")
     if space >= _CODE_LIMIT:
         def draw(m):
             u = rng.random((m, n))

@@ -259,7 +259,7 @@ def from_dev(t):
     return t.cpu().numpy().view(np.uint64)
 
 
-@pytest.mark.parametrize("schedule", [ct.SCHED_AUTO, ct.SCHED_SPLIT])
+@pytest.mark.parametrize("schedule", [ct.SCHED_AUTO, ct.SCHED_SPLIT, ct.SCHED_NODES])
 def test_batch_from_root_nodes_vs_oracle(schedule):
     import torch
     say("batch: FROM_ROOT search nodes, Zipf table 60k tuples, 256 nodes, schedule", schedule)
@@ -294,6 +294,71 @@ def test_batch_from_root_nodes_vs_oracle(schedule):
     ct.propagate_batch(jobs[:64], status[:64])
     torch.cuda.synchronize()
     assert (from_dev(dout[:64]) == got_dom[:64]).all()
+
+
+@pytest.mark.parametrize("n_nodes", [1, 100, 200])
+def test_batch_nodes_schedule_edge_cases(n_nodes):
+    """Granule-major node schedule on a table with multi-word domains, a
+    ragged last word and a granule count that is not a multiple of 8, with
+    nodes that fail (an empty domain, no surviving tuple), nodes equal to the
+    root, and rejected inputs (stray bits, values outside the root domains)."""
+    import torch
+    say("batch nodes schedule: edge cases,", n_nodes, "nodes")
+    rng = W.rng_for(11, 204, n_nodes)
+    ds = np.array([130, 3, 65, 1, 40], np.int32)
+    lo = np.array([-7, 0, 100, 5, 0], np.int32)
+    t = 64 * 64 * 9 + 37
+    hi = ds.copy()
+    hi[0] -= 10                               # the last 10 values of x0 have no support
+    tup = np.stack([rng.integers(lo[i], lo[i] + hi[i], size=t) for i in range(5)], 1).astype(np.int32)
+    G, Ot = pair(tup, lo, ds, schedule=ct.SCHED_NODES)
+    lay = W.DomLayout(ds, lo)
+    root = Ot.domains()
+    nodes = np.empty((n_nodes, lay.D), np.uint64)
+    for k in range(n_nodes):
+        kind = k % 10
+        if kind == 0:
+            nodes[k] = root
+        elif kind == 1:
+            d = root.copy()
+            for a in lay.values(root, 3):
+                lay.clear(d, 3, int(a))      # empty domain
+            nodes[k] = d
+        elif kind == 2:
+            d = root.copy()
+            d[lay.D - 1] |= np.uint64(1) << np.uint64(63)  # stray bit past the last value
+            nodes[k] = d
+        elif kind == 3:
+            d = lay.full()                    # values the root pruned
+            nodes[k] = d
+        else:
+            nodes[k] = random_subset(rng, lay, root, float(rng.uniform(0.05, 0.97)))
+    first = G.slots_alloc(n_nodes, max_depth=0)
+    din = to_dev(nodes)
+    dout = torch.zeros_like(din)
+    cts = torch.zeros((n_nodes, G.W), dtype=torch.int64, device="cuda")
+    status = torch.full((n_nodes,), 99, dtype=torch.int32, device="cuda")
+    jobs = [dict(table=G, slot=first + k, flags=ct.JOB_PROPAGATE | ct.JOB_FROM_ROOT,
+                 dom_in=din[k], dom_out=dout[k], ct_out=cts[k]) for k in range(n_nodes)]
+    for rep in range(2):
+        ct.propagate_batch(jobs, status)
+        torch.cuda.synchronize()
+        st = status.cpu().numpy()
+        got_dom, got_ct = from_dev(dout), from_dev(cts)
+        for k in range(n_nodes):
+            Ot.push()
+            os_, od, oc = Ot.propagate(nodes[k], want_ct=True)
+            Ot.pop()
+            assert st[k] == os_, (rep, k)
+            if os_ == O.OK:
+                assert (got_dom[k] == od).all(), (rep, k)
+                assert (got_ct[k] == oc).all(), (rep, k)
+                gd, gc = G.state(first + k)
+                assert (gd == od).all() and (gc == oc).all(), (rep, k)
+            elif os_ == O.FAIL:
+                assert not got_ct[k].any(), (rep, k)
+        if n_nodes > 3:
+            assert {int(x) for x in st} >= {ct.OK, ct.FAIL, ct.E_INVALID, ct.E_NOT_SUBSET}
 
 
 @pytest.mark.parametrize("schedule", [ct.SCHED_SOLO, ct.SCHED_SPLIT])

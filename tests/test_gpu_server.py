@@ -24,7 +24,7 @@ def small_tables(seed, n):
     for c in range(n):
         k = int(rng.integers(3, 6))
         ds = rng.integers(8, 40, size=k)
-        t = int(rng.integers(500, 30_000))
+        t = min(int(rng.integers(500, 30_000)), int(np.prod(ds)) // 2)
         tup = (W.distinct_uniform_tuples(rng, ds, t) if c % 2 == 0
                else W._distinct_zipf_mixed(rng, ds.astype(np.int64), 1.1, t))
         out.append(W.TableSpec(tup, np.zeros(k, np.int32), ds.astype(np.int32)))

@@ -1,5 +1,6 @@
 """Seeded generators: determinism and the shapes the workloads promise."""
 import numpy as np
+import pytest
 
 from paper_2507_18413_amd import workloads as W
 
@@ -57,3 +58,14 @@ def test_removal_pickers_only_remove():
     new = W.pick_small_removal(rng, lay1, d1)
     removed = sum(lay1.count(d1, i) - lay1.count(new, i) for i in range(3))
     assert removed in (1, 2)
+
+
+def test_distinct_generators_reject_more_tuples_than_the_space():
+    rng = W.rng_for(1, 900, 0)
+    with pytest.raises(ValueError):
+        W.distinct_uniform_tuples(rng, [3, 4], 13)
+    with pytest.raises(ValueError):
+        W.distinct_zipf_tuples(rng, 2, 3, 1.1, 10)
+    with pytest.raises(ValueError):
+        W._distinct_zipf_mixed(rng, np.array([27, 14, 8], np.int64), 1.1, 3025)
+    assert W._distinct_zipf_mixed(rng, np.array([3, 4], np.int64), 1.1, 12).shape == (12, 2)
