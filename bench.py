@@ -37,7 +37,7 @@ def parse():
     p.add_argument("--warmup", type=int, default=2)
     p.add_argument("--seed", type=int, default=None)
     p.add_argument("--calls", type=int, default=1000)
-    p.add_argument("--cpu-seconds", type=float, default=10.0)
+    p.add_argument("--cpu-seconds", type=float, default=12.0)
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--nodes", type=int, default=4096)
     p.add_argument("--no-nodes", action="store_true")
@@ -118,7 +118,7 @@ def cpu_baseline(spec, script, seconds):
                 props += 1
         passes += 1
         el = time.perf_counter() - t0
-        if el >= seconds or passes >= 50:
+        if el >= seconds:
             break
     while o.depth > 0:
         o.pop()
@@ -143,8 +143,8 @@ def nodes_leg(seed, n_nodes, reps, warmup, schedule=0):
     din = torch.from_numpy(nodes.view(np.int64)).cuda()
     dout = torch.zeros_like(din)
     status = torch.zeros(n_nodes, dtype=torch.int32, device="cuda")
-    jobs = [dict(table=table, slot=first + k, flags=ct.JOB_PROPAGATE | ct.JOB_FROM_ROOT,
-                 dom_in=din[k], dom_out=dout[k]) for k in range(n_nodes)]
+    jobs = ct.Batch([dict(table=table, slot=first + k, flags=ct.JOB_PROPAGATE | ct.JOB_FROM_ROOT,
+                          dom_in=din[k], dom_out=dout[k]) for k in range(n_nodes)])
     stream = torch.cuda.current_stream()
     for _ in range(warmup):
         ct.propagate_batch(jobs, status, stream)
@@ -492,6 +492,11 @@ def serve_leg(tables_spec, seed, rate, n_requests, n_searches, budget, sample_ch
     return out
 
 
+def note(msg):
+    """Progress on stderr (the JSON result line is the only stdout output)."""
+    print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -508,7 +513,9 @@ def main():
     if not args.no_serve:
         # generated before the GPU is initialised: the pool's workers are
         # fresh interpreters
+        note("generating the serving mix (300 tables)")
         serve_spec = W.config5_tables(seed, workers=min(16, os.cpu_count() or 1))
+    note("plain leg: building the 200,000-tuple table")
     torch.cuda.set_device(0)
     if args.calibration_copy:
         n = args.calibration_copy * (1 << 20) // 8
@@ -586,15 +593,20 @@ def main():
                      "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": traffic,
                      "bytes_per_launch": round(per_launch_bytes, 1)},
     }
+    note(f"plain leg done: {value:.0f} propagations/s")
     if not args.no_nodes:
+        note("search-node leg")
         out["batched_nodes"] = nodes_leg(seed, args.nodes, max(1, args.steps), 1)
     if not args.no_model:
+        note("multi-table model leg")
         out["batched_model"] = model_leg(seed, args.model_steps, 20, not args.no_cpu_baseline)
     if serve_spec is not None:
+        note("serving leg")
         out["serving"] = serve_leg(serve_spec, seed, args.serve_rate, args.serve_requests, 512,
                                    args.serve_budget, 0 if args.no_cpu_baseline else 8)
         del serve_spec
     if not args.no_cpu_baseline:
+        note("oracle on the host cores")
         cps, cprops, cel, passes = cpu_baseline(spec, script, args.cpu_seconds)
         out["cpu_baseline"] = {"value": round(cps, 1), "unit": "propagations/s", "cores": 1, "kind": "oracle",
                                "sample": f"{passes} replays of the same {n_calls}-call script "

@@ -139,7 +139,7 @@ struct NodeInfo {
 };
 
 struct NodesDesc {
-  int32_t nJobs, rowsCap, groups, pad;
+  int32_t nJobs, rowsCap, groups, groupSize;
   const CT_G DevJob* jobs;
   CT_G NodeInfo* info;     // nJobs
   CT_G uint16_t* rows;     // nJobs x rowsCap: row | 0x8000 (segment start) | 0x4000 (incremental)

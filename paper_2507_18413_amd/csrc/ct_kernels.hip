@@ -623,34 +623,52 @@ __device__ void filter_word(const KArgs& a, const DevJob& J, int q, int noop, in
       cnt[2] += __popcll(__ballot(mine));
       miss = __ballot(mine && !found);
     }
-    while (miss) {
-      const int l = __ffsll(miss) - 1;
-      miss &= miss - 1;
-      const int r = rowBase + l;
-      const CT_G uint64_t* row = T->S + (int64_t)r * stride;
-      int found = -1;
-      for (int p = 0; p < lim && found < 0; p += 4) {
-        uint64_t x[4];
-        int gg[4];
+    // the values still without a support scan the active granules in index
+    // order together: each step loads 4 currTable granules once and tests
+    // them against the rows of up to 3 values at a time; a value leaves the
+    // scan at its first supported word (its new residue)
+    uint64_t todo = miss;
+    for (int p = 0; p < lim && todo; p += 4) {
+      int gg[4];
+      uint64_t c[4];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          gg[j] = (p + j < lim) ? idx[p + j] : -1;
-          const int64_t w = (int64_t)gg[j] * GW + lane;
-          x[j] = gg[j] >= 0 ? (s->ct[w] & row[w]) : 0ull;
-        }
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          const unsigned long long bm = __ballot(x[j] != 0ull);
-          if (found < 0 && bm) found = gg[j] * GW + (__ffsll(bm) - 1);
-        }
-        cnt[2] += min(4, lim - p);
+      for (int j = 0; j < 4; ++j) {
+        gg[j] = (p + j < lim) ? idx[p + j] : -1;
+        c[j] = gg[j] >= 0 ? s->ct[(int64_t)gg[j] * GW + lane] : 0ull;
       }
-      if (found >= 0) {
-        if (lane == 0) s->res[r] = found;
-      } else {
-        unsup |= 1ull << l;
+      cnt[2] += (unsigned long long)min(4, lim - p) * (unsigned long long)__popcll(todo);
+      uint64_t t = todo;
+      while (t) {
+        int ls[3];
+#pragma unroll
+        for (int v = 0; v < 3; ++v) {
+          ls[v] = t ? __ffsll((unsigned long long)t) - 1 : -1;
+          t &= t - 1;
+        }
+        uint64_t x[3][4];
+#pragma unroll
+        for (int v = 0; v < 3; ++v) {
+          const CT_G uint64_t* row = T->S + (int64_t)(rowBase + max(ls[v], 0)) * stride;
+#pragma unroll
+          for (int j = 0; j < 4; ++j)
+            x[v][j] = (ls[v] >= 0 && gg[j] >= 0) ? (c[j] & row[(int64_t)gg[j] * GW + lane]) : 0ull;
+        }
+#pragma unroll
+        for (int v = 0; v < 3; ++v) {
+          if (ls[v] < 0) continue;
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            const unsigned long long bm = __ballot(x[v][j] != 0ull);
+            if (bm) {
+              if (lane == 0) s->res[rowBase + ls[v]] = gg[j] * GW + (__ffsll(bm) - 1);
+              todo &= ~(1ull << ls[v]);
+              break;
+            }
+          }
+        }
       }
     }
+    unsup = todo;
     dout = din & ~unsup;
   }
   if (lane == 0) {
@@ -794,8 +812,9 @@ __device__ void do_solo(const KArgs& a, const DevJob& J, Shared& sh) {
 //   nodes_update: one workgroup per (granule, node group): Alg. 2 from LDS
 //   nodes_finish: one workgroup per node: partition, FAIL, Alg. 3, status
 // ---------------------------------------------------------------------------
-constexpr int NODES_PER_GROUP = 64;
 constexpr int NODES_MAX_ROWS = 256;  // LDS tile of the update kernel: rows x 512 B
+constexpr int NODES_BLOCK = 512;     // update kernel: 8 waves
+constexpr int NODES_WAVES = NODES_BLOCK / WAVE;
 constexpr int XCDS = 8;
 
 __global__ void __launch_bounds__(BLOCK) nodes_prep_kernel(KArgs a, NodesDesc N) {
@@ -833,41 +852,83 @@ __global__ void __launch_bounds__(BLOCK) nodes_prep_kernel(KArgs a, NodesDesc N)
   }
 }
 
-// Block b of the launch runs on XCD b % 8 (round-robin dispatch); the blocks
-// of one granule are mapped to one XCD so that its L2 serves the tile to all
-// node groups after one fetch from HBM.
-__global__ void __launch_bounds__(BLOCK) nodes_update_kernel(KArgs a, NodesDesc N) {
-  extern __shared__ uint64_t tile[];
+// One workgroup per (granule, group of nodes).  LDS: the granule of every
+// support row (rows x 64 words), then the group's NodeInfo records and row
+// lists, all staged before any node is evaluated, so a node costs only LDS
+// reads and its currTable store.  Block b runs on XCD b % 8 (round-robin
+// dispatch): the blocks of one granule are mapped to one XCD so that its L2
+// serves the granule to every group after one fetch from HBM.
+__global__ void __launch_bounds__(NODES_BLOCK) nodes_update_kernel(KArgs a, NodesDesc N) {
+  extern __shared__ uint64_t lds[];
   const int b = blockIdx.x;
   const int xcd = b % XCDS, k = b / XCDS;
   const int g = (k / N.groups) * XCDS + xcd;
   const int group = k % N.groups;
   const TabDesc* T = N.jobs[0].tab;
   if (g >= T->nGran) return;
-  const int rows = T->rows;
+  const int rows = T->rows, cap = N.rowsCap;
   const int64_t stride = T->stride, W = T->W;
   const int lane = lane_id();
-  const CT_G uint64_t* S = T->S + (int64_t)g * GW;
-  for (int i = threadIdx.x; i < rows * GW; i += BLOCK) tile[i] = S[(int64_t)(i / GW) * stride + (i % GW)];
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
+  const int node0 = group * N.groupSize;
+  const int nG = min(N.groupSize, N.nJobs - node0);
+  uint64_t* tile = lds;
+  NodeInfo* info = (NodeInfo*)(lds + (size_t)rows * GW);
+  uint16_t* lists = (uint16_t*)(info + N.groupSize);
+
+  // staging: every load of a pass is issued before its LDS stores, so a
+  // thread has up to STAGE loads in flight (a row granule is 512 B, one
+  // 8-byte word per lane)
+  {
+    constexpr int STAGE = 16;
+    const CT_G uint64_t* S = T->S + (int64_t)g * GW;
+    // the group's NodeInfo records and row lists are contiguous in memory
+    const CT_G uint64_t* srcInfo = (const CT_G uint64_t*)(N.info + node0);
+    const CT_G uint64_t* srcList = (const CT_G uint64_t*)(N.rows + (int64_t)node0 * cap);
+    const int nTile = rows * GW;
+    const int nInfo = nG * (int)(sizeof(NodeInfo) / 8);
+    const int nList = nG * cap / 4;   // cap is a multiple of 4 entries
+    uint64_t* dInfo = (uint64_t*)info;
+    uint64_t* dList = (uint64_t*)lists;
+    const int total = nTile + nInfo + nList;
+    for (int base = 0; base < total; base += STAGE * NODES_BLOCK) {
+      uint64_t v[STAGE];
+#pragma unroll
+      for (int u = 0; u < STAGE; ++u) {
+        const int i = base + u * NODES_BLOCK + (int)threadIdx.x;
+        if (i < nTile) v[u] = S[(int64_t)(i / GW) * stride + (i % GW)];
+        else if (i < nTile + nInfo) v[u] = srcInfo[i - nTile];
+        else if (i < total) v[u] = srcList[i - nTile - nInfo];
+      }
+#pragma unroll
+      for (int u = 0; u < STAGE; ++u) {
+        const int i = base + u * NODES_BLOCK + (int)threadIdx.x;
+        if (i < nTile) tile[i] = v[u];
+        else if (i < nTile + nInfo) dInfo[i - nTile] = v[u];
+        else if (i < total) dList[i - nTile - nInfo] = v[u];
+      }
+    }
+  }
   const int64_t w = (int64_t)g * GW + lane;
   const uint64_t root = T->ct0[w];
   __syncthreads();
-  const int node0 = group * NODES_PER_GROUP;
-  const int nEnd = min(node0 + NODES_PER_GROUP, N.nJobs);
-  const int wv = __builtin_amdgcn_readfirstlane(wave_id());
-  for (int p = node0 + wv; p < nEnd; p += WAVES) {
-    const NodeInfo I = N.info[p];
-    if (I.status != ST_OK && I.status != ST_FAIL) continue;  // rejected input: nothing changes
+
+  for (int p = wv; p < nG; p += NODES_WAVES) {
+    // the record is the same for every lane: keep it in scalar registers so
+    // that the row loop below is uniform control flow
+    const int status = __builtin_amdgcn_readfirstlane(info[p].status);
+    const int nrows = __builtin_amdgcn_readfirstlane(info[p].nrows);
+    if (status != ST_OK && status != ST_FAIL) continue;  // rejected input: nothing changes
     uint64_t m = 0ull;
-    if (I.status == ST_OK) {
-      const CT_G uint16_t* rl = N.rows + (int64_t)p * N.rowsCap;
+    if (status == ST_OK) {
+      const uint16_t* rl = lists + p * cap;
       uint64_t acc = 0ull;
       bool inc = false, open = false;
       m = ~0ull;
-      for (int k0 = 0; k0 < I.nrows; k0 += WAVE) {
+      for (int k0 = 0; k0 < nrows; k0 += WAVE) {
         // 64 entries of the row list, one per lane, then read lane by lane
-        const int mine = (k0 + lane < I.nrows) ? (int)rl[k0 + lane] : 0;
-        const int cnt = min(WAVE, I.nrows - k0);
+        const int mine = (k0 + lane < nrows) ? (int)rl[k0 + lane] : 0;
+        const int cnt = min(WAVE, nrows - k0);
         for (int u0 = 0; u0 < cnt; u0 += ROW_UNROLL) {
           int e[ROW_UNROLL];
           uint64_t v[ROW_UNROLL];
@@ -892,48 +953,97 @@ __global__ void __launch_bounds__(BLOCK) nodes_update_kernel(KArgs a, NodesDesc 
       if (open) m &= inc ? ~acc : acc;
     }
     const uint64_t nw = root & m;
-    I.ct[w] = nw;
-    if (I.ct_out && w < W) I.ct_out[w] = nw;
+    CT_G uint64_t* ct = info[p].ct;
+    CT_G uint64_t* ctOut = info[p].ct_out;
+    ct[w] = nw;
+    if (ctOut && w < W) ctOut[w] = nw;
     const bool nz = __ballot(nw != 0ull) != 0ull;
-    if (lane == 0) N.nz[(int64_t)p * T->nGran + g] = nz ? 1 : 0;
+    if (lane == 0) N.nz[(int64_t)(node0 + p) * T->nGran + g] = nz ? 1 : 0;
   }
 }
 
+// One workgroup per node: wave 0 partitions the root's granule list by the
+// non-zero flags (survivors first, stable) and detects FAIL (Alg. 1); then
+// the four waves run filterDomains (Alg. 3) on interleaved domain words.
 __global__ void __launch_bounds__(BLOCK) nodes_finish_kernel(KArgs a, NodesDesc N) {
-  __shared__ Shared sh;
+  __shared__ int32_t shSurv;
   const int j = blockIdx.x;
+  const int lane = lane_id();
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
   const DevJob J = N.jobs[j];
   const TabDesc* T = J.tab;
   SlotDesc* s = J.slot;
-  const NodeInfo I = N.info[j];
-  const int limit0 = T->limit0;
-  if (threadIdx.x == 0) {
-    // the prologue's FAIL (an empty domain) shows up as no surviving granule
-    sh.status = I.status == ST_FAIL ? ST_OK : I.status;
-    sh.noop = 0;
-    sh.limit = limit0;
-    sh.nrows = I.nrows;
-    sh.trailTop = 0;
+  const int st0 = N.info[j].status;
+  const int nrows = N.info[j].nrows;
+  const bool run = st0 == ST_OK || st0 == ST_FAIL;
+  if (run && wv == 0) {
+    const int limit0 = T->limit0, nGran = T->nGran;
+    const CT_G uint8_t* nz = N.nz + (int64_t)j * nGran;
+    const CT_G int32_t* src = T->idx0;
+    CT_G int32_t* dst = s->idx[0];
+    const uint64_t below = (1ull << lane) - 1ull;
+    // granule ids and flags of 4 x 64 positions per round trip
+    int nSurv = 0;
+    for (int p0 = 0; p0 < limit0; p0 += 4 * WAVE) {
+      int gid[4];
+      bool f[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int p = p0 + u * WAVE + lane;
+        gid[u] = p < limit0 ? src[p] : -1;
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) f[u] = gid[u] >= 0 && nz[gid[u]];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) nSurv += __popcll(__ballot(f[u]));
+    }
+    int sv = 0, zr = nSurv;
+    for (int p0 = 0; p0 < limit0; p0 += 4 * WAVE) {
+      int gid[4];
+      bool f[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int p = p0 + u * WAVE + lane;
+        gid[u] = p < limit0 ? src[p] : -1;
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) f[u] = gid[u] >= 0 && nz[gid[u]];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const uint64_t bs = __ballot(f[u]), bz = __ballot(gid[u] >= 0 && !f[u]);
+        if (f[u]) dst[sv + __popcll(bs & below)] = gid[u];
+        else if (gid[u] >= 0) dst[zr + __popcll(bz & below)] = gid[u];
+        sv += __popcll(bs);
+        zr += __popcll(bz);
+      }
+    }
+    for (int p = limit0 + lane; p < nGran; p += WAVE) dst[p] = src[p];
+    if (lane == 0) {
+      shSurv = nSurv;
+      s->cur = 0;
+      s->limit = nSurv;
+      s->depth = 0;
+      s->trailTop = 0;
+      s->serial = J.serialBase;
+      s->failed = nSurv ? 0 : 1;
+      atomicAdd(&s->stats[S_JOBS], 1ull);
+      atomicAdd(&s->stats[S_GRAN_IN], (unsigned long long)limit0);
+      atomicAdd(&s->stats[S_ROWS], (unsigned long long)nrows);
+      if (nrows) atomicAdd(&s->stats[S_GRAN_ROWS], (unsigned long long)limit0 * (unsigned long long)nrows);
+    }
   }
-  const CT_G uint8_t* nz = N.nz + (int64_t)j * T->nGran;
-  for (int p = threadIdx.x; p < limit0; p += BLOCK) {
-    const int gid = T->idx0[p];
-    sh.gidx[p] = (uint16_t)gid;
-    sh.nz[p] = nz[gid];
-  }
-  __syncthreads();
-  const int st = finalize_update(J, sh, true, 0);
+  __syncthreads();  // the partition is visible to the workgroup
+  const int nSurv = run ? shSurv : 0;
+  const int st = run ? (nSurv ? ST_OK : ST_FAIL) : st0;
   if (st == ST_OK) {
     unsigned long long cnt[3] = {0, 0, 0};
-    const int lim = s->limit;
-    const CT_G int32_t* idx = s->idx[s->cur];
-    for (int q = wave_id(); q < T->D; q += WAVES) filter_word(a, J, q, 0, lim, idx, cnt);
+    for (int q = wv; q < T->D; q += WAVES) filter_word(a, J, q, 0, nSurv, s->idx[0], cnt);
     add_filter_stats(s, cnt);
   }
   __syncthreads();
   if (threadIdx.x == 0) {
-    if (I.nrows && (I.status == ST_OK || I.status == ST_FAIL))
-      atomicAdd(&s->stats[S_GRAN_ROWS], (unsigned long long)limit0 * (unsigned long long)I.nrows);
+    s->status = st;
+    s->pad2 = 0;
     item_fence(J);
     publish_status(J, st);
   }
@@ -1257,13 +1367,19 @@ hipError_t launch_model_round(const ModelDesc& M, const KArgs& a, int grid, hipS
 // M.pool holds the input; leaves pool = input AND every table's domains and
 // the dirty flags of the first round.
 int nodes_max_rows() { return NODES_MAX_ROWS; }
-int nodes_per_group() { return NODES_PER_GROUP; }
+
+// Dynamic LDS of the update kernel for a table of `rows` support rows and
+// groups of `groupSize` nodes with row lists of up to `cap` entries.
+size_t nodes_update_lds(int rows, int groupSize, int cap) {
+  return (size_t)rows * GW * sizeof(uint64_t) + (size_t)groupSize * sizeof(NodeInfo) +
+         (((size_t)groupSize * cap * sizeof(uint16_t) + 7) & ~(size_t)7);
+}
 
 hipError_t launch_nodes(const KArgs& a, const NodesDesc& N, int nGran, int rows, hipStream_t stream) {
   hipLaunchKernelGGL(nodes_prep_kernel, dim3(N.nJobs), dim3(BLOCK), 0, stream, a, N);
   const int blocks = (nGran + XCDS - 1) / XCDS * XCDS * N.groups;
-  hipLaunchKernelGGL(nodes_update_kernel, dim3(blocks), dim3(BLOCK), (size_t)rows * GW * sizeof(uint64_t),
-                     stream, a, N);
+  hipLaunchKernelGGL(nodes_update_kernel, dim3(blocks), dim3(NODES_BLOCK),
+                     nodes_update_lds(rows, N.groupSize, N.rowsCap), stream, a, N);
   hipLaunchKernelGGL(nodes_finish_kernel, dim3(N.nJobs), dim3(BLOCK), 0, stream, a, N);
   return hipGetLastError();
 }

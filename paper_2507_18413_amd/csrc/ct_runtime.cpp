@@ -28,7 +28,7 @@ int propagate_items_per_job_filter(int D);
 int propagate_max_grid();
 hipError_t launch_propagate(const KArgs& a, int grid, hipStream_t stream);
 int nodes_max_rows();
-int nodes_per_group();
+size_t nodes_update_lds(int rows, int groupSize, int cap);
 hipError_t launch_nodes(const KArgs& a, const NodesDesc& N, int nGran, int rows, hipStream_t stream);
 hipError_t launch_build_supports(const int32_t* tuples, int64_t t, int n, const VarDesc* vars,
                                  const int32_t* lo, uint64_t* S, int64_t stride, int64_t W,
@@ -229,17 +229,36 @@ bool use_solo(const ct_table* T, int nJobs) {
 
 // The search-node schedule takes a batch whose jobs all reset slots of one
 // table to the root and propagate (the slots are distinct: checked before).
+// Largest LDS of one workgroup on the current device (0 if unknown).
+int device_lds() {
+  int dev = 0, lds = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+    return 0;
+  return lds;
+}
+
+// Row-list entries per node: the table's row count rounded up to a multiple
+// of 4 (the update kernel copies lists as 8-byte words).
+int nodes_list_cap(const ct_table* T) { return (T->rows + 3) & ~3; }
+
+// Nodes per group of the update kernel: 64 (two workgroups per CU for tables
+// of up to ~120 rows), fewer when the table's tile leaves less LDS.
+int nodes_group_size(const ct_table* T) {
+  const size_t lds = (size_t)device_lds();
+  int gs = 64;
+  const int cap = nodes_list_cap(T);
+  while (gs > 8 && nodes_update_lds(T->rows, gs, cap) > lds) gs /= 2;
+  return nodes_update_lds(T->rows, gs, cap) <= lds ? gs : 0;
+}
+
 bool use_nodes(const ct_job* jobs, int n) {
   const ct_table* T = jobs[0].table;
   if (T->cfg.schedule != CT_SCHED_NODES && (T->cfg.schedule != CT_SCHED_AUTO || n < NODES_MIN_BATCH))
     return false;
   if (T->rows > nodes_max_rows() || T->nGran > MAX_GRAN) return false;
-  // the update kernel's LDS tile holds one granule of every support row
-  int dev = 0, lds = 0;
-  if (hipGetDevice(&dev) != hipSuccess ||
-      hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
-    return false;
-  if ((size_t)T->rows * GW * sizeof(uint64_t) > (size_t)lds) return false;
+  // the update kernel's LDS holds one granule of every support row
+  if (nodes_group_size(T) == 0) return false;
   for (int j = 0; j < n; ++j)
     if (jobs[j].table != T || jobs[j].flags != (CT_JOB_PROPAGATE | CT_JOB_FROM_ROOT)) return false;
   return true;
@@ -857,7 +876,7 @@ int ct_propagate_batch(const ct_job* jobs, int32_t n_jobs, void* stream_v, int32
   if (nodes) {
     const ct_table* T = jobs[0].table;
     const size_t need = align256(sizeof(NodeInfo) * n_jobs) +
-                        align256(sizeof(uint16_t) * (size_t)n_jobs * T->rows) +
+                        align256(sizeof(uint16_t) * (size_t)n_jobs * nodes_list_cap(T)) +
                         align256((size_t)n_jobs * T->nGran);
     if (q->capNodes < need) {
       HIPCHK(hipStreamSynchronize(stream));
@@ -956,12 +975,13 @@ int ct_propagate_batch(const ct_job* jobs, int32_t n_jobs, void* stream_v, int32
     const ct_table* T = jobs[0].table;
     NodesDesc N{};
     N.nJobs = n_jobs;
-    N.rowsCap = T->rows;
-    N.groups = (n_jobs + nodes_per_group() - 1) / nodes_per_group();
+    N.rowsCap = nodes_list_cap(T);
+    N.groupSize = nodes_group_size(T);
+    N.groups = (n_jobs + N.groupSize - 1) / N.groupSize;
     N.jobs = q->dJobs;
     N.info = (NodeInfo*)q->dNodes;
     N.rows = (uint16_t*)((char*)q->dNodes + align256(sizeof(NodeInfo) * n_jobs));
-    N.nz = (uint8_t*)((char*)N.rows + align256(sizeof(uint16_t) * (size_t)n_jobs * T->rows));
+    N.nz = (uint8_t*)((char*)N.rows + align256(sizeof(uint16_t) * (size_t)n_jobs * N.rowsCap));
     HIPCHK(launch_nodes(a, N, T->nGran, T->rows, stream));
     return CT_OK;
   }

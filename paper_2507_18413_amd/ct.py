@@ -283,26 +283,41 @@ def batch_status(stream=None):
         raise CTError(st, last_error())
 
 
+class Batch:
+    """A job list marshalled once into the ct_job array, for batches that are
+    launched repeatedly with the same jobs (the buffers stay the caller's)."""
+
+    def __init__(self, jobs):
+        jobs = list(jobs)
+        self.n = len(jobs)
+        self.arr = (ct_job * max(1, self.n))()
+        for k, j in enumerate(jobs):
+            a = self.arr[k]
+            a.table = j["table"].h.value
+            a.slot = int(j.get("slot", 0))
+            a.flags = int(j.get("flags", JOB_PROPAGATE))
+            a.n_pop = int(j.get("n_pop", 0))
+            a.n_push = int(j.get("n_push", 0))
+            a.dom_in = _ptr(j.get("dom_in"))
+            a.dom_out = _ptr(j.get("dom_out"))
+            a.ct_out = _ptr(j.get("ct_out"))
+        self._refs = jobs  # keep tensors alive
+
+    def run(self, status_dev, stream=None):
+        s = None if stream is None else (stream if isinstance(stream, int) else stream.cuda_stream)
+        st = lib().ct_propagate_batch(C.cast(self.arr, C.c_void_p), self.n, s, _ptr(status_dev))
+        if st < 0:
+            raise CTError(st, last_error())
+        return st
+
+
 def propagate_batch(jobs, status_dev, stream=None):
-    """jobs: iterable of dicts with keys table, slot, flags, n_pop, n_push,
-    dom_in, dom_out, ct_out (torch tensors or device addresses).
-    status_dev: int32 device tensor (or address) with one entry per job."""
-    jobs = list(jobs)
-    arr = (ct_job * max(1, len(jobs)))()
-    for k, j in enumerate(jobs):
-        arr[k].table = j["table"].h.value
-        arr[k].slot = int(j.get("slot", 0))
-        arr[k].flags = int(j.get("flags", JOB_PROPAGATE))
-        arr[k].n_pop = int(j.get("n_pop", 0))
-        arr[k].n_push = int(j.get("n_push", 0))
-        arr[k].dom_in = _ptr(j.get("dom_in"))
-        arr[k].dom_out = _ptr(j.get("dom_out"))
-        arr[k].ct_out = _ptr(j.get("ct_out"))
-    s = None if stream is None else (stream if isinstance(stream, int) else stream.cuda_stream)
-    st = lib().ct_propagate_batch(C.cast(arr, C.c_void_p), len(jobs), s, _ptr(status_dev))
-    if st < 0:
-        raise CTError(st, last_error())
-    return st
+    """jobs: a Batch, or an iterable of dicts with keys table, slot, flags,
+    n_pop, n_push, dom_in, dom_out, ct_out (torch tensors or device
+    addresses).  status_dev: int32 device tensor (or address) with one entry
+    per job."""
+    b = jobs if isinstance(jobs, Batch) else Batch(jobs)
+    return b.run(status_dev, stream)
 
 
 class Model:
