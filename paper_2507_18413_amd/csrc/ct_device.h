@@ -128,21 +128,29 @@ struct DevJob {
 };
 
 // Granule-major schedule of a batch of search nodes (jobs that all propagate
-// one table from its root state): per node the Alg. 1 prologue's outcome and
-// its row list, encoded for the update kernel, and per (node, granule) a
-// non-zero flag of the new currTable granule.
+// one table from its root state).  Per node: the Alg. 1 prologue's outcome
+// and its row list: one segment per variable of s_val, in variable order,
+// each padded to a multiple of 4 rows with the all-zero row `rows` of the
+// update kernel's tile, its first entry tagged 0x8000 (| 0x4000 when
+// incremental); per (node, granule) the non-zero flag of the new currTable
+// granule.
 struct NodeInfo {
-  int32_t status, nrows;
+  int32_t status, nrows;   // nrows: support rows OR-ed (without padding)
+  int32_t groups, pad;     // groups: list length / 4
   CT_G uint64_t* ct;       // the node's slot currTable
   CT_G uint64_t* ct_out;   // optional copy (W words), may be null
-  int64_t pad;
 };
 
+// A node's record in memory: its NodeInfo, then its row list (listCap
+// entries); records of consecutive nodes are contiguous (nodeWords words).
 struct NodesDesc {
-  int32_t nJobs, rowsCap, groups, groupSize;
+  int32_t nJobs, listCap, nodeWords, groups, groupSize;
+  int32_t rows, nGran, pad;  // the table's (copied: no dependent loads)
+  int64_t stride, W;
+  const CT_G uint64_t* S;
+  const CT_G uint64_t* ct0;
   const CT_G DevJob* jobs;
-  CT_G NodeInfo* info;     // nJobs
-  CT_G uint16_t* rows;     // nJobs x rowsCap: row | 0x8000 (segment start) | 0x4000 (incremental)
+  CT_G uint64_t* nodes;    // nJobs x nodeWords
   CT_G uint8_t* nz;        // nJobs x nGran
 };
 

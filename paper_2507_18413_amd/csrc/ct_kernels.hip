@@ -25,6 +25,8 @@
 // remaining work of the launch is skipped.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "ct_device.h"
 
 namespace ctk {
@@ -817,148 +819,290 @@ constexpr int NODES_BLOCK = 512;     // update kernel: 8 waves
 constexpr int NODES_WAVES = NODES_BLOCK / WAVE;
 constexpr int XCDS = 8;
 
+// Orders this wave's LDS accesses: a wave's LDS operations complete in issue
+// order, so only the compiler has to be kept from moving accesses across.
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Inclusive prefix sum over the 64 lanes.
+__device__ __forceinline__ int wave_scan_incl(int v) {
+  const int lane = lane_id();
+#pragma unroll
+  for (int d = 1; d < WAVE; d <<= 1) {
+    const int u = __shfl_up(v, d);
+    if (lane >= d) v += u;
+  }
+  return v;
+}
+
+// One wave per node: the Alg. 1 prologue of a root reset.  Per variable the
+// number of values of dom_in (|dom|) and of removed root values (|Delta|)
+// decide membership of s_val and the branch of Alg. 2 (incremental when
+// |Delta| < |dom|, or as the table's policy fixes it); the node's row list
+// holds, per variable of s_val, the support rows of Delta or of dom, padded
+// to a multiple of 4 rows with the zero row, the first one tagged.
 __global__ void __launch_bounds__(BLOCK) nodes_prep_kernel(KArgs a, NodesDesc N) {
-  __shared__ Shared sh;
-  const int j = blockIdx.x;
+  __shared__ int32_t shSize[WAVES][MAX_ARITY];
+  __shared__ int32_t shDcnt[WAVES][MAX_ARITY];
+  __shared__ int32_t shSeg[WAVES][MAX_ARITY];  // first list entry | inc << 30, or -1 (not in s_val)
+  __shared__ int32_t shWcnt[WAVES][MAX_D];     // popcount of Delta << 8 | popcount of dom, per word
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
+  const int j = blockIdx.x * WAVES + wv;
+  if (j >= N.nJobs) return;  // no workgroup barrier below
+  const int lane = lane_id();
   const DevJob J = N.jobs[j];
-  prologue(a, J, sh, false);
-  int st = sh.status;
-  // an empty reset segment is an empty domain: no tuple stays valid
-  if (st == ST_OK)
-    for (int g = 0; g < sh.nseg; ++g)
-      if (sh.segEnd[g] == (g ? sh.segEnd[g - 1] : 0)) st = ST_FAIL;
-  const int nrows = (st == ST_OK || st == ST_FAIL) ? sh.nrows : 0;
+  const TabDesc* T = J.tab;
+  const int n = T->n, D = T->D;
+  const uint16_t zeroRow = (uint16_t)T->rows;
+  int32_t* size = shSize[wv];
+  int32_t* dcnt = shDcnt[wv];
+  int32_t* seg = shSeg[wv];
+  int32_t* wcnt = shWcnt[wv];
+  for (int i = lane; i < n; i += WAVE) {
+    size[i] = 0;
+    dcnt[i] = 0;
+  }
+  wave_lds_sync();
+  bool stray = false, notSub = false;
+  for (int q = lane; q < D; q += WAVE) {
+    const uint64_t din = J.dom_in[q];
+    const uint64_t ld = T->dom0[q];
+    const int i = T->wordVar[q];
+    const VarDesc v = T->vars[i];
+    const int used = v.dsize - 64 * (q - v.domOff);
+    if (used < 64 && (din >> used) != 0) stray = true;
+    if (din & ~ld) notSub = true;
+    const int cs = __popcll(din), cd = __popcll(ld & ~din);
+    wcnt[q] = (cd << 8) | cs;
+    atomicAdd(&size[i], cs);
+    atomicAdd(&dcnt[i], cd);
+  }
+  int st = T->rootFailed ? ST_STATE
+           : __ballot(stray) ? ST_INVALID
+           : __ballot(notSub) ? ST_NOT_SUBSET : ST_OK;
+  wave_lds_sync();
+  // segments: variables of s_val in order, each padded to a multiple of 4
+  int total = 0, padded = 0;
+  bool emptyReset = false;
+  const int policy = T->policy;
+  for (int i0 = 0; i0 < n; i0 += WAVE) {
+    const int i = i0 + lane;
+    int cnt = 0, inc = 0;
+    bool in = false;
+    if (i < n) {
+      const int sz = size[i], dc = dcnt[i];
+      in = dc > 0;  // |dom| changed since the root
+      inc = policy == 2 ? 1 : policy == 1 ? 0 : (dc < sz ? 1 : 0);
+      cnt = in ? (inc ? dc : sz) : 0;
+      if (in && cnt == 0) emptyReset = true;  // a reset segment of an empty domain
+    }
+    const int groups = (cnt + 3) >> 2;
+    const int inclRows = wave_scan_incl(cnt);
+    const int inclPad = wave_scan_incl(4 * groups);
+    if (i < n) seg[i] = in ? ((padded + inclPad - 4 * groups) | (inc << 30)) : -1;
+    total += __shfl(inclRows, WAVE - 1);
+    padded += __shfl(inclPad, WAVE - 1);
+  }
+  if (st == ST_OK && __ballot(emptyReset)) st = ST_FAIL;
+  wave_lds_sync();
   if (st == ST_OK) {
-    CT_G uint16_t* out = N.rows + (int64_t)j * N.rowsCap;
-    for (int k = threadIdx.x; k < nrows; k += BLOCK) {
-      // mark the first row of each segment (segments are a few hundred rows
-      // at most: a linear search in LDS)
-      int g = 0;
-      while (sh.segEnd[g] <= k) ++g;
-      const int b = g ? sh.segEnd[g - 1] : 0;
-      uint32_t e = sh.rows[k];
-      if (k == b) e |= 0x8000u | (sh.segInc[g] ? 0x4000u : 0u);
-      out[k] = (uint16_t)e;
+    CT_G uint16_t* out = (CT_G uint16_t*)(N.nodes + (int64_t)j * N.nodeWords + sizeof(NodeInfo) / 8);
+    for (int q = lane; q < D; q += WAVE) {
+      const int i = T->wordVar[q];
+      const int sg = seg[i];
+      if (sg < 0) continue;
+      const int inc = sg >> 30;
+      const int start = sg & 0x3FFFFFFF;
+      const VarDesc v = T->vars[i];
+      int off = start;
+      for (int k = v.domOff; k < q; ++k) off += inc ? (wcnt[k] >> 8) : (wcnt[k] & 0xFF);
+      const uint64_t din = J.dom_in[q];
+      uint64_t bits = inc ? (T->dom0[q] & ~din) : din;
+      const int base = v.rowStart + (q - v.domOff) * 64;
+      while (bits) {
+        const int b = __ffsll((unsigned long long)bits) - 1;
+        bits &= bits - 1;
+        uint32_t e = (uint32_t)(base + b);
+        if (off == start) e |= 0x8000u | (inc ? 0x4000u : 0u);
+        out[off++] = (uint16_t)e;
+      }
+      // the variable's last word pads its segment
+      if (q == v.domOff + v.domWords - 1)
+        while (off & 3) out[off++] = zeroRow;
     }
   }
-  if (threadIdx.x == 0) {
+  if (lane == 0) {
     NodeInfo I;
     I.status = st;
-    I.nrows = nrows;
+    I.nrows = (st == ST_OK || st == ST_FAIL) ? total : 0;
+    I.groups = st == ST_OK ? padded / 4 : 0;
+    I.pad = 0;
     I.ct = J.slot->ct;
     I.ct_out = J.ct_out;
-    I.pad = 0;
-    N.info[j] = I;
+    *(CT_G NodeInfo*)(N.nodes + (int64_t)j * N.nodeWords) = I;
   }
 }
 
-// One workgroup per (granule, group of nodes).  LDS: the granule of every
-// support row (rows x 64 words), then the group's NodeInfo records and row
-// lists, all staged before any node is evaluated, so a node costs only LDS
-// reads and its currTable store.  Block b runs on XCD b % 8 (round-robin
-// dispatch): the blocks of one granule are mapped to one XCD so that its L2
-// serves the granule to every group after one fetch from HBM.
-__global__ void __launch_bounds__(NODES_BLOCK) nodes_update_kernel(KArgs a, NodesDesc N) {
-  extern __shared__ uint64_t lds[];
-  const int b = blockIdx.x;
-  const int xcd = b % XCDS, k = b / XCDS;
-  const int g = (k / N.groups) * XCDS + xcd;
-  const int group = k % N.groups;
-  const TabDesc* T = N.jobs[0].tab;
-  if (g >= T->nGran) return;
-  const int rows = T->rows, cap = N.rowsCap;
-  const int64_t stride = T->stride, W = T->W;
+// A tile is one granule of the table for one group of nodes.  LDS holds the
+// granule of every support row (rows x 64 words) and a zero row, then the
+// group's node records (NodeInfo and row list); a node then costs only LDS
+// reads and its currTable store.  A list is read 4 rows at a time (segments are
+// padded with the zero row): one broadcast LDS read gives the 4 row numbers,
+// 4 independent row reads are OR-ed in, and the next 4 numbers are read while
+// they are in flight.
+//
+// Persistent workgroups (as many as fit at once) walk the tiles: while one
+// tile is evaluated from LDS, the next one's words are already on their way
+// into registers, so the memory latency of staging is hidden.  Block b runs on
+// XCD b % 8 (round-robin dispatch) and takes tiles of the granules g with
+// g % 8 == b % 8, in granule order, so the blocks of an XCD work on the same
+// granule at about the same time and its L2 serves the granule to all of
+// them after one fetch from HBM.
+constexpr int NODES_TPF = 16;  // tile words per thread prefetched (rows <= 128)
+constexpr int NODES_NPF = 8;   // node-record words per thread prefetched
+
+struct NodesTile {
+  int g, node0, nG, nodeTotal;
+  uint64_t root;
+};
+
+__device__ __forceinline__ NodesTile nodes_tile(const NodesDesc& N, int xcd, int t) {
+  NodesTile x;
+  x.g = (t / N.groups) * XCDS + xcd;
+  x.node0 = (t % N.groups) * N.groupSize;
+  x.nG = min(N.groupSize, N.nJobs - x.node0);
+  x.nodeTotal = x.nG * N.nodeWords;
+  x.root = N.ct0[(int64_t)x.g * GW + lane_id()];
+  return x;
+}
+
+// Staging of a tile: thread t holds tile rows t / 64 + 8u (word t % 64) and
+// the words t + 512u of the group's node records.
+__device__ __forceinline__ void nodes_stage_issue(const NodesDesc& N, const NodesTile& x, uint64_t* vt,
+                                                  uint64_t* vn) {
+  const int r0 = (int)threadIdx.x / GW, l = (int)threadIdx.x % GW;
+  const CT_G uint64_t* S = N.S + (int64_t)r0 * N.stride + (int64_t)x.g * GW + l;
+#pragma unroll
+  for (int u = 0; u < NODES_TPF; ++u)
+    if (r0 + 8 * u < N.rows) vt[u] = S[(int64_t)(8 * u) * N.stride];
+  const CT_G uint64_t* src = N.nodes + (int64_t)x.node0 * N.nodeWords + threadIdx.x;
+#pragma unroll
+  for (int u = 0; u < NODES_NPF; ++u)
+    if ((int)threadIdx.x + NODES_BLOCK * u < x.nodeTotal) vn[u] = src[NODES_BLOCK * u];
+}
+
+// Stores the prefetched words (and loads and stores any beyond them); the
+// caller synchronizes the workgroup afterwards.
+__device__ __forceinline__ void nodes_stage_commit(const NodesDesc& N, const NodesTile& x, const uint64_t* vt,
+                                                   const uint64_t* vn, uint64_t* lds) {
+  const int r0 = (int)threadIdx.x / GW, l = (int)threadIdx.x % GW;
+#pragma unroll
+  for (int u = 0; u < NODES_TPF; ++u)
+    if (r0 + 8 * u < N.rows) lds[(r0 + 8 * u) * GW + l] = vt[u];
+  for (int r = r0 + 8 * NODES_TPF; r < N.rows; r += 8)
+    lds[r * GW + l] = N.S[(int64_t)r * N.stride + (int64_t)x.g * GW + l];
+  uint64_t* dst = lds + (size_t)(N.rows + 1) * GW;  // the zero row sits between
+#pragma unroll
+  for (int u = 0; u < NODES_NPF; ++u) {
+    const int i = (int)threadIdx.x + NODES_BLOCK * u;
+    if (i < x.nodeTotal) dst[i] = vn[u];
+  }
+  const CT_G uint64_t* src = N.nodes + (int64_t)x.node0 * N.nodeWords;
+  for (int i = (int)threadIdx.x + NODES_BLOCK * NODES_NPF; i < x.nodeTotal; i += NODES_BLOCK) dst[i] = src[i];
+}
+
+__device__ __forceinline__ void nodes_eval_tile(const NodesDesc& N, const NodesTile& x, const uint64_t* lds) {
   const int lane = lane_id();
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
-  const int node0 = group * N.groupSize;
-  const int nG = min(N.groupSize, N.nJobs - node0);
-  uint64_t* tile = lds;
-  NodeInfo* info = (NodeInfo*)(lds + (size_t)rows * GW);
-  uint16_t* lists = (uint16_t*)(info + N.groupSize);
-
-  // staging: every load of a pass is issued before its LDS stores, so a
-  // thread has up to STAGE loads in flight (a row granule is 512 B, one
-  // 8-byte word per lane)
-  {
-    constexpr int STAGE = 16;
-    const CT_G uint64_t* S = T->S + (int64_t)g * GW;
-    // the group's NodeInfo records and row lists are contiguous in memory
-    const CT_G uint64_t* srcInfo = (const CT_G uint64_t*)(N.info + node0);
-    const CT_G uint64_t* srcList = (const CT_G uint64_t*)(N.rows + (int64_t)node0 * cap);
-    const int nTile = rows * GW;
-    const int nInfo = nG * (int)(sizeof(NodeInfo) / 8);
-    const int nList = nG * cap / 4;   // cap is a multiple of 4 entries
-    uint64_t* dInfo = (uint64_t*)info;
-    uint64_t* dList = (uint64_t*)lists;
-    const int total = nTile + nInfo + nList;
-    for (int base = 0; base < total; base += STAGE * NODES_BLOCK) {
-      uint64_t v[STAGE];
-#pragma unroll
-      for (int u = 0; u < STAGE; ++u) {
-        const int i = base + u * NODES_BLOCK + (int)threadIdx.x;
-        if (i < nTile) v[u] = S[(int64_t)(i / GW) * stride + (i % GW)];
-        else if (i < nTile + nInfo) v[u] = srcInfo[i - nTile];
-        else if (i < total) v[u] = srcList[i - nTile - nInfo];
-      }
-#pragma unroll
-      for (int u = 0; u < STAGE; ++u) {
-        const int i = base + u * NODES_BLOCK + (int)threadIdx.x;
-        if (i < nTile) tile[i] = v[u];
-        else if (i < nTile + nInfo) dInfo[i - nTile] = v[u];
-        else if (i < total) dList[i - nTile - nInfo] = v[u];
-      }
-    }
-  }
-  const int64_t w = (int64_t)g * GW + lane;
-  const uint64_t root = T->ct0[w];
-  __syncthreads();
-
-  for (int p = wv; p < nG; p += NODES_WAVES) {
-    // the record is the same for every lane: keep it in scalar registers so
-    // that the row loop below is uniform control flow
-    const int status = __builtin_amdgcn_readfirstlane(info[p].status);
-    const int nrows = __builtin_amdgcn_readfirstlane(info[p].nrows);
+  const uint64_t* recs = lds + (size_t)(N.rows + 1) * GW;
+  const uint32_t laneOff = (uint32_t)lane * 8u;
+  const char* tileBytes = (const char*)lds;
+  const int64_t w = (int64_t)x.g * GW + lane;
+  for (int p = wv; p < x.nG; p += NODES_WAVES) {
+    const NodeInfo* info = (const NodeInfo*)(recs + p * N.nodeWords);
+    // the record is the same for every lane: scalar registers, uniform loops
+    const int status = __builtin_amdgcn_readfirstlane(info->status);
     if (status != ST_OK && status != ST_FAIL) continue;  // rejected input: nothing changes
-    uint64_t m = 0ull;
-    if (status == ST_OK) {
-      const uint16_t* rl = lists + p * cap;
-      uint64_t acc = 0ull;
-      bool inc = false, open = false;
-      m = ~0ull;
-      for (int k0 = 0; k0 < nrows; k0 += WAVE) {
-        // 64 entries of the row list, one per lane, then read lane by lane
-        const int mine = (k0 + lane < nrows) ? (int)rl[k0 + lane] : 0;
-        const int cnt = min(WAVE, nrows - k0);
-        for (int u0 = 0; u0 < cnt; u0 += ROW_UNROLL) {
-          int e[ROW_UNROLL];
-          uint64_t v[ROW_UNROLL];
-#pragma unroll
-          for (int u = 0; u < ROW_UNROLL; ++u) {
-            e[u] = __builtin_amdgcn_readlane(mine, u0 + u);
-            v[u] = tile[(e[u] & 0x3FFF) * GW + lane];
-          }
-#pragma unroll
-          for (int u = 0; u < ROW_UNROLL; ++u) {
-            if (u0 + u >= cnt) break;
-            if (e[u] & 0x8000) {
-              if (open) m &= inc ? ~acc : acc;
-              acc = 0ull;
-              inc = (e[u] & 0x4000) != 0;
-              open = true;
-            }
-            acc |= v[u];
-          }
-        }
+    const int ng = __builtin_amdgcn_readfirstlane(info->groups);
+    const uint64_t* rl = (const uint64_t*)(info + 1);  // 4 entries per word
+    uint64_t m = status == ST_OK ? ~0ull : 0ull;
+    uint64_t acc = 0ull;
+    bool inc = false, open = false;
+    // two groups (8 rows) per step; a missing second group reads the zero row
+    const uint64_t zeroGroup = (uint64_t)N.rows * 0x0001000100010001ull;
+    uint64_t eA = ng > 0 ? rl[0] : 0ull, eB = ng > 1 ? rl[1] : zeroGroup;
+    for (int q = 0; q < ng; q += 2) {
+      const uint32_t a0 = __builtin_amdgcn_readfirstlane((uint32_t)eA);
+      const uint32_t a1 = __builtin_amdgcn_readfirstlane((uint32_t)(eA >> 32));
+      const uint32_t b0 = __builtin_amdgcn_readfirstlane((uint32_t)eB);
+      const uint32_t b1 = __builtin_amdgcn_readfirstlane((uint32_t)(eB >> 32));
+      uint64_t x[8];
+      x[0] = *(const uint64_t*)(tileBytes + ((a0 & 0x3FFFu) << 9) + laneOff);
+      x[1] = *(const uint64_t*)(tileBytes + ((a0 >> 16) << 9) + laneOff);
+      x[2] = *(const uint64_t*)(tileBytes + ((a1 & 0xFFFFu) << 9) + laneOff);
+      x[3] = *(const uint64_t*)(tileBytes + ((a1 >> 16) << 9) + laneOff);
+      x[4] = *(const uint64_t*)(tileBytes + ((b0 & 0x3FFFu) << 9) + laneOff);
+      x[5] = *(const uint64_t*)(tileBytes + ((b0 >> 16) << 9) + laneOff);
+      x[6] = *(const uint64_t*)(tileBytes + ((b1 & 0xFFFFu) << 9) + laneOff);
+      x[7] = *(const uint64_t*)(tileBytes + ((b1 >> 16) << 9) + laneOff);
+      eA = q + 2 < ng ? rl[q + 2] : 0ull;
+      eB = q + 3 < ng ? rl[q + 3] : zeroGroup;
+      if (a0 & 0x8000u) {  // a segment starts with the first group
+        if (open) m &= inc ? ~acc : acc;
+        acc = 0ull;
+        inc = (a0 & 0x4000u) != 0;
+        open = true;
       }
-      if (open) m &= inc ? ~acc : acc;
+      acc |= (x[0] | x[1]) | (x[2] | x[3]);
+      if (b0 & 0x8000u) {  // ... or with the second
+        m &= inc ? ~acc : acc;
+        acc = 0ull;
+        inc = (b0 & 0x4000u) != 0;
+      }
+      acc |= (x[4] | x[5]) | (x[6] | x[7]);
     }
-    const uint64_t nw = root & m;
-    CT_G uint64_t* ct = info[p].ct;
-    CT_G uint64_t* ctOut = info[p].ct_out;
+    if (open) m &= inc ? ~acc : acc;
+    const uint64_t nw = x.root & m;
+    CT_G uint64_t* ct = info->ct;
+    CT_G uint64_t* ctOut = info->ct_out;
     ct[w] = nw;
-    if (ctOut && w < W) ctOut[w] = nw;
+    if (ctOut && w < N.W) ctOut[w] = nw;
     const bool nz = __ballot(nw != 0ull) != 0ull;
-    if (lane == 0) N.nz[(int64_t)(node0 + p) * T->nGran + g] = nz ? 1 : 0;
+    if (lane == 0) N.nz[(int64_t)(x.node0 + p) * N.nGran + x.g] = nz ? 1 : 0;
+  }
+}
+
+__global__ void __launch_bounds__(NODES_BLOCK) nodes_update_kernel(KArgs a, NodesDesc N) {
+  extern __shared__ uint64_t lds[];
+  const int xcd = blockIdx.x % XCDS;
+  const int perX = gridDim.x / XCDS;  // the grid is a multiple of 8
+  const int tilesX = (N.nGran - xcd + XCDS - 1) / XCDS * N.groups;
+  int t = blockIdx.x / XCDS;
+  if (t >= tilesX) return;
+  if (threadIdx.x < GW) lds[N.rows * GW + threadIdx.x] = 0ull;  // the zero row
+  uint64_t vt[NODES_TPF], vn[NODES_NPF];
+  NodesTile cur = nodes_tile(N, xcd, t);
+  nodes_stage_issue(N, cur, vt, vn);
+  nodes_stage_commit(N, cur, vt, vn, lds);
+  __syncthreads();
+  for (;;) {
+    const int tn = t + perX;
+    const bool more = tn < tilesX;
+    NodesTile nxt;
+    if (more) {
+      nxt = nodes_tile(N, xcd, tn);
+      nodes_stage_issue(N, nxt, vt, vn);  // in flight during the evaluation
+    }
+    nodes_eval_tile(N, cur, lds);
+    __syncthreads();  // every wave is done with this tile's LDS
+    if (!more) break;
+    nodes_stage_commit(N, nxt, vt, vn, lds);
+    __syncthreads();
+    t = tn;
+    cur = nxt;
   }
 }
 
@@ -973,8 +1117,9 @@ __global__ void __launch_bounds__(BLOCK) nodes_finish_kernel(KArgs a, NodesDesc 
   const DevJob J = N.jobs[j];
   const TabDesc* T = J.tab;
   SlotDesc* s = J.slot;
-  const int st0 = N.info[j].status;
-  const int nrows = N.info[j].nrows;
+  const CT_G NodeInfo* rec = (const CT_G NodeInfo*)(N.nodes + (int64_t)j * N.nodeWords);
+  const int st0 = rec->status;
+  const int nrows = rec->nrows;
   const bool run = st0 == ST_OK || st0 == ST_FAIL;
   if (run && wv == 0) {
     const int limit0 = T->limit0, nGran = T->nGran;
@@ -1368,18 +1513,39 @@ hipError_t launch_model_round(const ModelDesc& M, const KArgs& a, int grid, hipS
 // the dirty flags of the first round.
 int nodes_max_rows() { return NODES_MAX_ROWS; }
 
-// Dynamic LDS of the update kernel for a table of `rows` support rows and
-// groups of `groupSize` nodes with row lists of up to `cap` entries.
-size_t nodes_update_lds(int rows, int groupSize, int cap) {
-  return (size_t)rows * GW * sizeof(uint64_t) + (size_t)groupSize * sizeof(NodeInfo) +
-         (((size_t)groupSize * cap * sizeof(uint16_t) + 7) & ~(size_t)7);
+// Row-list entries per node (every segment padded to a multiple of 4, the
+// list to a multiple of 4 entries).
+int nodes_list_cap(int rows, int n) { return (rows + 3 * n + 3) & ~3; }
+
+// Words of a node's record: its NodeInfo and its row list.
+int nodes_node_words(int rows, int n) {
+  return (int)(sizeof(NodeInfo) / 8) + nodes_list_cap(rows, n) / 4;
 }
 
-hipError_t launch_nodes(const KArgs& a, const NodesDesc& N, int nGran, int rows, hipStream_t stream) {
-  hipLaunchKernelGGL(nodes_prep_kernel, dim3(N.nJobs), dim3(BLOCK), 0, stream, a, N);
-  const int blocks = (nGran + XCDS - 1) / XCDS * XCDS * N.groups;
-  hipLaunchKernelGGL(nodes_update_kernel, dim3(blocks), dim3(NODES_BLOCK),
-                     nodes_update_lds(rows, N.groupSize, N.rowsCap), stream, a, N);
+// Dynamic LDS of the update kernel for groups of `groupSize` nodes.
+size_t nodes_update_lds(int rows, int n, int groupSize) {
+  return (size_t)(rows + 1) * GW * sizeof(uint64_t) +
+         (size_t)groupSize * nodes_node_words(rows, n) * sizeof(uint64_t);
+}
+
+// Persistent workgroups of the update kernel: as many as fit at once, a
+// multiple of the XCD count.
+int nodes_update_grid(size_t ldsBytes) {
+  int dev = 0, cus = 0, perCu = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    return XCDS;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&perCu, nodes_update_kernel, NODES_BLOCK, ldsBytes) !=
+          hipSuccess ||
+      perCu < 1)
+    perCu = 1;
+  return std::max(XCDS, cus * perCu / XCDS * XCDS);
+}
+
+hipError_t launch_nodes(const KArgs& a, const NodesDesc& N, int n, hipStream_t stream) {
+  hipLaunchKernelGGL(nodes_prep_kernel, dim3((N.nJobs + WAVES - 1) / WAVES), dim3(BLOCK), 0, stream, a, N);
+  const size_t lds = nodes_update_lds(N.rows, n, N.groupSize);
+  hipLaunchKernelGGL(nodes_update_kernel, dim3(nodes_update_grid(lds)), dim3(NODES_BLOCK), lds, stream, a, N);
   hipLaunchKernelGGL(nodes_finish_kernel, dim3(N.nJobs), dim3(BLOCK), 0, stream, a, N);
   return hipGetLastError();
 }

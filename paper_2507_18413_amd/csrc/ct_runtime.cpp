@@ -28,8 +28,10 @@ int propagate_items_per_job_filter(int D);
 int propagate_max_grid();
 hipError_t launch_propagate(const KArgs& a, int grid, hipStream_t stream);
 int nodes_max_rows();
-size_t nodes_update_lds(int rows, int groupSize, int cap);
-hipError_t launch_nodes(const KArgs& a, const NodesDesc& N, int nGran, int rows, hipStream_t stream);
+int nodes_list_cap(int rows, int n);
+int nodes_node_words(int rows, int n);
+size_t nodes_update_lds(int rows, int n, int groupSize);
+hipError_t launch_nodes(const KArgs& a, const NodesDesc& N, int n, hipStream_t stream);
 hipError_t launch_build_supports(const int32_t* tuples, int64_t t, int n, const VarDesc* vars,
                                  const int32_t* lo, uint64_t* S, int64_t stride, int64_t W,
                                  hipStream_t stream);
@@ -89,7 +91,7 @@ struct QueueCtx {
   int32_t* pOff = nullptr;
   size_t capPinned = 0;
   hipEvent_t staged = nullptr;
-  // search-node schedule scratch (NodeInfo | row lists | granule flags)
+  // search-node schedule scratch (node records | granule flags)
   void* dNodes = nullptr;
   size_t capNodes = 0;
 };
@@ -238,18 +240,14 @@ int device_lds() {
   return lds;
 }
 
-// Row-list entries per node: the table's row count rounded up to a multiple
-// of 4 (the update kernel copies lists as 8-byte words).
-int nodes_list_cap(const ct_table* T) { return (T->rows + 3) & ~3; }
-
-// Nodes per group of the update kernel: 64 (two workgroups per CU for tables
-// of up to ~120 rows), fewer when the table's tile leaves less LDS.
+// Nodes per group of the update kernel: the largest multiple of 8 up to 64
+// for which two workgroups fit in a CU's LDS, else for which one does.
 int nodes_group_size(const ct_table* T) {
   const size_t lds = (size_t)device_lds();
-  int gs = 64;
-  const int cap = nodes_list_cap(T);
-  while (gs > 8 && nodes_update_lds(T->rows, gs, cap) > lds) gs /= 2;
-  return nodes_update_lds(T->rows, gs, cap) <= lds ? gs : 0;
+  for (int per = 2; per >= 1; --per)
+    for (int gs = 64; gs >= 8; gs -= 8)
+      if (per * nodes_update_lds(T->rows, T->n, gs) <= lds) return gs;
+  return 0;
 }
 
 bool use_nodes(const ct_job* jobs, int n) {
@@ -875,8 +873,7 @@ int ct_propagate_batch(const ct_job* jobs, int32_t n_jobs, void* stream_v, int32
   const bool nodes = use_nodes(jobs, n_jobs);
   if (nodes) {
     const ct_table* T = jobs[0].table;
-    const size_t need = align256(sizeof(NodeInfo) * n_jobs) +
-                        align256(sizeof(uint16_t) * (size_t)n_jobs * nodes_list_cap(T)) +
+    const size_t need = align256(sizeof(uint64_t) * (size_t)n_jobs * nodes_node_words(T->rows, T->n)) +
                         align256((size_t)n_jobs * T->nGran);
     if (q->capNodes < need) {
       HIPCHK(hipStreamSynchronize(stream));
@@ -975,14 +972,22 @@ int ct_propagate_batch(const ct_job* jobs, int32_t n_jobs, void* stream_v, int32
     const ct_table* T = jobs[0].table;
     NodesDesc N{};
     N.nJobs = n_jobs;
-    N.rowsCap = nodes_list_cap(T);
+    N.listCap = nodes_list_cap(T->rows, T->n);
     N.groupSize = nodes_group_size(T);
     N.groups = (n_jobs + N.groupSize - 1) / N.groupSize;
     N.jobs = q->dJobs;
-    N.info = (NodeInfo*)q->dNodes;
-    N.rows = (uint16_t*)((char*)q->dNodes + align256(sizeof(NodeInfo) * n_jobs));
-    N.nz = (uint8_t*)((char*)N.rows + align256(sizeof(uint16_t) * (size_t)n_jobs * N.rowsCap));
-    HIPCHK(launch_nodes(a, N, T->nGran, T->rows, stream));
+    char* base = (char*)q->dNodes;
+    N.nodeWords = nodes_node_words(T->rows, T->n);
+    N.nodes = (uint64_t*)base;
+    base += align256(sizeof(uint64_t) * (size_t)n_jobs * N.nodeWords);
+    N.nz = (uint8_t*)base;
+    N.rows = T->rows;
+    N.nGran = T->nGran;
+    N.stride = T->stride;
+    N.W = T->W;
+    N.S = T->hTab.S;
+    N.ct0 = T->hTab.ct0;
+    HIPCHK(launch_nodes(a, N, T->n, stream));
     return CT_OK;
   }
   const int total = a.nPrep + a.nUpd + a.nFilt;
