@@ -165,6 +165,8 @@ def nodes_leg(seed, n_nodes, reps, warmup, schedule=0):
     # root currTable once + per node currTable write + domains
     W_words = table.W
     comp = 8 * table.rows * W_words + 8 * W_words + n_nodes * (8 * W_words + 16 * lay.D)
+    from paper_2507_18413_amd import profiling
+    prof = profiling.read_summary(os.path.join(ROOT, "profiles", "nodes_update_config4.md"))
     return {
         "nodes": n_nodes, "tuples": spec.t, "ms_per_batch": round(gpu_ms, 3),
         "node_props_per_s": round(n_nodes / (gpu_ms / 1e3), 1),
@@ -173,6 +175,8 @@ def nodes_leg(seed, n_nodes, reps, warmup, schedule=0):
         "compulsory_bytes": comp,
         "compulsory_GBps": round(comp / (gpu_ms / 1e3) / 1e9, 1),
         "frac_of_hbm_peak": round(comp / (gpu_ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
+        "update_kernel_hbm_bytes": prof.get("hbm_bytes_per_launch") if prof else None,
+        "update_kernel_avg_us_profiled": prof.get("avg_us") if prof else None,
     }
 
 

@@ -1031,38 +1031,43 @@ __device__ __forceinline__ void nodes_eval_tile(const NodesDesc& N, const NodesT
     uint64_t m = status == ST_OK ? ~0ull : 0ull;
     uint64_t acc = 0ull;
     bool inc = false, open = false;
-    // two groups (8 rows) per step; a missing second group reads the zero row
+    // the list, 64 groups of 4 row numbers at a time, one group per lane;
+    // two groups (8 rows) per step, taken from the lanes by readlane, so the
+    // row reads of a step never wait for an LDS read of row numbers; a missing
+    // second group reads the zero row
     const uint64_t zeroGroup = (uint64_t)N.rows * 0x0001000100010001ull;
-    uint64_t eA = ng > 0 ? rl[0] : 0ull, eB = ng > 1 ? rl[1] : zeroGroup;
-    for (int q = 0; q < ng; q += 2) {
-      const uint32_t a0 = __builtin_amdgcn_readfirstlane((uint32_t)eA);
-      const uint32_t a1 = __builtin_amdgcn_readfirstlane((uint32_t)(eA >> 32));
-      const uint32_t b0 = __builtin_amdgcn_readfirstlane((uint32_t)eB);
-      const uint32_t b1 = __builtin_amdgcn_readfirstlane((uint32_t)(eB >> 32));
-      uint64_t x[8];
-      x[0] = *(const uint64_t*)(tileBytes + ((a0 & 0x3FFFu) << 9) + laneOff);
-      x[1] = *(const uint64_t*)(tileBytes + ((a0 >> 16) << 9) + laneOff);
-      x[2] = *(const uint64_t*)(tileBytes + ((a1 & 0xFFFFu) << 9) + laneOff);
-      x[3] = *(const uint64_t*)(tileBytes + ((a1 >> 16) << 9) + laneOff);
-      x[4] = *(const uint64_t*)(tileBytes + ((b0 & 0x3FFFu) << 9) + laneOff);
-      x[5] = *(const uint64_t*)(tileBytes + ((b0 >> 16) << 9) + laneOff);
-      x[6] = *(const uint64_t*)(tileBytes + ((b1 & 0xFFFFu) << 9) + laneOff);
-      x[7] = *(const uint64_t*)(tileBytes + ((b1 >> 16) << 9) + laneOff);
-      eA = q + 2 < ng ? rl[q + 2] : 0ull;
-      eB = q + 3 < ng ? rl[q + 3] : zeroGroup;
-      if (a0 & 0x8000u) {  // a segment starts with the first group
-        if (open) m &= inc ? ~acc : acc;
-        acc = 0ull;
-        inc = (a0 & 0x4000u) != 0;
-        open = true;
+    for (int c0 = 0; c0 < ng; c0 += WAVE) {
+      const uint64_t mine = c0 + lane < ng ? rl[c0 + lane] : zeroGroup;
+      const uint32_t mlo = (uint32_t)mine, mhi = (uint32_t)(mine >> 32);
+      const int cn = min(WAVE, ng - c0);
+      for (int q = 0; q < cn; q += 2) {
+        const uint32_t a0 = __builtin_amdgcn_readlane(mlo, q);
+        const uint32_t a1 = __builtin_amdgcn_readlane(mhi, q);
+        const uint32_t b0 = __builtin_amdgcn_readlane(mlo, q + 1);  // q + 1 <= 63
+        const uint32_t b1 = __builtin_amdgcn_readlane(mhi, q + 1);
+        uint64_t x[8];
+        x[0] = *(const uint64_t*)(tileBytes + ((a0 & 0x3FFFu) << 9) + laneOff);
+        x[1] = *(const uint64_t*)(tileBytes + ((a0 >> 16) << 9) + laneOff);
+        x[2] = *(const uint64_t*)(tileBytes + ((a1 & 0xFFFFu) << 9) + laneOff);
+        x[3] = *(const uint64_t*)(tileBytes + ((a1 >> 16) << 9) + laneOff);
+        x[4] = *(const uint64_t*)(tileBytes + ((b0 & 0x3FFFu) << 9) + laneOff);
+        x[5] = *(const uint64_t*)(tileBytes + ((b0 >> 16) << 9) + laneOff);
+        x[6] = *(const uint64_t*)(tileBytes + ((b1 & 0xFFFFu) << 9) + laneOff);
+        x[7] = *(const uint64_t*)(tileBytes + ((b1 >> 16) << 9) + laneOff);
+        if (a0 & 0x8000u) {  // a segment starts with the first group
+          if (open) m &= inc ? ~acc : acc;
+          acc = 0ull;
+          inc = (a0 & 0x4000u) != 0;
+          open = true;
+        }
+        acc |= (x[0] | x[1]) | (x[2] | x[3]);
+        if (b0 & 0x8000u) {  // ... or with the second
+          m &= inc ? ~acc : acc;
+          acc = 0ull;
+          inc = (b0 & 0x4000u) != 0;
+        }
+        acc |= (x[4] | x[5]) | (x[6] | x[7]);
       }
-      acc |= (x[0] | x[1]) | (x[2] | x[3]);
-      if (b0 & 0x8000u) {  // ... or with the second
-        m &= inc ? ~acc : acc;
-        acc = 0ull;
-        inc = (b0 & 0x4000u) != 0;
-      }
-      acc |= (x[4] | x[5]) | (x[6] | x[7]);
     }
     if (open) m &= inc ? ~acc : acc;
     const uint64_t nw = x.root & m;
@@ -1106,10 +1111,14 @@ __global__ void __launch_bounds__(NODES_BLOCK) nodes_update_kernel(KArgs a, Node
   }
 }
 
-// One workgroup per node: wave 0 partitions the root's granule list by the
-// non-zero flags (survivors first, stable) and detects FAIL (Alg. 1); then
-// the four waves run filterDomains (Alg. 3) on interleaved domain words.
-__global__ void __launch_bounds__(BLOCK) nodes_finish_kernel(KArgs a, NodesDesc N) {
+// One workgroup of 8 waves per node: wave 0 partitions the root's granule
+// list by the non-zero flags (survivors first, stable) and detects FAIL
+// (Alg. 1); then the waves run filterDomains (Alg. 3) on interleaved domain
+// words.
+constexpr int FINISH_BLOCK = 512;
+constexpr int FINISH_WAVES = FINISH_BLOCK / WAVE;
+
+__global__ void __launch_bounds__(FINISH_BLOCK) nodes_finish_kernel(KArgs a, NodesDesc N) {
   __shared__ int32_t shSurv;
   const int j = blockIdx.x;
   const int lane = lane_id();
@@ -1182,7 +1191,7 @@ __global__ void __launch_bounds__(BLOCK) nodes_finish_kernel(KArgs a, NodesDesc 
   const int st = run ? (nSurv ? ST_OK : ST_FAIL) : st0;
   if (st == ST_OK) {
     unsigned long long cnt[3] = {0, 0, 0};
-    for (int q = wv; q < T->D; q += WAVES) filter_word(a, J, q, 0, nSurv, s->idx[0], cnt);
+    for (int q = wv; q < T->D; q += FINISH_WAVES) filter_word(a, J, q, 0, nSurv, s->idx[0], cnt);
     add_filter_stats(s, cnt);
   }
   __syncthreads();
@@ -1546,7 +1555,7 @@ hipError_t launch_nodes(const KArgs& a, const NodesDesc& N, int n, hipStream_t s
   hipLaunchKernelGGL(nodes_prep_kernel, dim3((N.nJobs + WAVES - 1) / WAVES), dim3(BLOCK), 0, stream, a, N);
   const size_t lds = nodes_update_lds(N.rows, n, N.groupSize);
   hipLaunchKernelGGL(nodes_update_kernel, dim3(nodes_update_grid(lds)), dim3(NODES_BLOCK), lds, stream, a, N);
-  hipLaunchKernelGGL(nodes_finish_kernel, dim3(N.nJobs), dim3(BLOCK), 0, stream, a, N);
+  hipLaunchKernelGGL(nodes_finish_kernel, dim3(N.nJobs), dim3(FINISH_BLOCK), 0, stream, a, N);
   return hipGetLastError();
 }
 

@@ -5,7 +5,8 @@
         --fetch DIRF/c2_counter_collection.csv --write DIRW/c2_counter_collection.csv \
         --copy-bytes N --command "..." --out profiles/propagate_config2.md
 
-The kernel-trace statistics give the propagate kernel's average duration.
+The kernel-trace statistics give the chosen kernel's (--kernel, a regular
+expression; default the propagate kernel) average duration.
 The two counter runs (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch) are
 scaled by what the same counter reads for a plain copy kernel of known size
 (the runtime's device-to-device copyBuffer kernel of `--copy-bytes` bytes,
@@ -27,6 +28,7 @@ import statistics
 HERE = os.path.dirname(os.path.abspath(__file__))
 KERNEL_SRC = os.path.join(HERE, "csrc", "ct_kernels.hip")
 KERNEL = "propagate_kernel"
+DEFAULT_TITLE = "propagate_kernel, one large table (config 2)"
 
 
 def kernel_source_hash() -> str:
@@ -60,8 +62,9 @@ def pick(d, pattern):
 
 
 def summarize(args):
+    kernel = args.kernel
     stats = _rows(args.stats)
-    prop = [r for r in stats if KERNEL in r["Name"]][0]
+    prop = [r for r in stats if re.search(kernel, r["Name"])][0]
     avg_ns = float(prop["AverageNs"])
     out = {"kernel": prop["Name"], "calls": int(prop["Calls"]), "avg_us": round(avg_ns / 1e3, 3),
            "min_us": round(float(prop["MinNs"]) / 1e3, 3), "max_us": round(float(prop["MaxNs"]) / 1e3, 3),
@@ -75,8 +78,8 @@ def summarize(args):
     if args.fetch and args.write and args.copy_bytes:
         f = counter_by_kernel(args.fetch, "FETCH_SIZE")
         w = counter_by_kernel(args.write, "WRITE_SIZE")
-        _, (kf, nf) = pick(f, KERNEL)
-        _, (kw, nw) = pick(w, KERNEL)
+        _, (kf, nf) = pick(f, kernel)
+        _, (kw, nw) = pick(w, kernel)
         # the calibration copy is the largest copyBuffer dispatch of the run
         cname, (cf, _) = pick(counter_by_kernel(args.fetch, "FETCH_SIZE", largest=True), r"copyBuffer")
         _, (cw, _) = pick(counter_by_kernel(args.write, "WRITE_SIZE", largest=True), r"copyBuffer")
@@ -88,11 +91,11 @@ def summarize(args):
                     "copy_write_factor": round(wfac, 4), "hbm_bytes_per_launch": round(traffic, 1),
                     "dispatches_fetch": nf, "dispatches_write": nw})
         lines += ["", "HBM traffic (rocprofv3 --pmc FETCH_SIZE, then WRITE_SIZE; KiB per dispatch):", "",
-                  f"* propagate kernel: FETCH {kf:.2f} KiB, WRITE {kw:.2f} KiB per launch "
+                  f"* {prop['Name'][:60]}: FETCH {kf:.2f} KiB, WRITE {kw:.2f} KiB per launch "
                   f"({nf} / {nw} dispatches)",
                   f"* calibration copy of {args.copy_bytes} bytes ({cname[:50]}): FETCH reads {cf:.1f} KiB "
                   f"(factor {ffac:.3f}), WRITE reads {cw:.1f} KiB (factor {wfac:.3f})",
-                  f"* scaled HBM bytes per propagate launch: {traffic:.0f}"]
+                  f"* scaled HBM bytes per launch of that kernel: {traffic:.0f}"]
     lines += ["", "Machine-readable (read by bench.py while the kernel source hash matches):", "",
               "```json", json.dumps(out), "```", ""]
     with open(args.out, "w") as fh:
@@ -123,7 +126,8 @@ def main():
     s.add_argument("--write")
     s.add_argument("--copy-bytes", type=int, default=0)
     s.add_argument("--command", required=True)
-    s.add_argument("--title", default="propagate_kernel, one large table (config 2)")
+    s.add_argument("--kernel", default=KERNEL, help="regular expression naming the kernel")
+    s.add_argument("--title", default=DEFAULT_TITLE)
     s.add_argument("--out", required=True)
     a = p.parse_args()
     if a.cmd == "summarize":
