@@ -79,6 +79,17 @@ typedef struct ct_table ct_table;
 #define CT_SCHED_SOLO 1
 #define CT_SCHED_SPLIT 2
 #define CT_SCHED_NODES 3
+/* RESIDENT: synchronous calls on slot 0 (ct_propagate, ct_propagate_slot
+ * with slot 0) go to a resident engine: one persistent workgroup that keeps
+ * the slot's currTable, granule index, stamps, residues and domains in LDS
+ * and takes calls from a mailbox in pinned host memory, so a call costs no
+ * launch and few round trips to HBM.  Used when that state fits one
+ * workgroup's LDS (currTable of up to roughly a million tuples) and D <= 64;
+ * AUTO does the same.  Results are identical to the launched schedules.  The
+ * engine writes the state back and exits after 2 ms without a call (the
+ * next call starts it again) and before any other operation on the table's
+ * device state; one engine runs per process (see ct_quiesce). */
+#define CT_SCHED_RESIDENT 4
 
 typedef struct {
     int32_t branch_policy; /* CT_BRANCH_*; default AUTO */
@@ -359,6 +370,12 @@ int ct_get_timing(ct_table *t, double *kernel_ms, int64_t *launches);
 
 /* Thread-local message of the last error ("" if none). */
 const char *ct_last_error(void);
+
+/* Ends the resident engine of any table (CT_SCHED_RESIDENT) after it has
+ * written its state back to the device: call before the process exits, or
+ * before work on the GPU that must not wait up to 2 ms behind an idle engine.
+ * Synchronous; CT_OK or CT_E_DEVICE. */
+int ct_quiesce(void);
 
 #ifdef __cplusplus
 }

@@ -16,8 +16,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libct.so")
 BUILD = os.path.join(ROOT, "_build")
-SOURCES = [os.path.join(CSRC, "ct_kernels.hip"), os.path.join(CSRC, "ct_runtime.cpp"),
-           os.path.join(CSRC, "ct_server.cpp")]
+SOURCES = [os.path.join(CSRC, "ct_kernels.hip"), os.path.join(CSRC, "ct_engine.hip"),
+           os.path.join(CSRC, "ct_runtime.cpp"), os.path.join(CSRC, "ct_server.cpp")]
 ARCH = os.environ.get("CT_OFFLOAD_ARCH", "gfx950")
 HIPCC = "/opt/rocm/bin/hipcc"
 

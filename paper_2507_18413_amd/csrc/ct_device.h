@@ -50,7 +50,7 @@ constexpr int INLINE_WORDS = 64;   // dom_in words carried in kernel arguments
 
 // status codes (same values as the public header)
 constexpr int ST_OK = 0, ST_FAIL = 1, ST_INVALID = -1, ST_NOT_SUBSET = -2, ST_STATE = -3,
-              ST_NOMEM = -4;
+              ST_NOMEM = -4, ST_DEVICE = -5;
 
 // job flags
 constexpr uint32_t JF_PROPAGATE = 1u;
@@ -192,6 +192,37 @@ struct KArgs {
   unsigned long long* clock;
   DevJob job;
   uint64_t inl[INLINE_WORDS];
+};
+
+// ---------------------------------------------------------------------------
+// Resident engine of a table's primary slot (synchronous calls).  One
+// persistent workgroup keeps the slot's currTable, granule index, stamps,
+// residues and last domains in LDS and takes calls from a mailbox in
+// coherent pinned host memory; results go back the same way.
+// ---------------------------------------------------------------------------
+constexpr int ENG_OP_PROPAGATE = 1, ENG_OP_STOP = 2;
+
+struct EngCmd {             // written by the host, seq last (release)
+  int32_t seq, op, nPop, nPush;
+  int32_t serialBase, depthAfter, wantCt, pad;
+  uint64_t dom[INLINE_WORDS];
+};
+
+struct EngRes {             // written by the engine, seq last (release)
+  int32_t seq, status, alive, exitSeq;
+  uint64_t dom[INLINE_WORDS];
+  unsigned long long stats[8];  // the slot's counters after the call
+  unsigned long long callTicks, pad2;  // device clock (100 MHz) spent in the call
+};
+
+struct EngDesc {
+  const CT_G TabDesc* tab;
+  CT_G SlotDesc* slot;
+  EngCmd* cmd;              // device pointers of the pinned host buffers
+  EngRes* res;
+  uint64_t* ctOut;          // pinned host buffer of W words (calls that want currTable)
+  int64_t idleTicks;        // exit after this long without a call (device clock)
+  int32_t startSeq, pad;    // the last call seq already answered
 };
 
 }  // namespace ctk

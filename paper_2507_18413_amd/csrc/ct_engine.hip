@@ -1,0 +1,761 @@
+// ct_engine.hip -- resident engine for synchronous calls on a table's primary
+// slot (include/ct.h, CT_SCHED_RESIDENT).
+//
+// A synchronous call (ct_propagate) is a chain of dependent steps -- apply
+// pops and pushes, the Alg. 1 prologue, updateTable (Alg. 2) over the active
+// granules, the sparse-bitset compaction, filterDomains (Alg. 3) with its
+// residues -- over a few hundred KB.  Launched per call, every step pays a
+// round trip to memory and the call pays a launch.  Here one persistent
+// workgroup of 16 waves keeps the slot's currTable, granule index, stamps,
+// residues and last domains in LDS for as long as calls keep coming: only
+// the support rows (read-only) and the trail (written on changes, read on
+// pops) stay in HBM.  Calls arrive in a mailbox in coherent pinned host
+// memory (EngCmd) and results leave the same way (EngRes).  The engine
+// writes its state back to the slot and exits on a stop command or after
+// `idleTicks` of device clock without a call, so every launch ends.
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+
+#include "ct_device.h"
+
+namespace ctk {
+namespace {
+
+constexpr int EBLOCK = 1024;
+constexpr int EWAVES = EBLOCK / WAVE;
+constexpr int E_NG = 4;          // granules per wave per update step
+constexpr int E_ROWS = 4;        // support rows loaded per batch
+constexpr int E_LANE_SCAN = 16;  // words each missing lane checks after its residue
+
+struct EngState {
+  int32_t op, seq, lastSeq, nPop, nPush, serialBase, depthAfter, wantCt;
+  int32_t limit, failed, depth, serial, cur, status, noop, nseg;
+  int32_t nrows, badStray, badSub, trailCount, nSurv, devErr, pad0, pad1;
+  int64_t trailTop, lvTrailTop;
+  int32_t lvLimit, lvFailed, lvSerial, pad2;
+  int32_t waveSum[EWAVES];
+  unsigned long long stat[8];
+};
+
+// Dynamic LDS regions, in this order, each 8-byte aligned.
+enum { R_CT, R_IDX0, R_IDX1, R_STAMP, R_NZ, R_FIRST, R_RES, R_LAST, R_DIN, R_ROWS, R_WVAR, R_VARS, R_VSIZE,
+       R_VDCNT, R_SEGOF, R_SEGEND, R_SEGINC, R_STATE, R_END };
+
+__host__ __device__ inline size_t eng_align(size_t x) { return (x + 7) & ~(size_t)7; }
+
+__host__ __device__ inline void eng_layout(int n, int D, int nGran, int rows, size_t* off) {
+  size_t sz[R_END];
+  sz[R_CT] = (size_t)nGran * GW * 8;
+  sz[R_IDX0] = sz[R_IDX1] = (size_t)nGran * 2;
+  sz[R_STAMP] = (size_t)nGran * 4;
+  sz[R_NZ] = (size_t)nGran;
+  sz[R_FIRST] = (size_t)nGran * 4;
+  sz[R_RES] = (size_t)rows * 4;
+  sz[R_LAST] = sz[R_DIN] = (size_t)D * 8;
+  sz[R_ROWS] = (size_t)rows * 2;
+  sz[R_WVAR] = (size_t)D * 4;
+  sz[R_VARS] = (size_t)n * sizeof(VarDesc);
+  sz[R_VSIZE] = sz[R_VDCNT] = sz[R_SEGOF] = sz[R_SEGEND] = sz[R_SEGINC] = (size_t)n * 4;
+  sz[R_STATE] = sizeof(EngState);
+  size_t o = 0;
+  for (int r = 0; r < R_END; ++r) {
+    off[r] = o;
+    o += eng_align(sz[r]);
+  }
+  off[R_END] = o;
+}
+
+// Workgroup barrier that orders LDS only: outstanding global stores (trail,
+// levels) need not complete here.  The end of every call has a full
+// barrier, so a later call's waves see all of an earlier call's stores.
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+__device__ __forceinline__ int e_lane() { return threadIdx.x & (WAVE - 1); }
+__device__ __forceinline__ int e_wave() { return __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE); }
+
+struct Eng {
+  // table (read-only)
+  const CT_G uint64_t* S;
+  int64_t stride, W;
+  int n, D, nGran, rows, policy;
+  // slot arrays in HBM
+  CT_G SlotDesc* slot;
+  CT_G TrailHdr* trailHdr;
+  CT_G uint64_t* trailWords;
+  CT_G Level* levels;
+  CT_G uint64_t* levelDom;
+  int64_t trailCap;
+  // LDS
+  uint64_t* ct;
+  uint16_t* idx0;  // granule index ping-pong buffers (no array: a dynamically
+  uint16_t* idx1;  // indexed member would put this struct in scratch)
+  int32_t* stamp;
+  uint8_t* nz;
+  int32_t* first;  // per granule: its first trail entry among those undone by pops
+  int32_t* res;
+  uint64_t* last;
+  uint64_t* din;
+  uint16_t* rowList;
+  int32_t* wordVar;
+  VarDesc* vars;
+  int32_t *vsize, *vdcnt, *segOf, *segEnd, *segInc;
+  EngState* st;
+};
+
+// Inclusive prefix sum over the 64 lanes of a wave with DPP moves (VALU,
+// no LDS round trip): shifts by 1, 2, 4, 8 within each row of 16 lanes,
+// then the last lane of row 0 / 2 added to rows 1 / 3 (row_bcast:15) and
+// lane 31 added to rows 2 and 3 (row_bcast:31).  Lanes without a source
+// add the `old` operand, 0.
+__device__ __forceinline__ int e_wscan(int v) {
+  v += __builtin_amdgcn_update_dpp(0, v, 0x111, 0xf, 0xf, false);  // row_shr:1
+  v += __builtin_amdgcn_update_dpp(0, v, 0x112, 0xf, 0xf, false);  // row_shr:2
+  v += __builtin_amdgcn_update_dpp(0, v, 0x114, 0xf, 0xf, false);  // row_shr:4
+  v += __builtin_amdgcn_update_dpp(0, v, 0x118, 0xf, 0xf, false);  // row_shr:8
+  v += __builtin_amdgcn_update_dpp(0, v, 0x142, 0xa, 0xf, false);  // row_bcast:15
+  v += __builtin_amdgcn_update_dpp(0, v, 0x143, 0xc, 0xf, false);  // row_bcast:31
+  return v;
+}
+
+// ---------------------------------------------------------------------------
+// pops (all waves, every popped level at once) and pushes (wave 0; the
+// trail and the levels stay in HBM)
+// ---------------------------------------------------------------------------
+__device__ void e_pops_pushes(Eng& E) {
+  EngState* st = E.st;
+  const int nPop = st->nPop, nPush = st->nPush;
+  if (nPop > 0) {
+    // all popped levels at once: the state of the level popped to is in
+    // its Level record and domains; a granule saved on the trail after it
+    // gets the words of its first entry there (the oldest save holds the
+    // words of that level)
+    const int dT = st->depth - nPop;
+    if (threadIdx.x == 0) {
+      const Level L = E.levels[dT];
+      st->lvTrailTop = L.trailTop;
+      st->lvLimit = L.limit;
+      st->lvFailed = L.failed;
+      st->lvSerial = L.serial;
+    }
+    for (int g = threadIdx.x; g < E.nGran; g += EBLOCK) E.first[g] = 0x7fffffff;
+    for (int q = threadIdx.x; q < E.D; q += EBLOCK) E.last[q] = E.levelDom[(int64_t)dT * E.D + q];
+    lds_barrier();
+    const int64_t lo = st->lvTrailTop, top = st->trailTop;
+    for (int64_t e = lo + threadIdx.x; e < top; e += EBLOCK) atomicMin(&E.first[E.trailHdr[e].gran], (int)(e - lo));
+    lds_barrier();
+    for (int64_t e = lo + e_wave(); e < top; e += EWAVES) {
+      const TrailHdr h = E.trailHdr[e];
+      if (E.first[h.gran] == (int)(e - lo)) {
+        E.ct[(int64_t)h.gran * GW + e_lane()] = E.trailWords[e * GW + e_lane()];
+        if (e_lane() == 0) E.stamp[h.gran] = h.oldStamp;
+      }
+    }
+    lds_barrier();
+    if (threadIdx.x == 0) {
+      st->trailTop = lo;
+      st->limit = st->lvLimit;
+      st->failed = st->lvFailed;
+      st->serial = st->lvSerial;
+      st->depth = dT;
+    }
+    lds_barrier();
+  }
+  // each push records the state before this call's propagation (wave 0,
+  // which also runs the prologue next: no barrier needed)
+  if (threadIdx.x < WAVE && nPush > 0) {
+    const int lane = e_lane();
+    for (int k = 0; k < nPush; ++k) {
+      const int d = st->depth + k;
+      if (lane < E.D) E.levelDom[(int64_t)d * E.D + lane] = E.last[lane];
+      if (lane == 0) {
+        Level L;
+        L.trailTop = st->trailTop;
+        L.limit = st->limit;
+        L.failed = st->failed;
+        L.serial = k == 0 ? st->serial : st->serialBase + k - 1;
+        L.pad = 0;
+        E.levels[d] = L;
+      }
+    }
+    if (lane == 0) {
+      st->depth += nPush;
+      st->serial = st->serialBase + nPush - 1;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// prologue of Alg. 1, by wave 0 with one domain word per lane (the engine
+// takes tables of at most 64 domain words): checks, |dom| and |Delta| per
+// variable (prefix sums over the words), s_val, the branch of Alg. 2 per
+// variable and the list of support rows to OR, segment by segment
+// ---------------------------------------------------------------------------
+__device__ void e_prologue(Eng& E) {
+  EngState* st = E.st;
+  if (threadIdx.x < WAVE) {
+    const int q = e_lane();
+    const bool isWord = q < E.D;
+    uint64_t din = 0, ld = 0;
+    VarDesc v{};
+    v.domOff = q;
+    v.domWords = 1;
+    v.dsize = 64;
+    if (isWord) {
+      din = E.din[q];
+      ld = E.last[q];
+      v = E.vars[E.wordVar[q]];
+    }
+    const int used = v.dsize - 64 * (q - v.domOff);
+    const bool stray = isWord && used < 64 && (din >> used) != 0;
+    const bool notSub = isWord && (din & ~ld) != 0;
+    int status = st->failed ? ST_STATE : ST_OK;
+    if (status == ST_OK) {
+      if (__ballot(stray)) status = ST_INVALID;
+      else if (__ballot(notSub)) status = ST_NOT_SUBSET;
+    }
+    // |dom| and |Delta| of the word's variable: prefix sums over the words
+    const int first = v.domOff, lastW = v.domOff + v.domWords - 1;
+    const int cs = isWord ? __popcll(din) : 0, cd = isWord ? __popcll(ld & ~din) : 0;
+    const int scS = e_wscan(cs), scD = e_wscan(cd);
+    const int befS = __shfl(scS, max(first - 1, 0)), befD = __shfl(scD, max(first - 1, 0));
+    const int sz = __shfl(scS, lastW) - (first > 0 ? befS : 0);
+    const int dc = __shfl(scD, lastW) - (first > 0 ? befD : 0);
+    // decisions on each variable's first word
+    const bool head = isWord && q == first;
+    const bool in = head && dc > 0;  // |dom| changed since the last call: in s_val
+    const int policy = E.policy;
+    const int inc = policy == 2 ? 1 : policy == 1 ? 0 : (dc < sz ? 1 : 0);
+    const int cnt = in ? (inc ? dc : sz) : 0;
+    const int scSeg = e_wscan(in ? 1 : 0), scCnt = e_wscan(cnt);
+    const int nseg = __builtin_amdgcn_readlane(scSeg, WAVE - 1), nrows = __builtin_amdgcn_readlane(scCnt, WAVE - 1);
+    if (in) {
+      E.segEnd[scSeg - 1] = scCnt;
+      E.segInc[scSeg - 1] = inc;
+    }
+    // rows of each word: at its variable's segment start plus the rows of
+    // the variable's earlier words
+    const int vIn = __shfl(in ? 1 : 0, first), vInc = __shfl(inc, first), vStart = __shfl(scCnt - cnt, first);
+    const uint64_t bits = (isWord && vIn) ? (vInc ? (ld & ~din) : din) : 0ull;
+    const int nb = __popcll(bits);
+    const int scB = e_wscan(nb);
+    const int befB = __shfl(scB, max(first - 1, 0));
+    if (status == ST_OK && nseg > 0) {
+      int off = vStart + (scB - nb) - (first > 0 ? befB : 0);
+      const int base = v.rowStart + (q - v.domOff) * 64;
+      uint64_t b = bits;
+      while (b) {
+        const int k = __ffsll((unsigned long long)b) - 1;
+        b &= b - 1;
+        E.rowList[off++] = (uint16_t)(base + k);
+      }
+    }
+    if (q == 0) {
+      st->status = status;
+      st->nseg = nseg;
+      st->nrows = nrows;
+      st->noop = nseg == 0;
+    }
+  }
+  lds_barrier();
+}
+
+// ---------------------------------------------------------------------------
+// updateTable (Alg. 2) over the active granules: currTable in LDS, support
+// rows from HBM; first changes of a level are saved on the trail
+// ---------------------------------------------------------------------------
+__device__ void e_update(Eng& E) {
+  EngState* st = E.st;
+  const int lane = e_lane();
+  const int limit = st->limit, nseg = st->nseg, nrows = st->nrows, serial = st->serial;
+  const uint16_t* idxCur = st->cur ? E.idx1 : E.idx0;
+  const bool trailOn = st->depthAfter > 0;  // levels exist only above depth 0
+  const int64_t trailTop = st->trailTop;
+  unsigned long long nAct = 0, nTrail = 0;
+  for (int base = e_wave() * E_NG; base < limit; base += EWAVES * E_NG) {
+    int pos[E_NG], gs[E_NG], stv[E_NG];
+    bool act[E_NG];
+    uint64_t old[E_NG], m[E_NG], acc[E_NG];
+#pragma unroll
+    for (int u = 0; u < E_NG; ++u) {
+      pos[u] = base + u;
+      act[u] = pos[u] < limit;
+      gs[u] = act[u] ? __builtin_amdgcn_readfirstlane((int)idxCur[pos[u]]) : 0;  // same on every lane
+      old[u] = E.ct[(int64_t)gs[u] * GW + lane];
+      stv[u] = E.stamp[gs[u]];
+      m[u] = ~0ull;
+      acc[u] = 0ull;
+      nAct += act[u] ? 1 : 0;
+    }
+    int seg = 0;
+    int segEnd = nseg > 0 ? E.segEnd[0] : 0;
+    for (int k0 = 0; k0 < nrows; k0 += E_ROWS) {
+      uint64_t v[E_ROWS][E_NG];
+#pragma unroll
+      for (int j = 0; j < E_ROWS; ++j) {
+        const int k = k0 + j;
+        // rows past the end are never used; the row is the same on every lane
+        const int r = k < nrows ? __builtin_amdgcn_readfirstlane((int)E.rowList[k]) : 0;
+#pragma unroll
+        for (int u = 0; u < E_NG; ++u) {
+          // uniform base (scalar registers) + lane offset
+          const CT_G uint64_t* base = E.S + ((int64_t)r * E.stride + (int64_t)gs[u] * GW);
+          v[j][u] = base[lane];
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < E_ROWS; ++j) {
+        const int k = k0 + j;
+        if (k >= nrows) break;
+        while (k >= segEnd) {
+          const int inc = E.segInc[seg];
+#pragma unroll
+          for (int u = 0; u < E_NG; ++u) {
+            m[u] &= inc ? ~acc[u] : acc[u];
+            acc[u] = 0ull;
+          }
+          ++seg;
+          segEnd = E.segEnd[seg];
+        }
+#pragma unroll
+        for (int u = 0; u < E_NG; ++u) acc[u] |= v[j][u];
+      }
+    }
+    while (seg < nseg) {  // remaining segments (an empty reset segment gives 0)
+      const int inc = E.segInc[seg];
+#pragma unroll
+      for (int u = 0; u < E_NG; ++u) {
+        m[u] &= inc ? ~acc[u] : acc[u];
+        acc[u] = 0ull;
+      }
+      ++seg;
+    }
+    uint64_t nw[E_NG];
+    bool need[E_NG], changed[E_NG];
+    int nNeed = 0;
+#pragma unroll
+    for (int u = 0; u < E_NG; ++u) {
+      nw[u] = old[u] & m[u];
+      changed[u] = act[u] && (__ballot(nw[u] != old[u]) != 0ull);
+      need[u] = changed[u] && trailOn && stv[u] != serial;
+      nNeed += need[u] ? 1 : 0;
+    }
+    int tb = 0;
+    if (nNeed) {
+      if (lane == 0) tb = atomicAdd(&st->trailCount, nNeed);
+      tb = __shfl(tb, 0);
+    }
+#pragma unroll
+    for (int u = 0; u < E_NG; ++u) {
+      if (!act[u]) continue;
+      if (need[u]) {
+        const int64_t tp = trailTop + tb++;
+        if (tp < E.trailCap) {
+          E.trailWords[tp * GW + lane] = old[u];
+          if (lane == 0) {
+            TrailHdr h;
+            h.gran = gs[u];
+            h.oldStamp = stv[u];
+            E.trailHdr[tp] = h;
+            E.stamp[gs[u]] = serial;
+          }
+        } else if (lane == 0) {
+          st->devErr = 2;  // capacity is sized so that this cannot happen
+        }
+      }
+      if (changed[u]) E.ct[(int64_t)gs[u] * GW + lane] = nw[u];
+      const bool nzv = __ballot(nw[u] != 0ull) != 0ull;
+      if (lane == 0) E.nz[pos[u]] = nzv ? 1 : 0;
+    }
+    nTrail += nNeed;
+  }
+  if (lane == 0) {
+    if (nAct) atomicAdd(&st->stat[S_GRAN_ROWS], nAct * (unsigned long long)nrows);
+    if (nTrail) atomicAdd(&st->stat[S_TRAIL], nTrail);
+  }
+  lds_barrier();
+}
+
+// stable partition of the active granules (survivors first), new limit,
+// FAIL when none survives (Alg. 1); wave 0, 64 positions per step
+__device__ void e_partition(Eng& E) {
+  EngState* st = E.st;
+  if (threadIdx.x < WAVE) {
+    const int lane = e_lane();
+    const int limit = st->limit, cur = st->cur, nGran = E.nGran;
+    const uint16_t* src = cur ? E.idx1 : E.idx0;
+    uint16_t* dst = cur ? E.idx0 : E.idx1;
+    const uint64_t below = (1ull << lane) - 1ull;
+    int nSurv = 0;
+    for (int p0 = 0; p0 < limit; p0 += WAVE) {
+      const int p = p0 + lane;
+      nSurv += __popcll(__ballot(p < limit && E.nz[p]));
+    }
+    int sv = 0, zr = nSurv;
+    for (int p0 = 0; p0 < limit; p0 += WAVE) {
+      const int p = p0 + lane;
+      const bool in = p < limit;
+      const bool f = in && E.nz[p];
+      const uint64_t bs = __ballot(f), bz = __ballot(in && !f);
+      if (f) dst[sv + __popcll(bs & below)] = src[p];
+      else if (in) dst[zr + __popcll(bz & below)] = src[p];
+      sv += __popcll(bs);
+      zr += __popcll(bz);
+    }
+    for (int p = limit + lane; p < nGran; p += WAVE) dst[p] = src[p];
+    if (lane == 0) {
+      st->cur = 1 - cur;
+      st->limit = nSurv;
+      st->trailTop += st->trailCount;
+      st->trailCount = 0;
+      if (nSurv == 0) {
+        st->status = ST_FAIL;
+        st->failed = 1;
+      }
+    }
+  }
+  lds_barrier();
+}
+
+// ---------------------------------------------------------------------------
+// filterDomains (Alg. 3) for domain word q, by one wave: residue first, then
+// the words after it, then the active granules in index order
+// ---------------------------------------------------------------------------
+// The support word at a value's residue does not depend on currTable: it is
+// loaded before updateTable (e_residue_word) and tested after it.
+struct ResidueWord {
+  int rl, rw0;
+  uint64_t x;
+};
+
+__device__ __forceinline__ ResidueWord e_residue_word(const Eng& E, int q) {
+  const int lane = e_lane();
+  const VarDesc v = E.vars[E.wordVar[q]];
+  const int rowBase = v.rowStart + (q - v.domOff) * 64;
+  const bool present = (E.din[q] >> lane) & 1ull;
+  ResidueWord r;
+  r.rl = present ? rowBase + lane : rowBase;
+  r.rw0 = E.res[r.rl];
+  r.x = E.S[(int64_t)r.rl * E.stride + r.rw0];
+  return r;
+}
+
+__device__ void e_filter_word(Eng& E, int q, unsigned long long* cnt, bool havePre, ResidueWord pre) {
+  EngState* st = E.st;
+  const int lane = e_lane();
+  const int i = E.wordVar[q];
+  const VarDesc v = E.vars[i];
+  const uint64_t din = E.din[q];
+  int size = 0;
+  for (int k = v.domOff; k < v.domOff + v.domWords; ++k) size += __popcll(E.din[k]);
+  uint64_t dout = din;
+  if (!st->noop && size > 1) {  // s_sup: non-singleton variables
+    const int64_t stride = E.stride;
+    const int rowBase = v.rowStart + (q - v.domOff) * 64;
+    const bool present = (din >> lane) & 1ull;
+    const ResidueWord rwd = havePre ? pre : e_residue_word(E, q);
+    const int rl = rwd.rl, rw0 = rwd.rw0;
+    const bool hit = present && (E.ct[rw0] & rwd.x) != 0ull;
+    unsigned long long miss = __ballot(present && !hit);
+    cnt[0] += __popcll(__ballot(present));
+    cnt[1] += __popcll(miss);
+    if (miss) {
+      const bool mine = (miss >> lane) & 1ull;
+      const int64_t words = (int64_t)E.nGran * GW;
+      bool found = false;
+      const CT_G uint64_t* row = E.S + (int64_t)rl * stride;
+      for (int j0 = 0; j0 < E_LANE_SCAN; j0 += 8) {
+        uint64_t x[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+          int64_t w = rw0 + 1 + j0 + j;
+          if (w >= words) w -= words;
+          x[j] = row[w];
+        }
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+          int64_t w = rw0 + 1 + j0 + j;
+          if (w >= words) w -= words;
+          if (mine && !found && (E.ct[w] & x[j])) {
+            found = true;
+            E.res[rl] = (int)w;
+          }
+        }
+        if (!__ballot(mine && !found)) break;
+      }
+      cnt[2] += __popcll(__ballot(mine));
+      miss = __ballot(mine && !found);
+    }
+    // the values still without a support scan the active granules in index
+    // order together, up to 3 values x 4 granules per step
+    uint64_t todo = miss;
+    const int lim = st->limit;
+    const uint16_t* idx = st->cur ? E.idx1 : E.idx0;
+    for (int p = 0; p < lim && todo; p += 4) {
+      int gg[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) gg[j] = (p + j < lim) ? (int)idx[p + j] : -1;
+      cnt[2] += (unsigned long long)min(4, lim - p) * (unsigned long long)__popcll(todo);
+      uint64_t t = todo;
+      while (t) {
+        int ls[3];
+#pragma unroll
+        for (int u = 0; u < 3; ++u) {
+          ls[u] = t ? __ffsll((unsigned long long)t) - 1 : -1;
+          t &= t - 1;
+        }
+        uint64_t y[3][4];
+#pragma unroll
+        for (int u = 0; u < 3; ++u) {
+          const CT_G uint64_t* row = E.S + (int64_t)(rowBase + max(ls[u], 0)) * stride;
+#pragma unroll
+          for (int j = 0; j < 4; ++j) y[u][j] = row[(int64_t)max(gg[j], 0) * GW + lane];
+        }
+#pragma unroll
+        for (int u = 0; u < 3; ++u) {
+          if (ls[u] < 0) continue;
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            if (gg[j] < 0) break;
+            const unsigned long long bm = __ballot((E.ct[(int64_t)gg[j] * GW + lane] & y[u][j]) != 0ull);
+            if (bm) {
+              if (lane == 0) E.res[rowBase + ls[u]] = gg[j] * GW + (__ffsll(bm) - 1);
+              todo &= ~(1ull << ls[u]);
+              break;
+            }
+          }
+        }
+      }
+    }
+    dout = din & ~todo;
+  }
+  if (lane == 0) E.last[q] = dout;
+}
+
+__device__ void e_load(Eng& E, const EngDesc& D) {
+  const CT_G SlotDesc* s = E.slot;
+  EngState* st = E.st;
+  const int cur = s->cur;
+  const CT_G uint64_t* ct = s->ct;
+  const CT_G int32_t* idx = s->idx[cur];
+  for (int64_t i = threadIdx.x; i < (int64_t)E.nGran * GW; i += EBLOCK) E.ct[i] = ct[i];
+  for (int p = threadIdx.x; p < E.nGran; p += EBLOCK) {
+    E.idx0[p] = (uint16_t)idx[p];
+    E.stamp[p] = s->stamp[p];
+  }
+  for (int r = threadIdx.x; r < E.rows; r += EBLOCK) E.res[r] = s->res[r];
+  for (int q = threadIdx.x; q < E.D; q += EBLOCK) {
+    E.last[q] = s->lastDom[q];
+    E.wordVar[q] = D.tab->wordVar[q];
+  }
+  for (int i = threadIdx.x; i < E.n; i += EBLOCK) E.vars[i] = D.tab->vars[i];
+  if (threadIdx.x == 0) {
+    st->lastSeq = D.startSeq;
+    st->limit = s->limit;
+    st->failed = s->failed;
+    st->depth = s->depth;
+    st->serial = s->serial;
+    st->trailTop = s->trailTop;
+    st->cur = 0;
+    st->trailCount = 0;
+    st->devErr = 0;
+  }
+  if (threadIdx.x < 8) st->stat[threadIdx.x] = s->stats[threadIdx.x];
+  __syncthreads();
+}
+
+__device__ void e_store(Eng& E) {
+  CT_G SlotDesc* s = E.slot;
+  EngState* st = E.st;
+  CT_G uint64_t* ct = s->ct;
+  CT_G int32_t* idx = s->idx[0];
+  for (int64_t i = threadIdx.x; i < (int64_t)E.nGran * GW; i += EBLOCK) ct[i] = E.ct[i];
+  for (int p = threadIdx.x; p < E.nGran; p += EBLOCK) {
+    idx[p] = (st->cur ? E.idx1 : E.idx0)[p];
+    s->stamp[p] = E.stamp[p];
+  }
+  for (int r = threadIdx.x; r < E.rows; r += EBLOCK) s->res[r] = E.res[r];
+  for (int q = threadIdx.x; q < E.D; q += EBLOCK) s->lastDom[q] = E.last[q];
+  if (threadIdx.x < 8) s->stats[threadIdx.x] = st->stat[threadIdx.x];
+  if (threadIdx.x == 0) {
+    s->cur = 0;
+    s->limit = st->limit;
+    s->failed = st->failed;
+    s->depth = st->depth;
+    s->serial = st->serial;
+    s->trailTop = st->trailTop;
+  }
+  __threadfence();
+  __syncthreads();
+}
+
+}  // namespace
+
+__global__ void __launch_bounds__(EBLOCK) engine_kernel(EngDesc D) {
+  extern __shared__ uint64_t ldsWords[];
+  char* lds = (char*)ldsWords;
+  const CT_G TabDesc* T = D.tab;
+  Eng E;
+  E.S = T->S;
+  E.stride = T->stride;
+  E.W = T->W;
+  E.n = T->n;
+  E.D = T->D;
+  E.nGran = T->nGran;
+  E.rows = T->rows;
+  E.policy = T->policy;
+  E.slot = D.slot;
+  E.trailHdr = D.slot->trailHdr;
+  E.trailWords = D.slot->trailWords;
+  E.levels = D.slot->levels;
+  E.levelDom = D.slot->levelDom;
+  E.trailCap = D.slot->trailCap;
+  size_t off[R_END + 1];
+  eng_layout(E.n, E.D, E.nGran, E.rows, off);
+  E.ct = (uint64_t*)(lds + off[R_CT]);
+  E.idx0 = (uint16_t*)(lds + off[R_IDX0]);
+  E.idx1 = (uint16_t*)(lds + off[R_IDX1]);
+  E.stamp = (int32_t*)(lds + off[R_STAMP]);
+  E.nz = (uint8_t*)(lds + off[R_NZ]);
+  E.first = (int32_t*)(lds + off[R_FIRST]);
+  E.res = (int32_t*)(lds + off[R_RES]);
+  E.last = (uint64_t*)(lds + off[R_LAST]);
+  E.din = (uint64_t*)(lds + off[R_DIN]);
+  E.rowList = (uint16_t*)(lds + off[R_ROWS]);
+  E.wordVar = (int32_t*)(lds + off[R_WVAR]);
+  E.vars = (VarDesc*)(lds + off[R_VARS]);
+  E.vsize = (int32_t*)(lds + off[R_VSIZE]);
+  E.vdcnt = (int32_t*)(lds + off[R_VDCNT]);
+  E.segOf = (int32_t*)(lds + off[R_SEGOF]);
+  E.segEnd = (int32_t*)(lds + off[R_SEGEND]);
+  E.segInc = (int32_t*)(lds + off[R_SEGINC]);
+  E.st = (EngState*)(lds + off[R_STATE]);
+  EngState* st = E.st;
+  EngCmd* cmd = D.cmd;
+  EngRes* res = D.res;
+
+  e_load(E, D);
+  for (;;) {
+    // wave 0 waits for a call (bounded: an idle engine exits), then reads
+    // the whole command, header and domains, in one wave-wide load
+    if (threadIdx.x < WAVE) {
+      int seen = 0;
+      if (threadIdx.x == 0) {
+        const unsigned long long t0 = wall_clock64();
+        for (;;) {
+          const int sq = __hip_atomic_load(&cmd->seq, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_SYSTEM);
+          if (sq != st->lastSeq) {
+            st->seq = sq;
+            seen = 1;
+            break;
+          }
+          if ((long long)(wall_clock64() - t0) > D.idleTicks) break;
+          __builtin_amdgcn_s_sleep(8);
+        }
+      }
+      seen = __shfl(seen, 0);
+      constexpr int HDR = (int)(offsetof(EngCmd, dom) / 8);  // header words
+      uint64_t w0 = 0, w1 = 0;
+      if (seen) {
+        const uint64_t* words = (const uint64_t*)cmd;
+        const int l = threadIdx.x;
+        w0 = l < HDR + E.D ? words[l] : 0ull;
+        w1 = l + WAVE < HDR + E.D ? words[l + WAVE] : 0ull;
+        if (l >= HDR && l < HDR + E.D) E.din[l - HDR] = w0;
+        if (l + WAVE - HDR < E.D) E.din[l + WAVE - HDR] = w1;
+      }
+      // header words: {seq, op}, {nPop, nPush}, {serialBase, depthAfter}, {wantCt, pad}
+      const uint64_t h0 = __shfl(w0, 0), h1 = __shfl(w0, 1), h2 = __shfl(w0, 2), h3 = __shfl(w0, 3);
+      if (threadIdx.x == 0) {
+        st->op = seen ? (int32_t)(h0 >> 32) : 0;
+        st->nPop = (int32_t)h1;
+        st->nPush = (int32_t)(h1 >> 32);
+        st->serialBase = (int32_t)h2;
+        st->depthAfter = (int32_t)(h2 >> 32);
+        st->wantCt = (int32_t)h3;
+      }
+    }
+    lds_barrier();
+    if (st->op != ENG_OP_PROPAGATE) break;
+    const unsigned long long tStart = wall_clock64();
+
+    e_pops_pushes(E);
+    e_prologue(E);
+    // residue words of this wave's first domain word, in flight during the update
+    ResidueWord pre{0, 0, 0ull};
+    const bool havePre = st->status == ST_OK && !st->noop && e_wave() < E.D;
+    if (havePre) pre = e_residue_word(E, e_wave());
+    if (st->status == ST_OK && !st->noop) {
+      const int limitIn = st->limit;
+      e_update(E);
+      e_partition(E);
+      if (threadIdx.x == 0) {
+        atomicAdd(&st->stat[S_JOBS], 1ull);
+        atomicAdd(&st->stat[S_GRAN_IN], (unsigned long long)limitIn);
+        atomicAdd(&st->stat[S_ROWS], (unsigned long long)st->nrows);
+      }
+    } else if (st->status == ST_OK && threadIdx.x == 0) {
+      atomicAdd(&st->stat[S_JOBS], 1ull);
+      atomicAdd(&st->stat[S_GRAN_IN], (unsigned long long)st->limit);
+    }
+    lds_barrier();
+    if (st->status == ST_OK) {
+      unsigned long long cnt[3] = {0, 0, 0};
+      for (int q = e_wave(); q < E.D; q += EWAVES)
+        e_filter_word(E, q, cnt, havePre && q == e_wave(), pre);
+      if (e_lane() == 0 && (cnt[0] | cnt[1] | cnt[2])) {
+        atomicAdd(&st->stat[S_RES_CHECK], cnt[0]);
+        atomicAdd(&st->stat[S_RES_MISS], cnt[1]);
+        atomicAdd(&st->stat[S_SCAN], cnt[2]);
+      }
+    }
+    lds_barrier();
+    // wave 0 writes every output to host memory, so that its system-scope
+    // fence covers them all before the sequence number is published
+    if (threadIdx.x < WAVE) {
+      if (st->status == ST_OK) {
+        for (int q = threadIdx.x; q < E.D; q += WAVE) res->dom[q] = E.last[q];
+        if (st->wantCt)
+          for (int64_t w = threadIdx.x; w < E.W; w += WAVE) D.ctOut[w] = E.ct[w];
+      }
+      if (threadIdx.x < 8) res->stats[threadIdx.x] = st->stat[threadIdx.x];
+      if (threadIdx.x == 0) {
+        res->status = st->devErr ? ST_DEVICE : st->status;
+        res->callTicks = wall_clock64() - tStart;
+        st->lastSeq = st->seq;
+      }
+      // system-scope release: the outputs (written back from L2 where the
+      // device caches them) are visible before the sequence number
+      __threadfence_system();
+      if (threadIdx.x == 0)
+        __hip_atomic_store(&res->seq, st->seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+    }
+    __syncthreads();
+  }
+  e_store(E);
+  if (threadIdx.x == 0) {
+    res->exitSeq = st->lastSeq;
+    __threadfence_system();
+    __hip_atomic_store(&res->alive, 0, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// host side
+// ---------------------------------------------------------------------------
+size_t engine_lds_bytes(int n, int D, int nGran, int rows) {
+  size_t off[R_END + 1];
+  eng_layout(n, D, nGran, rows, off);
+  return off[R_END];
+}
+
+hipError_t launch_engine(const EngDesc& D, size_t lds, hipStream_t stream) {
+  hipLaunchKernelGGL(engine_kernel, dim3(1), dim3(EBLOCK), lds, stream, D);
+  return hipGetLastError();
+}
+
+}  // namespace ctk

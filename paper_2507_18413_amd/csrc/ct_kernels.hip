@@ -394,17 +394,25 @@ __device__ void update_granules(const KArgs& a, const DevJob& J, Shared& sh, int
   const CT_G int32_t* srcIdx = fromRoot ? T->idx0 : s->idx[s->cur];
   const int64_t trailTop = sh.trailTop;
 
+  // Loads below are unconditional, from clamped (always valid) addresses, and
+  // their results are selected afterwards: a load under a branch is followed
+  // by a wait for it, which would serialize the round trips to memory.
   unsigned long long nAct = 0;
-  int pos[NG], g[NG], stv[NG];
+  int pos[NG], g[NG], gs[NG], stv[NG];
   bool act[NG];
   uint64_t old[NG], m[NG], acc[NG];
 #pragma unroll
   for (int u = 0; u < NG; ++u) {
     pos[u] = p0 + u;
-    g[u] = pos[u] < nGran ? (lds ? (int)sh.gidx[pos[u]] : srcIdx[pos[u]]) : -1;
+    const int pc = min(pos[u], nGran - 1);
+    g[u] = lds ? (int)sh.gidx[pc] : srcIdx[pc];
+    if (pos[u] >= nGran) g[u] = -1;
     act[u] = pos[u] < limit && status == ST_OK;
-    old[u] = act[u] ? srcCt[(int64_t)g[u] * GW + lane] : 0ull;
-    stv[u] = (act[u] && trailOn && !noop) ? s->stamp[g[u]] : serial;
+    gs[u] = act[u] ? g[u] : 0;
+    const uint64_t o = srcCt[(int64_t)gs[u] * GW + lane];
+    const int sv = s->stamp[gs[u]];
+    old[u] = act[u] ? o : 0ull;
+    stv[u] = (act[u] && trailOn && !noop) ? sv : serial;
     m[u] = ~0ull;
     acc[u] = 0ull;
     nAct += act[u] ? 1 : 0;
@@ -417,10 +425,9 @@ __device__ void update_granules(const KArgs& a, const DevJob& J, Shared& sh, int
 #pragma unroll
       for (int j = 0; j < ROW_UNROLL; ++j) {
         const int k = k0 + j;
-        const int r = k < nrows ? (int)sh.rows[k] : -1;
+        const int r = k < nrows ? (int)sh.rows[k] : 0;  // rows past the end are never used
 #pragma unroll
-        for (int u = 0; u < NG; ++u)
-          v[j][u] = (r >= 0 && act[u]) ? T->S[(int64_t)r * stride + (int64_t)g[u] * GW + lane] : 0ull;
+        for (int u = 0; u < NG; ++u) v[j][u] = T->S[(int64_t)r * stride + (int64_t)gs[u] * GW + lane];
       }
 #pragma unroll
       for (int j = 0; j < ROW_UNROLL; ++j) {
@@ -464,6 +471,15 @@ __device__ void update_granules(const KArgs& a, const DevJob& J, Shared& sh, int
     wr[u] = act[u] && (changed || fromRoot || root);
   }
   int tbase = 0;
+  // the slot's arrays, read once: the stores below could otherwise force a
+  // reload (and a wait) of the descriptor before each of them
+  const int64_t trailCap = s->trailCap;
+  CT_G uint64_t* const sCt = s->ct;
+  CT_G uint64_t* const sTrailWords = s->trailWords;
+  CT_G TrailHdr* const sTrailHdr = s->trailHdr;
+  CT_G int32_t* const sStamp = s->stamp;
+  CT_G int32_t* const sNz = s->nzFlag;
+  CT_G uint64_t* const ctOut = J.ct_out;
   if (nNeed) {
     if (lane == 0) tbase = atomicAdd(trailCounter, nNeed);
     tbase = __shfl(tbase, 0);
@@ -474,31 +490,31 @@ __device__ void update_granules(const KArgs& a, const DevJob& J, Shared& sh, int
     const int64_t w = (int64_t)g[u] * GW + lane;
     if (pos[u] >= limit) {
       // inactive granule (all zero by invariant)
-      if (fromRoot) s->ct[w] = 0ull;
-      if (J.ct_out && w < W) J.ct_out[w] = 0ull;
+      if (fromRoot) sCt[w] = 0ull;
+      if (ctOut && w < W) ctOut[w] = 0ull;
       continue;
     }
     if (need[u]) {
       const int64_t tp = trailTop + tbase++;
-      if (tp < s->trailCap) {
-        s->trailWords[tp * GW + lane] = old[u];
+      if (tp < trailCap) {
+        sTrailWords[tp * GW + lane] = old[u];
         if (lane == 0) {
           TrailHdr h;
           h.gran = g[u];
           h.oldStamp = stv[u];
-          s->trailHdr[tp] = h;
-          s->stamp[g[u]] = serial;
+          sTrailHdr[tp] = h;
+          sStamp[g[u]] = serial;
         }
       } else if (lane == 0) {
         raise_error(a, 2);  // capacity is sized so that this cannot happen
       }
     }
-    if (wr[u]) s->ct[w] = nw[u];
-    if (J.ct_out && w < W) J.ct_out[w] = nw[u];
+    if (wr[u]) sCt[w] = nw[u];
+    if (ctOut && w < W) ctOut[w] = nw[u];
     const bool nz = __ballot(nw[u] != 0ull) != 0ull;
     if (lane == 0) {
       if (lds) sh.nz[pos[u]] = nz ? 1 : 0;
-      else s->nzFlag[pos[u]] = nz ? 1 : 0;
+      else sNz[pos[u]] = nz ? 1 : 0;
     }
   }
   if (lane == 0 && status == ST_OK) {
@@ -572,7 +588,12 @@ __device__ int finalize_update(const DevJob& J, Shared& sh, bool ldsFlags, int j
 __device__ void filter_word(const KArgs& a, const DevJob& J, int q, int noop, int lim,
                             const CT_G int32_t* idx, unsigned long long* cnt) {
   const TabDesc* T = J.tab;
-  SlotDesc* s = J.slot;
+  SlotDesc* slot = J.slot;
+  // the slot's arrays, read once (see update_granules)
+  struct {
+    CT_G uint64_t* ct;
+    CT_G int32_t* res;
+  } sv{slot->ct, slot->res}, *s = &sv;
   const int lane = lane_id();
   const int i = T->wordVar[q];
   const VarDesc v = T->vars[i];
@@ -584,12 +605,11 @@ __device__ void filter_word(const KArgs& a, const DevJob& J, int q, int noop, in
     const int64_t stride = T->stride;
     const int rowBase = v.rowStart + (q - v.domOff) * 64;
     const bool present = (din >> lane) & 1ull;
-    bool hit = false;
-    if (present) {
-      const int r = rowBase + lane;
-      const int rw = s->res[r];
-      hit = (s->ct[rw] & T->S[(int64_t)r * stride + rw]) != 0ull;
-    }
+    // unconditional loads from valid addresses (row of the word's first value
+    // for absent lanes), results selected afterwards
+    const int rl = present ? rowBase + lane : rowBase;
+    const int rw0 = s->res[rl];
+    const bool hit = present && (s->ct[rw0] & T->S[(int64_t)rl * stride + rw0]) != 0ull;
     unsigned long long miss = __ballot(present && !hit);
     cnt[0] += __popcll(__ballot(present));
     cnt[1] += __popcll(miss);
@@ -599,9 +619,9 @@ __device__ void filter_word(const KArgs& a, const DevJob& J, int q, int noop, in
       // (wrapping at the end of the table): a value's supports are spread
       // over the whole table, so a nearby word usually still holds one
       const bool mine = (miss >> lane) & 1ull;
-      const int r = rowBase + lane;
+      const int r = rl;
       const int64_t words = (int64_t)T->nGran * GW;
-      int64_t w = mine ? (int64_t)s->res[r] : 0;
+      int64_t w = mine ? (int64_t)rw0 : 0;
       bool found = false;
 #pragma unroll 1
       for (int step = 0; step < LANE_SCAN; step += 4) {
@@ -611,7 +631,8 @@ __device__ void filter_word(const KArgs& a, const DevJob& J, int q, int noop, in
         for (int j = 0; j < 4; ++j) {
           ww[j] = w + 1 + step + j;
           if (ww[j] >= words) ww[j] -= words;
-          x[j] = (mine && !found) ? (s->ct[ww[j]] & T->S[(int64_t)r * stride + ww[j]]) : 0ull;
+          const uint64_t y = s->ct[ww[j]] & T->S[(int64_t)r * stride + ww[j]];
+          x[j] = (mine && !found) ? y : 0ull;
         }
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
@@ -635,8 +656,10 @@ __device__ void filter_word(const KArgs& a, const DevJob& J, int q, int noop, in
       uint64_t c[4];
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
-        gg[j] = (p + j < lim) ? idx[p + j] : -1;
-        c[j] = gg[j] >= 0 ? s->ct[(int64_t)gg[j] * GW + lane] : 0ull;
+        const int gv = idx[min(p + j, lim - 1)];
+        gg[j] = (p + j < lim) ? gv : -1;
+        const uint64_t cv = s->ct[(int64_t)gv * GW + lane];
+        c[j] = gg[j] >= 0 ? cv : 0ull;
       }
       cnt[2] += (unsigned long long)min(4, lim - p) * (unsigned long long)__popcll(todo);
       uint64_t t = todo;
@@ -652,8 +675,10 @@ __device__ void filter_word(const KArgs& a, const DevJob& J, int q, int noop, in
         for (int v = 0; v < 3; ++v) {
           const CT_G uint64_t* row = T->S + (int64_t)(rowBase + max(ls[v], 0)) * stride;
 #pragma unroll
-          for (int j = 0; j < 4; ++j)
-            x[v][j] = (ls[v] >= 0 && gg[j] >= 0) ? (c[j] & row[(int64_t)gg[j] * GW + lane]) : 0ull;
+          for (int j = 0; j < 4; ++j) {
+            const uint64_t y = c[j] & row[(int64_t)max(gg[j], 0) * GW + lane];
+            x[v][j] = (ls[v] >= 0 && gg[j] >= 0) ? y : 0ull;
+          }
         }
 #pragma unroll
         for (int v = 0; v < 3; ++v) {
@@ -675,7 +700,7 @@ __device__ void filter_word(const KArgs& a, const DevJob& J, int q, int noop, in
   }
   if (lane == 0) {
     J.dom_out[q] = dout;
-    s->lastDom[q] = dout;
+    slot->lastDom[q] = dout;
   }
 }
 

@@ -27,6 +27,8 @@ int propagate_items_per_job_update(int nGran);
 int propagate_items_per_job_filter(int D);
 int propagate_max_grid();
 hipError_t launch_propagate(const KArgs& a, int grid, hipStream_t stream);
+size_t engine_lds_bytes(int n, int D, int nGran, int rows);
+hipError_t launch_engine(const EngDesc& D, size_t lds, hipStream_t stream);
 int nodes_max_rows();
 int nodes_list_cap(int rows, int n);
 int nodes_node_words(int rows, int n);
@@ -156,6 +158,14 @@ struct ct_table {
   // (no host events: they would add dispatch packets to every call)
   unsigned long long* dClock = nullptr;  // 5 words, see KArgs::clock
   bool timing = false;
+  // resident engine of slot 0 (see ct_engine.hip)
+  bool engEligible = false, engOn = false;
+  size_t engLds = 0;
+  hipStream_t engStream = nullptr;
+  EngCmd* pCmd = nullptr;   // coherent pinned mailbox
+  EngRes* pRes = nullptr;
+  int32_t engSeq = 0;
+  unsigned long long engTicks = 0, engCalls = 0;  // timing of engine calls
 };
 
 namespace {
@@ -282,7 +292,11 @@ bool needs_prep(const DevJob& J) {
 }
 
 // Run one job synchronously on the table's stream.
+int quiesce(ct_table* T);
+
 int run_single(ct_table* T, DevJob& J, const uint64_t* dom_in_host) {
+  int qrc = quiesce(T);
+  if (qrc) return qrc;
   KArgs a{};
   a.jobs = nullptr;
   a.nJobs = 1;
@@ -339,6 +353,138 @@ int run_single(ct_table* T, DevJob& J, const uint64_t* dom_in_host) {
   return CT_OK;
 }
 
+int ensure_pinned_ct(ct_table* T);
+
+// ---------------------------------------------------------------------------
+// resident engine of a table's slot 0 (one engine alive per process: each
+// holds a hardware queue while it waits for calls)
+// ---------------------------------------------------------------------------
+std::mutex g_engMu;
+ct_table* g_engOwner = nullptr;
+std::set<ct_table*> g_tables;  // live tables (for ct_quiesce)
+constexpr double kEngineIdleMs = 2.0;  // an engine without calls for this long exits
+
+int64_t engine_idle_ticks() {
+  int dev = 0, khz = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess || khz <= 0)
+    khz = 100000;
+  return (int64_t)(kEngineIdleMs * khz);
+}
+
+// Waits for the engine of T to end (it has exited or was told to) and
+// marks it stopped; its state is then back in the slot's device arrays.
+int engine_join(ct_table* T) {
+  const auto t0 = std::chrono::steady_clock::now();
+  while (__atomic_load_n(&T->pRes->alive, __ATOMIC_ACQUIRE) != 0) {
+    if (std::chrono::steady_clock::now() - t0 > std::chrono::seconds(2)) break;
+  }
+  hipError_t e = hipStreamSynchronize(T->engStream);
+  T->engOn = false;
+  if (g_engOwner == T) g_engOwner = nullptr;
+  if (e != hipSuccess) {
+    T->poisoned = true;
+    return fail(CT_E_DEVICE, "engine failed: %s", hipGetErrorString(e));
+  }
+  return CT_OK;
+}
+
+int engine_stop(ct_table* T) {
+  if (!T || !T->engOn) return CT_OK;
+  if (__atomic_load_n(&T->pRes->alive, __ATOMIC_ACQUIRE) != 0) {
+    T->pCmd->op = ENG_OP_STOP;
+    __atomic_store_n(&T->pCmd->seq, ++T->engSeq, __ATOMIC_RELEASE);
+  }
+  return engine_join(T);
+}
+
+int engine_start(ct_table* T) {
+  if (g_engOwner && g_engOwner != T) {
+    int rc = engine_stop(g_engOwner);
+    if (rc) return rc;
+  }
+  if (T->tailPending) {  // earlier launches on the slot end first
+    HIPCHK(hipStreamSynchronize(T->stream));
+    T->tailPending = false;
+  }
+  if (!T->engStream) HIPCHK(hipStreamCreateWithFlags(&T->engStream, hipStreamNonBlocking));
+  if (!T->pCmd) {
+    HIPCHK(hipHostMalloc((void**)&T->pCmd, sizeof(EngCmd), hipHostMallocMapped | hipHostMallocCoherent));
+    HIPCHK(hipHostMalloc((void**)&T->pRes, sizeof(EngRes), hipHostMallocMapped | hipHostMallocCoherent));
+    memset((void*)T->pCmd, 0, sizeof(EngCmd));
+    memset((void*)T->pRes, 0, sizeof(EngRes));
+  }
+  int rc = ensure_pinned_ct(T);
+  if (rc) return rc;
+  EngDesc D{};
+  D.tab = T->dTab;
+  D.slot = T->slots[0].dev;
+  HIPCHK(hipHostGetDevicePointer((void**)&D.cmd, T->pCmd, 0));
+  HIPCHK(hipHostGetDevicePointer((void**)&D.res, T->pRes, 0));
+  HIPCHK(hipHostGetDevicePointer((void**)&D.ctOut, T->pCt, 0));
+  D.idleTicks = engine_idle_ticks();
+  D.startSeq = T->engSeq;
+  T->pRes->seq = T->engSeq;
+  __atomic_store_n(&T->pRes->alive, 1, __ATOMIC_RELEASE);
+  HIPCHK(launch_engine(D, T->engLds, T->engStream));
+  T->engOn = true;
+  g_engOwner = T;
+  return CT_OK;
+}
+
+// One call through the engine; *status receives the call's status and the
+// outputs are in T->pRes->dom and (wantCt) T->pCt.
+int engine_call(ct_table* T, const DevJob& J, const uint64_t* dom_in, bool wantCt, int* status) {
+  std::lock_guard<std::mutex> lk(g_engMu);
+  int rc;
+  if (T->engOn && __atomic_load_n(&T->pRes->alive, __ATOMIC_ACQUIRE) == 0 && (rc = engine_join(T))) return rc;
+  if (!T->engOn && (rc = engine_start(T))) return rc;
+  EngCmd* c = T->pCmd;
+  c->op = ENG_OP_PROPAGATE;
+  c->nPop = J.nPop;
+  c->nPush = J.nPush;
+  c->serialBase = J.serialBase;
+  c->depthAfter = J.depthAfter;
+  c->wantCt = wantCt ? 1 : 0;
+  memcpy(c->dom, dom_in, sizeof(uint64_t) * T->D);
+  const int32_t seq = ++T->engSeq;
+  __atomic_store_n(&c->seq, seq, __ATOMIC_RELEASE);
+  const auto t0 = std::chrono::steady_clock::now();
+  for (uint32_t spin = 0;; ++spin) {
+    if (__atomic_load_n(&T->pRes->seq, __ATOMIC_ACQUIRE) == seq) break;
+    if (__atomic_load_n(&T->pRes->alive, __ATOMIC_ACQUIRE) == 0) {
+      if (__atomic_load_n(&T->pRes->seq, __ATOMIC_ACQUIRE) == seq) break;
+      // the engine went idle before it saw this call: start a new one
+      if ((rc = engine_join(T))) return rc;
+      T->engSeq = seq - 1;
+      if ((rc = engine_start(T))) return rc;
+      T->engSeq = seq;
+      continue;
+    }
+    if ((spin & 1023) == 1023 && std::chrono::steady_clock::now() - t0 > std::chrono::seconds(2)) {
+      T->poisoned = true;
+      return fail(CT_E_DEVICE, "engine did not answer");
+    }
+  }
+  *status = T->pRes->status;
+  if (T->timing) {
+    T->engTicks += T->pRes->callTicks;
+    T->engCalls += 1;
+  }
+  return CT_OK;
+}
+
+bool engine_wanted(const ct_table* T) {
+  return T->engEligible && (T->cfg.schedule == CT_SCHED_AUTO || T->cfg.schedule == CT_SCHED_RESIDENT);
+}
+
+// Any other use of a table's device state first ends its engine.
+int quiesce(ct_table* T) {
+  if (!T || !T->engOn) return CT_OK;
+  std::lock_guard<std::mutex> lk(g_engMu);
+  return engine_stop(T);
+}
+
 int32_t* pinned_dev(ct_table* T, int32_t* host) {
   int32_t* d = nullptr;
   if (hipHostGetDevicePointer((void**)&d, host, 0) != hipSuccess) return nullptr;
@@ -390,8 +536,21 @@ extern "C" {
 
 const char* ct_last_error(void) { return g_err.c_str(); }
 
+int ct_quiesce(void) {
+  std::lock_guard<std::mutex> lk(g_engMu);
+  return g_engOwner ? engine_stop(g_engOwner) : CT_OK;
+}
+
 void ct_destroy(ct_table* T) {
   if (!T) return;
+  (void)quiesce(T);
+  {
+    std::lock_guard<std::mutex> lk(g_engMu);
+    g_tables.erase(T);
+  }
+  if (T->pCmd) (void)hipHostFree(T->pCmd);
+  if (T->pRes) (void)hipHostFree(T->pRes);
+  if (T->engStream) (void)hipStreamDestroy(T->engStream);
   if (T->stream) (void)hipStreamSynchronize(T->stream);
   for (void* p : T->blocks) (void)hipFree(p);
   queue_free(T->q);
@@ -546,7 +705,16 @@ static int create_impl(ct_table* T, const int32_t* tuples, int64_t t, int32_t n,
   }
   HIPCHK(hipMemcpy(T->dTab, &tb, sizeof(TabDesc), hipMemcpyHostToDevice));
   int first = 0;
-  return ct_slots_alloc(T, 1, -1, &first);
+  if ((rc = ct_slots_alloc(T, 1, -1, &first))) return rc;
+  // the resident engine holds the slot's state in one workgroup's LDS
+  T->engLds = engine_lds_bytes(T->n, T->D, T->nGran, T->rows);
+  int dev = 0, lds = 0;
+  HIPCHK(hipGetDevice(&dev));
+  HIPCHK(hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+  T->engEligible = T->D <= INLINE_WORDS && T->W > 0 && T->engLds <= (size_t)lds;
+  std::lock_guard<std::mutex> lk(g_engMu);
+  g_tables.insert(T);
+  return CT_OK;
 }
 
 int ct_create(const int32_t* tuples, int64_t n_tuples, int32_t arity, const int32_t* dom_lo,
@@ -566,7 +734,7 @@ int ct_create(const int32_t* tuples, int64_t n_tuples, int32_t arity, const int3
   T->cfg.max_depth = 256;
   T->cfg.schedule = CT_SCHED_AUTO;
   if (cfg) {
-    if (cfg->schedule < 0 || cfg->schedule > 3) {
+    if (cfg->schedule < 0 || cfg->schedule > 4) {
       delete T;
       return fail(CT_E_INVALID, "schedule %d", cfg->schedule);
     }
@@ -625,6 +793,7 @@ int ct_slots_alloc(ct_table* T, int32_t n, int32_t max_depth, int32_t* first_slo
   int rc = check_poison(T);
   if (rc) return rc;
   if (n < 1) return fail(CT_E_INVALID, "n < 1");
+  if ((rc = quiesce(T))) return rc;
   if (max_depth < 0) max_depth = T->cfg.max_depth;
   SlotDesc* d = nullptr;
   std::vector<SlotDesc> h;
@@ -695,10 +864,17 @@ int ct_propagate_slot(ct_table* T, int32_t slot, const uint64_t* dom_in, uint64_
     J.ct_out = pinned_dev64(T, T->pCt);
   }
   S.pendPop = S.pendPush = 0;
-  if ((rc = run_single(T, J, dom_in))) return rc;
-  const int status = *T->pStatus;
+  int status = CT_OK;
+  const uint64_t* domRes = T->pDomOut;
+  if (slot == 0 && engine_wanted(T)) {
+    if ((rc = engine_call(T, J, dom_in, ct_out != nullptr, &status))) return rc;
+    domRes = T->pRes->dom;
+  } else {
+    if ((rc = run_single(T, J, dom_in))) return rc;
+    status = *T->pStatus;
+  }
   if (status == CT_OK) {
-    memcpy(dom_out, T->pDomOut, sizeof(uint64_t) * T->D);
+    memcpy(dom_out, domRes, sizeof(uint64_t) * T->D);
     if (ct_out) memcpy(ct_out, T->pCt, sizeof(uint64_t) * T->W);
   } else if (status == CT_FAIL) {
     S.failed = 1;
@@ -732,6 +908,7 @@ int ct_get_state(ct_table* T, int32_t slot, uint64_t* dom_out, uint64_t* ct_out)
   int rc = check_poison(T);
   if (rc) return rc;
   if ((rc = check_slot(T, slot))) return rc;
+  if ((rc = quiesce(T))) return rc;
   if ((rc = flush_slot(T, slot))) return rc;
   HIPCHK(hipStreamSynchronize(T->stream));
   SlotDesc s{};
@@ -752,9 +929,15 @@ int ct_slot_stats(ct_table* T, int32_t slot, ct_stats* st) {
   if (rc) return rc;
   if ((rc = check_slot(T, slot))) return rc;
   if (!st) return fail(CT_E_INVALID, "st is NULL");
-  HIPCHK(hipStreamSynchronize(T->stream));
   SlotDesc s{};
-  HIPCHK(hipMemcpy(&s, T->slots[slot].dev, sizeof(SlotDesc), hipMemcpyDeviceToHost));
+  if (slot == 0 && T->engOn && __atomic_load_n(&T->pRes->alive, __ATOMIC_ACQUIRE) != 0) {
+    // the engine holds the counters: its snapshot after the last call
+    for (int k = 0; k < 8; ++k) s.stats[k] = T->pRes->stats[k];
+  } else {
+    if ((rc = quiesce(T))) return rc;
+    HIPCHK(hipStreamSynchronize(T->stream));
+    HIPCHK(hipMemcpy(&s, T->slots[slot].dev, sizeof(SlotDesc), hipMemcpyDeviceToHost));
+  }
   st->jobs = (int64_t)s.stats[S_JOBS];
   st->granules_in = (int64_t)s.stats[S_GRAN_IN];
   st->rows_or = (int64_t)s.stats[S_ROWS];
@@ -796,6 +979,8 @@ int ct_set_timing(ct_table* T, int32_t on) {
   }
   if (T->dClock) HIPCHK(hipMemcpy(T->dClock, kClockInit, sizeof(kClockInit), hipMemcpyHostToDevice));
   T->timing = on != 0;
+  T->engTicks = 0;
+  T->engCalls = 0;
   return CT_OK;
 }
 
@@ -803,14 +988,18 @@ int ct_get_timing(ct_table* T, double* kernel_ms, int64_t* launches) {
   if (!T) return fail(CT_E_INVALID, "null table");
   unsigned long long c[5] = {0, 0, 0, 0, 0};
   if (T->dClock) {
+    int rc = quiesce(T);  // launched calls on the table's stream have ended
+    if (rc) return rc;
     HIPCHK(hipStreamSynchronize(T->stream));
     HIPCHK(hipMemcpy(c, T->dClock, sizeof(c), hipMemcpyDeviceToHost));
   }
   int dev = 0, khz = 0;
   HIPCHK(hipGetDevice(&dev));
   HIPCHK(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev));
-  if (kernel_ms) *kernel_ms = khz > 0 ? (double)c[3] / (double)khz : 0.0;
-  if (launches) *launches = (int64_t)c[4];
+  // launched calls, plus calls served by the resident engine (device time of
+  // each call inside the engine)
+  if (kernel_ms) *kernel_ms = khz > 0 ? (double)(c[3] + T->engTicks) / (double)khz : 0.0;
+  if (launches) *launches = (int64_t)(c[4] + T->engCalls);
   return CT_OK;
 }
 
@@ -848,6 +1037,10 @@ int ct_propagate_batch(const ct_job* jobs, int32_t n_jobs, void* stream_v, int32
   {
     std::set<ct_table*> tabs;
     for (int j = 0; j < n_jobs; ++j) tabs.insert(jobs[j].table);
+    for (ct_table* T : tabs) {
+      int rc = quiesce(T);
+      if (rc) return rc;
+    }
     for (ct_table* T : tabs)
       if (T->tailPending) {
         HIPCHK(hipStreamSynchronize(T->stream));

@@ -20,7 +20,7 @@ HEADER = os.path.join(ROOT, "include", "ct.h")
 OK, FAIL = 0, 1
 E_INVALID, E_NOT_SUBSET, E_STATE, E_NOMEM, E_DEVICE = -1, -2, -3, -4, -5
 BRANCH_AUTO, BRANCH_RESET, BRANCH_INCREMENTAL = 0, 1, 2
-SCHED_AUTO, SCHED_SOLO, SCHED_SPLIT, SCHED_NODES = 0, 1, 2, 3
+SCHED_AUTO, SCHED_SOLO, SCHED_SPLIT, SCHED_NODES, SCHED_RESIDENT = 0, 1, 2, 3, 4
 JOB_PROPAGATE, JOB_FROM_ROOT = 1, 2
 
 
@@ -137,12 +137,16 @@ def lib():
             "ct_server_stats": ([P, P], C.c_int),
             "ct_server_now": ([], C.c_double),
             "ct_last_error": ([], C.c_char_p),
+            "ct_quiesce": ([], C.c_int),
         }
         for name, (args, res) in sig.items():
             f = getattr(L, name)
             f.argtypes = args
             f.restype = res
         _lib = L
+        # a resident engine writes its state back and ends before exit
+        import atexit
+        atexit.register(L.ct_quiesce)
     return _lib
 
 
