@@ -204,7 +204,7 @@ constexpr int ENG_OP_PROPAGATE = 1, ENG_OP_STOP = 2;
 
 struct EngCmd {             // written by the host, seq last (release)
   int32_t seq, op, nPop, nPush;
-  int32_t serialBase, depthAfter, wantCt, pad;
+  int32_t serialBase, depthAfter, wantCt, wantStats;
   uint64_t dom[INLINE_WORDS];
 };
 

@@ -29,7 +29,7 @@ constexpr int E_ROWS = 4;        // support rows loaded per batch
 constexpr int E_LANE_SCAN = 16;  // words each missing lane checks after its residue
 
 struct EngState {
-  int32_t op, seq, lastSeq, nPop, nPush, serialBase, depthAfter, wantCt;
+  int32_t op, seq, lastSeq, nPop, nPush, serialBase, depthAfter, wantCt, wantStats, pad3;
   int32_t limit, failed, depth, serial, cur, status, noop, nseg;
   int32_t nrows, badStray, badSub, trailCount, nSurv, devErr, pad0, pad1;
   int64_t trailTop, lvTrailTop;
@@ -53,7 +53,7 @@ __host__ __device__ inline void eng_layout(int n, int D, int nGran, int rows, si
   sz[R_FIRST] = (size_t)nGran * 4;
   sz[R_RES] = (size_t)rows * 4;
   sz[R_LAST] = sz[R_DIN] = (size_t)D * 8;
-  sz[R_ROWS] = (size_t)rows * 2;
+  sz[R_ROWS] = ((size_t)rows + 16) * 2;  // batches read up to 16 entries past the end
   sz[R_WVAR] = (size_t)D * 4;
   sz[R_VARS] = (size_t)n * sizeof(VarDesc);
   sz[R_VSIZE] = sz[R_VDCNT] = sz[R_SEGOF] = sz[R_SEGEND] = sz[R_SEGINC] = (size_t)n * 4;
@@ -78,8 +78,19 @@ __device__ __forceinline__ void lds_barrier() {
 __device__ __forceinline__ int e_lane() { return threadIdx.x & (WAVE - 1); }
 __device__ __forceinline__ int e_wave() { return __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE); }
 
+// Support rows through a buffer resource: one scalar descriptor, a scalar
+// byte offset per (row, granule) and the lane's byte offset in one vector
+// register shared by every load (loads past num_records return 0).
+constexpr int BUF_DWORD3 = 0x00020000;  // raw buffer, gfx9 family
+
+__device__ __forceinline__ uint64_t e_ld(__amdgpu_buffer_rsrc_t rs, uint32_t voff, uint32_t soff) {
+  const auto v = __builtin_amdgcn_raw_buffer_load_b64(rs, (int)voff, (int)soff, 0);
+  return (uint64_t)v[0] | ((uint64_t)v[1] << 32);
+}
+
 struct Eng {
   // table (read-only)
+  __amdgpu_buffer_rsrc_t Sbuf;
   const CT_G uint64_t* S;
   int64_t stride, W;
   int n, D, nGran, rows, policy;
@@ -272,6 +283,7 @@ __device__ void e_update(Eng& E) {
   EngState* st = E.st;
   const int lane = e_lane();
   const int limit = st->limit, nseg = st->nseg, nrows = st->nrows, serial = st->serial;
+  const uint32_t laneOff = (uint32_t)lane * 8u;
   const uint16_t* idxCur = st->cur ? E.idx1 : E.idx0;
   const bool trailOn = st->depthAfter > 0;  // levels exist only above depth 0
   const int64_t trailTop = st->trailTop;
@@ -295,17 +307,20 @@ __device__ void e_update(Eng& E) {
     int segEnd = nseg > 0 ? E.segEnd[0] : 0;
     for (int k0 = 0; k0 < nrows; k0 += E_ROWS) {
       uint64_t v[E_ROWS][E_NG];
+      // the batch's row numbers, two per 32-bit LDS word, into scalar
+      // registers (the same on every lane)
+      uint32_t idw[(E_ROWS + 1) / 2];
+      const uint32_t* lw = (const uint32_t*)(E.rowList + k0);  // k0 is even
+#pragma unroll
+      for (int i = 0; i < (E_ROWS + 1) / 2; ++i) idw[i] = __builtin_amdgcn_readfirstlane(lw[i]);
 #pragma unroll
       for (int j = 0; j < E_ROWS; ++j) {
         const int k = k0 + j;
-        // rows past the end are never used; the row is the same on every lane
-        const int r = k < nrows ? __builtin_amdgcn_readfirstlane((int)E.rowList[k]) : 0;
+        const uint32_t id = (j & 1) ? (idw[j / 2] >> 16) : (idw[j / 2] & 0xFFFFu);
+        const int r = k < nrows ? (int)id : 0;  // rows past the end are never used
 #pragma unroll
-        for (int u = 0; u < E_NG; ++u) {
-          // uniform base (scalar registers) + lane offset
-          const CT_G uint64_t* base = E.S + ((int64_t)r * E.stride + (int64_t)gs[u] * GW);
-          v[j][u] = base[lane];
-        }
+        for (int u = 0; u < E_NG; ++u)
+          v[j][u] = e_ld(E.Sbuf, laneOff, (uint32_t)(((int64_t)r * E.stride + (int64_t)gs[u] * GW) * 8));
       }
 #pragma unroll
       for (int j = 0; j < E_ROWS; ++j) {
@@ -601,6 +616,9 @@ __global__ void __launch_bounds__(EBLOCK) engine_kernel(EngDesc D) {
   const CT_G TabDesc* T = D.tab;
   Eng E;
   E.S = T->S;
+  E.Sbuf = __builtin_amdgcn_make_buffer_rsrc((void*)T->S, (short)0,
+                                             (int)min((int64_t)T->rows * T->stride * 8, (int64_t)0x7fffffff),
+                                             BUF_DWORD3);
   E.stride = T->stride;
   E.W = T->W;
   E.n = T->n;
@@ -668,7 +686,7 @@ __global__ void __launch_bounds__(EBLOCK) engine_kernel(EngDesc D) {
         if (l >= HDR && l < HDR + E.D) E.din[l - HDR] = w0;
         if (l + WAVE - HDR < E.D) E.din[l + WAVE - HDR] = w1;
       }
-      // header words: {seq, op}, {nPop, nPush}, {serialBase, depthAfter}, {wantCt, pad}
+      // header words: {seq, op}, {nPop, nPush}, {serialBase, depthAfter}, {wantCt, wantStats}
       const uint64_t h0 = __shfl(w0, 0), h1 = __shfl(w0, 1), h2 = __shfl(w0, 2), h3 = __shfl(w0, 3);
       if (threadIdx.x == 0) {
         st->op = seen ? (int32_t)(h0 >> 32) : 0;
@@ -677,6 +695,7 @@ __global__ void __launch_bounds__(EBLOCK) engine_kernel(EngDesc D) {
         st->serialBase = (int32_t)h2;
         st->depthAfter = (int32_t)(h2 >> 32);
         st->wantCt = (int32_t)h3;
+        st->wantStats = (int32_t)(h3 >> 32);
       }
     }
     lds_barrier();
@@ -722,15 +741,14 @@ __global__ void __launch_bounds__(EBLOCK) engine_kernel(EngDesc D) {
         if (st->wantCt)
           for (int64_t w = threadIdx.x; w < E.W; w += WAVE) D.ctOut[w] = E.ct[w];
       }
-      if (threadIdx.x < 8) res->stats[threadIdx.x] = st->stat[threadIdx.x];
+      if (st->wantStats && threadIdx.x < 8) res->stats[threadIdx.x] = st->stat[threadIdx.x];
       if (threadIdx.x == 0) {
         res->status = st->devErr ? ST_DEVICE : st->status;
         res->callTicks = wall_clock64() - tStart;
         st->lastSeq = st->seq;
       }
-      // system-scope release: the outputs (written back from L2 where the
-      // device caches them) are visible before the sequence number
-      __threadfence_system();
+      // system-scope release (it writes back what L2 holds of the outputs
+      // first): the outputs are visible before the sequence number
       if (threadIdx.x == 0)
         __hip_atomic_store(&res->seq, st->seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
     }

@@ -165,6 +165,7 @@ struct ct_table {
   EngCmd* pCmd = nullptr;   // coherent pinned mailbox
   EngRes* pRes = nullptr;
   int32_t engSeq = 0;
+  bool engStatsFresh = false;  // pRes->stats is from the last call
   unsigned long long engTicks = 0, engCalls = 0;  // timing of engine calls
 };
 
@@ -434,7 +435,7 @@ int engine_start(ct_table* T) {
 
 // One call through the engine; *status receives the call's status and the
 // outputs are in T->pRes->dom and (wantCt) T->pCt.
-int engine_call(ct_table* T, const DevJob& J, const uint64_t* dom_in, bool wantCt, int* status) {
+int engine_call(ct_table* T, const DevJob& J, const uint64_t* dom_in, bool wantCt, bool wantStats, int* status) {
   std::lock_guard<std::mutex> lk(g_engMu);
   int rc;
   if (T->engOn && __atomic_load_n(&T->pRes->alive, __ATOMIC_ACQUIRE) == 0 && (rc = engine_join(T))) return rc;
@@ -446,6 +447,7 @@ int engine_call(ct_table* T, const DevJob& J, const uint64_t* dom_in, bool wantC
   c->serialBase = J.serialBase;
   c->depthAfter = J.depthAfter;
   c->wantCt = wantCt ? 1 : 0;
+  c->wantStats = wantStats ? 1 : 0;
   memcpy(c->dom, dom_in, sizeof(uint64_t) * T->D);
   const int32_t seq = ++T->engSeq;
   __atomic_store_n(&c->seq, seq, __ATOMIC_RELEASE);
@@ -467,6 +469,7 @@ int engine_call(ct_table* T, const DevJob& J, const uint64_t* dom_in, bool wantC
     }
   }
   *status = T->pRes->status;
+  T->engStatsFresh = wantStats;
   if (T->timing) {
     T->engTicks += T->pRes->callTicks;
     T->engCalls += 1;
@@ -867,7 +870,7 @@ int ct_propagate_slot(ct_table* T, int32_t slot, const uint64_t* dom_in, uint64_
   int status = CT_OK;
   const uint64_t* domRes = T->pDomOut;
   if (slot == 0 && engine_wanted(T)) {
-    if ((rc = engine_call(T, J, dom_in, ct_out != nullptr, &status))) return rc;
+    if ((rc = engine_call(T, J, dom_in, ct_out != nullptr, st != nullptr, &status))) return rc;
     domRes = T->pRes->dom;
   } else {
     if ((rc = run_single(T, J, dom_in))) return rc;
@@ -930,7 +933,7 @@ int ct_slot_stats(ct_table* T, int32_t slot, ct_stats* st) {
   if ((rc = check_slot(T, slot))) return rc;
   if (!st) return fail(CT_E_INVALID, "st is NULL");
   SlotDesc s{};
-  if (slot == 0 && T->engOn && __atomic_load_n(&T->pRes->alive, __ATOMIC_ACQUIRE) != 0) {
+  if (slot == 0 && T->engOn && T->engStatsFresh && __atomic_load_n(&T->pRes->alive, __ATOMIC_ACQUIRE) != 0) {
     // the engine holds the counters: its snapshot after the last call
     for (int k = 0; k < 8; ++k) s.stats[k] = T->pRes->stats[k];
   } else {
