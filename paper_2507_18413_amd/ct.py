@@ -193,6 +193,15 @@ class Table:
         self.n, self.D, self.W, self.t = info.n_vars, info.D, info.W, info.n_tuples
         self.rows, self.granules, self.root_failed = info.rows, info.granules, bool(info.root_failed)
         self.dom_off = off
+        # marshalling buffers of the synchronous calls: fixed addresses, so a
+        # call converts no pointer (numpy's ctypes pointers cost microseconds)
+        self._din = np.zeros(max(self.D, 1), np.uint64)
+        self._dout = np.zeros(max(self.D, 1), np.uint64)
+        self._din_p = self._din.__array_interface__["data"][0]
+        self._dout_p = self._dout.__array_interface__["data"][0]
+        self._prop = L.ct_propagate_slot
+        self._push = L.ct_push_slot
+        self._pop = L.ct_pop_slot
 
     @property
     def n_slots(self):
@@ -212,16 +221,17 @@ class Table:
             pass
 
     def propagate(self, dom_in, slot=0, want_ct=False, want_stats=False):
-        dom_in = np.ascontiguousarray(dom_in, dtype=np.uint64)
-        assert dom_in.shape[0] == self.D
-        dom_out = dom_in.copy()
+        if len(dom_in) != self.D:
+            raise ValueError(f"dom_in has {len(dom_in)} words, the table {self.D}")
+        self._din[: self.D] = dom_in
+        self._dout[: self.D] = self._din[: self.D]
         ct = np.zeros(max(self.W, 1), np.uint64) if want_ct else None
         stats = ct_stats() if want_stats else None
-        st = lib().ct_propagate_slot(self.h, int(slot), _p(dom_in), _p(dom_out), _p(ct),
-                                     C.byref(stats) if stats is not None else None)
+        st = self._prop(self.h, int(slot), self._din_p, self._dout_p, _p(ct),
+                        C.byref(stats) if stats is not None else None)
         if st == E_DEVICE:
             raise CTError(st, last_error())
-        out = [st, dom_out]
+        out = [st, self._dout[: self.D].copy()]
         if want_ct:
             out.append(ct[: self.W])
         if want_stats:
@@ -229,10 +239,10 @@ class Table:
         return tuple(out)
 
     def push(self, slot=0):
-        return lib().ct_push_slot(self.h, int(slot))
+        return self._push(self.h, int(slot))
 
     def pop(self, slot=0):
-        return lib().ct_pop_slot(self.h, int(slot))
+        return self._pop(self.h, int(slot))
 
     def state(self, slot=0):
         dom = np.zeros(self.D, np.uint64)
