@@ -108,7 +108,7 @@ def test_random_sequences_vs_oracle(chunk):
         lay = W.DomLayout(ds, lo)
         init = random_subset(rng, lay, lay.full(), 0.8) if rng.random() < 0.3 else None
         policy = int(rng.integers(0, 3))
-        schedule = (ct.SCHED_SOLO, ct.SCHED_SPLIT)[case % 2]
+        schedule = (ct.SCHED_SOLO, ct.SCHED_SPLIT, ct.SCHED_RESIDENT)[case % 3]
         say(f"chunk={chunk} case={case}")
         G, Ot = pair(tup, lo, ds, init=init, policy=policy, schedule=schedule)
         assert (G.create_status == ct.FAIL) == (Ot.create_status == O.FAIL)
