@@ -106,6 +106,8 @@ typedef struct {
     int32_t n_slots;
     int32_t granules;   /* 64-word groups of currTable tracked by the sparse index */
     int32_t root_failed;/* 1 if the root propagation found no valid tuple */
+    int32_t resident;   /* 1 if synchronous calls on slot 0 use the resident engine */
+    int32_t pad;
 } ct_layout_info;
 
 /* Cumulative per-slot work counters (never reset; take differences). */

@@ -775,6 +775,8 @@ int ct_layout(const ct_table* T, ct_layout_info* info, int32_t* dom_off) {
     info->n_slots = (int32_t)T->slots.size();
     info->granules = T->nGran;
     info->root_failed = T->rootFailed;
+    info->resident = engine_wanted(T) ? 1 : 0;
+    info->pad = 0;
   }
   if (dom_off) memcpy(dom_off, T->domOff.data(), sizeof(int32_t) * T->n);
   return CT_OK;

@@ -37,7 +37,7 @@ class ct_config(C.Structure):
 class ct_layout_info(C.Structure):
     _fields_ = [("n_vars", C.c_int32), ("D", C.c_int32), ("W", C.c_int64), ("n_tuples", C.c_int64),
                 ("rows", C.c_int32), ("n_slots", C.c_int32), ("granules", C.c_int32),
-                ("root_failed", C.c_int32)]
+                ("root_failed", C.c_int32), ("resident", C.c_int32), ("pad", C.c_int32)]
 
 
 class ct_stats(C.Structure):
@@ -192,6 +192,7 @@ class Table:
         L.ct_layout(h, C.byref(info), _p(off))
         self.n, self.D, self.W, self.t = info.n_vars, info.D, info.W, info.n_tuples
         self.rows, self.granules, self.root_failed = info.rows, info.granules, bool(info.root_failed)
+        self.resident = bool(info.resident)
         self.dom_off = off
         # marshalling buffers of the synchronous calls: fixed addresses, so a
         # call converts no pointer (numpy's ctypes pointers cost microseconds)

@@ -26,13 +26,16 @@ import re
 import statistics
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-KERNEL_SRC = os.path.join(HERE, "csrc", "ct_kernels.hip")
+KERNEL_SRCS = [os.path.join(HERE, "csrc", "ct_kernels.hip"), os.path.join(HERE, "csrc", "ct_engine.hip")]
 KERNEL = "propagate_kernel"
 DEFAULT_TITLE = "propagate_kernel, one large table (config 2)"
 
 
 def kernel_source_hash() -> str:
-    return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for path in KERNEL_SRCS:
+        h.update(open(path, "rb").read())
+    return h.hexdigest()[:16]
 
 
 def _rows(path):
@@ -90,12 +93,21 @@ def summarize(args):
                     "copy_kernel": cname, "copy_fetch_factor": round(ffac, 4),
                     "copy_write_factor": round(wfac, 4), "hbm_bytes_per_launch": round(traffic, 1),
                     "dispatches_fetch": nf, "dispatches_write": nw})
+        if args.calls:
+            # a resident kernel serves many calls per dispatch: all its
+            # dispatches' bytes over all the calls of the counted runs
+            per_call = (kf * nf / ffac + kw * nw / wfac) * 1024 / args.calls
+            out["hbm_bytes_per_call"] = round(per_call, 1)
+            out["calls_counted"] = args.calls
         lines += ["", "HBM traffic (rocprofv3 --pmc FETCH_SIZE, then WRITE_SIZE; KiB per dispatch):", "",
                   f"* {prop['Name'][:60]}: FETCH {kf:.2f} KiB, WRITE {kw:.2f} KiB per launch "
                   f"({nf} / {nw} dispatches)",
                   f"* calibration copy of {args.copy_bytes} bytes ({cname[:50]}): FETCH reads {cf:.1f} KiB "
                   f"(factor {ffac:.3f}), WRITE reads {cw:.1f} KiB (factor {wfac:.3f})",
                   f"* scaled HBM bytes per launch of that kernel: {traffic:.0f}"]
+    if "hbm_bytes_per_call" in out:
+        lines += [f"* over all {out['dispatches_fetch']} dispatches and the {args.calls} calls they served "
+                  f"(counter runs): {out['hbm_bytes_per_call']:.0f} HBM bytes per call"]
     lines += ["", "Machine-readable (read by bench.py while the kernel source hash matches):", "",
               "```json", json.dumps(out), "```", ""]
     with open(args.out, "w") as fh:
@@ -127,6 +139,8 @@ def main():
     s.add_argument("--copy-bytes", type=int, default=0)
     s.add_argument("--command", required=True)
     s.add_argument("--kernel", default=KERNEL, help="regular expression naming the kernel")
+    s.add_argument("--calls", type=int, default=0,
+                   help="calls served by the kernel's dispatches in each counter run (resident kernels)")
     s.add_argument("--title", default=DEFAULT_TITLE)
     s.add_argument("--out", required=True)
     a = p.parse_args()
