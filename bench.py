@@ -49,6 +49,8 @@ def parse():
     p.add_argument("--calibration-copy", type=int, default=0,
                    help="MiB copied once by torch before the timed run (counter calibration)")
     p.add_argument("--no-model", action="store_true")
+    p.add_argument("--root-batch-only", action="store_true",
+                   help="only the batched root recomputation of the 2,000-table model (profiling)")
     return p.parse_args()
 
 
@@ -236,6 +238,64 @@ class PlainModel:
         return 0, pool, props
 
 
+def root_batch_leg(tabs, specs, reps, per_table=True):
+    """Every table's root recomputed from scratch (ROOT jobs: all tuples,
+    every variable on the reset branch) in one batched launch: each support
+    row is streamed once, the HBM-bound form of updateTable.  Compared with
+    one launch per table, and checked against each table's own root."""
+    import numpy as np
+    import torch
+    from paper_2507_18413_amd import ct
+    from paper_2507_18413_amd import workloads as W
+    n = len(tabs)
+    fulls = [W.DomLayout(sp.dsizes, sp.lo).full() for sp in specs]
+    offs = np.cumsum([0] + [len(f) for f in fulls])
+    din = torch.from_numpy(np.concatenate(fulls).view(np.int64)).cuda()
+    dout = torch.zeros_like(din)
+    status = torch.full((n,), 99, dtype=torch.int32, device="cuda")
+    jobs = []
+    for k, t in enumerate(tabs):
+        slot = t.slots_alloc(1, max_depth=0)
+        jobs.append(dict(table=t, slot=slot, flags=ct.JOB_PROPAGATE | ct.JOB_ROOT,
+                         dom_in=din[offs[k]:offs[k + 1]], dom_out=dout[offs[k]:offs[k + 1]]))
+    batch = ct.Batch(jobs)
+    batch.run(status)
+    torch.cuda.synchronize()
+    st = status.cpu().numpy()
+    got = dout.cpu().numpy().view(np.uint64)
+    same = all(int(st[k]) == (ct.FAIL if t.root_failed else ct.OK) and
+               (t.root_failed or (got[offs[k]:offs[k + 1]] == t.domains(0)).all())
+               for k, t in enumerate(tabs))
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        batch.run(status)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    rows_w = sum(int(t.rows) * int(t.W) for t in tabs)
+    # compulsory bytes: every support row once, currTable written once, the
+    # domains read and written
+    byts = 8 * rows_w + 8 * sum(int(t.W) for t in tabs) + 16 * int(offs[-1])
+    out = {"jobs": n, "matches_table_roots": bool(same), "ms_per_batch": round(ms, 4),
+           "compulsory_bytes": byts, "compulsory_GBps": round(byts / ms / 1e6, 1),
+           "frac_of_hbm_peak": round(byts / ms / 1e6 / HBM_PEAK_GBS, 4),
+           "kernels": "ctk::root_stream_kernel + ctk::root_finish_kernel",
+           "timing": "HIP events around the batches on the launch stream"}
+    if per_table:
+        singles = [ct.Batch([j]) for j in jobs]
+        torch.cuda.synchronize()
+        e0.record()
+        for b in singles:
+            b.run(status)
+        e1.record()
+        torch.cuda.synchronize()
+        ms1 = e0.elapsed_time(e1)
+        out["one_launch_per_table_ms"] = round(ms1, 3)
+        out["batched_speedup"] = round(ms1 / ms, 2)
+    return out
+
+
 def model_leg(seed, steps, plain_steps, cpu):
     """Batched CT across constraints: 2,000 tables over a pool of 5,000
     variables, root fixpoint then `steps` search steps (push, remove 5 % of
@@ -254,6 +314,7 @@ def model_leg(seed, steps, plain_steps, cpu):
     for tb, sc in zip(tabs, spec.scopes):
         M.add(tb, sc)
     build_s = time.perf_counter() - t0 - gen_s
+    root_batch = root_batch_leg(tabs, spec.tables, 5)
     full = lay.full()
     dev = lambda a: torch.from_numpy(np.ascontiguousarray(a).view(np.int64)).cuda()
     pin, pout = dev(full), dev(full)
@@ -308,7 +369,7 @@ def model_leg(seed, steps, plain_steps, cpu):
            "root_fixpoint_ms": round(root_s * 1e3, 3), "root_fixpoint_tuned_ms": round(root_tuned_s * 1e3, 3),
            "autotuned_solo_max_granules": best, "root_props": props, "root_rounds": rounds,
            "steps": steps, "batched_props": bprops, "batched_step_props_per_s": round(bprops / batched_s, 1),
-           "batched_ms_per_step": round(batched_s / steps * 1e3, 3)}
+           "batched_ms_per_step": round(batched_s / steps * 1e3, 3), "root_gac_batch": root_batch}
     # plain GPU baseline (one launch per table propagation) on the first steps
     pm = PlainModel(tabs, spec.scopes, lay)
     pm.push()
@@ -513,6 +574,15 @@ def main():
     from paper_2507_18413_amd import workloads as W
 
     seed = W.DEFAULT_SEED if args.seed is None else args.seed
+    if args.root_batch_only:
+        note("generating the 2,000-table model")
+        mspec = W.config3_model(seed)
+        torch.cuda.set_device(0)
+        tabs = [ct.Table(tb.tuples, tb.lo, tb.dsizes) for tb in mspec.tables]
+        note("batched root recomputation")
+        print(json.dumps({"root_gac_batch": root_batch_leg(tabs, mspec.tables, max(1, args.steps),
+                                                           per_table=False)}), flush=True)
+        return
     serve_spec = None
     if not args.no_serve:
         # generated before the GPU is initialised: the pool's workers are

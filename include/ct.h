@@ -201,6 +201,13 @@ int ct_slot_stats(ct_table *t, int32_t slot, ct_stats *st);
  * --------------------------------------------------------------------- */
 #define CT_JOB_PROPAGATE 1u /* run enforceGAC after the pops and pushes */
 #define CT_JOB_FROM_ROOT 2u /* reset the slot to the root state (depth 0) first */
+/* Recompute the root state from scratch into the slot, as at creation (Alg. 1
+ * with every variable on the reset branch of Alg. 2, starting from all
+ * tuples; Sec. 3, "Procedures"): dom_in = the table's initial domains, or any
+ * domains without stray bits; the slot ends at depth 0 holding GAC of dom_in.
+ * Streams every support row once.  Needs CT_JOB_PROPAGATE; no pops/pushes;
+ * not with CT_JOB_FROM_ROOT. */
+#define CT_JOB_ROOT 4u
 
 typedef struct {
     ct_table *table;
@@ -222,8 +229,11 @@ typedef struct {
  * CT_E_NOMEM).  Returns immediately after queueing; CT_E_INVALID for a
  * malformed batch (two jobs on one slot, pop below depth 0, FROM_ROOT with
  * pops or pushes), CT_E_NOMEM (push beyond max_depth).  In a batch a push on
- * a failed slot is allowed (the level records the failed flag).  The tables
- * must not be used from another stream until the batch completes.
+ * a failed slot is allowed (the level records the failed flag).  A FROM_ROOT
+ * or ROOT job whose input is rejected (CT_E_INVALID, CT_E_NOT_SUBSET,
+ * CT_E_STATE) still resets its slot, which then holds the table's root state
+ * at depth 0.  The tables must not be used from another stream until the
+ * batch completes.
  */
 int ct_propagate_batch(const ct_job *jobs, int32_t n_jobs, void *stream, int32_t *status_dev);
 

@@ -59,6 +59,7 @@ constexpr uint32_t JF_ROOT = 4u;      // creation: every variable takes the rese
 constexpr uint32_t JF_INLINE_DOM = 8u;
 constexpr uint32_t JF_HOST_OUT = 16u;   // status / outputs in host memory: system-scope release
 constexpr uint32_t JF_SOLO = 32u;       // whole job in one workgroup
+constexpr uint32_t JF_SCRATCH = 64u;    // with JF_ROOT | JF_FROM_ROOT: root state recomputed from all tuples
 
 struct VarDesc {
   int32_t rowStart, dsize, domOff, domWords;
@@ -75,7 +76,7 @@ struct TabDesc {
   const CT_G int32_t* idx0;
   const CT_G uint64_t* dom0;
   int32_t limit0, rootFailed;
-  int32_t policy, pad;
+  int32_t policy, tailBits;      // tailBits: tuples in the last currTable word (1..64)
 };
 
 struct TrailHdr {
@@ -152,6 +153,14 @@ struct NodesDesc {
   const CT_G DevJob* jobs;
   CT_G uint64_t* nodes;    // nJobs x nodeWords
   CT_G uint8_t* nz;        // nJobs x nGran
+};
+
+// Batch of roots recomputed from scratch: one task per workgroup of the
+// stream kernel, (job, first granule) pairs, each covering WAVES consecutive
+// granules of the job (one per wave), largest tables first.
+struct RootDesc {
+  const CT_G int32_t* tasks;  // nTasks x 2
+  int32_t nTasks, pad;
 };
 
 // Multi-table model: pool variables shared by tables (device side of a

@@ -131,6 +131,14 @@ __device__ __forceinline__ uint64_t job_din(const KArgs& a, const DevJob& J, int
   return (J.flags & JF_INLINE_DOM) ? a.inl[k] : J.dom_in[k];
 }
 
+// Word w of the set of all tuples (the starting currTable of a root state
+// recomputed from scratch): ones up to the last tuple, zero past it.
+__device__ __forceinline__ uint64_t all_tuples_word(const TabDesc* T, int64_t w) {
+  if (w >= T->W) return 0ull;
+  if (w < T->W - 1 || T->tailBits >= 64) return ~0ull;
+  return (1ull << T->tailBits) - 1ull;
+}
+
 // Job status for the caller.  Outputs in host memory are published with a
 // system-scope release after a system-scope fence, so a host that sees the
 // status also sees the domain words written before it.
@@ -264,12 +272,16 @@ __device__ void prologue(const KArgs& a, const DevJob& J, Shared& sh, bool pushH
   SlotDesc* s = J.slot;
   const bool fromRoot = J.flags & JF_FROM_ROOT;
   const bool root = J.flags & JF_ROOT;
+  const bool scratch = J.flags & JF_SCRATCH;
   const int n = T->n, D = T->D;
   const CT_G uint64_t* last = fromRoot ? T->dom0 : s->lastDom;
   if (threadIdx.x == 0) {
     sh.bad_stray = 0;
     sh.bad_sub = 0;
-    if (fromRoot) {
+    if (scratch) {  // every tuple, every granule
+      sh.limit = T->nGran;
+      sh.status = ST_OK;
+    } else if (fromRoot) {
       sh.limit = T->limit0;
       sh.status = T->rootFailed ? ST_STATE : ST_OK;
     } else {
@@ -390,6 +402,7 @@ __device__ void update_granules(const KArgs& a, const DevJob& J, Shared& sh, int
   const int nseg = sh.nseg, nrows = sh.nrows;
   const int serial = sh.serial;
   const int lane = lane_id();
+  const bool scratch = J.flags & JF_SCRATCH;
   const CT_G uint64_t* srcCt = fromRoot ? T->ct0 : s->ct;
   const CT_G int32_t* srcIdx = fromRoot ? T->idx0 : s->idx[s->cur];
   const int64_t trailTop = sh.trailTop;
@@ -405,11 +418,11 @@ __device__ void update_granules(const KArgs& a, const DevJob& J, Shared& sh, int
   for (int u = 0; u < NG; ++u) {
     pos[u] = p0 + u;
     const int pc = min(pos[u], nGran - 1);
-    g[u] = lds ? (int)sh.gidx[pc] : srcIdx[pc];
+    g[u] = scratch ? pc : lds ? (int)sh.gidx[pc] : srcIdx[pc];
     if (pos[u] >= nGran) g[u] = -1;
     act[u] = pos[u] < limit && status == ST_OK;
     gs[u] = act[u] ? g[u] : 0;
-    const uint64_t o = srcCt[(int64_t)gs[u] * GW + lane];
+    const uint64_t o = scratch ? all_tuples_word(T, (int64_t)gs[u] * GW + lane) : srcCt[(int64_t)gs[u] * GW + lane];
     const int sv = s->stamp[gs[u]];
     old[u] = act[u] ? o : 0ull;
     stv[u] = (act[u] && trailOn && !noop) ? sv : serial;
@@ -524,6 +537,25 @@ __device__ void update_granules(const KArgs& a, const DevJob& J, Shared& sh, int
 }
 
 // ---------------------------------------------------------------------------
+// A job that resets its slot to the root (depth 0) and then rejects its input
+// still performs the reset: the slot becomes a copy of the table's root state
+// (one workgroup, any block size; a rare path, so the whole currTable is copied).
+// ---------------------------------------------------------------------------
+__device__ void slot_reset_root(const TabDesc* T, SlotDesc* s, int serial) {
+  for (int64_t w = threadIdx.x; w < T->stride; w += blockDim.x) s->ct[w] = T->ct0[w];
+  for (int p = threadIdx.x; p < T->nGran; p += blockDim.x) s->idx[0][p] = T->idx0[p];
+  for (int q = threadIdx.x; q < T->D; q += blockDim.x) s->lastDom[q] = T->dom0[q];
+  if (threadIdx.x == 0) {
+    s->cur = 0;
+    s->limit = T->limit0;
+    s->failed = T->rootFailed;
+    s->depth = 0;
+    s->trailTop = 0;
+    s->serial = serial;
+  }
+}
+
+// ---------------------------------------------------------------------------
 // End of updateTable for a job (one workgroup): stable partition of the
 // active granule list (survivors first), new limit, trail top, FAIL when no
 // granule survives (Alg. 1 line 5).  Returns the job status.
@@ -536,6 +568,7 @@ __device__ int finalize_update(const DevJob& J, Shared& sh, bool ldsFlags, int j
   const int nGran = T->nGran;
   int st = sh.status;
   if (st == ST_OK && !sh.noop) {
+    const bool scratch = J.flags & JF_SCRATCH;  // index = identity
     const CT_G int32_t* src = fromRoot ? T->idx0 : s->idx[s->cur];
     const int dstBuf = fromRoot ? 0 : 1 - s->cur;
     CT_G int32_t* dst = s->idx[dstBuf];
@@ -548,11 +581,11 @@ __device__ int finalize_update(const DevJob& J, Shared& sh, bool ldsFlags, int j
     int sv = block_scan_excl(cnt, &nSurv, sh);
     int zr = nSurv + (b - sv);
     for (int p = b; p < e; ++p) {
-      const int gid = ldsFlags ? (int)sh.gidx[p] : src[p];
+      const int gid = scratch ? p : ldsFlags ? (int)sh.gidx[p] : src[p];
       const int f = ldsFlags ? sh.nz[p] : s->nzFlag[p];
       if (f) dst[sv++] = gid; else dst[zr++] = gid;
     }
-    for (int p = limit + threadIdx.x; p < nGran; p += BLOCK) dst[p] = src[p];
+    for (int p = limit + threadIdx.x; p < nGran; p += BLOCK) dst[p] = scratch ? p : src[p];
     if (nSurv == 0) st = ST_FAIL;
     if (threadIdx.x == 0) {
       s->cur = dstBuf;
@@ -567,6 +600,8 @@ __device__ int finalize_update(const DevJob& J, Shared& sh, bool ldsFlags, int j
       }
       if (nSurv == 0) s->failed = 1;
     }
+  } else if (fromRoot && st != ST_OK) {
+    slot_reset_root(T, s, J.serialBase);
   }
   if (threadIdx.x == 0) {
     s->status = st;
@@ -805,7 +840,8 @@ __device__ void do_solo(const KArgs& a, const DevJob& J, Shared& sh) {
     // the job's granule list, read once (each update step is then a single
     // round of independent loads)
     const CT_G int32_t* src = (J.flags & JF_FROM_ROOT) ? J.tab->idx0 : s->idx[s->cur];
-    for (int p = threadIdx.x; p < span; p += BLOCK) sh.gidx[p] = (uint16_t)src[p];
+    const bool scratch = J.flags & JF_SCRATCH;
+    for (int p = threadIdx.x; p < span; p += BLOCK) sh.gidx[p] = (uint16_t)(scratch ? p : src[p]);
   }
   __syncthreads();
   for (int c = 0; c < span; c += WAVES * NGS) {
@@ -1211,12 +1247,155 @@ __global__ void __launch_bounds__(FINISH_BLOCK) nodes_finish_kernel(KArgs a, Nod
       if (nrows) atomicAdd(&s->stats[S_GRAN_ROWS], (unsigned long long)limit0 * (unsigned long long)nrows);
     }
   }
+  if (!run) slot_reset_root(T, s, J.serialBase);
   __syncthreads();  // the partition is visible to the workgroup
   const int nSurv = run ? shSurv : 0;
   const int st = run ? (nSurv ? ST_OK : ST_FAIL) : st0;
   if (st == ST_OK) {
     unsigned long long cnt[3] = {0, 0, 0};
     for (int q = wv; q < T->D; q += FINISH_WAVES) filter_word(a, J, q, 0, nSurv, s->idx[0], cnt);
+    add_filter_stats(s, cnt);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    s->status = st;
+    s->pad2 = 0;
+    item_fence(J);
+    publish_status(J, st);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Batches whose jobs all recompute a root from scratch.  Stream: one wave per
+// (job, granule); a currTable word is the AND over the variables of the OR
+// of the support rows of the values in dom_in, starting from all tuples
+// (Alg. 2 with every variable on the reset branch).  A granule's words are
+// final once its wave ends, so the stream has no hand-offs; support rows are
+// fetched ROOT_UNROLL at a time, each as one coalesced 512-byte load of the
+// wave.  Finish: one workgroup per job validates dom_in, partitions the
+// granules (survivors first, Alg. 1's FAIL when none), sets the slot to
+// depth 0 and runs filterDomains (Alg. 3).
+// ---------------------------------------------------------------------------
+constexpr int ROOT_UNROLL = 16;
+
+__global__ void __launch_bounds__(BLOCK) root_stream_kernel(KArgs a, RootDesc R) {
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
+  const int job = R.tasks[2 * blockIdx.x];
+  const int g = R.tasks[2 * blockIdx.x + 1] + wv;
+  const DevJob J = a.jobs[job];
+  const TabDesc* T = J.tab;
+  if (g >= T->nGran) return;
+  const unsigned lane = (unsigned)lane_id();
+  const int64_t stride = T->stride;
+  const int64_t gOff = (int64_t)g * GW;
+  uint64_t acc = all_tuples_word(T, gOff + lane);
+  for (int i = 0; i < T->n; ++i) {
+    const VarDesc v = T->vars[i];
+    uint64_t orv = 0;
+    for (int k = 0; k < v.domWords; ++k) {
+      const int used = v.dsize - 64 * k;
+      uint64_t bits = job_din(a, J, v.domOff + k);  // uniform
+      if (used < 64) bits &= (1ull << used) - 1ull;  // stray bits: the finish rejects the job
+      const CT_G uint64_t* rows = T->S + (int64_t)(v.rowStart + 64 * k) * stride + gOff;
+      int b = 0;
+      while (bits) {
+        // past the last value the previous row is fetched again (OR is
+        // idempotent, the load hits the cache)
+        uint64_t x[ROOT_UNROLL];
+#pragma unroll
+        for (int u = 0; u < ROOT_UNROLL; ++u) {
+          if (bits) {
+            b = __ffsll((unsigned long long)bits) - 1;
+            bits &= bits - 1;
+          }
+          x[u] = rows[(int64_t)b * stride + lane];
+        }
+#pragma unroll
+        for (int u = 0; u < ROOT_UNROLL; ++u) orv |= x[u];
+      }
+    }
+    acc &= orv;
+    if (__ballot(acc != 0ull) == 0ull) break;  // the granule is already empty
+  }
+  SlotDesc* s = J.slot;
+  s->ct[gOff + lane] = acc;
+  if (J.ct_out && gOff + lane < T->W) J.ct_out[gOff + lane] = acc;
+  const bool nz = __ballot(acc != 0ull) != 0ull;
+  if (lane == 0) s->nzFlag[g] = nz ? 1 : 0;
+}
+
+__global__ void __launch_bounds__(FINISH_BLOCK) root_finish_kernel(KArgs a) {
+  __shared__ int32_t shSurv, shStray, shRows;
+  const int lane = lane_id();
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
+  const DevJob J = a.jobs[blockIdx.x];
+  const TabDesc* T = J.tab;
+  SlotDesc* s = J.slot;
+  if (threadIdx.x == 0) {
+    shStray = 0;
+    shRows = 0;
+  }
+  __syncthreads();
+  for (int q = threadIdx.x; q < T->D; q += FINISH_BLOCK) {
+    const uint64_t din = job_din(a, J, q);
+    const VarDesc v = T->vars[T->wordVar[q]];
+    const int used = v.dsize - 64 * (q - v.domOff);
+    if (used < 64 && (din >> used) != 0) shStray = 1;
+    atomicAdd(&shRows, __popcll(din));
+  }
+  __syncthreads();
+  if (shStray) {
+    slot_reset_root(T, s, J.serialBase);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      s->status = ST_INVALID;
+      s->pad2 = 0;
+      item_fence(J);
+      publish_status(J, ST_INVALID);
+    }
+    return;
+  }
+  if (wv == 0) {
+    const int nGran = T->nGran;
+    const CT_G int32_t* nzf = s->nzFlag;
+    CT_G int32_t* dst = s->idx[0];
+    const uint64_t below = (1ull << lane) - 1ull;
+    int nSurv = 0;
+    for (int p0 = 0; p0 < nGran; p0 += WAVE) {
+      const int p = p0 + lane;
+      nSurv += __popcll(__ballot(p < nGran && nzf[min(p, nGran - 1)] != 0));
+    }
+    int sv = 0, zr = nSurv;
+    for (int p0 = 0; p0 < nGran; p0 += WAVE) {
+      const int p = p0 + lane;
+      const bool in = p < nGran;
+      const bool f = in && nzf[min(p, nGran - 1)] != 0;
+      const uint64_t bs = __ballot(f), bz = __ballot(in && !f);
+      if (f) dst[sv + __popcll(bs & below)] = p;
+      else if (in) dst[zr + __popcll(bz & below)] = p;
+      sv += __popcll(bs);
+      zr += __popcll(bz);
+    }
+    if (lane == 0) {
+      shSurv = nSurv;
+      s->cur = 0;
+      s->limit = nSurv;
+      s->depth = 0;
+      s->trailTop = 0;
+      s->serial = J.serialBase;
+      s->failed = nSurv ? 0 : 1;
+      const unsigned long long rows = (unsigned long long)shRows;
+      atomicAdd(&s->stats[S_JOBS], 1ull);
+      atomicAdd(&s->stats[S_GRAN_IN], (unsigned long long)nGran);
+      atomicAdd(&s->stats[S_ROWS], rows);
+      if (rows) atomicAdd(&s->stats[S_GRAN_ROWS], (unsigned long long)nGran * rows);
+    }
+  }
+  __syncthreads();
+  const int st = shSurv ? ST_OK : ST_FAIL;
+  if (st == ST_OK) {
+    unsigned long long cnt[3] = {0, 0, 0};
+    for (int q = wv; q < T->D; q += FINISH_WAVES) filter_word(a, J, q, 0, shSurv, s->idx[0], cnt);
     add_filter_stats(s, cnt);
   }
   __syncthreads();
@@ -1581,6 +1760,13 @@ hipError_t launch_nodes(const KArgs& a, const NodesDesc& N, int n, hipStream_t s
   const size_t lds = nodes_update_lds(N.rows, n, N.groupSize);
   hipLaunchKernelGGL(nodes_update_kernel, dim3(nodes_update_grid(lds)), dim3(NODES_BLOCK), lds, stream, a, N);
   hipLaunchKernelGGL(nodes_finish_kernel, dim3(N.nJobs), dim3(FINISH_BLOCK), 0, stream, a, N);
+  return hipGetLastError();
+}
+
+hipError_t launch_roots(const KArgs& a, const RootDesc& R, hipStream_t stream) {
+  if (R.nTasks > 0)
+    hipLaunchKernelGGL(root_stream_kernel, dim3(R.nTasks), dim3(BLOCK), 0, stream, a, R);
+  hipLaunchKernelGGL(root_finish_kernel, dim3(a.nJobs), dim3(FINISH_BLOCK), 0, stream, a);
   return hipGetLastError();
 }
 

@@ -34,6 +34,7 @@ int nodes_list_cap(int rows, int n);
 int nodes_node_words(int rows, int n);
 size_t nodes_update_lds(int rows, int n, int groupSize);
 hipError_t launch_nodes(const KArgs& a, const NodesDesc& N, int n, hipStream_t stream);
+hipError_t launch_roots(const KArgs& a, const RootDesc& R, hipStream_t stream);
 hipError_t launch_build_supports(const int32_t* tuples, int64_t t, int n, const VarDesc* vars,
                                  const int32_t* lo, uint64_t* S, int64_t stride, int64_t W,
                                  hipStream_t stream);
@@ -233,6 +234,7 @@ constexpr int SOLO_MAX_GRAN = 4;      // tables up to 16,384 tuples run solo
 constexpr int SOLO_MIN_BATCH = 256;   // batches this large run every job solo
 
 constexpr int NODES_MIN_BATCH = 64;   // AUTO: batches of root resets this large run granule-major
+constexpr int SCRATCH_SOLO_MAX_GRAN = 16;  // AUTO: roots recomputed solo up to 65,536 tuples
 
 bool use_solo(const ct_table* T, int nJobs) {
   if (T->cfg.schedule == CT_SCHED_SOLO) return true;
@@ -259,6 +261,15 @@ int nodes_group_size(const ct_table* T) {
     for (int gs = 64; gs >= 8; gs -= 8)
       if (per * nodes_update_lds(T->rows, T->n, gs) <= lds) return gs;
   return 0;
+}
+
+// Batches of roots recomputed from scratch run on their own streaming
+// kernels when every job is a ROOT job of a table on the AUTO schedule.
+bool use_roots(const ct_job* jobs, int n) {
+  for (int j = 0; j < n; ++j)
+    if (jobs[j].flags != (CT_JOB_PROPAGATE | CT_JOB_ROOT) || jobs[j].table->cfg.schedule != CT_SCHED_AUTO)
+      return false;
+  return true;
 }
 
 bool use_nodes(const ct_job* jobs, int n) {
@@ -678,6 +689,7 @@ static int create_impl(ct_table* T, const int32_t* tuples, int64_t t, int32_t n,
   tb.vars = T->dVars;
   tb.wordVar = T->dWordVar;
   tb.policy = T->cfg.branch_policy;
+  tb.tailBits = T->W > 0 ? (int32_t)(t - 64 * (T->W - 1)) : 0;
   HIPCHK(hipMemcpy(T->dTab, &tb, sizeof(TabDesc), hipMemcpyHostToDevice));
 
   // root propagation: every variable takes the reset branch over dom0
@@ -1023,8 +1035,12 @@ int ct_propagate_batch(const ct_job* jobs, int32_t n_jobs, void* stream_v, int32
     if ((rc = check_slot(T, cj.slot))) return rc;
     if (!seen.insert({T, cj.slot}).second)
       return fail(CT_E_INVALID, "job %d: slot %d appears twice in the batch", j, cj.slot);
-    if (cj.flags & ~(CT_JOB_PROPAGATE | CT_JOB_FROM_ROOT))
+    if (cj.flags & ~(CT_JOB_PROPAGATE | CT_JOB_FROM_ROOT | CT_JOB_ROOT))
       return fail(CT_E_INVALID, "job %d: unknown flags", j);
+    if ((cj.flags & CT_JOB_ROOT) && (cj.flags & CT_JOB_FROM_ROOT))
+      return fail(CT_E_INVALID, "job %d: ROOT and FROM_ROOT together", j);
+    if ((cj.flags & CT_JOB_ROOT) && (cj.n_pop || cj.n_push || !(cj.flags & CT_JOB_PROPAGATE)))
+      return fail(CT_E_INVALID, "job %d: ROOT needs PROPAGATE and no pops/pushes", j);
     if (cj.n_pop < 0 || cj.n_push < 0) return fail(CT_E_INVALID, "job %d: negative pops/pushes", j);
     const SlotHost& S = T->slots[cj.slot];
     if (cj.flags & CT_JOB_FROM_ROOT) {
@@ -1069,6 +1085,7 @@ int ct_propagate_batch(const ct_job* jobs, int32_t n_jobs, void* stream_v, int32
     }
   }
   const bool nodes = use_nodes(jobs, n_jobs);
+  const bool roots = !nodes && use_roots(jobs, n_jobs);
   if (nodes) {
     const ct_table* T = jobs[0].table;
     const size_t need = align256(sizeof(uint64_t) * (size_t)n_jobs * nodes_node_words(T->rows, T->n)) +
@@ -1098,8 +1115,9 @@ int ct_propagate_batch(const ct_job* jobs, int32_t n_jobs, void* stream_v, int32
     J.ct_out = cj.ct_out;
     J.status_out = status_dev + j;
     J.flags = ((cj.flags & CT_JOB_PROPAGATE) ? JF_PROPAGATE : 0u) |
-              ((cj.flags & CT_JOB_FROM_ROOT) ? JF_FROM_ROOT : 0u);
-    if (cj.flags & CT_JOB_FROM_ROOT) {
+              ((cj.flags & CT_JOB_FROM_ROOT) ? JF_FROM_ROOT : 0u) |
+              ((cj.flags & CT_JOB_ROOT) ? (JF_ROOT | JF_FROM_ROOT | JF_SCRATCH) : 0u);
+    if (cj.flags & (CT_JOB_FROM_ROOT | CT_JOB_ROOT)) {
       S.pendPop = S.pendPush = 0;
       S.depth = 0;
       S.failedAt.clear();
@@ -1125,14 +1143,35 @@ int ct_propagate_batch(const ct_job* jobs, int32_t n_jobs, void* stream_v, int32
       J.depthAfter = S.depth;
     }
     S.failed = 2;
-    if ((J.flags & JF_PROPAGATE) && !nodes && use_solo(T, n_jobs)) J.flags |= JF_SOLO;
+    // a root recomputed from scratch streams every support row: large
+    // tables are split over workgroups (the queue balances them), small ones
+    // run solo
+    const bool solo = (J.flags & JF_SCRATCH) && T->cfg.schedule == CT_SCHED_AUTO
+                          ? T->nGran <= SCRATCH_SOLO_MAX_GRAN
+                          : use_solo(T, n_jobs);
+    if ((J.flags & JF_PROPAGATE) && !nodes && solo) J.flags |= JF_SOLO;
     job_counts(T, J);
     updOff[j + 1] = updOff[j] + J.nUpd;
     filtOff[j + 1] = filtOff[j] + J.nFilt;
     if (needs_prep(J)) prep.push_back(j);
   }
-  // stage to the device
-  const size_t nOff = 2 * (size_t)(n_jobs + 1) + prep.size() + 1;
+  // root streams: WAVES granules per task, tables with the most support rows
+  // first (their tasks are the longest)
+  std::vector<int32_t> rootTasks;
+  if (roots) {
+    std::vector<int> order(n_jobs);
+    for (int j = 0; j < n_jobs; ++j) order[j] = j;
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int x, int y) { return jobs[x].table->rows > jobs[y].table->rows; });
+    for (int j : order)
+      for (int g = 0; g < jobs[j].table->nGran; g += WAVES) {
+        rootTasks.push_back(j);
+        rootTasks.push_back(g);
+      }
+  }
+  // stage to the device (the root tasks start at an even offset: int pairs)
+  const size_t rootBase = (2 * (size_t)(n_jobs + 1) + prep.size() + 2) & ~(size_t)1;
+  const size_t nOff = roots ? rootBase + rootTasks.size() : 2 * (size_t)(n_jobs + 1) + prep.size() + 1;
   if (q->capJobs < (size_t)n_jobs || q->capPinned < nOff) {
     HIPCHK(hipStreamSynchronize(stream));
     if (q->dJobs) (void)hipFree(q->dJobs);
@@ -1152,6 +1191,7 @@ int ct_propagate_batch(const ct_job* jobs, int32_t n_jobs, void* stream_v, int32
   memcpy(q->pOff, updOff.data(), sizeof(int32_t) * (n_jobs + 1));
   memcpy(q->pOff + (n_jobs + 1), filtOff.data(), sizeof(int32_t) * (n_jobs + 1));
   if (!prep.empty()) memcpy(q->pOff + 2 * (n_jobs + 1), prep.data(), sizeof(int32_t) * prep.size());
+  if (!rootTasks.empty()) memcpy(q->pOff + rootBase, rootTasks.data(), sizeof(int32_t) * rootTasks.size());
   HIPCHK(hipMemcpyAsync(q->dJobs, q->pJobs, sizeof(DevJob) * n_jobs, hipMemcpyHostToDevice, stream));
   HIPCHK(hipMemcpyAsync(q->dOff, q->pOff, sizeof(int32_t) * nOff, hipMemcpyHostToDevice, stream));
   HIPCHK(hipEventRecord(q->staged, stream));
@@ -1186,6 +1226,13 @@ int ct_propagate_batch(const ct_job* jobs, int32_t n_jobs, void* stream_v, int32
     N.S = T->hTab.S;
     N.ct0 = T->hTab.ct0;
     HIPCHK(launch_nodes(a, N, T->n, stream));
+    return CT_OK;
+  }
+  if (roots) {
+    RootDesc R{};
+    R.tasks = q->dOff + rootBase;
+    R.nTasks = (int32_t)(rootTasks.size() / 2);
+    HIPCHK(launch_roots(a, R, stream));
     return CT_OK;
   }
   const int total = a.nPrep + a.nUpd + a.nFilt;

@@ -21,7 +21,7 @@ OK, FAIL = 0, 1
 E_INVALID, E_NOT_SUBSET, E_STATE, E_NOMEM, E_DEVICE = -1, -2, -3, -4, -5
 BRANCH_AUTO, BRANCH_RESET, BRANCH_INCREMENTAL = 0, 1, 2
 SCHED_AUTO, SCHED_SOLO, SCHED_SPLIT, SCHED_NODES, SCHED_RESIDENT = 0, 1, 2, 3, 4
-JOB_PROPAGATE, JOB_FROM_ROOT = 1, 2
+JOB_PROPAGATE, JOB_FROM_ROOT, JOB_ROOT = 1, 2, 4
 
 
 class CTError(RuntimeError):

@@ -357,6 +357,10 @@ def test_batch_nodes_schedule_edge_cases(n_nodes):
                 assert (gd == od).all() and (gc == oc).all(), (rep, k)
             elif os_ == O.FAIL:
                 assert not got_ct[k].any(), (rep, k)
+            else:
+                # rejected input: the slot still holds the root
+                gd, _ = G.state(first + k)
+                assert (gd == root).all(), (rep, k)
         if n_nodes > 3:
             assert {int(x) for x in st} >= {ct.OK, ct.FAIL, ct.E_INVALID, ct.E_NOT_SUBSET}
 
@@ -410,3 +414,122 @@ def test_batch_with_backtracking_equals_sequential(schedule):
                     Gs.pop(fs + k)
                     Gb.pop(fb + k)
                     depth[k] -= 1
+
+
+@pytest.mark.parametrize("schedule,mixed", [(ct.SCHED_AUTO, False), (ct.SCHED_AUTO, True),
+                                            (ct.SCHED_SOLO, False), (ct.SCHED_SPLIT, False)])
+def test_batch_root_from_scratch_vs_oracle(schedule, mixed):
+    """ROOT jobs recompute a table's root state from all tuples (Alg. 1, every
+    variable on the reset branch) for any input domains: the result must be
+    the GAC closure that an oracle table created with those initial domains
+    reaches, and the slot must then carry on like that oracle table.  A batch
+    of ROOT jobs alone runs on the streaming root kernels; mixed with an
+    ordinary job, or under the SOLO / SPLIT schedules, on the work queue."""
+    import torch
+    say("batch ROOT jobs from scratch, schedule", schedule, "mixed" if mixed else "")
+    rng = W.rng_for(12, 205, schedule)
+    cases = []
+    # a one-granule table, and one of 21 granules with multi-word domains and a
+    # ragged last word (solo below 17 granules, split above under AUTO)
+    for t, ds, lo in [(300, [5, 7, 3], [0, -2, 1]),
+                      (64 * 64 * 20 + 37, [130, 3, 65, 1, 40], [-7, 0, 100, 5, 0])]:
+        ds = np.array(ds, np.int32)
+        lo = np.array(lo, np.int32)
+        hi = ds.copy()
+        hi[0] = max(1, hi[0] - 2)              # the last values of x0 have no support
+        tup = np.stack([rng.integers(lo[i], lo[i] + hi[i], size=t) for i in range(len(ds))],
+                       1).astype(np.int32)
+        cases.append((tup, lo, ds))
+    tabs, jobs_spec = [], []
+    for ci, (tup, lo, ds) in enumerate(cases):
+        lay = W.DomLayout(ds, lo)
+        init = random_subset(rng, lay, lay.full(), 0.9)   # the table's own initial domains
+        G = ct.Table(tup, lo, ds, init_dom=init, schedule=schedule)
+        G.init_dom = init
+        tabs.append(G)
+        nj = 10
+        first = G.slots_alloc(nj, max_depth=4)
+        for k in range(nj):
+            kind = k % 5
+            if kind == 0:
+                d = init.copy()                  # recomputes the table's own root
+            elif kind == 1:
+                d = lay.full()                   # values the table's root pruned
+            elif kind == 2:
+                d = lay.full()
+                for a in lay.values(d, 1):
+                    lay.clear(d, 1, int(a))      # an empty domain
+            elif kind == 3:
+                d = lay.full()
+                d[lay.D - 1] |= np.uint64(1) << np.uint64(63)   # a stray bit
+            else:
+                d = random_subset(rng, lay, lay.full(), float(rng.uniform(0.1, 0.95)))
+            jobs_spec.append((ci, G, first + k, d, kind))
+    # one batch mixes both tables; ordinary jobs first move every slot off the root
+    status = torch.full((len(jobs_spec),), 99, dtype=torch.int32, device="cuda")
+    pre = []
+    for ci, G, slot, d, kind in jobs_spec:
+        assert G.push(slot) == ct.OK
+        sub = random_subset(rng, W.DomLayout(cases[ci][2], cases[ci][1]), G.domains(slot), 0.7)
+        G.propagate(sub, slot=slot)
+        pre.append(G.state(slot))
+    dins = [to_dev(d) for _, _, _, d, _ in jobs_spec]
+    douts = [torch.zeros_like(x) for x in dins]
+    cts = [torch.zeros((G.W,), dtype=torch.int64, device="cuda") for _, G, _, _, _ in jobs_spec]
+    jobs = [dict(table=G, slot=slot, flags=ct.JOB_PROPAGATE | ct.JOB_ROOT,
+                 dom_in=dins[j], dom_out=douts[j], ct_out=cts[j])
+            for j, (_, G, slot, _, _) in enumerate(jobs_spec)]
+    if mixed:
+        # an ordinary job on slot 0 of the first table, checked against a
+        # single call on a twin table
+        tup, lo, ds = cases[0]
+        G0 = tabs[0]
+        twin = ct.Table(tup, lo, ds, init_dom=G0.domains(0))
+        sub = random_subset(rng, W.DomLayout(ds, lo), G0.domains(0), 0.6)
+        xin, xout = to_dev(sub), to_dev(np.zeros_like(sub))
+        jobs.append(dict(table=G0, slot=0, flags=ct.JOB_PROPAGATE, dom_in=xin, dom_out=xout))
+        status = torch.full((len(jobs),), 99, dtype=torch.int32, device="cuda")
+    ct.propagate_batch(jobs, status)
+    torch.cuda.synchronize()
+    st = status.cpu().numpy()
+    if mixed:
+        ts, td = twin.propagate(sub)
+        assert st[-1] == ts
+        if ts == ct.OK:
+            assert (from_dev(xout) == td).all()
+    for j, (ci, G, slot, d, kind) in enumerate(jobs_spec):
+        tup, lo, ds = cases[ci]
+        if kind == 3:
+            assert st[j] == ct.E_INVALID, j
+            # a rejected job still resets the slot: it holds the table's root at depth 0
+            gd, gc = G.state(slot)
+            od, oc, _ = O.OracleTable(tup, lo, ds, init_dom=G.init_dom).state()
+            assert (gd == od).all() and (gc == oc).all(), j
+            assert G.pop(slot) != ct.OK, j
+            continue
+        Ox = O.OracleTable(tup, lo, ds, init_dom=d)
+        od, oc, of = Ox.state()
+        if of:
+            assert st[j] == ct.FAIL, (j, st[j])
+            assert not from_dev(cts[j]).any(), j
+            continue
+        assert st[j] == ct.OK, (j, st[j])
+        assert (from_dev(douts[j]) == od).all(), j
+        assert (from_dev(cts[j]) == oc).all(), j
+        gd, gc = G.state(slot)
+        assert (gd == od).all() and (gc == oc).all(), j
+        if kind == 0 and not mixed:
+            rd, rc = G.state(0)
+            assert (gd == rd).all() and (gc == rc).all(), j
+        # the slot is at depth 0 and continues like the oracle table
+        lay = W.DomLayout(ds, lo)
+        assert G.pop(slot) != ct.OK, j
+        assert G.push(slot) == ct.OK and Ox.push() == O.OK
+        sub = random_subset(rng, lay, od, 0.6)
+        gs_, gdd = G.propagate(sub, slot=slot)
+        os_, odd = Ox.propagate(sub)
+        assert gs_ == os_, j
+        if os_ == O.OK:
+            assert (gdd == odd).all(), j
+        assert G.pop(slot) == ct.OK and Ox.pop() == O.OK
+        same_state(G, Ox, slot, f"job {j} after pop")
