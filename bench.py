@@ -28,6 +28,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+LDS_PEAK_GBS = 256 * 128 * 2.4  # 256 CUs x 128 B/clock x 2.4 GHz
 
 
 def parse():
@@ -151,7 +152,6 @@ def nodes_leg(seed, n_nodes, reps, warmup, schedule=0):
     for _ in range(warmup):
         ct.propagate_batch(jobs, status, stream)
     torch.cuda.synchronize()
-    s0 = [table.stats(first + k) for k in (0,)]
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     t0 = time.perf_counter()
     e0.record(stream)
@@ -162,6 +162,10 @@ def nodes_leg(seed, n_nodes, reps, warmup, schedule=0):
     wall = time.perf_counter() - t0
     ct.batch_status(stream)
     gpu_ms = e0.elapsed_time(e1) / reps
+    # the update kernel reads one 512-byte granule of a support row from LDS
+    # per (node, selected row, active granule); the slots are fresh, so their
+    # counters cover exactly the warmup and timed batches
+    lds_bytes = 512 * sum(table.stats(first + k)["granule_rows"] for k in range(n_nodes)) / (warmup + reps)
     st = status.cpu().numpy()
     # algorithmic bytes of one batch: compulsory traffic = supports once +
     # root currTable once + per node currTable write + domains
@@ -179,6 +183,10 @@ def nodes_leg(seed, n_nodes, reps, warmup, schedule=0):
         "frac_of_hbm_peak": round(comp / (gpu_ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
         "update_kernel_hbm_bytes": prof.get("hbm_bytes_per_launch") if prof else None,
         "update_kernel_avg_us_profiled": prof.get("avg_us") if prof else None,
+        "update_kernel_lds_bytes": lds_bytes,
+        "update_kernel_lds_roofline": None if not prof else {
+            "bound": "lds", "achieved": round(lds_bytes / prof["avg_us"] / 1e3, 1), "peak": LDS_PEAK_GBS,
+            "unit": "GB/s", "frac": round(lds_bytes / prof["avg_us"] / 1e3 / LDS_PEAK_GBS, 4)},
     }
 
 
@@ -268,8 +276,10 @@ def root_batch_leg(tabs, specs, reps, per_table=True):
                for k, t in enumerate(tabs))
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record()
+    h0 = time.perf_counter()
     for _ in range(reps):
         batch.run(status)
+    host_ms = (time.perf_counter() - h0) * 1e3 / reps
     e1.record()
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / reps
@@ -280,8 +290,19 @@ def root_batch_leg(tabs, specs, reps, per_table=True):
     out = {"jobs": n, "matches_table_roots": bool(same), "ms_per_batch": round(ms, 4),
            "compulsory_bytes": byts, "compulsory_GBps": round(byts / ms / 1e6, 1),
            "frac_of_hbm_peak": round(byts / ms / 1e6 / HBM_PEAK_GBS, 4),
-           "kernels": "ctk::root_stream_kernel + ctk::root_finish_kernel",
+           "host_issue_ms_per_batch": round(host_ms, 4),
            "timing": "HIP events around the batches on the launch stream"}
+    # the streaming kernel alone, from the committed rocprofv3 summary
+    from paper_2507_18413_amd import profiling
+    prof = profiling.read_summary(os.path.join(ROOT, "profiles", "root_stream_config3.md"))
+    stream_bytes = 8 * rows_w + 8 * sum(int(t.W) for t in tabs)
+    out["stream_kernel"] = {"name": "ctk::root_stream_kernel", "algorithmic_bytes": stream_bytes}
+    if prof:
+        us = prof["avg_us"]
+        out["stream_kernel"].update({
+            "avg_us_profiled": us, "hbm_bytes_profiled": prof.get("hbm_bytes_per_launch"),
+            "roofline": {"bound": "hbm", "achieved": round(stream_bytes / us / 1e3, 1), "peak": HBM_PEAK_GBS,
+                         "unit": "GB/s", "frac": round(stream_bytes / us / 1e3 / HBM_PEAK_GBS, 4)}})
     if per_table:
         singles = [ct.Batch([j]) for j in jobs]
         torch.cuda.synchronize()
@@ -314,7 +335,7 @@ def model_leg(seed, steps, plain_steps, cpu):
     for tb, sc in zip(tabs, spec.scopes):
         M.add(tb, sc)
     build_s = time.perf_counter() - t0 - gen_s
-    root_batch = root_batch_leg(tabs, spec.tables, 5)
+    root_batch = root_batch_leg(tabs, spec.tables, 20)
     full = lay.full()
     dev = lambda a: torch.from_numpy(np.ascontiguousarray(a).view(np.int64)).cuda()
     pin, pout = dev(full), dev(full)
@@ -557,6 +578,21 @@ def serve_leg(tables_spec, seed, rate, n_requests, n_searches, budget, sample_ch
     return out
 
 
+def calibration_copy(mib):
+    """One device-to-device copy of `mib` MiB by the runtime (the reference
+    dispatch that scales the HBM byte counters)."""
+    if not mib:
+        return
+    import torch
+    n = mib * (1 << 20) // 8
+    src = torch.ones(n, dtype=torch.int64, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    del src, dst
+
+
 def note(msg):
     """Progress on stderr (the JSON result line is the only stdout output)."""
     print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
@@ -578,6 +614,7 @@ def main():
         note("generating the 2,000-table model")
         mspec = W.config3_model(seed)
         torch.cuda.set_device(0)
+        calibration_copy(args.calibration_copy)
         tabs = [ct.Table(tb.tuples, tb.lo, tb.dsizes) for tb in mspec.tables]
         note("batched root recomputation")
         print(json.dumps({"root_gac_batch": root_batch_leg(tabs, mspec.tables, max(1, args.steps),
@@ -591,14 +628,7 @@ def main():
         serve_spec = W.config5_tables(seed, workers=min(16, os.cpu_count() or 1))
     note("plain leg: building the 200,000-tuple table")
     torch.cuda.set_device(0)
-    if args.calibration_copy:
-        n = args.calibration_copy * (1 << 20) // 8
-        src = torch.ones(n, dtype=torch.int64, device="cuda")
-        dst = torch.empty_like(src)
-        torch.cuda.synchronize()
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
+    calibration_copy(args.calibration_copy)
     spec = W.config2_table(seed)
     lay = spec.layout()
     # the table under test (synchronous calls go to the resident engine when

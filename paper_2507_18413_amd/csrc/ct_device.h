@@ -108,7 +108,9 @@ struct SlotDesc {
   int64_t trailTop;
   int32_t cur, limit, failed, depth, serial, pad1;
   // per-job scratch
-  int32_t updCount, filtCount, jobTrail, prepDone, updDone, status, newLimit, pad2;
+  int32_t updCount, filtCount, jobTrail, prepDone, updDone, status;
+  int32_t nzCount;  // granules a root stream found non-empty (reset by its finish)
+  int32_t pad2;
   unsigned long long stats[8];
 };
 

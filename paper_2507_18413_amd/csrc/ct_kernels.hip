@@ -539,13 +539,14 @@ __device__ void update_granules(const KArgs& a, const DevJob& J, Shared& sh, int
 // ---------------------------------------------------------------------------
 // A job that resets its slot to the root (depth 0) and then rejects its input
 // still performs the reset: the slot becomes a copy of the table's root state
-// (one workgroup, any block size; a rare path, so the whole currTable is copied).
+// (threads tid of nthr, a workgroup or a wave; a rare path, so the whole
+// currTable is copied).
 // ---------------------------------------------------------------------------
-__device__ void slot_reset_root(const TabDesc* T, SlotDesc* s, int serial) {
-  for (int64_t w = threadIdx.x; w < T->stride; w += blockDim.x) s->ct[w] = T->ct0[w];
-  for (int p = threadIdx.x; p < T->nGran; p += blockDim.x) s->idx[0][p] = T->idx0[p];
-  for (int q = threadIdx.x; q < T->D; q += blockDim.x) s->lastDom[q] = T->dom0[q];
-  if (threadIdx.x == 0) {
+__device__ void slot_reset_root(const TabDesc* T, SlotDesc* s, int serial, int tid, int nthr) {
+  for (int64_t w = tid; w < T->stride; w += nthr) s->ct[w] = T->ct0[w];
+  for (int p = tid; p < T->nGran; p += nthr) s->idx[0][p] = T->idx0[p];
+  for (int q = tid; q < T->D; q += nthr) s->lastDom[q] = T->dom0[q];
+  if (tid == 0) {
     s->cur = 0;
     s->limit = T->limit0;
     s->failed = T->rootFailed;
@@ -601,7 +602,7 @@ __device__ int finalize_update(const DevJob& J, Shared& sh, bool ldsFlags, int j
       if (nSurv == 0) s->failed = 1;
     }
   } else if (fromRoot && st != ST_OK) {
-    slot_reset_root(T, s, J.serialBase);
+    slot_reset_root(T, s, J.serialBase, threadIdx.x, blockDim.x);
   }
   if (threadIdx.x == 0) {
     s->status = st;
@@ -1247,7 +1248,7 @@ __global__ void __launch_bounds__(FINISH_BLOCK) nodes_finish_kernel(KArgs a, Nod
       if (nrows) atomicAdd(&s->stats[S_GRAN_ROWS], (unsigned long long)limit0 * (unsigned long long)nrows);
     }
   }
-  if (!run) slot_reset_root(T, s, J.serialBase);
+  if (!run) slot_reset_root(T, s, J.serialBase, threadIdx.x, blockDim.x);
   __syncthreads();  // the partition is visible to the workgroup
   const int nSurv = run ? shSurv : 0;
   const int st = run ? (nSurv ? ST_OK : ST_FAIL) : st0;
@@ -1271,18 +1272,19 @@ __global__ void __launch_bounds__(FINISH_BLOCK) nodes_finish_kernel(KArgs a, Nod
 // of the support rows of the values in dom_in, starting from all tuples
 // (Alg. 2 with every variable on the reset branch).  A granule's words are
 // final once its wave ends, so the stream has no hand-offs; support rows are
-// fetched ROOT_UNROLL at a time, each as one coalesced 512-byte load of the
-// wave.  Finish: one workgroup per job validates dom_in, partitions the
-// granules (survivors first, Alg. 1's FAIL when none), sets the slot to
-// depth 0 and runs filterDomains (Alg. 3).
+// fetched ROOT_UNROLL at a time, each as one coalesced 512-byte non-temporal
+// load of the wave (read once: kept out of the caches' way).  Finish (next launch): one workgroup per job validates dom_in,
+// partitions the granules (survivors first; Alg. 1's FAIL when none), sets
+// the slot to depth 0 and runs filterDomains (Alg. 3).  The launch boundary
+// orders the two; a hand-off inside one launch would need a release per wave
+// (an L2 write-back on this chip), which costs more than the second launch.
 // ---------------------------------------------------------------------------
-constexpr int ROOT_UNROLL = 16;
+constexpr int ROOT_UNROLL = 4;
 
 __global__ void __launch_bounds__(BLOCK) root_stream_kernel(KArgs a, RootDesc R) {
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
-  const int job = R.tasks[2 * blockIdx.x];
+  const DevJob J = a.jobs[R.tasks[2 * blockIdx.x]];
   const int g = R.tasks[2 * blockIdx.x + 1] + wv;
-  const DevJob J = a.jobs[job];
   const TabDesc* T = J.tab;
   if (g >= T->nGran) return;
   const unsigned lane = (unsigned)lane_id();
@@ -1308,7 +1310,7 @@ __global__ void __launch_bounds__(BLOCK) root_stream_kernel(KArgs a, RootDesc R)
             b = __ffsll((unsigned long long)bits) - 1;
             bits &= bits - 1;
           }
-          x[u] = rows[(int64_t)b * stride + lane];
+          x[u] = __builtin_nontemporal_load(rows + (int64_t)b * stride + lane);
         }
 #pragma unroll
         for (int u = 0; u < ROOT_UNROLL; ++u) orv |= x[u];
@@ -1321,10 +1323,13 @@ __global__ void __launch_bounds__(BLOCK) root_stream_kernel(KArgs a, RootDesc R)
   s->ct[gOff + lane] = acc;
   if (J.ct_out && gOff + lane < T->W) J.ct_out[gOff + lane] = acc;
   const bool nz = __ballot(acc != 0ull) != 0ull;
-  if (lane == 0) s->nzFlag[g] = nz ? 1 : 0;
+  if (lane == 0) {
+    s->nzFlag[g] = nz ? 1 : 0;
+    if (nz) atomicAdd(&s->nzCount, 1);
+  }
 }
 
-__global__ void __launch_bounds__(FINISH_BLOCK) root_finish_kernel(KArgs a) {
+__global__ void __launch_bounds__(BLOCK) root_finish_kernel(KArgs a) {
   __shared__ int32_t shSurv, shStray, shRows;
   const int lane = lane_id();
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
@@ -1334,9 +1339,11 @@ __global__ void __launch_bounds__(FINISH_BLOCK) root_finish_kernel(KArgs a) {
   if (threadIdx.x == 0) {
     shStray = 0;
     shRows = 0;
+    shSurv = s->nzCount;  // counted by the stream
+    s->nzCount = 0;
   }
   __syncthreads();
-  for (int q = threadIdx.x; q < T->D; q += FINISH_BLOCK) {
+  for (int q = threadIdx.x; q < T->D; q += BLOCK) {
     const uint64_t din = job_din(a, J, q);
     const VarDesc v = T->vars[T->wordVar[q]];
     const int used = v.dsize - 64 * (q - v.domOff);
@@ -1344,65 +1351,55 @@ __global__ void __launch_bounds__(FINISH_BLOCK) root_finish_kernel(KArgs a) {
     atomicAdd(&shRows, __popcll(din));
   }
   __syncthreads();
+  int st;
   if (shStray) {
-    slot_reset_root(T, s, J.serialBase);
+    slot_reset_root(T, s, J.serialBase, threadIdx.x, BLOCK);  // the reset still happens
+    st = ST_INVALID;
+  } else {
+    if (wv == 0) {
+      const int nGran = T->nGran;
+      const CT_G int32_t* nzf = s->nzFlag;
+      CT_G int32_t* dst = s->idx[0];
+      const uint64_t below = (1ull << lane) - 1ull;
+      const int nSurv = shSurv;
+      int sv = 0, zr = nSurv;
+      for (int p0 = 0; p0 < nGran; p0 += WAVE) {
+        const int p = p0 + lane;
+        const bool in = p < nGran;
+        const bool f = in && nzf[min(p, nGran - 1)] != 0;
+        const uint64_t bs = __ballot(f), bz = __ballot(in && !f);
+        if (f) dst[sv + __popcll(bs & below)] = p;
+        else if (in) dst[zr + __popcll(bz & below)] = p;
+        sv += __popcll(bs);
+        zr += __popcll(bz);
+      }
+      if (lane == 0) {
+        s->cur = 0;
+        s->limit = nSurv;
+        s->depth = 0;
+        s->trailTop = 0;
+        s->serial = J.serialBase;
+        s->failed = nSurv ? 0 : 1;
+        const unsigned long long rows = (unsigned long long)shRows;
+        atomicAdd(&s->stats[S_JOBS], 1ull);
+        atomicAdd(&s->stats[S_GRAN_IN], (unsigned long long)nGran);
+        atomicAdd(&s->stats[S_ROWS], rows);
+        if (rows) atomicAdd(&s->stats[S_GRAN_ROWS], (unsigned long long)nGran * rows);
+      }
+    }
     __syncthreads();
-    if (threadIdx.x == 0) {
-      s->status = ST_INVALID;
-      s->pad2 = 0;
-      item_fence(J);
-      publish_status(J, ST_INVALID);
+    st = shSurv ? ST_OK : ST_FAIL;
+    if (st == ST_OK) {
+      unsigned long long cnt[3] = {0, 0, 0};
+      for (int q = wv; q < T->D; q += WAVES) filter_word(a, J, q, 0, shSurv, s->idx[0], cnt);
+      add_filter_stats(s, cnt);
     }
-    return;
-  }
-  if (wv == 0) {
-    const int nGran = T->nGran;
-    const CT_G int32_t* nzf = s->nzFlag;
-    CT_G int32_t* dst = s->idx[0];
-    const uint64_t below = (1ull << lane) - 1ull;
-    int nSurv = 0;
-    for (int p0 = 0; p0 < nGran; p0 += WAVE) {
-      const int p = p0 + lane;
-      nSurv += __popcll(__ballot(p < nGran && nzf[min(p, nGran - 1)] != 0));
-    }
-    int sv = 0, zr = nSurv;
-    for (int p0 = 0; p0 < nGran; p0 += WAVE) {
-      const int p = p0 + lane;
-      const bool in = p < nGran;
-      const bool f = in && nzf[min(p, nGran - 1)] != 0;
-      const uint64_t bs = __ballot(f), bz = __ballot(in && !f);
-      if (f) dst[sv + __popcll(bs & below)] = p;
-      else if (in) dst[zr + __popcll(bz & below)] = p;
-      sv += __popcll(bs);
-      zr += __popcll(bz);
-    }
-    if (lane == 0) {
-      shSurv = nSurv;
-      s->cur = 0;
-      s->limit = nSurv;
-      s->depth = 0;
-      s->trailTop = 0;
-      s->serial = J.serialBase;
-      s->failed = nSurv ? 0 : 1;
-      const unsigned long long rows = (unsigned long long)shRows;
-      atomicAdd(&s->stats[S_JOBS], 1ull);
-      atomicAdd(&s->stats[S_GRAN_IN], (unsigned long long)nGran);
-      atomicAdd(&s->stats[S_ROWS], rows);
-      if (rows) atomicAdd(&s->stats[S_GRAN_ROWS], (unsigned long long)nGran * rows);
-    }
-  }
-  __syncthreads();
-  const int st = shSurv ? ST_OK : ST_FAIL;
-  if (st == ST_OK) {
-    unsigned long long cnt[3] = {0, 0, 0};
-    for (int q = wv; q < T->D; q += FINISH_WAVES) filter_word(a, J, q, 0, shSurv, s->idx[0], cnt);
-    add_filter_stats(s, cnt);
   }
   __syncthreads();
   if (threadIdx.x == 0) {
     s->status = st;
     s->pad2 = 0;
-    item_fence(J);
+    if (J.flags & JF_HOST_OUT) __threadfence_system();
     publish_status(J, st);
   }
 }
@@ -1546,7 +1543,7 @@ __global__ void __launch_bounds__(BLOCK) init_slots_kernel(const TabDesc* T, Slo
     s->prepDone = 0;
     s->updDone = 0;
     s->status = 0;
-    s->newLimit = 0;
+    s->nzCount = 0;
     s->pad2 = 0;
     for (int x = 0; x < 8; ++x) s->stats[x] = 0;
   }
@@ -1766,7 +1763,7 @@ hipError_t launch_nodes(const KArgs& a, const NodesDesc& N, int n, hipStream_t s
 hipError_t launch_roots(const KArgs& a, const RootDesc& R, hipStream_t stream) {
   if (R.nTasks > 0)
     hipLaunchKernelGGL(root_stream_kernel, dim3(R.nTasks), dim3(BLOCK), 0, stream, a, R);
-  hipLaunchKernelGGL(root_finish_kernel, dim3(a.nJobs), dim3(FINISH_BLOCK), 0, stream, a);
+  hipLaunchKernelGGL(root_finish_kernel, dim3(a.nJobs), dim3(BLOCK), 0, stream, a);
   return hipGetLastError();
 }
 

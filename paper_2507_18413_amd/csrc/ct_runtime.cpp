@@ -7,6 +7,7 @@
 #include <hip/hip_runtime_api.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cstdarg>
 #include <cstdio>
@@ -74,6 +75,7 @@ struct SlotHost {
   int pendPop = 0, pendPush = 0;
   int8_t failed = 0;
   std::vector<int8_t> failedAt;  // failed flag recorded by each push
+  uint64_t batchMark = 0;        // last batch that named this slot
 };
 
 struct DevBlock {
@@ -84,16 +86,15 @@ struct DevBlock {
 struct QueueCtx {
   int32_t* queue = nullptr;   // 4 ints on the device
   int32_t* hostErr = nullptr; // pinned
-  // batch staging
-  DevJob* dJobs = nullptr;
-  int32_t* dOff = nullptr;    // updOff | filtOff | prepList
-  size_t capJobs = 0;
+  // batch staging: job descriptors, then (256-byte aligned) updOff | filtOff
+  // | prepList | root tasks, sent in one copy; two pinned buffers in turn let
+  // the host fill one while the other's copy is still queued
+  char* dStage = nullptr;
+  char* pStage[2] = {nullptr, nullptr};
+  hipEvent_t staged[2] = {nullptr, nullptr};
+  size_t capStage = 0;
+  int turn = 0;
   std::vector<DevJob> hJobs;
-  std::vector<int32_t> hOff;
-  DevJob* pJobs = nullptr;    // pinned staging
-  int32_t* pOff = nullptr;
-  size_t capPinned = 0;
-  hipEvent_t staged = nullptr;
   // search-node schedule scratch (node records | granule flags)
   void* dNodes = nullptr;
   size_t capNodes = 0;
@@ -104,19 +105,19 @@ int queue_init(QueueCtx& q) {
   HIPCHK(hipMemset(q.queue, 0, 4 * sizeof(int32_t)));
   HIPCHK(hipHostMalloc((void**)&q.hostErr, sizeof(int32_t), hipHostMallocMapped | hipHostMallocCoherent));
   *q.hostErr = 0;
-  HIPCHK(hipEventCreateWithFlags(&q.staged, hipEventDisableTiming));
+  for (int k = 0; k < 2; ++k) HIPCHK(hipEventCreateWithFlags(&q.staged[k], hipEventDisableTiming));
   return CT_OK;
 }
 
 void queue_free(QueueCtx& q) {
   if (q.queue) (void)hipFree(q.queue);
   if (q.hostErr) (void)hipHostFree(q.hostErr);
-  if (q.dJobs) (void)hipFree(q.dJobs);
-  if (q.dOff) (void)hipFree(q.dOff);
-  if (q.pJobs) (void)hipHostFree(q.pJobs);
-  if (q.pOff) (void)hipHostFree(q.pOff);
+  if (q.dStage) (void)hipFree(q.dStage);
+  for (int k = 0; k < 2; ++k) {
+    if (q.pStage[k]) (void)hipHostFree(q.pStage[k]);
+    if (q.staged[k]) (void)hipEventDestroy(q.staged[k]);
+  }
   if (q.dNodes) (void)hipFree(q.dNodes);
-  if (q.staged) (void)hipEventDestroy(q.staged);
   q = QueueCtx();
 }
 
@@ -155,6 +156,7 @@ struct ct_table {
   uint64_t* pCt = nullptr;      // W words (lazily)
   int32_t* pStatus = nullptr;
   bool tailPending = false;  // a synchronous call returned before its kernel ended
+  uint64_t batchMark = 0;    // last batch that named this table
   // optional kernel timing of synchronous launches, on the device clock
   // (no host events: they would add dispatch packets to every call)
   unsigned long long* dClock = nullptr;  // 5 words, see KArgs::clock
@@ -1025,16 +1027,19 @@ int ct_propagate_batch(const ct_job* jobs, int32_t n_jobs, void* stream_v, int32
     return fail(CT_E_INVALID, "bad batch arguments");
   if (n_jobs == 0) return CT_OK;
   hipStream_t stream = (hipStream_t)stream_v;
-  // validate (no state is touched before every job passes)
-  std::set<std::pair<const ct_table*, int>> seen;
+  // validate (no state is touched before every job passes; the marks that
+  // find a slot named twice carry no state)
+  static std::atomic<uint64_t> batchCounter{0};
+  const uint64_t mark = ++batchCounter;
   for (int j = 0; j < n_jobs; ++j) {
     const ct_job& cj = jobs[j];
     ct_table* T = cj.table;
     int rc = check_poison(T);
     if (rc) return rc;
     if ((rc = check_slot(T, cj.slot))) return rc;
-    if (!seen.insert({T, cj.slot}).second)
+    if (T->slots[cj.slot].batchMark == mark)
       return fail(CT_E_INVALID, "job %d: slot %d appears twice in the batch", j, cj.slot);
+    T->slots[cj.slot].batchMark = mark;
     if (cj.flags & ~(CT_JOB_PROPAGATE | CT_JOB_FROM_ROOT | CT_JOB_ROOT))
       return fail(CT_E_INVALID, "job %d: unknown flags", j);
     if ((cj.flags & CT_JOB_ROOT) && (cj.flags & CT_JOB_FROM_ROOT))
@@ -1055,18 +1060,16 @@ int ct_propagate_batch(const ct_job* jobs, int32_t n_jobs, void* stream_v, int32
       return fail(CT_E_INVALID, "job %d: dom_in / dom_out is NULL", j);
   }
   // the synchronous calls of these tables may still be finishing their tail
-  {
-    std::set<ct_table*> tabs;
-    for (int j = 0; j < n_jobs; ++j) tabs.insert(jobs[j].table);
-    for (ct_table* T : tabs) {
-      int rc = quiesce(T);
-      if (rc) return rc;
+  for (int j = 0; j < n_jobs; ++j) {
+    ct_table* T = jobs[j].table;
+    if (T->batchMark == mark) continue;
+    T->batchMark = mark;
+    int rc = quiesce(T);
+    if (rc) return rc;
+    if (T->tailPending) {
+      HIPCHK(hipStreamSynchronize(T->stream));
+      T->tailPending = false;
     }
-    for (ct_table* T : tabs)
-      if (T->tailPending) {
-        HIPCHK(hipStreamSynchronize(T->stream));
-        T->tailPending = false;
-      }
   }
   QueueCtx* q = nullptr;
   {
@@ -1172,34 +1175,40 @@ int ct_propagate_batch(const ct_job* jobs, int32_t n_jobs, void* stream_v, int32
   // stage to the device (the root tasks start at an even offset: int pairs)
   const size_t rootBase = (2 * (size_t)(n_jobs + 1) + prep.size() + 2) & ~(size_t)1;
   const size_t nOff = roots ? rootBase + rootTasks.size() : 2 * (size_t)(n_jobs + 1) + prep.size() + 1;
-  if (q->capJobs < (size_t)n_jobs || q->capPinned < nOff) {
+  const size_t offAt = align256(sizeof(DevJob) * (size_t)n_jobs);
+  const size_t stageBytes = offAt + sizeof(int32_t) * nOff;
+  if (q->capStage < stageBytes) {
     HIPCHK(hipStreamSynchronize(stream));
-    if (q->dJobs) (void)hipFree(q->dJobs);
-    if (q->dOff) (void)hipFree(q->dOff);
-    if (q->pJobs) (void)hipHostFree(q->pJobs);
-    if (q->pOff) (void)hipHostFree(q->pOff);
-    q->capJobs = std::max<size_t>(n_jobs, 2 * q->capJobs);
-    q->capPinned = std::max<size_t>(nOff, 2 * (q->capJobs + 1) + q->capJobs + 1);
-    HIPCHK(hipMalloc(&q->dJobs, sizeof(DevJob) * q->capJobs));
-    HIPCHK(hipMalloc(&q->dOff, sizeof(int32_t) * q->capPinned));
-    HIPCHK(hipHostMalloc((void**)&q->pJobs, sizeof(DevJob) * q->capJobs, hipHostMallocDefault));
-    HIPCHK(hipHostMalloc((void**)&q->pOff, sizeof(int32_t) * q->capPinned, hipHostMallocDefault));
-  } else {
-    HIPCHK(hipEventSynchronize(q->staged));  // previous staging copy has left the pinned buffers
+    if (q->dStage) (void)hipFree(q->dStage);
+    for (int k = 0; k < 2; ++k)
+      if (q->pStage[k]) (void)hipHostFree(q->pStage[k]);
+    const size_t cap = std::max(stageBytes, 2 * q->capStage);
+    q->dStage = nullptr;
+    q->pStage[0] = q->pStage[1] = nullptr;
+    q->capStage = 0;
+    HIPCHK(hipMalloc(&q->dStage, cap));
+    for (int k = 0; k < 2; ++k) HIPCHK(hipHostMalloc((void**)&q->pStage[k], cap, hipHostMallocDefault));
+    q->capStage = cap;
   }
-  memcpy(q->pJobs, q->hJobs.data(), sizeof(DevJob) * n_jobs);
-  memcpy(q->pOff, updOff.data(), sizeof(int32_t) * (n_jobs + 1));
-  memcpy(q->pOff + (n_jobs + 1), filtOff.data(), sizeof(int32_t) * (n_jobs + 1));
-  if (!prep.empty()) memcpy(q->pOff + 2 * (n_jobs + 1), prep.data(), sizeof(int32_t) * prep.size());
-  if (!rootTasks.empty()) memcpy(q->pOff + rootBase, rootTasks.data(), sizeof(int32_t) * rootTasks.size());
-  HIPCHK(hipMemcpyAsync(q->dJobs, q->pJobs, sizeof(DevJob) * n_jobs, hipMemcpyHostToDevice, stream));
-  HIPCHK(hipMemcpyAsync(q->dOff, q->pOff, sizeof(int32_t) * nOff, hipMemcpyHostToDevice, stream));
-  HIPCHK(hipEventRecord(q->staged, stream));
+  q->turn ^= 1;
+  // the copy that last read this pinned buffer (two batches ago) has ended
+  HIPCHK(hipEventSynchronize(q->staged[q->turn]));
+  char* ps = q->pStage[q->turn];
+  int32_t* pOff = (int32_t*)(ps + offAt);
+  memcpy(ps, q->hJobs.data(), sizeof(DevJob) * n_jobs);
+  memcpy(pOff, updOff.data(), sizeof(int32_t) * (n_jobs + 1));
+  memcpy(pOff + (n_jobs + 1), filtOff.data(), sizeof(int32_t) * (n_jobs + 1));
+  if (!prep.empty()) memcpy(pOff + 2 * (n_jobs + 1), prep.data(), sizeof(int32_t) * prep.size());
+  if (!rootTasks.empty()) memcpy(pOff + rootBase, rootTasks.data(), sizeof(int32_t) * rootTasks.size());
+  HIPCHK(hipMemcpyAsync(q->dStage, ps, stageBytes, hipMemcpyHostToDevice, stream));
+  HIPCHK(hipEventRecord(q->staged[q->turn], stream));
+  DevJob* dJobs = (DevJob*)q->dStage;
+  int32_t* dOff = (int32_t*)(q->dStage + offAt);
   KArgs a{};
-  a.jobs = q->dJobs;
-  a.updOff = q->dOff;
-  a.filtOff = q->dOff + (n_jobs + 1);
-  a.prepList = q->dOff + 2 * (n_jobs + 1);
+  a.jobs = dJobs;
+  a.updOff = dOff;
+  a.filtOff = dOff + (n_jobs + 1);
+  a.prepList = dOff + 2 * (n_jobs + 1);
   a.nJobs = n_jobs;
   a.nPrep = (int32_t)prep.size();
   a.nUpd = updOff[n_jobs];
@@ -1213,7 +1222,7 @@ int ct_propagate_batch(const ct_job* jobs, int32_t n_jobs, void* stream_v, int32
     N.listCap = nodes_list_cap(T->rows, T->n);
     N.groupSize = nodes_group_size(T);
     N.groups = (n_jobs + N.groupSize - 1) / N.groupSize;
-    N.jobs = q->dJobs;
+    N.jobs = dJobs;
     char* base = (char*)q->dNodes;
     N.nodeWords = nodes_node_words(T->rows, T->n);
     N.nodes = (uint64_t*)base;
@@ -1230,7 +1239,7 @@ int ct_propagate_batch(const ct_job* jobs, int32_t n_jobs, void* stream_v, int32
   }
   if (roots) {
     RootDesc R{};
-    R.tasks = q->dOff + rootBase;
+    R.tasks = dOff + rootBase;
     R.nTasks = (int32_t)(rootTasks.size() / 2);
     HIPCHK(launch_roots(a, R, stream));
     return CT_OK;
