@@ -218,16 +218,17 @@ typedef struct {
     uint32_t flags;      /* CT_JOB_* */
     int32_t n_pop;       /* levels popped first (<= the slot's depth) */
     int32_t n_push;      /* levels pushed after the pops */
-    const uint64_t *dom_in; /* device, D words of the table (PROPAGATE) */
-    uint64_t *dom_out;      /* device, D words (PROPAGATE; may alias dom_in) */
-    uint64_t *ct_out;       /* device, W words, nullable */
+    const uint64_t *dom_in; /* device-accessible (device memory or mapped pinned
+                               host memory), D words of the table (PROPAGATE) */
+    uint64_t *dom_out;      /* device-accessible, D words (PROPAGATE; may alias dom_in) */
+    uint64_t *ct_out;       /* device-accessible, W words, nullable */
 } ct_job;
 
 /*
  * ct_propagate_batch -- runs every job in one persistent launch on `stream`
  * (a hipStream_t; NULL = the null stream) driven by a device work queue.
  * Each job's result equals that of the same pops, pushes and ct_propagate on
- * its slot alone.  status_dev (device, n_jobs int32) receives each job's
+ * its slot alone.  status_dev (device-accessible, n_jobs int32) receives each job's
  * status (CT_OK, CT_FAIL, CT_E_NOT_SUBSET, CT_E_INVALID, CT_E_STATE,
  * CT_E_NOMEM).  Returns immediately after queueing; CT_E_INVALID for a
  * malformed batch (two jobs on one slot, pop below depth 0, FROM_ROOT with

@@ -36,6 +36,7 @@ void set_error(const char* msg);
 namespace {
 
 constexpr int DW = 64;  // domain words per request in the staging buffers
+constexpr unsigned kPinned = hipHostMallocMapped | hipHostMallocCoherent;
 
 double now_s() {
   return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
@@ -71,6 +72,8 @@ struct Flight {
   bool busy = false;
   hipStream_t stream = nullptr;
   hipEvent_t ev = nullptr;
+  // pinned host buffers, read and written by the batch's kernels in place
+  // (d* = their device addresses): no copies around a batch
   uint64_t *pIn = nullptr, *pOut = nullptr, *dIn = nullptr, *dOut = nullptr;
   int32_t *pStatus = nullptr, *dStatus = nullptr;
   std::vector<int> searches;
@@ -229,14 +232,8 @@ int launch(ct_server* s, Flight& f) {
   const int n = (int)jobs.size();
   if (n == 0) return 0;
   f.tLaunch = now_s();
-  hipError_t e = hipMemcpyAsync(f.dIn, f.pIn, sizeof(uint64_t) * DW * n, hipMemcpyHostToDevice, f.stream);
-  int rc = e == hipSuccess ? ct_propagate_batch(jobs.data(), n, f.stream, f.dStatus) : CT_E_DEVICE;
-  if (rc == CT_OK) {
-    e = hipMemcpyAsync(f.pOut, f.dOut, sizeof(uint64_t) * DW * n, hipMemcpyDeviceToHost, f.stream);
-    if (e == hipSuccess) e = hipMemcpyAsync(f.pStatus, f.dStatus, sizeof(int32_t) * n, hipMemcpyDeviceToHost, f.stream);
-    if (e == hipSuccess) e = hipEventRecord(f.ev, f.stream);
-    if (e != hipSuccess) rc = CT_E_DEVICE;
-  }
+  int rc = ct_propagate_batch(jobs.data(), n, f.stream, f.dStatus);
+  if (rc == CT_OK && hipEventRecord(f.ev, f.stream) != hipSuccess) rc = CT_E_DEVICE;
   if (rc != CT_OK) {
     s->broken = true;
     for (size_t k = 0; k < f.reqs.size(); ++k) {
@@ -280,9 +277,15 @@ void server_loop(ct_server* s) {
     for (Flight& f : s->flights) inFlight |= f.busy;
     if (s->stop && !inFlight) break;
     if (!progress) {
+      if (inFlight) {
+        // a batch is running: poll its event again at once (a timed wait
+        // would sleep for the kernel's timer slack, tens of microseconds,
+        // after the batch ends)
+        std::this_thread::yield();
+        continue;
+      }
       std::unique_lock<std::mutex> lk(s->mu);
-      if (s->incoming.empty() && !s->stop)
-        s->cvIn.wait_for(lk, std::chrono::microseconds(inFlight ? 5 : 200));
+      if (s->incoming.empty() && !s->stop) s->cvIn.wait_for(lk, std::chrono::microseconds(200));
     }
   }
 }
@@ -306,12 +309,12 @@ int ct_server_create(const ct_server_cfg* cfg, ct_server** out) {
   for (Flight& f : s->flights) {
     bool ok = hipStreamCreateWithFlags(&f.stream, hipStreamNonBlocking) == hipSuccess &&
               hipEventCreateWithFlags(&f.ev, hipEventDisableTiming) == hipSuccess &&
-              hipHostMalloc((void**)&f.pIn, sizeof(uint64_t) * words, hipHostMallocDefault) == hipSuccess &&
-              hipHostMalloc((void**)&f.pOut, sizeof(uint64_t) * words, hipHostMallocDefault) == hipSuccess &&
-              hipHostMalloc((void**)&f.pStatus, sizeof(int32_t) * s->cfg.max_batch, hipHostMallocDefault) == hipSuccess &&
-              hipMalloc((void**)&f.dIn, sizeof(uint64_t) * words) == hipSuccess &&
-              hipMalloc((void**)&f.dOut, sizeof(uint64_t) * words) == hipSuccess &&
-              hipMalloc((void**)&f.dStatus, sizeof(int32_t) * s->cfg.max_batch) == hipSuccess;
+              hipHostMalloc((void**)&f.pIn, sizeof(uint64_t) * words, kPinned) == hipSuccess &&
+              hipHostMalloc((void**)&f.pOut, sizeof(uint64_t) * words, kPinned) == hipSuccess &&
+              hipHostMalloc((void**)&f.pStatus, sizeof(int32_t) * s->cfg.max_batch, kPinned) == hipSuccess &&
+              hipHostGetDevicePointer((void**)&f.dIn, f.pIn, 0) == hipSuccess &&
+              hipHostGetDevicePointer((void**)&f.dOut, f.pOut, 0) == hipSuccess &&
+              hipHostGetDevicePointer((void**)&f.dStatus, f.pStatus, 0) == hipSuccess;
     if (!ok) {
       ct_server_destroy(s);
       ctk::set_error("server resource allocation failed");
@@ -333,9 +336,6 @@ void ct_server_destroy(ct_server* s) {
     if (f.pIn) (void)hipHostFree(f.pIn);
     if (f.pOut) (void)hipHostFree(f.pOut);
     if (f.pStatus) (void)hipHostFree(f.pStatus);
-    if (f.dIn) (void)hipFree(f.dIn);
-    if (f.dOut) (void)hipFree(f.dOut);
-    if (f.dStatus) (void)hipFree(f.dStatus);
     if (f.ev) (void)hipEventDestroy(f.ev);
     if (f.stream) (void)hipStreamDestroy(f.stream);
   }
