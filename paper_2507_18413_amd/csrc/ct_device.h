@@ -148,7 +148,8 @@ struct NodeInfo {
 // entries); records of consecutive nodes are contiguous (nodeWords words).
 struct NodesDesc {
   int32_t nJobs, listCap, nodeWords, groups, groupSize;
-  int32_t rows, nGran, pad;  // the table's (copied: no dependent loads)
+  int32_t rows, nGran;       // the table's (copied: no dependent loads)
+  int32_t tw;                // granules per tile of the update kernel (1 or 2)
   int64_t stride, W;
   const CT_G uint64_t* S;
   const CT_G uint64_t* ct0;

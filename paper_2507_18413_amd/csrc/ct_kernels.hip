@@ -876,9 +876,7 @@ __device__ void do_solo(const KArgs& a, const DevJob& J, Shared& sh) {
 //   nodes_update: one workgroup per (granule, node group): Alg. 2 from LDS
 //   nodes_finish: one workgroup per node: partition, FAIL, Alg. 3, status
 // ---------------------------------------------------------------------------
-constexpr int NODES_MAX_ROWS = 256;  // LDS tile of the update kernel: rows x 512 B
-constexpr int NODES_BLOCK = 512;     // update kernel: 8 waves
-constexpr int NODES_WAVES = NODES_BLOCK / WAVE;
+constexpr int NODES_MAX_ROWS = 256;  // LDS tile of the update kernel: rows x 512 B at least
 constexpr int XCDS = 8;
 
 // Orders this wave's LDS accesses: a wave's LDS operations complete in issue
@@ -1008,90 +1006,127 @@ __global__ void __launch_bounds__(BLOCK) nodes_prep_kernel(KArgs a, NodesDesc N)
   }
 }
 
-// A tile is one granule of the table for one group of nodes.  LDS holds the
-// granule of every support row (rows x 64 words) and a zero row, then the
-// group's node records (NodeInfo and row list); a node then costs only LDS
-// reads and its currTable store.  A list is read 4 rows at a time (segments are
-// padded with the zero row): one broadcast LDS read gives the 4 row numbers,
-// 4 independent row reads are OR-ed in, and the next 4 numbers are read while
-// they are in flight.
+// A tile is TW consecutive granules (a span of 64·TW words) of the table for
+// one group of nodes.  LDS holds that span of every support row (rows x 64·TW
+// words) and a zero row, then the group's node records (NodeInfo and row
+// list); a node then costs only LDS reads and its currTable store.  A list is
+// read 8 rows per step: the row numbers come from registers by readlane (one
+// group of 4 per lane), the rows are independent LDS reads OR-ed in.  With
+// TW = 2 a lane holds two consecutive words and every row read is one 16-byte
+// load per lane (1 KB per wave): LDS serves 16-byte loads at about twice the
+// rate of 8-byte ones.  TW = 2 is used when the doubled tile fits a CU's LDS
+// (one 16-wave workgroup per CU), else TW = 1 (8-wave workgroups, two per CU).
 //
 // Persistent workgroups (as many as fit at once) walk the tiles: while one
 // tile is evaluated from LDS, the next one's words are already on their way
 // into registers, so the memory latency of staging is hidden.  Block b runs on
-// XCD b % 8 (round-robin dispatch) and takes tiles of the granules g with
-// g % 8 == b % 8, in granule order, so the blocks of an XCD work on the same
-// granule at about the same time and its L2 serves the granule to all of
-// them after one fetch from HBM.
+// XCD b % 8 (round-robin dispatch) and takes the spans s with s % 8 == b % 8,
+// in order, so the blocks of an XCD work on the same span at about the same
+// time and its L2 serves it to all of them after one fetch from HBM.
 constexpr int NODES_TPF = 16;  // tile words per thread prefetched (rows <= 128)
-constexpr int NODES_NPF = 8;   // node-record words per thread prefetched
+constexpr int NODES_NPF = 5;   // node-record words per thread prefetched
 
-struct NodesTile {
-  int g, node0, nG, nodeTotal;
-  uint64_t root;
+template <int TW>
+struct NodesCfg {
+  static constexpr int SPAN = GW * TW;           // words per row of a tile
+  static constexpr int BLOCKT = TW == 2 ? 1024 : 512;
+  static constexpr int WAVEST = BLOCKT / WAVE;
+  static constexpr int RSTEP = BLOCKT / SPAN;    // rows staged per pass (8)
 };
 
+typedef uint64_t u64x2 __attribute__((ext_vector_type(2)));
+
+struct NodesTile {
+  int g, node0, nG, nodeTotal;  // g: first granule of the span
+  u64x2 root;                   // the root's words of this lane (TW = 1: .x)
+};
+
+template <int TW>
 __device__ __forceinline__ NodesTile nodes_tile(const NodesDesc& N, int xcd, int t) {
   NodesTile x;
-  x.g = (t / N.groups) * XCDS + xcd;
+  x.g = ((t / N.groups) * XCDS + xcd) * TW;
   x.node0 = (t % N.groups) * N.groupSize;
   x.nG = min(N.groupSize, N.nJobs - x.node0);
   x.nodeTotal = x.nG * N.nodeWords;
-  x.root = N.ct0[(int64_t)x.g * GW + lane_id()];
+  const int64_t w = (int64_t)x.g * GW + TW * lane_id();
+  if (TW == 2) {
+    // a span past the last granule reads as zero
+    x.root = w < N.stride ? *(const CT_G u64x2*)(N.ct0 + w) : u64x2{0ull, 0ull};
+  } else {
+    x.root = u64x2{N.ct0[w], 0ull};
+  }
   return x;
 }
 
-// Staging of a tile: thread t holds tile rows t / 64 + 8u (word t % 64) and
-// the words t + 512u of the group's node records.
+// Staging of a tile: thread t holds words t % SPAN of tile rows t / SPAN + 8u
+// and the words t + BLOCKT·u of the group's node records.
+template <int TW>
 __device__ __forceinline__ void nodes_stage_issue(const NodesDesc& N, const NodesTile& x, uint64_t* vt,
                                                   uint64_t* vn) {
-  const int r0 = (int)threadIdx.x / GW, l = (int)threadIdx.x % GW;
-  const CT_G uint64_t* S = N.S + (int64_t)r0 * N.stride + (int64_t)x.g * GW + l;
+  using C = NodesCfg<TW>;
+  const int r0 = (int)threadIdx.x / C::SPAN, l = (int)threadIdx.x % C::SPAN;
+  const int64_t w = (int64_t)x.g * GW + l;
+  const bool inRow = w < N.stride;  // words past the last granule are not loaded
+  const CT_G uint64_t* S = N.S + (int64_t)r0 * N.stride + w;
 #pragma unroll
   for (int u = 0; u < NODES_TPF; ++u)
-    if (r0 + 8 * u < N.rows) vt[u] = S[(int64_t)(8 * u) * N.stride];
+    if (r0 + C::RSTEP * u < N.rows) vt[u] = inRow ? S[(int64_t)(C::RSTEP * u) * N.stride] : 0ull;
   const CT_G uint64_t* src = N.nodes + (int64_t)x.node0 * N.nodeWords + threadIdx.x;
 #pragma unroll
   for (int u = 0; u < NODES_NPF; ++u)
-    if ((int)threadIdx.x + NODES_BLOCK * u < x.nodeTotal) vn[u] = src[NODES_BLOCK * u];
+    if ((int)threadIdx.x + C::BLOCKT * u < x.nodeTotal) vn[u] = src[C::BLOCKT * u];
 }
 
 // Stores the prefetched words (and loads and stores any beyond them); the
 // caller synchronizes the workgroup afterwards.
+template <int TW>
 __device__ __forceinline__ void nodes_stage_commit(const NodesDesc& N, const NodesTile& x, const uint64_t* vt,
                                                    const uint64_t* vn, uint64_t* lds) {
-  const int r0 = (int)threadIdx.x / GW, l = (int)threadIdx.x % GW;
+  using C = NodesCfg<TW>;
+  const int r0 = (int)threadIdx.x / C::SPAN, l = (int)threadIdx.x % C::SPAN;
+  const int64_t w = (int64_t)x.g * GW + l;
+  const bool inRow = w < N.stride;
 #pragma unroll
   for (int u = 0; u < NODES_TPF; ++u)
-    if (r0 + 8 * u < N.rows) lds[(r0 + 8 * u) * GW + l] = vt[u];
-  for (int r = r0 + 8 * NODES_TPF; r < N.rows; r += 8)
-    lds[r * GW + l] = N.S[(int64_t)r * N.stride + (int64_t)x.g * GW + l];
-  uint64_t* dst = lds + (size_t)(N.rows + 1) * GW;  // the zero row sits between
+    if (r0 + C::RSTEP * u < N.rows) lds[(r0 + C::RSTEP * u) * C::SPAN + l] = vt[u];
+  for (int r = r0 + C::RSTEP * NODES_TPF; r < N.rows; r += C::RSTEP)
+    lds[r * C::SPAN + l] = inRow ? N.S[(int64_t)r * N.stride + w] : 0ull;
+  uint64_t* dst = lds + (size_t)(N.rows + 1) * C::SPAN;  // the zero row sits between
 #pragma unroll
   for (int u = 0; u < NODES_NPF; ++u) {
-    const int i = (int)threadIdx.x + NODES_BLOCK * u;
+    const int i = (int)threadIdx.x + C::BLOCKT * u;
     if (i < x.nodeTotal) dst[i] = vn[u];
   }
   const CT_G uint64_t* src = N.nodes + (int64_t)x.node0 * N.nodeWords;
-  for (int i = (int)threadIdx.x + NODES_BLOCK * NODES_NPF; i < x.nodeTotal; i += NODES_BLOCK) dst[i] = src[i];
+  for (int i = (int)threadIdx.x + C::BLOCKT * NODES_NPF; i < x.nodeTotal; i += C::BLOCKT) dst[i] = src[i];
 }
 
+// Row r of the tile for this lane: its word (TW = 1) or its two words (TW = 2).
+template <int TW>
+__device__ __forceinline__ u64x2 nodes_row(const char* tileBytes, uint32_t r, uint32_t laneOff) {
+  if (TW == 2) return *(const u64x2*)(tileBytes + (r << 10) + laneOff);
+  return u64x2{*(const uint64_t*)(tileBytes + (r << 9) + laneOff), 0ull};
+}
+
+template <int TW>
 __device__ __forceinline__ void nodes_eval_tile(const NodesDesc& N, const NodesTile& x, const uint64_t* lds) {
+  using C = NodesCfg<TW>;
   const int lane = lane_id();
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
-  const uint64_t* recs = lds + (size_t)(N.rows + 1) * GW;
-  const uint32_t laneOff = (uint32_t)lane * 8u;
+  const uint64_t* recs = lds + (size_t)(N.rows + 1) * C::SPAN;
+  const uint32_t laneOff = (uint32_t)lane * 8u * TW;
   const char* tileBytes = (const char*)lds;
-  const int64_t w = (int64_t)x.g * GW + lane;
-  for (int p = wv; p < x.nG; p += NODES_WAVES) {
+  const int64_t w = (int64_t)x.g * GW + TW * lane;
+  for (int p = wv; p < x.nG; p += C::WAVEST) {
     const NodeInfo* info = (const NodeInfo*)(recs + p * N.nodeWords);
     // the record is the same for every lane: scalar registers, uniform loops
     const int status = __builtin_amdgcn_readfirstlane(info->status);
     if (status != ST_OK && status != ST_FAIL) continue;  // rejected input: nothing changes
     const int ng = __builtin_amdgcn_readfirstlane(info->groups);
     const uint64_t* rl = (const uint64_t*)(info + 1);  // 4 entries per word
-    uint64_t m = status == ST_OK ? ~0ull : 0ull;
-    uint64_t acc = 0ull;
+    const uint64_t m0 = status == ST_OK ? ~0ull : 0ull;
+    u64x2 m = {m0, m0};
+    u64x2 acc = {0ull, 0ull};
     bool inc = false, open = false;
     // the list, 64 groups of 4 row numbers at a time, one group per lane;
     // two groups (8 rows) per step, taken from the lanes by readlane, so the
@@ -1107,77 +1142,107 @@ __device__ __forceinline__ void nodes_eval_tile(const NodesDesc& N, const NodesT
         const uint32_t a1 = __builtin_amdgcn_readlane(mhi, q);
         const uint32_t b0 = __builtin_amdgcn_readlane(mlo, q + 1);  // q + 1 <= 63
         const uint32_t b1 = __builtin_amdgcn_readlane(mhi, q + 1);
-        uint64_t x[8];
-        x[0] = *(const uint64_t*)(tileBytes + ((a0 & 0x3FFFu) << 9) + laneOff);
-        x[1] = *(const uint64_t*)(tileBytes + ((a0 >> 16) << 9) + laneOff);
-        x[2] = *(const uint64_t*)(tileBytes + ((a1 & 0xFFFFu) << 9) + laneOff);
-        x[3] = *(const uint64_t*)(tileBytes + ((a1 >> 16) << 9) + laneOff);
-        x[4] = *(const uint64_t*)(tileBytes + ((b0 & 0x3FFFu) << 9) + laneOff);
-        x[5] = *(const uint64_t*)(tileBytes + ((b0 >> 16) << 9) + laneOff);
-        x[6] = *(const uint64_t*)(tileBytes + ((b1 & 0xFFFFu) << 9) + laneOff);
-        x[7] = *(const uint64_t*)(tileBytes + ((b1 >> 16) << 9) + laneOff);
+        // 8 rows in flight (TW = 1), or 4 when each is 16 bytes per lane
+        u64x2 v[4], u[4];
+        v[0] = nodes_row<TW>(tileBytes, a0 & 0x3FFFu, laneOff);
+        v[1] = nodes_row<TW>(tileBytes, a0 >> 16, laneOff);
+        v[2] = nodes_row<TW>(tileBytes, a1 & 0xFFFFu, laneOff);
+        v[3] = nodes_row<TW>(tileBytes, a1 >> 16, laneOff);
+        if (TW == 1) {
+          u[0] = nodes_row<TW>(tileBytes, b0 & 0x3FFFu, laneOff);
+          u[1] = nodes_row<TW>(tileBytes, b0 >> 16, laneOff);
+          u[2] = nodes_row<TW>(tileBytes, b1 & 0xFFFFu, laneOff);
+          u[3] = nodes_row<TW>(tileBytes, b1 >> 16, laneOff);
+        }
         if (a0 & 0x8000u) {  // a segment starts with the first group
           if (open) m &= inc ? ~acc : acc;
-          acc = 0ull;
+          acc = u64x2{0ull, 0ull};
           inc = (a0 & 0x4000u) != 0;
           open = true;
         }
-        acc |= (x[0] | x[1]) | (x[2] | x[3]);
+        acc |= (v[0] | v[1]) | (v[2] | v[3]);
+        if (TW == 2) {
+          u[0] = nodes_row<TW>(tileBytes, b0 & 0x3FFFu, laneOff);
+          u[1] = nodes_row<TW>(tileBytes, b0 >> 16, laneOff);
+          u[2] = nodes_row<TW>(tileBytes, b1 & 0xFFFFu, laneOff);
+          u[3] = nodes_row<TW>(tileBytes, b1 >> 16, laneOff);
+        }
         if (b0 & 0x8000u) {  // ... or with the second
           m &= inc ? ~acc : acc;
-          acc = 0ull;
+          acc = u64x2{0ull, 0ull};
           inc = (b0 & 0x4000u) != 0;
         }
-        acc |= (x[4] | x[5]) | (x[6] | x[7]);
+        acc |= (u[0] | u[1]) | (u[2] | u[3]);
       }
     }
     if (open) m &= inc ? ~acc : acc;
-    const uint64_t nw = x.root & m;
+    const u64x2 nw = x.root & m;
     CT_G uint64_t* ct = info->ct;
     CT_G uint64_t* ctOut = info->ct_out;
-    ct[w] = nw;
-    if (ctOut && w < N.W) ctOut[w] = nw;
-    const bool nz = __ballot(nw != 0ull) != 0ull;
-    if (lane == 0) N.nz[(int64_t)(x.node0 + p) * N.nGran + x.g] = nz ? 1 : 0;
+    const unsigned long long nzl = __ballot((nw.x | nw.y) != 0ull);
+    if (TW == 2) {
+      // lanes 0-31 hold granule g, lanes 32-63 granule g + 1 (when it exists)
+      if (w < N.stride) *(CT_G u64x2*)(ct + w) = nw;
+      if (ctOut) {
+        if (w + 1 < N.W) {
+          ctOut[w] = nw.x;
+          ctOut[w + 1] = nw.y;
+        } else if (w < N.W) {
+          ctOut[w] = nw.x;
+        }
+      }
+      if (lane == 0) {
+        CT_G uint8_t* nz = N.nz + (int64_t)(x.node0 + p) * N.nGran + x.g;
+        nz[0] = (nzl & 0xFFFFFFFFull) ? 1 : 0;
+        if (x.g + 1 < N.nGran) nz[1] = (nzl >> 32) ? 1 : 0;
+      }
+    } else {
+      ct[w] = nw.x;
+      if (ctOut && w < N.W) ctOut[w] = nw.x;
+      if (lane == 0) N.nz[(int64_t)(x.node0 + p) * N.nGran + x.g] = nzl ? 1 : 0;
+    }
   }
 }
 
-__global__ void __launch_bounds__(NODES_BLOCK) nodes_update_kernel(KArgs a, NodesDesc N) {
+template <int TW>
+__global__ void __launch_bounds__(NodesCfg<TW>::BLOCKT, 4) nodes_update_kernel(KArgs a, NodesDesc N) {
   extern __shared__ uint64_t lds[];
+  using C = NodesCfg<TW>;
   const int xcd = blockIdx.x % XCDS;
   const int perX = gridDim.x / XCDS;  // the grid is a multiple of 8
-  const int tilesX = (N.nGran - xcd + XCDS - 1) / XCDS * N.groups;
+  const int spans = (N.nGran + TW - 1) / TW;
+  const int tilesX = (spans - xcd + XCDS - 1) / XCDS * N.groups;
   int t = blockIdx.x / XCDS;
   if (t >= tilesX) return;
-  if (threadIdx.x < GW) lds[N.rows * GW + threadIdx.x] = 0ull;  // the zero row
+  if (threadIdx.x < C::SPAN) lds[N.rows * C::SPAN + threadIdx.x] = 0ull;  // the zero row
   uint64_t vt[NODES_TPF], vn[NODES_NPF];
-  NodesTile cur = nodes_tile(N, xcd, t);
-  nodes_stage_issue(N, cur, vt, vn);
-  nodes_stage_commit(N, cur, vt, vn, lds);
+  NodesTile cur = nodes_tile<TW>(N, xcd, t);
+  nodes_stage_issue<TW>(N, cur, vt, vn);
+  nodes_stage_commit<TW>(N, cur, vt, vn, lds);
   __syncthreads();
   for (;;) {
     const int tn = t + perX;
     const bool more = tn < tilesX;
     NodesTile nxt;
     if (more) {
-      nxt = nodes_tile(N, xcd, tn);
-      nodes_stage_issue(N, nxt, vt, vn);  // in flight during the evaluation
+      nxt = nodes_tile<TW>(N, xcd, tn);
+      nodes_stage_issue<TW>(N, nxt, vt, vn);  // in flight during the evaluation
     }
-    nodes_eval_tile(N, cur, lds);
+    nodes_eval_tile<TW>(N, cur, lds);
     __syncthreads();  // every wave is done with this tile's LDS
     if (!more) break;
-    nodes_stage_commit(N, nxt, vt, vn, lds);
+    nodes_stage_commit<TW>(N, nxt, vt, vn, lds);
     __syncthreads();
     t = tn;
     cur = nxt;
   }
 }
 
-// One workgroup of 8 waves per node: wave 0 partitions the root's granule
+// One workgroup of 4 waves per node: wave 0 partitions the root's granule
 // list by the non-zero flags (survivors first, stable) and detects FAIL
 // (Alg. 1); then the waves run filterDomains (Alg. 3) on interleaved domain
 // words.
-constexpr int FINISH_BLOCK = 512;
+constexpr int FINISH_BLOCK = 256;
 constexpr int FINISH_WAVES = FINISH_BLOCK / WAVE;
 
 __global__ void __launch_bounds__(FINISH_BLOCK) nodes_finish_kernel(KArgs a, NodesDesc N) {
@@ -1732,21 +1797,25 @@ int nodes_node_words(int rows, int n) {
   return (int)(sizeof(NodeInfo) / 8) + nodes_list_cap(rows, n) / 4;
 }
 
-// Dynamic LDS of the update kernel for groups of `groupSize` nodes.
-size_t nodes_update_lds(int rows, int n, int groupSize) {
-  return (size_t)(rows + 1) * GW * sizeof(uint64_t) +
+// Dynamic LDS of the update kernel for groups of `groupSize` nodes and tiles
+// of `tw` granules.
+size_t nodes_update_lds(int rows, int n, int groupSize, int tw) {
+  return (size_t)(rows + 1) * GW * tw * sizeof(uint64_t) +
          (size_t)groupSize * nodes_node_words(rows, n) * sizeof(uint64_t);
 }
 
+int nodes_update_block(int tw) { return tw == 2 ? NodesCfg<2>::BLOCKT : NodesCfg<1>::BLOCKT; }
+
 // Persistent workgroups of the update kernel: as many as fit at once, a
 // multiple of the XCD count.
+template <int TW>
 int nodes_update_grid(size_t ldsBytes) {
   int dev = 0, cus = 0, perCu = 0;
   if (hipGetDevice(&dev) != hipSuccess ||
       hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
     return XCDS;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&perCu, nodes_update_kernel, NODES_BLOCK, ldsBytes) !=
-          hipSuccess ||
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&perCu, nodes_update_kernel<TW>, NodesCfg<TW>::BLOCKT,
+                                                   ldsBytes) != hipSuccess ||
       perCu < 1)
     perCu = 1;
   return std::max(XCDS, cus * perCu / XCDS * XCDS);
@@ -1754,8 +1823,13 @@ int nodes_update_grid(size_t ldsBytes) {
 
 hipError_t launch_nodes(const KArgs& a, const NodesDesc& N, int n, hipStream_t stream) {
   hipLaunchKernelGGL(nodes_prep_kernel, dim3((N.nJobs + WAVES - 1) / WAVES), dim3(BLOCK), 0, stream, a, N);
-  const size_t lds = nodes_update_lds(N.rows, n, N.groupSize);
-  hipLaunchKernelGGL(nodes_update_kernel, dim3(nodes_update_grid(lds)), dim3(NODES_BLOCK), lds, stream, a, N);
+  const size_t lds = nodes_update_lds(N.rows, n, N.groupSize, N.tw);
+  if (N.tw == 2)
+    hipLaunchKernelGGL(nodes_update_kernel<2>, dim3(nodes_update_grid<2>(lds)), dim3(NodesCfg<2>::BLOCKT), lds,
+                       stream, a, N);
+  else
+    hipLaunchKernelGGL(nodes_update_kernel<1>, dim3(nodes_update_grid<1>(lds)), dim3(NodesCfg<1>::BLOCKT), lds,
+                       stream, a, N);
   hipLaunchKernelGGL(nodes_finish_kernel, dim3(N.nJobs), dim3(FINISH_BLOCK), 0, stream, a, N);
   return hipGetLastError();
 }

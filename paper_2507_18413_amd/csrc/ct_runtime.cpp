@@ -33,7 +33,7 @@ hipError_t launch_engine(const EngDesc& D, size_t lds, hipStream_t stream);
 int nodes_max_rows();
 int nodes_list_cap(int rows, int n);
 int nodes_node_words(int rows, int n);
-size_t nodes_update_lds(int rows, int n, int groupSize);
+size_t nodes_update_lds(int rows, int n, int groupSize, int tw);
 hipError_t launch_nodes(const KArgs& a, const NodesDesc& N, int n, hipStream_t stream);
 hipError_t launch_roots(const KArgs& a, const RootDesc& R, hipStream_t stream);
 hipError_t launch_build_supports(const int32_t* tuples, int64_t t, int n, const VarDesc* vars,
@@ -255,14 +255,30 @@ int device_lds() {
   return lds;
 }
 
-// Nodes per group of the update kernel: the largest multiple of 8 up to 64
-// for which two workgroups fit in a CU's LDS, else for which one does.
-int nodes_group_size(const ct_table* T) {
+// Tile of the node update kernel: nodes per group (a multiple of 8 up to 64)
+// and granules per tile.  Two-granule tiles (16-byte LDS reads) when the tile
+// and a group of at least 32 nodes fit one workgroup's LDS; else one-granule
+// tiles with the largest group for which two workgroups fit a CU, else one.
+struct NodesPlan {
+  int groupSize = 0, tw = 1;
+};
+
+NodesPlan nodes_plan(const ct_table* T) {
   const size_t lds = (size_t)device_lds();
+  NodesPlan p;
+  for (int gs = 64; gs >= 32; gs -= 8)
+    if (nodes_update_lds(T->rows, T->n, gs, 2) <= lds) {
+      p.groupSize = gs;
+      p.tw = 2;
+      return p;
+    }
   for (int per = 2; per >= 1; --per)
     for (int gs = 64; gs >= 8; gs -= 8)
-      if (per * nodes_update_lds(T->rows, T->n, gs) <= lds) return gs;
-  return 0;
+      if (per * nodes_update_lds(T->rows, T->n, gs, 1) <= lds) {
+        p.groupSize = gs;
+        return p;
+      }
+  return p;
 }
 
 // Batches of roots recomputed from scratch run on their own streaming
@@ -280,7 +296,7 @@ bool use_nodes(const ct_job* jobs, int n) {
     return false;
   if (T->rows > nodes_max_rows() || T->nGran > MAX_GRAN) return false;
   // the update kernel's LDS holds one granule of every support row
-  if (nodes_group_size(T) == 0) return false;
+  if (nodes_plan(T).groupSize == 0) return false;
   for (int j = 0; j < n; ++j)
     if (jobs[j].table != T || jobs[j].flags != (CT_JOB_PROPAGATE | CT_JOB_FROM_ROOT)) return false;
   return true;
@@ -1220,7 +1236,9 @@ int ct_propagate_batch(const ct_job* jobs, int32_t n_jobs, void* stream_v, int32
     NodesDesc N{};
     N.nJobs = n_jobs;
     N.listCap = nodes_list_cap(T->rows, T->n);
-    N.groupSize = nodes_group_size(T);
+    const NodesPlan plan = nodes_plan(T);
+    N.groupSize = plan.groupSize;
+    N.tw = plan.tw;
     N.groups = (n_jobs + N.groupSize - 1) / N.groupSize;
     N.jobs = dJobs;
     char* base = (char*)q->dNodes;

@@ -296,18 +296,25 @@ def test_batch_from_root_nodes_vs_oracle(schedule):
     assert (from_dev(dout[:64]) == got_dom[:64]).all()
 
 
-@pytest.mark.parametrize("n_nodes", [1, 100, 200])
-def test_batch_nodes_schedule_edge_cases(n_nodes):
+@pytest.mark.parametrize("n_nodes,rows", [(1, 239), (100, 239), (200, 239), (1, 94), (150, 94)])
+def test_batch_nodes_schedule_edge_cases(n_nodes, rows):
     """Granule-major node schedule on a table with multi-word domains, a
-    ragged last word and a granule count that is not a multiple of 8, with
-    nodes that fail (an empty domain, no surviving tuple), nodes equal to the
-    root, and rejected inputs (stray bits, values outside the root domains)."""
+    ragged last word (an odd word count) and a granule count that is not a
+    multiple of 8, with nodes that fail (an empty domain, no surviving tuple),
+    nodes equal to the root, and rejected inputs (stray bits, values outside
+    the root domains).  239 support rows take one-granule tiles (10
+    granules); 94 rows take two-granule tiles (9 granules: the last tile half
+    past the table's end)."""
     import torch
-    say("batch nodes schedule: edge cases,", n_nodes, "nodes")
-    rng = W.rng_for(11, 204, n_nodes)
-    ds = np.array([130, 3, 65, 1, 40], np.int32)
+    say("batch nodes schedule: edge cases,", n_nodes, "nodes,", rows, "rows")
+    rng = W.rng_for(11, 204, n_nodes + rows)
+    if rows == 239:
+        ds = np.array([130, 3, 65, 1, 40], np.int32)
+    else:
+        ds = np.array([40, 3, 20, 1, 30], np.int32)
+    assert int(ds.sum()) == rows
     lo = np.array([-7, 0, 100, 5, 0], np.int32)
-    t = 64 * 64 * 9 + 37
+    t = 64 * 64 * 9 + 37 if rows == 239 else 64 * 64 * 8 + 37   # 577 or 513 words
     hi = ds.copy()
     hi[0] -= 10                               # the last 10 values of x0 have no support
     tup = np.stack([rng.integers(lo[i], lo[i] + hi[i], size=t) for i in range(5)], 1).astype(np.int32)
