@@ -246,6 +246,52 @@ class PlainModel:
         return 0, pool, props
 
 
+def wide_leg(seed, n_calls, cpu):
+    """Plain calls on a wide-scope table (100 variables, domains 64-160,
+    10,000 tuples; filterDomains dominates): the paper's instance shape."""
+    import numpy as np
+    from paper_2507_18413_amd import ct
+    from paper_2507_18413_amd import workloads as W
+    spec = W.wide_table(seed)
+    lay = spec.layout()
+    rec = ct.Table(spec.tuples, spec.lo, spec.dsizes, schedule=ct.SCHED_SOLO)
+    script = W.run_plain_script(GpuSut(rec), lay, n_calls, seed, 6, W.pick_fraction_removal)
+    rec.close()
+    depth = sum(1 if k == "push" else -1 if k == "pop" else 0 for k, _ in script)
+    script += [("pop", None)] * depth
+    table = ct.Table(spec.tuples, spec.lo, spec.dsizes)
+    replay(table, script)
+    lat = []
+    t0 = time.perf_counter()
+    props = replay(table, script, lat)
+    el = time.perf_counter() - t0
+    lat_us = np.array(lat) * 1e6
+    out = {"workload": "arity 100, domains U{64..160}, 10,000 distinct uniform tuples "
+                       f"({table.rows} support rows of {table.W} words, {table.D} domain words); "
+                       f"{n_calls} calls as in the plain leg",
+           "props_per_s": round(props / el, 1),
+           "latency_us": {"p50": round(float(np.percentile(lat_us, 50)), 2),
+                          "p99": round(float(np.percentile(lat_us, 99)), 2)}}
+    if cpu:
+        from oracle import oracle as O
+        o = O.OracleTable(spec.tuples, spec.lo, spec.dsizes)
+
+        class OracleSut:
+            def propagate(self, d):
+                return o.propagate(d)
+
+            def push(self):
+                o.push()
+
+            def pop(self):
+                o.pop()
+
+        t0 = time.perf_counter()
+        oprops = replay(OracleSut(), script)
+        out["oracle_props_per_s"] = round(oprops / (time.perf_counter() - t0), 1)
+    return out
+
+
 def root_batch_leg(tabs, specs, reps, per_table=True):
     """Every table's root recomputed from scratch (ROOT jobs: all tuples,
     every variable on the reset branch) in one batched launch: each support
@@ -710,6 +756,8 @@ def main():
                      "bytes_per_call": round(per_launch_bytes, 1)},
     }
     note(f"plain leg done: {value:.0f} propagations/s")
+    note("wide-scope leg")
+    out["wide_scope"] = wide_leg(seed, 300, not args.no_cpu_baseline)
     if not args.no_nodes:
         note("search-node leg")
         out["batched_nodes"] = nodes_leg(seed, args.nodes, max(1, args.steps), 1)

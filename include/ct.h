@@ -69,12 +69,13 @@ typedef struct ct_table ct_table;
  * granules and filterDomains over workgroups of 4 domain words.  NODES is the
  * search-node schedule of ct_propagate_batch: when every job of a batch is a
  * CT_JOB_FROM_ROOT propagation of the same table of at most 256 support rows
- * (sum of the domain sizes), one workgroup per (granule, up to 64 jobs)
- * stages that granule of every support row in LDS and evaluates updateTable
- * for its jobs from there, so the supports are read once per group of jobs; other batches and
- * single calls fall back to AUTO.  AUTO picks SOLO for tables of at most 4
- * granules (16,384 tuples) and for batches of at least 256 jobs, and NODES
- * for eligible batches of at least 64 jobs.  A batch whose jobs are all
+ * (sum of the domain sizes), one workgroup per (one or two granules, up to
+ * 64 jobs) stages those granules of every support row in LDS and evaluates
+ * updateTable for its jobs from there, so the supports are read once per
+ * group of jobs; other batches and single calls fall back to AUTO.  AUTO picks SOLO for tables of at most 4
+ * granules (16,384 tuples) and at most 16 domain words (wider tables spread
+ * filterDomains over workgroups) and for batches of at least 256 jobs, and
+ * NODES for eligible batches of at least 64 jobs.  A batch whose jobs are all
  * CT_JOB_ROOT on AUTO tables runs as two launches: one wave per (job,
  * granule) streams every support row of its granule once, then one
  * workgroup per job partitions and filters.  Results are identical. */

@@ -232,7 +232,8 @@ int check_poison(const ct_table* T) {
   return CT_OK;
 }
 
-constexpr int SOLO_MAX_GRAN = 4;      // tables up to 16,384 tuples run solo
+constexpr int SOLO_MAX_GRAN = 4;      // tables up to 16,384 tuples run solo ...
+constexpr int SOLO_MAX_D = 16;        // ... unless filterDomains has more words than 4 waves take at once
 constexpr int SOLO_MIN_BATCH = 256;   // batches this large run every job solo
 
 constexpr int NODES_MIN_BATCH = 64;   // AUTO: batches of root resets this large run granule-major
@@ -241,7 +242,7 @@ constexpr int SCRATCH_SOLO_MAX_GRAN = 16;  // AUTO: roots recomputed solo up to 
 bool use_solo(const ct_table* T, int nJobs) {
   if (T->cfg.schedule == CT_SCHED_SOLO) return true;
   if (T->cfg.schedule == CT_SCHED_SPLIT) return false;
-  return T->nGran <= SOLO_MAX_GRAN || nJobs >= SOLO_MIN_BATCH;
+  return (T->nGran <= SOLO_MAX_GRAN && T->D <= SOLO_MAX_D) || nJobs >= SOLO_MIN_BATCH;
 }
 
 // The search-node schedule takes a batch whose jobs all reset slots of one

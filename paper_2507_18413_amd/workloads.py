@@ -234,6 +234,19 @@ def config2_table(seed: int = DEFAULT_SEED, t: int = 200_000, d: int = 50, n: in
     return TableSpec(tup, np.zeros(n, np.int32), np.full(n, d, np.int32))
 
 
+def wide_table(seed: int = DEFAULT_SEED, n: int = 100, dom=(64, 160), t: int = 10_000) -> TableSpec:
+    """A wide-scope table in the shape of the paper's linear-constraint
+    instances (Sec. 5.1, Table 2: tens to hundreds of variables, large
+    domains, a few thousand tuples): arity n, domain sizes uniform in
+    [dom[0], dom[1]], t distinct uniform tuples.  Support rows are many and
+    short (about 11,000 rows of 157 words at the defaults), so a call is
+    dominated by filterDomains."""
+    rng = rng_for(seed, 6, 0)
+    ds = rng.integers(dom[0], dom[1] + 1, size=n).astype(np.int32)
+    tup = distinct_uniform_tuples(rng, ds, t)
+    return TableSpec(tup, np.zeros(n, np.int32), ds)
+
+
 def config4_table(seed: int = DEFAULT_SEED, t: int = 1_000_000, d: int = 20, n: int = 6,
                   s: float = 1.1) -> TableSpec:
     """Arity 6, domain size 20, distinct tuples with Zipf(1.1) columns."""

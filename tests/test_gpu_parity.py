@@ -191,6 +191,49 @@ def test_config2_full(schedule):
     assert G.W == 3125
 
 
+@pytest.mark.parametrize("schedule", [ct.SCHED_AUTO, ct.SCHED_SPLIT, ct.SCHED_SOLO])
+def test_wide_scope_vs_oracle(schedule):
+    """A wide-scope table (100 variables, domains 64-160, 10,000 tuples:
+    11,072 support rows of 157 words, 227 domain words; filterDomains
+    dominates): 200 calls with backtracking, every call checked."""
+    say("wide scope: arity 100, d in [64,160], 10,000 tuples, 200 calls, schedule", schedule)
+    spec = W.wide_table()
+    G, Ot = run_plain(spec, 200, W.pick_fraction_removal, 6, schedule=schedule)
+    assert G.D == 227 and G.rows == 11072 and G.W == 157
+
+
+def test_wide_scope_nodes_batch_vs_oracle():
+    """Search nodes on the wide-scope table (too many rows for the node
+    schedule: the work queue runs them), each node against the oracle."""
+    import torch
+    say("wide scope: 96 search nodes in one batch")
+    spec = W.wide_table()
+    lay = spec.layout()
+    G, Ot = pair(spec.tuples, spec.lo, spec.dsizes)
+    root = Ot.domains()
+    n = 96
+    nodes = W.config4_nodes(lay, root, n, max_frac=0.3)
+    first = G.slots_alloc(n, max_depth=0)
+    din = to_dev(nodes)
+    dout = torch.zeros_like(din)
+    cts = torch.zeros((n, G.W), dtype=torch.int64, device="cuda")
+    status = torch.full((n,), 99, dtype=torch.int32, device="cuda")
+    jobs = [dict(table=G, slot=first + k, flags=ct.JOB_PROPAGATE | ct.JOB_FROM_ROOT,
+                 dom_in=din[k], dom_out=dout[k], ct_out=cts[k]) for k in range(n)]
+    ct.propagate_batch(jobs, status)
+    torch.cuda.synchronize()
+    st = status.cpu().numpy()
+    got_dom, got_ct = from_dev(dout), from_dev(cts)
+    for k in range(n):
+        Ot.push()
+        os_, od, oc = Ot.propagate(nodes[k], want_ct=True)
+        Ot.pop()
+        assert st[k] == os_, k
+        if os_ == O.OK:
+            assert (got_dom[k] == od).all(), k
+            assert (got_ct[k] == oc).all(), k
+
+
 def test_errors_match_oracle():
     g = json.load(open(GOLDEN))
     tup = np.array(g["tuples"], np.int32)

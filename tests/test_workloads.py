@@ -69,3 +69,13 @@ def test_distinct_generators_reject_more_tuples_than_the_space():
     with pytest.raises(ValueError):
         W._distinct_zipf_mixed(rng, np.array([27, 14, 8], np.int64), 1.1, 3025)
     assert W._distinct_zipf_mixed(rng, np.array([3, 4], np.int64), 1.1, 12).shape == (12, 2)
+
+
+def test_wide_table_shape_and_determinism():
+    a = W.wide_table()
+    b = W.wide_table()
+    assert a.n == 100 and a.t == 10_000
+    assert (a.tuples == b.tuples).all() and (a.dsizes == b.dsizes).all()
+    assert a.dsizes.min() >= 64 and a.dsizes.max() <= 160
+    assert (a.tuples >= 0).all() and (a.tuples < a.dsizes[None, :]).all()
+    assert np.unique(a.tuples, axis=0).shape[0] == a.t
