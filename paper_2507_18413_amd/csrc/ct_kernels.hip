@@ -264,6 +264,17 @@ __device__ void do_prep(const KArgs& a, const DevJob& J, Shared& sh) {
   }
 }
 
+// Inclusive prefix sum over the 64 lanes.
+__device__ __forceinline__ int wave_scan_incl(int v) {
+  const int lane = lane_id();
+#pragma unroll
+  for (int d = 1; d < WAVE; d <<= 1) {
+    const int u = __shfl_up(v, d);
+    if (lane >= d) v += u;
+  }
+  return v;
+}
+
 // ---------------------------------------------------------------------------
 // prologue of Alg. 1 for one job (every update item recomputes it in LDS)
 // ---------------------------------------------------------------------------
@@ -332,27 +343,47 @@ __device__ void prologue(const KArgs& a, const DevJob& J, Shared& sh, bool pushH
     atomicAdd(&sh.dcnt[i], __popcll(dl));
   }
   __syncthreads();
-  if (threadIdx.x == 0) {
-    if (sh.status == ST_OK) {
-      if (sh.bad_stray) sh.status = ST_INVALID;
-      else if (sh.bad_sub) sh.status = ST_NOT_SUBSET;
-    }
+  if (threadIdx.x < WAVE) {
+    // wave 0: the segments of s_val in variable order (prefix sums over the
+    // variables, 64 at a time)
+    const int lane = threadIdx.x;
     const int policy = T->policy;
     int nseg = 0, nrows = 0;
-    for (int i = 0; i < n; ++i) {
-      const bool inSval = root || sh.dcnt[i] > 0;  // |dom| changed since the last call
-      if (!inSval) { sh.segOf[i] = -1; continue; }
-      const int inc = root ? 0
-                           : (policy == 2 ? 1 : policy == 1 ? 0 : (sh.dcnt[i] < sh.size[i] ? 1 : 0));
-      nrows += inc ? sh.dcnt[i] : sh.size[i];
-      sh.segOf[i] = nseg;
-      sh.segInc[nseg] = inc;
-      sh.segEnd[nseg] = nrows;
-      ++nseg;
+    for (int i0 = 0; i0 < n; i0 += WAVE) {
+      const int i = i0 + lane;
+      bool inSval = false;
+      int inc = 0, cnt = 0;
+      if (i < n) {
+        inSval = root || sh.dcnt[i] > 0;  // |dom| changed since the last call
+        if (inSval) {
+          inc = root ? 0 : (policy == 2 ? 1 : policy == 1 ? 0 : (sh.dcnt[i] < sh.size[i] ? 1 : 0));
+          cnt = inc ? sh.dcnt[i] : sh.size[i];
+        }
+      }
+      const int segIncl = wave_scan_incl(inSval ? 1 : 0);
+      const int rowsIncl = wave_scan_incl(cnt);
+      if (i < n) {
+        if (inSval) {
+          const int sg = nseg + segIncl - 1;
+          sh.segOf[i] = sg;
+          sh.segInc[sg] = inc;
+          sh.segEnd[sg] = nrows + rowsIncl;
+        } else {
+          sh.segOf[i] = -1;
+        }
+      }
+      nseg += __shfl(segIncl, WAVE - 1);
+      nrows += __shfl(rowsIncl, WAVE - 1);
     }
-    sh.nseg = nseg;
-    sh.nrows = nrows;
-    sh.noop = (nseg == 0) && !fromRoot;
+    if (lane == 0) {
+      if (sh.status == ST_OK) {
+        if (sh.bad_stray) sh.status = ST_INVALID;
+        else if (sh.bad_sub) sh.status = ST_NOT_SUBSET;
+      }
+      sh.nseg = nseg;
+      sh.nrows = nrows;
+      sh.noop = (nseg == 0) && !fromRoot;
+    }
   }
   __syncthreads();
   if (sh.status != ST_OK || sh.noop) return;
@@ -887,16 +918,6 @@ __device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Inclusive prefix sum over the 64 lanes.
-__device__ __forceinline__ int wave_scan_incl(int v) {
-  const int lane = lane_id();
-#pragma unroll
-  for (int d = 1; d < WAVE; d <<= 1) {
-    const int u = __shfl_up(v, d);
-    if (lane >= d) v += u;
-  }
-  return v;
-}
 
 // One wave per node: the Alg. 1 prologue of a root reset.  Per variable the
 // number of values of dom_in (|dom|) and of removed root values (|Delta|)
