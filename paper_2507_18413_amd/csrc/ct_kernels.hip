@@ -652,8 +652,40 @@ __device__ int finalize_update(const DevJob& J, Shared& sh, bool ldsFlags, int j
 // filterDomains (Alg. 3) for domain word q, by one wave: residue word first,
 // then the active granules in index order until a support is found.
 // ---------------------------------------------------------------------------
+// What filterDomains reads for domain word q before currTable is final: the
+// word, its variable's size, and per value (lane) the residue and the support
+// word at the residue (supports and residues do not change during the
+// update), so a filter that waits for the update has them loaded meanwhile.
+struct FilterPre {
+  uint64_t din, sres;
+  VarDesc v;
+  int size, rl, rw0;
+};
+
+__device__ __forceinline__ FilterPre filter_pre(const KArgs& a, const DevJob& J, int q) {
+  const TabDesc* T = J.tab;
+  const int lane = lane_id();
+  FilterPre f;
+  f.v = T->vars[T->wordVar[q]];
+  f.din = job_din(a, J, q);
+  f.size = 0;
+  for (int k = f.v.domOff; k < f.v.domOff + f.v.domWords; ++k) f.size += __popcll(job_din(a, J, k));
+  const int rowBase = f.v.rowStart + (q - f.v.domOff) * 64;
+  // these loads run before the job's input is validated: a lane past the
+  // variable's last value (a stray bit) takes the word's first row, and the
+  // residue is clamped to the row, so every address is inside the table
+  const int used = f.v.dsize - 64 * (q - f.v.domOff);
+  const bool present = lane < used && ((f.din >> lane) & 1ull);
+  // unconditional loads from valid addresses (row of the word's first value
+  // for absent lanes), results selected afterwards
+  f.rl = present ? rowBase + lane : rowBase;
+  f.rw0 = min(max(J.slot->res[f.rl], 0), (int)T->stride - 1);
+  f.sres = T->S[(int64_t)f.rl * T->stride + f.rw0];
+  return f;
+}
+
 __device__ void filter_word(const KArgs& a, const DevJob& J, int q, int noop, int lim,
-                            const CT_G int32_t* idx, unsigned long long* cnt) {
+                            const CT_G int32_t* idx, unsigned long long* cnt, const FilterPre& f) {
   const TabDesc* T = J.tab;
   SlotDesc* slot = J.slot;
   // the slot's arrays, read once (see update_granules)
@@ -662,21 +694,17 @@ __device__ void filter_word(const KArgs& a, const DevJob& J, int q, int noop, in
     CT_G int32_t* res;
   } sv{slot->ct, slot->res}, *s = &sv;
   const int lane = lane_id();
-  const int i = T->wordVar[q];
-  const VarDesc v = T->vars[i];
-  const uint64_t din = job_din(a, J, q);
-  int size = 0;
-  for (int k = v.domOff; k < v.domOff + v.domWords; ++k) size += __popcll(job_din(a, J, k));
+  const VarDesc v = f.v;
+  const uint64_t din = f.din;
+  const int size = f.size;
   uint64_t dout = din;
   if (!noop && size > 1) {  // s_sup: non-singleton variables
     const int64_t stride = T->stride;
     const int rowBase = v.rowStart + (q - v.domOff) * 64;
     const bool present = (din >> lane) & 1ull;
-    // unconditional loads from valid addresses (row of the word's first value
-    // for absent lanes), results selected afterwards
-    const int rl = present ? rowBase + lane : rowBase;
-    const int rw0 = s->res[rl];
-    const bool hit = present && (s->ct[rw0] & T->S[(int64_t)rl * stride + rw0]) != 0ull;
+    const int rl = f.rl;
+    const int rw0 = f.rw0;
+    const bool hit = present && (s->ct[rw0] & f.sres) != 0ull;
     unsigned long long miss = __ballot(present && !hit);
     cnt[0] += __popcll(__ballot(present));
     cnt[1] += __popcll(miss);
@@ -771,6 +799,11 @@ __device__ void filter_word(const KArgs& a, const DevJob& J, int q, int noop, in
   }
 }
 
+__device__ __forceinline__ void filter_word(const KArgs& a, const DevJob& J, int q, int noop, int lim,
+                                            const CT_G int32_t* idx, unsigned long long* cnt) {
+  filter_word(a, J, q, noop, lim, idx, cnt, filter_pre(a, J, q));
+}
+
 __device__ void add_filter_stats(SlotDesc* s, const unsigned long long* cnt) {
   if (lane_id() == 0 && (cnt[0] | cnt[1] | cnt[2])) {
     atomicAdd(&s->stats[S_RES_CHECK], cnt[0]);
@@ -835,12 +868,14 @@ __device__ void do_update(const KArgs& a, const DevJob& J, int chunk, Shared& sh
 // split mode: one filter item (one domain word per wave)
 __device__ void do_filter(const KArgs& a, const DevJob& J, int chunk, Shared& sh) {
   SlotDesc* s = J.slot;
+  const int q = chunk * WAVES + wave_id();
+  const int qc = min(q, J.tab->D - 1);
+  const FilterPre pre = filter_pre(a, J, qc);  // in flight while the update runs
   if (!block_wait(a, &s->updDone, 1, sh)) return;
   const int jobStatus = s->status;
-  const int q = chunk * WAVES + wave_id();
   unsigned long long cnt[3] = {0, 0, 0};
   if (q < J.tab->D && jobStatus == ST_OK) {
-    filter_word(a, J, q, s->pad2, s->limit, s->idx[s->cur], cnt);
+    filter_word(a, J, q, s->pad2, s->limit, s->idx[s->cur], cnt, pre);
   }
   add_filter_stats(s, cnt);
   // the last filter item of the job reports OK
