@@ -1294,18 +1294,19 @@ __global__ void __launch_bounds__(NodesCfg<TW>::BLOCKT, 4) nodes_update_kernel(K
   }
 }
 
-// One workgroup of 4 waves per node: wave 0 partitions the root's granule
-// list by the non-zero flags (survivors first, stable) and detects FAIL
-// (Alg. 1); then the waves run filterDomains (Alg. 3) on interleaved domain
-// words.
+// One wave per node, four nodes per workgroup, so the nodes of a batch are
+// resident at once: the stable partition of the root's granule list by the
+// non-zero flags (survivors first) and FAIL (Alg. 1), then filterDomains
+// (Alg. 3) over the node's domain words, the residue loads of FINISH_PRE words
+// in flight together.
 constexpr int FINISH_BLOCK = 256;
-constexpr int FINISH_WAVES = FINISH_BLOCK / WAVE;
+constexpr int FINISH_NODES = FINISH_BLOCK / WAVE;
+constexpr int FINISH_PRE = 4;
 
 __global__ void __launch_bounds__(FINISH_BLOCK) nodes_finish_kernel(KArgs a, NodesDesc N) {
-  __shared__ int32_t shSurv;
-  const int j = blockIdx.x;
+  const int j = blockIdx.x * FINISH_NODES + __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
+  if (j >= N.nJobs) return;
   const int lane = lane_id();
-  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
   const DevJob J = N.jobs[j];
   const TabDesc* T = J.tab;
   SlotDesc* s = J.slot;
@@ -1313,14 +1314,14 @@ __global__ void __launch_bounds__(FINISH_BLOCK) nodes_finish_kernel(KArgs a, Nod
   const int st0 = rec->status;
   const int nrows = rec->nrows;
   const bool run = st0 == ST_OK || st0 == ST_FAIL;
-  if (run && wv == 0) {
+  int nSurv = 0;
+  if (run) {
     const int limit0 = T->limit0, nGran = T->nGran;
     const CT_G uint8_t* nz = N.nz + (int64_t)j * nGran;
     const CT_G int32_t* src = T->idx0;
     CT_G int32_t* dst = s->idx[0];
     const uint64_t below = (1ull << lane) - 1ull;
     // granule ids and flags of 4 x 64 positions per round trip
-    int nSurv = 0;
     for (int p0 = 0; p0 < limit0; p0 += 4 * WAVE) {
       int gid[4];
       bool f[4];
@@ -1356,7 +1357,6 @@ __global__ void __launch_bounds__(FINISH_BLOCK) nodes_finish_kernel(KArgs a, Nod
     }
     for (int p = limit0 + lane; p < nGran; p += WAVE) dst[p] = src[p];
     if (lane == 0) {
-      shSurv = nSurv;
       s->cur = 0;
       s->limit = nSurv;
       s->depth = 0;
@@ -1368,18 +1368,25 @@ __global__ void __launch_bounds__(FINISH_BLOCK) nodes_finish_kernel(KArgs a, Nod
       atomicAdd(&s->stats[S_ROWS], (unsigned long long)nrows);
       if (nrows) atomicAdd(&s->stats[S_GRAN_ROWS], (unsigned long long)limit0 * (unsigned long long)nrows);
     }
+    __threadfence_block();  // the index written by the lanes is read by the filter's scans
+  } else {
+    slot_reset_root(T, s, J.serialBase, lane, WAVE);
   }
-  if (!run) slot_reset_root(T, s, J.serialBase, threadIdx.x, blockDim.x);
-  __syncthreads();  // the partition is visible to the workgroup
-  const int nSurv = run ? shSurv : 0;
   const int st = run ? (nSurv ? ST_OK : ST_FAIL) : st0;
   if (st == ST_OK) {
     unsigned long long cnt[3] = {0, 0, 0};
-    for (int q = wv; q < T->D; q += FINISH_WAVES) filter_word(a, J, q, 0, nSurv, s->idx[0], cnt);
+    const int D = T->D;
+    for (int q0 = 0; q0 < D; q0 += FINISH_PRE) {
+      FilterPre pre[FINISH_PRE];
+#pragma unroll
+      for (int u = 0; u < FINISH_PRE; ++u) pre[u] = filter_pre(a, J, min(q0 + u, D - 1));
+#pragma unroll
+      for (int u = 0; u < FINISH_PRE; ++u)
+        if (q0 + u < D) filter_word(a, J, q0 + u, 0, nSurv, s->idx[0], cnt, pre[u]);
+    }
     add_filter_stats(s, cnt);
   }
-  __syncthreads();
-  if (threadIdx.x == 0) {
+  if (lane == 0) {
     s->status = st;
     s->pad2 = 0;
     item_fence(J);
@@ -1886,7 +1893,8 @@ hipError_t launch_nodes(const KArgs& a, const NodesDesc& N, int n, hipStream_t s
   else
     hipLaunchKernelGGL(nodes_update_kernel<1>, dim3(nodes_update_grid<1>(lds)), dim3(NodesCfg<1>::BLOCKT), lds,
                        stream, a, N);
-  hipLaunchKernelGGL(nodes_finish_kernel, dim3(N.nJobs), dim3(FINISH_BLOCK), 0, stream, a, N);
+  hipLaunchKernelGGL(nodes_finish_kernel, dim3((N.nJobs + FINISH_NODES - 1) / FINISH_NODES), dim3(FINISH_BLOCK), 0,
+                     stream, a, N);
   return hipGetLastError();
 }
 
