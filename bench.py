@@ -292,6 +292,56 @@ def wide_leg(seed, n_calls, cpu):
     return out
 
 
+def solver_leg(seed, max_nodes, cpu):
+    """A depth-first search through the library on a generated knapsack-like
+    model (30 variables over {0..9}, 10 tables of arity 8 with 110k-380k
+    tuples, one linear inequality on the host), table propagation on the GPU;
+    the same search with the oracle's tables beside it."""
+    from paper_2507_18413_amd import solver as S
+    from paper_2507_18413_amd.workloads import DomLayout
+    import numpy as np
+    kw = dict(n_vars=30, d=10, n_tables=10, arity=8, density=(0.001, 0.004))
+    dsz, tables, w, cap = S.lin_model(seed, **kw)
+    lay = DomLayout(dsz, np.zeros_like(dsz))
+    M, tabs = S.build_gpu(dsz, tables)
+    prop = S.GpuTables(M, lay.D)
+    g = S.Search(lay, prop, S.LinearLE(lay, range(lay.n), w, cap))
+    t0 = time.perf_counter()
+    g.run(lay.full(), max_nodes, 10 ** 6)
+    el = time.perf_counter() - t0
+    out = {"model": "30 variables over {0..9}, 10 tables of arity 8 ("
+                    f"{sum(len(t) for t, _ in tables)} tuples), sum w_i x_i <= cap",
+           "nodes": g.nodes, "fails": g.fails, "solutions": len(g.solutions),
+           "table_propagations": prop.props, "seconds": round(el, 3),
+           "nodes_per_s": round(g.nodes / el, 1)}
+    if cpu:
+        from oracle import oracle as O
+
+        class OracleTables:
+            def __init__(self):
+                self.ots = [O.OracleTable(t, np.zeros(len(sc), np.int32), dsz[sc]) for t, sc in tables]
+
+            def fixpoint(self, pool):
+                st, o, _ = O.fixpoint(self.ots, [sc for _, sc in tables], lay, pool)
+                return st != O.OK, (o if st == O.OK else pool)
+
+            def push(self):
+                for x in self.ots:
+                    x.push()
+
+            def pop(self):
+                for x in self.ots:
+                    x.pop()
+
+        o = S.Search(lay, OracleTables(), S.LinearLE(lay, range(lay.n), w, cap))
+        t0 = time.perf_counter()
+        o.run(lay.full(), max_nodes, 10 ** 6)
+        oel = time.perf_counter() - t0
+        out["oracle_seconds"] = round(oel, 3)
+        out["same_tree_as_oracle"] = bool((o.nodes, o.fails, o.solutions) == (g.nodes, g.fails, g.solutions))
+    return out
+
+
 def root_batch_leg(tabs, specs, reps, per_table=True):
     """Every table's root recomputed from scratch (ROOT jobs: all tuples,
     every variable on the reset branch) in one batched launch: each support
@@ -758,6 +808,8 @@ def main():
     note(f"plain leg done: {value:.0f} propagations/s")
     note("wide-scope leg")
     out["wide_scope"] = wide_leg(seed, 300, not args.no_cpu_baseline)
+    note("search driver leg")
+    out["search_driver"] = solver_leg(seed, 400, not args.no_cpu_baseline)
     if not args.no_nodes:
         note("search-node leg")
         out["batched_nodes"] = nodes_leg(seed, args.nodes, max(1, args.steps), 1)
