@@ -94,7 +94,7 @@ def replay(table, script, lat=None):
 
 
 def algorithmic_bytes(d_stats, D, calls):
-    """Bytes the method must move for the counted work (see DESIGN.md):
+    """Bytes the method must move for the counted work:
     every active granule reads its k support-row segments and its currTable
     words and writes the words back; each trailed granule saves 64 words and
     a header; each residue check reads two words; each scanned granule reads
@@ -137,11 +137,11 @@ def nodes_leg(seed, n_nodes, reps, warmup, schedule=0):
     import torch
     from paper_2507_18413_amd import ct
     from paper_2507_18413_amd import workloads as W
-    spec = W.config4_table(seed)
+    spec = W.zipf_table(seed)
     lay = spec.layout()
     table = ct.Table(spec.tuples, spec.lo, spec.dsizes, max_depth=0, schedule=schedule)
     root = table.domains()
-    nodes = W.config4_nodes(lay, root, n_nodes, seed)
+    nodes = W.node_states(lay, root, n_nodes, seed)
     first = table.slots_alloc(n_nodes, max_depth=0)
     din = torch.from_numpy(nodes.view(np.int64)).cuda()
     dout = torch.zeros_like(din)
@@ -172,7 +172,7 @@ def nodes_leg(seed, n_nodes, reps, warmup, schedule=0):
     W_words = table.W
     comp = 8 * table.rows * W_words + 8 * W_words + n_nodes * (8 * W_words + 16 * lay.D)
     from paper_2507_18413_amd import profiling
-    prof = profiling.read_summary(os.path.join(ROOT, "profiles", "nodes_update_config4.md"))
+    prof = profiling.read_summary(os.path.join(ROOT, "profiles", "nodes_update_4096_nodes.md"))
     return {
         "nodes": n_nodes, "tuples": spec.t, "ms_per_batch": round(gpu_ms, 3),
         "node_props_per_s": round(n_nodes / (gpu_ms / 1e3), 1),
@@ -390,7 +390,7 @@ def root_batch_leg(tabs, specs, reps, per_table=True):
            "timing": "HIP events around the batches on the launch stream"}
     # the streaming kernel alone, from the committed rocprofv3 summary
     from paper_2507_18413_amd import profiling
-    prof = profiling.read_summary(os.path.join(ROOT, "profiles", "root_stream_config3.md"))
+    prof = profiling.read_summary(os.path.join(ROOT, "profiles", "root_stream_2000_tables.md"))
     stream_bytes = 8 * rows_w + 8 * sum(int(t.W) for t in tabs)
     out["stream_kernel"] = {"name": "ctk::root_stream_kernel", "algorithmic_bytes": stream_bytes}
     if prof:
@@ -423,7 +423,7 @@ def model_leg(seed, steps, plain_steps, cpu):
     from paper_2507_18413_amd import ct
     from paper_2507_18413_amd import workloads as W
     t0 = time.perf_counter()
-    spec = W.config3_model(seed)
+    spec = W.multi_table_model(seed)
     lay = spec.pool_layout()
     gen_s = time.perf_counter() - t0
     tabs = [ct.Table(tb.tuples, tb.lo, tb.dsizes) for tb in spec.tables]
@@ -698,7 +698,7 @@ def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the library runs "
-              f"on a single MI355X; see DESIGN.md for how the path would shard)", file=sys.stderr)
+              f"on a single MI355X; sharding over several GPUs is a design, not a build)", file=sys.stderr)
         sys.exit(2)
     import numpy as np
     import torch
@@ -708,7 +708,7 @@ def main():
     seed = W.DEFAULT_SEED if args.seed is None else args.seed
     if args.root_batch_only:
         note("generating the 2,000-table model")
-        mspec = W.config3_model(seed)
+        mspec = W.multi_table_model(seed)
         torch.cuda.set_device(0)
         calibration_copy(args.calibration_copy)
         tabs = [ct.Table(tb.tuples, tb.lo, tb.dsizes) for tb in mspec.tables]
@@ -721,11 +721,11 @@ def main():
         # generated before the GPU is initialised: the pool's workers are
         # fresh interpreters
         note("generating the serving mix (300 tables)")
-        serve_spec = W.config5_tables(seed, workers=min(16, os.cpu_count() or 1))
+        serve_spec = W.serving_tables(seed, workers=min(16, os.cpu_count() or 1))
     note("plain leg: building the 200,000-tuple table")
     torch.cuda.set_device(0)
     calibration_copy(args.calibration_copy)
-    spec = W.config2_table(seed)
+    spec = W.large_table(seed)
     lay = spec.layout()
     # the table under test (synchronous calls go to the resident engine when
     # its state fits one workgroup's LDS) and a twin on launched kernels that
@@ -768,7 +768,7 @@ def main():
     from paper_2507_18413_amd import profiling
     kname = "ctk::engine_kernel" if table.resident else "ctk::propagate_kernel"
     prof = profiling.read_summary(os.path.join(
-        ROOT, "profiles", "engine_config2.md" if table.resident else "propagate_config2.md"))
+        ROOT, "profiles", "engine_large_table.md" if table.resident else "propagate_large_table.md"))
     # HBM bytes per call: per dispatch for launched calls; for the engine,
     # per call (its dispatches serve many calls each)
     traffic = (prof.get("hbm_bytes_per_call") if table.resident else prof.get("hbm_bytes_per_launch")) \

@@ -3,7 +3,7 @@
     python -m paper_2507_18413_amd.profiling summarize \
         --stats DIR/c2_kernel_stats.csv \
         --fetch DIRF/c2_counter_collection.csv --write DIRW/c2_counter_collection.csv \
-        --copy-bytes N --command "..." --out profiles/propagate_config2.md
+        --copy-bytes N --command "..." --out profiles/propagate_large_table.md
 
 The kernel-trace statistics give the chosen kernel's (--kernel, a regular
 expression; default the propagate kernel) average duration.
@@ -28,7 +28,7 @@ import statistics
 HERE = os.path.dirname(os.path.abspath(__file__))
 KERNEL_SRCS = [os.path.join(HERE, "csrc", "ct_kernels.hip"), os.path.join(HERE, "csrc", "ct_engine.hip")]
 KERNEL = "propagate_kernel"
-DEFAULT_TITLE = "propagate_kernel, one large table (config 2)"
+DEFAULT_TITLE = "propagate_kernel, one 200,000-tuple table"
 
 
 def kernel_source_hash() -> str:

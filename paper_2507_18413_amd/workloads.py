@@ -15,7 +15,7 @@ are zero.
 The workloads stand in for the paper's MiniZinc instance suites (LIN_B,
 LIN_EB, orienteering, the Gecode comparison set, Sec. 5.1), which are not
 available: every table here is drawn from a seeded generator with the stated
-shape.  Seeds follow ``SeedSequence([base, config, stream])``.
+shape.  Seeds follow ``SeedSequence([base, family, stream])``.
 """
 from __future__ import annotations
 
@@ -27,9 +27,9 @@ import numpy as np
 DEFAULT_SEED = 20250724
 
 
-def rng_for(base: int, config: int, stream: int = 0) -> np.random.Generator:
-    """Independent PCG64 stream for (base seed, config number, stream id)."""
-    return np.random.Generator(np.random.PCG64(np.random.SeedSequence([base, config, stream])))
+def rng_for(base: int, family: int, stream: int = 0) -> np.random.Generator:
+    """Independent PCG64 stream for (base seed, workload family number, stream id)."""
+    return np.random.Generator(np.random.PCG64(np.random.SeedSequence([base, family, stream])))
 
 
 # ---------------------------------------------------------------------------
@@ -220,14 +220,14 @@ class TableSpec:
         return DomLayout(self.dsizes, self.lo)
 
 
-def config1_table(seed: int = DEFAULT_SEED) -> TableSpec:
+def tiny_table(seed: int = DEFAULT_SEED) -> TableSpec:
     """Arity 3, every domain {0..7}, 200 distinct tuples out of the 512 codes."""
     rng = rng_for(seed, 1, 0)
     tup = distinct_uniform_tuples(rng, [8, 8, 8], 200)
     return TableSpec(tup, np.zeros(3, np.int32), np.full(3, 8, np.int32))
 
 
-def config2_table(seed: int = DEFAULT_SEED, t: int = 200_000, d: int = 50, n: int = 5) -> TableSpec:
+def large_table(seed: int = DEFAULT_SEED, t: int = 200_000, d: int = 50, n: int = 5) -> TableSpec:
     """Arity 5, domain size 50, 200,000 distinct uniform tuples (3,125 words per row)."""
     rng = rng_for(seed, 2, 0)
     tup = distinct_uniform_tuples(rng, [d] * n, t)
@@ -247,7 +247,7 @@ def wide_table(seed: int = DEFAULT_SEED, n: int = 100, dom=(64, 160), t: int = 1
     return TableSpec(tup, np.zeros(n, np.int32), ds)
 
 
-def config4_table(seed: int = DEFAULT_SEED, t: int = 1_000_000, d: int = 20, n: int = 6,
+def zipf_table(seed: int = DEFAULT_SEED, t: int = 1_000_000, d: int = 20, n: int = 6,
                   s: float = 1.1) -> TableSpec:
     """Arity 6, domain size 20, distinct tuples with Zipf(1.1) columns."""
     rng = rng_for(seed, 4, 0)
@@ -255,7 +255,7 @@ def config4_table(seed: int = DEFAULT_SEED, t: int = 1_000_000, d: int = 20, n: 
     return TableSpec(tup, np.zeros(n, np.int32), np.full(n, d, np.int32))
 
 
-def config4_nodes(layout: DomLayout, root_dom: np.ndarray, n_nodes: int,
+def node_states(layout: DomLayout, root_dom: np.ndarray, n_nodes: int,
                   seed: int = DEFAULT_SEED, max_frac: float = 0.6) -> np.ndarray:
     """Search-node domain states: per node and variable draw f ~ U[0, max_frac]
     and remove floor(f * |root domain|) values chosen uniformly from the root
@@ -287,7 +287,7 @@ class ModelSpec:
         return DomLayout(self.pool_dsizes, np.zeros_like(self.pool_dsizes))
 
 
-def config3_model(seed: int = DEFAULT_SEED, n_pool: int = 5000, n_tables: int = 2000,
+def multi_table_model(seed: int = DEFAULT_SEED, n_pool: int = 5000, n_tables: int = 2000,
                   arity=(2, 8), dom=(4, 64), tuples=(100, 500_000), plant: bool = True) -> ModelSpec:
     """Pool of variables with d ~ U{dom}, tables of arity ~ U{arity} over distinct
     pool variables, tuple counts log-uniform in ``tuples`` capped at half the
@@ -317,7 +317,7 @@ def config3_model(seed: int = DEFAULT_SEED, n_pool: int = 5000, n_tables: int = 
     return ModelSpec(pool, tables, scopes)
 
 
-def _config5_one(args):
+def _serving_one(args):
     seed, c, ds, t, s = args
     trng = rng_for(seed, 5, 1 + c)
     if c % 2 == 0:
@@ -327,7 +327,7 @@ def _config5_one(args):
     return TableSpec(tup, np.zeros(ds.shape[0], np.int32), ds.astype(np.int32))
 
 
-def config5_tables(seed: int = DEFAULT_SEED, n_tables: int = 300, arity=(3, 10), dom=(8, 128),
+def serving_tables(seed: int = DEFAULT_SEED, n_tables: int = 300, arity=(3, 10), dom=(8, 128),
                    tuples=(1_000, 2_000_000), s: float = 1.1, workers: int = 0):
     """Serving mix: even-index tables uniform, odd-index Zipf(s) columns.
 
@@ -345,8 +345,8 @@ def config5_tables(seed: int = DEFAULT_SEED, n_tables: int = 300, arity=(3, 10),
     if workers and workers > 1:
         import multiprocessing as mp
         with mp.get_context("spawn").Pool(workers) as pool:
-            return pool.map(_config5_one, jobs, chunksize=1)
-    return [_config5_one(j) for j in jobs]
+            return pool.map(_serving_one, jobs, chunksize=1)
+    return [_serving_one(j) for j in jobs]
 
 
 def _distinct_zipf_mixed(rng, dsizes, s, t):
@@ -437,7 +437,7 @@ class Backtracker:
         return 0
 
 
-def run_plain_script(sut, layout: DomLayout, n_calls: int, seed: int, config: int,
+def run_plain_script(sut, layout: DomLayout, n_calls: int, seed: int, family: int,
                      picker, on_step=None):
     """Drive one table through a simulated search.
 
@@ -448,7 +448,7 @@ def run_plain_script(sut, layout: DomLayout, n_calls: int, seed: int, config: in
     called after each operation (kind in {"prop", "pop"}).  Returns the list
     of operations as (kind, payload) for replay.
     """
-    rng = rng_for(seed, config, 7)
+    rng = rng_for(seed, family, 7)
     bt = Backtracker(rng)
     depth = 0
     script = []

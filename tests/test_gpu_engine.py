@@ -47,7 +47,7 @@ def unwind(G, Ot, rng, status):
 
 @pytest.mark.parametrize("policy", [ct.BRANCH_AUTO, ct.BRANCH_RESET, ct.BRANCH_INCREMENTAL])
 def test_long_run_without_state_reads(policy):
-    spec = W.config2_table(t=40_000, d=24, n=5)
+    spec = W.large_table(t=40_000, d=24, n=5)
     say("engine: 400 calls, policy", policy)
     G, Ot = pair(spec, policy=policy)
     lay = spec.layout()
@@ -63,7 +63,7 @@ def test_long_run_without_state_reads(policy):
 
 
 def test_idle_exit_and_restart():
-    spec = W.config2_table(t=20_000, d=20, n=4)
+    spec = W.large_table(t=20_000, d=20, n=4)
     say("engine: idle exits between calls")
     G, Ot = pair(spec)
     lay = spec.layout()
@@ -78,7 +78,7 @@ def test_idle_exit_and_restart():
 
 
 def test_tables_take_turns():
-    a = W.config2_table(t=15_000, d=16, n=4)
+    a = W.large_table(t=15_000, d=16, n=4)
     b = W.TableSpec(W.distinct_uniform_tuples(W.rng_for(4, 602, 0), [9, 9, 9], 300),
                     np.zeros(3, np.int32), np.full(3, 9, np.int32))
     say("engine: two tables alternate (one engine per process)")
@@ -97,13 +97,13 @@ def test_tables_take_turns():
 
 def test_other_slots_batches_and_stats_interleaved():
     import torch
-    spec = W.config2_table(t=30_000, d=20, n=5)
+    spec = W.large_table(t=30_000, d=20, n=5)
     say("engine: slot 0 calls interleaved with batches on other slots, stats")
     G, Ot = pair(spec)
     lay = spec.layout()
     root = Ot.domains()
     first = G.slots_alloc(8, max_depth=0)
-    nodes = W.config4_nodes(lay, root, 8, max_frac=0.3)
+    nodes = W.node_states(lay, root, 8, max_frac=0.3)
     din = torch.from_numpy(nodes.view(np.int64)).cuda()
     dout = torch.zeros_like(din)
     status = torch.zeros(8, dtype=torch.int32, device="cuda")

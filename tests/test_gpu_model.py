@@ -123,10 +123,10 @@ def test_search_steps_vs_oracle(schedule):
                 pool = stack.pop()
 
 
-def test_scaled_config3_root_and_steps():
+def test_scaled_multi_table_root_and_steps():
     import torch
-    say("config3 scaled: 150 tables over 400 variables")
-    spec = W.config3_model(n_pool=400, n_tables=150, tuples=(100, 20_000))
+    say("multi-table model scaled: 150 tables over 400 variables")
+    spec = W.multi_table_model(n_pool=400, n_tables=150, tuples=(100, 20_000))
     lay, M, gts, ots = build(spec)
     full = lay.full()
     out = dev(full)

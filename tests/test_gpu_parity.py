@@ -146,11 +146,11 @@ def test_random_sequences_vs_oracle(chunk):
             same_state(G, Ot, where=f"step {step}")
 
 
-def run_plain(spec, n_calls, picker, config, check_every=1, schedule=ct.SCHED_AUTO):
+def run_plain(spec, n_calls, picker, family, check_every=1, schedule=ct.SCHED_AUTO):
     G, Ot = pair(spec.tuples, spec.lo, spec.dsizes, schedule=schedule)
     lay = spec.layout()
     same_state(G, Ot, where="root")
-    rng = W.rng_for(W.DEFAULT_SEED, config, 9)
+    rng = W.rng_for(W.DEFAULT_SEED, family, 9)
     bt = W.Backtracker(rng)
     depth = 0
     for call in range(n_calls):
@@ -171,22 +171,22 @@ def run_plain(spec, n_calls, picker, config, check_every=1, schedule=ct.SCHED_AU
     return G, Ot
 
 
-def test_config1_full():
-    say("config1: arity 3, d=8, 200 tuples, 100 calls")
-    run_plain(W.config1_table(), 100, W.pick_small_removal, 1)
+def test_tiny_table_full():
+    say("tiny table: arity 3, d=8, 200 tuples, 100 calls")
+    run_plain(W.tiny_table(), 100, W.pick_small_removal, 1)
 
 
 @pytest.mark.parametrize("schedule", [ct.SCHED_SOLO, ct.SCHED_SPLIT])
-def test_config2_scaled(schedule):
-    say("config2 scaled: arity 5, d=50, 20,000 tuples, 300 calls, schedule", schedule)
-    spec = W.config2_table(t=20_000)
+def test_large_table_scaled(schedule):
+    say("large table scaled: arity 5, d=50, 20,000 tuples, 300 calls, schedule", schedule)
+    spec = W.large_table(t=20_000)
     run_plain(spec, 300, W.pick_fraction_removal, 2, schedule=schedule)
 
 
 @pytest.mark.parametrize("schedule", [ct.SCHED_AUTO, ct.SCHED_SPLIT])
-def test_config2_full(schedule):
-    say("config2 full: arity 5, d=50, 200,000 tuples, 1,000 calls, schedule", schedule)
-    spec = W.config2_table()
+def test_large_table_full(schedule):
+    say("large table: arity 5, d=50, 200,000 tuples, 1,000 calls, schedule", schedule)
+    spec = W.large_table()
     G, Ot = run_plain(spec, 1000, W.pick_fraction_removal, 2, schedule=schedule)
     assert G.W == 3125
 
@@ -212,7 +212,7 @@ def test_wide_scope_nodes_batch_vs_oracle():
     G, Ot = pair(spec.tuples, spec.lo, spec.dsizes)
     root = Ot.domains()
     n = 96
-    nodes = W.config4_nodes(lay, root, n, max_frac=0.3)
+    nodes = W.node_states(lay, root, n, max_frac=0.3)
     first = G.slots_alloc(n, max_depth=0)
     din = to_dev(nodes)
     dout = torch.zeros_like(din)
@@ -258,7 +258,7 @@ def test_errors_match_oracle():
 
 
 def test_depth_limit():
-    spec = W.config1_table()
+    spec = W.tiny_table()
     G = ct.Table(spec.tuples, spec.lo, spec.dsizes, max_depth=3)
     for _ in range(3):
         assert G.push() == ct.OK
@@ -306,11 +306,11 @@ def from_dev(t):
 def test_batch_from_root_nodes_vs_oracle(schedule):
     import torch
     say("batch: FROM_ROOT search nodes, Zipf table 60k tuples, 256 nodes, schedule", schedule)
-    spec = W.config4_table(t=60_000)
+    spec = W.zipf_table(t=60_000)
     lay = spec.layout()
     G, Ot = pair(spec.tuples, spec.lo, spec.dsizes, schedule=schedule)
     root = Ot.domains()
-    nodes = W.config4_nodes(lay, root, 256)
+    nodes = W.node_states(lay, root, 256)
     first = G.slots_alloc(256, max_depth=0)
     din = to_dev(nodes)
     dout = torch.zeros_like(din)
@@ -419,7 +419,7 @@ def test_batch_nodes_schedule_edge_cases(n_nodes, rows):
 def test_batch_with_backtracking_equals_sequential(schedule):
     import torch
     say("batch: 32 slots with pops/pushes vs single calls, schedule", schedule)
-    spec = W.config2_table(t=30_000, d=20, n=4)
+    spec = W.large_table(t=30_000, d=20, n=4)
     lay = spec.layout()
     Gb = ct.Table(spec.tuples, spec.lo, spec.dsizes, schedule=schedule)   # batched
     Gs = ct.Table(spec.tuples, spec.lo, spec.dsizes,             # single calls, other schedule

@@ -6,15 +6,15 @@ from paper_2507_18413_amd import workloads as W
 
 
 def test_same_seed_same_bytes():
-    a = W.config1_table(7)
-    b = W.config1_table(7)
-    c = W.config1_table(8)
+    a = W.tiny_table(7)
+    b = W.tiny_table(7)
+    c = W.tiny_table(8)
     assert a.tuples.tobytes() == b.tuples.tobytes()
     assert a.tuples.tobytes() != c.tuples.tobytes()
 
 
-def test_config1_shape_distinct():
-    s = W.config1_table()
+def test_tiny_table_shape_distinct():
+    s = W.tiny_table()
     assert s.tuples.shape == (200, 3)
     assert s.tuples.min() >= 0 and s.tuples.max() <= 7
     assert len({tuple(r) for r in s.tuples.tolist()}) == 200
