@@ -31,8 +31,8 @@
  * ct_create; every slot starts as a copy of the root state (the state after
  * the root propagation in ct_create).
  *
- * Status codes: CT_OK, CT_FAIL (domain wipe-out: no valid tuple, Alg. 1 line
- * 5), or a negative error.  No call throws; after an error ct_last_error()
+ * Status codes: CT_OK, CT_FAIL (domain wipe-out: no valid tuple, Alg. 1's
+ * failure test), or a negative error.  No call throws; after an error ct_last_error()
  * returns a message for the calling thread.  A ct_table may be used by one
  * thread at a time; distinct tables are independent.
  */
@@ -53,7 +53,7 @@ extern "C" {
 #define CT_E_NOMEM (-4)      /* device or host allocation, trail or depth capacity */
 #define CT_E_DEVICE (-5)     /* HIP error or device-side timeout; handle is poisoned */
 
-/* update branch policy (Alg. 2 line 3): AUTO takes the incremental branch
+/* update branch policy (Alg. 2's branch choice): AUTO takes the incremental branch
  * (OR over the removed values, complemented) iff |Delta_i| < |dom(x_i)|,
  * else the reset branch (OR over the remaining values).  Both give the same
  * currTable; the forced modes exist for testing and ablation. */

@@ -42,7 +42,7 @@
 #define CTO_E_STATE (-3)
 #define CTO_E_NOMEM (-4)
 
-#define CTO_MODE_AUTO 0        /* Alg. 2 line 3 rule */
+#define CTO_MODE_AUTO 0        /* Alg. 2's branch rule */
 #define CTO_MODE_RESET 1       /* always OR over dom(x_i)  */
 #define CTO_MODE_INCREMENTAL 2 /* always OR over Delta_i, complement */
 
@@ -273,7 +273,7 @@ int cto_propagate(cto_table *T, const uint64_t *dom_in, uint64_t *dom_out, uint6
     T->st_sval = 0;
     T->st_ssup = 0;
 
-    /* Alg. 1, lines 1-3 */
+    /* Alg. 1: Delta, s_val, s_sup */
     for (int i = 0; i < n; i++) {
         size[i] = var_size(T, dom, i);
         if (size[i] != T->last_sizes[i]) {
@@ -307,14 +307,14 @@ int cto_propagate(cto_table *T, const uint64_t *dom_in, uint64_t *dom_out, uint6
         for (int64_t w = 0; w < W; w++) T->ct[w] &= mask[w];
         if (!any_word(T->ct, W)) break;
     }
-    /* Alg. 1, line 5 */
+    /* Alg. 1: failure test */
     if (!any_word(T->ct, W)) {
         T->failed = 1;
         if (ct_out) memset(ct_out, 0, sizeof(uint64_t) * W);
         free(dom); free(mask); free(size); free(s_val); free(s_sup);
         return CTO_FAIL;
     }
-    /* Alg. 1, line 6 -> Alg. 3 */
+    /* Alg. 1 goes on to filterDomains (Alg. 3) */
     filter_domains(T, dom, s_sup);
     memcpy(T->last_dom, dom, sizeof(uint64_t) * T->D);
     if (dom_out) memcpy(dom_out, dom, sizeof(uint64_t) * T->D);

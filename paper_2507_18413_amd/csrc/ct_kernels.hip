@@ -14,7 +14,7 @@
 //                           Delta / s_val / s_sup prologue of Alg. 1 recomputed
 //                           per item in LDS; the last update item of a job
 //                           records the job's pushes, partitions the sparse
-//                           index and decides FAIL (Alg. 1 line 5)
+//                           index and decides FAIL (Alg. 1's failure test)
 //   filter (nFilt per job)  filterDomains (Alg. 3), one domain word per wave,
 //                           residue word first, then a scan of active granules
 // Workgroup b starts with item b; when the grid is smaller than the item
@@ -590,7 +590,7 @@ __device__ void slot_reset_root(const TabDesc* T, SlotDesc* s, int serial, int t
 // ---------------------------------------------------------------------------
 // End of updateTable for a job (one workgroup): stable partition of the
 // active granule list (survivors first), new limit, trail top, FAIL when no
-// granule survives (Alg. 1 line 5).  Returns the job status.
+// granule survives (Alg. 1's failure test).  Returns the job status.
 // ---------------------------------------------------------------------------
 __device__ int finalize_update(const DevJob& J, Shared& sh, bool ldsFlags, int jobTrail) {
   const TabDesc* T = J.tab;
