@@ -292,7 +292,9 @@ int ct_model_pop(ct_model *m);
 
 /* Scheduling knob of the model's rounds: tables of at most solo_max_granules
  * granules run in one workgroup each, larger ones are split over workgroups
- * (see CT_SCHED_*); rounds_per_graph rounds are captured per graph.  The
+ * (see CT_SCHED_*); rounds_per_graph rounds are captured per graph.  A
+ * fixpoint's first launch is a one-round graph (most search steps converge in
+ * a round or two), the launches after it take rounds_per_graph rounds.  The
  * default is chosen by ct_model_autotune or is (4, 8). */
 int ct_model_set_schedule(ct_model *m, int32_t solo_max_granules, int32_t rounds_per_graph);
 

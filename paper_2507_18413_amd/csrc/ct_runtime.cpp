@@ -1315,7 +1315,8 @@ struct ct_model {
   std::vector<DevJob> hJobs;
   KArgs a{};
   int grid = 1;
-  hipGraphExec_t exec = nullptr;
+  hipGraphExec_t exec = nullptr;   // roundsPerGraph rounds
+  hipGraphExec_t exec1 = nullptr;  // one round: a fixpoint's first launch
   int32_t* pFlags = nullptr;   // pinned copy of M.flags
   int32_t* dStatus = nullptr;  // statuses of push/pop batches
 };
@@ -1335,7 +1336,9 @@ int model_alloc(ct_model* m, void** p, size_t bytes) {
 void model_free_device(ct_model* m) {
   if (m->stream) (void)hipStreamSynchronize(m->stream);
   if (m->exec) (void)hipGraphExecDestroy(m->exec);
+  if (m->exec1) (void)hipGraphExecDestroy(m->exec1);
   m->exec = nullptr;
+  m->exec1 = nullptr;
   for (void* p : m->blocks) (void)hipFree(p);
   m->blocks.clear();
   m->dStatus = nullptr;
@@ -1451,22 +1454,27 @@ int model_build(ct_model* m) {
   a.hostErr = m->q.hostErr;
   const int total = a.nUpd + a.nFilt;
   m->grid = std::max(1, std::min(total, propagate_max_grid()));
-  // capture rounds_per_graph rounds
-  hipGraph_t g = nullptr;
-  HIPCHK(hipStreamBeginCapture(m->stream, hipStreamCaptureModeThreadLocal));
-  for (int r = 0; r < m->roundsPerGraph; ++r) {
-    hipError_t e = launch_model_round(M, a, m->grid, m->stream);
-    if (e != hipSuccess) {
-      hipGraph_t dummy = nullptr;
-      (void)hipStreamEndCapture(m->stream, &dummy);
-      if (dummy) (void)hipGraphDestroy(dummy);
-      return fail(CT_E_DEVICE, "model round capture failed: %s", hipGetErrorString(e));
+  // capture a one-round graph (a fixpoint's first launch: most search steps
+  // converge in a round or two, and rounds after convergence cost launches)
+  // and a rounds_per_graph-round graph for the launches after it
+  for (int which = 0; which < 2; ++which) {
+    const int rounds = which == 0 ? 1 : m->roundsPerGraph;
+    hipGraph_t g = nullptr;
+    HIPCHK(hipStreamBeginCapture(m->stream, hipStreamCaptureModeThreadLocal));
+    for (int r = 0; r < rounds; ++r) {
+      hipError_t e = launch_model_round(M, a, m->grid, m->stream);
+      if (e != hipSuccess) {
+        hipGraph_t dummy = nullptr;
+        (void)hipStreamEndCapture(m->stream, &dummy);
+        if (dummy) (void)hipGraphDestroy(dummy);
+        return fail(CT_E_DEVICE, "model round capture failed: %s", hipGetErrorString(e));
+      }
     }
+    HIPCHK(hipStreamEndCapture(m->stream, &g));
+    hipError_t e = hipGraphInstantiate(which == 0 ? &m->exec1 : &m->exec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) return fail(CT_E_DEVICE, "hipGraphInstantiate failed: %s", hipGetErrorString(e));
   }
-  HIPCHK(hipStreamEndCapture(m->stream, &g));
-  hipError_t e = hipGraphInstantiate(&m->exec, g, nullptr, nullptr, 0);
-  (void)hipGraphDestroy(g);
-  if (e != hipSuccess) return fail(CT_E_DEVICE, "hipGraphInstantiate failed: %s", hipGetErrorString(e));
   m->built = true;
   return CT_OK;
 }
@@ -1614,15 +1622,14 @@ int ct_model_fixpoint(ct_model* m, const uint64_t* pool_in, uint64_t* pool_out, 
   if (!m->built && (rc = model_build(m))) return rc;
   ModelDesc& M = m->M;
   HIPCHK(hipMemcpyAsync(M.pool, pool_in, sizeof(uint64_t) * m->poolWords, hipMemcpyDeviceToDevice, m->stream));
-  {
-    int32_t fl[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    HIPCHK(hipMemcpyAsync(M.flags, fl, sizeof(fl), hipMemcpyHostToDevice, m->stream));
-    HIPCHK(launch_model_seed(M, m->stream));
-    HIPCHK(hipStreamSynchronize(m->stream));
-  }
+  // (eager, never inside the captured rounds)
+  HIPCHK(hipMemsetAsync(M.flags, 0, sizeof(int32_t) * 8, m->stream));
+  HIPCHK(launch_model_seed(M, m->stream));
   for (int replays = 0;; ++replays) {
     if (replays > 100000) return fail(CT_E_DEVICE, "fixpoint did not converge");
-    HIPCHK(hipGraphLaunch(m->exec, m->stream));
+    HIPCHK(hipGraphLaunch(replays == 0 ? m->exec1 : m->exec, m->stream));
+    // the pool is copied out with the flags: when they say done, it is there
+    HIPCHK(hipMemcpyAsync(pool_out, M.pool, sizeof(uint64_t) * m->poolWords, hipMemcpyDeviceToDevice, m->stream));
     HIPCHK(hipMemcpyAsync(m->pFlags, M.flags, sizeof(int32_t) * 8, hipMemcpyDeviceToHost, m->stream));
     hipError_t e = hipStreamSynchronize(m->stream);
     if (e != hipSuccess) {
@@ -1641,8 +1648,6 @@ int ct_model_fixpoint(ct_model* m, const uint64_t* pool_in, uint64_t* pool_out, 
   if (m->pFlags[1] == 2)
     return fail(CT_E_STATE, "a table of the model is in the failed state (pop it first)");
   if (m->pFlags[1]) return CT_FAIL;
-  HIPCHK(hipMemcpyAsync(pool_out, M.pool, sizeof(uint64_t) * m->poolWords, hipMemcpyDeviceToDevice, m->stream));
-  HIPCHK(hipStreamSynchronize(m->stream));
   return CT_OK;
 }
 
