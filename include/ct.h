@@ -286,15 +286,18 @@ int ct_model_layout(const ct_model *m, int32_t *pool_off, int32_t *pool_words);
 int ct_model_fixpoint(ct_model *m, const uint64_t *pool_in, uint64_t *pool_out, void *stream,
                       int64_t *n_props, int64_t *n_rounds);
 
-/* Push / pop one level on slot 0 of every table of the model (one launch). */
+/* Push / pop one level on slot 0 of every table of the model (one launch,
+ * queued on the model's stream; the next fixpoint reports a device-side error
+ * of it, and any other call on one of the tables first waits for it). */
 int ct_model_push(ct_model *m);
 int ct_model_pop(ct_model *m);
 
 /* Scheduling knob of the model's rounds: tables of at most solo_max_granules
  * granules run in one workgroup each, larger ones are split over workgroups
  * (see CT_SCHED_*); rounds_per_graph rounds are captured per graph.  A
- * fixpoint's first launch is a one-round graph (most search steps converge in
- * a round or two), the launches after it take rounds_per_graph rounds.  The
+ * fixpoint's first two launches are one-round graphs (most search steps
+ * converge in a round or two), the launches after them take rounds_per_graph
+ * rounds.  The
  * default is chosen by ct_model_autotune or is (4, 8). */
 int ct_model_set_schedule(ct_model *m, int32_t solo_max_granules, int32_t rounds_per_graph);
 

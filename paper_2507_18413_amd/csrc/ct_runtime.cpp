@@ -157,6 +157,7 @@ struct ct_table {
   int32_t* pStatus = nullptr;
   bool tailPending = false;  // a synchronous call returned before its kernel ended
   uint64_t batchMark = 0;    // last batch that named this table
+  hipStream_t pendStream = nullptr;  // a model's stream holding queued work on slot 0
   // optional kernel timing of synchronous launches, on the device clock
   // (no host events: they would add dispatch packets to every call)
   unsigned long long* dClock = nullptr;  // 5 words, see KArgs::clock
@@ -323,7 +324,7 @@ bool needs_prep(const DevJob& J) {
 }
 
 // Run one job synchronously on the table's stream.
-int quiesce(ct_table* T);
+int quiesce(ct_table* T, hipStream_t same = nullptr);
 
 int run_single(ct_table* T, DevJob& J, const uint64_t* dom_in_host) {
   int qrc = quiesce(T);
@@ -512,8 +513,15 @@ bool engine_wanted(const ct_table* T) {
 }
 
 // Any other use of a table's device state first ends its engine.
-int quiesce(ct_table* T) {
-  if (!T || !T->engOn) return CT_OK;
+// Before device work on T (from `same`, nullable): work a model queued on
+// slot 0 from another stream has ended, and the table's engine is stopped.
+int quiesce(ct_table* T, hipStream_t same) {
+  if (!T) return CT_OK;
+  if (T->pendStream && T->pendStream != same) {
+    HIPCHK(hipStreamSynchronize(T->pendStream));
+    T->pendStream = nullptr;
+  }
+  if (!T->engOn) return CT_OK;
   std::lock_guard<std::mutex> lk(g_engMu);
   return engine_stop(T);
 }
@@ -1081,7 +1089,7 @@ int ct_propagate_batch(const ct_job* jobs, int32_t n_jobs, void* stream_v, int32
     ct_table* T = jobs[j].table;
     if (T->batchMark == mark) continue;
     T->batchMark = mark;
-    int rc = quiesce(T);
+    int rc = quiesce(T, stream);
     if (rc) return rc;
     if (T->tailPending) {
       HIPCHK(hipStreamSynchronize(T->stream));
@@ -1454,9 +1462,9 @@ int model_build(ct_model* m) {
   a.hostErr = m->q.hostErr;
   const int total = a.nUpd + a.nFilt;
   m->grid = std::max(1, std::min(total, propagate_max_grid()));
-  // capture a one-round graph (a fixpoint's first launch: most search steps
-  // converge in a round or two, and rounds after convergence cost launches)
-  // and a rounds_per_graph-round graph for the launches after it
+  // capture a one-round graph (a fixpoint's first two launches: most search
+  // steps converge in a round or two, and rounds after convergence cost
+  // launches) and a rounds_per_graph-round graph for the launches after them
   for (int which = 0; which < 2; ++which) {
     const int rounds = which == 0 ? 1 : m->roundsPerGraph;
     hipGraph_t g = nullptr;
@@ -1488,8 +1496,16 @@ int model_sync_tables(ct_model* m) {
     int rc = check_poison(T);
     if (rc) return rc;
     if ((rc = flush_slot(T, 0))) return rc;
-    HIPCHK(hipStreamSynchronize(T->stream));
-    if (m->built && m->hJobs[c].depthAfter != T->slots[0].depth) {
+    if ((rc = quiesce(T, m->stream))) return rc;
+    // only a synchronous call's unfinished tail can still be on the table's
+    // stream (everything else on it is waited for where it is queued)
+    if (T->tailPending) {
+      HIPCHK(hipStreamSynchronize(T->stream));
+      T->tailPending = false;
+    }
+    // a round's job only asks whether levels exist (depth > 0: trail the
+    // words it changes), so the job array is sent again only when that flips
+    if (m->built && (m->hJobs[c].depthAfter > 0) != (T->slots[0].depth > 0)) {
       m->hJobs[c].depthAfter = T->slots[0].depth;
       changed = true;
     }
@@ -1515,10 +1531,13 @@ int model_push_pop(ct_model* m, bool push) {
     jobs[c].n_pop = push ? 0 : 1;
     jobs[c].n_push = push ? 1 : 0;
   }
+  // queued on the model's stream, ahead of the next fixpoint's rounds; a
+  // device-side error of this batch is reported by that fixpoint, and any
+  // other use of a table waits for it (quiesce)
   int rc = ct_propagate_batch(jobs.data(), nT, m->stream, m->dStatus);
   if (rc) return rc;
-  HIPCHK(hipStreamSynchronize(m->stream));
-  return ct_batch_status(m->stream);
+  for (ct_table* T : m->tabs) T->pendStream = m->stream;
+  return CT_OK;
 }
 
 }  // namespace
@@ -1565,7 +1584,13 @@ int ct_model_create(int32_t n_vars, const int32_t* dom_lo, const int32_t* dom_si
 
 void ct_model_destroy(ct_model* m) {
   if (!m) return;
-  model_free_device(m);
+  model_free_device(m);  // waits for the model's stream
+  {
+    // the live tables no longer wait for this stream
+    std::lock_guard<std::mutex> lk(g_engMu);
+    for (ct_table* T : m->tabs)
+      if (g_tables.count(T) && T->pendStream == m->stream) T->pendStream = nullptr;
+  }
   queue_free(m->q);
   if (m->pFlags) (void)hipHostFree(m->pFlags);
   if (m->stream) (void)hipStreamDestroy(m->stream);
@@ -1627,7 +1652,7 @@ int ct_model_fixpoint(ct_model* m, const uint64_t* pool_in, uint64_t* pool_out, 
   HIPCHK(launch_model_seed(M, m->stream));
   for (int replays = 0;; ++replays) {
     if (replays > 100000) return fail(CT_E_DEVICE, "fixpoint did not converge");
-    HIPCHK(hipGraphLaunch(replays == 0 ? m->exec1 : m->exec, m->stream));
+    HIPCHK(hipGraphLaunch(replays < 2 ? m->exec1 : m->exec, m->stream));
     // the pool is copied out with the flags: when they say done, it is there
     HIPCHK(hipMemcpyAsync(pool_out, M.pool, sizeof(uint64_t) * m->poolWords, hipMemcpyDeviceToDevice, m->stream));
     HIPCHK(hipMemcpyAsync(m->pFlags, M.flags, sizeof(int32_t) * 8, hipMemcpyDeviceToHost, m->stream));
@@ -1641,6 +1666,14 @@ int ct_model_fixpoint(ct_model* m, const uint64_t* pool_in, uint64_t* pool_out, 
       return fail(CT_E_DEVICE, "device-side error %d in a model round", *m->q.hostErr);
     }
     if (m->pFlags[1] || !m->pFlags[0]) break;
+  }
+  // the push / pop batches queued on the model's stream before these rounds
+  // have ended with them
+  for (ct_table* T : m->tabs)
+    if (T->pendStream == m->stream) T->pendStream = nullptr;
+  if ((rc = ct_batch_status(m->stream))) {
+    for (ct_table* T : m->tabs) T->poisoned = true;
+    return rc;
   }
   for (ct_table* T : m->tabs) T->slots[0].failed = 2;
   if (n_props) *n_props = m->pFlags[3];
