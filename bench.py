@@ -50,6 +50,8 @@ def parse():
     p.add_argument("--calibration-copy", type=int, default=0,
                    help="MiB copied once by torch before the timed run (counter calibration)")
     p.add_argument("--no-model", action="store_true")
+    p.add_argument("--no-wide", action="store_true")
+    p.add_argument("--no-driver", action="store_true")
     p.add_argument("--root-batch-only", action="store_true",
                    help="only the batched root recomputation of the 2,000-table model (profiling)")
     return p.parse_args()
@@ -806,10 +808,12 @@ def main():
                      "bytes_per_call": round(per_launch_bytes, 1)},
     }
     note(f"plain leg done: {value:.0f} propagations/s")
-    note("wide-scope leg")
-    out["wide_scope"] = wide_leg(seed, 300, not args.no_cpu_baseline)
-    note("search driver leg")
-    out["search_driver"] = solver_leg(seed, 400, not args.no_cpu_baseline)
+    if not args.no_wide:
+        note("wide-scope leg")
+        out["wide_scope"] = wide_leg(seed, 300, not args.no_cpu_baseline)
+    if not args.no_driver:
+        note("search driver leg")
+        out["search_driver"] = solver_leg(seed, 400, not args.no_cpu_baseline)
     if not args.no_nodes:
         note("search-node leg")
         out["batched_nodes"] = nodes_leg(seed, args.nodes, max(1, args.steps), 1)
