@@ -512,9 +512,9 @@ bool engine_wanted(const ct_table* T) {
   return T->engEligible && (T->cfg.schedule == CT_SCHED_AUTO || T->cfg.schedule == CT_SCHED_RESIDENT);
 }
 
-// Any other use of a table's device state first ends its engine.
-// Before device work on T (from `same`, nullable): work a model queued on
-// slot 0 from another stream has ended, and the table's engine is stopped.
+// Before any other use of a table's device state (from `same`, nullable):
+// work a model queued on slot 0 from another stream has ended, and the
+// table's engine is stopped.
 int quiesce(ct_table* T, hipStream_t same) {
   if (!T) return CT_OK;
   if (T->pendStream && T->pendStream != same) {

@@ -224,8 +224,17 @@ class Table:
     def propagate(self, dom_in, slot=0, want_ct=False, want_stats=False):
         if len(dom_in) != self.D:
             raise ValueError(f"dom_in has {len(dom_in)} words, the table {self.D}")
-        self._din[: self.D] = dom_in
-        self._dout[: self.D] = self._din[: self.D]
+        D = self.D
+        if not (want_ct or want_stats):
+            # the common call: one copy in, one out
+            self._din[:D] = dom_in
+            st = self._prop(self.h, slot, self._din_p, self._dout_p, None, None)
+            if st == E_DEVICE:
+                raise CTError(st, last_error())
+            # dom_out is written only on OK (the input is returned otherwise)
+            return st, (self._dout if st == OK else self._din)[:D].copy()
+        self._din[:D] = dom_in
+        self._dout[:D] = self._din[:D]
         ct = np.zeros(max(self.W, 1), np.uint64) if want_ct else None
         stats = ct_stats() if want_stats else None
         st = self._prop(self.h, int(slot), self._din_p, self._dout_p, _p(ct),
