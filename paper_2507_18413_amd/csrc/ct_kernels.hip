@@ -1464,6 +1464,12 @@ __global__ void __launch_bounds__(BLOCK) root_finish_kernel(KArgs a) {
   const DevJob J = a.jobs[blockIdx.x];
   const TabDesc* T = J.tab;
   SlotDesc* s = J.slot;
+  // the filter's first two words per wave: their residue loads are in
+  // flight during the validation and the partition (their addresses stay in
+  // the table whatever the input)
+  const int D = T->D;
+  const FilterPre pre0 = filter_pre(a, J, min(wv, D - 1));
+  const FilterPre pre1 = filter_pre(a, J, min(wv + WAVES, D - 1));
   if (threadIdx.x == 0) {
     shStray = 0;
     shRows = 0;
@@ -1519,7 +1525,10 @@ __global__ void __launch_bounds__(BLOCK) root_finish_kernel(KArgs a) {
     st = shSurv ? ST_OK : ST_FAIL;
     if (st == ST_OK) {
       unsigned long long cnt[3] = {0, 0, 0};
-      for (int q = wv; q < T->D; q += WAVES) filter_word(a, J, q, 0, shSurv, s->idx[0], cnt);
+      for (int q = wv, k = 0; q < D; q += WAVES, ++k) {
+        if (k < 2) filter_word(a, J, q, 0, shSurv, s->idx[0], cnt, k == 0 ? pre0 : pre1);
+        else filter_word(a, J, q, 0, shSurv, s->idx[0], cnt);
+      }
       add_filter_stats(s, cnt);
     }
   }

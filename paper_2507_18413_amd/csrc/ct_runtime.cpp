@@ -7,6 +7,7 @@
 #include <hip/hip_runtime_api.h>
 
 #include <algorithm>
+#include <array>
 #include <atomic>
 #include <chrono>
 #include <cstdarg>
@@ -127,10 +128,22 @@ std::map<hipStream_t, QueueCtx*> g_queues;
 }  // namespace
 
 struct ct_table {
+  // the fields every call reads first, together (a batch of thousands of
+  // jobs touches them for every table)
   int n = 0;
   int64_t t = 0, W = 0, stride = 0;
   int rows = 0, D = 0, nGran = 0;
   ct_config cfg{};
+  TabDesc* dTab = nullptr;
+  std::vector<SlotHost> slots;
+  int32_t serialCounter = 1;
+  bool poisoned = false;
+  bool tailPending = false;  // a synchronous call returned before its kernel ended
+  bool engEligible = false, engOn = false;
+  int rootFailed = 0;
+  hipStream_t stream = nullptr;
+  uint64_t batchMark = 0;    // last batch that named this table
+  hipStream_t pendStream = nullptr;  // a model's stream holding queued work on slot 0
   std::vector<int32_t> lo, dsz, domOff;
   std::vector<VarDesc> vars;
   std::vector<int32_t> wordVar;
@@ -139,31 +152,21 @@ struct ct_table {
   VarDesc* dVars = nullptr;
   int32_t* dWordVar = nullptr;
   int32_t* dLo = nullptr;
-  TabDesc* dTab = nullptr;
   TabDesc hTab{};
   SlotDesc* dRoot = nullptr;
   SlotDesc hRoot{};
   std::vector<void*> blocks;  // device allocations to free
-  std::vector<SlotHost> slots;
-  int32_t serialCounter = 1;
-  bool poisoned = false;
-  int rootFailed = 0;
-  hipStream_t stream = nullptr;
   QueueCtx q;
   // pinned staging of the synchronous calls
   uint64_t* pDomOut = nullptr;  // D words
   uint64_t* pDomIn = nullptr;   // D words (used when D > INLINE_WORDS)
   uint64_t* pCt = nullptr;      // W words (lazily)
   int32_t* pStatus = nullptr;
-  bool tailPending = false;  // a synchronous call returned before its kernel ended
-  uint64_t batchMark = 0;    // last batch that named this table
-  hipStream_t pendStream = nullptr;  // a model's stream holding queued work on slot 0
   // optional kernel timing of synchronous launches, on the device clock
   // (no host events: they would add dispatch packets to every call)
   unsigned long long* dClock = nullptr;  // 5 words, see KArgs::clock
   bool timing = false;
-  // resident engine of slot 0 (see ct_engine.hip)
-  bool engEligible = false, engOn = false;
+  // resident engine of slot 0 (see ct_engine.hip; engEligible, engOn above)
   size_t engLds = 0;
   hipStream_t engStream = nullptr;
   EngCmd* pCmd = nullptr;   // coherent pinned mailbox
@@ -1187,14 +1190,21 @@ int ct_propagate_batch(const ct_job* jobs, int32_t n_jobs, void* stream_v, int32
   // first (their tasks are the longest)
   std::vector<int32_t> rootTasks;
   if (roots) {
-    std::vector<int> order(n_jobs);
-    for (int j = 0; j < n_jobs; ++j) order[j] = j;
-    std::stable_sort(order.begin(), order.end(),
-                     [&](int x, int y) { return jobs[x].table->rows > jobs[y].table->rows; });
-    for (int j : order)
-      for (int g = 0; g < jobs[j].table->nGran; g += WAVES) {
-        rootTasks.push_back(j);
-        rootTasks.push_back(g);
+    // (rows, granules, job) read once per table, then sorted as plain data
+    std::vector<std::array<int32_t, 3>> key(n_jobs);
+    size_t nTasks = 0;
+    for (int j = 0; j < n_jobs; ++j) {
+      const ct_table* T = jobs[j].table;
+      key[j] = {-T->rows, -T->nGran, j};
+      nTasks += (size_t)(T->nGran + WAVES - 1) / WAVES;
+    }
+    std::sort(key.begin(), key.end());
+    rootTasks.resize(2 * nTasks);
+    size_t at = 0;
+    for (const auto& k : key)
+      for (int g = 0; g < -k[1]; g += WAVES) {
+        rootTasks[at++] = k[2];
+        rootTasks[at++] = g;
       }
   }
   // stage to the device (the root tasks start at an even offset: int pairs)
