@@ -29,6 +29,7 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 LDS_PEAK_GBS = 256 * 128 * 2.4  # 256 CUs x 128 B/clock x 2.4 GHz
+MAX_DEPTH_SERVE = 64  # push levels per serving slot
 
 
 def parse():
@@ -556,7 +557,7 @@ def serve_leg(tables_spec, seed, rate, n_requests, n_searches, budget, sample_ch
     from paper_2507_18413_amd import ct
     from paper_2507_18413_amd import workloads as W
     t0 = time.perf_counter()
-    tabs = [ct.Table(sp.tuples, sp.lo, sp.dsizes, max_depth=64) for sp in tables_spec]
+    tabs = [ct.Table(sp.tuples, sp.lo, sp.dsizes, max_depth=MAX_DEPTH_SERVE) for sp in tables_spec]
     build_s = time.perf_counter() - t0
     rng = W.rng_for(seed, 5, 777)
     # per-table pools of deltas: U{1..4} variables, ceil(5 %) of each one's
@@ -573,7 +574,7 @@ def serve_leg(tables_spec, seed, rate, n_requests, n_searches, budget, sample_ch
         pools.append(pool)
     srv = ct.Server(mem_budget=budget, max_batch=1024, streams=2)
     search_tab = rng.integers(0, len(tabs), size=n_searches)
-    sids = [srv.add_search(tabs[int(c)], max_depth=64) for c in search_tab]
+    sids = [srv.add_search(tabs[int(c)], max_depth=MAX_DEPTH_SERVE) for c in search_tab]
     depth = np.zeros(n_searches, np.int64)
     count = np.zeros(n_searches, np.int64)
     length = rng.integers(50, 201, size=n_searches)
@@ -606,6 +607,10 @@ def serve_leg(tables_spec, seed, rate, n_requests, n_searches, budget, sample_ch
             else:
                 n_pop = 1 if failed[s] else (int(rng.integers(1, depth[s] + 1)) if count[s] % 10 == 0 and depth[s] else 0)
                 push = 1
+                # the slots hold max_depth levels: a search that would pass
+                # it backtracks to half of it first
+                if depth[s] - n_pop + push > MAX_DEPTH_SERVE:
+                    n_pop = depth[s] - MAX_DEPTH_SERVE // 2
             depth[s] += push - n_pop
             failed[s] = False
             rem = pools[c][int(rng.integers(0, 256))]
