@@ -18,6 +18,7 @@ a fixpoint per search step, batched vs one launch per table vs the CPU
 oracle), and the CPU oracle timed on a bounded sample of the same script.
 """
 import argparse
+import gc
 import json
 import os
 import sys
@@ -817,6 +818,14 @@ def main():
                      "bytes_per_call": round(per_launch_bytes, 1)},
     }
     note(f"plain leg done: {value:.0f} propagations/s")
+    if serve_spec is not None:
+        # first of the other legs: its tables (gigabytes of host arrays) are
+        # released before the batched legs time their host-side issue
+        note("serving leg")
+        out["serving"] = serve_leg(serve_spec, seed, args.serve_rate, args.serve_requests, 512,
+                                   args.serve_budget, 0 if args.no_cpu_baseline else 8)
+        serve_spec = None
+        gc.collect()
     if not args.no_wide:
         note("wide-scope leg")
         out["wide_scope"] = wide_leg(seed, 300, not args.no_cpu_baseline)
@@ -829,11 +838,6 @@ def main():
     if not args.no_model:
         note("multi-table model leg")
         out["batched_model"] = model_leg(seed, args.model_steps, 20, not args.no_cpu_baseline)
-    if serve_spec is not None:
-        note("serving leg")
-        out["serving"] = serve_leg(serve_spec, seed, args.serve_rate, args.serve_requests, 512,
-                                   args.serve_budget, 0 if args.no_cpu_baseline else 8)
-        del serve_spec
     if not args.no_cpu_baseline:
         note("oracle on the host cores")
         cps, cprops, cel, passes = cpu_baseline(spec, script, args.cpu_seconds)
