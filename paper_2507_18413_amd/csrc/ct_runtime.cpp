@@ -95,7 +95,10 @@ struct QueueCtx {
   hipEvent_t staged[2] = {nullptr, nullptr};
   size_t capStage = 0;
   int turn = 0;
+  // host scratch of a batch, kept between batches (no allocation per call)
   std::vector<DevJob> hJobs;
+  std::vector<int32_t> updOff, filtOff, prep, rootTasks;
+  std::vector<std::array<int32_t, 3>> rootKey;
   // search-node schedule scratch (node records | granule flags)
   void* dNodes = nullptr;
   size_t capNodes = 0;
@@ -1132,7 +1135,12 @@ int ct_propagate_batch(const ct_job* jobs, int32_t n_jobs, void* stream_v, int32
   }
   // job descriptors
   q->hJobs.resize(n_jobs);
-  std::vector<int32_t> updOff(n_jobs + 1, 0), filtOff(n_jobs + 1, 0), prep;
+  std::vector<int32_t>& updOff = q->updOff;
+  std::vector<int32_t>& filtOff = q->filtOff;
+  std::vector<int32_t>& prep = q->prep;
+  updOff.assign(n_jobs + 1, 0);
+  filtOff.assign(n_jobs + 1, 0);
+  prep.clear();
   for (int j = 0; j < n_jobs; ++j) {
     const ct_job& cj = jobs[j];
     ct_table* T = cj.table;
@@ -1188,10 +1196,12 @@ int ct_propagate_batch(const ct_job* jobs, int32_t n_jobs, void* stream_v, int32
   }
   // root streams: WAVES granules per task, tables with the most support rows
   // first (their tasks are the longest)
-  std::vector<int32_t> rootTasks;
+  std::vector<int32_t>& rootTasks = q->rootTasks;
+  rootTasks.clear();
   if (roots) {
     // (rows, granules, job) read once per table, then sorted as plain data
-    std::vector<std::array<int32_t, 3>> key(n_jobs);
+    std::vector<std::array<int32_t, 3>>& key = q->rootKey;
+    key.resize(n_jobs);
     size_t nTasks = 0;
     for (int j = 0; j < n_jobs; ++j) {
       const ct_table* T = jobs[j].table;
