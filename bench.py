@@ -708,6 +708,10 @@ def note(msg):
 
 def main():
     args = parse()
+    # the cyclic garbage collector runs between the legs only: a full
+    # collection inside a timed loop (tens of ms once the run holds many
+    # Python objects) would be charged to the library
+    gc.disable()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the library runs "
               f"on a single MI355X; sharding over several GPUs is a design, not a build)", file=sys.stderr)
@@ -827,15 +831,19 @@ def main():
         serve_spec = None
         gc.collect()
     if not args.no_wide:
+        gc.collect()
         note("wide-scope leg")
         out["wide_scope"] = wide_leg(seed, 300, not args.no_cpu_baseline)
     if not args.no_driver:
+        gc.collect()
         note("search driver leg")
         out["search_driver"] = solver_leg(seed, 400, not args.no_cpu_baseline)
     if not args.no_nodes:
+        gc.collect()
         note("search-node leg")
         out["batched_nodes"] = nodes_leg(seed, args.nodes, max(1, args.steps), 1)
     if not args.no_model:
+        gc.collect()
         note("multi-table model leg")
         out["batched_model"] = model_leg(seed, args.model_steps, 20, not args.no_cpu_baseline)
     if not args.no_cpu_baseline:
