@@ -841,7 +841,7 @@ def main():
     if not args.no_nodes:
         gc.collect()
         note("search-node leg")
-        out["batched_nodes"] = nodes_leg(seed, args.nodes, max(1, args.steps), 1)
+        out["batched_nodes"] = nodes_leg(seed, args.nodes, max(20, args.steps), 1)
     if not args.no_model:
         gc.collect()
         note("multi-table model leg")

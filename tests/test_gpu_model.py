@@ -154,3 +154,33 @@ def test_scaled_multi_table_root_and_steps():
         M.pop()
         for o in ots:
             o.pop()
+
+
+def test_queued_push_pop_seen_by_direct_table_use():
+    """The model's push and pop are queued on its stream without waiting; a
+    direct call on one of its tables right after must see them done."""
+    spec = random_model(9, 30, 20, (8, 40), (2, 4), (500, 4000))
+    say("model push / pop queued, then direct table use")
+    lay, M, gts, ots = build(spec)
+    pool = lay.full()
+    st, _, _ = M.fixpoint(dev(pool), out := dev(pool))
+    assert st == ct.OK
+    before = [g.state(0) for g in gts]
+    rng = W.rng_for(9, 303, 0)
+    for trial in range(10):
+        M.push()
+        new = W.pick_fraction_removal(rng, lay, host(out).copy(), 0.3, (3, 6))
+        st, _, _ = M.fixpoint(dev(new), dev(new))
+        M.pop()  # queued: the table calls below must wait for it
+        for g, (d0, c0) in zip(gts, before):
+            d, c = g.state(0)
+            assert (d == d0).all() and (c == c0).all(), trial
+    # a direct propagate right after a queued push lands on the pushed level
+    M.push()
+    g = gts[0]
+    sub = g.domains(0).copy()
+    s2, d2 = g.propagate(sub)
+    assert s2 == ct.OK
+    assert g.pop(0) == ct.OK
+    d, c = g.state(0)
+    assert (d == before[0][0]).all() and (c == before[0][1]).all()
