@@ -53,6 +53,7 @@ def parse():
                    help="MiB copied once by torch before the timed run (counter calibration)")
     p.add_argument("--no-model", action="store_true")
     p.add_argument("--no-wide", action="store_true")
+    p.add_argument("--no-split", action="store_true")
     p.add_argument("--no-driver", action="store_true")
     p.add_argument("--root-batch-only", action="store_true",
                    help="only the batched root recomputation of the 2,000-table model (profiling)")
@@ -270,12 +271,14 @@ def wide_leg(seed, n_calls, cpu):
     props = replay(table, script, lat)
     el = time.perf_counter() - t0
     lat_us = np.array(lat) * 1e6
+    split = split_leg(table, script, 1)
     out = {"workload": "arity 100, domains U{64..160}, 10,000 distinct uniform tuples "
                        f"({table.rows} support rows of {table.W} words, {table.D} domain words); "
                        f"{n_calls} calls as in the plain leg",
            "props_per_s": round(props / el, 1),
            "latency_us": {"p50": round(float(np.percentile(lat_us, 50)), 2),
-                          "p99": round(float(np.percentile(lat_us, 99)), 2)}}
+                          "p99": round(float(np.percentile(lat_us, 99)), 2)},
+           "split_propagators": split}
     if cpu:
         from oracle import oracle as O
         o = O.OracleTable(spec.tuples, spec.lo, spec.dsizes)
@@ -293,6 +296,28 @@ def wide_leg(seed, n_calls, cpu):
         t0 = time.perf_counter()
         oprops = replay(OracleSut(), script)
         out["oracle_props_per_s"] = round(oprops / (time.perf_counter() - t0), 1)
+    return out
+
+
+def split_leg(table, script, passes):
+    """The same call script through the two split propagators of the table
+    (updateTable or filterDomains on the device, the other procedure on the
+    host; one copy each way per call)."""
+    import numpy as np
+    from paper_2507_18413_amd import ct
+    out = {}
+    for name, mode in (("update_on_device", ct.SPLIT_UPDATE), ("filter_on_device", ct.SPLIT_FILTER)):
+        sp = ct.SplitPropagator(table, mode)
+        replay(sp, script)
+        lat = []
+        t0 = time.perf_counter()
+        props = sum(replay(sp, script, lat) for _ in range(passes))
+        el = time.perf_counter() - t0
+        lat_us = np.array(lat) * 1e6
+        out[name] = {"props_per_s": round(props / el, 1),
+                     "latency_us": {"p50": round(float(np.percentile(lat_us, 50)), 2),
+                                    "p99": round(float(np.percentile(lat_us, 99)), 2)}}
+        sp.close()
     return out
 
 
@@ -822,6 +847,9 @@ def main():
                      "bytes_per_call": round(per_launch_bytes, 1)},
     }
     note(f"plain leg done: {value:.0f} propagations/s")
+    if not args.no_split:
+        note("split propagators on the plain script")
+        out["split_propagators"] = split_leg(table, script, max(1, args.steps))
     if serve_spec is not None:
         # first of the other legs: its tables (gigabytes of host arrays) are
         # released before the batched legs time their host-side issue

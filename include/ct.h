@@ -375,6 +375,39 @@ int ct_server_stats(ct_server *s, int64_t *out6);
 /* The steady clock the timestamps use (seconds). */
 double ct_server_now(void);
 
+/*
+ * Split propagators -- the two variants of Sec. 4 that run only one of CT's
+ * procedures on the device (Sec. 4.1 and 4.2), for comparison with
+ * ct_propagate, which runs all of enforceGAC (Alg. 1) there.  A split
+ * propagator starts from the table's root state, keeps its own currTable,
+ * domains and levels on the host (the table's slots are untouched) and uses
+ * the table's device supports, which must outlive it.
+ *   CT_SPLIT_UPDATE: updateTable's mask (Alg. 2) on the device; the host
+ *     ANDs it into currTable and runs filterDomains (Alg. 3, residues).
+ *   CT_SPLIT_FILTER: updateTable on the host; filterDomains on the device
+ *     over the words of the variables with more than one value.
+ * Each call is one host-to-device copy, one launch and one device-to-host
+ * copy, synchronous.  ct_split_propagate has ct_propagate's contract (host
+ * pointers; dom_in a subset of the current domains, no stray bits; CT_OK
+ * with the GAC domains and currTable, CT_FAIL with dom_out untouched and
+ * ct_out zeroed and the propagator failed until popped; CT_E_NOT_SUBSET /
+ * CT_E_INVALID / CT_E_STATE change nothing; CT_E_DEVICE poisons it) and the
+ * same results; the table's branch policy applies.  push / pop save and
+ * restore the whole host state (no depth limit); push on a failed
+ * propagator and pop at depth 0 return CT_E_STATE.  ct_split_create returns
+ * CT_E_INVALID for an unknown mode, CT_E_NOMEM when the host copy of the
+ * supports (rows x W words) or a buffer cannot be allocated.
+ */
+#define CT_SPLIT_UPDATE 1
+#define CT_SPLIT_FILTER 2
+typedef struct ct_split ct_split;
+int ct_split_create(ct_table *t, int32_t mode, ct_split **out);
+int ct_split_propagate(ct_split *s, const uint64_t *dom_in, uint64_t *dom_out, uint64_t *ct_out);
+int ct_split_push(ct_split *s);
+int ct_split_pop(ct_split *s);
+/* Frees the propagator; NULL is ignored. */
+void ct_split_destroy(ct_split *s);
+
 /* Synchronizes `stream` and reports whether a batch launched on it hit a
  * device-side error (a bounded wait that expired): CT_OK or CT_E_DEVICE (the
  * error is cleared; the slots of the affected jobs are undefined). */

@@ -237,4 +237,15 @@ struct EngDesc {
   int32_t startSeq, pad;    // the last call seq already answered
 };
 
+// Read-only view of a table's immutable parts (host code only): device
+// supports, layout, branch policy and the device root state.
+struct TableView {
+  const uint64_t* S;        // device, rows x stride
+  int64_t stride, W;
+  int32_t n, D, rows, rootFailed, branchPolicy, pad;
+  const VarDesc* vars;      // host, n
+  const uint64_t* rootCt;   // device, W words
+  const uint64_t* rootDom;  // device, D words
+};
+
 }  // namespace ctk

@@ -1316,6 +1316,25 @@ int root_domains(ct_table* T, uint64_t* out) {
 }
 
 void set_error(const char* msg) { g_err = msg; }
+
+// Read-only view of a table for the split propagators (ct_split.cpp): the
+// supports, the layout and the root state never change after ct_create.
+int table_view(const ct_table* T, TableView* v) {
+  int rc = check_poison(T);
+  if (rc) return rc;
+  v->S = T->dS;
+  v->stride = T->stride;
+  v->W = T->W;
+  v->n = T->n;
+  v->D = T->D;
+  v->rows = T->rows;
+  v->rootFailed = T->rootFailed;
+  v->branchPolicy = T->cfg.branch_policy;
+  v->vars = T->vars.data();
+  v->rootCt = T->hRoot.ct;
+  v->rootDom = T->hRoot.lastDom;
+  return CT_OK;
+}
 }  // namespace ctk
 
 // ===========================================================================

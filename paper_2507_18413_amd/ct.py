@@ -22,6 +22,7 @@ E_INVALID, E_NOT_SUBSET, E_STATE, E_NOMEM, E_DEVICE = -1, -2, -3, -4, -5
 BRANCH_AUTO, BRANCH_RESET, BRANCH_INCREMENTAL = 0, 1, 2
 SCHED_AUTO, SCHED_SOLO, SCHED_SPLIT, SCHED_NODES, SCHED_RESIDENT = 0, 1, 2, 3, 4
 JOB_PROPAGATE, JOB_FROM_ROOT, JOB_ROOT = 1, 2, 4
+SPLIT_UPDATE, SPLIT_FILTER = 1, 2
 
 
 class CTError(RuntimeError):
@@ -136,6 +137,11 @@ def lib():
             "ct_server_poll": ([P, P, I32, I32], C.c_int),
             "ct_server_stats": ([P, P], C.c_int),
             "ct_server_now": ([], C.c_double),
+            "ct_split_create": ([P, I32, C.POINTER(P)], C.c_int),
+            "ct_split_propagate": ([P, P, P, P], C.c_int),
+            "ct_split_push": ([P], C.c_int),
+            "ct_split_pop": ([P], C.c_int),
+            "ct_split_destroy": ([P], None),
             "ct_last_error": ([], C.c_char_p),
             "ct_quiesce": ([], C.c_int),
         }
@@ -305,6 +311,56 @@ def batch_status(stream=None):
     st = lib().ct_batch_status(s)
     if st < 0:
         raise CTError(st, last_error())
+
+
+class SplitPropagator:
+    """One of the two split propagators over a table (updateTable or
+    filterDomains on the device, the other procedure on the host); same
+    calls and results as ``Table.propagate`` / ``push`` / ``pop``."""
+
+    def __init__(self, table: Table, mode: int):
+        L = lib()
+        h = C.c_void_p()
+        st = L.ct_split_create(table.h, int(mode), C.byref(h))
+        if st < 0:
+            raise CTError(st, last_error())
+        self.h = h
+        self.table = table  # the supports stay on the table's device buffers
+        self.D, self.W = table.D, table.W
+        self._din = np.zeros(max(self.D, 1), np.uint64)
+        self._dout = np.zeros(max(self.D, 1), np.uint64)
+        self._din_p = self._din.__array_interface__["data"][0]
+        self._dout_p = self._dout.__array_interface__["data"][0]
+        self._prop = L.ct_split_propagate
+
+    def close(self):
+        if getattr(self, "h", None) is not None and self.h.value is not None:
+            lib().ct_split_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def propagate(self, dom_in, want_ct=False):
+        if len(dom_in) != self.D:
+            raise ValueError(f"dom_in has {len(dom_in)} words, the table {self.D}")
+        D = self.D
+        self._din[:D] = dom_in
+        ct = np.zeros(max(self.W, 1), np.uint64) if want_ct else None
+        st = self._prop(self.h, self._din_p, self._dout_p, _p(ct))
+        if st == E_DEVICE:
+            raise CTError(st, last_error())
+        dom = (self._dout if st == OK else self._din)[:D].copy()
+        return (st, dom, ct[: self.W]) if want_ct else (st, dom)
+
+    def push(self):
+        return lib().ct_split_push(self.h)
+
+    def pop(self):
+        return lib().ct_split_pop(self.h)
 
 
 class Batch:
