@@ -220,11 +220,13 @@ int ct_split_create(ct_table* t, int32_t mode, ct_split** out) {
     }                                                                                         \
   } while (0)
   CREATECHK(hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking));
+  // blocking copies into the (pageable) host vectors: each has landed when
+  // the call returns
   if (W > 0 && v.rows > 0)
-    CREATECHK(hipMemcpy2DAsync(s->S.data(), sizeof(uint64_t) * W, v.S, sizeof(uint64_t) * v.stride,
-                               sizeof(uint64_t) * W, v.rows, hipMemcpyDeviceToHost, s->stream));
-  if (W > 0) CREATECHK(hipMemcpyAsync(s->ct.data(), v.rootCt, sizeof(uint64_t) * W, hipMemcpyDeviceToHost, s->stream));
-  CREATECHK(hipMemcpyAsync(s->lastDom.data(), v.rootDom, sizeof(uint64_t) * D, hipMemcpyDeviceToHost, s->stream));
+    CREATECHK(hipMemcpy2D(s->S.data(), sizeof(uint64_t) * W, v.S, sizeof(uint64_t) * v.stride,
+                          sizeof(uint64_t) * W, v.rows, hipMemcpyDeviceToHost));
+  if (W > 0) CREATECHK(hipMemcpy(s->ct.data(), v.rootCt, sizeof(uint64_t) * W, hipMemcpyDeviceToHost));
+  CREATECHK(hipMemcpy(s->lastDom.data(), v.rootDom, sizeof(uint64_t) * D, hipMemcpyDeviceToHost));
   // stage: update variant = segment starts + row list in, mask out;
   //        filter variant = currTable + domains + word list in, domains out
   const size_t upd = align16(sizeof(int32_t) * (v.n + 1)) + align16(sizeof(int32_t) * (v.rows + 1)) +
@@ -240,11 +242,10 @@ int ct_split_create(ct_table* t, int32_t mode, ct_split** out) {
       for (int k = 0; k < x.domWords; ++k) wordRow[x.domOff + k] = x.rowStart + 64 * k;
     CREATECHK(hipMalloc((void**)&s->dWordRow, sizeof(int32_t) * std::max<int64_t>(D, 1)));
     CREATECHK(hipMalloc((void**)&s->dRes, sizeof(int32_t) * std::max(v.rows, 1)));
-    CREATECHK(hipMemcpyAsync(s->dWordRow, wordRow.data(), sizeof(int32_t) * D, hipMemcpyHostToDevice, s->stream));
-    CREATECHK(hipMemsetAsync(s->dRes, 0, sizeof(int32_t) * std::max(v.rows, 1), s->stream));
-    CREATECHK(hipStreamSynchronize(s->stream));  // wordRow is a local
+    CREATECHK(hipMemcpy(s->dWordRow, wordRow.data(), sizeof(int32_t) * D, hipMemcpyHostToDevice));
+    CREATECHK(hipMemset(s->dRes, 0, sizeof(int32_t) * std::max(v.rows, 1)));
   }
-  CREATECHK(hipStreamSynchronize(s->stream));
+  CREATECHK(hipStreamSynchronize(nullptr));  // the memset above
 #undef CREATECHK
   for (int i = 0; i < v.n; ++i) s->lastSizes[i] = s->var_size(s->lastDom.data(), i);
   s->failed = v.rootFailed != 0;

@@ -145,3 +145,32 @@ def test_split_errors_and_table_untouched(mode):
     with pytest.raises(ct.CTError):
         ct.SplitPropagator(G, 7)
     S.close()
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_split_created_right_after_engine_calls(mode):
+    """A split propagator created on a table whose resident engine has just
+    served calls (still alive, holding slot 0 in LDS) starts from the root
+    and matches the oracle from its first call: its host copies of the
+    supports and of the root state have landed before the first call."""
+    spec = W.large_table(t=20_000)
+    lay = spec.layout()
+    G = ct.Table(spec.tuples, spec.lo, spec.dsizes)
+    Ot = O.OracleTable(spec.tuples, spec.lo, spec.dsizes)
+    rng = W.rng_for(W.DEFAULT_SEED, 206, mode)
+    root = Ot.domains()
+    for _ in range(20):  # engine calls on slot 0, each from the root and popped
+        assert G.push() == ct.OK
+        G.propagate(W.pick_fraction_removal(rng, lay, root))
+        assert G.pop() == ct.OK
+    say("split created after engine calls, mode", mode, "resident", G.resident)
+    S = ct.SplitPropagator(G, mode)
+    for call in range(50):
+        dom_in = W.pick_fraction_removal(rng, lay, Ot.domains())
+        gs, gd, gc = S.propagate(dom_in, want_ct=True)
+        os_, od, oc = Ot.propagate(dom_in, want_ct=True)
+        assert gs == os_, call
+        if os_ != O.OK:
+            break
+        assert (gd == od).all() and (gc == oc).all(), call
+    S.close()
