@@ -308,15 +308,33 @@ def split_leg(table, script, passes):
     out = {}
     for name, mode in (("update_on_device", ct.SPLIT_UPDATE), ("filter_on_device", ct.SPLIT_FILTER)):
         sp = ct.SplitPropagator(table, mode)
-        replay(sp, script)
+        bad = []
+
+        class Counted:
+            """Counts error statuses (a propagator that went wrong answers
+            every later call with an error, quickly)."""
+
+            def propagate(self, d):
+                st = sp.propagate(d)[0]
+                if st < 0:
+                    bad.append(st)
+
+            def push(self):
+                sp.push()
+
+            def pop(self):
+                sp.pop()
+
+        replay(Counted(), script)
         lat = []
         t0 = time.perf_counter()
-        props = sum(replay(sp, script, lat) for _ in range(passes))
+        props = sum(replay(Counted(), script, lat) for _ in range(passes))
         el = time.perf_counter() - t0
         lat_us = np.array(lat) * 1e6
         out[name] = {"props_per_s": round(props / el, 1),
                      "latency_us": {"p50": round(float(np.percentile(lat_us, 50)), 2),
-                                    "p99": round(float(np.percentile(lat_us, 99)), 2)}}
+                                    "p99": round(float(np.percentile(lat_us, 99)), 2)},
+                     "error_statuses": len(bad)}
         sp.close()
     return out
 

@@ -7,13 +7,16 @@
 // the supports: a sparse bitset (the currTable words and the index of the
 // non-zero ones, compacted after every variable's update, Alg. 2) for the
 // filter variant, filterDomains with host residues (Alg. 3) for the update
-// variant.  A call makes one host-to-device copy, one launch and one
-// device-to-host copy from and to pinned buffers, then waits: the round trip
-// that the paper measures for these variants (Sec. 5.2).  Backtracking
-// saves the host state whole at every push.
+// variant.  A call makes one host-to-device copy (blocking: the inputs have
+// landed before the launch) and one launch whose workgroups write their
+// results into coherent pinned host memory and then each publish the call's
+// sequence number; the host waits for the stream and for every flag: the
+// round trip that the paper measures for these variants (Sec. 5.2).  Backtracking saves the host state
+// whole at every push.
 #include <hip/hip_runtime_api.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -27,11 +30,14 @@
 namespace ctk {
 int table_view(const ct_table* t, TableView* v);
 void set_error(const char* msg);
+int split_update_grid(int64_t W);
+int split_filter_grid(int nWords);
 hipError_t launch_split_update(const uint64_t* S, int64_t stride, int64_t W, const int32_t* segBegin,
-                               int nSeg, const int32_t* rowList, uint64_t* mask, hipStream_t stream);
+                               int nSeg, const int32_t* rowList, uint64_t* mask, int32_t* flags, int32_t seq,
+                               hipStream_t stream);
 hipError_t launch_split_filter(const uint64_t* S, int64_t stride, int64_t W, const uint64_t* ct,
-                               uint64_t* dom, const int32_t* words, int nWords, const int32_t* wordRow,
-                               int32_t* res, hipStream_t stream);
+                               const uint64_t* dom, const int32_t* words, int nWords, const int32_t* wordRow,
+                               int32_t* res, uint64_t* domOut, int32_t* flags, int32_t seq, hipStream_t stream);
 }  // namespace ctk
 
 using namespace ctk;
@@ -72,7 +78,7 @@ struct ct_split {
   int mode = 0;
   TableView v{};
   std::vector<VarDesc> vars;
-  std::vector<uint64_t> S;  // rows x W, host copy of the supports
+  uint64_t* S = nullptr;  // rows x W, host copy of the supports (pinned: copied without staging)
   // host CT state
   std::vector<uint64_t> ct, lastDom;
   std::vector<int32_t> lastSizes, nz, res;  // nz: indexes of the non-zero currTable words
@@ -84,9 +90,16 @@ struct ct_split {
   std::vector<char> sVal, sSup;
   // device
   hipStream_t stream = nullptr;
-  char* dStage = nullptr;  // one call's inputs and outputs
+  char* dStage = nullptr;  // one call's inputs
   char* pStage = nullptr;  // pinned mirror
   size_t stageBytes = 0;
+  // results: written by the kernel straight into coherent pinned memory,
+  // then one flag per workgroup set to the call's sequence number
+  uint64_t* pOut = nullptr;
+  uint64_t* dOut = nullptr;  // device address of pOut
+  int32_t* pFlags = nullptr;
+  int32_t* dFlags = nullptr;
+  int32_t seq = 0;
   int32_t* dWordRow = nullptr;
   int32_t* dRes = nullptr;
 
@@ -96,6 +109,9 @@ struct ct_split {
     if (dWordRow) (void)hipFree(dWordRow);
     if (dRes) (void)hipFree(dRes);
     if (pStage) (void)hipHostFree(pStage);
+    if (pOut) (void)hipHostFree(pOut);
+    if (pFlags) (void)hipHostFree(pFlags);
+    if (S) (void)hipHostFree(S);
     if (stream) (void)hipStreamDestroy(stream);
   }
 
@@ -104,7 +120,7 @@ struct ct_split {
     for (int k = 0; k < vars[i].domWords; ++k) c += __builtin_popcountll(d[vars[i].domOff + k]);
     return c;
   }
-  const uint64_t* row(int r) const { return S.data() + (size_t)r * v.W; }
+  const uint64_t* row(int r) const { return S + (size_t)r * v.W; }
 };
 
 namespace {
@@ -169,6 +185,19 @@ void host_filter(ct_split* s) {
   }
 }
 
+// Waits (bounded) until every one of the call's `grid` workgroups has
+// published its outputs.
+bool wait_flags(ct_split* s, int grid) {
+  const auto t0 = std::chrono::steady_clock::now();
+  for (int b = 0; b < grid; ++b) {
+    int spins = 0;
+    while (__atomic_load_n(&s->pFlags[b], __ATOMIC_ACQUIRE) != s->seq) {
+      if (++spins % 1024 == 0 && std::chrono::steady_clock::now() - t0 > std::chrono::seconds(2)) return false;
+    }
+  }
+  return true;
+}
+
 void rebuild_index(ct_split* s) {
   s->nz.clear();
   for (int64_t w = 0; w < s->v.W; ++w)
@@ -193,7 +222,6 @@ int ct_split_create(ct_table* t, int32_t mode, ct_split** out) {
   const int64_t W = v.W, D = v.D;
   try {
     s->vars.assign(v.vars, v.vars + v.n);
-    s->S.resize((size_t)v.rows * (size_t)W);
     s->ct.resize((size_t)W);
     s->lastDom.resize((size_t)D);
     s->dom.resize((size_t)D);
@@ -220,22 +248,41 @@ int ct_split_create(ct_table* t, int32_t mode, ct_split** out) {
     }                                                                                         \
   } while (0)
   CREATECHK(hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking));
-  // blocking copies into the (pageable) host vectors: each has landed when
-  // the call returns
+  // blocking copies into pinned host memory (no staging through a bounce
+  // buffer): each has landed when the call returns
+  CREATECHK(hipHostMalloc((void**)&s->S, sizeof(uint64_t) * std::max<size_t>((size_t)v.rows * (size_t)W, 1),
+                          hipHostMallocDefault));
   if (W > 0 && v.rows > 0)
-    CREATECHK(hipMemcpy2D(s->S.data(), sizeof(uint64_t) * W, v.S, sizeof(uint64_t) * v.stride,
-                          sizeof(uint64_t) * W, v.rows, hipMemcpyDeviceToHost));
-  if (W > 0) CREATECHK(hipMemcpy(s->ct.data(), v.rootCt, sizeof(uint64_t) * W, hipMemcpyDeviceToHost));
-  CREATECHK(hipMemcpy(s->lastDom.data(), v.rootDom, sizeof(uint64_t) * D, hipMemcpyDeviceToHost));
-  // stage: update variant = segment starts + row list in, mask out;
-  //        filter variant = currTable + domains + word list in, domains out
+    CREATECHK(hipMemcpy2D(s->S, sizeof(uint64_t) * W, v.S, sizeof(uint64_t) * v.stride, sizeof(uint64_t) * W,
+                          v.rows, hipMemcpyDeviceToHost));
+  // stage: update variant = segment starts + row list;
+  //        filter variant = currTable + domains + word list
   const size_t upd = align16(sizeof(int32_t) * (v.n + 1)) + align16(sizeof(int32_t) * (v.rows + 1)) +
                      align16(sizeof(uint64_t) * std::max<int64_t>(W, 1));
   const size_t flt = align16(sizeof(uint64_t) * std::max<int64_t>(W, 1)) + align16(sizeof(uint64_t) * D) +
                      align16(sizeof(int32_t) * D);
   s->stageBytes = mode == CT_SPLIT_UPDATE ? upd : flt;
   CREATECHK(hipMalloc((void**)&s->dStage, s->stageBytes));
-  CREATECHK(hipHostMalloc((void**)&s->pStage, s->stageBytes, hipHostMallocDefault));
+  // the inputs' pinned mirror (coherent pinned memory, like the library's
+  // other host buffers that the device reads or writes)
+  CREATECHK(hipHostMalloc((void**)&s->pStage, s->stageBytes, hipHostMallocMapped | hipHostMallocCoherent));
+  // the root state, through the pinned stage (it holds W and D words in either layout)
+  if (W > 0) {
+    CREATECHK(hipMemcpy(s->pStage, v.rootCt, sizeof(uint64_t) * W, hipMemcpyDeviceToHost));
+    memcpy(s->ct.data(), s->pStage, sizeof(uint64_t) * W);
+  }
+  CREATECHK(hipMemcpy(s->pStage, v.rootDom, sizeof(uint64_t) * D, hipMemcpyDeviceToHost));
+  memcpy(s->lastDom.data(), s->pStage, sizeof(uint64_t) * D);
+  {
+    const int64_t outWords = std::max<int64_t>(mode == CT_SPLIT_UPDATE ? W : D, 1);
+    const int grid = std::max(mode == CT_SPLIT_UPDATE ? split_update_grid(std::max<int64_t>(W, 1))
+                                                      : split_filter_grid((int)D), 1);
+    CREATECHK(hipHostMalloc((void**)&s->pOut, sizeof(uint64_t) * outWords, hipHostMallocMapped | hipHostMallocCoherent));
+    CREATECHK(hipHostMalloc((void**)&s->pFlags, sizeof(int32_t) * grid, hipHostMallocMapped | hipHostMallocCoherent));
+    memset(s->pFlags, 0, sizeof(int32_t) * grid);
+    CREATECHK(hipHostGetDevicePointer((void**)&s->dOut, s->pOut, 0));
+    CREATECHK(hipHostGetDevicePointer((void**)&s->dFlags, s->pFlags, 0));
+  }
   if (mode == CT_SPLIT_FILTER) {
     std::vector<int32_t> wordRow((size_t)D, 0);
     for (const VarDesc& x : s->vars)
@@ -303,17 +350,19 @@ int ct_split_propagate(ct_split* s, const uint64_t* dom_in, uint64_t* dom_out, u
     const int nSeg = (int)s->segBegin.size();
     s->segBegin.push_back((int32_t)s->rowList.size());
     const size_t oSeg = 0, oRows = align16(sizeof(int32_t) * (n + 1));
-    const size_t oMask = oRows + align16(sizeof(int32_t) * (s->v.rows + 1));
     memcpy(s->pStage + oSeg, s->segBegin.data(), sizeof(int32_t) * s->segBegin.size());
     memcpy(s->pStage + oRows, s->rowList.data(), sizeof(int32_t) * s->rowList.size());
     const size_t inBytes = oRows + sizeof(int32_t) * s->rowList.size();
-    SPLITCHK(hipMemcpyAsync(s->dStage, s->pStage, inBytes, hipMemcpyHostToDevice, s->stream));
+    SPLITCHK(hipMemcpy(s->dStage, s->pStage, inBytes, hipMemcpyHostToDevice));  // landed on return
+    ++s->seq;
     SPLITCHK(launch_split_update(s->v.S, s->v.stride, W, (const int32_t*)(s->dStage + oSeg), nSeg,
-                                 (const int32_t*)(s->dStage + oRows), (uint64_t*)(s->dStage + oMask), s->stream));
-    SPLITCHK(hipMemcpyAsync(s->pStage + oMask, s->dStage + oMask, sizeof(uint64_t) * W, hipMemcpyDeviceToHost,
-                            s->stream));
+                                 (const int32_t*)(s->dStage + oRows), s->dOut, s->dFlags, s->seq, s->stream));
     SPLITCHK(hipStreamSynchronize(s->stream));
-    const uint64_t* mask = (const uint64_t*)(s->pStage + oMask);
+    if (!wait_flags(s, split_update_grid(W))) {
+      s->poisoned = true;
+      return sfail(CT_E_DEVICE, "split update: results not published");
+    }
+    const uint64_t* mask = s->pOut;
     size_t keep = 0;
     for (size_t j = 0; j < s->nz.size(); ++j) {
       const int32_t w = s->nz[j];
@@ -346,14 +395,18 @@ int ct_split_propagate(ct_split* s, const uint64_t* dom_in, uint64_t* dom_out, u
       memcpy(s->pStage + oDom, s->dom.data(), sizeof(uint64_t) * D);
       memcpy(s->pStage + oWords, s->words.data(), sizeof(int32_t) * s->words.size());
       const size_t inBytes = oWords + sizeof(int32_t) * s->words.size();
-      SPLITCHK(hipMemcpyAsync(s->dStage, s->pStage, inBytes, hipMemcpyHostToDevice, s->stream));
+      SPLITCHK(hipMemcpy(s->dStage, s->pStage, inBytes, hipMemcpyHostToDevice));  // landed on return
+      ++s->seq;
       SPLITCHK(launch_split_filter(s->v.S, s->v.stride, W, (const uint64_t*)(s->dStage + oCt),
-                                   (uint64_t*)(s->dStage + oDom), (const int32_t*)(s->dStage + oWords),
-                                   (int)s->words.size(), s->dWordRow, s->dRes, s->stream));
-      SPLITCHK(hipMemcpyAsync(s->pStage + oDom, s->dStage + oDom, sizeof(uint64_t) * D, hipMemcpyDeviceToHost,
-                              s->stream));
+                                   (const uint64_t*)(s->dStage + oDom), (const int32_t*)(s->dStage + oWords),
+                                   (int)s->words.size(), s->dWordRow, s->dRes, s->dOut, s->dFlags, s->seq,
+                                   s->stream));
       SPLITCHK(hipStreamSynchronize(s->stream));
-      memcpy(s->dom.data(), s->pStage + oDom, sizeof(uint64_t) * D);
+      if (!wait_flags(s, split_filter_grid((int)s->words.size()))) {
+        s->poisoned = true;
+        return sfail(CT_E_DEVICE, "split filter: results not published");
+      }
+      for (int32_t k : s->words) s->dom[k] = s->pOut[k];
       for (int i = 0; i < n; ++i)
         if (s->sSup[i]) s->lastSizes[i] = s->var_size(s->dom.data(), i);
     }
