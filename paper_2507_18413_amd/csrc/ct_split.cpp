@@ -289,7 +289,8 @@ int ct_split_create(ct_table* t, int32_t mode, ct_split** out) {
       for (int k = 0; k < x.domWords; ++k) wordRow[x.domOff + k] = x.rowStart + 64 * k;
     CREATECHK(hipMalloc((void**)&s->dWordRow, sizeof(int32_t) * std::max<int64_t>(D, 1)));
     CREATECHK(hipMalloc((void**)&s->dRes, sizeof(int32_t) * std::max(v.rows, 1)));
-    CREATECHK(hipMemcpy(s->dWordRow, wordRow.data(), sizeof(int32_t) * D, hipMemcpyHostToDevice));
+    memcpy(s->pStage, wordRow.data(), sizeof(int32_t) * D);  // pinned source, no staging
+    CREATECHK(hipMemcpy(s->dWordRow, s->pStage, sizeof(int32_t) * D, hipMemcpyHostToDevice));
     CREATECHK(hipMemset(s->dRes, 0, sizeof(int32_t) * std::max(v.rows, 1)));
   }
   CREATECHK(hipStreamSynchronize(nullptr));  // the memset above
