@@ -386,8 +386,8 @@ double ct_server_now(void);
  *     ANDs it into currTable and runs filterDomains (Alg. 3, residues).
  *   CT_SPLIT_FILTER: updateTable on the host; filterDomains on the device
  *     over the words of the variables with more than one value.
- * Each call is one host-to-device copy, one launch and one device-to-host
- * copy, synchronous.  ct_split_propagate has ct_propagate's contract (host
+ * Each call is one host-to-device copy and one launch whose results the
+ * device writes into pinned host memory; synchronous.  ct_split_propagate has ct_propagate's contract (host
  * pointers; dom_in a subset of the current domains, no stray bits; CT_OK
  * with the GAC domains and currTable, CT_FAIL with dom_out untouched and
  * ct_out zeroed and the propagator failed until popped; CT_E_NOT_SUBSET /
