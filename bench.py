@@ -302,7 +302,8 @@ def wide_leg(seed, n_calls, cpu):
 def split_leg(table, script, passes):
     """The same call script through the two split propagators of the table
     (updateTable or filterDomains on the device, the other procedure on the
-    host; one copy each way per call)."""
+    host; one copy in per call, results written by the device into pinned
+    host memory)."""
     import numpy as np
     from paper_2507_18413_amd import ct
     out = {}
