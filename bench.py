@@ -54,6 +54,8 @@ def parse():
     p.add_argument("--no-model", action="store_true")
     p.add_argument("--no-wide", action="store_true")
     p.add_argument("--no-split", action="store_true")
+    p.add_argument("--wide-only", action="store_true",
+                   help="only the wide-scope leg, without its split propagators (profiling)")
     p.add_argument("--no-driver", action="store_true")
     p.add_argument("--root-batch-only", action="store_true",
                    help="only the batched root recomputation of the 2,000-table model (profiling)")
@@ -251,7 +253,7 @@ class PlainModel:
         return 0, pool, props
 
 
-def wide_leg(seed, n_calls, cpu):
+def wide_leg(seed, n_calls, cpu, split=True):
     """Plain calls on a wide-scope table (100 variables, domains 64-160,
     10,000 tuples; filterDomains dominates): the paper's instance shape."""
     import numpy as np
@@ -259,7 +261,9 @@ def wide_leg(seed, n_calls, cpu):
     from paper_2507_18413_amd import workloads as W
     spec = W.wide_table(seed)
     lay = spec.layout()
-    rec = ct.Table(spec.tuples, spec.lo, spec.dsizes, schedule=ct.SCHED_SOLO)
+    # the recorder runs the schedule the timed table gets, so a profile of
+    # the leg averages one kind of launch
+    rec = ct.Table(spec.tuples, spec.lo, spec.dsizes, schedule=ct.SCHED_SPLIT)
     script = W.run_plain_script(GpuSut(rec), lay, n_calls, seed, 6, W.pick_fraction_removal)
     rec.close()
     depth = sum(1 if k == "push" else -1 if k == "pop" else 0 for k, _ in script)
@@ -271,14 +275,14 @@ def wide_leg(seed, n_calls, cpu):
     props = replay(table, script, lat)
     el = time.perf_counter() - t0
     lat_us = np.array(lat) * 1e6
-    split = split_leg(table, script, 1)
+    split_out = split_leg(table, script, 1) if split else None
     out = {"workload": "arity 100, domains U{64..160}, 10,000 distinct uniform tuples "
                        f"({table.rows} support rows of {table.W} words, {table.D} domain words); "
                        f"{n_calls} calls as in the plain leg",
            "props_per_s": round(props / el, 1),
            "latency_us": {"p50": round(float(np.percentile(lat_us, 50)), 2),
                           "p99": round(float(np.percentile(lat_us, 99)), 2)},
-           "split_propagators": split}
+           "split_propagators": split_out}
     if cpu:
         from oracle import oracle as O
         o = O.OracleTable(spec.tuples, spec.lo, spec.dsizes)
@@ -775,6 +779,12 @@ def main():
         note("batched root recomputation")
         print(json.dumps({"root_gac_batch": root_batch_leg(tabs, mspec.tables, max(1, args.steps),
                                                            per_table=False)}), flush=True)
+        return
+    if args.wide_only:
+        torch.cuda.set_device(0)
+        calibration_copy(args.calibration_copy)
+        note("wide-scope leg")
+        print(json.dumps({"wide_scope": wide_leg(seed, 300, False, split=False)}), flush=True)
         return
     serve_spec = None
     if not args.no_serve:
