@@ -13,10 +13,15 @@
  *     satisfiability check: Sec. 3 ("Data structures", "Procedures");
  *   - GAC and propagation to a fixpoint: Sec. 2, first paragraphs.
  *
- * Everything is dense and direct: one uint64 word holds 64 tuples (tuple j is
- * bit j%64 of word j/64), every support row has W = ceil(t/64) words, no
- * sparse word list, no residues.  Backtracking keeps a full snapshot of the
- * propagator state per level.  Readings of points the paper leaves open:
+ * The plain mode is dense and direct: one uint64 word holds 64 tuples (tuple
+ * j is bit j%64 of word j/64), every support row has W = ceil(t/64) words, no
+ * sparse word list, no residues, and backtracking keeps a full snapshot of
+ * the propagator state per level.  The fast mode (cto_create_fast) reaches
+ * the same results with CT's economies -- the list of non-zero currTable
+ * words, residues checked first by filterDomains (Sec. 2), a trail of
+ * currTable words -- and serves as the timed serial baseline; both modes
+ * count the work of each call (cto_last_stats).  Readings of points the
+ * paper leaves open:
  *   - the incremental branch (OR over the removed values, then complement) is
  *     taken iff |Delta_i| < |dom(x_i)| (strict, as printed in Alg. 2); the
  *     branch labels printed as comments in Alg. 2 are swapped relative to the
@@ -28,8 +33,11 @@
  *     domain, so tuples holding values outside a domain are never valid;
  *   - a failed state accepts only pop; pop below depth 0 is an error.
  *
- * parity unpinned: none of the functions (each result is pinned by the tests
- * against brute-force GAC, the paper's Table 1 and closed-form invariants).
+ * parity unpinned: none of the functions.  Results of both modes are pinned
+ * by the tests against brute-force GAC, the paper's Table 1 and closed-form
+ * invariants; the fast mode also against the plain mode call by call; the
+ * work counters by hand counts on Table 1 and by counts taken from the
+ * previous call's currTable.
  */
 #include <stdint.h>
 #include <stdlib.h>
@@ -46,6 +54,22 @@
 #define CTO_MODE_RESET 1       /* always OR over dom(x_i)  */
 #define CTO_MODE_INCREMENTAL 2 /* always OR over Delta_i, complement */
 
+/* per-call work counters (cto_last_stats) */
+enum {
+    CTO_ST_NZ_WORDS = 0,  /* non-zero currTable words at entry */
+    CTO_ST_ROWS_OR,       /* support rows OR-ed by updateTable (up to Alg. 2's break) */
+    CTO_ST_SVAL,          /* |s_val| */
+    CTO_ST_SSUP,          /* |s_sup| */
+    CTO_ST_NZ_GRANULES,   /* 64-word groups of currTable holding a non-zero word at entry */
+    CTO_ST_ROWS_SEL,      /* rows Alg. 2's branch rule selects over all of s_val:
+                             sum of |Delta_i| (incremental) or |dom(x_i)| (reset) */
+    CTO_ST_RES_CHECKS,    /* fast mode: values tested by filterDomains */
+    CTO_ST_RES_MISSES,    /* fast mode: residue word no longer intersecting */
+    CTO_ST_SCAN_WORDS,    /* fast mode: words scanned after residue misses */
+    CTO_ST_UPD_WORDS,     /* support words read by updateTable */
+    CTO_NSTATS
+};
+
 typedef struct {
     int n;
     int64_t t, W;
@@ -61,9 +85,22 @@ typedef struct {
     uint64_t *snap_ct, *snap_dom;
     int32_t *snap_sizes, *snap_failed;
     /* counters of the last propagate call (work done, not results) */
-    int64_t st_nonzero_words_in; /* non-zero currTable words at entry */
-    int64_t st_update_rows;      /* support rows OR-ed by updateTable */
-    int64_t st_sval, st_ssup;
+    int64_t st[CTO_NSTATS];
+    /* fast mode (cto_create_fast): the sparse form of currTable, residues
+     * and a word trail instead of snapshots of currTable */
+    int fast;
+    int32_t *idx;        /* W: permutation of the word ids; idx[0..limit) are
+                            the non-zero words of ct */
+    int64_t limit;
+    int32_t *res;        /* rows: residue word of each (x_i, a) */
+    uint64_t *fmask;     /* W: mask scratch */
+    int32_t *stamp;      /* W: serial of the level that last saved the word */
+    int32_t serial, next_serial;
+    int64_t tr_top, tr_cap;
+    int32_t *tr_w;       /* trail: word id and old value */
+    uint64_t *tr_v;
+    int64_t *lv_top, *lv_limit;  /* per level: trail top, limit, serial */
+    int32_t *lv_serial;
 } cto_table;
 
 static int popc(uint64_t x) { return __builtin_popcountll(x); }
@@ -87,6 +124,16 @@ static int any_word(const uint64_t *x, int64_t W) {
     for (int64_t w = 0; w < W; w++)
         if (x[w]) return 1;
     return 0;
+}
+
+/* 64-word groups of x holding a non-zero word (a work count) */
+static int64_t nonzero_granules(const uint64_t *x, int64_t W) {
+    int64_t g = 0;
+    for (int64_t w0 = 0; w0 < W; w0 += 64) {
+        int64_t e = w0 + 64 < W ? w0 + 64 : W;
+        if (any_word(x + w0, e - w0)) g++;
+    }
+    return g;
 }
 
 /* tail bits of each variable's last word must be zero */
@@ -121,6 +168,8 @@ void cto_destroy(cto_table *T) {
     free(T->lo); free(T->dsz); free(T->row_start); free(T->dom_off); free(T->dom_words);
     free(T->S); free(T->ct); free(T->last_dom); free(T->last_sizes);
     free(T->snap_ct); free(T->snap_dom); free(T->snap_sizes); free(T->snap_failed);
+    free(T->idx); free(T->res); free(T->fmask); free(T->stamp); free(T->tr_w); free(T->tr_v);
+    free(T->lv_top); free(T->lv_limit); free(T->lv_serial);
     free(T);
 }
 
@@ -249,9 +298,13 @@ int cto_support_row(const cto_table *T, int32_t row, uint64_t *out) {
  * dom_in: the solver's current domains (must be a subset of the domains this
  * propagator returned last).  dom_out may alias dom_in.
  */
+static int propagate_fast(cto_table *T, const uint64_t *dom_in, uint64_t *dom_out, uint64_t *ct_out,
+                          int32_t mode);
+
 int cto_propagate(cto_table *T, const uint64_t *dom_in, uint64_t *dom_out, uint64_t *ct_out,
                   int32_t mode) {
     if (!T || !dom_in) return CTO_E_INVALID;
+    if (T->fast) return propagate_fast(T, dom_in, dom_out, ct_out, mode);
     if (T->failed) return CTO_E_STATE;
     if (stray_bits(T, dom_in)) return CTO_E_INVALID;
     for (int k = 0; k < T->D; k++)
@@ -267,11 +320,9 @@ int cto_propagate(cto_table *T, const uint64_t *dom_in, uint64_t *dom_out, uint6
         return CTO_E_NOMEM;
     }
     memcpy(dom, dom_in, sizeof(uint64_t) * T->D);
-    T->st_nonzero_words_in = 0;
-    for (int64_t w = 0; w < W; w++) T->st_nonzero_words_in += T->ct[w] != 0;
-    T->st_update_rows = 0;
-    T->st_sval = 0;
-    T->st_ssup = 0;
+    memset(T->st, 0, sizeof(T->st));
+    for (int64_t w = 0; w < W; w++) T->st[CTO_ST_NZ_WORDS] += T->ct[w] != 0;
+    T->st[CTO_ST_NZ_GRANULES] = nonzero_granules(T->ct, W);
 
     /* Alg. 1: Delta, s_val, s_sup */
     for (int i = 0; i < n; i++) {
@@ -279,12 +330,21 @@ int cto_propagate(cto_table *T, const uint64_t *dom_in, uint64_t *dom_out, uint6
         if (size[i] != T->last_sizes[i]) {
             s_val[i] = 1;
             T->last_sizes[i] = size[i];
-            T->st_sval++;
+            T->st[CTO_ST_SVAL]++;
         }
         if (size[i] > 1) {
             s_sup[i] = 1;
-            T->st_ssup++;
+            T->st[CTO_ST_SSUP]++;
         }
+    }
+    /* rows the branch rule selects over all of s_val (work count only) */
+    for (int i = 0; i < n; i++) {
+        if (!s_val[i]) continue;
+        int delta = 0;
+        for (int k = 0; k < T->dom_words[i]; k++)
+            delta += popc(T->last_dom[T->dom_off[i] + k] & ~dom[T->dom_off[i] + k]);
+        int incremental = mode == CTO_MODE_INCREMENTAL || (mode == CTO_MODE_AUTO && delta < size[i]);
+        T->st[CTO_ST_ROWS_SEL] += incremental ? delta : size[i];
     }
     /* Alg. 2: updateTable */
     for (int i = 0; i < n; i++) {
@@ -300,7 +360,8 @@ int cto_propagate(cto_table *T, const uint64_t *dom_in, uint64_t *dom_out, uint6
             if (!take) continue;
             const uint64_t *r = row_ptr(T, i, a);
             for (int64_t w = 0; w < W; w++) mask[w] |= r[w];
-            T->st_update_rows++;
+            T->st[CTO_ST_ROWS_OR]++;
+            T->st[CTO_ST_UPD_WORDS] += W;
         }
         if (incremental)
             for (int64_t w = 0; w < W; w++) mask[w] = ~mask[w];
@@ -323,16 +384,20 @@ int cto_propagate(cto_table *T, const uint64_t *dom_in, uint64_t *dom_out, uint6
     return CTO_OK;
 }
 
-void cto_last_stats(const cto_table *T, int64_t *out4) {
-    out4[0] = T->st_nonzero_words_in;
-    out4[1] = T->st_update_rows;
-    out4[2] = T->st_sval;
-    out4[3] = T->st_ssup;
+/* Work counters of the last propagate call: the first min(n, CTO_NSTATS)
+ * entries of the CTO_ST_* list.  Returns CTO_NSTATS. */
+int cto_last_stats(const cto_table *T, int64_t *out, int32_t n) {
+    for (int k = 0; k < n && k < CTO_NSTATS; k++) out[k] = T->st[k];
+    return CTO_NSTATS;
 }
+
+static int push_fast(cto_table *T);
+static int pop_fast(cto_table *T);
 
 /* push: snapshot of currTable, last domains, lastSizes and the failed flag */
 int cto_push(cto_table *T) {
     if (!T) return CTO_E_INVALID;
+    if (T->fast) return push_fast(T);
     if (T->failed) return CTO_E_STATE;
     if (T->depth == T->cap) {
         int nc = T->cap ? 2 * T->cap : 16;
@@ -362,10 +427,239 @@ int cto_push(cto_table *T) {
 
 int cto_pop(cto_table *T) {
     if (!T) return CTO_E_INVALID;
+    if (T->fast) return pop_fast(T);
     if (T->depth == 0) return CTO_E_STATE;
     T->depth--;
     int64_t Wa = T->W > 0 ? T->W : 1;
     memcpy(T->ct, T->snap_ct + (int64_t)T->depth * Wa, sizeof(uint64_t) * Wa);
+    memcpy(T->last_dom, T->snap_dom + (int64_t)T->depth * T->D, sizeof(uint64_t) * T->D);
+    memcpy(T->last_sizes, T->snap_sizes + (int64_t)T->depth * T->n, sizeof(int32_t) * T->n);
+    T->failed = T->snap_failed[T->depth];
+    return CTO_OK;
+}
+
+/* ========================================================================
+ * Fast mode: the same results by CT's own economies (Sec. 2: the sparse
+ * bitset of non-zero currTable words, residues checked first by
+ * filterDomains; reversible state by a trail of currTable words).  It exists
+ * to time a competent serial CT beside the GPU and to count the work CT
+ * does; every call agrees with the plain mode (tested call by call).
+ * ===================================================================== */
+
+/* Builds the fast-mode structures from the state left by cto_create. */
+static int fast_init(cto_table *T) {
+    int64_t Wa = T->W > 0 ? T->W : 1;
+    T->idx = (int32_t *)malloc(sizeof(int32_t) * Wa);
+    T->res = (int32_t *)calloc((size_t)(T->rows > 0 ? T->rows : 1), sizeof(int32_t));
+    T->fmask = (uint64_t *)malloc(sizeof(uint64_t) * Wa);
+    T->stamp = (int32_t *)calloc((size_t)Wa, sizeof(int32_t));
+    if (!T->idx || !T->res || !T->fmask || !T->stamp) return CTO_E_NOMEM;
+    int64_t k = 0;
+    for (int64_t w = 0; w < T->W; w++)
+        if (T->ct[w]) T->idx[k++] = (int32_t)w;
+    T->limit = T->failed ? 0 : k;
+    for (int64_t w = 0; w < T->W; w++)
+        if (!T->ct[w]) T->idx[k++] = (int32_t)w;
+    T->serial = 0;
+    T->next_serial = 0;
+    T->fast = 1;
+    return CTO_OK;
+}
+
+/* cto_create with the fast-mode state: same arguments and statuses. */
+int cto_create_fast(const int32_t *tuples, int64_t t, int32_t n, const int32_t *lo,
+                    const int32_t *dsz, const uint64_t *init_dom, cto_table **out) {
+    int st = cto_create(tuples, t, n, lo, dsz, init_dom, out);
+    if (!*out) return st;
+    if (fast_init(*out) != CTO_OK) {
+        cto_destroy(*out);
+        *out = NULL;
+        return CTO_E_NOMEM;
+    }
+    return st;
+}
+
+/* saves word w on the trail before its first change in the current level */
+static int trail_word(cto_table *T, int32_t w) {
+    if (T->depth == 0 || T->stamp[w] == T->serial) return CTO_OK;
+    if (T->tr_top == T->tr_cap) {
+        int64_t nc = T->tr_cap ? 2 * T->tr_cap : 1024;
+        int32_t *a = (int32_t *)realloc(T->tr_w, sizeof(int32_t) * nc);
+        if (!a) return CTO_E_NOMEM;
+        T->tr_w = a;
+        uint64_t *b = (uint64_t *)realloc(T->tr_v, sizeof(uint64_t) * nc);
+        if (!b) return CTO_E_NOMEM;
+        T->tr_v = b;
+        T->tr_cap = nc;
+    }
+    T->tr_w[T->tr_top] = w;
+    T->tr_v[T->tr_top] = T->ct[w];
+    T->tr_top++;
+    T->stamp[w] = T->serial;
+    return CTO_OK;
+}
+
+static int propagate_fast(cto_table *T, const uint64_t *dom_in, uint64_t *dom_out, uint64_t *ct_out,
+                          int32_t mode) {
+    if (T->failed) return CTO_E_STATE;
+    if (stray_bits(T, dom_in)) return CTO_E_INVALID;
+    for (int k = 0; k < T->D; k++)
+        if (dom_in[k] & ~T->last_dom[k]) return CTO_E_NOT_SUBSET;
+    const int n = T->n;
+    const int64_t W = T->W;
+    uint64_t *dom = (uint64_t *)malloc(sizeof(uint64_t) * T->D);
+    int32_t *size = (int32_t *)malloc(sizeof(int32_t) * n);
+    char *s_val = (char *)calloc((size_t)n, 1), *s_sup = (char *)calloc((size_t)n, 1);
+    if (!dom || !size || !s_val || !s_sup) {
+        free(dom); free(size); free(s_val); free(s_sup);
+        return CTO_E_NOMEM;
+    }
+    memcpy(dom, dom_in, sizeof(uint64_t) * T->D);
+    memset(T->st, 0, sizeof(T->st));
+    T->st[CTO_ST_NZ_WORDS] = T->limit;
+    {   /* granules: distinct w / 64 among the listed words */
+        int64_t last = -1, g = 0;
+        char *seen = (char *)calloc((size_t)(W / 64 + 1), 1);
+        if (!seen) {
+            free(dom); free(size); free(s_val); free(s_sup);
+            return CTO_E_NOMEM;
+        }
+        for (int64_t k = 0; k < T->limit; k++) {
+            int64_t gr = T->idx[k] / 64;
+            if (!seen[gr]) { seen[gr] = 1; g++; }
+            last = gr;
+        }
+        (void)last;
+        free(seen);
+        T->st[CTO_ST_NZ_GRANULES] = g;
+    }
+    /* Alg. 1: s_val, s_sup */
+    for (int i = 0; i < n; i++) {
+        size[i] = var_size(T, dom, i);
+        if (size[i] != T->last_sizes[i]) {
+            s_val[i] = 1;
+            T->last_sizes[i] = size[i];
+            T->st[CTO_ST_SVAL]++;
+        }
+        if (size[i] > 1) {
+            s_sup[i] = 1;
+            T->st[CTO_ST_SSUP]++;
+        }
+    }
+    /* Alg. 2 over the listed (non-zero) words only */
+    int rc = CTO_OK;
+    for (int i = 0; i < n; i++) {
+        if (!s_val[i]) continue;
+        int delta = 0;
+        for (int k = 0; k < T->dom_words[i]; k++)
+            delta += popc(T->last_dom[T->dom_off[i] + k] & ~dom[T->dom_off[i] + k]);
+        int incremental = mode == CTO_MODE_INCREMENTAL || (mode == CTO_MODE_AUTO && delta < size[i]);
+        T->st[CTO_ST_ROWS_SEL] += incremental ? delta : size[i];
+        if (T->limit == 0) continue;  /* past Alg. 2's break: selected, not read */
+        for (int64_t k = 0; k < T->limit; k++) T->fmask[T->idx[k]] = 0;
+        for (int a = 0; a < T->dsz[i]; a++) {
+            int was = has_value(T, T->last_dom, i, a), is = has_value(T, dom, i, a);
+            if (!(incremental ? (was && !is) : is)) continue;
+            const uint64_t *r = row_ptr(T, i, a);
+            for (int64_t k = 0; k < T->limit; k++) T->fmask[T->idx[k]] |= r[T->idx[k]];
+            T->st[CTO_ST_ROWS_OR]++;
+            T->st[CTO_ST_UPD_WORDS] += T->limit;
+        }
+        /* intersect; a word that becomes zero leaves the list (swapped with
+         * the last listed word: the listed set of an earlier limit is kept) */
+        for (int64_t k = T->limit - 1; k >= 0; k--) {
+            const int32_t w = T->idx[k];
+            const uint64_t nw = T->ct[w] & (incremental ? ~T->fmask[w] : T->fmask[w]);
+            if (nw == T->ct[w]) continue;
+            if ((rc = trail_word(T, w)) != CTO_OK) break;
+            T->ct[w] = nw;
+            if (nw == 0) {
+                T->idx[k] = T->idx[T->limit - 1];
+                T->idx[T->limit - 1] = w;
+                T->limit--;
+            }
+        }
+        if (rc != CTO_OK) break;
+    }
+    if (rc == CTO_OK && T->limit == 0) {  /* Alg. 1: failure test */
+        T->failed = 1;
+        if (ct_out) memset(ct_out, 0, sizeof(uint64_t) * W);
+        rc = CTO_FAIL;
+    } else if (rc == CTO_OK) {
+        /* Alg. 3 with residues: the residue word first, then the listed words */
+        for (int i = 0; i < n; i++) {
+            if (!s_sup[i]) continue;
+            for (int a = 0; a < T->dsz[i]; a++) {
+                if (!has_value(T, dom, i, a)) continue;
+                const int row = T->row_start[i] + a;
+                const uint64_t *r = row_ptr(T, i, a);
+                T->st[CTO_ST_RES_CHECKS]++;
+                if (T->ct[T->res[row]] & r[T->res[row]]) continue;
+                T->st[CTO_ST_RES_MISSES]++;
+                int found = 0;
+                for (int64_t k = 0; k < T->limit; k++) {
+                    const int32_t w = T->idx[k];
+                    T->st[CTO_ST_SCAN_WORDS]++;
+                    if (T->ct[w] & r[w]) {
+                        T->res[row] = w;
+                        found = 1;
+                        break;
+                    }
+                }
+                if (!found) dom[T->dom_off[i] + a / 64] &= ~(1ull << (a % 64));
+            }
+            T->last_sizes[i] = var_size(T, dom, i);
+        }
+        memcpy(T->last_dom, dom, sizeof(uint64_t) * T->D);
+        if (dom_out) memcpy(dom_out, dom, sizeof(uint64_t) * T->D);
+        if (ct_out) memcpy(ct_out, T->ct, sizeof(uint64_t) * W);
+    }
+    free(dom); free(size); free(s_val); free(s_sup);
+    return rc;
+}
+
+static int push_fast(cto_table *T) {
+    if (T->failed) return CTO_E_STATE;
+    if (T->depth == T->cap) {
+        int nc = T->cap ? 2 * T->cap : 16;
+        uint64_t *b = (uint64_t *)realloc(T->snap_dom, sizeof(uint64_t) * (size_t)T->D * nc);
+        if (!b) return CTO_E_NOMEM;
+        T->snap_dom = b;
+        int32_t *c = (int32_t *)realloc(T->snap_sizes, sizeof(int32_t) * (size_t)T->n * nc);
+        if (!c) return CTO_E_NOMEM;
+        T->snap_sizes = c;
+        int32_t *d = (int32_t *)realloc(T->snap_failed, sizeof(int32_t) * nc);
+        if (!d) return CTO_E_NOMEM;
+        T->snap_failed = d;
+        int64_t *e = (int64_t *)realloc(T->lv_top, sizeof(int64_t) * nc);
+        if (!e) return CTO_E_NOMEM;
+        T->lv_top = e;
+        int64_t *f = (int64_t *)realloc(T->lv_limit, sizeof(int64_t) * nc);
+        if (!f) return CTO_E_NOMEM;
+        T->lv_limit = f;
+        int32_t *g = (int32_t *)realloc(T->lv_serial, sizeof(int32_t) * nc);
+        if (!g) return CTO_E_NOMEM;
+        T->lv_serial = g;
+        T->cap = nc;
+    }
+    memcpy(T->snap_dom + (int64_t)T->depth * T->D, T->last_dom, sizeof(uint64_t) * T->D);
+    memcpy(T->snap_sizes + (int64_t)T->depth * T->n, T->last_sizes, sizeof(int32_t) * T->n);
+    T->snap_failed[T->depth] = T->failed;
+    T->lv_top[T->depth] = T->tr_top;
+    T->lv_limit[T->depth] = T->limit;
+    T->lv_serial[T->depth] = T->serial;
+    T->depth++;
+    T->serial = ++T->next_serial;
+    return CTO_OK;
+}
+
+static int pop_fast(cto_table *T) {
+    if (T->depth == 0) return CTO_E_STATE;
+    T->depth--;
+    for (int64_t e = T->tr_top - 1; e >= T->lv_top[T->depth]; e--) T->ct[T->tr_w[e]] = T->tr_v[e];
+    T->tr_top = T->lv_top[T->depth];
+    T->limit = T->lv_limit[T->depth];
+    T->serial = T->lv_serial[T->depth];
     memcpy(T->last_dom, T->snap_dom + (int64_t)T->depth * T->D, sizeof(uint64_t) * T->D);
     memcpy(T->last_sizes, T->snap_sizes + (int64_t)T->depth * T->n, sizeof(int32_t) * T->n);
     T->failed = T->snap_failed[T->depth];
@@ -383,13 +677,17 @@ int cto_pop(cto_table *T) {
  * and intersected with the domains it returned last: values it removed
  * before were unsupported under larger domains and stay unsupported, so the
  * closure is unchanged, and the input is always a subset of its state.
- * `order` (nullable) gives the initial queue order.
+ * `order` (nullable) gives the initial queue: its first n_init entries
+ * (n_init < 0: all n_tables; without `order`, tables 0..n_init-1).  Starting
+ * from a state that was already a fixpoint, a queue holding only the tables
+ * whose scope contains a variable that pool_in changed reaches the same
+ * closure (the others are still GAC).
  * Returns CTO_OK with pool_out = the GAC closure, or CTO_FAIL.
  */
 int cto_fixpoint(int32_t n_tables, cto_table **tabs, const int32_t *scope_off,
                  const int32_t *scopes, int32_t n_pool, const int32_t *pool_off,
                  const uint64_t *pool_in, int32_t pool_words, uint64_t *pool_out,
-                 const int32_t *order, int64_t *n_props) {
+                 const int32_t *order, int32_t n_init, int64_t *n_props) {
     memcpy(pool_out, pool_in, sizeof(uint64_t) * pool_words);
     int32_t *queue = (int32_t *)malloc(sizeof(int32_t) * (n_tables + 1));
     char *inq = (char *)calloc((size_t)n_tables + 1, 1);
@@ -416,8 +714,10 @@ int cto_fixpoint(int32_t n_tables, cto_table **tabs, const int32_t *scope_off,
             vtabs[vstart[v] + vcount[v]++] = c;
         }
     int head = 0, tail = 0, size = 0, cap = n_tables + 1;
-    for (int c = 0; c < n_tables; c++) {
+    if (n_init < 0 || n_init > n_tables) n_init = n_tables;
+    for (int c = 0; c < n_init; c++) {
         int cc = order ? order[c] : c;
+        if (inq[cc]) continue;
         queue[tail] = cc; tail = (tail + 1) % cap; size++;
         inq[cc] = 1;
     }

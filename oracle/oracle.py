@@ -32,6 +32,8 @@ def lib():
         P = C.c_void_p
         L.cto_create.argtypes = [P, C.c_int64, C.c_int32, P, P, P, C.POINTER(P)]
         L.cto_create.restype = C.c_int
+        L.cto_create_fast.argtypes = [P, C.c_int64, C.c_int32, P, P, P, C.POINTER(P)]
+        L.cto_create_fast.restype = C.c_int
         L.cto_destroy.argtypes = [P]
         L.cto_layout.argtypes = [P, P, P, P, P]
         L.cto_get_state.argtypes = [P, P, P, P]
@@ -39,8 +41,9 @@ def lib():
         L.cto_propagate.argtypes = [P, P, P, P, C.c_int32]
         L.cto_push.argtypes = [P]
         L.cto_pop.argtypes = [P]
-        L.cto_last_stats.argtypes = [P, P]
-        L.cto_fixpoint.argtypes = [C.c_int32, P, P, P, C.c_int32, P, P, C.c_int32, P, P, P]
+        L.cto_last_stats.argtypes = [P, P, C.c_int32]
+        L.cto_last_stats.restype = C.c_int
+        L.cto_fixpoint.argtypes = [C.c_int32, P, P, P, C.c_int32, P, P, C.c_int32, P, P, C.c_int32, P]
         L.cto_fixpoint.restype = C.c_int
         _lib = L
     return _lib
@@ -53,8 +56,11 @@ def _p(a):
 class OracleTable:
     """One table constraint with its reversible propagator state."""
 
-    def __init__(self, tuples, lo, dsizes, init_dom=None):
+    def __init__(self, tuples, lo, dsizes, init_dom=None, fast=False):
+        """fast: CT's sparse word list, residues and a word trail (same
+        results as the plain mode, which follows Alg. 1-3 densely)."""
         L = lib()
+        self.fast = bool(fast)
         tuples = np.ascontiguousarray(tuples, dtype=np.int32)
         self.n = int(len(dsizes))
         self.lo = np.ascontiguousarray(lo, dtype=np.int32)
@@ -63,8 +69,9 @@ class OracleTable:
         if init_dom is not None:
             init_dom = np.ascontiguousarray(init_dom, dtype=np.uint64)
         h = C.c_void_p()
-        st = L.cto_create(_p(tuples) if t else None, t, self.n, _p(self.lo), _p(self.dsizes),
-                          _p(init_dom), C.byref(h))
+        create = L.cto_create_fast if fast else L.cto_create
+        st = create(_p(tuples) if t else None, t, self.n, _p(self.lo), _p(self.dsizes),
+                    _p(init_dom), C.byref(h))
         self.create_status = st
         if h.value is None:
             raise ValueError(f"cto_create failed with status {st}")
@@ -115,11 +122,19 @@ class OracleTable:
             return st, dom_out, ct[: self.W]
         return st, dom_out
 
+    STAT_NAMES = ("nonzero_words_in", "update_rows", "sval", "ssup", "nonzero_granules_in",
+                  "rows_selected", "residue_checks", "residue_misses", "scan_words", "update_words")
+
     def last_stats(self):
-        out = np.zeros(4, np.int64)
-        lib().cto_last_stats(self.h, _p(out))
-        return dict(nonzero_words_in=int(out[0]), update_rows=int(out[1]),
-                    sval=int(out[2]), ssup=int(out[3]))
+        """Work counters of the last propagate call (see cto_last_stats):
+        non-zero currTable words and 64-word granules at entry, rows OR-ed
+        (up to Alg. 2's break) and rows selected over all of s_val, |s_val|,
+        |s_sup|, support words read by updateTable, and in the fast mode the
+        residue checks, misses and words scanned by filterDomains."""
+        out = np.zeros(len(self.STAT_NAMES), np.int64)
+        n = lib().cto_last_stats(self.h, _p(out), len(self.STAT_NAMES))
+        assert n == len(self.STAT_NAMES)
+        return {k: int(v) for k, v in zip(self.STAT_NAMES, out)}
 
     def push(self):
         return lib().cto_push(self.h)
@@ -128,9 +143,12 @@ class OracleTable:
         return lib().cto_pop(self.h)
 
 
-def fixpoint(tables, scopes, pool_layout, pool_in, order=None):
+def fixpoint(tables, scopes, pool_layout, pool_in, order=None, seed=None):
     """GAC closure over tables sharing pool variables (FIFO queue of tables).
 
+    order: the initial queue (default: every table in index order); seed: the
+    tables to start from instead (a fixpoint whose previous state was a
+    fixpoint needs only the tables touching a changed variable).
     Returns (status, pool_out, n_propagations)."""
     L = lib()
     n = len(tables)
@@ -143,9 +161,13 @@ def fixpoint(tables, scopes, pool_layout, pool_in, order=None):
     pool_off = np.ascontiguousarray(pool_layout.off, dtype=np.int32)
     pool_in = np.ascontiguousarray(pool_in, dtype=np.uint64)
     pool_out = np.zeros_like(pool_in)
+    n_init = -1
+    if seed is not None:
+        order = np.asarray(seed, dtype=np.int32)
+        n_init = int(order.shape[0])
     ordr = None if order is None else np.ascontiguousarray(order, dtype=np.int32)
     props = C.c_int64()
     st = L.cto_fixpoint(n, C.cast(arr, C.c_void_p), _p(scope_off), _p(flat), pool_layout.n,
                         _p(pool_off), _p(pool_in), int(pool_in.shape[0]), _p(pool_out), _p(ordr),
-                        C.byref(props))
+                        n_init, C.byref(props))
     return st, pool_out, props.value

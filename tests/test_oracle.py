@@ -275,3 +275,54 @@ def test_fixpoint_against_naive_closure(seed):
         assert (st == O.FAIL) == failed
         if not failed:
             assert lay.to_sets(pool_out) == want
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_seeded_fixpoint_after_a_fixpoint_equals_the_closure(seed):
+    """After a fixpoint, a search step that removes values of some pool
+    variables needs only the tables whose scope holds one of them: the
+    fixpoint seeded with those tables equals the enumeration closure (and the
+    fixpoint seeded with every table)."""
+    rng = rng_for(seed, 105, 0)
+    n_pool = int(rng.integers(4, 8))
+    pool_ds = rng.integers(2, 5, size=n_pool).astype(np.int32)
+    lay = DomLayout(pool_ds, np.zeros(n_pool, np.int32))
+    tables, scopes = [], []
+    for c in range(int(rng.integers(3, 7))):
+        k = int(rng.integers(1, min(4, n_pool) + 1))
+        scope = rng.choice(n_pool, size=k, replace=False).astype(np.int32)
+        ds = pool_ds[scope]
+        t = int(rng.integers(2, 20))
+        tup = np.stack([rng.integers(0, ds[i], size=t) for i in range(k)], axis=1).astype(np.int32)
+        tables.append((tup, np.zeros(k, np.int32)))
+        scopes.append(scope)
+    checked = 0
+    for trial in range(6):
+        seeded = [O.OracleTable(tp, lo, pool_ds[s]) for (tp, lo), s in zip(tables, scopes)]
+        full = [O.OracleTable(tp, lo, pool_ds[s]) for (tp, lo), s in zip(tables, scopes)]
+        if any(o.create_status == O.FAIL for o in seeded):
+            break
+        st, root, _ = O.fixpoint(seeded, scopes, lay, lay.full())
+        O.fixpoint(full, scopes, lay, lay.full())
+        if st != O.OK:
+            break
+        pool = root
+        for step in range(4):
+            new = random_subset(rng, lay, pool, 0.8)
+            changed = [v for v in range(n_pool) if lay.to_sets(new)[v] != lay.to_sets(pool)[v]]
+            touch = [c for c, sc in enumerate(scopes) if set(int(v) for v in sc) & set(changed)]
+            for o in seeded + full:
+                o.push()
+            st_s, out_s, props_s = O.fixpoint(seeded, scopes, lay, new, seed=touch)
+            st_f, out_f, _ = O.fixpoint(full, scopes, lay, new)
+            failed, want = closure(tables, scopes, lay.to_sets(new))
+            assert (st_s == O.FAIL) == (st_f == O.FAIL) == failed
+            assert props_s <= len(tables) * 64
+            checked += 1
+            if failed:
+                for o in seeded + full:
+                    o.pop()
+                continue
+            assert lay.to_sets(out_s) == want == lay.to_sets(out_f)
+            pool = out_s
+    assert checked > 0

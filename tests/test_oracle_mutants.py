@@ -27,6 +27,19 @@ MUTANTS = [
     ("no stray-bit check", "int used = d - 64 * (T->dom_words[i] - 1);", "int used = 64;"),
     ("no subset check", "if (dom_in[k] & ~T->last_dom[k]) return CTO_E_NOT_SUBSET;", ";"),
     ("pop restores nothing", "memcpy(T->ct, T->snap_ct + (int64_t)T->depth * Wa, sizeof(uint64_t) * Wa);", ";"),
+    # fast mode (sparse word list, residues, word trail)
+    ("fast: emptied word stays listed", "                T->limit--;\n", "\n"),
+    ("fast: removal swap dropped", "T->idx[k] = T->idx[T->limit - 1];", ";"),
+    ("fast: no trail", "if (T->depth == 0 || T->stamp[w] == T->serial) return CTO_OK;", "return CTO_OK;"),
+    ("fast: residue trusted without currTable", "if (T->ct[T->res[row]] & r[T->res[row]]) continue;",
+     "if (r[T->res[row]]) continue;"),
+    ("fast: mask ignores the last listed word",
+     "for (int64_t k = 0; k < T->limit; k++) T->fmask[T->idx[k]] |= r[T->idx[k]];",
+     "for (int64_t k = 0; k + 1 < T->limit; k++) T->fmask[T->idx[k]] |= r[T->idx[k]];"),
+    ("fast: pop keeps the limit", "T->limit = T->lv_limit[T->depth];", ";"),
+    # work counters
+    ("rows selected counts the domain on both branches", "T->st[CTO_ST_ROWS_SEL] += incremental ? delta : size[i];",
+     "T->st[CTO_ST_ROWS_SEL] += size[i];"),
 ]
 
 
@@ -42,6 +55,7 @@ def test_pins_kill_mutant(name, old, new, tmp_path):
                    check=True, capture_output=True)
     env = dict(os.environ, CT_ORACLE_LIB=str(lib))
     r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
-                        os.path.join(ROOT, "tests", "test_oracle.py")],
+                        os.path.join(ROOT, "tests", "test_oracle.py"),
+                        os.path.join(ROOT, "tests", "test_oracle_fast.py")],
                        cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
     assert r.returncode != 0, f"mutant survived the pins: {name}\n{r.stdout[-2000:]}"
