@@ -176,7 +176,10 @@ int ct_propagate_slot(ct_table *t, int32_t slot, const uint64_t *dom_in, uint64_
                       uint64_t *ct_out, ct_stats *st);
 
 /*
- * ct_push / ct_pop -- backtracking.  push records a level; pop restores the
+ * ct_push / ct_pop -- backtracking.  CT's state is reversible: the solver
+ * saves and restores it when the search backtracks (Sec. 3, the propagator's
+ * state is managed by the solver; Sec. 5.2.1, backtracking phases that grow
+ * domains and valid tuples again).  push records a level; pop restores the
  * slot's currTable, domains and failed flag exactly as they were at the
  * matching push.  push on a failed slot -> CT_E_STATE; push beyond max_depth
  * -> CT_E_NOMEM; pop at depth 0 -> CT_E_STATE.  Both are cheap host calls;
@@ -187,15 +190,30 @@ int ct_pop(ct_table *t);
 int ct_push_slot(ct_table *t, int32_t slot);
 int ct_pop_slot(ct_table *t, int32_t slot);
 
-/* Current domains (D words) and currTable (W words) of a slot, host
- * pointers, both nullable. */
+/* Current domains (D words; the domains the slot's last propagation
+ * returned, Alg. 3's output) and currTable (W words; the tuples valid under
+ * them, Sec. 2) of a slot, host pointers, both nullable.  A failed slot
+ * reports its domains at the failure's input and a zero currTable. */
 int ct_get_state(ct_table *t, int32_t slot, uint64_t *dom_out, uint64_t *ct_out);
 
-/* Adds n slots, each a copy of the root state with room for max_depth push
- * levels (negative = the table's default; 0 = no levels, for slots that are
- * only reset by CT_JOB_FROM_ROOT jobs or never pushed).  Synchronous.
- * *first_slot receives the first new id. */
+/* Adds n slots with consecutive ids, each a copy of the root state (the
+ * state after the constructor's root propagation, Sec. 3) with room for
+ * max_depth push levels (negative = the table's default; 0 = no levels, for
+ * slots that are only reset by CT_JOB_FROM_ROOT jobs or never pushed).
+ * Synchronous.  *first_slot receives the first id.  The first run of n
+ * consecutive slots released by ct_slots_free whose trails hold max_depth
+ * levels is reused (reset to the root state); otherwise new slots are
+ * allocated on the device (CT_E_NOMEM if that fails). */
 int ct_slots_alloc(ct_table *t, int32_t n, int32_t max_depth, int32_t *first_slot);
+
+/* Releases slots first .. first + n - 1 (slot 0, the table's own, cannot be
+ * released).  A released slot answers every call that names it (propagate,
+ * push, pop, get_state, slot_stats, batch jobs) with CT_E_INVALID until
+ * ct_slots_alloc hands it out again.  Its device memory stays with the table
+ * (freed by ct_destroy) and is reused by ct_slots_alloc.  The caller releases
+ * a slot only after every batch that names it has completed.  CT_E_INVALID
+ * for a range outside the table, slot 0, or a slot already released. */
+int ct_slots_free(ct_table *t, int32_t first, int32_t n);
 
 /* Cumulative counters of a slot (host pointer). */
 int ct_slot_stats(ct_table *t, int32_t slot, ct_stats *st);
@@ -354,13 +372,16 @@ typedef struct {
 } ct_completion;
 
 int ct_server_create(const ct_server_cfg *cfg, ct_server **out);
-/* Stops the thread after the requests in flight, frees the server's slots'
- * bookkeeping (the tables keep their memory). */
+/* Stops the thread after the requests in flight and returns every slot its
+ * searches still hold to their tables (ct_slots_free; the tables keep the
+ * memory and reuse the slots). */
 void ct_server_destroy(ct_server *s);
 /* Registers a search on table t with room for max_depth levels (all searches
  * of one table use the same max_depth); it starts at the table's root state
  * when its first request is admitted.  Searches are registered before the
- * first ct_server_submit (CT_E_STATE afterwards).  The first request of a
+ * first ct_server_submit (CT_E_STATE afterwards); a registration that races
+ * the first submit from another thread is serialized with it (one of the two
+ * comes first under the server's lock).  The first request of a
  * search (and the first after a CT_REQ_FINISH) has n_pop = 0 and push = 0. */
 int ct_server_add_search(ct_server *s, ct_table *t, int32_t max_depth, int32_t *search);
 /* Thread-safe. */
@@ -368,10 +389,14 @@ int ct_server_submit(ct_server *s, const ct_request *req);
 /* Up to max completions, waiting up to wait_us microseconds for the first;
  * returns the number written (>= 0) or a negative error. */
 int ct_server_poll(ct_server *s, ct_completion *out, int32_t max, int32_t wait_us);
-/* Counters: [0] requests done, [1] launches, [2] admission waits (times a
- * ready request could not get a slot), [3] slot bytes in use, [4] peak slot
- * bytes, [5] slots allocated. */
-int ct_server_stats(ct_server *s, int64_t *out6);
+/* Counters, the first min(n, CT_SERVER_NSTATS) written to out (host):
+ * [0] requests done, [1] launches, [2] admission waits (times a ready request
+ * could not get a slot), [3] slot bytes in use, [4] peak slot bytes, [5]
+ * slots allocated (new ones; a slot freed by a finished search is reused),
+ * [6] launches that carried two or more requests, [7] launches whose
+ * requests named two or more tables, [8] the largest batch launched. */
+#define CT_SERVER_NSTATS 9
+int ct_server_stats(ct_server *s, int64_t *out, int32_t n);
 /* The steady clock the timestamps use (seconds). */
 double ct_server_now(void);
 
@@ -422,6 +447,13 @@ int ct_batch_status(void *stream);
  * timing was last switched on. */
 int ct_set_timing(ct_table *t, int32_t on);
 int ct_get_timing(ct_table *t, double *kernel_ms, int64_t *launches);
+/* Lifetimes of the kernel launches that served the synchronous calls since
+ * timing was switched on, on the same device clock: for launched calls the
+ * same figures as ct_get_timing; for the resident engine, each launch's
+ * whole lifetime from its start to its exit (the polling between calls
+ * included), counting the launches started while timing was on.  Ends a
+ * running engine first (so its lifetime is known).  Synchronous. */
+int ct_get_dispatch_timing(ct_table *t, double *dispatch_ms, int64_t *dispatches);
 
 /* Thread-local message of the last error ("" if none). */
 const char *ct_last_error(void);

@@ -72,6 +72,8 @@ constexpr int32_t kStatusPending = 0x7fff0001;
 struct SlotHost {
   SlotDesc* dev = nullptr;
   int maxDepth = 0;
+  int capDepth = 0;        // levels the slot's device trail was sized for
+  bool freed = false;      // released by ct_slots_free (reused by ct_slots_alloc)
   int depth = 0;           // depth including pending operations
   int pendPop = 0, pendPush = 0;
   int8_t failed = 0;
@@ -177,6 +179,9 @@ struct ct_table {
   int32_t engSeq = 0;
   bool engStatsFresh = false;  // pRes->stats is from the last call
   unsigned long long engTicks = 0, engCalls = 0;  // timing of engine calls
+  // lifetimes of the engine launches started while timing was on
+  bool engTimed = false;
+  unsigned long long engLifeTicks = 0, engLaunches = 0;
 };
 
 namespace {
@@ -420,6 +425,10 @@ int engine_join(ct_table* T) {
   hipError_t e = hipStreamSynchronize(T->engStream);
   T->engOn = false;
   if (g_engOwner == T) g_engOwner = nullptr;
+  if (e == hipSuccess && T->engTimed && T->timing) {
+    T->engLifeTicks += T->pRes->lifeTicks;
+    T->engLaunches += 1;
+  }
   if (e != hipSuccess) {
     T->poisoned = true;
     return fail(CT_E_DEVICE, "engine failed: %s", hipGetErrorString(e));
@@ -462,6 +471,7 @@ int engine_start(ct_table* T) {
   HIPCHK(hipHostGetDevicePointer((void**)&D.ctOut, T->pCt, 0));
   D.idleTicks = engine_idle_ticks();
   D.startSeq = T->engSeq;
+  T->engTimed = T->timing;
   T->pRes->seq = T->engSeq;
   __atomic_store_n(&T->pRes->alive, 1, __ATOMIC_RELEASE);
   HIPCHK(launch_engine(D, T->engLds, T->engStream));
@@ -571,7 +581,125 @@ int ensure_pinned_ct(ct_table* T) {
 int check_slot(const ct_table* T, int slot) {
   if (slot < 0 || slot >= (int)T->slots.size())
     return fail(CT_E_INVALID, "slot %d out of range (%zu slots)", slot, T->slots.size());
+  if (T->slots[slot].freed) return fail(CT_E_INVALID, "slot %d was freed", slot);
   return CT_OK;
+}
+
+// ---------------------------------------------------------------------------
+// batch staging shared by ct_propagate_batch and ct_propagate_batch_static
+// ---------------------------------------------------------------------------
+// Validates every job (no state is touched before all pass; the marks that
+// find a slot named twice carry no state), then waits for what the tables
+// may still have in flight elsewhere (a model's queued work, the resident
+// engine, the tail of a synchronous call).
+int batch_validate_quiesce(const ct_job* jobs, int n_jobs, hipStream_t stream) {
+  static std::atomic<uint64_t> batchCounter{0};
+  const uint64_t mark = ++batchCounter;
+  for (int j = 0; j < n_jobs; ++j) {
+    const ct_job& cj = jobs[j];
+    ct_table* T = cj.table;
+    int rc = check_poison(T);
+    if (rc) return rc;
+    if ((rc = check_slot(T, cj.slot))) return rc;
+    if (T->slots[cj.slot].batchMark == mark)
+      return fail(CT_E_INVALID, "job %d: slot %d appears twice in the batch", j, cj.slot);
+    T->slots[cj.slot].batchMark = mark;
+    if (cj.flags & ~(CT_JOB_PROPAGATE | CT_JOB_FROM_ROOT | CT_JOB_ROOT))
+      return fail(CT_E_INVALID, "job %d: unknown flags", j);
+    if ((cj.flags & CT_JOB_ROOT) && (cj.flags & CT_JOB_FROM_ROOT))
+      return fail(CT_E_INVALID, "job %d: ROOT and FROM_ROOT together", j);
+    if ((cj.flags & CT_JOB_ROOT) && (cj.n_pop || cj.n_push || !(cj.flags & CT_JOB_PROPAGATE)))
+      return fail(CT_E_INVALID, "job %d: ROOT needs PROPAGATE and no pops/pushes", j);
+    if (cj.n_pop < 0 || cj.n_push < 0) return fail(CT_E_INVALID, "job %d: negative pops/pushes", j);
+    const SlotHost& S = T->slots[cj.slot];
+    if (cj.flags & CT_JOB_FROM_ROOT) {
+      if (cj.n_pop || cj.n_push) return fail(CT_E_INVALID, "job %d: FROM_ROOT with pops/pushes", j);
+      if (!(cj.flags & CT_JOB_PROPAGATE)) return fail(CT_E_INVALID, "job %d: FROM_ROOT needs PROPAGATE", j);
+    } else {
+      if (cj.n_pop > S.depth) return fail(CT_E_INVALID, "job %d: pop below depth 0", j);
+      if (S.depth - cj.n_pop + cj.n_push > S.maxDepth)
+        return fail(CT_E_NOMEM, "job %d: depth beyond max_depth", j);
+    }
+    if ((cj.flags & CT_JOB_PROPAGATE) && (!cj.dom_in || !cj.dom_out))
+      return fail(CT_E_INVALID, "job %d: dom_in / dom_out is NULL", j);
+  }
+  // the synchronous calls of these tables may still be finishing their tail
+  for (int j = 0; j < n_jobs; ++j) {
+    ct_table* T = jobs[j].table;
+    if (T->batchMark == mark) continue;
+    T->batchMark = mark;
+    int rc = quiesce(T, stream);
+    if (rc) return rc;
+    if (T->tailPending) {
+      HIPCHK(hipStreamSynchronize(T->stream));
+      T->tailPending = false;
+    }
+  }
+  return CT_OK;
+}
+
+// Device descriptors of a validated batch, written into out[n_jobs], the
+// item offsets updOff / filtOff (n_jobs + 1 entries, [0] = 0 on entry) and
+// the prep list (up to n_jobs entries); returns the prep list's length.
+// Applies the jobs' pops and pushes to the host mirror of each slot.
+int batch_build(const ct_job* jobs, int n_jobs, int32_t* status_dev, bool nodes, DevJob* out,
+                int32_t* updOff, int32_t* filtOff, int32_t* prep) {
+  int nPrep = 0;
+  updOff[0] = filtOff[0] = 0;
+  for (int j = 0; j < n_jobs; ++j) {
+    const ct_job& cj = jobs[j];
+    ct_table* T = cj.table;
+    SlotHost& S = T->slots[cj.slot];
+    DevJob& J = out[j];
+    J = DevJob{};
+    J.tab = T->dTab;
+    J.slot = S.dev;
+    J.dom_in = cj.dom_in;
+    J.dom_out = cj.dom_out;
+    J.ct_out = cj.ct_out;
+    J.status_out = status_dev + j;
+    J.flags = ((cj.flags & CT_JOB_PROPAGATE) ? JF_PROPAGATE : 0u) |
+              ((cj.flags & CT_JOB_FROM_ROOT) ? JF_FROM_ROOT : 0u) |
+              ((cj.flags & CT_JOB_ROOT) ? (JF_ROOT | JF_FROM_ROOT | JF_SCRATCH) : 0u);
+    if (cj.flags & (CT_JOB_FROM_ROOT | CT_JOB_ROOT)) {
+      S.pendPop = S.pendPush = 0;
+      S.depth = 0;
+      S.failedAt.clear();
+      J.serialBase = T->serialCounter++;
+      J.depthAfter = 0;
+    } else {
+      // pending single-call operations (pops P then pushes Q) come first
+      int P = S.pendPop, Q = S.pendPush;
+      if (cj.n_pop <= Q) {
+        Q = Q - cj.n_pop + cj.n_push;
+      } else {
+        P += cj.n_pop - Q;
+        Q = cj.n_push;
+      }
+      S.pendPop = S.pendPush = 0;
+      J.nPop = P;
+      J.nPush = Q;
+      J.serialBase = T->serialCounter;
+      T->serialCounter += Q;
+      for (int k = 0; k < cj.n_pop; ++k) S.failedAt.pop_back();
+      for (int k = 0; k < cj.n_push; ++k) S.failedAt.push_back(2);
+      S.depth = S.depth - cj.n_pop + cj.n_push;
+      J.depthAfter = S.depth;
+    }
+    S.failed = 2;
+    // a root recomputed from scratch streams every support row: large
+    // tables are split over workgroups (the queue balances them), small ones
+    // run solo
+    const bool solo = (J.flags & JF_SCRATCH) && T->cfg.schedule == CT_SCHED_AUTO
+                          ? T->nGran <= SCRATCH_SOLO_MAX_GRAN
+                          : use_solo(T, n_jobs);
+    if ((J.flags & JF_PROPAGATE) && !nodes && solo) J.flags |= JF_SOLO;
+    job_counts(T, J);
+    updOff[j + 1] = updOff[j] + J.nUpd;
+    filtOff[j + 1] = filtOff[j] + J.nFilt;
+    if (needs_prep(J)) prep[nPrep++] = j;
+  }
+  return nPrep;
 }
 
 }  // namespace
@@ -845,6 +973,32 @@ int ct_slots_alloc(ct_table* T, int32_t n, int32_t max_depth, int32_t* first_slo
   if (n < 1) return fail(CT_E_INVALID, "n < 1");
   if ((rc = quiesce(T))) return rc;
   if (max_depth < 0) max_depth = T->cfg.max_depth;
+  // reuse: the first run of n consecutive freed slots whose trails hold
+  // max_depth levels; each is reset to the root state
+  int run = 0, first = -1;
+  for (int k = 0; k < (int)T->slots.size() && first < 0; ++k) {
+    const SlotHost& S = T->slots[k];
+    run = (S.freed && S.capDepth >= max_depth) ? run + 1 : 0;
+    if (run == n) first = k - n + 1;
+  }
+  if (first >= 0) {
+    for (int k = first; k < first + n; ++k)
+      HIPCHK(launch_init_slots(T->dTab, T->slots[k].dev, 1, T->hRoot.res, T->stream));
+    HIPCHK(hipStreamSynchronize(T->stream));
+    for (int k = first; k < first + n; ++k) {
+      SlotHost& S = T->slots[k];
+      const int cap = S.capDepth;
+      SlotDesc* dev = S.dev;
+      S = SlotHost();
+      S.dev = dev;
+      S.capDepth = cap;
+      S.maxDepth = max_depth;
+      S.failed = T->rootFailed ? 1 : 0;
+      S.failedAt.reserve(max_depth);
+    }
+    if (first_slot) *first_slot = first;
+    return CT_OK;
+  }
   SlotDesc* d = nullptr;
   std::vector<SlotDesc> h;
   if ((rc = alloc_slots(T, n, max_depth, &d, h))) return rc;
@@ -855,8 +1009,32 @@ int ct_slots_alloc(ct_table* T, int32_t n, int32_t max_depth, int32_t* first_slo
     SlotHost s;
     s.dev = d + k;
     s.maxDepth = max_depth;
+    s.capDepth = max_depth;
     s.failed = T->rootFailed ? 1 : 0;
+    // a push never grows this vector past its capacity (no allocation per push)
+    s.failedAt.reserve(max_depth);
     T->slots.push_back(s);
+  }
+  return CT_OK;
+}
+
+int ct_slots_free(ct_table* T, int32_t first, int32_t n) {
+  int rc = check_poison(T);
+  if (rc) return rc;
+  if (n < 1 || first < 1 || first > (int)T->slots.size() - n)
+    return fail(CT_E_INVALID, "slots [%d, %d) cannot be freed (%zu slots; slot 0 stays)", first, first + n,
+                T->slots.size());
+  for (int k = first; k < first + n; ++k)
+    if (T->slots[k].freed) return fail(CT_E_INVALID, "slot %d is already free", k);
+  // batches queued on other streams may still use the slots: the caller
+  // frees a slot only after its last batch has completed
+  if ((rc = quiesce(T))) return rc;
+  for (int k = first; k < first + n; ++k) {
+    SlotHost& S = T->slots[k];
+    S.freed = true;
+    S.depth = 0;
+    S.pendPop = S.pendPush = 0;
+    S.failedAt.clear();
   }
   return CT_OK;
 }
@@ -1031,6 +1209,25 @@ int ct_set_timing(ct_table* T, int32_t on) {
   T->timing = on != 0;
   T->engTicks = 0;
   T->engCalls = 0;
+  T->engLifeTicks = 0;
+  T->engLaunches = 0;
+  return CT_OK;
+}
+
+int ct_get_dispatch_timing(ct_table* T, double* dispatch_ms, int64_t* dispatches) {
+  if (!T) return fail(CT_E_INVALID, "null table");
+  unsigned long long c[5] = {0, 0, 0, 0, 0};
+  if (T->dClock) {
+    int rc = quiesce(T);  // also ends a running engine: its lifetime is then known
+    if (rc) return rc;
+    HIPCHK(hipStreamSynchronize(T->stream));
+    HIPCHK(hipMemcpy(c, T->dClock, sizeof(c), hipMemcpyDeviceToHost));
+  }
+  int dev = 0, khz = 0;
+  HIPCHK(hipGetDevice(&dev));
+  HIPCHK(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev));
+  if (dispatch_ms) *dispatch_ms = khz > 0 ? (double)(c[3] + T->engLifeTicks) / (double)khz : 0.0;
+  if (dispatches) *dispatches = (int64_t)(c[4] + T->engLaunches);
   return CT_OK;
 }
 
@@ -1058,50 +1255,8 @@ int ct_propagate_batch(const ct_job* jobs, int32_t n_jobs, void* stream_v, int32
     return fail(CT_E_INVALID, "bad batch arguments");
   if (n_jobs == 0) return CT_OK;
   hipStream_t stream = (hipStream_t)stream_v;
-  // validate (no state is touched before every job passes; the marks that
-  // find a slot named twice carry no state)
-  static std::atomic<uint64_t> batchCounter{0};
-  const uint64_t mark = ++batchCounter;
-  for (int j = 0; j < n_jobs; ++j) {
-    const ct_job& cj = jobs[j];
-    ct_table* T = cj.table;
-    int rc = check_poison(T);
-    if (rc) return rc;
-    if ((rc = check_slot(T, cj.slot))) return rc;
-    if (T->slots[cj.slot].batchMark == mark)
-      return fail(CT_E_INVALID, "job %d: slot %d appears twice in the batch", j, cj.slot);
-    T->slots[cj.slot].batchMark = mark;
-    if (cj.flags & ~(CT_JOB_PROPAGATE | CT_JOB_FROM_ROOT | CT_JOB_ROOT))
-      return fail(CT_E_INVALID, "job %d: unknown flags", j);
-    if ((cj.flags & CT_JOB_ROOT) && (cj.flags & CT_JOB_FROM_ROOT))
-      return fail(CT_E_INVALID, "job %d: ROOT and FROM_ROOT together", j);
-    if ((cj.flags & CT_JOB_ROOT) && (cj.n_pop || cj.n_push || !(cj.flags & CT_JOB_PROPAGATE)))
-      return fail(CT_E_INVALID, "job %d: ROOT needs PROPAGATE and no pops/pushes", j);
-    if (cj.n_pop < 0 || cj.n_push < 0) return fail(CT_E_INVALID, "job %d: negative pops/pushes", j);
-    const SlotHost& S = T->slots[cj.slot];
-    if (cj.flags & CT_JOB_FROM_ROOT) {
-      if (cj.n_pop || cj.n_push) return fail(CT_E_INVALID, "job %d: FROM_ROOT with pops/pushes", j);
-      if (!(cj.flags & CT_JOB_PROPAGATE)) return fail(CT_E_INVALID, "job %d: FROM_ROOT needs PROPAGATE", j);
-    } else {
-      if (cj.n_pop > S.depth) return fail(CT_E_INVALID, "job %d: pop below depth 0", j);
-      if (S.depth - cj.n_pop + cj.n_push > S.maxDepth)
-        return fail(CT_E_NOMEM, "job %d: depth beyond max_depth", j);
-    }
-    if ((cj.flags & CT_JOB_PROPAGATE) && (!cj.dom_in || !cj.dom_out))
-      return fail(CT_E_INVALID, "job %d: dom_in / dom_out is NULL", j);
-  }
-  // the synchronous calls of these tables may still be finishing their tail
-  for (int j = 0; j < n_jobs; ++j) {
-    ct_table* T = jobs[j].table;
-    if (T->batchMark == mark) continue;
-    T->batchMark = mark;
-    int rc = quiesce(T, stream);
-    if (rc) return rc;
-    if (T->tailPending) {
-      HIPCHK(hipStreamSynchronize(T->stream));
-      T->tailPending = false;
-    }
-  }
+  int rc = batch_validate_quiesce(jobs, n_jobs, stream);
+  if (rc) return rc;
   QueueCtx* q = nullptr;
   {
     std::lock_guard<std::mutex> lk(g_qmu);
@@ -1140,60 +1295,10 @@ int ct_propagate_batch(const ct_job* jobs, int32_t n_jobs, void* stream_v, int32
   std::vector<int32_t>& prep = q->prep;
   updOff.assign(n_jobs + 1, 0);
   filtOff.assign(n_jobs + 1, 0);
-  prep.clear();
-  for (int j = 0; j < n_jobs; ++j) {
-    const ct_job& cj = jobs[j];
-    ct_table* T = cj.table;
-    SlotHost& S = T->slots[cj.slot];
-    DevJob& J = q->hJobs[j];
-    J = DevJob{};
-    J.tab = T->dTab;
-    J.slot = S.dev;
-    J.dom_in = cj.dom_in;
-    J.dom_out = cj.dom_out;
-    J.ct_out = cj.ct_out;
-    J.status_out = status_dev + j;
-    J.flags = ((cj.flags & CT_JOB_PROPAGATE) ? JF_PROPAGATE : 0u) |
-              ((cj.flags & CT_JOB_FROM_ROOT) ? JF_FROM_ROOT : 0u) |
-              ((cj.flags & CT_JOB_ROOT) ? (JF_ROOT | JF_FROM_ROOT | JF_SCRATCH) : 0u);
-    if (cj.flags & (CT_JOB_FROM_ROOT | CT_JOB_ROOT)) {
-      S.pendPop = S.pendPush = 0;
-      S.depth = 0;
-      S.failedAt.clear();
-      J.serialBase = T->serialCounter++;
-      J.depthAfter = 0;
-    } else {
-      // pending single-call operations (pops P then pushes Q) come first
-      int P = S.pendPop, Q = S.pendPush;
-      if (cj.n_pop <= Q) {
-        Q = Q - cj.n_pop + cj.n_push;
-      } else {
-        P += cj.n_pop - Q;
-        Q = cj.n_push;
-      }
-      S.pendPop = S.pendPush = 0;
-      J.nPop = P;
-      J.nPush = Q;
-      J.serialBase = T->serialCounter;
-      T->serialCounter += Q;
-      for (int k = 0; k < cj.n_pop; ++k) S.failedAt.pop_back();
-      for (int k = 0; k < cj.n_push; ++k) S.failedAt.push_back(2);
-      S.depth = S.depth - cj.n_pop + cj.n_push;
-      J.depthAfter = S.depth;
-    }
-    S.failed = 2;
-    // a root recomputed from scratch streams every support row: large
-    // tables are split over workgroups (the queue balances them), small ones
-    // run solo
-    const bool solo = (J.flags & JF_SCRATCH) && T->cfg.schedule == CT_SCHED_AUTO
-                          ? T->nGran <= SCRATCH_SOLO_MAX_GRAN
-                          : use_solo(T, n_jobs);
-    if ((J.flags & JF_PROPAGATE) && !nodes && solo) J.flags |= JF_SOLO;
-    job_counts(T, J);
-    updOff[j + 1] = updOff[j] + J.nUpd;
-    filtOff[j + 1] = filtOff[j] + J.nFilt;
-    if (needs_prep(J)) prep.push_back(j);
-  }
+  prep.resize(n_jobs);
+  const int nPrep = batch_build(jobs, n_jobs, status_dev, nodes, q->hJobs.data(), updOff.data(),
+                                filtOff.data(), prep.data());
+  prep.resize(nPrep);
   // root streams: WAVES granules per task, tables with the most support rows
   // first (their tasks are the longest)
   std::vector<int32_t>& rootTasks = q->rootTasks;

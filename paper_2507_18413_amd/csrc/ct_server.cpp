@@ -63,7 +63,6 @@ struct Search {
 struct TableInfo {
   ct_table* T = nullptr;
   std::vector<uint64_t> root;
-  std::vector<int> freeSlots;
   int64_t slotBytes = 0;
   int maxDepth = 0;
 };
@@ -96,7 +95,7 @@ struct ct_server {
   std::thread th;
   std::atomic<bool> stop{false};
   std::atomic<bool> broken{false};
-  std::atomic<int64_t> stats[6] = {};
+  std::atomic<int64_t> stats[CT_SERVER_NSTATS] = {};
   size_t rr = 0;  // round-robin start for fairness
   bool started = false;  // first request submitted: the search list is fixed
 };
@@ -120,7 +119,9 @@ void complete(ct_server* s, const SReq& q, int status, double tLaunch) {
 void release_slot(ct_server* s, Search& S) {
   if (S.slot < 0) return;
   TableInfo& ti = s->tables[S.tab];
-  ti.freeSlots.push_back(S.slot);
+  // the slot goes back to the table (ct_slots_alloc reuses it); its last
+  // batch has completed (harvested)
+  (void)ct_slots_free(ti.T, S.slot, 1);
   s->stats[3] -= ti.slotBytes;
   S.slot = -1;
   S.fresh = true;
@@ -137,14 +138,13 @@ bool admit(ct_server* s, Search& S) {
   const int64_t budget = s->cfg.mem_budget;
   // within budget, and always at least one search so that work can proceed
   if (budget > 0 && s->stats[3] > 0 && s->stats[3] + ti.slotBytes > budget) return false;
-  if (ti.freeSlots.empty()) {
-    int32_t first = -1;
-    if (ct_slots_alloc(ti.T, 1, ti.maxDepth, &first) != CT_OK) return false;
-    ti.freeSlots.push_back(first);
-    s->stats[5]++;
-  }
-  S.slot = ti.freeSlots.back();
-  ti.freeSlots.pop_back();
+  // a slot freed by an earlier search of the table is reused
+  ct_layout_info before{};
+  if (ct_layout(ti.T, &before, nullptr) != CT_OK) return false;
+  int32_t slot = -1;
+  if (ct_slots_alloc(ti.T, 1, ti.maxDepth, &slot) != CT_OK) return false;
+  if (slot >= before.n_slots) s->stats[5]++;
+  S.slot = slot;
   s->stats[3] += ti.slotBytes;
   s->stats[4] = std::max(s->stats[4].load(), s->stats[3].load());
   S.fresh = true;
@@ -246,6 +246,15 @@ int launch(ct_server* s, Flight& f) {
   }
   f.busy = true;
   s->stats[1]++;
+  if (n >= 2) {
+    s->stats[6]++;
+    for (int k = 1; k < n; ++k)
+      if (jobs[k].table != jobs[0].table) {
+        s->stats[7]++;
+        break;
+      }
+  }
+  s->stats[8] = std::max<int64_t>(s->stats[8].load(), n);
   return n;
 }
 
@@ -331,8 +340,12 @@ void ct_server_destroy(ct_server* s) {
   s->stop = true;
   s->cvIn.notify_all();
   if (s->th.joinable()) s->th.join();
-  for (Flight& f : s->flights) {
+  for (Flight& f : s->flights)
     if (f.stream) (void)hipStreamSynchronize(f.stream);
+  // slots still held by searches go back to their tables
+  for (Search& S : s->searches)
+    if (S.slot >= 0) (void)ct_slots_free(S.T, S.slot, 1);
+  for (Flight& f : s->flights) {
     if (f.pIn) (void)hipHostFree(f.pIn);
     if (f.pOut) (void)hipHostFree(f.pOut);
     if (f.pStatus) (void)hipHostFree(f.pStatus);
@@ -344,6 +357,10 @@ void ct_server_destroy(ct_server* s) {
 
 int ct_server_add_search(ct_server* s, ct_table* t, int32_t max_depth, int32_t* search) {
   if (!s || !t || max_depth < 0) return CT_E_INVALID;
+  // the lock is held from the check of `started` to the end: a first submit
+  // on another thread cannot slip in between (the server thread reads the
+  // search list without the lock once started)
+  std::lock_guard<std::mutex> lk(s->mu);
   if (s->started) {
     ctk::set_error("searches are added before the first request");
     return CT_E_STATE;
@@ -355,7 +372,6 @@ int ct_server_add_search(ct_server* s, ct_table* t, int32_t max_depth, int32_t* 
     ctk::set_error("tables served must have at most 64 domain words");
     return CT_E_INVALID;
   }
-  std::lock_guard<std::mutex> lk(s->mu);
   auto it = s->tableIndex.find(t);
   int tab;
   if (it == s->tableIndex.end()) {
@@ -417,9 +433,9 @@ int ct_server_poll(ct_server* s, ct_completion* out, int32_t max, int32_t wait_u
   return n;
 }
 
-int ct_server_stats(ct_server* s, int64_t* out6) {
-  if (!s || !out6) return CT_E_INVALID;
-  for (int k = 0; k < 6; ++k) out6[k] = s->stats[k].load();
+int ct_server_stats(ct_server* s, int64_t* out, int32_t n) {
+  if (!s || !out || n < 0) return CT_E_INVALID;
+  for (int k = 0; k < n && k < CT_SERVER_NSTATS; ++k) out[k] = s->stats[k].load();
   return CT_OK;
 }
 

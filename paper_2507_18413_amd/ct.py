@@ -116,11 +116,13 @@ def lib():
             "ct_pop_slot": ([P, I32], C.c_int),
             "ct_get_state": ([P, I32, P, P], C.c_int),
             "ct_slots_alloc": ([P, I32, I32, C.POINTER(I32)], C.c_int),
+            "ct_slots_free": ([P, I32, I32], C.c_int),
             "ct_slot_stats": ([P, I32, C.POINTER(ct_stats)], C.c_int),
             "ct_propagate_batch": ([P, I32, P, P], C.c_int),
             "ct_batch_status": ([P], C.c_int),
             "ct_set_timing": ([P, I32], C.c_int),
             "ct_get_timing": ([P, C.POINTER(C.c_double), C.POINTER(I64)], C.c_int),
+            "ct_get_dispatch_timing": ([P, C.POINTER(C.c_double), C.POINTER(I64)], C.c_int),
             "ct_model_create": ([I32, P, P, C.POINTER(P)], C.c_int),
             "ct_model_destroy": ([P], None),
             "ct_model_add": ([P, P, P, C.POINTER(I32)], C.c_int),
@@ -135,7 +137,7 @@ def lib():
             "ct_server_add_search": ([P, P, I32, C.POINTER(I32)], C.c_int),
             "ct_server_submit": ([P, C.POINTER(ct_request)], C.c_int),
             "ct_server_poll": ([P, P, I32, I32], C.c_int),
-            "ct_server_stats": ([P, P], C.c_int),
+            "ct_server_stats": ([P, P, I32], C.c_int),
             "ct_server_now": ([], C.c_double),
             "ct_split_create": ([P, I32, C.POINTER(P)], C.c_int),
             "ct_split_propagate": ([P, P, P, P], C.c_int),
@@ -286,6 +288,11 @@ class Table:
             raise CTError(st, last_error())
         return first.value
 
+    def slots_free(self, first, n=1):
+        st = lib().ct_slots_free(self.h, int(first), int(n))
+        if st < 0:
+            raise CTError(st, last_error())
+
     def set_timing(self, on=True):
         st = lib().ct_set_timing(self.h, 1 if on else 0)
         if st < 0:
@@ -297,12 +304,28 @@ class Table:
         lib().ct_get_timing(self.h, C.byref(ms), C.byref(n))
         return ms.value, n.value
 
+    def dispatch_timing(self):
+        """(cumulative launch lifetimes in ms, launches) since set_timing(True);
+        for the resident engine, whole launch lifetimes (ends the engine)."""
+        ms, n = C.c_double(), C.c_int64()
+        st = lib().ct_get_dispatch_timing(self.h, C.byref(ms), C.byref(n))
+        if st < 0:
+            raise CTError(st, last_error())
+        return ms.value, n.value
+
     def stats(self, slot=0):
         s = ct_stats()
         st = lib().ct_slot_stats(self.h, int(slot), C.byref(s))
         if st < 0:
             raise CTError(st, last_error())
         return s.as_dict()
+
+
+def quiesce():
+    """End the resident engine of any table (it writes its state back)."""
+    st = lib().ct_quiesce()
+    if st < 0:
+        raise CTError(st, last_error())
 
 
 def batch_status(stream=None):
@@ -529,10 +552,12 @@ class Server:
         return out
 
     def stats(self):
-        a = np.zeros(6, np.int64)
-        lib().ct_server_stats(self.h, _p(a))
+        a = np.zeros(9, np.int64)
+        lib().ct_server_stats(self.h, _p(a), 9)
         return dict(done=int(a[0]), launches=int(a[1]), admission_waits=int(a[2]),
-                    slot_bytes_in_use=int(a[3]), peak_slot_bytes=int(a[4]), slots_allocated=int(a[5]))
+                    slot_bytes_in_use=int(a[3]), peak_slot_bytes=int(a[4]), slots_allocated=int(a[5]),
+                    multi_request_launches=int(a[6]), multi_table_launches=int(a[7]),
+                    max_batch=int(a[8]))
 
     @staticmethod
     def now():

@@ -102,4 +102,12 @@ def test_mixed_equals_alone(budget):
     assert stats["done"] == 24 * 30
     if budget:
         assert stats["admission_waits"] > 0
+    else:
+        # continuous batching really mixed the searches: fewer launches than
+        # requests, some launch carried several searches, some of them on
+        # different tables
+        assert stats["launches"] < stats["done"], stats
+        assert stats["multi_request_launches"] > 0, stats
+        assert stats["multi_table_launches"] > 0, stats
+        assert stats["max_batch"] >= 2, stats
     check_alone(specs, searches, results)
