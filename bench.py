@@ -111,11 +111,24 @@ def algorithmic_bytes(d_stats, D, calls):
             + 16 * d_stats["residue_checks"] + 2 * g * d_stats["scan_granules"] + 16 * D * calls)
 
 
-def cpu_baseline(spec, script, seconds):
+def oracle_bytes(st, D):
+    """Algorithmic bytes of one call from the oracle's own counts (the
+    word-level form: support words read by updateTable, currTable words read
+    and written, a support word per residue check and per scanned word, the
+    domain words in and out)."""
+    return (8 * st["update_words"] + 16 * st["nonzero_words_in"] + 8 * (st["residue_checks"] + st["scan_words"])
+            + 16 * D)
+
+
+def cpu_baseline(spec, script, seconds, fast=True):
+    """The oracle replaying the script on one host thread: (props/s, props,
+    seconds, passes, support words read per call, algorithmic bytes per call)."""
     from oracle import oracle as O
-    o = O.OracleTable(spec.tuples, spec.lo, spec.dsizes)
+    o = O.OracleTable(spec.tuples, spec.lo, spec.dsizes, fast=fast)
+    D = spec.layout().D
     props = 0
     passes = 0
+    words = byts = 0
     t0 = time.perf_counter()
     while True:
         for kind, payload in script:
@@ -126,16 +139,49 @@ def cpu_baseline(spec, script, seconds):
             else:
                 o.propagate(payload)
                 props += 1
+                if passes == 0:
+                    st = o.last_stats()
+                    words += st["update_words"] + st["scan_words"] + st["residue_checks"]
+                    byts += oracle_bytes(st, D)
         passes += 1
         el = time.perf_counter() - t0
         if el >= seconds:
             break
     while o.depth > 0:
         o.pop()
-    return props / el, props, el, passes
+    n1 = sum(1 for k, _ in script if k == "prop")
+    return props / el, props, el, passes, words / max(n1, 1), byts / max(n1, 1)
 
 
-def nodes_leg(seed, n_nodes, reps, warmup, schedule=0):
+def nodes_oracle_threads(spec, nodes, threads, seconds):
+    """Oracle (fast mode) propagations of the node states on `threads` host
+    threads (the oracle's calls release the interpreter lock), each thread
+    with its own oracle table; a bounded prefix of the nodes.  Returns
+    (nodes done, seconds, threads)."""
+    from concurrent.futures import ThreadPoolExecutor
+    from oracle import oracle as O
+    tabs = [O.OracleTable(spec.tuples, spec.lo, spec.dsizes, fast=True) for _ in range(threads)]
+    n = len(nodes)
+
+    def work(k, stop):
+        o = tabs[k]
+        done = 0
+        for i in range(k, n, threads):
+            if time.perf_counter() > stop:
+                break
+            o.push()
+            o.propagate(nodes[i])
+            o.pop()
+            done += 1
+        return done
+
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(threads) as ex:
+        done = sum(ex.map(lambda k: work(k, t0 + seconds), range(threads)))
+    return done, time.perf_counter() - t0, threads
+
+
+def nodes_leg(seed, n_nodes, reps, warmup, schedule=0, plain=True, cpu=False):
     """Batched CT across search nodes: one arity-6 table with 1,000,000 Zipf
     tuples, n_nodes independent domain states (each removes a random 0-60 %
     of every variable's values), all propagated from the root state in one
@@ -180,7 +226,37 @@ def nodes_leg(seed, n_nodes, reps, warmup, schedule=0):
     comp = 8 * table.rows * W_words + 8 * W_words + n_nodes * (8 * W_words + 16 * lay.D)
     from paper_2507_18413_amd import profiling
     prof = profiling.read_summary(os.path.join(ROOT, "profiles", "nodes_update_4096_nodes.md"))
-    return {
+    extra = {}
+    if plain:
+        # the same node states, one launch per node (a one-job batch on the
+        # same table: updateTable split over workgroups, then filterDomains)
+        singles = [ct.Batch([dict(table=table, slot=first + k, flags=ct.JOB_PROPAGATE | ct.JOB_FROM_ROOT,
+                                  dom_in=din[k], dom_out=dout[k])]) for k in range(n_nodes)]
+        for b in singles[:8]:
+            b.run(status[:1], stream)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        p0 = time.perf_counter()
+        for k, b in enumerate(singles):
+            b.run(status[k:k + 1], stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        pwall = time.perf_counter() - p0
+        ct.batch_status(stream)
+        pms = e0.elapsed_time(e1)
+        same = bool((status.cpu().numpy() == st).all())
+        extra["plain_one_launch_per_node"] = {
+            "ms_total": round(pms, 3), "node_props_per_s": round(n_nodes / (pms / 1e3), 1),
+            "wall_ms_total": round(pwall * 1e3, 3), "same_statuses_as_batch": same,
+            "batched_speedup": round(pms / gpu_ms, 1)}
+    if cpu:
+        hi = host_info()
+        thr = max(1, min(16, hi["usable_cores"] or 1))
+        done, sec, thr = nodes_oracle_threads(spec, nodes, thr, 8.0)
+        extra["oracle_all_cores"] = {"node_props_per_s": round(done / sec, 1), "threads": thr,
+                                     "sample": f"{done} of the {n_nodes} node states in {sec:.1f} s, "
+                                               "fast mode, one oracle table per thread"}
+    return {**extra, 
         "nodes": n_nodes, "tuples": spec.t, "ms_per_batch": round(gpu_ms, 3),
         "node_props_per_s": round(n_nodes / (gpu_ms / 1e3), 1),
         "wall_ms_per_batch": round(wall / reps * 1e3, 3),
@@ -221,13 +297,19 @@ class PlainModel:
             t.pop()
         self.last = self.stack.pop()
 
-    def fixpoint(self, pool):
+    def fixpoint(self, pool, seed=None):
+        """AC-3 from `pool`; seed: the tables to start from (default all; a
+        step after a fixpoint needs only the tables touching a changed
+        variable, the rule the batched model's first round follows)."""
         import numpy as np
         from collections import deque
         lay = self.lay
         pool = pool.copy()
-        q = deque(range(len(self.t)))
-        inq = [True] * len(self.t)
+        start = range(len(self.t)) if seed is None else seed
+        q = deque(start)
+        inq = [False] * len(self.t)
+        for c in start:
+            inq[c] = True
         props = 0
         while q:
             c = q.popleft()
@@ -270,11 +352,20 @@ def wide_leg(seed, n_calls, cpu, split=True):
     script += [("pop", None)] * depth
     table = ct.Table(spec.tuples, spec.lo, spec.dsizes)
     replay(table, script)
+    s0 = table.stats()
+    table.set_timing(True)
     lat = []
     t0 = time.perf_counter()
     props = replay(table, script, lat)
     el = time.perf_counter() - t0
+    kernel_ms, launches = table.timing()
+    table.set_timing(False)
+    s1 = table.stats()
+    d = {k: s1[k] - s0[k] for k in s1}
+    byts = algorithmic_bytes(d, lay.D, props)
     lat_us = np.array(lat) * 1e6
+    from paper_2507_18413_amd import profiling
+    prof = profiling.read_summary(os.path.join(ROOT, "profiles", "propagate_wide_scope.md"))
     split_out = split_leg(table, script, 1) if split else None
     out = {"workload": "arity 100, domains U{64..160}, 10,000 distinct uniform tuples "
                        f"({table.rows} support rows of {table.W} words, {table.D} domain words); "
@@ -282,6 +373,13 @@ def wide_leg(seed, n_calls, cpu, split=True):
            "props_per_s": round(props / el, 1),
            "latency_us": {"p50": round(float(np.percentile(lat_us, 50)), 2),
                           "p99": round(float(np.percentile(lat_us, 99)), 2)},
+           "kernel": {"name": "ctk::propagate_kernel", "launches": launches,
+                      "device_us_per_launch": round(kernel_ms * 1e3 / max(launches, 1), 3),
+                      "algorithmic_bytes_per_call": round(byts / max(props, 1), 1),
+                      "algorithmic_GBps": round(byts / (kernel_ms / 1e3) / 1e9, 2) if kernel_ms > 0 else None,
+                      "profiled_hbm_bytes_per_launch": prof.get("hbm_bytes_per_launch") if prof else None,
+                      "profiled_avg_us": prof.get("avg_us") if prof else None,
+                      "counters_per_call": {k: round(v / max(props, 1), 1) for k, v in d.items()}},
            "split_propagators": split_out}
     if cpu:
         from oracle import oracle as O
@@ -300,6 +398,56 @@ def wide_leg(seed, n_calls, cpu, split=True):
         t0 = time.perf_counter()
         oprops = replay(OracleSut(), script)
         out["oracle_props_per_s"] = round(oprops / (time.perf_counter() - t0), 1)
+    return out
+
+
+def tiny_leg(seed, reps, cpu):
+    """Plain calls on the tiny table (arity 3, domains {0..7}, 200 distinct
+    tuples; one currTable granule): 100 calls removing 1-2 values each, with
+    push / pop every 10 calls -- launch-latency bound: latency p50 / p99 and
+    calls/s (a roofline fraction means nothing at 768 bytes per call)."""
+    import numpy as np
+    from paper_2507_18413_amd import ct
+    from paper_2507_18413_amd import workloads as W
+    spec = W.tiny_table(seed)
+    lay = spec.layout()
+    rec = ct.Table(spec.tuples, spec.lo, spec.dsizes, schedule=ct.SCHED_SOLO)
+    script = W.run_plain_script(GpuSut(rec), lay, 100, seed, 1, W.pick_small_removal)
+    rec.close()
+    depth = sum(1 if k == "push" else -1 if k == "pop" else 0 for k, _ in script)
+    script += [("pop", None)] * depth
+    table = ct.Table(spec.tuples, spec.lo, spec.dsizes)
+    for _ in range(3):
+        replay(table, script)
+    lat = []
+    t0 = time.perf_counter()
+    props = sum(replay(table, script, lat) for _ in range(reps))
+    el = time.perf_counter() - t0
+    lat_us = np.array(lat) * 1e6
+    out = {"workload": "arity 3, domains {0..7}, 200 distinct tuples, 100 calls removing 1-2 values, "
+                       "push before every call, pop U{1..depth} every 10 calls",
+           "calls": props, "props_per_s": round(props / el, 1),
+           "latency_us": {"p50": round(float(np.percentile(lat_us, 50)), 2),
+                          "p99": round(float(np.percentile(lat_us, 99)), 2)},
+           "schedule": "resident engine" if table.resident else "launched"}
+    if cpu:
+        from oracle import oracle as O
+        o = O.OracleTable(spec.tuples, spec.lo, spec.dsizes, fast=True)
+
+        class OracleSut:
+            def propagate(self, d):
+                return o.propagate(d)
+
+            def push(self):
+                o.push()
+
+            def pop(self):
+                o.pop()
+
+        t0 = time.perf_counter()
+        oprops = sum(replay(OracleSut(), script) for _ in range(reps))
+        out["oracle_fast_props_per_s"] = round(oprops / (time.perf_counter() - t0), 1)
+    table.close()
     return out
 
 
@@ -465,7 +613,7 @@ def root_batch_leg(tabs, specs, reps, per_table=True):
     return out
 
 
-def model_leg(seed, steps, plain_steps, cpu):
+def model_leg(seed, steps, cpu):
     """Batched CT across constraints: 2,000 tables over a pool of 5,000
     variables, root fixpoint then `steps` search steps (push, remove 5 % of
     the values of 1-3 pool variables, fixpoint; every 10 steps pop
@@ -504,8 +652,20 @@ def model_leg(seed, steps, plain_steps, cpu):
     rng = W.rng_for(seed, 3, 99)
     bt = W.Backtracker(rng)
     stack, pool, script = [], root.copy(), []
+    var_tabs = {}
+    for c, sc in enumerate(spec.scopes):
+        for v in sc:
+            var_tabs.setdefault(int(v), []).append(c)
+    seeds = []
     for k in range(steps):
         new = W.pick_fraction_removal(rng, lay, pool)
+        # tables whose scope holds a variable the step changes
+        touched = set()
+        for v in range(lay.n):
+            o_, w_ = int(lay.off[v]), int(lay.words[v])
+            if (new[o_:o_ + w_] != pool[o_:o_ + w_]).any():
+                touched.update(var_tabs.get(v, []))
+        seeds.append(sorted(touched))
         M.push()
         stack.append(pool)
         out = dev(new)
@@ -539,21 +699,22 @@ def model_leg(seed, steps, plain_steps, cpu):
            "autotuned_solo_max_granules": best, "root_props": props, "root_rounds": rounds,
            "steps": steps, "batched_props": bprops, "batched_step_props_per_s": round(bprops / batched_s, 1),
            "batched_ms_per_step": round(batched_s / steps * 1e3, 3), "root_gac_batch": root_batch}
-    # plain GPU baseline (one launch per table propagation) on the first steps
+    # plain GPU baseline: AC-3 on the host, one synchronous launch per table
+    # propagation, seeded like the batched model's first round with the
+    # tables the step touches; the same steps as the batched run
     pm = PlainModel(tabs, spec.scopes, lay)
     pm.push()
     p0 = time.perf_counter()
     _, _, rprops = pm.fixpoint(full)
     out["plain_root_ms"] = round((time.perf_counter() - p0) * 1e3, 3)
     pm.pop()
-    pcnt, pstep = 0, 0
+    pcnt, pstep, si = 0, 0, 0
     p0 = time.perf_counter()
     for kind, x in script:
-        if pstep >= plain_steps and kind == "step":
-            break
         if kind == "step":
             pm.push()
-            st3, _, pp = pm.fixpoint(x)
+            st3, _, pp = pm.fixpoint(x, seed=seeds[si])
+            si += 1
             pcnt += pp
             pstep += 1
         else:
@@ -562,15 +723,18 @@ def model_leg(seed, steps, plain_steps, cpu):
     while pm.stack:
         pm.pop()
     out["plain_steps"] = pstep
+    out["plain_props"] = pcnt
     out["plain_step_props_per_s"] = round(pcnt / plain_s, 1)
     out["plain_ms_per_step"] = round(plain_s / max(pstep, 1) * 1e3, 3)
-    # both reach the same closure each step; the one-launch-per-table AC-3
-    # propagates every table once per step, the rounds only tables whose
-    # variables changed, so the per-step time is the like-for-like figure
-    out["batched_speedup_per_step"] = round(out["plain_ms_per_step"] / out["batched_ms_per_step"], 1)
+    # both reach the same closure from the same input every step; per-step
+    # time is the like-for-like figure (the two count slightly different
+    # propagations: the plain queue also runs a touched table whose own
+    # domains lost nothing)
+    out["batched_speedup_per_step"] = round(out["plain_ms_per_step"] / out["batched_ms_per_step"], 2)
+    out["batched_wins"] = bool(out["batched_ms_per_step"] < out["plain_ms_per_step"])
     if cpu:
         from oracle import oracle as O
-        ots = [O.OracleTable(tb.tuples, tb.lo, tb.dsizes) for tb in spec.tables]
+        ots = [O.OracleTable(tb.tuples, tb.lo, tb.dsizes, fast=True) for tb in spec.tables]
         c0 = time.perf_counter()
         for o in ots:
             o.push()
@@ -579,38 +743,43 @@ def model_leg(seed, steps, plain_steps, cpu):
         out["root_matches_oracle"] = bool(ost == st and (ost != 0 or (opool == root).all()))
         for o in ots:
             o.pop()
-        ocnt, ostep = 0, 0
+        ocnt, ostep, si = 0, 0, 0
         c0 = time.perf_counter()
         for kind, x in script:
             if kind == "step":
-                if ostep >= plain_steps:
-                    break
                 for o in ots:
                     o.push()
-                _, _, pp = O.fixpoint(ots, spec.scopes, lay, x)
+                _, _, pp = O.fixpoint(ots, spec.scopes, lay, x, seed=seeds[si])
+                si += 1
                 ocnt += pp
                 ostep += 1
             else:
                 for o in ots:
                     o.pop()
         oel = time.perf_counter() - c0
+        out["oracle_steps"] = ostep
+        out["oracle_props"] = ocnt
         out["oracle_step_props_per_s"] = round(ocnt / oel, 1)
         out["oracle_ms_per_step"] = round(oel / max(ostep, 1) * 1e3, 3)
+        out["oracle_note"] = ("fast mode, 1 thread, seeded FIFO AC-3; every push / pop visits all "
+                              "2,000 tables")
     return out
 
 
-def serve_leg(tables_spec, seed, rate, n_requests, n_searches, budget, sample_check):
-    """Serving loop: Poisson arrivals at `rate` requests/s, each given to a
-    random idle search among `n_searches` simulated DFS searches bound to
-    uniformly drawn tables of the 300-table mix; latency = completion time -
-    arrival time (arrivals wait while no search is idle)."""
+def serve_leg(tables_spec, seed, rate, n_requests, n_searches, budget, sample_check, tabs=None):
+    """Serving loop: Poisson arrivals at `rate` requests/s (rate <= 0: every
+    request arrives at once, a saturation run), each given to a random idle
+    search among `n_searches` simulated DFS searches bound to uniformly drawn
+    tables of the 300-table mix; latency = completion time - arrival time
+    (arrivals wait while no search is idle)."""
     import collections
     import numpy as np
     import torch
     from paper_2507_18413_amd import ct
     from paper_2507_18413_amd import workloads as W
     t0 = time.perf_counter()
-    tabs = [ct.Table(sp.tuples, sp.lo, sp.dsizes, max_depth=MAX_DEPTH_SERVE) for sp in tables_spec]
+    if tabs is None:
+        tabs = [ct.Table(sp.tuples, sp.lo, sp.dsizes, max_depth=MAX_DEPTH_SERVE) for sp in tables_spec]
     build_s = time.perf_counter() - t0
     rng = W.rng_for(seed, 5, 777)
     # per-table pools of deltas: U{1..4} variables, ceil(5 %) of each one's
@@ -632,7 +801,7 @@ def serve_leg(tables_spec, seed, rate, n_requests, n_searches, budget, sample_ch
     count = np.zeros(n_searches, np.int64)
     length = rng.integers(50, 201, size=n_searches)
     failed = np.zeros(n_searches, bool)
-    arrivals = W.poisson_arrivals(rng, rate, n_requests)
+    arrivals = W.poisson_arrivals(rng, rate, n_requests) if rate > 0 else np.zeros(n_requests)
     idle = list(range(n_searches))
     waiting = collections.deque()
     t_arr, t_launch, t_done, sreq = {}, [], [], {}
@@ -703,6 +872,8 @@ def serve_leg(tables_spec, seed, rate, n_requests, n_searches, budget, sample_ch
                           "p99": round(float(np.percentile(lat, 99)), 1),
                           "mean": round(float(lat.mean()), 1)},
            "launches": st["launches"], "mean_batch": round(n_requests / max(st["launches"], 1), 2),
+           "max_batch": st["max_batch"], "multi_request_launches": st["multi_request_launches"],
+           "multi_table_launches": st["multi_table_launches"],
            "admission_waits": st["admission_waits"], "peak_slot_bytes": st["peak_slot_bytes"],
            "slots_allocated": st["slots_allocated"], "mem_budget": budget}
     # the sampled searches replayed alone on the oracle must give the same results
@@ -734,6 +905,45 @@ def serve_leg(tables_spec, seed, rate, n_requests, n_searches, budget, sample_ch
     return out
 
 
+def host_info():
+    """Cores and CPU model of the machine the run is on."""
+    model = None
+    try:
+        for ln in open("/proc/cpuinfo"):
+            if ln.startswith("model name"):
+                model = ln.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count()
+    return {"cpu_model": model, "nproc": os.cpu_count(), "usable_cores": usable, "under_profiler": under_profiler()}
+
+
+def copy_probe(mib=2048, reps=10):
+    """Device-to-device copy of `mib` MiB by the runtime: HBM bytes moved
+    (read + write) per second, the measured ceiling beside the 8 TB/s peak."""
+    import torch
+    n = mib * (1 << 20) // 8
+    src = torch.ones(n, dtype=torch.int64, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del src, dst
+    torch.cuda.empty_cache()
+    return {"bytes": 2 * mib * (1 << 20), "ms": round(ms, 4),
+            "GBps": round(2 * mib * (1 << 20) / ms / 1e6, 1), "what": f"torch copy_ of {mib} MiB (read + write)"}
+
+
 def calibration_copy(mib):
     """One device-to-device copy of `mib` MiB by the runtime (the reference
     dispatch that scales the HBM byte counters)."""
@@ -747,6 +957,22 @@ def calibration_copy(mib):
     dst.copy_(src)
     torch.cuda.synchronize()
     del src, dst
+
+
+def under_profiler(env=None):
+    """True when a profiler's preload library is in the process (rocprofv3
+    loads its tool library before the program starts, and that library has
+    already initialised the GPU)."""
+    env = os.environ if env is None else env
+    pre = env.get("LD_PRELOAD", "")
+    return "rocprof" in pre or any(k.startswith("ROCPROF") for k in env)
+
+
+def serving_workers(env=None):
+    """Worker threads for generating the serving mix (threads, never
+    processes: under a profiler the GPU is initialised before main() runs,
+    and such a process must not start fresh interpreters)."""
+    return min(16, os.cpu_count() or 1)
 
 
 def note(msg):
@@ -788,10 +1014,9 @@ def main():
         return
     serve_spec = None
     if not args.no_serve:
-        # generated before the GPU is initialised: the pool's workers are
-        # fresh interpreters
-        note("generating the serving mix (300 tables)")
-        serve_spec = W.serving_tables(seed, workers=min(16, os.cpu_count() or 1))
+        workers = serving_workers()
+        note(f"generating the serving mix (300 tables, {workers} threads)")
+        serve_spec = W.serving_tables(seed, workers=workers)
     note("plain leg: building the 200,000-tuple table")
     torch.cuda.set_device(0)
     calibration_copy(args.calibration_copy)
@@ -814,6 +1039,9 @@ def main():
         replay(table, script)
     torch.cuda.synchronize()
     s0 = table.stats()
+    # the warmup's engine launch ends here, so that the timed calls are
+    # served by launches whose whole lifetime is measured
+    ct.quiesce()
     table.set_timing(True)
     lat = []
     torch.cuda.synchronize()
@@ -824,6 +1052,7 @@ def main():
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     kernel_ms, launches = table.timing()
+    disp_ms, dispatches = table.dispatch_timing()
     table.set_timing(False)
     s1 = table.stats()
     d = {k: s1[k] - s0[k] for k in s1}
@@ -831,18 +1060,26 @@ def main():
     value = props / elapsed
     lat_us = np.array(lat) * 1e6
     bytes_total = algorithmic_bytes(d, lay.D, props)
-    per_launch_bytes = bytes_total / max(launches, 1)
-    avg_kernel_s = kernel_ms / 1e3 / max(launches, 1)
-    achieved = per_launch_bytes / avg_kernel_s / 1e9 if avg_kernel_s > 0 else 0.0
+    bytes_per_call = bytes_total / max(props, 1)
+    # roofline of the dominant kernel: the algorithmic bytes of the calls a
+    # launch served over the launch's lifetime (device clock, every launch
+    # of the timed region); for the resident engine a launch serves many
+    # calls and its lifetime includes the waits for the next call
+    achieved = bytes_total / (disp_ms / 1e3) / 1e9 if disp_ms > 0 else 0.0
+    busy_s = kernel_ms / 1e3
 
     from paper_2507_18413_amd import profiling
     kname = "ctk::engine_kernel" if table.resident else "ctk::propagate_kernel"
     prof = profiling.read_summary(os.path.join(
         ROOT, "profiles", "engine_large_table.md" if table.resident else "propagate_large_table.md"))
-    # HBM bytes per call: per dispatch for launched calls; for the engine,
-    # per call (its dispatches serve many calls each)
-    traffic = (prof.get("hbm_bytes_per_call") if table.resident else prof.get("hbm_bytes_per_launch")) \
-        if prof else None
+    calls_per_launch = props / max(dispatches, 1)
+    # HBM bytes per launch of the timed region: the profiled bytes per call
+    # (the engine's dispatches serve many calls each) times the calls a
+    # timed launch served
+    traffic = None
+    if prof:
+        per_call = prof.get("hbm_bytes_per_call") if table.resident else prof.get("hbm_bytes_per_launch")
+        traffic = None if per_call is None else round(per_call * calls_per_launch, 1)
     out = {
         "metric": "CT propagations/sec (plain calls, one large table)",
         "value": round(value, 1),
@@ -865,17 +1102,28 @@ def main():
         "latency_us": {"p50": round(float(np.percentile(lat_us, 50)), 2),
                        "p99": round(float(np.percentile(lat_us, 99)), 2),
                        "mean": round(float(lat_us.mean()), 2)},
-        "kernel": {"name": kname, "calls": launches,
-                   "device_us_per_call": round(avg_kernel_s * 1e6, 3),
-                   "timing": "device clock inside the kernel, per call (a resident engine serves many "
-                             "calls per dispatch)" if table.resident else
-                             "device clock inside the kernel, per launch",
-                   "support_words_per_s": round(d["granule_rows"] * 64 / elapsed, 1)},
+        "kernel": {"name": kname, "calls": props, "launches": dispatches,
+                   "calls_per_launch": round(calls_per_launch, 1),
+                   "launch_us_avg": round(disp_ms * 1e3 / max(dispatches, 1), 3),
+                   "launch_us_per_call": round(disp_ms * 1e3 / max(props, 1), 3),
+                   "busy_us_per_call": round(busy_s * 1e6 / max(launches, 1), 3),
+                   "timing": "device clock: launch lifetimes (from the launch's start to its exit, the "
+                             "engine's waits for calls included) and, per call, the time from command "
+                             "receipt to publication" if table.resident else
+                             "device clock: launch lifetimes (earliest workgroup start to latest end)",
+                   "support_words_per_s": round(d["granule_rows"] * 64 / elapsed, 1),
+                   "achieved_GBps_busy": round(bytes_total / busy_s / 1e9, 2) if busy_s > 0 else None},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": traffic,
-                     "bytes_per_call": round(per_launch_bytes, 1)},
+                     "frac": round(achieved / HBM_PEAK_GBS, 6), "traffic": traffic,
+                     "bytes_per_launch": round(bytes_total / max(dispatches, 1), 1),
+                     "bytes_per_call": round(bytes_per_call, 1)},
+        "host": host_info(),
     }
     note(f"plain leg done: {value:.0f} propagations/s")
+    note("tiny-table leg")
+    out["tiny_table"] = tiny_leg(seed, 50, not args.no_cpu_baseline)
+    note("copy probe")
+    out["copy_probe"] = copy_probe()
     if not args.no_split:
         note("split propagators on the plain script")
         out["split_propagators"] = split_leg(table, script, max(1, args.steps))
@@ -883,8 +1131,22 @@ def main():
         # first of the other legs: its tables (gigabytes of host arrays) are
         # released before the batched legs time their host-side issue
         note("serving leg")
+        stabs = [ct.Table(sp.tuples, sp.lo, sp.dsizes, max_depth=MAX_DEPTH_SERVE) for sp in serve_spec]
         out["serving"] = serve_leg(serve_spec, seed, args.serve_rate, args.serve_requests, 512,
-                                   args.serve_budget, 0 if args.no_cpu_baseline else 8)
+                                   args.serve_budget, 0 if args.no_cpu_baseline else 8, tabs=stabs)
+        note("serving leg: saturation and a memory budget")
+        sat = serve_leg(serve_spec, seed + 1, 0.0, args.serve_requests // 4, 512, 0, 0, tabs=stabs)
+        peak = out["serving"]["peak_slot_bytes"]
+        bud = serve_leg(serve_spec, seed + 2, 0.0, args.serve_requests // 8, 512, max(1, peak // 4),
+                        0 if args.no_cpu_baseline else 4, tabs=stabs)
+        out["serving"]["saturation"] = {k: sat[k] for k in ("requests", "throughput_req_per_s", "latency_us",
+                                                          "launches", "mean_batch", "max_batch",
+                                                          "multi_table_launches")}
+        out["serving"]["budget_quarter_of_peak"] = {
+            k: bud[k] for k in ("requests", "mem_budget", "throughput_req_per_s", "latency_us", "mean_batch",
+                                "admission_waits", "peak_slot_bytes", "sampled_searches_equal_alone")
+            if k in bud}
+        del stabs
         serve_spec = None
         gc.collect()
     if not args.no_wide:
@@ -898,17 +1160,30 @@ def main():
     if not args.no_nodes:
         gc.collect()
         note("search-node leg")
-        out["batched_nodes"] = nodes_leg(seed, args.nodes, max(20, args.steps), 1)
+        out["batched_nodes"] = nodes_leg(seed, args.nodes, max(20, args.steps), 1,
+                                         cpu=not args.no_cpu_baseline)
     if not args.no_model:
         gc.collect()
         note("multi-table model leg")
-        out["batched_model"] = model_leg(seed, args.model_steps, 20, not args.no_cpu_baseline)
+        out["batched_model"] = model_leg(seed, args.model_steps, not args.no_cpu_baseline)
     if not args.no_cpu_baseline:
         note("oracle on the host cores")
-        cps, cprops, cel, passes = cpu_baseline(spec, script, args.cpu_seconds)
+        cps, cprops, cel, passes, wpc, bpc = cpu_baseline(spec, script, args.cpu_seconds)
+        pps, pprops, pel, ppasses, _, _ = cpu_baseline(spec, script, max(1.0, args.cpu_seconds / 4), fast=False)
+        hi = host_info()
         out["cpu_baseline"] = {"value": round(cps, 1), "unit": "propagations/s", "cores": 1, "kind": "oracle",
                                "sample": f"{passes} replays of the same {n_calls}-call script "
-                                         f"({cprops} propagations, {cel:.1f} s, 1 thread)"}
+                                         f"({cprops} propagations, {cel:.1f} s, 1 thread; the oracle's "
+                                         f"fast mode: sparse word list, residues, word trail)",
+                               "mode": "fast", "cpu_model": hi["cpu_model"], "nproc": hi["nproc"],
+                               "usable_cores": hi["usable_cores"],
+                               "support_words_per_call": round(wpc, 1),
+                               "support_words_per_s": round(wpc * cps, 1),
+                               "algorithmic_bytes_per_call": round(bpc, 1),
+                               "plain_mode": {"value": round(pps, 1), "sample": f"{ppasses} replays, {pel:.1f} s, "
+                                                                               "1 thread (dense Alg. 1-3)"},
+                               "why_one_core": "the calls of one search depend on each other: each is the "
+                                               "next call's input"}
     print(json.dumps(out), flush=True)
 
 

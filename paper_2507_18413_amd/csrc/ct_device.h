@@ -224,7 +224,8 @@ struct EngRes {             // written by the engine, seq last (release)
   int32_t seq, status, alive, exitSeq;
   uint64_t dom[INLINE_WORDS];
   unsigned long long stats[8];  // the slot's counters after the call
-  unsigned long long callTicks, pad2;  // device clock (100 MHz) spent in the call
+  unsigned long long callTicks;  // device clock (100 MHz) spent in the call
+  unsigned long long lifeTicks;  // written at exit: the launch's lifetime (device clock)
 };
 
 struct EngDesc {

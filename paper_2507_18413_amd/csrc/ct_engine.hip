@@ -656,6 +656,7 @@ __global__ void __launch_bounds__(EBLOCK) engine_kernel(EngDesc D) {
   EngCmd* cmd = D.cmd;
   EngRes* res = D.res;
 
+  const unsigned long long tLife = wall_clock64();
   e_load(E, D);
   for (;;) {
     // wave 0 waits for a call (bounded: an idle engine exits), then reads
@@ -757,6 +758,7 @@ __global__ void __launch_bounds__(EBLOCK) engine_kernel(EngDesc D) {
   e_store(E);
   if (threadIdx.x == 0) {
     res->exitSeq = st->lastSeq;
+    res->lifeTicks = wall_clock64() - tLife;
     __threadfence_system();
     __hip_atomic_store(&res->alive, 0, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
   }

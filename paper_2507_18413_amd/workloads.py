@@ -332,7 +332,9 @@ def serving_tables(seed: int = DEFAULT_SEED, n_tables: int = 300, arity=(3, 10),
     """Serving mix: even-index tables uniform, odd-index Zipf(s) columns.
 
     Each table's tuples come from its own stream, so the result does not
-    depend on ``workers`` (> 1: a pool of fresh interpreter processes)."""
+    depend on ``workers`` (> 1: a pool of threads; numpy's sorting and
+    drawing release the interpreter lock, and no process is started, so the
+    call is safe in a process that already uses the GPU)."""
     rng = rng_for(seed, 5, 0)
     jobs = []
     for c in range(n_tables):
@@ -343,9 +345,9 @@ def serving_tables(seed: int = DEFAULT_SEED, n_tables: int = 300, arity=(3, 10),
         t = max(1, min(t, space // 2))
         jobs.append((seed, c, ds, t, s))
     if workers and workers > 1:
-        import multiprocessing as mp
-        with mp.get_context("spawn").Pool(workers) as pool:
-            return pool.map(_serving_one, jobs, chunksize=1)
+        from concurrent.futures import ThreadPoolExecutor
+        with ThreadPoolExecutor(workers) as ex:
+            return list(ex.map(_serving_one, jobs))
     return [_serving_one(j) for j in jobs]
 
 
