@@ -39,6 +39,7 @@
  * work counters by hand counts on Table 1 and by counts taken from the
  * previous call's currTable.
  */
+#define _GNU_SOURCE /* qsort_r */
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -49,6 +50,10 @@
 #define CTO_E_NOT_SUBSET (-2)
 #define CTO_E_STATE (-3)
 #define CTO_E_NOMEM (-4)
+
+#define CTO_KIND_POSITIVE 0    /* the tuples list the allowed combinations */
+#define CTO_KIND_NEGATIVE 1    /* the tuples list the forbidden combinations */
+#define CTO_STAR ((int32_t)0x80000000)  /* a cell of a short table: any value */
 
 #define CTO_MODE_AUTO 0        /* Alg. 2's branch rule */
 #define CTO_MODE_RESET 1       /* always OR over dom(x_i)  */
@@ -75,7 +80,11 @@ typedef struct {
     int64_t t, W;
     int rows, D;
     int32_t *lo, *dsz, *row_start, *dom_off, *dom_words;
-    uint64_t *S;        /* rows x W: supports[x_i, v] (Sec. 2) */
+    int kind;           /* CTO_KIND_POSITIVE or CTO_KIND_NEGATIVE */
+    int has_star;       /* a short table: some cell holds CTO_STAR */
+    uint64_t *S;        /* rows x W: supports[x_i, v] (Sec. 2); a star cell
+                           supports every value of its column */
+    uint64_t *S_strict; /* short tables only: the cells that name v itself */
     uint64_t *ct;       /* W: currTable */
     uint64_t *last_dom; /* D: domains after the previous call */
     int32_t *last_sizes;/* n: lastSizes of Alg. 1 */
@@ -118,6 +127,14 @@ static int has_value(const cto_table *T, const uint64_t *dom, int i, int a) {
 static uint64_t *row_ptr(const cto_table *T, int i, int a) {
     /* supportJmp[i] + (v - variablesOffsets[i]) of Sec. 3, with a = v - lo_i */
     return T->S + (int64_t)(T->row_start[i] + a) * T->W;
+}
+
+/* the row OR-ed by the incremental branch: a removed value invalidates only
+ * the tuples that name it (a star cell keeps its tuple valid while the
+ * column's domain is not empty) */
+static uint64_t *strict_row_ptr(const cto_table *T, int i, int a) {
+    if (!T->S_strict) return row_ptr(T, i, a);
+    return T->S_strict + (int64_t)(T->row_start[i] + a) * T->W;
 }
 
 static int any_word(const uint64_t *x, int64_t W) {
@@ -166,7 +183,7 @@ static void filter_domains(cto_table *T, uint64_t *dom, const char *s_sup) {
 void cto_destroy(cto_table *T) {
     if (!T) return;
     free(T->lo); free(T->dsz); free(T->row_start); free(T->dom_off); free(T->dom_words);
-    free(T->S); free(T->ct); free(T->last_dom); free(T->last_sizes);
+    free(T->S); free(T->S_strict); free(T->ct); free(T->last_dom); free(T->last_sizes);
     free(T->snap_ct); free(T->snap_dom); free(T->snap_sizes); free(T->snap_failed);
     free(T->idx); free(T->res); free(T->fmask); free(T->stamp); free(T->tr_w); free(T->tr_v);
     free(T->lv_top); free(T->lv_limit); free(T->lv_serial);
@@ -178,14 +195,50 @@ void cto_destroy(cto_table *T) {
  * the root propagation (Sec. 3, constructor).  Returns CTO_OK, CTO_FAIL (the
  * handle exists, in the failed state), or an error with *out = NULL.
  */
-int cto_create(const int32_t *tuples, int64_t t, int32_t n, const int32_t *lo,
-               const int32_t *dsz, const uint64_t *init_dom, cto_table **out) {
+/* qsort_r comparator of tuple indices by their rows */
+static int cmp_rows(const void *pa, const void *pb, void *arg) {
+    const int32_t *tup = (const int32_t *)((void **)arg)[0];
+    const int n = *(const int *)((void **)arg)[1];
+    const int64_t a = *(const int64_t *)pa, b = *(const int64_t *)pb;
+    for (int i = 0; i < n; i++) {
+        int32_t x = tup[a * n + i], y = tup[b * n + i];
+        if (x != y) return x < y ? -1 : 1;
+    }
+    return 0;
+}
+
+/* 1 if two tuples are equal (sort of the indices) */
+static int has_duplicates(const int32_t *tuples, int64_t t, int n) {
+    if (t < 2) return 0;
+    int64_t *ix = (int64_t *)malloc(sizeof(int64_t) * t);
+    if (!ix) return -1;
+    for (int64_t j = 0; j < t; j++) ix[j] = j;
+    int nn = n;
+    void *arg[2] = {(void *)tuples, &nn};
+    qsort_r(ix, (size_t)t, sizeof(int64_t), cmp_rows, arg);
+    int dup = 0;
+    for (int64_t j = 1; j < t && !dup; j++) dup = cmp_rows(&ix[j - 1], &ix[j], arg) == 0;
+    free(ix);
+    return dup;
+}
+
+static int filter_negative(cto_table *T, uint64_t *dom);
+
+static int create_impl(const int32_t *tuples, int64_t t, int32_t n, const int32_t *lo,
+                       const int32_t *dsz, const uint64_t *init_dom, int32_t kind, cto_table **out) {
     *out = NULL;
     if (n < 1 || t < 0 || !lo || !dsz || (t > 0 && !tuples)) return CTO_E_INVALID;
+    if (kind != CTO_KIND_POSITIVE && kind != CTO_KIND_NEGATIVE) return CTO_E_INVALID;
     for (int i = 0; i < n; i++)
         if (dsz[i] < 1) return CTO_E_INVALID;
+    int star = 0;
+    for (int64_t k = 0; k < t * n && !star; k++) star = tuples[k] == CTO_STAR;
+    /* a negative table lists distinct combinations and has no star cell */
+    if (kind == CTO_KIND_NEGATIVE && (star || has_duplicates(tuples, t, n) != 0)) return CTO_E_INVALID;
     cto_table *T = (cto_table *)calloc(1, sizeof(cto_table));
     if (!T) return CTO_E_NOMEM;
+    T->kind = kind;
+    T->has_star = star;
     T->n = n;
     T->t = t;
     T->W = (t + 63) / 64;
@@ -215,15 +268,21 @@ int cto_create(const int32_t *tuples, int64_t t, int32_t n, const int32_t *lo,
     T->S = (uint64_t *)calloc((size_t)rows * (size_t)Wa, sizeof(uint64_t));
     T->ct = (uint64_t *)calloc((size_t)Wa, sizeof(uint64_t));
     T->last_dom = (uint64_t *)calloc((size_t)D, sizeof(uint64_t));
-    if (!T->S || !T->ct || !T->last_dom) {
+    if (star) T->S_strict = (uint64_t *)calloc((size_t)rows * (size_t)Wa, sizeof(uint64_t));
+    if (!T->S || !T->ct || !T->last_dom || (star && !T->S_strict)) {
         cto_destroy(T);
         return CTO_E_NOMEM;
     }
     for (int64_t j = 0; j < t; j++) {
         for (int i = 0; i < n; i++) {
+            if (tuples[j * n + i] == CTO_STAR) { /* short table: every value of x_i */
+                for (int a = 0; a < dsz[i]; a++) row_ptr(T, i, a)[j / 64] |= 1ull << (j % 64);
+                continue;
+            }
             int64_t v = (int64_t)tuples[j * n + i] - lo[i];
             if (v < 0 || v >= dsz[i]) continue; /* value outside dom0: no row */
             row_ptr(T, i, (int)v)[j / 64] |= 1ull << (j % 64);
+            if (star) strict_row_ptr(T, i, (int)v)[j / 64] |= 1ull << (j % 64);
         }
     }
     /* initial domains */
@@ -257,6 +316,13 @@ int cto_create(const int32_t *tuples, int64_t t, int32_t n, const int32_t *lo,
     }
     free(mask);
     for (int i = 0; i < n; i++) T->last_sizes[i] = var_size(T, T->last_dom, i);
+    if (kind == CTO_KIND_NEGATIVE) {
+        free(s_sup);
+        int st = filter_negative(T, T->last_dom);
+        if (st == CTO_FAIL) T->failed = 1;
+        *out = T;
+        return st;
+    }
     if (!any_word(T->ct, T->W)) {
         T->failed = 1;
         free(s_sup);
@@ -268,6 +334,81 @@ int cto_create(const int32_t *tuples, int64_t t, int32_t n, const int32_t *lo,
     free(s_sup);
     *out = T;
     return CTO_OK;
+}
+
+/*
+ * Build supports (Sec. 2: cell ([x_i, v], j) is 1 iff tau_j[i] = v; a star
+ * cell of a short table -- the paper's footnote on short tables, Sec. 2 --
+ * supports every value of its column) and run the root propagation (Sec. 3,
+ * constructor).  Returns CTO_OK, CTO_FAIL (the handle exists, in the failed
+ * state), or an error with *out = NULL.
+ */
+int cto_create(const int32_t *tuples, int64_t t, int32_t n, const int32_t *lo,
+               const int32_t *dsz, const uint64_t *init_dom, cto_table **out) {
+    return create_impl(tuples, t, n, lo, dsz, init_dom, CTO_KIND_POSITIVE, out);
+}
+
+/* cto_create for a positive (kind 0) or negative (kind 1) table.  A negative
+ * table lists forbidden combinations (the paper's footnote, Sec. 2): the
+ * valid tuples are the combinations of the domains that it does not list;
+ * its tuples must be distinct and hold no star (CTO_E_INVALID). */
+int cto_create_kind(const int32_t *tuples, int64_t t, int32_t n, const int32_t *lo,
+                    const int32_t *dsz, const uint64_t *init_dom, int32_t kind, cto_table **out) {
+    return create_impl(tuples, t, n, lo, dsz, init_dom, kind, out);
+}
+
+/*
+ * filterDomains of a negative table.  currTable holds the listed (forbidden)
+ * tuples whose every value is in the current domains.  Value a of x_i has a
+ * valid (allowed) tuple iff fewer than prod_{k != i} |dom(x_k)| of the
+ * combinations with x_i = a are listed, i.e. iff
+ * popcount(currTable & supports[x_i, a]) < prod_{k != i} |dom(x_k)|.
+ * Every variable is filtered (a singleton too: its value may have no
+ * allowed tuple), each decision on the input domains.  Removing unsupported
+ * values removes no allowed tuple, so one pass reaches GAC.  The listed
+ * tuples naming a removed value then leave currTable, so that currTable
+ * stays the listed tuples valid under the output domains.  CTO_FAIL iff a
+ * domain is empty.
+ */
+static int filter_negative(cto_table *T, uint64_t *dom) {
+    const int n = T->n;
+    const int64_t cap = T->t + 1; /* a count never exceeds t */
+    int32_t *size = (int32_t *)malloc(sizeof(int32_t) * n);
+    uint64_t *out = (uint64_t *)malloc(sizeof(uint64_t) * T->D);
+    if (!size || !out) {
+        free(size); free(out);
+        return CTO_E_NOMEM;
+    }
+    for (int i = 0; i < n; i++) size[i] = var_size(T, dom, i);
+    memcpy(out, dom, sizeof(uint64_t) * T->D);
+    for (int i = 0; i < n; i++) {
+        int64_t prod = 1;
+        for (int k = 0; k < n; k++) {
+            if (k == i) continue;
+            prod *= size[k];
+            if (prod > cap) prod = cap;
+        }
+        for (int a = 0; a < T->dsz[i]; a++) {
+            if (!has_value(T, dom, i, a)) continue;
+            const uint64_t *r = row_ptr(T, i, a);
+            int64_t cnt = 0;
+            for (int64_t w = 0; w < T->W; w++) cnt += popc(T->ct[w] & r[w]);
+            if (cnt == prod) out[T->dom_off[i] + a / 64] &= ~(1ull << (a % 64));
+        }
+    }
+    int empty = 0;
+    for (int i = 0; i < n; i++) {
+        for (int a = 0; a < T->dsz[i]; a++) {
+            if (!has_value(T, dom, i, a) || has_value(T, out, i, a)) continue;
+            const uint64_t *r = row_ptr(T, i, a);
+            for (int64_t w = 0; w < T->W; w++) T->ct[w] &= ~r[w];
+        }
+        T->last_sizes[i] = var_size(T, out, i);
+        if (T->last_sizes[i] == 0) empty = 1;
+    }
+    memcpy(dom, out, sizeof(uint64_t) * T->D);
+    free(size); free(out);
+    return empty ? CTO_FAIL : CTO_OK;
 }
 
 int cto_layout(const cto_table *T, int32_t *D, int64_t *W, int32_t *rows, int32_t *depth) {
@@ -298,6 +439,15 @@ int cto_support_row(const cto_table *T, int32_t row, uint64_t *out) {
  * dom_in: the solver's current domains (must be a subset of the domains this
  * propagator returned last).  dom_out may alias dom_in.
  */
+/* Alg. 2's branch: incremental iff |Delta_i| < |dom(x_i)| (or forced); an
+ * emptied domain always takes the reset branch (OR over no value: no tuple
+ * survives -- with star cells the incremental branch would keep the tuples
+ * holding a star in that column). */
+static int branch_incremental(int32_t mode, int delta, int size) {
+    if (size == 0) return 0;
+    return mode == CTO_MODE_INCREMENTAL || (mode == CTO_MODE_AUTO && delta < size);
+}
+
 static int propagate_fast(cto_table *T, const uint64_t *dom_in, uint64_t *dom_out, uint64_t *ct_out,
                           int32_t mode);
 
@@ -343,7 +493,7 @@ int cto_propagate(cto_table *T, const uint64_t *dom_in, uint64_t *dom_out, uint6
         int delta = 0;
         for (int k = 0; k < T->dom_words[i]; k++)
             delta += popc(T->last_dom[T->dom_off[i] + k] & ~dom[T->dom_off[i] + k]);
-        int incremental = mode == CTO_MODE_INCREMENTAL || (mode == CTO_MODE_AUTO && delta < size[i]);
+        int incremental = branch_incremental(mode, delta, size[i]);
         T->st[CTO_ST_ROWS_SEL] += incremental ? delta : size[i];
     }
     /* Alg. 2: updateTable */
@@ -352,13 +502,13 @@ int cto_propagate(cto_table *T, const uint64_t *dom_in, uint64_t *dom_out, uint6
         int delta = 0;
         for (int k = 0; k < T->dom_words[i]; k++)
             delta += popc(T->last_dom[T->dom_off[i] + k] & ~dom[T->dom_off[i] + k]);
-        int incremental = mode == CTO_MODE_INCREMENTAL || (mode == CTO_MODE_AUTO && delta < size[i]);
+        int incremental = branch_incremental(mode, delta, size[i]);
         memset(mask, 0, sizeof(uint64_t) * Wa);
         for (int a = 0; a < T->dsz[i]; a++) {
             int was = has_value(T, T->last_dom, i, a), is = has_value(T, dom, i, a);
             int take = incremental ? (was && !is) : is;
             if (!take) continue;
-            const uint64_t *r = row_ptr(T, i, a);
+            const uint64_t *r = incremental ? strict_row_ptr(T, i, a) : row_ptr(T, i, a);
             for (int64_t w = 0; w < W; w++) mask[w] |= r[w];
             T->st[CTO_ST_ROWS_OR]++;
             T->st[CTO_ST_UPD_WORDS] += W;
@@ -366,7 +516,22 @@ int cto_propagate(cto_table *T, const uint64_t *dom_in, uint64_t *dom_out, uint6
         if (incremental)
             for (int64_t w = 0; w < W; w++) mask[w] = ~mask[w];
         for (int64_t w = 0; w < W; w++) T->ct[w] &= mask[w];
-        if (!any_word(T->ct, W)) break;
+        /* Alg. 2's break (a negative table has no early failure: an empty
+         * currTable means no combination is forbidden) */
+        if (T->kind == CTO_KIND_POSITIVE && !any_word(T->ct, W)) break;
+    }
+    if (T->kind == CTO_KIND_NEGATIVE) {
+        int st = filter_negative(T, dom);
+        if (st == CTO_FAIL) {
+            T->failed = 1;
+            if (ct_out) memset(ct_out, 0, sizeof(uint64_t) * W);
+        } else if (st == CTO_OK) {
+            memcpy(T->last_dom, dom, sizeof(uint64_t) * T->D);
+            if (dom_out) memcpy(dom_out, dom, sizeof(uint64_t) * T->D);
+            if (ct_out) memcpy(ct_out, T->ct, sizeof(uint64_t) * W);
+        }
+        free(dom); free(mask); free(size); free(s_val); free(s_sup);
+        return st;
     }
     /* Alg. 1: failure test */
     if (!any_word(T->ct, W)) {
@@ -553,14 +718,14 @@ static int propagate_fast(cto_table *T, const uint64_t *dom_in, uint64_t *dom_ou
         int delta = 0;
         for (int k = 0; k < T->dom_words[i]; k++)
             delta += popc(T->last_dom[T->dom_off[i] + k] & ~dom[T->dom_off[i] + k]);
-        int incremental = mode == CTO_MODE_INCREMENTAL || (mode == CTO_MODE_AUTO && delta < size[i]);
+        int incremental = branch_incremental(mode, delta, size[i]);
         T->st[CTO_ST_ROWS_SEL] += incremental ? delta : size[i];
         if (T->limit == 0) continue;  /* past Alg. 2's break: selected, not read */
         for (int64_t k = 0; k < T->limit; k++) T->fmask[T->idx[k]] = 0;
         for (int a = 0; a < T->dsz[i]; a++) {
             int was = has_value(T, T->last_dom, i, a), is = has_value(T, dom, i, a);
             if (!(incremental ? (was && !is) : is)) continue;
-            const uint64_t *r = row_ptr(T, i, a);
+            const uint64_t *r = incremental ? strict_row_ptr(T, i, a) : row_ptr(T, i, a);
             for (int64_t k = 0; k < T->limit; k++) T->fmask[T->idx[k]] |= r[T->idx[k]];
             T->st[CTO_ST_ROWS_OR]++;
             T->st[CTO_ST_UPD_WORDS] += T->limit;

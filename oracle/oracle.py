@@ -17,6 +17,8 @@ LIB_PATH = os.path.join(HERE, "libct_oracle.so")
 LIB_PATH = os.environ.get("CT_ORACLE_LIB", LIB_PATH)
 
 OK, FAIL, E_INVALID, E_NOT_SUBSET, E_STATE, E_NOMEM = 0, 1, -1, -2, -3, -4
+KIND_POSITIVE, KIND_NEGATIVE = 0, 1
+STAR = -(1 << 31)  # a cell of a short table: any value of the column
 MODE_AUTO, MODE_RESET, MODE_INCREMENTAL = 0, 1, 2
 
 _lib = None
@@ -34,6 +36,8 @@ def lib():
         L.cto_create.restype = C.c_int
         L.cto_create_fast.argtypes = [P, C.c_int64, C.c_int32, P, P, P, C.POINTER(P)]
         L.cto_create_fast.restype = C.c_int
+        L.cto_create_kind.argtypes = [P, C.c_int64, C.c_int32, P, P, P, C.c_int32, C.POINTER(P)]
+        L.cto_create_kind.restype = C.c_int
         L.cto_destroy.argtypes = [P]
         L.cto_layout.argtypes = [P, P, P, P, P]
         L.cto_get_state.argtypes = [P, P, P, P]
@@ -56,11 +60,16 @@ def _p(a):
 class OracleTable:
     """One table constraint with its reversible propagator state."""
 
-    def __init__(self, tuples, lo, dsizes, init_dom=None, fast=False):
+    def __init__(self, tuples, lo, dsizes, init_dom=None, fast=False, kind=KIND_POSITIVE):
         """fast: CT's sparse word list, residues and a word trail (same
-        results as the plain mode, which follows Alg. 1-3 densely)."""
+        results as the plain mode, which follows Alg. 1-3 densely; positive
+        tables only).  kind: KIND_POSITIVE (cells may hold STAR: a short
+        table) or KIND_NEGATIVE (the tuples are the forbidden combinations)."""
         L = lib()
         self.fast = bool(fast)
+        self.kind = int(kind)
+        if fast and kind != KIND_POSITIVE:
+            raise ValueError("the fast mode takes positive tables")
         tuples = np.ascontiguousarray(tuples, dtype=np.int32)
         self.n = int(len(dsizes))
         self.lo = np.ascontiguousarray(lo, dtype=np.int32)
@@ -69,9 +78,13 @@ class OracleTable:
         if init_dom is not None:
             init_dom = np.ascontiguousarray(init_dom, dtype=np.uint64)
         h = C.c_void_p()
-        create = L.cto_create_fast if fast else L.cto_create
-        st = create(_p(tuples) if t else None, t, self.n, _p(self.lo), _p(self.dsizes),
-                    _p(init_dom), C.byref(h))
+        if kind != KIND_POSITIVE:
+            st = L.cto_create_kind(_p(tuples) if t else None, t, self.n, _p(self.lo), _p(self.dsizes),
+                                   _p(init_dom), int(kind), C.byref(h))
+        else:
+            create = L.cto_create_fast if fast else L.cto_create
+            st = create(_p(tuples) if t else None, t, self.n, _p(self.lo), _p(self.dsizes),
+                        _p(init_dom), C.byref(h))
         self.create_status = st
         if h.value is None:
             raise ValueError(f"cto_create failed with status {st}")

@@ -53,3 +53,47 @@ def closure(tables, scopes, pool_sets):
                     pool[v] = out[k]
                     changed = True
     return False, pool
+
+
+STAR = -(1 << 31)  # a cell of a short table: any value of its column
+
+
+def gac_short(tuples, lo, dom_sets):
+    """Short table (cells may be STAR): a tuple is valid iff every cell is
+    STAR or names a value of the domain; GAC by enumerating the product and
+    testing each point against every tuple.  Returns (failed, out_sets,
+    valid_indices)."""
+    n = len(dom_sets)
+    rows = [[None if int(tp[i]) == STAR else int(tp[i]) - int(lo[i]) for i in range(n)] for tp in tuples]
+    keep = [set() for _ in range(n)]
+    any_point = False
+    for point in itertools.product(*[sorted(s) for s in dom_sets]):
+        if any(all(c is None or c == p for c, p in zip(r, point)) for r in rows):
+            any_point = True
+            for i, a in enumerate(point):
+                keep[i].add(a)
+    valid = [j for j, r in enumerate(rows)
+             if all((c is None and dom_sets[i]) or (c is not None and c in dom_sets[i]) for i, c in enumerate(r))]
+    if not any_point:
+        return True, None, []
+    return False, keep, valid
+
+
+def gac_negative(tuples, lo, dom_sets):
+    """Negative table: the tuples are forbidden; a point of the product is
+    allowed iff it is not listed.  Returns (failed, out_sets,
+    listed_indices_in_the_product_of_out_sets)."""
+    n = len(dom_sets)
+    listed = {tuple(int(tp[i]) - int(lo[i]) for i in range(n)) for tp in tuples}
+    keep = [set() for _ in range(n)]
+    any_point = False
+    for point in itertools.product(*[sorted(s) for s in dom_sets]):
+        if point not in listed:
+            any_point = True
+            for i, a in enumerate(point):
+                keep[i].add(a)
+    if not any_point:
+        return True, None, []
+    valid = [j for j, tp in enumerate(tuples)
+             if all(int(tp[i]) - int(lo[i]) in keep[i] for i in range(n))]
+    return False, keep, valid

@@ -21,7 +21,8 @@ MUTANTS = [
     ("s_sup threshold", "if (size[i] > 1) {", "if (size[i] > 2) {"),
     ("delta reversed", "int take = incremental ? (was && !is) : is;",
      "int take = incremental ? (is && !was) : is;"),
-    ("update stops after first variable", "if (!any_word(T->ct, W)) break;", "break;"),
+    ("update stops after first variable", "if (T->kind == CTO_KIND_POSITIVE && !any_word(T->ct, W)) break;",
+     "break;"),
     ("fixpoint never re-queues", "if (c2 == c || inq[c2]) continue;", "continue;"),
     ("OR instead of AND into currTable", "T->ct[w] &= mask[w];", "T->ct[w] |= mask[w];"),
     ("no stray-bit check", "int used = d - 64 * (T->dom_words[i] - 1);", "int used = 64;"),
@@ -37,6 +38,16 @@ MUTANTS = [
      "for (int64_t k = 0; k < T->limit; k++) T->fmask[T->idx[k]] |= r[T->idx[k]];",
      "for (int64_t k = 0; k + 1 < T->limit; k++) T->fmask[T->idx[k]] |= r[T->idx[k]];"),
     ("fast: pop keeps the limit", "T->limit = T->lv_limit[T->depth];", ";"),
+    # short and negative tables
+    ("negative: product includes the filtered variable", "if (k == i) continue;", ";"),
+    ("negative: removed values keep their tuples", "for (int64_t w = 0; w < T->W; w++) T->ct[w] &= ~r[w];", ";"),
+    ("negative: unsupported iff count below the product", "if (cnt == prod) out[", "if (cnt < prod) out["),
+    ("short: incremental branch ORs star rows",
+     "const uint64_t *r = incremental ? strict_row_ptr(T, i, a) : row_ptr(T, i, a);",
+     "const uint64_t *r = row_ptr(T, i, a);"),
+    ("short: emptied domain on the incremental branch", "if (size == 0) return 0;", ";"),
+    ("short: star cell supports no value", "for (int a = 0; a < dsz[i]; a++) row_ptr(T, i, a)[j / 64] |= 1ull << (j % 64);",
+     ";"),
     # work counters
     ("rows selected counts the domain on both branches", "T->st[CTO_ST_ROWS_SEL] += incremental ? delta : size[i];",
      "T->st[CTO_ST_ROWS_SEL] += size[i];"),
@@ -56,6 +67,7 @@ def test_pins_kill_mutant(name, old, new, tmp_path):
     env = dict(os.environ, CT_ORACLE_LIB=str(lib))
     r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
                         os.path.join(ROOT, "tests", "test_oracle.py"),
-                        os.path.join(ROOT, "tests", "test_oracle_fast.py")],
+                        os.path.join(ROOT, "tests", "test_oracle_fast.py"),
+                        os.path.join(ROOT, "tests", "test_oracle_kinds.py")],
                        cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
     assert r.returncode != 0, f"mutant survived the pins: {name}\n{r.stdout[-2000:]}"
