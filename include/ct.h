@@ -111,7 +111,8 @@ typedef struct {
     int32_t granules;   /* 64-word groups of currTable tracked by the sparse index */
     int32_t root_failed;/* 1 if the root propagation found no valid tuple */
     int32_t resident;   /* 1 if synchronous calls on slot 0 use the resident engine */
-    int32_t pad;
+    int32_t kind;       /* CT_KIND_POSITIVE, CT_KIND_SHORT (positive with star cells) or
+                           CT_KIND_NEGATIVE */
 } ct_layout_info;
 
 /* Cumulative per-slot work counters (never reset; take differences). */
@@ -136,12 +137,45 @@ typedef struct {
  * pointers owned by the caller and not retained.
  * Returns CT_OK, or CT_FAIL with *out valid but its root state failed, or
  * CT_E_INVALID (arity < 1 or > 256, n_tuples < 0, dom_size < 1, more than
- * 16384 support rows, stray init_dom bits), CT_E_NOMEM, CT_E_DEVICE with
+ * 2^22 support rows (sum of dom_size) or 65,536 domain words, more than
+ * 33,554,432 tuples, stray init_dom bits), CT_E_NOMEM, CT_E_DEVICE with
  * *out = NULL.
  */
 int ct_create(const int32_t *tuples, int64_t n_tuples, int32_t arity, const int32_t *dom_lo,
               const int32_t *dom_size, const uint64_t *init_dom, const ct_config *cfg,
               ct_table **out);
+
+/*
+ * ct_create_table -- ct_create for a table of a given kind (the table kinds
+ * of the paper's footnote on Sec. 2):
+ *   CT_KIND_POSITIVE: the tuples are the allowed combinations.  A cell may
+ *     hold CT_STAR, standing for every value of its column (a short table;
+ *     INT32_MIN is therefore not a value).  A star cell is in the support
+ *     row of every value of its column; a short table's updateTable takes
+ *     the reset branch of Alg. 2 for every changed variable (OR over the
+ *     remaining values: a star tuple stays valid while its column's domain is
+ *     not empty), so CT_BRANCH_INCREMENTAL is refused (CT_E_INVALID).
+ *   CT_KIND_NEGATIVE: the tuples are the forbidden combinations, distinct
+ *     and without stars, with at most 8,192 support rows and 1,024 domain
+ *     words (CT_E_INVALID otherwise).  The valid tuples are the
+ *     combinations of the domains that the table does not list; currTable
+ *     holds the listed tuples whose every value is in the slot's domains.
+ *     A value of x_i stays iff fewer than prod_{k != i} |dom(x_k)| listed
+ *     tuples with x_i = a are in currTable; every variable is filtered; the
+ *     listed tuples of removed values then leave currTable; CT_FAIL iff a
+ *     domain is empty (an empty currTable is no failure).  Calls run in one
+ *     workgroup each (CT_SCHED_SOLO), never on the resident engine, the
+ *     search-node or the root-stream schedules; the split propagators refuse
+ *     negative tables.
+ * Everything else is ct_create's contract.
+ */
+#define CT_KIND_POSITIVE 0
+#define CT_KIND_NEGATIVE 1
+#define CT_KIND_SHORT 2 /* reported by ct_layout only */
+#define CT_STAR ((int32_t)0x80000000)
+int ct_create_table(const int32_t *tuples, int64_t n_tuples, int32_t arity, const int32_t *dom_lo,
+                    const int32_t *dom_size, const uint64_t *init_dom, const ct_config *cfg, int32_t kind,
+                    ct_table **out);
 
 /* Frees every device and host resource of the table; NULL is ignored. */
 void ct_destroy(ct_table *t);
@@ -319,10 +353,28 @@ int ct_model_pop(ct_model *m);
  * default is chosen by ct_model_autotune or is (4, 8). */
 int ct_model_set_schedule(ct_model *m, int32_t solo_max_granules, int32_t rounds_per_graph);
 
-/* Autotuner: times one fixpoint from pool_in for each candidate threshold
- * (1, 4, 16, 64, 256 granules), restoring every table between trials with a
- * push / pop, keeps the fastest and returns it in *best (nullable). */
-int ct_model_autotune(ct_model *m, const uint64_t *pool_in, int32_t *best);
+/* Autotuner of the rounds' schedule.  Tables are grouped in classes by
+ * floor(log4) of their granule count and of their support-row count; each
+ * class gets a schedule: solo (one workgroup per table, 4 granules of 64
+ * words per wavefront per step) or split (update items spread over
+ * workgroups) with a tile of 2, 4 or 8 granules per wavefront per item.
+ * Classes are tuned one after the other, those with the most granules in all
+ * first, each candidate timed as the median of 3 fixpoints from pool_in
+ * (device pointer), every table restored between trials with a push / pop;
+ * every candidate must reach the same fixpoint (CT_E_DEVICE otherwise).
+ * cache_path (nullable): a JSON file of choices keyed by the device
+ * architecture and the class buckets ("gfx950 g2 r3": [solo, tile]); when
+ * it holds every class of the model, those choices are applied without
+ * timing anything (*from_cache = 1), otherwise the tuned choices are merged
+ * into it.  *timed (nullable) receives the number of candidates timed.
+ * Classes the tuner never saw follow ct_model_set_schedule's threshold with
+ * the default tile (2). */
+int ct_model_autotune(ct_model *m, const uint64_t *pool_in, const char *cache_path, int32_t *from_cache,
+                      int32_t *timed);
+/* Effective schedule of table `table` (index from ct_model_add) in the
+ * model's rounds: *solo = 1 for one workgroup per table, *tile = granules
+ * per wavefront per update step (solo) or item (split). */
+int ct_model_get_choice(const ct_model *m, int32_t table, int32_t *solo, int32_t *tile);
 
 /* ------------------------------------------------------------------------
  * Serving: continuous batching of propagate requests from many searches
@@ -457,6 +509,13 @@ int ct_get_dispatch_timing(ct_table *t, double *dispatch_ms, int64_t *dispatches
 
 /* Thread-local message of the last error ("" if none). */
 const char *ct_last_error(void);
+
+/* Test hook for the callers' error paths: the nth device or pinned host
+ * allocation the library makes from now on (tables, slots, batch staging,
+ * models) fails as if the memory were exhausted, and the call that made it
+ * returns CT_E_NOMEM after releasing what it had allocated; nth <= 0 turns
+ * the hook off.  Returns the previous setting (allocations still to go). */
+int ct_debug_fail_alloc(int32_t nth);
 
 /* Ends the resident engine of any table (CT_SCHED_RESIDENT) after it has
  * written its state back to the device: call before the process exits, or

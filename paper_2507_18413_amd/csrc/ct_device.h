@@ -43,8 +43,11 @@ constexpr int GW = 64;             // words per granule
 constexpr int BLOCK = 256;         // threads per workgroup of the propagate kernel
 constexpr int WAVES = BLOCK / WAVE;
 constexpr int MAX_ARITY = 256;
-constexpr int MAX_ROWS = 16384;    // support rows per table (row lists kept in LDS)
-constexpr int MAX_D = 1024;        // domain words per table kept in LDS
+constexpr int MAX_TABLE_ROWS = 1 << 22;  // support rows per table (row lists are staged in chunks)
+constexpr int MAX_TABLE_D = 1 << 16;     // domain words per table
+constexpr int MAX_D = 1024;        // domain words of a job cached in LDS (the rest read from memory)
+constexpr int NEG_MAX_ROWS = 8192; // negative tables: support rows (their second update pass lists
+                                   // the removed values' rows in one LDS chunk)
 constexpr int MAX_GRAN = 8192;     // granules per table (partition done in LDS)
 constexpr int INLINE_WORDS = 64;   // dom_in words carried in kernel arguments
 
@@ -77,6 +80,7 @@ struct TabDesc {
   const CT_G uint64_t* dom0;
   int32_t limit0, rootFailed;
   int32_t policy, tailBits;      // tailBits: tuples in the last currTable word (1..64)
+  int32_t kind, pad;             // 0: positive (allowed tuples), 1: negative (forbidden tuples)
 };
 
 struct TrailHdr {
@@ -126,7 +130,8 @@ struct DevJob {
   int32_t serialBase;      // serial of the k-th pushed level = serialBase + k
   int32_t nUpd, nFilt;     // item counts of this job
   int32_t depthAfter;      // slot depth once the pops and pushes are applied
-  int32_t pad;
+  int32_t tile;            // split jobs: granules per wave per update item (2, 4 or 8;
+                           // 0 = 2); solo jobs step 4 granules per wave
   const CT_G int32_t* active;  // nullable: the job is skipped when *active == 0
 };
 
@@ -243,7 +248,7 @@ struct EngDesc {
 struct TableView {
   const uint64_t* S;        // device, rows x stride
   int64_t stride, W;
-  int32_t n, D, rows, rootFailed, branchPolicy, pad;
+  int32_t n, D, rows, rootFailed, branchPolicy, kind;
   const VarDesc* vars;      // host, n
   const uint64_t* rootCt;   // device, W words
   const uint64_t* rootDom;  // device, D words

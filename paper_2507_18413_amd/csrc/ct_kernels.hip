@@ -31,12 +31,17 @@
 
 namespace ctk {
 
-constexpr int NGW = 2;                 // granules per wave per update item (split mode)
-constexpr int GPI = WAVES * NGW;       // granules per update item (split mode)
-constexpr int NGS = 4;                 // granules per wave per step (solo mode)
+constexpr int NGW = 2;                 // granules per wave per update step (split mode)
+constexpr int NGS = 4;                 // default granules per wave per step (solo mode)
 constexpr int LANE_SCAN = 16;          // words each missing lane checks before the wave scan
 constexpr int ROW_UNROLL = 8;          // support rows loaded per batch
+constexpr int ROWS_CHUNK = 8192;       // row-list entries staged in LDS at a time
 constexpr uint32_t SPIN_LIMIT = 1u << 22;
+constexpr int32_t STAR_CELL = (int32_t)0x80000000;  // a short table's cell: every value of its column
+
+// Steps of NGW granules a wave takes per update item for a job's tile
+// (granules per wave per item: 2, 4 or 8; 0 = 2).
+__host__ __device__ __forceinline__ int tile_reps(int tile) { return tile == 8 ? 4 : tile == 4 ? 2 : 1; }
 
 __device__ __forceinline__ int lane_id() { return threadIdx.x & (WAVE - 1); }
 __device__ __forceinline__ int wave_id() { return threadIdx.x / WAVE; }
@@ -61,8 +66,9 @@ struct Shared {
   int32_t segInc[MAX_ARITY];
   int32_t wsum[WAVES];
   int32_t trailCount;          // trail entries of a job run by one workgroup
-  uint64_t din[MAX_D];
-  uint16_t rows[MAX_ROWS];
+  uint64_t din[MAX_D];         // the job's first MAX_D domain words (the rest are read from memory)
+  uint64_t dout[MAX_D];        // negative tables: the filtered domains, published if no domain empties
+  uint32_t rows[ROWS_CHUNK];   // entries [k0, k0 + ROWS_CHUNK) of the job's row list
   uint8_t nz[MAX_GRAN];        // granule non-zero flags of a job run by one workgroup
   uint16_t gidx[MAX_GRAN];     // granule list of a job run by one workgroup
 };
@@ -129,6 +135,13 @@ __device__ __forceinline__ DevJob job_of(const KArgs& a, int j) {
 
 __device__ __forceinline__ uint64_t job_din(const KArgs& a, const DevJob& J, int k) {
   return (J.flags & JF_INLINE_DOM) ? a.inl[k] : J.dom_in[k];
+}
+
+// Domain word q of the job's input: the prologue's LDS copy for the first
+// MAX_D words, memory beyond (inline inputs have at most INLINE_WORDS words,
+// all in the copy).
+__device__ __forceinline__ uint64_t din_at(const DevJob& J, const Shared& sh, int q) {
+  return q < MAX_D ? sh.din[q] : J.dom_in[q];
 }
 
 // Word w of the set of all tuples (the starting currTable of a root state
@@ -251,7 +264,7 @@ __device__ void apply_pops_pushes(const DevJob& J, Shared& sh) {
   }
 }
 
-__device__ void do_prep(const KArgs& a, const DevJob& J, Shared& sh) {
+__device__ __forceinline__ void do_prep(const KArgs& a, const DevJob& J, Shared& sh) {
   apply_pops_pushes(J, sh);
   if (threadIdx.x == 0) {
     if (!(J.flags & JF_PROPAGATE)) {
@@ -274,6 +287,8 @@ __device__ __forceinline__ int wave_scan_incl(int v) {
   }
   return v;
 }
+
+__device__ void stage_rows(const DevJob& J, Shared& sh, int k0);
 
 // ---------------------------------------------------------------------------
 // prologue of Alg. 1 for one job (every update item recomputes it in LDS)
@@ -338,7 +353,7 @@ __device__ void prologue(const KArgs& a, const DevJob& J, Shared& sh, bool pushH
       if (pushHere)
         for (int k = 0; k < J.nPush; ++k) s->levelDom[(int64_t)(sh.depth + k) * D + q] = ld;
     }
-    sh.din[q] = din;
+    if (q < MAX_D) sh.din[q] = din;
     atomicAdd(&sh.size[i], __popcll(din));
     atomicAdd(&sh.dcnt[i], __popcll(dl));
   }
@@ -387,28 +402,40 @@ __device__ void prologue(const KArgs& a, const DevJob& J, Shared& sh, bool pushH
   }
   __syncthreads();
   if (sh.status != ST_OK || sh.noop) return;
-  // list the selected rows of every segment: word q of variable i contributes
-  // the set bits of (Delta word or domain word) in ascending order
-  for (int q = threadIdx.x; q < D; q += BLOCK) {
+  stage_rows(J, sh, 0);
+  __syncthreads();
+}
+
+// Entries [k0, k0 + ROWS_CHUNK) of the job's row list into sh.rows: the
+// selected rows of every segment, in segment order; word q of variable i
+// contributes the set bits of its Delta word (incremental) or domain word
+// (reset) in ascending order.  Whole block; a barrier must follow.
+__device__ void stage_rows(const DevJob& J, Shared& sh, int k0) {
+  const TabDesc* T = J.tab;
+  const CT_G uint64_t* last = (J.flags & JF_FROM_ROOT) ? T->dom0 : J.slot->lastDom;
+  const int k1 = k0 + ROWS_CHUNK;
+  for (int q = threadIdx.x; q < T->D; q += BLOCK) {
     const int i = T->wordVar[q];
     const int sg = sh.segOf[i];
     if (sg < 0) continue;
     const VarDesc v = T->vars[i];
     const int inc = sh.segInc[sg];
     int off = sg == 0 ? 0 : sh.segEnd[sg - 1];
-    for (int k = v.domOff; k < q; ++k) {
-      const uint64_t dk = sh.din[k];
+    for (int k = v.domOff; k < q && off < k1; ++k) {
+      const uint64_t dk = din_at(J, sh, k);
       off += __popcll(inc ? (last[k] & ~dk) : dk);
     }
-    uint64_t bits = inc ? (last[q] & ~sh.din[q]) : sh.din[q];
+    const uint64_t dq = din_at(J, sh, q);
+    uint64_t bits = inc ? (last[q] & ~dq) : dq;
+    if (off >= k1 || off + __popcll(bits) <= k0) continue;
     const int base = v.rowStart + (q - v.domOff) * 64;
-    while (bits) {
+    while (bits && off < k1) {
       const int b = __ffsll((unsigned long long)bits) - 1;
       bits &= bits - 1;
-      sh.rows[off++] = (uint16_t)(base + b);
+      if (off >= k0) sh.rows[off - k0] = (uint32_t)(base + b);
+      ++off;
     }
   }
-  __syncthreads();
 }
 
 // ---------------------------------------------------------------------------
@@ -461,22 +488,33 @@ __device__ void update_granules(const KArgs& a, const DevJob& J, Shared& sh, int
     acc[u] = 0ull;
     nAct += act[u] ? 1 : 0;
   }
-  if (status == ST_OK && !noop && nAct > 0) {
-    int seg = 0;
-    int segEnd = nseg > 0 ? sh.segEnd[0] : 0;
-    for (int k0 = 0; k0 < nrows; k0 += ROW_UNROLL) {
+  // a row list longer than the LDS chunk is staged chunk by chunk, with the
+  // whole block (every wave runs this loop the same number of times)
+  const bool work = status == ST_OK && !noop;
+  const bool chunked = nrows > ROWS_CHUNK;
+  int seg = 0;
+  int segEnd = nseg > 0 ? sh.segEnd[0] : 0;
+  for (int c0 = 0; work && c0 < nrows; c0 += ROWS_CHUNK) {
+    if (chunked) {
+      __syncthreads();
+      stage_rows(J, sh, c0);
+      __syncthreads();
+    }
+    if (nAct == 0) continue;
+    const int c1 = min(nrows, c0 + ROWS_CHUNK);
+    for (int k0 = c0; k0 < c1; k0 += ROW_UNROLL) {
       uint64_t v[ROW_UNROLL][NG];
 #pragma unroll
       for (int j = 0; j < ROW_UNROLL; ++j) {
         const int k = k0 + j;
-        const int r = k < nrows ? (int)sh.rows[k] : 0;  // rows past the end are never used
+        const int r = k < c1 ? (int)sh.rows[k - c0] : 0;  // rows past the end are never used
 #pragma unroll
         for (int u = 0; u < NG; ++u) v[j][u] = T->S[(int64_t)r * stride + (int64_t)gs[u] * GW + lane];
       }
 #pragma unroll
       for (int j = 0; j < ROW_UNROLL; ++j) {
         const int k = k0 + j;
-        if (k >= nrows) break;
+        if (k >= c1) break;
         while (k >= segEnd) {
           const int inc = sh.segInc[seg];
 #pragma unroll
@@ -491,6 +529,8 @@ __device__ void update_granules(const KArgs& a, const DevJob& J, Shared& sh, int
         for (int u = 0; u < NG; ++u) acc[u] |= v[j][u];
       }
     }
+  }
+  if (work && nAct > 0) {
     while (seg < nseg) {  // remaining segments (an empty reset segment gives 0)
       const int inc = sh.segInc[seg];
 #pragma unroll
@@ -592,8 +632,11 @@ __device__ void slot_reset_root(const TabDesc* T, SlotDesc* s, int serial, int t
 // active granule list (survivors first), new limit, trail top, FAIL when no
 // granule survives (Alg. 1's failure test).  Returns the job status.
 // ---------------------------------------------------------------------------
-__device__ int finalize_update(const DevJob& J, Shared& sh, bool ldsFlags, int jobTrail) {
+__device__ int finalize_update(const DevJob& J, Shared& sh, bool ldsFlags, int jobTrail, bool count = true) {
   const TabDesc* T = J.tab;
+  // a negative table's currTable holds forbidden tuples: empty means no
+  // combination is forbidden, not a failure
+  const bool negative = T->kind != 0;
   SlotDesc* s = J.slot;
   const bool fromRoot = J.flags & JF_FROM_ROOT;
   const int limit = sh.limit;
@@ -618,7 +661,7 @@ __device__ int finalize_update(const DevJob& J, Shared& sh, bool ldsFlags, int j
       if (f) dst[sv++] = gid; else dst[zr++] = gid;
     }
     for (int p = limit + threadIdx.x; p < nGran; p += BLOCK) dst[p] = scratch ? p : src[p];
-    if (nSurv == 0) st = ST_FAIL;
+    if (nSurv == 0 && !negative) st = ST_FAIL;
     if (threadIdx.x == 0) {
       s->cur = dstBuf;
       s->limit = nSurv;
@@ -630,7 +673,7 @@ __device__ int finalize_update(const DevJob& J, Shared& sh, bool ldsFlags, int j
       } else {
         s->trailTop = sh.trailTop + jobTrail;
       }
-      if (nSurv == 0) s->failed = 1;
+      if (nSurv == 0 && !negative) s->failed = 1;
     }
   } else if (fromRoot && st != ST_OK) {
     slot_reset_root(T, s, J.serialBase, threadIdx.x, blockDim.x);
@@ -638,7 +681,7 @@ __device__ int finalize_update(const DevJob& J, Shared& sh, bool ldsFlags, int j
   if (threadIdx.x == 0) {
     s->status = st;
     s->pad2 = sh.noop;
-    if (st == ST_OK || st == ST_FAIL) {
+    if (count && (st == ST_OK || st == ST_FAIL)) {
       atomicAdd(&s->stats[S_JOBS], 1ull);
       atomicAdd(&s->stats[S_GRAN_IN], (unsigned long long)limit);
       atomicAdd(&s->stats[S_ROWS], (unsigned long long)(sh.noop ? 0 : sh.nrows));
@@ -815,13 +858,17 @@ __device__ void add_filter_stats(SlotDesc* s, const unsigned long long* cnt) {
 // ---------------------------------------------------------------------------
 // split mode: one update item of a job (the last one finalizes the job)
 // ---------------------------------------------------------------------------
-__device__ void do_update(const KArgs& a, const DevJob& J, int chunk, Shared& sh) {
+__device__ __forceinline__ void do_update(const KArgs& a, const DevJob& J, int chunk, Shared& sh) {
   SlotDesc* s = J.slot;
   if (J.nPop > 0) {
     if (!block_wait(a, &s->prepDone, 1, sh)) return;
   }
   prologue(a, J, sh, false);
-  update_granules<NGW>(a, J, sh, chunk * GPI + wave_id() * NGW, false, &s->jobTrail);
+  // the job's tile: each wave takes tile granules of the item, NGW at a
+  // time (the item covers WAVES x tile granules)
+  const int reps = tile_reps(J.tile);
+  for (int r = 0; r < reps; ++r)
+    update_granules<NGW>(a, J, sh, ((chunk * reps + r) * WAVES + wave_id()) * NGW, false, &s->jobTrail);
 
   // count finished items; the last one finalizes the job
   __syncthreads();
@@ -866,7 +913,7 @@ __device__ void do_update(const KArgs& a, const DevJob& J, int chunk, Shared& sh
 }
 
 // split mode: one filter item (one domain word per wave)
-__device__ void do_filter(const KArgs& a, const DevJob& J, int chunk, Shared& sh) {
+__device__ __forceinline__ void do_filter(const KArgs& a, const DevJob& J, int chunk, Shared& sh) {
   SlotDesc* s = J.slot;
   const int q = chunk * WAVES + wave_id();
   const int qc = min(q, J.tab->D - 1);
@@ -892,17 +939,139 @@ __device__ void do_filter(const KArgs& a, const DevJob& J, int chunk, Shared& sh
 }
 
 // ---------------------------------------------------------------------------
+// filterDomains of a negative table for domain word q (one wave; whole job
+// in one workgroup).  currTable holds the forbidden tuples whose values are
+// all in the input domains; value a of x_i has an allowed tuple iff fewer
+// than prod_{k != i} |dom(x_k)| (sh.dcnt[i], capped above the tuple count)
+// of them have x_i = a.  Each lane counts its value's row against the
+// active granules (currTable words are the same for every lane).  Returns
+// the filtered word.
+// ---------------------------------------------------------------------------
+__device__ uint64_t neg_filter_word(const DevJob& J, int q, int lim, const CT_G int32_t* idx, const Shared& sh) {
+  const TabDesc* T = J.tab;
+  const CT_G uint64_t* ct = J.slot->ct;
+  const int i = T->wordVar[q];
+  const VarDesc v = T->vars[i];
+  const uint64_t din = sh.din[q];
+  const int64_t prod = sh.dcnt[i];
+  // no count can reach the product: every value keeps an allowed tuple
+  if (din == 0ull || prod > (int64_t)lim * GW * 64) return din;
+  const int lane = lane_id();
+  const bool present = (din >> lane) & 1ull;
+  const int row = v.rowStart + (q - v.domOff) * 64 + (present ? lane : 0);
+  const CT_G uint64_t* srow = T->S + (int64_t)row * T->stride;
+  int64_t cnt = 0;
+  for (int p = 0; p < lim; ++p) {
+    const int64_t base = (int64_t)idx[p] * GW;
+#pragma unroll 8
+    for (int k = 0; k < GW; ++k) cnt += __popcll(ct[base + k] & srow[base + k]);
+  }
+  return din & ~__ballot(present && cnt == prod);
+}
+
+// A negative table's filterDomains in one workgroup, after updateTable and
+// its partition (st: the job status so far): per-variable products,
+// every variable filtered into sh.dout, failure iff a domain empties.  On
+// success the removed values' rows are listed as one incremental segment
+// (in word order) for a second update pass that takes their tuples out of
+// currTable.  Returns the status; *rows2 receives the listed rows.
+__device__ int neg_filter(const DevJob& J, Shared& sh, int st, int* rows2) {
+  SlotDesc* s = J.slot;
+  const TabDesc* T = J.tab;
+  const int n = T->n, D = T->D;
+  *rows2 = 0;
+  if (st != ST_OK) return st;
+  const int64_t cap = (int64_t)T->nGran * GW * 64 + 1;
+  for (int i = threadIdx.x; i < n; i += BLOCK) {
+    int64_t prod = 1;
+    for (int k = 0; k < n; ++k) {
+      if (k == i) continue;
+      prod = min(prod * (int64_t)sh.size[k], cap);
+    }
+    sh.dcnt[i] = (int32_t)prod;
+  }
+  if (threadIdx.x == 0) sh.bad_sub = 0;
+  __syncthreads();
+  {
+    const int lim = s->limit;
+    const CT_G int32_t* idx = s->idx[s->cur];
+    for (int q = wave_id(); q < D; q += WAVES) {
+      const uint64_t dout = sh.noop ? sh.din[q] : neg_filter_word(J, q, lim, idx, sh);
+      if (lane_id() == 0) sh.dout[q] = dout;
+    }
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < n; i += BLOCK) {
+    const VarDesc v = T->vars[i];
+    uint64_t any = 0ull;
+    for (int k = 0; k < v.domWords; ++k) any |= sh.dout[v.domOff + k];
+    if (!any) sh.bad_sub = 1;
+  }
+  __syncthreads();
+  if (sh.bad_sub) {
+    if (threadIdx.x == 0) {
+      s->failed = 1;
+      s->status = ST_FAIL;
+    }
+    return ST_FAIL;
+  }
+  if (sh.noop) return ST_OK;
+  const int per = (D + BLOCK - 1) / BLOCK;
+  const int b = min((int)threadIdx.x * per, D), e = min(b + per, D);
+  int cnt = 0;
+  for (int q = b; q < e; ++q) cnt += __popcll(sh.din[q] & ~sh.dout[q]);
+  int total = 0;
+  int off = block_scan_excl(cnt, &total, sh);
+  for (int q = b; q < e; ++q) {
+    const VarDesc v = T->vars[T->wordVar[q]];
+    const int base = v.rowStart + (q - v.domOff) * 64;
+    uint64_t bits = sh.din[q] & ~sh.dout[q];
+    while (bits) {
+      const int k = __ffsll((unsigned long long)bits) - 1;
+      bits &= bits - 1;
+      sh.rows[off++] = (uint32_t)(base + k);
+    }
+  }
+  if (total > 0) {
+    // the second pass reads the slot's own (updated) currTable and granule
+    // list; its trail entries follow the first pass's
+    if (threadIdx.x == 0) {
+      sh.nseg = 1;
+      sh.segEnd[0] = total;
+      sh.segInc[0] = 1;
+      sh.nrows = total;
+      sh.status = ST_OK;
+      sh.limit = s->limit;
+      sh.trailTop = s->trailTop;
+      sh.trailCount = 0;
+    }
+    __syncthreads();
+    const CT_G int32_t* idx = s->idx[s->cur];
+    for (int p = threadIdx.x; p < sh.limit; p += BLOCK) sh.gidx[p] = (uint16_t)idx[p];
+    __syncthreads();
+  }
+  *rows2 = total;
+  return ST_OK;
+}
+
+// ---------------------------------------------------------------------------
 // solo mode: the whole job in one workgroup -- pops/pushes, prologue, all
 // granules, partition, filter -- with no hand-off between workgroups.
 // ---------------------------------------------------------------------------
-__device__ void do_solo(const KArgs& a, const DevJob& J, Shared& sh) {
+__device__ __forceinline__ void do_solo(const KArgs& a, const DevJob& J0, Shared& sh) {
+  // a negative table filters before its update is complete (its second
+  // pass takes the removed values' tuples out) and writes currTable out at
+  // the end of the call
+  const bool negative = J0.tab->kind != 0;
+  DevJob J = J0;
+  if (negative) J.ct_out = nullptr;
   SlotDesc* s = J.slot;
   const bool pushHere = J.nPop == 0 && J.nPush > 0;
   if (!pushHere) apply_pops_pushes(J, sh);
   prologue(a, J, sh, pushHere);
   if (threadIdx.x == 0) sh.trailCount = 0;
   const int nGran = J.tab->nGran;
-  const int span = sh.status == ST_OK ? nGran : 0;
+  int span = sh.status == ST_OK ? nGran : 0;
   {
     // the job's granule list, read once (each update step is then a single
     // round of independent loads)
@@ -911,12 +1080,32 @@ __device__ void do_solo(const KArgs& a, const DevJob& J, Shared& sh) {
     for (int p = threadIdx.x; p < span; p += BLOCK) sh.gidx[p] = (uint16_t)(scratch ? p : src[p]);
   }
   __syncthreads();
-  for (int c = 0; c < span; c += WAVES * NGS) {
-    update_granules<NGS>(a, J, sh, c + wave_id() * NGS, true, &sh.trailCount);
+  int st = ST_OK;
+  for (int pass = 0;; ++pass) {
+    for (int c = 0; c < span; c += WAVES * NGS) {
+      update_granules<NGS>(a, J, sh, c + wave_id() * NGS, true, &sh.trailCount);
+    }
+    __syncthreads();
+    st = finalize_update(J, sh, true, sh.trailCount, pass == 0);
+    if (!negative || pass == 1) break;
+    int rows2 = 0;
+    st = neg_filter(J, sh, st, &rows2);
+    if (rows2 == 0) break;
+    span = sh.limit;
+    J.flags &= ~(JF_FROM_ROOT | JF_ROOT | JF_SCRATCH);
   }
-  __syncthreads();
-  const int st = finalize_update(J, sh, true, sh.trailCount);
-  if (st == ST_OK) {
+  if (negative) {
+    __syncthreads();
+    const TabDesc* T = J.tab;
+    if (st == ST_OK) {
+      for (int q = threadIdx.x; q < T->D; q += BLOCK) {
+        J0.dom_out[q] = sh.dout[q];
+        s->lastDom[q] = sh.dout[q];
+      }
+    }
+    if (J0.ct_out && (st == ST_OK || st == ST_FAIL))
+      for (int64_t w = threadIdx.x; w < T->W; w += BLOCK) J0.ct_out[w] = st == ST_OK ? s->ct[w] : 0ull;
+  } else if (st == ST_OK) {
     unsigned long long cnt[3] = {0, 0, 0};
     const int lim = s->limit;
     const CT_G int32_t* idx = s->idx[s->cur];
@@ -1634,9 +1823,22 @@ __global__ void __launch_bounds__(BLOCK) build_supports_kernel(const int32_t* tu
   for (int i = 0; i < n; ++i) {
     const VarDesc v = vars[i];
     int r = -1;
+    bool star = false;
     if (j < t) {
-      const int64_t val = (int64_t)tuples[j * n + i] - lo[i];
-      if (val >= 0 && val < v.dsize) r = v.rowStart + (int)val;
+      const int32_t raw = tuples[j * n + i];
+      star = raw == STAR_CELL;
+      const int64_t val = (int64_t)raw - lo[i];
+      if (!star && val >= 0 && val < v.dsize) r = v.rowStart + (int)val;
+    }
+    // a star cell (short table) is in every row of its column: each row
+    // word is the ballot of its lanes or'ed with the star lanes, written once
+    const unsigned long long starMask = __ballot(star);
+    if (starMask) {
+      for (int k = 0; k < v.dsize; ++k) {
+        const unsigned long long m = __ballot(r == v.rowStart + k) | starMask;
+        if (lane == 0) S[(int64_t)(v.rowStart + k) * stride + w] = m;
+      }
+      continue;
     }
     bool pending = r >= 0;
     for (;;) {
@@ -1812,7 +2014,11 @@ __global__ void __launch_bounds__(BLOCK) model_mark_kernel(ModelDesc M) {
 // ---------------------------------------------------------------------------
 namespace ctk {
 
-int propagate_items_per_job_update(int nGran) { return (nGran + GPI - 1) / GPI; }
+// update items of a split job: WAVES x (granules per wave of its tile) granules each
+int propagate_items_per_job_update(int nGran, int tile) {
+  const int gpi = WAVES * NGW * tile_reps(tile);
+  return (nGran + gpi - 1) / gpi;
+}
 int propagate_items_per_job_filter(int D) { return (D + WAVES - 1) / WAVES; }
 
 // Workgroups of the propagate kernel that are resident at once on the whole

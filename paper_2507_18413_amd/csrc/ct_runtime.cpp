@@ -25,7 +25,7 @@
 using namespace ctk;
 
 namespace ctk {
-int propagate_items_per_job_update(int nGran);
+int propagate_items_per_job_update(int nGran, int tile);
 int propagate_items_per_job_filter(int D);
 int propagate_max_grid();
 hipError_t launch_propagate(const KArgs& a, int grid, hipStream_t stream);
@@ -68,6 +68,29 @@ int fail(int code, const char* fmt, ...) {
 
 constexpr int32_t kStatusPending = 0x7fff0001;
 
+// Injected allocation failure (a test hook): the g_failAlloc-th allocation
+// from now fails.
+std::atomic<int32_t> g_failAlloc{0};
+
+bool alloc_injected() {
+  int32_t n = g_failAlloc.load();
+  while (n > 0)
+    if (g_failAlloc.compare_exchange_weak(n, n - 1)) return n == 1;
+  return false;
+}
+
+// A device or pinned host allocation: CT_E_NOMEM when it fails (or when
+// the injected failure fires on it).
+#define ALLOCCHK(expr)                                                                      \
+  do {                                                                                      \
+    if (alloc_injected()) return fail(CT_E_NOMEM, "injected allocation failure: %s", #expr); \
+    hipError_t e_ = (expr);                                                                 \
+    if (e_ != hipSuccess) {                                                                 \
+      (void)hipGetLastError();                                                              \
+      return fail(CT_E_NOMEM, "%s failed: %s", #expr, hipGetErrorString(e_));              \
+    }                                                                                       \
+  } while (0)
+
 // failed flag as known on the host: 0 no, 1 yes, 2 unknown (after batches)
 struct SlotHost {
   SlotDesc* dev = nullptr;
@@ -107,9 +130,9 @@ struct QueueCtx {
 };
 
 int queue_init(QueueCtx& q) {
-  HIPCHK(hipMalloc(&q.queue, 4 * sizeof(int32_t)));
+  ALLOCCHK(hipMalloc(&q.queue, 4 * sizeof(int32_t)));
   HIPCHK(hipMemset(q.queue, 0, 4 * sizeof(int32_t)));
-  HIPCHK(hipHostMalloc((void**)&q.hostErr, sizeof(int32_t), hipHostMallocMapped | hipHostMallocCoherent));
+  ALLOCCHK(hipHostMalloc((void**)&q.hostErr, sizeof(int32_t), hipHostMallocMapped | hipHostMallocCoherent));
   *q.hostErr = 0;
   for (int k = 0; k < 2; ++k) HIPCHK(hipEventCreateWithFlags(&q.staged[k], hipEventDisableTiming));
   return CT_OK;
@@ -145,6 +168,8 @@ struct ct_table {
   bool poisoned = false;
   bool tailPending = false;  // a synchronous call returned before its kernel ended
   bool engEligible = false, engOn = false;
+  int kind = CT_KIND_POSITIVE;  // CT_KIND_POSITIVE or CT_KIND_NEGATIVE
+  bool shortTab = false;        // a positive table with star cells
   int rootFailed = 0;
   hipStream_t stream = nullptr;
   uint64_t batchMark = 0;    // last batch that named this table
@@ -188,6 +213,7 @@ namespace {
 
 int dev_alloc(ct_table* T, void** p, size_t bytes) {
   if (bytes == 0) bytes = 8;
+  if (alloc_injected()) return fail(CT_E_NOMEM, "injected allocation failure: hipMalloc(%zu)", bytes);
   hipError_t e = hipMalloc(p, bytes);
   if (e != hipSuccess) {
     (void)hipGetLastError();
@@ -252,7 +278,9 @@ constexpr int NODES_MIN_BATCH = 64;   // AUTO: batches of root resets this large
 constexpr int SCRATCH_SOLO_MAX_GRAN = 16;  // AUTO: roots recomputed solo up to 65,536 tuples
 
 bool use_solo(const ct_table* T, int nJobs) {
-  if (T->cfg.schedule == CT_SCHED_SOLO) return true;
+  // a negative table's call filters and then removes the pruned values'
+  // tuples, in one workgroup
+  if (T->kind == CT_KIND_NEGATIVE || T->cfg.schedule == CT_SCHED_SOLO) return true;
   if (T->cfg.schedule == CT_SCHED_SPLIT) return false;
   return (T->nGran <= SOLO_MAX_GRAN && T->D <= SOLO_MAX_D) || nJobs >= SOLO_MIN_BATCH;
 }
@@ -298,7 +326,8 @@ NodesPlan nodes_plan(const ct_table* T) {
 // kernels when every job is a ROOT job of a table on the AUTO schedule.
 bool use_roots(const ct_job* jobs, int n) {
   for (int j = 0; j < n; ++j)
-    if (jobs[j].flags != (CT_JOB_PROPAGATE | CT_JOB_ROOT) || jobs[j].table->cfg.schedule != CT_SCHED_AUTO)
+    if (jobs[j].flags != (CT_JOB_PROPAGATE | CT_JOB_ROOT) || jobs[j].table->cfg.schedule != CT_SCHED_AUTO ||
+        jobs[j].table->kind != CT_KIND_POSITIVE)
       return false;
   return true;
 }
@@ -307,6 +336,7 @@ bool use_nodes(const ct_job* jobs, int n) {
   const ct_table* T = jobs[0].table;
   if (T->cfg.schedule != CT_SCHED_NODES && (T->cfg.schedule != CT_SCHED_AUTO || n < NODES_MIN_BATCH))
     return false;
+  if (T->kind != CT_KIND_POSITIVE) return false;
   if (T->rows > nodes_max_rows() || T->nGran > MAX_GRAN) return false;
   // the update kernel's LDS holds one granule of every support row
   if (nodes_plan(T).groupSize == 0) return false;
@@ -324,7 +354,7 @@ void job_counts(const ct_table* T, DevJob& J) {
     J.nUpd = 1;
     J.nFilt = 0;
   } else {
-    J.nUpd = propagate_items_per_job_update(T->nGran);
+    J.nUpd = propagate_items_per_job_update(T->nGran, J.tile);
     J.nFilt = propagate_items_per_job_filter(T->D);
   }
 }
@@ -456,8 +486,8 @@ int engine_start(ct_table* T) {
   }
   if (!T->engStream) HIPCHK(hipStreamCreateWithFlags(&T->engStream, hipStreamNonBlocking));
   if (!T->pCmd) {
-    HIPCHK(hipHostMalloc((void**)&T->pCmd, sizeof(EngCmd), hipHostMallocMapped | hipHostMallocCoherent));
-    HIPCHK(hipHostMalloc((void**)&T->pRes, sizeof(EngRes), hipHostMallocMapped | hipHostMallocCoherent));
+    ALLOCCHK(hipHostMalloc((void**)&T->pCmd, sizeof(EngCmd), hipHostMallocMapped | hipHostMallocCoherent));
+    ALLOCCHK(hipHostMalloc((void**)&T->pRes, sizeof(EngRes), hipHostMallocMapped | hipHostMallocCoherent));
     memset((void*)T->pCmd, 0, sizeof(EngCmd));
     memset((void*)T->pRes, 0, sizeof(EngRes));
   }
@@ -573,7 +603,7 @@ int flush_slot(ct_table* T, int slot) {
 
 int ensure_pinned_ct(ct_table* T) {
   if (T->pCt) return CT_OK;
-  HIPCHK(hipHostMalloc((void**)&T->pCt, sizeof(uint64_t) * std::max<int64_t>(T->W, 1),
+  ALLOCCHK(hipHostMalloc((void**)&T->pCt, sizeof(uint64_t) * std::max<int64_t>(T->W, 1),
                        hipHostMallocMapped | hipHostMallocCoherent));
   return CT_OK;
 }
@@ -690,7 +720,7 @@ int batch_build(const ct_job* jobs, int n_jobs, int32_t* status_dev, bool nodes,
     // a root recomputed from scratch streams every support row: large
     // tables are split over workgroups (the queue balances them), small ones
     // run solo
-    const bool solo = (J.flags & JF_SCRATCH) && T->cfg.schedule == CT_SCHED_AUTO
+    const bool solo = (J.flags & JF_SCRATCH) && T->cfg.schedule == CT_SCHED_AUTO && T->kind == CT_KIND_POSITIVE
                           ? T->nGran <= SCRATCH_SOLO_MAX_GRAN
                           : use_solo(T, n_jobs);
     if ((J.flags & JF_PROPAGATE) && !nodes && solo) J.flags |= JF_SOLO;
@@ -710,6 +740,8 @@ int batch_build(const ct_job* jobs, int n_jobs, int32_t* status_dev, bool nodes,
 extern "C" {
 
 const char* ct_last_error(void) { return g_err.c_str(); }
+
+int ct_debug_fail_alloc(int32_t nth) { return g_failAlloc.exchange(nth > 0 ? nth : 0); }
 
 int ct_quiesce(void) {
   std::lock_guard<std::mutex> lk(g_engMu);
@@ -737,8 +769,39 @@ void ct_destroy(ct_table* T) {
   delete T;
 }
 
+// 1 if two tuples of the table are equal (hash of each row, then the rows
+// with equal hashes compared)
+bool has_duplicate_rows(const int32_t* tuples, int64_t t, int n) {
+  std::vector<std::pair<uint64_t, int64_t>> h((size_t)t);
+  for (int64_t j = 0; j < t; ++j) {
+    uint64_t x = 1469598103934665603ull;
+    for (int i = 0; i < n; ++i) x = (x ^ (uint32_t)tuples[j * n + i]) * 1099511628211ull;
+    h[(size_t)j] = {x, j};
+  }
+  std::sort(h.begin(), h.end());
+  for (size_t k = 1; k < h.size(); ++k)
+    if (h[k].first == h[k - 1].first &&
+        std::equal(tuples + h[k].second * n, tuples + h[k].second * n + n, tuples + h[k - 1].second * n))
+      return true;
+  return false;
+}
+
 static int create_impl(ct_table* T, const int32_t* tuples, int64_t t, int32_t n,
                        const int32_t* lo, const int32_t* dsz, const uint64_t* init_dom) {
+  bool star = false;
+  for (int64_t k = 0; k < t * n && !star; ++k) star = tuples[k] == CT_STAR;
+  if (T->kind == CT_KIND_NEGATIVE) {
+    if (star) return fail(CT_E_INVALID, "a negative table has no star cell");
+    if (has_duplicate_rows(tuples, t, n)) return fail(CT_E_INVALID, "a negative table lists distinct tuples");
+  }
+  if (star) {
+    // a star cell supports every value of its column: the update takes the
+    // reset branch (OR over the remaining values), which needs no other rows
+    if (T->cfg.branch_policy == CT_BRANCH_INCREMENTAL)
+      return fail(CT_E_INVALID, "a short table's update takes the reset branch");
+    T->cfg.branch_policy = CT_BRANCH_RESET;
+    T->shortTab = true;
+  }
   T->n = n;
   T->t = t;
   T->W = (t + 63) / 64;
@@ -761,8 +824,11 @@ static int create_impl(ct_table* T, const int32_t* tuples, int64_t t, int32_t n,
   }
   T->rows = rows;
   T->D = D;
-  if (rows > MAX_ROWS) return fail(CT_E_INVALID, "%d support rows exceed the limit %d", rows, MAX_ROWS);
-  if (D > MAX_D) return fail(CT_E_INVALID, "%d domain words exceed the limit %d", D, MAX_D);
+  if (rows > MAX_TABLE_ROWS) return fail(CT_E_INVALID, "%d support rows exceed the limit %d", rows, MAX_TABLE_ROWS);
+  if (D > MAX_TABLE_D) return fail(CT_E_INVALID, "%d domain words exceed the limit %d", D, MAX_TABLE_D);
+  if (T->kind == CT_KIND_NEGATIVE && (rows > NEG_MAX_ROWS || D > MAX_D))
+    return fail(CT_E_INVALID, "a negative table has at most %d support rows and %d domain words", NEG_MAX_ROWS,
+                MAX_D);
   if (T->nGran > MAX_GRAN)
     return fail(CT_E_INVALID, "%lld tuples exceed the limit %lld", (long long)t,
                 (long long)MAX_GRAN * GW * 64);
@@ -788,9 +854,9 @@ static int create_impl(ct_table* T, const int32_t* tuples, int64_t t, int32_t n,
   // coherent (fine-grained) pinned buffers: the kernel's writes reach host
   // memory without waiting for the end of the kernel
   const unsigned kCoherent = hipHostMallocMapped | hipHostMallocCoherent;
-  HIPCHK(hipHostMalloc((void**)&T->pDomOut, sizeof(uint64_t) * D, kCoherent));
-  HIPCHK(hipHostMalloc((void**)&T->pDomIn, sizeof(uint64_t) * D, kCoherent));
-  HIPCHK(hipHostMalloc((void**)&T->pStatus, sizeof(int32_t) * 4, kCoherent));
+  ALLOCCHK(hipHostMalloc((void**)&T->pDomOut, sizeof(uint64_t) * D, kCoherent));
+  ALLOCCHK(hipHostMalloc((void**)&T->pDomIn, sizeof(uint64_t) * D, kCoherent));
+  ALLOCCHK(hipHostMalloc((void**)&T->pStatus, sizeof(int32_t) * 4, kCoherent));
 
   // static data
   if ((rc = dev_alloc(T, (void**)&T->dS, sizeof(uint64_t) * (size_t)rows * T->stride))) return rc;
@@ -804,7 +870,7 @@ static int create_impl(ct_table* T, const int32_t* tuples, int64_t t, int32_t n,
   HIPCHK(hipMemsetAsync(T->dS, 0, sizeof(uint64_t) * (size_t)rows * T->stride, T->stream));
   if (t > 0) {
     int32_t* dTup = nullptr;
-    HIPCHK(hipMalloc(&dTup, sizeof(int32_t) * (size_t)t * n));
+    ALLOCCHK(hipMalloc(&dTup, sizeof(int32_t) * (size_t)t * n));
     hipError_t e = hipMemcpyAsync(dTup, tuples, sizeof(int32_t) * (size_t)t * n,
                                   hipMemcpyHostToDevice, T->stream);
     if (e == hipSuccess)
@@ -851,6 +917,7 @@ static int create_impl(ct_table* T, const int32_t* tuples, int64_t t, int32_t n,
   tb.wordVar = T->dWordVar;
   tb.policy = T->cfg.branch_policy;
   tb.tailBits = T->W > 0 ? (int32_t)(t - 64 * (T->W - 1)) : 0;
+  tb.kind = T->kind;
   HIPCHK(hipMemcpy(T->dTab, &tb, sizeof(TabDesc), hipMemcpyHostToDevice));
 
   // root propagation: every variable takes the reset branch over dom0
@@ -887,7 +954,9 @@ static int create_impl(ct_table* T, const int32_t* tuples, int64_t t, int32_t n,
   int dev = 0, lds = 0;
   HIPCHK(hipGetDevice(&dev));
   HIPCHK(hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
-  T->engEligible = T->D <= INLINE_WORDS && T->W > 0 && T->engLds <= (size_t)lds;
+  // (the engine lists rows with 16-bit ids)
+  T->engEligible = T->D <= INLINE_WORDS && T->W > 0 && T->engLds <= (size_t)lds && T->kind == CT_KIND_POSITIVE &&
+                   T->rows <= 65535;
   std::lock_guard<std::mutex> lk(g_engMu);
   g_tables.insert(T);
   return CT_OK;
@@ -896,8 +965,15 @@ static int create_impl(ct_table* T, const int32_t* tuples, int64_t t, int32_t n,
 int ct_create(const int32_t* tuples, int64_t n_tuples, int32_t arity, const int32_t* dom_lo,
               const int32_t* dom_size, const uint64_t* init_dom, const ct_config* cfg,
               ct_table** out) {
+  return ct_create_table(tuples, n_tuples, arity, dom_lo, dom_size, init_dom, cfg, CT_KIND_POSITIVE, out);
+}
+
+int ct_create_table(const int32_t* tuples, int64_t n_tuples, int32_t arity, const int32_t* dom_lo,
+                    const int32_t* dom_size, const uint64_t* init_dom, const ct_config* cfg, int32_t kind,
+                    ct_table** out) {
   if (!out) return fail(CT_E_INVALID, "out is NULL");
   *out = nullptr;
+  if (kind != CT_KIND_POSITIVE && kind != CT_KIND_NEGATIVE) return fail(CT_E_INVALID, "kind %d", kind);
   if (arity < 1 || arity > MAX_ARITY) return fail(CT_E_INVALID, "arity %d not in [1, %d]", arity, MAX_ARITY);
   if (n_tuples < 0) return fail(CT_E_INVALID, "n_tuples < 0");
   if (n_tuples > 0 && !tuples) return fail(CT_E_INVALID, "tuples is NULL");
@@ -909,6 +985,7 @@ int ct_create(const int32_t* tuples, int64_t n_tuples, int32_t arity, const int3
   T->cfg.branch_policy = CT_BRANCH_AUTO;
   T->cfg.max_depth = 256;
   T->cfg.schedule = CT_SCHED_AUTO;
+  T->kind = kind;
   if (cfg) {
     if (cfg->schedule < 0 || cfg->schedule > 4) {
       delete T;
@@ -949,7 +1026,7 @@ int ct_layout(const ct_table* T, ct_layout_info* info, int32_t* dom_off) {
     info->granules = T->nGran;
     info->root_failed = T->rootFailed;
     info->resident = engine_wanted(T) ? 1 : 0;
-    info->pad = 0;
+    info->kind = T->kind == CT_KIND_NEGATIVE ? CT_KIND_NEGATIVE : T->shortTab ? CT_KIND_SHORT : CT_KIND_POSITIVE;
   }
   if (dom_off) memcpy(dom_off, T->domOff.data(), sizeof(int32_t) * T->n);
   return CT_OK;
@@ -1265,6 +1342,7 @@ int ct_propagate_batch(const ct_job* jobs, int32_t n_jobs, void* stream_v, int32
       q = new QueueCtx();
       int rc = queue_init(*q);
       if (rc) {
+        queue_free(*q);
         delete q;
         return rc;
       }
@@ -1284,21 +1362,10 @@ int ct_propagate_batch(const ct_job* jobs, int32_t n_jobs, void* stream_v, int32
       if (q->dNodes) (void)hipFree(q->dNodes);
       q->dNodes = nullptr;
       q->capNodes = 0;
-      HIPCHK(hipMalloc(&q->dNodes, need));
+      ALLOCCHK(hipMalloc(&q->dNodes, need));
       q->capNodes = need;
     }
   }
-  // job descriptors
-  q->hJobs.resize(n_jobs);
-  std::vector<int32_t>& updOff = q->updOff;
-  std::vector<int32_t>& filtOff = q->filtOff;
-  std::vector<int32_t>& prep = q->prep;
-  updOff.assign(n_jobs + 1, 0);
-  filtOff.assign(n_jobs + 1, 0);
-  prep.resize(n_jobs);
-  const int nPrep = batch_build(jobs, n_jobs, status_dev, nodes, q->hJobs.data(), updOff.data(),
-                                filtOff.data(), prep.data());
-  prep.resize(nPrep);
   // root streams: WAVES granules per task, tables with the most support rows
   // first (their tasks are the longest)
   std::vector<int32_t>& rootTasks = q->rootTasks;
@@ -1322,12 +1389,13 @@ int ct_propagate_batch(const ct_job* jobs, int32_t n_jobs, void* stream_v, int32
         rootTasks[at++] = g;
       }
   }
-  // stage to the device (the root tasks start at an even offset: int pairs)
-  const size_t rootBase = (2 * (size_t)(n_jobs + 1) + prep.size() + 2) & ~(size_t)1;
-  const size_t nOff = roots ? rootBase + rootTasks.size() : 2 * (size_t)(n_jobs + 1) + prep.size() + 1;
+  // staging capacity for the largest prep list (every job), allocated
+  // before any slot's host state changes: a failed allocation leaves the
+  // slots as they were
   const size_t offAt = align256(sizeof(DevJob) * (size_t)n_jobs);
-  const size_t stageBytes = offAt + sizeof(int32_t) * nOff;
-  if (q->capStage < stageBytes) {
+  const size_t maxOff = 2 * (size_t)(n_jobs + 1) + (size_t)n_jobs + 2 + rootTasks.size();
+  if (q->capStage < offAt + sizeof(int32_t) * maxOff) {
+    const size_t stageBytes = offAt + sizeof(int32_t) * maxOff;
     HIPCHK(hipStreamSynchronize(stream));
     if (q->dStage) (void)hipFree(q->dStage);
     for (int k = 0; k < 2; ++k)
@@ -1336,10 +1404,25 @@ int ct_propagate_batch(const ct_job* jobs, int32_t n_jobs, void* stream_v, int32
     q->dStage = nullptr;
     q->pStage[0] = q->pStage[1] = nullptr;
     q->capStage = 0;
-    HIPCHK(hipMalloc(&q->dStage, cap));
-    for (int k = 0; k < 2; ++k) HIPCHK(hipHostMalloc((void**)&q->pStage[k], cap, hipHostMallocDefault));
+    ALLOCCHK(hipMalloc(&q->dStage, cap));
+    for (int k = 0; k < 2; ++k) ALLOCCHK(hipHostMalloc((void**)&q->pStage[k], cap, hipHostMallocDefault));
     q->capStage = cap;
   }
+  // job descriptors (the slots' host mirrors take the jobs' pops and pushes)
+  q->hJobs.resize(n_jobs);
+  std::vector<int32_t>& updOff = q->updOff;
+  std::vector<int32_t>& filtOff = q->filtOff;
+  std::vector<int32_t>& prep = q->prep;
+  updOff.assign(n_jobs + 1, 0);
+  filtOff.assign(n_jobs + 1, 0);
+  prep.resize(n_jobs);
+  const int nPrep = batch_build(jobs, n_jobs, status_dev, nodes, q->hJobs.data(), updOff.data(),
+                                filtOff.data(), prep.data());
+  prep.resize(nPrep);
+  // stage to the device (the root tasks start at an even offset: int pairs)
+  const size_t rootBase = (2 * (size_t)(n_jobs + 1) + prep.size() + 2) & ~(size_t)1;
+  const size_t nOff = roots ? rootBase + rootTasks.size() : 2 * (size_t)(n_jobs + 1) + prep.size() + 1;
+  const size_t stageBytes = offAt + sizeof(int32_t) * nOff;
   q->turn ^= 1;
   // the copy that last read this pinned buffer (two batches ago) has ended
   HIPCHK(hipEventSynchronize(q->staged[q->turn]));
@@ -1435,6 +1518,7 @@ int table_view(const ct_table* T, TableView* v) {
   v->rows = T->rows;
   v->rootFailed = T->rootFailed;
   v->branchPolicy = T->cfg.branch_policy;
+  v->kind = T->kind;
   v->vars = T->vars.data();
   v->rootCt = T->hRoot.ct;
   v->rootDom = T->hRoot.lastDom;
@@ -1458,6 +1542,10 @@ struct ct_model {
   hipStream_t stream = nullptr;
   QueueCtx q;
   int soloMax = 4, roundsPerGraph = 8;
+  // schedule per class of tables (granule bucket, rows bucket), set by the
+  // autotuner: solo or split, and the tile (granules per wave); classes
+  // without an entry follow soloMax with the default tile
+  std::map<std::pair<int, int>, std::pair<int, int>> choice;
   // device state, rebuilt when the table set or the schedule changes
   bool built = false;
   std::vector<void*> blocks;
@@ -1476,6 +1564,7 @@ struct ct_model {
 namespace {
 
 int model_alloc(ct_model* m, void** p, size_t bytes) {
+  if (alloc_injected()) return fail(CT_E_NOMEM, "injected allocation failure: hipMalloc(%zu)", bytes);
   hipError_t e = hipMalloc(p, bytes ? bytes : 8);
   if (e != hipSuccess) {
     (void)hipGetLastError();
@@ -1506,6 +1595,26 @@ int model_upload(ct_model* m, T** dst, const std::vector<T>& src) {
   if (rc) return rc;
   if (!src.empty()) HIPCHK(hipMemcpy(*dst, src.data(), sizeof(T) * src.size(), hipMemcpyHostToDevice));
   return CT_OK;
+}
+
+// Class of a table for the autotuner: floor(log4) of its granule count and
+// of its support-row count.
+int log4_bucket(int64_t x) {
+  int b = 0;
+  while (x >= 4) {
+    x /= 4;
+    ++b;
+  }
+  return b;
+}
+
+std::pair<int, int> table_class(const ct_table* T) { return {log4_bucket(T->nGran), log4_bucket(T->rows)}; }
+
+// (solo, tile) of a table's round job
+std::pair<int, int> model_choice(const ct_model* m, const ct_table* T) {
+  auto it = m->choice.find(table_class(T));
+  if (it != m->choice.end()) return it->second;
+  return {T->nGran <= m->soloMax ? 1 : 0, 0};
 }
 
 // Device arrays, one propagate job per table, and the graph of K rounds.
@@ -1583,7 +1692,9 @@ int model_build(ct_model* m) {
     J.dom_in = M.domIn + bufOff[c];
     J.dom_out = M.domOut + bufOff[c];
     J.status_out = M.status + c;
-    J.flags = JF_PROPAGATE | (T->nGran <= m->soloMax ? JF_SOLO : 0u);
+    const auto ch = model_choice(m, T);
+    J.flags = JF_PROPAGATE | (ch.first || T->kind == CT_KIND_NEGATIVE ? JF_SOLO : 0u);
+    J.tile = ch.second;
     J.depthAfter = T->slots[0].depth;
     J.active = M.dirty + c;
     job_counts(T, J);
@@ -1840,51 +1951,146 @@ int ct_model_pop(ct_model* m) {
   return model_push_pop(m, false);
 }
 
-int ct_model_autotune(ct_model* m, const uint64_t* pool_in, int32_t* best) {
+int ct_model_get_choice(const ct_model* m, int32_t table, int32_t* solo, int32_t* tile) {
+  if (!m || table < 0 || table >= (int)m->tabs.size()) return fail(CT_E_INVALID, "bad table index");
+  const auto ch = model_choice(m, m->tabs[table]);
+  if (solo) *solo = ch.first;
+  if (tile) *tile = ch.first ? 4 : (ch.second == 0 ? 2 : ch.second);
+  return CT_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+std::string device_arch() {
+  int dev = 0;
+  hipDeviceProp_t prop{};
+  if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) return "unknown";
+  std::string a = prop.gcnArchName;
+  const size_t c = a.find(':');
+  return c == std::string::npos ? a : a.substr(0, c);
+}
+
+std::string class_key(const std::string& arch, std::pair<int, int> c) {
+  return arch + " g" + std::to_string(c.first) + " r" + std::to_string(c.second);
+}
+
+// The tuning cache: a JSON object, one entry per line,
+//   "gfx950 g2 r3": [solo, tile],
+// keyed by architecture, granule bucket and rows bucket.
+std::map<std::string, std::pair<int, int>> cache_read(const char* path) {
+  std::map<std::string, std::pair<int, int>> out;
+  FILE* f = path ? fopen(path, "r") : nullptr;
+  if (!f) return out;
+  char line[256], key[128];
+  int solo = 0, tile = 0;
+  while (fgets(line, sizeof(line), f))
+    if (sscanf(line, " \"%127[^\"]\": [%d, %d]", key, &solo, &tile) == 3) out[key] = {solo, tile};
+  fclose(f);
+  return out;
+}
+
+bool cache_write(const char* path, const std::map<std::string, std::pair<int, int>>& entries) {
+  const std::string tmp = std::string(path) + ".tmp";
+  FILE* f = fopen(tmp.c_str(), "w");
+  if (!f) return false;
+  fprintf(f, "{\n");
+  size_t k = 0;
+  for (const auto& e : entries)
+    fprintf(f, "\"%s\": [%d, %d]%s\n", e.first.c_str(), e.second.first, e.second.second,
+            ++k < entries.size() ? "," : "");
+  fprintf(f, "}\n");
+  fclose(f);
+  return rename(tmp.c_str(), path) == 0;
+}
+
+}  // namespace
+
+extern "C" {
+
+int ct_model_autotune(ct_model* m, const uint64_t* pool_in, const char* cache_path, int32_t* from_cache,
+                      int32_t* timed) {
   if (!m || !pool_in) return fail(CT_E_INVALID, "bad arguments");
-  static const int cands[] = {1, 4, 16, 64, 256};
+  if (from_cache) *from_cache = 0;
+  if (timed) *timed = 0;
+  // classes present, the largest total granule count first
+  std::map<std::pair<int, int>, int64_t> work;
+  for (ct_table* T : m->tabs) work[table_class(T)] += T->nGran;
+  std::vector<std::pair<int64_t, std::pair<int, int>>> order;
+  for (const auto& w : work) order.push_back({-w.second, w.first});
+  std::sort(order.begin(), order.end());
+  const std::string arch = device_arch();
+  auto cache = cache_read(cache_path);
+  bool all = !order.empty();
+  for (const auto& o : order) all = all && cache.count(class_key(arch, o.second));
+  if (cache_path && all) {
+    for (const auto& o : order) m->choice[o.second] = cache[class_key(arch, o.second)];
+    model_free_device(m);
+    if (from_cache) *from_cache = 1;
+    return CT_OK;
+  }
   uint64_t* scratch = nullptr;
-  HIPCHK(hipMalloc(&scratch, sizeof(uint64_t) * m->poolWords));
+  ALLOCCHK(hipMalloc(&scratch, sizeof(uint64_t) * m->poolWords));
   std::vector<uint64_t> ref(m->poolWords), got(m->poolWords);
-  double bestT = 1e30;
-  int bestC = m->soloMax, refSt = -100;
-  int rc = CT_OK;
-  for (int ci = 0; ci < 5 && rc == CT_OK; ++ci) {
-    if ((rc = ct_model_set_schedule(m, cands[ci], m->roundsPerGraph))) break;
-    if ((rc = ct_model_push(m))) break;
-    if ((rc = model_sync_tables(m))) break;
-    if (!m->built && (rc = model_build(m))) break;
-    const auto t0 = std::chrono::steady_clock::now();
-    const int st = ct_model_fixpoint(m, pool_in, scratch, nullptr, nullptr, nullptr);
-    const double el = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-    if (st != CT_OK && st != CT_FAIL) {
-      rc = st;
-      break;
+  int refSt = -100, rc = CT_OK, nTimed = 0;
+  // one candidate: the median of 3 timed fixpoints from pool_in, each
+  // between a push and a pop; every candidate must reach the same fixpoint
+  auto measure = [&](double* ms) -> int {
+    model_free_device(m);
+    std::vector<double> t;
+    for (int rep = 0; rep < 3; ++rep) {
+      int r;
+      if ((r = ct_model_push(m))) return r;
+      if ((r = model_sync_tables(m))) return r;
+      if (!m->built && (r = model_build(m))) return r;
+      const auto t0 = std::chrono::steady_clock::now();
+      const int st = ct_model_fixpoint(m, pool_in, scratch, nullptr, nullptr, nullptr);
+      t.push_back(std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count());
+      if (st != CT_OK && st != CT_FAIL) return st;
+      if (st == CT_OK && hipMemcpy(got.data(), scratch, sizeof(uint64_t) * m->poolWords,
+                                   hipMemcpyDeviceToHost) != hipSuccess)
+        return fail(CT_E_DEVICE, "copy failed");
+      if (refSt == -100) {
+        refSt = st;
+        ref = got;
+      } else if (st != refSt || (st == CT_OK && got != ref)) {
+        return fail(CT_E_DEVICE, "schedules disagree on the fixpoint");
+      }
+      if ((r = ct_model_pop(m))) return r;
     }
-    if (st == CT_OK) {
-      hipError_t e = hipMemcpy(got.data(), scratch, sizeof(uint64_t) * m->poolWords, hipMemcpyDeviceToHost);
-      if (e != hipSuccess) {
-        rc = fail(CT_E_DEVICE, "copy failed");
-        break;
+    std::sort(t.begin(), t.end());
+    *ms = t[1];
+    ++nTimed;
+    return CT_OK;
+  };
+  // coordinate descent over the classes: solo (one workgroup; its step is
+  // fixed) or split with 2, 4 or 8 granules per wave per update item
+  const std::pair<int, int> opts[] = {{1, 0}, {0, 2}, {0, 4}, {0, 8}};
+  for (const auto& o : order) {
+    const auto cls = o.second;
+    std::pair<int, int> best{0, 0};
+    double bestMs = 1e30;
+    for (const auto& opt : opts) {
+      m->choice[cls] = opt;
+      double ms = 0;
+      if ((rc = measure(&ms))) break;
+      if (ms < bestMs) {
+        bestMs = ms;
+        best = opt;
       }
     }
-    if (refSt == -100) {
-      refSt = st;
-      ref = got;
-    } else if (st != refSt || (st == CT_OK && got != ref)) {
-      rc = fail(CT_E_DEVICE, "schedules disagree on the fixpoint");
-      break;
-    }
-    if ((rc = ct_model_pop(m))) break;
-    if (el < bestT) {
-      bestT = el;
-      bestC = cands[ci];
-    }
+    if (rc) break;
+    m->choice[cls] = best;
+    cache[class_key(arch, cls)] = best;
   }
   (void)hipFree(scratch);
+  model_free_device(m);
+  if (timed) *timed = nTimed;
   if (rc) return rc;
-  if (best) *best = bestC;
-  return ct_model_set_schedule(m, bestC, m->roundsPerGraph);
+  if (cache_path && !cache_write(cache_path, cache))
+    return fail(CT_E_INVALID, "cannot write the tuning cache %s", cache_path);
+  return CT_OK;
 }
 
 }  // extern "C"

@@ -215,6 +215,7 @@ int ct_split_create(ct_table* t, int32_t mode, ct_split** out) {
   TableView v{};
   int rc = table_view(t, &v);
   if (rc) return rc;
+  if (v.kind != 0) return sfail(CT_E_INVALID, "the split propagators take positive tables");
   ct_split* s = new (std::nothrow) ct_split;
   if (!s) return sfail(CT_E_NOMEM, "host allocation failed");
   s->mode = mode;

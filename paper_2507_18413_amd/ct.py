@@ -23,6 +23,8 @@ BRANCH_AUTO, BRANCH_RESET, BRANCH_INCREMENTAL = 0, 1, 2
 SCHED_AUTO, SCHED_SOLO, SCHED_SPLIT, SCHED_NODES, SCHED_RESIDENT = 0, 1, 2, 3, 4
 JOB_PROPAGATE, JOB_FROM_ROOT, JOB_ROOT = 1, 2, 4
 SPLIT_UPDATE, SPLIT_FILTER = 1, 2
+KIND_POSITIVE, KIND_NEGATIVE, KIND_SHORT = 0, 1, 2
+STAR = -(1 << 31)  # a cell of a short table: every value of its column
 
 
 class CTError(RuntimeError):
@@ -38,7 +40,7 @@ class ct_config(C.Structure):
 class ct_layout_info(C.Structure):
     _fields_ = [("n_vars", C.c_int32), ("D", C.c_int32), ("W", C.c_int64), ("n_tuples", C.c_int64),
                 ("rows", C.c_int32), ("n_slots", C.c_int32), ("granules", C.c_int32),
-                ("root_failed", C.c_int32), ("resident", C.c_int32), ("pad", C.c_int32)]
+                ("root_failed", C.c_int32), ("resident", C.c_int32), ("kind", C.c_int32)]
 
 
 class ct_stats(C.Structure):
@@ -105,6 +107,7 @@ def lib():
         P, I32, I64 = C.c_void_p, C.c_int32, C.c_int64
         sig = {
             "ct_create": ([P, I64, I32, P, P, P, P, C.POINTER(P)], C.c_int),
+            "ct_create_table": ([P, I64, I32, P, P, P, P, I32, C.POINTER(P)], C.c_int),
             "ct_destroy": ([P], None),
             "ct_layout": ([P, C.POINTER(ct_layout_info), P], C.c_int),
             "ct_get_supports": ([P, I32, I32, P], C.c_int),
@@ -131,7 +134,8 @@ def lib():
             "ct_model_push": ([P], C.c_int),
             "ct_model_pop": ([P], C.c_int),
             "ct_model_set_schedule": ([P, I32, I32], C.c_int),
-            "ct_model_autotune": ([P, P, C.POINTER(I32)], C.c_int),
+            "ct_model_autotune": ([P, P, C.c_char_p, C.POINTER(I32), C.POINTER(I32)], C.c_int),
+            "ct_model_get_choice": ([P, I32, C.POINTER(I32), C.POINTER(I32)], C.c_int),
             "ct_server_create": ([C.POINTER(ct_server_cfg), C.POINTER(P)], C.c_int),
             "ct_server_destroy": ([P], None),
             "ct_server_add_search": ([P, P, I32, C.POINTER(I32)], C.c_int),
@@ -145,6 +149,7 @@ def lib():
             "ct_split_pop": ([P], C.c_int),
             "ct_split_destroy": ([P], None),
             "ct_last_error": ([], C.c_char_p),
+            "ct_debug_fail_alloc": ([I32], C.c_int),
             "ct_quiesce": ([], C.c_int),
         }
         for name, (args, res) in sig.items():
@@ -179,7 +184,7 @@ class Table:
     """One table constraint on the GPU with its slots (reversible states)."""
 
     def __init__(self, tuples, lo, dsizes, init_dom=None, branch_policy=BRANCH_AUTO, max_depth=256,
-                 schedule=SCHED_AUTO):
+                 schedule=SCHED_AUTO, kind=KIND_POSITIVE):
         L = lib()
         tuples = np.ascontiguousarray(tuples, dtype=np.int32)
         lo = np.ascontiguousarray(lo, dtype=np.int32)
@@ -189,8 +194,8 @@ class Table:
             init_dom = np.ascontiguousarray(init_dom, dtype=np.uint64)
         cfg = ct_config(int(branch_policy), int(max_depth), int(schedule))
         h = C.c_void_p()
-        st = L.ct_create(_p(tuples) if t else None, t, int(ds.shape[0]), _p(lo), _p(ds), _p(init_dom),
-                         C.byref(cfg), C.byref(h))
+        st = L.ct_create_table(_p(tuples) if t else None, t, int(ds.shape[0]), _p(lo), _p(ds), _p(init_dom),
+                               C.byref(cfg), int(kind), C.byref(h))
         if st < 0:
             raise CTError(st, last_error())
         self.h = h
@@ -201,6 +206,7 @@ class Table:
         self.n, self.D, self.W, self.t = info.n_vars, info.D, info.W, info.n_tuples
         self.rows, self.granules, self.root_failed = info.rows, info.granules, bool(info.root_failed)
         self.resident = bool(info.resident)
+        self.kind = int(info.kind)
         self.dom_off = off
         # marshalling buffers of the synchronous calls: fixed addresses, so a
         # call converts no pointer (numpy's ctypes pointers cost microseconds)
@@ -488,12 +494,23 @@ class Model:
         if st < 0:
             raise CTError(st, last_error())
 
-    def autotune(self, pool_in):
-        best = C.c_int32()
-        st = lib().ct_model_autotune(self.h, _ptr(pool_in), C.byref(best))
+    def autotune(self, pool_in, cache_path=None):
+        """Tune the per-class schedule (solo / split, tile); returns
+        (from_cache, candidates timed)."""
+        fc, timed = C.c_int32(), C.c_int32()
+        path = None if cache_path is None else os.fsencode(cache_path)
+        st = lib().ct_model_autotune(self.h, _ptr(pool_in), path, C.byref(fc), C.byref(timed))
         if st < 0:
             raise CTError(st, last_error())
-        return best.value
+        return bool(fc.value), timed.value
+
+    def choice(self, table_index):
+        """(solo, tile) of a table's round job."""
+        solo, tile = C.c_int32(), C.c_int32()
+        st = lib().ct_model_get_choice(self.h, int(table_index), C.byref(solo), C.byref(tile))
+        if st < 0:
+            raise CTError(st, last_error())
+        return bool(solo.value), tile.value
 
 
 class Server:

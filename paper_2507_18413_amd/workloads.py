@@ -247,6 +247,18 @@ def wide_table(seed: int = DEFAULT_SEED, n: int = 100, dom=(64, 160), t: int = 1
     return TableSpec(tup, np.zeros(n, np.int32), ds)
 
 
+def paper_shape_table(seed: int = DEFAULT_SEED, n: int = 150, dom=(2, 2000), t: int = 15_000) -> TableSpec:
+    """A table of the size of the paper's Gecode comparison set (Sec. 5.3:
+    100-150 variables, domains up to 2,000 values, 10,000-15,000 tuples):
+    arity n, domain sizes uniform in [dom[0], dom[1]], t distinct uniform
+    tuples.  About 150,000 support rows of 235 words and 2,400 domain words
+    at the defaults: a call is dominated by filterDomains."""
+    rng = rng_for(seed, 10, 0)
+    ds = rng.integers(dom[0], dom[1] + 1, size=n).astype(np.int32)
+    tup = distinct_uniform_tuples(rng, ds, t)
+    return TableSpec(tup, np.zeros(n, np.int32), ds)
+
+
 def zipf_table(seed: int = DEFAULT_SEED, t: int = 1_000_000, d: int = 20, n: int = 6,
                   s: float = 1.1) -> TableSpec:
     """Arity 6, domain size 20, distinct tuples with Zipf(1.1) columns."""
@@ -382,6 +394,28 @@ def _distinct_zipf_mixed(rng, dsizes, s, t):
         # keep only distinct codes; size the next round from the distinct rate
         rate = max((got.shape[0] - before) / draw, 1e-3)
         draw = int((t - got.shape[0]) / rate * 1.15) + 1024
+
+
+def lin_instance(seed: int = DEFAULT_SEED, n: int = 100, dom=(2, 160), t: int = 10_000,
+                 eq_frac: float = 0.5, weights=(1, 20)):
+    """A bounded-knapsack instance in the shape of the paper's first test set
+    (Sec. 5.1: one table constraint over all the item-count variables plus one
+    linear equation over some of them; Table 2 gives 80-200 variables and
+    5,000-15,000 tuples).  Variable i counts the copies of item i, domain
+    {0..d_i - 1} with d_i ~ U{dom}; the table lists t distinct knapsack
+    configurations drawn uniformly; the equation sum_{i in E} w_i x_i = C
+    with w_i ~ U{weights} over a random subset E of ``eq_frac`` of the
+    variables, and C the weighted sum of one configuration of the table (so
+    the instance has a solution).  Returns (TableSpec, E, w, C)."""
+    rng = rng_for(seed, 9, 0)
+    ds = rng.integers(dom[0], dom[1] + 1, size=n).astype(np.int64)
+    tup = distinct_uniform_tuples(rng, ds, t)
+    k = max(1, int(round(eq_frac * n)))
+    E = np.sort(rng.choice(n, size=k, replace=False)).astype(np.int64)
+    w = rng.integers(weights[0], weights[1] + 1, size=k).astype(np.int64)
+    planted = tup[int(rng.integers(0, t))]
+    C = int((w * planted[E].astype(np.int64)).sum())
+    return TableSpec(tup, np.zeros(n, np.int32), ds.astype(np.int32)), E, w, C
 
 
 # ---------------------------------------------------------------------------

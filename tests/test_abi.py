@@ -96,3 +96,22 @@ def test_host_and_device_kernel_names_match(tmp_path):
     host_k = {k for k in re.findall(r"(_ZN3ctk\w*kernel\w*)", host) if "__device_stub__" not in k}
     assert dev_k and host_k
     assert host_k <= dev_k, host_k - dev_k
+
+
+def test_kernels_keep_their_registers(tmp_path):
+    """No kernel of the library spills to scratch memory at -O3 for gfx950
+    (a spill turns every register access of the hot loops into a memory
+    round trip)."""
+    import re
+    csrc = os.path.join(ROOT, "paper_2507_18413_amd", "csrc")
+    for name in ("ct_kernels.hip", "ct_engine.hip", "ct_split.hip"):
+        cmd = ["/opt/rocm/bin/hipcc", "--offload-arch=gfx950", "-O3", "-std=c++17", "-c",
+               "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+               "-I", os.path.join(ROOT, "include"), "-I", csrc, os.path.join(csrc, name),
+               "-o", str(tmp_path / (name + ".o")), "-Rpass-analysis=kernel-resource-usage"]
+        out = subprocess.run(cmd, check=True, capture_output=True, text=True).stderr
+        kernels = re.findall(r"Function Name: (\S+)", out)
+        scratch = [int(x) for x in re.findall(r"ScratchSize \[bytes/lane\]: (\d+)", out)]
+        assert kernels and len(kernels) == len(scratch), name
+        spilling = [k for k, sz in zip(kernels, scratch) if sz]
+        assert not spilling, (name, spilling)

@@ -1,5 +1,6 @@
 """Multi-table fixpoint on the GPU against the oracle's FIFO fixpoint and the
 enumeration closure: pool domains must match bit for bit after every step."""
+import os
 import sys
 
 import numpy as np
@@ -123,7 +124,7 @@ def test_search_steps_vs_oracle(schedule):
                 pool = stack.pop()
 
 
-def test_scaled_multi_table_root_and_steps():
+def test_scaled_multi_table_root_and_steps(tmp_path):
     import torch
     say("multi-table model scaled: 150 tables over 400 variables")
     spec = W.multi_table_model(n_pool=400, n_tables=150, tuples=(100, 20_000))
@@ -137,8 +138,18 @@ def test_scaled_multi_table_root_and_steps():
     if st == ct.OK:
         assert (pool == opool).all()
     assert props >= len(spec.tables) and rounds >= 1
-    best = M.autotune(dev(pool))
-    assert best in (1, 4, 16, 64, 256)
+    cache = os.path.join(str(tmp_path), "tune.json")
+    from_cache, timed = M.autotune(dev(pool), cache)
+    assert not from_cache and timed >= 4
+    choices = [M.choice(c) for c in range(len(gts))]
+    assert all(t in (2, 4, 8) for _, t in choices)
+    text = open(cache).read()
+    assert text.startswith("{") and '": [' in text
+    # a second tuning of the same model (or any model whose classes the
+    # cache holds) reuses the cached choices without timing
+    from_cache, timed = M.autotune(dev(pool), cache)
+    assert from_cache and timed == 0
+    assert [M.choice(c) for c in range(len(gts))] == choices
     rng = W.rng_for(3, 303, 0)
     for step in range(10):
         M.push()
