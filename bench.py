@@ -57,6 +57,9 @@ def parse():
     p.add_argument("--wide-only", action="store_true",
                    help="only the wide-scope leg, without its split propagators (profiling)")
     p.add_argument("--no-driver", action="store_true")
+    p.add_argument("--no-tiny", action="store_true", help="skip the tiny-table leg (profiling the plain leg)")
+    p.add_argument("--no-probe", action="store_true", help="skip the device copy probe")
+    p.add_argument("--no-paper-shape", action="store_true")
     p.add_argument("--root-batch-only", action="store_true",
                    help="only the batched root recomputation of the 2,000-table model (profiling)")
     return p.parse_args()
@@ -335,13 +338,15 @@ class PlainModel:
         return 0, pool, props
 
 
-def wide_leg(seed, n_calls, cpu, split=True):
-    """Plain calls on a wide-scope table (100 variables, domains 64-160,
-    10,000 tuples; filterDomains dominates): the paper's instance shape."""
+def wide_leg(seed, n_calls, cpu, split=True, paper_shape=False):
+    """Plain calls on a wide-scope table, where filterDomains dominates: 100
+    variables, domains 64-160, 10,000 tuples (the shape of the paper's
+    linear instances), or with paper_shape 150 variables, domains up to
+    2,000, 15,000 tuples (the size of its Gecode comparison set)."""
     import numpy as np
     from paper_2507_18413_amd import ct
     from paper_2507_18413_amd import workloads as W
-    spec = W.wide_table(seed)
+    spec = W.paper_shape_table(seed) if paper_shape else W.wide_table(seed)
     lay = spec.layout()
     # the recorder runs the schedule the timed table gets, so a profile of
     # the leg averages one kind of launch
@@ -367,8 +372,9 @@ def wide_leg(seed, n_calls, cpu, split=True):
     from paper_2507_18413_amd import profiling
     prof = profiling.read_summary(os.path.join(ROOT, "profiles", "propagate_wide_scope.md"))
     split_out = split_leg(table, script, 1) if split else None
-    out = {"workload": "arity 100, domains U{64..160}, 10,000 distinct uniform tuples "
-                       f"({table.rows} support rows of {table.W} words, {table.D} domain words); "
+    shape = ("arity 150, domains U{2..2000}, 15,000 distinct uniform tuples" if paper_shape else
+             "arity 100, domains U{64..160}, 10,000 distinct uniform tuples")
+    out = {"workload": f"{shape} ({table.rows} support rows of {table.W} words, {table.D} domain words); "
                        f"{n_calls} calls as in the plain leg",
            "props_per_s": round(props / el, 1),
            "latency_us": {"p50": round(float(np.percentile(lat_us, 50)), 2),
@@ -383,21 +389,24 @@ def wide_leg(seed, n_calls, cpu, split=True):
            "split_propagators": split_out}
     if cpu:
         from oracle import oracle as O
-        o = O.OracleTable(spec.tuples, spec.lo, spec.dsizes)
+        for fast in (True, False):
+            o = O.OracleTable(spec.tuples, spec.lo, spec.dsizes, fast=fast)
 
-        class OracleSut:
-            def propagate(self, d):
-                return o.propagate(d)
+            class OracleSut:
+                def propagate(self, d):
+                    return o.propagate(d)
 
-            def push(self):
-                o.push()
+                def push(self):
+                    o.push()
 
-            def pop(self):
-                o.pop()
+                def pop(self):
+                    o.pop()
 
-        t0 = time.perf_counter()
-        oprops = replay(OracleSut(), script)
-        out["oracle_props_per_s"] = round(oprops / (time.perf_counter() - t0), 1)
+            t0 = time.perf_counter()
+            oprops = replay(OracleSut(), script)
+            out["oracle_fast_props_per_s" if fast else "oracle_plain_props_per_s"] = \
+                round(oprops / (time.perf_counter() - t0), 1)
+    table.close()
     return out
 
 
@@ -492,53 +501,48 @@ def split_leg(table, script, passes):
     return out
 
 
-def solver_leg(seed, max_nodes, cpu):
-    """A depth-first search through the library on a generated knapsack-like
-    model (30 variables over {0..9}, 10 tables of arity 8 with 110k-380k
-    tuples, one linear inequality on the host), table propagation on the GPU;
-    the same search with the oracle's tables beside it."""
+def solver_leg(seed, cpu, n=100, dom=(2, 160), t=10_000):
+    """A complete search of an instance in the form of the paper's first test
+    set (Sec. 5.1): one table constraint over all n item-count variables of a
+    bounded knapsack (t distinct configurations) and one linear equation
+    over all of them (the form of the Gecode comparison set, Sec. 5.3),
+    input order and largest value first, all solutions.  The table is one
+    ct.Table on the GPU (synchronous calls); the equation is propagated on
+    the host.  The same search with the oracle's table (fast mode) beside it
+    must explore the same tree."""
+    from paper_2507_18413_amd import ct
     from paper_2507_18413_amd import solver as S
-    from paper_2507_18413_amd.workloads import DomLayout
-    import numpy as np
-    kw = dict(n_vars=30, d=10, n_tables=10, arity=8, density=(0.001, 0.004))
-    dsz, tables, w, cap = S.lin_model(seed, **kw)
-    lay = DomLayout(dsz, np.zeros_like(dsz))
-    M, tabs = S.build_gpu(dsz, tables)
-    prop = S.GpuTables(M, lay.D)
-    g = S.Search(lay, prop, S.LinearLE(lay, range(lay.n), w, cap))
+    from paper_2507_18413_amd import workloads as W
+    spec, E, w, c = W.lin_instance(seed, n=n, dom=dom, t=t, eq_frac=1.0)
+    lay = spec.layout()
+    table = ct.Table(spec.tuples, spec.lo, spec.dsizes, max_depth=max(256, n + 8))
+    prop = S.OneTable(table)
+    g = S.Search(lay, prop, S.LinearEQ(lay, E, w, c), var_order="input", val_order="max")
     t0 = time.perf_counter()
-    g.run(lay.full(), max_nodes, 10 ** 6)
+    g.run(lay.full(), 10 ** 7, 10 ** 7)
     el = time.perf_counter() - t0
-    out = {"model": "30 variables over {0..9}, 10 tables of arity 8 ("
-                    f"{sum(len(t) for t, _ in tables)} tuples), sum w_i x_i <= cap",
+    out = {"instance": f"{n} variables, domains U{{{dom[0]}..{dom[1]}}} ({int(spec.dsizes.sum())} support rows, "
+                       f"{lay.D} domain words), {t} distinct tuples, sum w_i x_i = C over all variables "
+                       f"(w_i in 1..20); input order, largest value first, all solutions",
            "nodes": g.nodes, "fails": g.fails, "solutions": len(g.solutions),
-           "table_propagations": prop.props, "seconds": round(el, 3),
-           "nodes_per_s": round(g.nodes / el, 1)}
+           "table_propagations": prop.props, "solve_seconds": round(el, 3),
+           "table_seconds": round(prop.seconds, 3),
+           "table_props_per_s": round(prop.props / prop.seconds, 1) if prop.seconds > 0 else None,
+           "nodes_per_s": round(g.nodes / el, 1), "table_schedule": "resident engine" if table.resident
+           else "launched"}
+    table.close()
     if cpu:
         from oracle import oracle as O
-
-        class OracleTables:
-            def __init__(self):
-                self.ots = [O.OracleTable(t, np.zeros(len(sc), np.int32), dsz[sc]) for t, sc in tables]
-
-            def fixpoint(self, pool):
-                st, o, _ = O.fixpoint(self.ots, [sc for _, sc in tables], lay, pool)
-                return st != O.OK, (o if st == O.OK else pool)
-
-            def push(self):
-                for x in self.ots:
-                    x.push()
-
-            def pop(self):
-                for x in self.ots:
-                    x.pop()
-
-        o = S.Search(lay, OracleTables(), S.LinearLE(lay, range(lay.n), w, cap))
+        o = O.OracleTable(spec.tuples, spec.lo, spec.dsizes, fast=True)
+        oprop = S.OneTable(o)
+        s2 = S.Search(lay, oprop, S.LinearEQ(lay, E, w, c), var_order="input", val_order="max")
         t0 = time.perf_counter()
-        o.run(lay.full(), max_nodes, 10 ** 6)
+        s2.run(lay.full(), 10 ** 7, 10 ** 7)
         oel = time.perf_counter() - t0
-        out["oracle_seconds"] = round(oel, 3)
-        out["same_tree_as_oracle"] = bool((o.nodes, o.fails, o.solutions) == (g.nodes, g.fails, g.solutions))
+        out["oracle_solve_seconds"] = round(oel, 3)
+        out["oracle_table_seconds"] = round(oprop.seconds, 3)
+        out["oracle_table_props_per_s"] = round(oprop.props / oprop.seconds, 1) if oprop.seconds > 0 else None
+        out["same_tree_as_oracle"] = bool((s2.nodes, s2.fails, s2.solutions) == (g.nodes, g.fails, g.solutions))
     return out
 
 
@@ -642,7 +646,15 @@ def model_leg(seed, steps, cpu):
     st, props, rounds = M.fixpoint(pin, pout)
     root_s = time.perf_counter() - r0
     M.pop()
-    best = M.autotune(pin)
+    cache = os.environ.get("CT_TUNE_CACHE") or os.path.join(ROOT, "gpurun_out", "ct_tune_cache.json")
+    os.makedirs(os.path.dirname(cache), exist_ok=True)
+    from_cache, timed = M.autotune(pin, cache)
+    classes = {}
+    for c, tb in enumerate(tabs):
+        cls = f"g{log4_bucket(tb.granules)} r{log4_bucket(tb.rows)}"
+        classes.setdefault(cls, M.choice(c))
+    best = {"from_cache": from_cache, "candidates_timed": timed,
+            "classes": {k: {"solo": v[0], "tile": v[1]} for k, v in sorted(classes.items())}}
     r0 = time.perf_counter()
     st, props, rounds = M.fixpoint(pin, pout)
     root_tuned_s = time.perf_counter() - r0
@@ -696,7 +708,7 @@ def model_leg(seed, steps, cpu):
     out = {"tables": len(spec.tables), "pool_vars": lay.n, "tuples": int(sum(tb.t for tb in spec.tables)),
            "support_bytes": supports_bytes, "generate_s": round(gen_s, 1), "build_s": round(build_s, 1),
            "root_fixpoint_ms": round(root_s * 1e3, 3), "root_fixpoint_tuned_ms": round(root_tuned_s * 1e3, 3),
-           "autotuned_solo_max_granules": best, "root_props": props, "root_rounds": rounds,
+           "autotune": best, "root_props": props, "root_rounds": rounds,
            "steps": steps, "batched_props": bprops, "batched_step_props_per_s": round(bprops / batched_s, 1),
            "batched_ms_per_step": round(batched_s / steps * 1e3, 3), "root_gac_batch": root_batch}
     # plain GPU baseline: AC-3 on the host, one synchronous launch per table
@@ -903,6 +915,15 @@ def serve_leg(tables_spec, seed, rate, n_requests, n_searches, budget, sample_ch
                     dom = od
         out["sampled_searches_equal_alone"] = ok
     return out
+
+
+def log4_bucket(x):
+    """floor(log4(x)) for x >= 1 (the autotuner's class buckets)."""
+    b = 0
+    while x >= 4:
+        x //= 4
+        b += 1
+    return b
 
 
 def host_info():
@@ -1112,7 +1133,8 @@ def main():
                              "receipt to publication" if table.resident else
                              "device clock: launch lifetimes (earliest workgroup start to latest end)",
                    "support_words_per_s": round(d["granule_rows"] * 64 / elapsed, 1),
-                   "achieved_GBps_busy": round(bytes_total / busy_s / 1e9, 2) if busy_s > 0 else None},
+                   "achieved_GBps_busy": round(bytes_total / busy_s / 1e9, 2) if busy_s > 0 else None,
+                   "profiled_launch_us_per_call": prof.get("dispatch_us_per_call") if prof else None},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 6), "traffic": traffic,
                      "bytes_per_launch": round(bytes_total / max(dispatches, 1), 1),
@@ -1120,10 +1142,12 @@ def main():
         "host": host_info(),
     }
     note(f"plain leg done: {value:.0f} propagations/s")
-    note("tiny-table leg")
-    out["tiny_table"] = tiny_leg(seed, 50, not args.no_cpu_baseline)
-    note("copy probe")
-    out["copy_probe"] = copy_probe()
+    if not args.no_tiny:
+        note("tiny-table leg")
+        out["tiny_table"] = tiny_leg(seed, 50, not args.no_cpu_baseline)
+    if not args.no_probe:
+        note("copy probe")
+        out["copy_probe"] = copy_probe()
     if not args.no_split:
         note("split propagators on the plain script")
         out["split_propagators"] = split_leg(table, script, max(1, args.steps))
@@ -1153,10 +1177,14 @@ def main():
         gc.collect()
         note("wide-scope leg")
         out["wide_scope"] = wide_leg(seed, 300, not args.no_cpu_baseline)
+        if not args.no_paper_shape:
+            gc.collect()
+            note("paper-shape leg")
+            out["paper_shape"] = wide_leg(seed, 200, not args.no_cpu_baseline, split=False, paper_shape=True)
     if not args.no_driver:
         gc.collect()
         note("search driver leg")
-        out["search_driver"] = solver_leg(seed, 400, not args.no_cpu_baseline)
+        out["search_driver"] = solver_leg(seed, not args.no_cpu_baseline)
     if not args.no_nodes:
         gc.collect()
         note("search-node leg")

@@ -72,12 +72,20 @@ def summarize(args):
     out = {"kernel": prop["Name"], "calls": int(prop["Calls"]), "avg_us": round(avg_ns / 1e3, 3),
            "min_us": round(float(prop["MinNs"]) / 1e3, 3), "max_us": round(float(prop["MaxNs"]) / 1e3, 3),
            "kernel_source_sha256": kernel_source_hash()}
+    if args.calls_traced:
+        # a resident kernel serves many calls per dispatch: its dispatches'
+        # whole lifetimes over the calls they served
+        out["calls_traced"] = args.calls_traced
+        out["dispatch_us_per_call"] = round(avg_ns * int(prop["Calls"]) / 1e3 / args.calls_traced, 3)
     lines = [f"# {args.title}", "", f"Command (from the repository root): `{args.command}`", "",
              "Kernel-trace statistics (rocprofv3 --kernel-trace --stats):", "",
              "| kernel | calls | avg µs | min µs | max µs | share |", "|---|---|---|---|---|---|"]
     for r in stats[:6]:
         lines.append(f"| {r['Name'][:60]} | {r['Calls']} | {float(r['AverageNs'])/1e3:.3f} | "
                      f"{float(r['MinNs'])/1e3:.3f} | {float(r['MaxNs'])/1e3:.3f} | {float(r['Percentage']):.2f} % |")
+    if args.calls_traced:
+        lines += ["", f"* {prop['Name'][:60]}: {out['calls']} dispatches served the {args.calls_traced} calls of the "
+                      f"traced run: {out['dispatch_us_per_call']:.3f} µs of dispatch lifetime per call"]
     if args.fetch and args.write and args.copy_bytes:
         f = counter_by_kernel(args.fetch, "FETCH_SIZE")
         w = counter_by_kernel(args.write, "WRITE_SIZE")
@@ -141,6 +149,8 @@ def main():
     s.add_argument("--kernel", default=KERNEL, help="regular expression naming the kernel")
     s.add_argument("--calls", type=int, default=0,
                    help="calls served by the kernel's dispatches in each counter run (resident kernels)")
+    s.add_argument("--calls-traced", type=int, default=0,
+                   help="calls served by the kernel's dispatches in the kernel-trace run (resident kernels)")
     s.add_argument("--title", default=DEFAULT_TITLE)
     s.add_argument("--out", required=True)
     a = p.parse_args()

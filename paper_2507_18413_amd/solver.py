@@ -81,11 +81,101 @@ class LinearLE:
         return False, out
 
 
+class LinearEQ:
+    """sum_i w_i * x_i = c over pool variables (w_i > 0, lo_i = 0), bounds
+    reasoning repeated until the bounds settle: with Smin / Smax the sums of
+    the weighted minima / maxima, x_i <= min_i + (c - Smin) // w_i and
+    x_i >= max_i - (Smax - c) // w_i; fails when c lies outside
+    [Smin, Smax] or a domain empties."""
+
+    def __init__(self, layout: DomLayout, vars_, weights, c: int):
+        self.lay = layout
+        self.vars = [int(v) for v in vars_]
+        self.w = [int(x) for x in weights]
+        self.c = int(c)
+
+    def propagate(self, pool: np.ndarray):
+        lay = self.lay
+        vals = [lay.values(pool, v) for v in self.vars]
+        if any(v.size == 0 for v in vals):
+            return True, pool
+        lo = [int(v[0]) for v in vals]
+        hi = [int(v[-1]) for v in vals]
+        smin = sum(w * a for w, a in zip(self.w, lo))
+        smax = sum(w * b for w, b in zip(self.w, hi))
+        changed = False
+        while True:
+            if self.c < smin or self.c > smax:
+                return True, pool
+            moved = False
+            for k, w in enumerate(self.w):
+                nhi = min(hi[k], lo[k] + (self.c - smin) // w)
+                nlo = max(lo[k], hi[k] - (smax - self.c) // w)
+                if nhi != hi[k] or nlo != lo[k]:
+                    v = vals[k]
+                    v = v[(v >= nlo) & (v <= nhi)]
+                    if v.size == 0:
+                        return True, pool
+                    vals[k] = v
+                    a, b = int(v[0]), int(v[-1])
+                    smin += w * (a - lo[k])
+                    smax += w * (b - hi[k])
+                    lo[k], hi[k] = a, b
+                    moved = changed = True
+                    if self.c < smin or self.c > smax:
+                        return True, pool
+            if not moved:
+                break
+        if not changed:
+            return False, pool
+        out = pool.copy()
+        for v, k in zip(self.vars, range(len(self.vars))):
+            for a in lay.values(pool, v):
+                if int(a) < lo[k] or int(a) > hi[k]:
+                    lay.clear(out, v, int(a))
+        return False, out
+
+
+class OneTable:
+    """One table constraint over all the pool variables, in column order, as
+    a table propagator: a single propagate call reaches its GAC (a table is
+    idempotent after its own call).  ``t`` is a ``ct.Table`` or any object
+    with the same propagate / push / pop (the oracle's table in the tests)."""
+
+    def __init__(self, t):
+        self.t = t
+        self.props = 0
+        self.seconds = 0.0  # host time spent inside the table's propagate calls
+
+    def fixpoint(self, pool: np.ndarray):
+        t0 = time.perf_counter()
+        st, out = self.t.propagate(pool)[:2]
+        self.seconds += time.perf_counter() - t0
+        self.props += 1
+        if st != 0:
+            return True, pool
+        return False, np.asarray(out, dtype=np.uint64).copy()
+
+    def push(self):
+        self.t.push()
+
+    def pop(self):
+        self.t.pop()
+
+
 class Search:
-    def __init__(self, layout: DomLayout, tables, linear: LinearLE):
+    """Depth-first search.  var_order: "min_dom" (smallest domain of more
+    than one value, lowest index first) or "input" (the first variable with
+    more than one value, MiniZinc's input_order); val_order: "min"
+    (increasing values) or "max" (decreasing, indomain_max)."""
+
+    def __init__(self, layout: DomLayout, tables, linear, var_order: str = "min_dom",
+                 val_order: str = "min"):
         self.lay = layout
         self.tables = tables
         self.lin = linear
+        self.var_order = var_order
+        self.val_order = val_order
         self.nodes = 0
         self.fails = 0
         self.solutions = []
@@ -106,9 +196,15 @@ class Search:
         best, size = -1, 0
         for i in range(self.lay.n):
             k = self.lay.values(pool, i).size
+            if k > 1 and self.var_order == "input":
+                return i
             if k > 1 and (best < 0 or k < size):
                 best, size = i, k
         return best
+
+    def _values(self, pool, var):
+        v = list(self.lay.values(pool, var))
+        return v[::-1] if self.val_order == "max" else v
 
     def run(self, pool: np.ndarray, max_nodes: int, max_solutions: int):
         """Depth-first search from ``pool``; stops after ``max_nodes`` nodes or
@@ -127,7 +223,7 @@ class Search:
             self.solutions.append(self.lay.to_sets(pool))
             self.tables.pop()
             return self.nodes
-        stack.append((pool, var, list(self.lay.values(pool, var))))
+        stack.append((pool, var, self._values(pool, var)))
         while stack and self.nodes < max_nodes and len(self.solutions) < max_solutions:
             base, var, left = stack[-1]
             if not left:
@@ -151,7 +247,7 @@ class Search:
                 self.solutions.append(self.lay.to_sets(child))
                 self.tables.pop()
                 continue
-            stack.append((child, nv, list(self.lay.values(child, nv))))
+            stack.append((child, nv, self._values(child, nv)))
         while stack:
             stack.pop()
             self.tables.pop()
