@@ -137,11 +137,13 @@ struct DevJob {
 
 // Granule-major schedule of a batch of search nodes (jobs that all propagate
 // one table from its root state).  Per node: the Alg. 1 prologue's outcome
-// and its row list: one segment per variable of s_val, in variable order,
-// each padded to a multiple of 4 rows with the all-zero row `rows` of the
-// update kernel's tile, its first entry tagged 0x8000 (| 0x4000 when
-// incremental); per (node, granule) the non-zero flag of the new currTable
-// granule.
+// and its row list: one segment holding the removed values' rows of every
+// incremental variable of s_val (the complement of their OR is the AND of
+// their incremental masks), then one segment per reset variable, in
+// variable order, each padded to a multiple of 4 rows with the all-zero row
+// `rows` of the update kernel's tile, its first entry tagged 0x8000 (| 0x4000
+// when incremental); per (node, granule) the non-zero flag of the new
+// currTable granule.
 struct NodeInfo {
   int32_t status, nrows;   // nrows: support rows OR-ed (without padding)
   int32_t groups, pad;     // groups: list length / 4

@@ -1147,8 +1147,10 @@ __device__ __forceinline__ void wave_lds_sync() {
 // number of values of dom_in (|dom|) and of removed root values (|Delta|)
 // decide membership of s_val and the branch of Alg. 2 (incremental when
 // |Delta| < |dom|, or as the table's policy fixes it); the node's row list
-// holds, per variable of s_val, the support rows of Delta or of dom, padded
-// to a multiple of 4 rows with the zero row, the first one tagged.
+// holds one segment with the rows of Delta of every incremental variable,
+// then per reset variable of s_val a segment with the rows of dom, each
+// segment padded to a multiple of 4 rows with the zero row and its first
+// entry tagged.
 __global__ void __launch_bounds__(BLOCK) nodes_prep_kernel(KArgs a, NodesDesc N) {
   __shared__ int32_t shSize[WAVES][MAX_ARITY];
   __shared__ int32_t shDcnt[WAVES][MAX_ARITY];
@@ -1189,25 +1191,49 @@ __global__ void __launch_bounds__(BLOCK) nodes_prep_kernel(KArgs a, NodesDesc N)
            : __ballot(stray) ? ST_INVALID
            : __ballot(notSub) ? ST_NOT_SUBSET : ST_OK;
   wave_lds_sync();
-  // segments: variables of s_val in order, each padded to a multiple of 4
-  int total = 0, padded = 0;
+  // segments.  Alg. 2's incremental masks AND together into the complement
+  // of one OR over every removed value of those variables (De Morgan), so the
+  // incremental variables of s_val share one segment, first, padded once to
+  // a multiple of 4; each reset variable follows with a segment of its own,
+  // padded the same way
+  int total = 0, incTotal = 0;
   bool emptyReset = false;
   const int policy = T->policy;
+  auto branch = [&](int i, bool* in, int* inc, int* cnt) {
+    *in = false;
+    *inc = 0;
+    *cnt = 0;
+    if (i >= n) return;
+    const int sz = size[i], dc = dcnt[i];
+    *in = dc > 0;  // |dom| changed since the root
+    *inc = policy == 2 ? 1 : policy == 1 ? 0 : (dc < sz ? 1 : 0);
+    *cnt = *in ? (*inc ? dc : sz) : 0;
+  };
   for (int i0 = 0; i0 < n; i0 += WAVE) {
     const int i = i0 + lane;
-    int cnt = 0, inc = 0;
-    bool in = false;
-    if (i < n) {
-      const int sz = size[i], dc = dcnt[i];
-      in = dc > 0;  // |dom| changed since the root
-      inc = policy == 2 ? 1 : policy == 1 ? 0 : (dc < sz ? 1 : 0);
-      cnt = in ? (inc ? dc : sz) : 0;
-      if (in && cnt == 0) emptyReset = true;  // a reset segment of an empty domain
-    }
-    const int groups = (cnt + 3) >> 2;
-    const int inclRows = wave_scan_incl(cnt);
+    bool in;
+    int inc, cnt;
+    branch(i, &in, &inc, &cnt);
+    const int c = (in && inc) ? cnt : 0;
+    const int incl = wave_scan_incl(c);
+    if (i < n) seg[i] = (in && inc) ? ((incTotal + incl - c) | (1 << 30)) : -1;
+    incTotal += __shfl(incl, WAVE - 1);
+  }
+  const int incPadded = (incTotal + 3) & ~3;
+  int padded = incPadded;
+  total = incTotal;
+  for (int i0 = 0; i0 < n; i0 += WAVE) {
+    const int i = i0 + lane;
+    bool in;
+    int inc, cnt;
+    branch(i, &in, &inc, &cnt);
+    const bool rs = in && !inc;
+    if (rs && cnt == 0) emptyReset = true;  // a reset segment of an empty domain
+    const int c = rs ? cnt : 0;
+    const int groups = (c + 3) >> 2;
+    const int inclRows = wave_scan_incl(c);
     const int inclPad = wave_scan_incl(4 * groups);
-    if (i < n) seg[i] = in ? ((padded + inclPad - 4 * groups) | (inc << 30)) : -1;
+    if (rs) seg[i] = padded + inclPad - 4 * groups;
     total += __shfl(inclRows, WAVE - 1);
     padded += __shfl(inclPad, WAVE - 1);
   }
@@ -1231,13 +1257,17 @@ __global__ void __launch_bounds__(BLOCK) nodes_prep_kernel(KArgs a, NodesDesc N)
         const int b = __ffsll((unsigned long long)bits) - 1;
         bits &= bits - 1;
         uint32_t e = (uint32_t)(base + b);
-        if (off == start) e |= 0x8000u | (inc ? 0x4000u : 0u);
+        // the first entry of the shared incremental segment, or of a reset
+        // variable's segment, carries the segment tag
+        if (inc ? off == 0 : off == start) e |= 0x8000u | (inc ? 0x4000u : 0u);
         out[off++] = (uint16_t)e;
       }
-      // the variable's last word pads its segment
-      if (q == v.domOff + v.domWords - 1)
+      // a reset variable's last word pads its segment
+      if (!inc && q == v.domOff + v.domWords - 1)
         while (off & 3) out[off++] = zeroRow;
     }
+    // the padding of the shared incremental segment
+    if (lane < incPadded - incTotal) out[incTotal + lane] = zeroRow;
   }
   if (lane == 0) {
     NodeInfo I;
