@@ -60,6 +60,8 @@ def parse():
     p.add_argument("--no-tiny", action="store_true", help="skip the tiny-table leg (profiling the plain leg)")
     p.add_argument("--no-probe", action="store_true", help="skip the device copy probe")
     p.add_argument("--no-paper-shape", action="store_true")
+    p.add_argument("--nodes-only", action="store_true",
+                   help="only the search-node batches (4,096 nodes, 1,000,000-tuple Zipf table; profiling)")
     p.add_argument("--root-batch-only", action="store_true",
                    help="only the batched root recomputation of the 2,000-table model (profiling)")
     return p.parse_args()
@@ -1026,6 +1028,13 @@ def main():
         note("batched root recomputation")
         print(json.dumps({"root_gac_batch": root_batch_leg(tabs, mspec.tables, max(1, args.steps),
                                                            per_table=False)}), flush=True)
+        return
+    if args.nodes_only:
+        torch.cuda.set_device(0)
+        calibration_copy(args.calibration_copy)
+        note("search-node leg")
+        print(json.dumps({"batched_nodes": nodes_leg(seed, args.nodes, max(1, args.steps), max(0, args.warmup),
+                                                     plain=False)}), flush=True)
         return
     if args.wide_only:
         torch.cuda.set_device(0)

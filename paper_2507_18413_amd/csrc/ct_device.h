@@ -50,6 +50,7 @@ constexpr int NEG_MAX_ROWS = 8192; // negative tables: support rows (their secon
                                    // the removed values' rows in one LDS chunk)
 constexpr int MAX_GRAN = 8192;     // granules per table (partition done in LDS)
 constexpr int INLINE_WORDS = 64;   // dom_in words carried in kernel arguments
+constexpr int ENG_MAX_D = 512;     // domain words of a table served by the resident engine
 
 // status codes (same values as the public header)
 constexpr int ST_OK = 0, ST_FAIL = 1, ST_INVALID = -1, ST_NOT_SUBSET = -2, ST_STATE = -3,
@@ -224,12 +225,12 @@ constexpr int ENG_OP_PROPAGATE = 1, ENG_OP_STOP = 2;
 struct EngCmd {             // written by the host, seq last (release)
   int32_t seq, op, nPop, nPush;
   int32_t serialBase, depthAfter, wantCt, wantStats;
-  uint64_t dom[INLINE_WORDS];
+  uint64_t dom[ENG_MAX_D];
 };
 
 struct EngRes {             // written by the engine, seq last (release)
   int32_t seq, status, alive, exitSeq;
-  uint64_t dom[INLINE_WORDS];
+  uint64_t dom[ENG_MAX_D];
   unsigned long long stats[8];  // the slot's counters after the call
   unsigned long long callTicks;  // device clock (100 MHz) spent in the call
   unsigned long long lifeTicks;  // written at exit: the launch's lifetime (device clock)

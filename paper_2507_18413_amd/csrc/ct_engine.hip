@@ -31,7 +31,7 @@ constexpr int E_LANE_SCAN = 16;  // words each missing lane checks after its res
 struct EngState {
   int32_t op, seq, lastSeq, nPop, nPush, serialBase, depthAfter, wantCt, wantStats, pad3;
   int32_t limit, failed, depth, serial, cur, status, noop, nseg;
-  int32_t nrows, badStray, badSub, trailCount, nSurv, devErr, pad0, pad1;
+  int32_t nrows, badStray, badSub, trailCount, nSurv, devErr, nMiss, nLeft;
   int64_t trailTop, lvTrailTop;
   int32_t lvLimit, lvFailed, lvSerial, pad2;
   int32_t waveSum[EWAVES];
@@ -40,9 +40,20 @@ struct EngState {
 
 // Dynamic LDS regions, in this order, each 8-byte aligned.
 enum { R_CT, R_IDX0, R_IDX1, R_STAMP, R_NZ, R_FIRST, R_RES, R_LAST, R_DIN, R_ROWS, R_WVAR, R_VARS, R_VSIZE,
-       R_VDCNT, R_SEGOF, R_SEGEND, R_SEGINC, R_STATE, R_END };
+       R_VDCNT, R_SEGOF, R_SEGEND, R_SEGINC, R_WCNT, R_MSLOT, R_LEFT, R_MFOUND, R_STATE, R_END };
+
+// Tables of at most this many domain words filter one word per wave (one
+// pass, no barrier); wider ones filter flat over the value slots.
+constexpr int E_NARROW_D = 16;
+// The flat filter keeps the values whose residue word missed in a list of at
+// most this many entries (a domain slot fits 16 bits: ENG_MAX_D x 64 slots);
+// wider domains are filtered in chunks of slots.
+constexpr int E_MISS_CAP = 16384;
+static_assert(ENG_MAX_D * 64 <= 65536, "domain slots fit 16 bits");
 
 __host__ __device__ inline size_t eng_align(size_t x) { return (x + 7) & ~(size_t)7; }
+
+__host__ __device__ inline int eng_miss_cap(int D) { return D * 64 < E_MISS_CAP ? D * 64 : E_MISS_CAP; }
 
 __host__ __device__ inline void eng_layout(int n, int D, int nGran, int rows, size_t* off) {
   size_t sz[R_END];
@@ -57,6 +68,10 @@ __host__ __device__ inline void eng_layout(int n, int D, int nGran, int rows, si
   sz[R_WVAR] = (size_t)D * 4;
   sz[R_VARS] = (size_t)n * sizeof(VarDesc);
   sz[R_VSIZE] = sz[R_VDCNT] = sz[R_SEGOF] = sz[R_SEGEND] = sz[R_SEGINC] = (size_t)n * 4;
+  sz[R_WCNT] = (size_t)D * 4;
+  const int cap = D > E_NARROW_D ? eng_miss_cap(D) : 0;
+  sz[R_MSLOT] = sz[R_LEFT] = (size_t)cap * 2;
+  sz[R_MFOUND] = (size_t)cap;
   sz[R_STATE] = sizeof(EngState);
   size_t o = 0;
   for (int r = 0; r < R_END; ++r) {
@@ -76,6 +91,14 @@ __device__ __forceinline__ void lds_barrier() {
 }
 
 __device__ __forceinline__ int e_lane() { return threadIdx.x & (WAVE - 1); }
+// The thread index, opaque to the optimizer: a phase of the call loop
+// computes its per-thread LDS addresses from it afresh, instead of keeping
+// every phase's addresses live across the whole loop (which spilled them).
+__device__ __forceinline__ int e_tid() {
+  int t = threadIdx.x;
+  asm volatile("" : "+v"(t));
+  return t;
+}
 __device__ __forceinline__ int e_wave() { return __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE); }
 
 // Support rows through a buffer resource: one scalar descriptor, a scalar
@@ -115,6 +138,11 @@ struct Eng {
   int32_t* wordVar;
   VarDesc* vars;
   int32_t *vsize, *vdcnt, *segOf, *segEnd, *segInc;
+  int32_t* wcnt;     // per domain word: popcount of Delta << 16 | popcount of dom_in (wide prologue)
+  uint16_t* mSlot;   // filter misses: domain slot (word << 6 | bit)
+  uint16_t* left;    //   misses the walk after the residue did not resolve
+  uint8_t* mFound;   //   a support was found by the granule scans
+  int missCap;
   EngState* st;
 };
 
@@ -138,6 +166,7 @@ __device__ __forceinline__ int e_wscan(int v) {
 // trail and the levels stay in HBM)
 // ---------------------------------------------------------------------------
 __device__ void e_pops_pushes(Eng& E) {
+  const int tid = e_tid();
   EngState* st = E.st;
   const int nPop = st->nPop, nPush = st->nPush;
   if (nPop > 0) {
@@ -146,18 +175,18 @@ __device__ void e_pops_pushes(Eng& E) {
     // gets the words of its first entry there (the oldest save holds the
     // words of that level)
     const int dT = st->depth - nPop;
-    if (threadIdx.x == 0) {
+    if (tid == 0) {
       const Level L = E.levels[dT];
       st->lvTrailTop = L.trailTop;
       st->lvLimit = L.limit;
       st->lvFailed = L.failed;
       st->lvSerial = L.serial;
     }
-    for (int g = threadIdx.x; g < E.nGran; g += EBLOCK) E.first[g] = 0x7fffffff;
-    for (int q = threadIdx.x; q < E.D; q += EBLOCK) E.last[q] = E.levelDom[(int64_t)dT * E.D + q];
+    for (int g = tid; g < E.nGran; g += EBLOCK) E.first[g] = 0x7fffffff;
+    for (int q = tid; q < E.D; q += EBLOCK) E.last[q] = E.levelDom[(int64_t)dT * E.D + q];
     lds_barrier();
     const int64_t lo = st->lvTrailTop, top = st->trailTop;
-    for (int64_t e = lo + threadIdx.x; e < top; e += EBLOCK) atomicMin(&E.first[E.trailHdr[e].gran], (int)(e - lo));
+    for (int64_t e = lo + tid; e < top; e += EBLOCK) atomicMin(&E.first[E.trailHdr[e].gran], (int)(e - lo));
     lds_barrier();
     for (int64_t e = lo + e_wave(); e < top; e += EWAVES) {
       const TrailHdr h = E.trailHdr[e];
@@ -167,7 +196,7 @@ __device__ void e_pops_pushes(Eng& E) {
       }
     }
     lds_barrier();
-    if (threadIdx.x == 0) {
+    if (tid == 0) {
       st->trailTop = lo;
       st->limit = st->lvLimit;
       st->failed = st->lvFailed;
@@ -178,11 +207,11 @@ __device__ void e_pops_pushes(Eng& E) {
   }
   // each push records the state before this call's propagation (wave 0,
   // which also runs the prologue next: no barrier needed)
-  if (threadIdx.x < WAVE && nPush > 0) {
+  if (tid < WAVE && nPush > 0) {
     const int lane = e_lane();
     for (int k = 0; k < nPush; ++k) {
       const int d = st->depth + k;
-      if (lane < E.D) E.levelDom[(int64_t)d * E.D + lane] = E.last[lane];
+      for (int q = lane; q < E.D; q += WAVE) E.levelDom[(int64_t)d * E.D + q] = E.last[q];
       if (lane == 0) {
         Level L;
         L.trailTop = st->trailTop;
@@ -201,14 +230,15 @@ __device__ void e_pops_pushes(Eng& E) {
 }
 
 // ---------------------------------------------------------------------------
-// prologue of Alg. 1, by wave 0 with one domain word per lane (the engine
-// takes tables of at most 64 domain words): checks, |dom| and |Delta| per
-// variable (prefix sums over the words), s_val, the branch of Alg. 2 per
-// variable and the list of support rows to OR, segment by segment
+// prologue of Alg. 1, by wave 0 with one domain word per lane (tables of at
+// most 64 domain words): checks, |dom| and |Delta| per variable (prefix sums
+// over the words), s_val, the branch of Alg. 2 per variable and the list of
+// support rows to OR, segment by segment
 // ---------------------------------------------------------------------------
-__device__ void e_prologue(Eng& E) {
+__device__ void e_prologue_narrow(Eng& E) {
+  const int tid = e_tid();
   EngState* st = E.st;
-  if (threadIdx.x < WAVE) {
+  if (tid < WAVE) {
     const int q = e_lane();
     const bool isWord = q < E.D;
     uint64_t din = 0, ld = 0;
@@ -238,6 +268,7 @@ __device__ void e_prologue(Eng& E) {
     const int dc = __shfl(scD, lastW) - (first > 0 ? befD : 0);
     // decisions on each variable's first word
     const bool head = isWord && q == first;
+    if (head) E.vsize[E.wordVar[q]] = sz;  // |dom(x_i)|: the filter's s_sup test
     const bool in = head && dc > 0;  // |dom| changed since the last call: in s_val
     const int policy = E.policy;
     const int inc = policy == 2 ? 1 : policy == 1 ? 0 : (dc < sz ? 1 : 0);
@@ -273,6 +304,98 @@ __device__ void e_prologue(Eng& E) {
     }
   }
   lds_barrier();
+}
+
+// ---------------------------------------------------------------------------
+// the same prologue for tables of more than 64 domain words: per-word checks
+// and counts by every thread (LDS atomics per variable), the variables'
+// decisions and segments by wave 0 (64 variables per step), then the row
+// list by every thread, one domain word each
+// ---------------------------------------------------------------------------
+__device__ void e_prologue_wide(Eng& E) {
+  EngState* st = E.st;
+  const int tid = e_tid();
+  for (int i = tid; i < E.n; i += EBLOCK) {
+    E.vsize[i] = 0;
+    E.vdcnt[i] = 0;
+  }
+  if (tid == 0) {
+    st->badStray = 0;
+    st->badSub = 0;
+  }
+  lds_barrier();
+  int stray = 0, notSub = 0;
+  for (int q = tid; q < E.D; q += EBLOCK) {
+    const uint64_t din = E.din[q], ld = E.last[q];
+    const int i = E.wordVar[q];
+    const VarDesc v = E.vars[i];
+    const int used = v.dsize - 64 * (q - v.domOff);
+    if (used < 64 && (din >> used) != 0) stray = 1;
+    if (din & ~ld) notSub = 1;
+    const int cs = __popcll(din), cd = __popcll(ld & ~din);
+    E.wcnt[q] = (cd << 16) | cs;
+    atomicAdd(&E.vsize[i], cs);
+    atomicAdd(&E.vdcnt[i], cd);
+  }
+  if (__ballot(stray) && e_lane() == 0) atomicOr(&st->badStray, 1);
+  if (__ballot(notSub) && e_lane() == 0) atomicOr(&st->badSub, 1);
+  lds_barrier();
+  int status = st->failed ? ST_STATE : st->badStray ? ST_INVALID : st->badSub ? ST_NOT_SUBSET : ST_OK;
+  if (threadIdx.x < WAVE) {
+    const int lane = e_lane();
+    const int policy = E.policy;
+    int nseg = 0, nrows = 0;
+    for (int i0 = 0; i0 < E.n; i0 += WAVE) {
+      const int i = i0 + lane;
+      int cnt = 0, inc = 0;
+      bool in = false;
+      if (i < E.n) {
+        const int sz = E.vsize[i], dc = E.vdcnt[i];
+        in = dc > 0;  // |dom| changed since the last call: in s_val
+        inc = policy == 2 ? 1 : policy == 1 ? 0 : (dc < sz ? 1 : 0);
+        cnt = in ? (inc ? dc : sz) : 0;
+      }
+      const int scSeg = e_wscan(in ? 1 : 0), scCnt = e_wscan(cnt);
+      if (in) {
+        E.segEnd[nseg + scSeg - 1] = nrows + scCnt;
+        E.segInc[nseg + scSeg - 1] = inc;
+      }
+      if (i < E.n) E.segOf[i] = in ? ((nrows + scCnt - cnt) | (inc << 30)) : -1;
+      nseg += __builtin_amdgcn_readlane(scSeg, WAVE - 1);
+      nrows += __builtin_amdgcn_readlane(scCnt, WAVE - 1);
+    }
+    if (lane == 0) {
+      st->status = status;
+      st->nseg = nseg;
+      st->nrows = nrows;
+      st->noop = nseg == 0;
+    }
+  }
+  lds_barrier();
+  if (status == ST_OK && !st->noop) {
+    for (int q = tid; q < E.D; q += EBLOCK) {
+      const int i = E.wordVar[q];
+      const int sg = E.segOf[i];
+      if (sg < 0) continue;
+      const int inc = sg >> 30;
+      const VarDesc v = E.vars[i];
+      int off = sg & 0x3FFFFFFF;
+      for (int k = v.domOff; k < q; ++k) off += inc ? (E.wcnt[k] >> 16) : (E.wcnt[k] & 0xFFFF);
+      uint64_t b = inc ? (E.last[q] & ~E.din[q]) : E.din[q];
+      const int base = v.rowStart + (q - v.domOff) * 64;
+      while (b) {
+        const int k = __ffsll((unsigned long long)b) - 1;
+        b &= b - 1;
+        E.rowList[off++] = (uint16_t)(base + k);
+      }
+    }
+  }
+  lds_barrier();
+}
+
+__device__ __forceinline__ void e_prologue(Eng& E) {
+  if (E.D <= WAVE) e_prologue_narrow(E);
+  else e_prologue_wide(E);
 }
 
 // ---------------------------------------------------------------------------
@@ -398,8 +521,9 @@ __device__ void e_update(Eng& E) {
 // stable partition of the active granules (survivors first), new limit,
 // FAIL when none survives (Alg. 1); wave 0, 64 positions per step
 __device__ void e_partition(Eng& E) {
+  const int tid = e_tid();
   EngState* st = E.st;
-  if (threadIdx.x < WAVE) {
+  if (tid < WAVE) {
     const int lane = e_lane();
     const int limit = st->limit, cur = st->cur, nGran = E.nGran;
     const uint16_t* src = cur ? E.idx1 : E.idx0;
@@ -437,8 +561,10 @@ __device__ void e_partition(Eng& E) {
 }
 
 // ---------------------------------------------------------------------------
-// filterDomains (Alg. 3) for domain word q, by one wave: residue first, then
-// the words after it, then the active granules in index order
+// filterDomains (Alg. 3) of tables of at most E_NARROW_D domain words: one
+// wave per domain word, all words at once, no workgroup barrier.  For word q:
+// the residue first, then the words after it, then the active granules in
+// index order
 // ---------------------------------------------------------------------------
 // The support word at a value's residue does not depend on currTable: it is
 // loaded before updateTable (e_residue_word) and tested after it.
@@ -551,6 +677,188 @@ __device__ void e_filter_word(Eng& E, int q, unsigned long long* cnt, bool haveP
   if (lane == 0) E.last[q] = dout;
 }
 
+// ---------------------------------------------------------------------------
+// filterDomains (Alg. 3): every present value of a variable with two or more
+// values (s_sup) keeps its place iff its support row meets currTable.  The
+// work is flat over the domain slots (word << 6 | bit), so every wave takes
+// part whatever the number of domain words:
+//   A. one thread per slot tests the support word at the value's residue
+//      (loaded before updateTable for the first EBLOCK slots: the residue
+//      and the support rows do not change during it); misses go to a list;
+//   B. one thread per miss reads the 16 words after the residue;
+//   C. the misses still without a support scan the active granules, in
+//      tasks of (value, 4 granules) shared by the waves;
+//   values with no support found leave dom_out.
+// Slots are taken in chunks of at most missCap (the miss list's size).
+// ---------------------------------------------------------------------------
+struct ResiduePre {
+  int rw;      // the residue of the thread's first slot
+  uint64_t x;  // the support word there
+};
+
+__device__ __forceinline__ int e_slot_row(const Eng& E, int slot) {
+  const VarDesc v = E.vars[E.wordVar[slot >> 6]];
+  return v.rowStart + ((slot >> 6) - v.domOff) * 64 + (slot & 63);
+}
+
+// the slot is a value filterDomains checks: present in dom_in, and its
+// variable has two or more values
+__device__ __forceinline__ bool e_checked(const Eng& E, int slot) {
+  return ((E.din[slot >> 6] >> (slot & 63)) & 1ull) && E.vsize[E.wordVar[slot >> 6]] > 1;
+}
+
+// Residue word of slot `slot` (row 0 for a slot that is not checked: an
+// unconditional load from a valid address).
+__device__ __forceinline__ ResiduePre e_residue(const Eng& E, int slot, bool chk) {
+  ResiduePre r;
+  const int row = chk ? e_slot_row(E, slot) : 0;
+  r.rw = E.res[row];
+  r.x = E.S[(int64_t)row * E.stride + r.rw];
+  return r;
+}
+
+constexpr int E_A_UNROLL = 4;  // residue loads per thread in flight (phase A)
+constexpr int E_C_TASKS = 2;   // (value, 4 granules) tasks per wave step (phase C)
+
+__device__ void e_filter(Eng& E, bool havePre, ResiduePre pre) {
+  EngState* st = E.st;
+  const int lane = e_lane();
+  const int tid = e_tid();
+  const int nSlots = E.D * 64;
+  const int cap = E.missCap;
+  const int64_t words = (int64_t)E.nGran * GW;
+  const int lim = st->limit;
+  const uint16_t* idx = st->cur ? E.idx1 : E.idx0;
+  unsigned long long cChk = 0, cMiss = 0, cScan = 0;
+  for (int base = 0; base < nSlots; base += cap) {
+    const int end = min(nSlots, base + cap);
+    if (tid == 0) {
+      st->nMiss = 0;
+      st->nLeft = 0;
+    }
+    lds_barrier();
+    // A: residues
+    for (int s0 = base + tid; s0 < end; s0 += EBLOCK * E_A_UNROLL) {
+      bool chk[E_A_UNROLL];
+      ResiduePre r[E_A_UNROLL];
+      const bool usePre = havePre && s0 == tid;  // the first step of the first chunk
+#pragma unroll
+      for (int u = 0; u < E_A_UNROLL; ++u) {
+        const int sl = s0 + u * EBLOCK;
+        chk[u] = sl < end && e_checked(E, sl);
+        if (u == 0 && usePre) r[u] = pre;
+        else r[u] = e_residue(E, sl < end ? sl : 0, chk[u]);
+      }
+#pragma unroll
+      for (int u = 0; u < E_A_UNROLL; ++u) {
+        if (!chk[u]) continue;
+        ++cChk;
+        if ((E.ct[r[u].rw] & r[u].x) == 0ull) {
+          const int k = atomicAdd(&st->nMiss, 1);
+          E.mSlot[k] = (uint16_t)(s0 + u * EBLOCK);
+          ++cMiss;
+        }
+      }
+    }
+    lds_barrier();
+    // B: the 16 words after the residue, one thread per miss
+    const int nMiss = st->nMiss;
+    for (int k = tid; k < nMiss; k += EBLOCK) {
+      const int row = e_slot_row(E, E.mSlot[k]);
+      const int rw0 = E.res[row];  // the residue that missed (not changed since)
+      const CT_G uint64_t* rp = E.S + (int64_t)row * E.stride;
+      int found = -1;
+      for (int j0 = 0; j0 < E_LANE_SCAN && found < 0; j0 += 8) {
+        uint64_t x[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+          int w = rw0 + 1 + j0 + j;
+          if (w >= words) w -= (int)words;
+          x[j] = rp[w];
+        }
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+          int w = rw0 + 1 + j0 + j;
+          if (w >= words) w -= (int)words;
+          if (found < 0 && (E.ct[w] & x[j])) found = w;
+        }
+      }
+      ++cScan;
+      if (found >= 0) {
+        E.res[row] = found;
+      } else {
+        const int j = atomicAdd(&st->nLeft, 1);
+        E.left[j] = (uint16_t)k;
+        E.mFound[j] = 0;
+      }
+    }
+    lds_barrier();
+    // C: the active granules, in index order per value; task t is value
+    // t % nLeft, granules 4 (t / nLeft) .. +3, so every value's first
+    // granules come first and a value found there skips the rest
+    const int nLeft = st->nLeft;
+    const int chunks = (lim + 3) / 4;
+    const int nTasks = nLeft * chunks;
+    for (int t0 = e_wave() * E_C_TASKS; t0 < nTasks; t0 += EWAVES * E_C_TASKS) {
+      int jv[E_C_TASKS], row[E_C_TASKS], g[E_C_TASKS][4];
+      bool live[E_C_TASKS];
+      uint64_t y[E_C_TASKS][4];
+#pragma unroll
+      for (int u = 0; u < E_C_TASKS; ++u) {
+        const int t = t0 + u;
+        live[u] = t < nTasks;
+        jv[u] = live[u] ? t % nLeft : 0;
+        const int c = live[u] ? t / nLeft : 0;
+        live[u] = live[u] && !E.mFound[jv[u]];
+        // the same on every lane: scalar registers
+        row[u] = __builtin_amdgcn_readfirstlane(live[u] ? e_slot_row(E, E.mSlot[E.left[jv[u]]]) : 0);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int p = 4 * c + q;
+          g[u][q] = __builtin_amdgcn_readfirstlane((live[u] && p < lim) ? (int)idx[p] : -1);
+          y[u][q] = E.S[(int64_t)row[u] * E.stride + (int64_t)max(g[u][q], 0) * GW + lane];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < E_C_TASKS; ++u) {
+        if (!live[u]) continue;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          if (g[u][q] < 0) break;
+          ++cScan;
+          const unsigned long long bm =
+              __ballot((E.ct[(int64_t)g[u][q] * GW + lane] & y[u][q]) != 0ull);
+          if (bm) {
+            if (lane == 0) {
+              E.mFound[jv[u]] = 1;
+              E.res[row[u]] = g[u][q] * GW + (__ffsll(bm) - 1);
+            }
+            break;
+          }
+        }
+      }
+    }
+    lds_barrier();
+    // values with no support leave the domain
+    for (int j = tid; j < nLeft; j += EBLOCK) {
+      if (!E.mFound[j]) {
+        const int sl = E.mSlot[E.left[j]];
+        atomicAnd((unsigned long long*)&E.last[sl >> 6], ~(1ull << (sl & 63)));
+      }
+    }
+    lds_barrier();
+  }
+  // the counters: summed over the wave first (every lane is active here)
+  const int sChk = __builtin_amdgcn_readlane(e_wscan((int)cChk), WAVE - 1);
+  const int sMiss = __builtin_amdgcn_readlane(e_wscan((int)cMiss), WAVE - 1);
+  const int sScan = __builtin_amdgcn_readlane(e_wscan((int)cScan), WAVE - 1);
+  if (lane == 0 && (sChk | sMiss | sScan)) {
+    atomicAdd(&st->stat[S_RES_CHECK], (unsigned long long)sChk);
+    atomicAdd(&st->stat[S_RES_MISS], (unsigned long long)sMiss);
+    atomicAdd(&st->stat[S_SCAN], (unsigned long long)sScan);
+  }
+}
+
 __device__ void e_load(Eng& E, const EngDesc& D) {
   const CT_G SlotDesc* s = E.slot;
   EngState* st = E.st;
@@ -651,6 +959,11 @@ __global__ void __launch_bounds__(EBLOCK) engine_kernel(EngDesc D) {
   E.segOf = (int32_t*)(lds + off[R_SEGOF]);
   E.segEnd = (int32_t*)(lds + off[R_SEGEND]);
   E.segInc = (int32_t*)(lds + off[R_SEGINC]);
+  E.wcnt = (int32_t*)(lds + off[R_WCNT]);
+  E.mSlot = (uint16_t*)(lds + off[R_MSLOT]);
+  E.left = (uint16_t*)(lds + off[R_LEFT]);
+  E.mFound = (uint8_t*)(lds + off[R_MFOUND]);
+  E.missCap = eng_miss_cap(E.D);
   E.st = (EngState*)(lds + off[R_STATE]);
   EngState* st = E.st;
   EngCmd* cmd = D.cmd;
@@ -678,14 +991,33 @@ __global__ void __launch_bounds__(EBLOCK) engine_kernel(EngDesc D) {
       }
       seen = __shfl(seen, 0);
       constexpr int HDR = (int)(offsetof(EngCmd, dom) / 8);  // header words
-      uint64_t w0 = 0, w1 = 0;
+      constexpr int CHUNKS = (HDR + ENG_MAX_D) / WAVE;      // whole 64-word chunks of EngCmd
+      static_assert(CHUNKS * WAVE <= HDR + ENG_MAX_D, "chunks within the mailbox");
+      uint64_t w0 = 0;
       if (seen) {
         const uint64_t* words = (const uint64_t*)cmd;
-        const int l = threadIdx.x;
-        w0 = l < HDR + E.D ? words[l] : 0ull;
-        w1 = l + WAVE < HDR + E.D ? words[l + WAVE] : 0ull;
-        if (l >= HDR && l < HDR + E.D) E.din[l - HDR] = w0;
-        if (l + WAVE - HDR < E.D) E.din[l + WAVE - HDR] = w1;
+        const int l = e_tid();
+        // the header and the domains, 64 words per wave-wide load; every
+        // load of the needed chunks is issued before the first is used (all
+        // addresses lie inside the mailbox, used or not)
+        if (HDR + E.D <= 2 * WAVE) {
+          const uint64_t a = words[l], b = words[l + WAVE];
+          if (l >= HDR && l - HDR < E.D) E.din[l - HDR] = a;
+          if (l + WAVE - HDR < E.D) E.din[l + WAVE - HDR] = b;
+          w0 = a;
+        } else {
+          uint64_t w[CHUNKS + 1];
+#pragma unroll
+          for (int u = 0; u < CHUNKS; ++u) w[u] = words[l + u * WAVE];
+          // the last, partial chunk
+          w[CHUNKS] = CHUNKS * WAVE + l < HDR + ENG_MAX_D ? words[CHUNKS * WAVE + l] : 0ull;
+#pragma unroll
+          for (int u = 0; u <= CHUNKS; ++u) {
+            const int k = l + u * WAVE - HDR;
+            if (k >= 0 && k < E.D) E.din[k] = w[u];
+          }
+          w0 = w[0];
+        }
       }
       // header words: {seq, op}, {nPop, nPush}, {serialBase, depthAfter}, {wantCt, wantStats}
       const uint64_t h0 = __shfl(w0, 0), h1 = __shfl(w0, 1), h2 = __shfl(w0, 2), h3 = __shfl(w0, 3);
@@ -705,10 +1037,21 @@ __global__ void __launch_bounds__(EBLOCK) engine_kernel(EngDesc D) {
 
     e_pops_pushes(E);
     e_prologue(E);
-    // residue words of this wave's first domain word, in flight during the update
-    ResidueWord pre{0, 0, 0ull};
-    const bool havePre = st->status == ST_OK && !st->noop && e_wave() < E.D;
-    if (havePre) pre = e_residue_word(E, e_wave());
+    // residue words in flight during the update: this wave's domain word
+    // (narrow tables) or this thread's first value slot (wide tables)
+    const bool narrow = E.D <= E_NARROW_D;
+    ResidueWord preW{0, 0, 0ull};
+    ResiduePre pre{0, 0ull};
+    const bool havePre = st->status == ST_OK && !st->noop;
+    if (havePre) {
+      if (narrow) {
+        if (e_wave() < E.D) preW = e_residue_word(E, e_wave());
+      } else {
+        const int tid = e_tid();
+        const int sl = tid < E.D * 64 ? tid : 0;
+        pre = e_residue(E, sl, tid < E.D * 64 && e_checked(E, sl));
+      }
+    }
     if (st->status == ST_OK && !st->noop) {
       const int limitIn = st->limit;
       e_update(E);
@@ -723,14 +1066,21 @@ __global__ void __launch_bounds__(EBLOCK) engine_kernel(EngDesc D) {
       atomicAdd(&st->stat[S_GRAN_IN], (unsigned long long)st->limit);
     }
     lds_barrier();
-    if (st->status == ST_OK) {
+    if (st->status == ST_OK && narrow) {
       unsigned long long cnt[3] = {0, 0, 0};
       for (int q = e_wave(); q < E.D; q += EWAVES)
-        e_filter_word(E, q, cnt, havePre && q == e_wave(), pre);
+        e_filter_word(E, q, cnt, havePre && q == e_wave(), preW);
       if (e_lane() == 0 && (cnt[0] | cnt[1] | cnt[2])) {
         atomicAdd(&st->stat[S_RES_CHECK], cnt[0]);
         atomicAdd(&st->stat[S_RES_MISS], cnt[1]);
         atomicAdd(&st->stat[S_SCAN], cnt[2]);
+      }
+    } else if (st->status == ST_OK) {
+      // dom_out starts as dom_in; the filter clears the values it removes
+      for (int q = e_tid(); q < E.D; q += EBLOCK) E.last[q] = E.din[q];
+      if (!st->noop) {
+        lds_barrier();
+        e_filter(E, havePre, pre);
       }
     }
     lds_barrier();

@@ -1295,9 +1295,10 @@ __global__ void __launch_bounds__(BLOCK) nodes_prep_kernel(KArgs a, NodesDesc N)
 // Persistent workgroups (as many as fit at once) walk the tiles: while one
 // tile is evaluated from LDS, the next one's words are already on their way
 // into registers, so the memory latency of staging is hidden.  Block b runs on
-// XCD b % 8 (round-robin dispatch) and takes the spans s with s % 8 == b % 8,
-// in order, so the blocks of an XCD work on the same span at about the same
-// time and its L2 serves it to all of them after one fetch from HBM.
+// XCD b % 8 (round-robin dispatch) and works on the spans s with
+// s % 8 == b % 8 (they stay in that XCD's L2): the XCD's tiles, span-major,
+// are cut into one contiguous range per block, so a block keeps a span's
+// rows in LDS across its groups and restages only the node records.
 constexpr int NODES_TPF = 16;  // tile words per thread prefetched (rows <= 128)
 constexpr int NODES_NPF = 5;   // node-record words per thread prefetched
 
@@ -1337,35 +1338,41 @@ __device__ __forceinline__ NodesTile nodes_tile(const NodesDesc& N, int xcd, int
 // and the words t + BLOCKT·u of the group's node records.
 template <int TW>
 __device__ __forceinline__ void nodes_stage_issue(const NodesDesc& N, const NodesTile& x, uint64_t* vt,
-                                                  uint64_t* vn) {
+                                                  uint64_t* vn, bool rows) {
   using C = NodesCfg<TW>;
   const int r0 = (int)threadIdx.x / C::SPAN, l = (int)threadIdx.x % C::SPAN;
   const int64_t w = (int64_t)x.g * GW + l;
   const bool inRow = w < N.stride;  // words past the last granule are not loaded
   const CT_G uint64_t* S = N.S + (int64_t)r0 * N.stride + w;
+  if (rows) {
 #pragma unroll
-  for (int u = 0; u < NODES_TPF; ++u)
-    if (r0 + C::RSTEP * u < N.rows) vt[u] = inRow ? S[(int64_t)(C::RSTEP * u) * N.stride] : 0ull;
+    for (int u = 0; u < NODES_TPF; ++u)
+      if (r0 + C::RSTEP * u < N.rows) vt[u] = inRow ? S[(int64_t)(C::RSTEP * u) * N.stride] : 0ull;
+  }
   const CT_G uint64_t* src = N.nodes + (int64_t)x.node0 * N.nodeWords + threadIdx.x;
 #pragma unroll
   for (int u = 0; u < NODES_NPF; ++u)
     if ((int)threadIdx.x + C::BLOCKT * u < x.nodeTotal) vn[u] = src[C::BLOCKT * u];
 }
 
-// Stores the prefetched words (and loads and stores any beyond them); the
-// caller synchronizes the workgroup afterwards.
+// Stores the prefetched words (and loads and stores any beyond them) and
+// resets the tile's node counter; the caller synchronizes the workgroup
+// afterwards.  The support rows are staged only for a new span.
 template <int TW>
 __device__ __forceinline__ void nodes_stage_commit(const NodesDesc& N, const NodesTile& x, const uint64_t* vt,
-                                                   const uint64_t* vn, uint64_t* lds) {
+                                                   const uint64_t* vn, uint64_t* lds, bool rows, int* next) {
   using C = NodesCfg<TW>;
   const int r0 = (int)threadIdx.x / C::SPAN, l = (int)threadIdx.x % C::SPAN;
   const int64_t w = (int64_t)x.g * GW + l;
   const bool inRow = w < N.stride;
+  if (rows) {
 #pragma unroll
-  for (int u = 0; u < NODES_TPF; ++u)
-    if (r0 + C::RSTEP * u < N.rows) lds[(r0 + C::RSTEP * u) * C::SPAN + l] = vt[u];
-  for (int r = r0 + C::RSTEP * NODES_TPF; r < N.rows; r += C::RSTEP)
-    lds[r * C::SPAN + l] = inRow ? N.S[(int64_t)r * N.stride + w] : 0ull;
+    for (int u = 0; u < NODES_TPF; ++u)
+      if (r0 + C::RSTEP * u < N.rows) lds[(r0 + C::RSTEP * u) * C::SPAN + l] = vt[u];
+    for (int r = r0 + C::RSTEP * NODES_TPF; r < N.rows; r += C::RSTEP)
+      lds[r * C::SPAN + l] = inRow ? N.S[(int64_t)r * N.stride + w] : 0ull;
+  }
+  if (threadIdx.x == 0) *next = 0;
   uint64_t* dst = lds + (size_t)(N.rows + 1) * C::SPAN;  // the zero row sits between
 #pragma unroll
   for (int u = 0; u < NODES_NPF; ++u) {
@@ -1384,7 +1391,8 @@ __device__ __forceinline__ u64x2 nodes_row(const char* tileBytes, uint32_t r, ui
 }
 
 template <int TW>
-__device__ __forceinline__ void nodes_eval_tile(const NodesDesc& N, const NodesTile& x, const uint64_t* lds) {
+__device__ __forceinline__ void nodes_eval_tile(const NodesDesc& N, const NodesTile& x, const uint64_t* lds,
+                                                int* next) {
   using C = NodesCfg<TW>;
   const int lane = lane_id();
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
@@ -1392,7 +1400,16 @@ __device__ __forceinline__ void nodes_eval_tile(const NodesDesc& N, const NodesT
   const uint32_t laneOff = (uint32_t)lane * 8u * TW;
   const char* tileBytes = (const char*)lds;
   const int64_t w = (int64_t)x.g * GW + TW * lane;
-  for (int p = wv; p < x.nG; p += C::WAVEST) {
+  // the waves take the group's nodes one at a time from the tile's counter:
+  // nodes differ in row count, so a fixed share per wave would leave waves
+  // idle at the tile's barrier.  Every lane adds one, so a wave's fetch moves
+  // the counter by 64 and the node is the value any lane got divided by 64:
+  // no branch on the lane precedes the wave-uniform exit test (a
+  // lane-0-only atomic followed by a shuffle let the compiler send the other
+  // lanes back to the test with a stale node id, so they never left the loop)
+  for (;;) {
+    const int p = __builtin_amdgcn_readfirstlane(atomicAdd(next, 1)) >> 6;
+    if (p >= x.nG) break;
     const NodeInfo* info = (const NodeInfo*)(recs + p * N.nodeWords);
     // the record is the same for every lane: scalar registers, uniform loops
     const int status = __builtin_amdgcn_readfirstlane(info->status);
@@ -1481,32 +1498,42 @@ __device__ __forceinline__ void nodes_eval_tile(const NodesDesc& N, const NodesT
 
 template <int TW>
 __global__ void __launch_bounds__(NodesCfg<TW>::BLOCKT, 4) nodes_update_kernel(KArgs a, NodesDesc N) {
+  // the tile (16-byte row reads need the array at LDS offset 0: no static
+  // LDS in this kernel), the group's node records, then the node counter
   extern __shared__ uint64_t lds[];
   using C = NodesCfg<TW>;
+  int* next = (int*)(lds + (size_t)(N.rows + 1) * C::SPAN + (size_t)N.groupSize * N.nodeWords);
   const int xcd = blockIdx.x % XCDS;
   const int perX = gridDim.x / XCDS;  // the grid is a multiple of 8
   const int spans = (N.nGran + TW - 1) / TW;
   const int tilesX = (spans - xcd + XCDS - 1) / XCDS * N.groups;
-  int t = blockIdx.x / XCDS;
-  if (t >= tilesX) return;
+  // the XCD's tiles, span by span with the groups of a span in a row, are
+  // cut into one contiguous range per block: a block stages a span's rows
+  // once and then only the next group's node records
+  const int k = blockIdx.x / XCDS;
+  const int hi = (int)((int64_t)(k + 1) * tilesX / perX);
+  int t = (int)((int64_t)k * tilesX / perX);
+  if (t >= hi) return;
   if (threadIdx.x < C::SPAN) lds[N.rows * C::SPAN + threadIdx.x] = 0ull;  // the zero row
   uint64_t vt[NODES_TPF], vn[NODES_NPF];
   NodesTile cur = nodes_tile<TW>(N, xcd, t);
-  nodes_stage_issue<TW>(N, cur, vt, vn);
-  nodes_stage_commit<TW>(N, cur, vt, vn, lds);
+  nodes_stage_issue<TW>(N, cur, vt, vn, true);
+  nodes_stage_commit<TW>(N, cur, vt, vn, lds, true, next);
   __syncthreads();
   for (;;) {
-    const int tn = t + perX;
-    const bool more = tn < tilesX;
+    const int tn = t + 1;
+    const bool more = tn < hi;
     NodesTile nxt;
+    bool rows = false;
     if (more) {
       nxt = nodes_tile<TW>(N, xcd, tn);
-      nodes_stage_issue<TW>(N, nxt, vt, vn);  // in flight during the evaluation
+      rows = nxt.g != cur.g;  // the same for every thread
+      nodes_stage_issue<TW>(N, nxt, vt, vn, rows);  // in flight during the evaluation
     }
-    nodes_eval_tile<TW>(N, cur, lds);
+    nodes_eval_tile<TW>(N, cur, lds, next);
     __syncthreads();  // every wave is done with this tile's LDS
     if (!more) break;
-    nodes_stage_commit<TW>(N, nxt, vt, vn, lds);
+    nodes_stage_commit<TW>(N, nxt, vt, vn, lds, rows, next);
     __syncthreads();
     t = tn;
     cur = nxt;
@@ -2106,10 +2133,10 @@ int nodes_node_words(int rows, int n) {
 }
 
 // Dynamic LDS of the update kernel for groups of `groupSize` nodes and tiles
-// of `tw` granules.
+// of `tw` granules: the tile with its zero row, the records, the node counter.
 size_t nodes_update_lds(int rows, int n, int groupSize, int tw) {
   return (size_t)(rows + 1) * GW * tw * sizeof(uint64_t) +
-         (size_t)groupSize * nodes_node_words(rows, n) * sizeof(uint64_t);
+         (size_t)groupSize * nodes_node_words(rows, n) * sizeof(uint64_t) + 16;
 }
 
 int nodes_update_block(int tw) { return tw == 2 ? NodesCfg<2>::BLOCKT : NodesCfg<1>::BLOCKT; }

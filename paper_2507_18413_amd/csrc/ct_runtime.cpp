@@ -955,7 +955,7 @@ static int create_impl(ct_table* T, const int32_t* tuples, int64_t t, int32_t n,
   HIPCHK(hipGetDevice(&dev));
   HIPCHK(hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
   // (the engine lists rows with 16-bit ids)
-  T->engEligible = T->D <= INLINE_WORDS && T->W > 0 && T->engLds <= (size_t)lds && T->kind == CT_KIND_POSITIVE &&
+  T->engEligible = T->D <= ENG_MAX_D && T->W > 0 && T->engLds <= (size_t)lds && T->kind == CT_KIND_POSITIVE &&
                    T->rows <= 65535;
   std::lock_guard<std::mutex> lk(g_engMu);
   g_tables.insert(T);

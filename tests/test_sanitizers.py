@@ -32,9 +32,9 @@ def test_runtime_host_paths_under_sanitizers(tmp_path):
         pytest.skip("no HIP runtime library to link against")
     csrc = os.path.join(ROOT, "paper_2507_18413_amd", "csrc")
     objs = []
-    for name in ("ct_kernels.hip", "ct_engine.hip", "ct_split.hip"):
-        obj = tmp_path / (name + ".o")
-        cmd = B.compile_cmd(os.path.join(csrc, name), str(obj))
+    for src in (s for s in B.SOURCES if s.endswith(".hip")):
+        obj = tmp_path / (os.path.basename(src) + ".o")
+        cmd = B.compile_cmd(src, str(obj))
         subprocess.run(cmd, check=True, capture_output=True)
         objs.append(str(obj))
     exe = tmp_path / "runtime_driver"
