@@ -294,6 +294,30 @@ typedef struct {
  */
 int ct_propagate_batch(const ct_job *jobs, int32_t n_jobs, void *stream, int32_t *status_dev);
 
+/*
+ * ct_propagate_batch_noalloc -- ct_propagate_batch for callers that cannot
+ * allocate memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc): the same jobs, statuses and results,
+ * but no device, pinned or host allocation.  The work-queue counters, the
+ * staged job descriptors and the search-node schedule's records live in a
+ * static device array of 16 MiB that each GPU holds until the process ends
+ * (set up on the device's first call), and the descriptors are built in
+ * static host arrays.  Limits: at most 8,192 jobs, at most 2 MiB of staged
+ * descriptors (about 88 bytes per job plus the root tasks of a batch of
+ * CT_JOB_ROOT jobs: one per 4 granules), and for a batch on the search-node
+ * schedule at most 14 MiB of node records and flags (per job about 8 x
+ * (4 + (rows + 3 x arity + 3) / 4) + granules bytes); a batch beyond them is
+ * refused with CT_E_INVALID before anything changes.  Every no-allocation
+ * call on one GPU shares that array and the host arrays: calls are
+ * serialized on the host, and calls whose batches overlap on the GPU (on
+ * different streams, or before an earlier one has completed on another
+ * stream) race and give undefined results; batches queued on one stream
+ * run in order and are safe.  Each call clears the queue counters first
+ * (a small kernel on `stream`).  Device-side errors are reported by
+ * ct_batch_status on the stream of the last no-allocation call.
+ */
+int ct_propagate_batch_noalloc(const ct_job *jobs, int32_t n_jobs, void *stream, int32_t *status_dev);
+
 /* ------------------------------------------------------------------------
  * Many tables sharing variables: propagation to a fixpoint
  * --------------------------------------------------------------------- */

@@ -17,7 +17,8 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libct.so")
 BUILD = os.path.join(ROOT, "_build")
 SOURCES = [os.path.join(CSRC, "ct_kernels.hip"), os.path.join(CSRC, "ct_engine.hip"),
-           os.path.join(CSRC, "ct_split.hip"), os.path.join(CSRC, "ct_runtime.cpp"),
+           os.path.join(CSRC, "ct_split.hip"), os.path.join(CSRC, "ct_noalloc.hip"),
+           os.path.join(CSRC, "ct_runtime.cpp"),
            os.path.join(CSRC, "ct_server.cpp"), os.path.join(CSRC, "ct_split.cpp")]
 ARCH = os.environ.get("CT_OFFLOAD_ARCH", "gfx950")
 HIPCC = "/opt/rocm/bin/hipcc"

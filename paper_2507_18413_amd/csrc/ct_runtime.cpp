@@ -37,6 +37,8 @@ int nodes_node_words(int rows, int n);
 size_t nodes_update_lds(int rows, int n, int groupSize, int tw);
 hipError_t launch_nodes(const KArgs& a, const NodesDesc& N, int n, hipStream_t stream);
 hipError_t launch_roots(const KArgs& a, const RootDesc& R, hipStream_t stream);
+hipError_t noalloc_scratch(char** ptr, size_t* bytes);
+hipError_t launch_noalloc_reset(int32_t* q, hipStream_t stream);
 hipError_t launch_build_supports(const int32_t* tuples, int64_t t, int n, const VarDesc* vars,
                                  const int32_t* lo, uint64_t* S, int64_t stride, int64_t W,
                                  hipStream_t stream);
@@ -46,15 +48,15 @@ hipError_t launch_init_slots(const TabDesc* T, SlotDesc* slots, int n, const int
 
 namespace {
 
-thread_local std::string g_err;
+// the calling thread's last error message, in a fixed buffer: reporting an
+// error allocates nothing
+thread_local char g_err[512];
 
 int fail(int code, const char* fmt, ...) {
-  char buf[512];
   va_list ap;
   va_start(ap, fmt);
-  vsnprintf(buf, sizeof(buf), fmt, ap);
+  vsnprintf(g_err, sizeof(g_err), fmt, ap);
   va_end(ap);
-  g_err = buf;
   return code;
 }
 
@@ -67,6 +69,9 @@ int fail(int code, const char* fmt, ...) {
   } while (0)
 
 constexpr int32_t kStatusPending = 0x7fff0001;
+
+// device-side errors of ct_propagate_batch_noalloc calls on `stream`
+int noalloc_status(hipStream_t stream);
 
 // Injected allocation failure (a test hook): the g_failAlloc-th allocation
 // from now fails.
@@ -739,7 +744,7 @@ int batch_build(const ct_job* jobs, int n_jobs, int32_t* status_dev, bool nodes,
 // ===========================================================================
 extern "C" {
 
-const char* ct_last_error(void) { return g_err.c_str(); }
+const char* ct_last_error(void) { return g_err; }
 
 int ct_debug_fail_alloc(int32_t nth) { return g_failAlloc.exchange(nth > 0 ? nth : 0); }
 
@@ -1005,9 +1010,10 @@ int ct_create_table(const int32_t* tuples, int64_t n_tuples, int32_t arity, cons
   }
   int rc = create_impl(T, tuples, n_tuples, arity, dom_lo, dom_size, init_dom);
   if (rc != CT_OK) {
-    std::string msg = g_err;
+    char msg[sizeof(g_err)];
+    memcpy(msg, g_err, sizeof(g_err));
     ct_destroy(T);
-    g_err = msg;
+    memcpy(g_err, msg, sizeof(g_err));
     return rc;
   }
   *out = T;
@@ -1256,6 +1262,8 @@ int ct_slot_stats(ct_table* T, int32_t slot, ct_stats* st) {
 
 int ct_batch_status(void* stream_v) {
   hipStream_t stream = (hipStream_t)stream_v;
+  int rc = noalloc_status(stream);
+  if (rc) return rc;
   QueueCtx* q = nullptr;
   {
     std::lock_guard<std::mutex> lk(g_qmu);
@@ -1327,6 +1335,177 @@ int ct_get_timing(ct_table* T, double* kernel_ms, int64_t* launches) {
   return CT_OK;
 }
 
+}  // extern "C"
+
+namespace {
+
+// What a validated batch needs, before any slot's host state changes.
+struct BatchPlan {
+  bool nodes = false, roots = false;
+  size_t nodesBytes = 0;   // search-node records and granule flags
+  size_t nTaskInts = 0;    // root tasks, two ints each
+  size_t offAt = 0;        // byte offset of the int section of the staging area
+  size_t stageBytes = 0;   // staging bytes for the largest prep list
+};
+
+BatchPlan batch_plan(const ct_job* jobs, int n_jobs) {
+  BatchPlan p;
+  p.nodes = use_nodes(jobs, n_jobs);
+  p.roots = !p.nodes && use_roots(jobs, n_jobs);
+  if (p.nodes) {
+    const ct_table* T = jobs[0].table;
+    p.nodesBytes = align256(sizeof(uint64_t) * (size_t)n_jobs * nodes_node_words(T->rows, T->n)) +
+                   align256((size_t)n_jobs * T->nGran);
+  }
+  if (p.roots) {
+    size_t nTasks = 0;
+    for (int j = 0; j < n_jobs; ++j) nTasks += (size_t)(jobs[j].table->nGran + WAVES - 1) / WAVES;
+    p.nTaskInts = 2 * nTasks;
+  }
+  p.offAt = align256(sizeof(DevJob) * (size_t)n_jobs);
+  // job descriptors, then updOff | filtOff | prep list | root tasks (even offset)
+  p.stageBytes = p.offAt + sizeof(int32_t) * (2 * (size_t)(n_jobs + 1) + (size_t)n_jobs + 2 + p.nTaskInts);
+  return p;
+}
+
+// Where a batch's scratch lives: device counters, staging and search-node
+// scratch, and the host arrays the descriptors are built in.  Capacities
+// must cover the batch's plan.
+struct BatchRes {
+  int32_t* queue = nullptr;     // device: [0] head, [1] exit count, [2] launches, [3] error
+  int32_t* hostErr = nullptr;   // pinned, nullable
+  char* dStage = nullptr;       // device staging
+  char* hStage = nullptr;       // host staging (the source of the one copy)
+  hipEvent_t staged = nullptr;  // nullable: recorded after the copy
+  void* dNodes = nullptr;
+  DevJob* hJobs = nullptr;      // n_jobs
+  int32_t* updOff = nullptr;    // n_jobs + 1
+  int32_t* filtOff = nullptr;   // n_jobs + 1
+  int32_t* prep = nullptr;      // n_jobs
+  int32_t* rootTasks = nullptr; // plan.nTaskInts
+  std::array<int32_t, 3>* rootKey = nullptr;  // n_jobs
+};
+
+// Builds the descriptors of a validated batch (applying its pops and pushes
+// to the slots' host mirrors), stages them in one copy and launches it.
+int batch_launch(const ct_job* jobs, int n_jobs, hipStream_t stream, int32_t* status_dev, const BatchPlan& p,
+                 const BatchRes& r) {
+  // root streams: WAVES granules per task, tables with the most support rows
+  // first (their tasks are the longest)
+  if (p.roots) {
+    for (int j = 0; j < n_jobs; ++j) {
+      const ct_table* T = jobs[j].table;
+      r.rootKey[j] = {-T->rows, -T->nGran, j};
+    }
+    std::sort(r.rootKey, r.rootKey + n_jobs);
+    size_t at = 0;
+    for (int k = 0; k < n_jobs; ++k)
+      for (int g = 0; g < -r.rootKey[k][1]; g += WAVES) {
+        r.rootTasks[at++] = r.rootKey[k][2];
+        r.rootTasks[at++] = g;
+      }
+  }
+  const int nPrep = batch_build(jobs, n_jobs, status_dev, p.nodes, r.hJobs, r.updOff, r.filtOff, r.prep);
+  // stage to the device (the root tasks start at an even offset: int pairs)
+  const size_t rootBase = (2 * (size_t)(n_jobs + 1) + (size_t)nPrep + 2) & ~(size_t)1;
+  const size_t nOff = p.roots ? rootBase + p.nTaskInts : 2 * (size_t)(n_jobs + 1) + (size_t)nPrep + 1;
+  const size_t stageBytes = p.offAt + sizeof(int32_t) * nOff;
+  int32_t* pOff = (int32_t*)(r.hStage + p.offAt);
+  memcpy(r.hStage, r.hJobs, sizeof(DevJob) * n_jobs);
+  memcpy(pOff, r.updOff, sizeof(int32_t) * (n_jobs + 1));
+  memcpy(pOff + (n_jobs + 1), r.filtOff, sizeof(int32_t) * (n_jobs + 1));
+  if (nPrep) memcpy(pOff + 2 * (n_jobs + 1), r.prep, sizeof(int32_t) * nPrep);
+  if (p.roots && p.nTaskInts) memcpy(pOff + rootBase, r.rootTasks, sizeof(int32_t) * p.nTaskInts);
+  HIPCHK(hipMemcpyAsync(r.dStage, r.hStage, stageBytes, hipMemcpyHostToDevice, stream));
+  if (r.staged) HIPCHK(hipEventRecord(r.staged, stream));
+  DevJob* dJobs = (DevJob*)r.dStage;
+  int32_t* dOff = (int32_t*)(r.dStage + p.offAt);
+  KArgs a{};
+  a.jobs = dJobs;
+  a.updOff = dOff;
+  a.filtOff = dOff + (n_jobs + 1);
+  a.prepList = dOff + 2 * (n_jobs + 1);
+  a.nJobs = n_jobs;
+  a.nPrep = nPrep;
+  a.nUpd = r.updOff[n_jobs];
+  a.nFilt = r.filtOff[n_jobs];
+  a.queue = r.queue;
+  a.hostErr = r.hostErr;
+  if (p.nodes) {
+    const ct_table* T = jobs[0].table;
+    NodesDesc N{};
+    N.nJobs = n_jobs;
+    N.listCap = nodes_list_cap(T->rows, T->n);
+    const NodesPlan plan = nodes_plan(T);
+    N.groupSize = plan.groupSize;
+    N.tw = plan.tw;
+    N.groups = (n_jobs + N.groupSize - 1) / N.groupSize;
+    N.jobs = dJobs;
+    char* base = (char*)r.dNodes;
+    N.nodeWords = nodes_node_words(T->rows, T->n);
+    N.nodes = (uint64_t*)base;
+    base += align256(sizeof(uint64_t) * (size_t)n_jobs * N.nodeWords);
+    N.nz = (uint8_t*)base;
+    N.rows = T->rows;
+    N.nGran = T->nGran;
+    N.stride = T->stride;
+    N.W = T->W;
+    N.S = T->hTab.S;
+    N.ct0 = T->hTab.ct0;
+    HIPCHK(launch_nodes(a, N, T->n, stream));
+    return CT_OK;
+  }
+  if (p.roots) {
+    RootDesc R{};
+    R.tasks = dOff + rootBase;
+    R.nTasks = (int32_t)(p.nTaskInts / 2);
+    HIPCHK(launch_roots(a, R, stream));
+    return CT_OK;
+  }
+  const int total = a.nPrep + a.nUpd + a.nFilt;
+  if (total > 0) HIPCHK(launch_propagate(a, std::min(total, propagate_max_grid()), stream));
+  return CT_OK;
+}
+
+// ct_propagate_batch_noalloc: fixed limits of the static scratch (device
+// array in ct_noalloc.hip) and of the host arrays the descriptors are built in
+constexpr int NA_MAX_JOBS = 8192;
+constexpr size_t NA_QUEUE_BYTES = 256;
+constexpr size_t NA_STAGE_BYTES = (size_t)2 << 20;
+constexpr size_t NA_MAX_TASK_INTS = (NA_STAGE_BYTES - (size_t)NA_MAX_JOBS * 128) / sizeof(int32_t);
+
+struct NoAllocHost {
+  std::mutex mu;  // the host arrays are shared by every caller
+  bool used = false;
+  hipStream_t lastStream = nullptr;  // the stream of the last call (ct_batch_status)
+  DevJob jobs[NA_MAX_JOBS];
+  int32_t updOff[NA_MAX_JOBS + 1], filtOff[NA_MAX_JOBS + 1], prep[NA_MAX_JOBS];
+  std::array<int32_t, 3> rootKey[NA_MAX_JOBS];
+  int32_t rootTasks[NA_MAX_TASK_INTS];
+  alignas(256) char stage[NA_STAGE_BYTES];
+};
+NoAllocHost g_na;
+
+int noalloc_status(hipStream_t stream) {
+  std::lock_guard<std::mutex> lk(g_na.mu);
+  if (!g_na.used || g_na.lastStream != stream) return CT_OK;
+  char* scratch = nullptr;
+  size_t bytes = 0;
+  HIPCHK(noalloc_scratch(&scratch, &bytes));
+  HIPCHK(hipStreamSynchronize(stream));
+  int32_t w[2] = {0, 0};  // the error words of the last call and of an earlier one
+  HIPCHK(hipMemcpy(w, scratch + 3 * sizeof(int32_t), sizeof(w), hipMemcpyDeviceToHost));
+  if (!w[0] && !w[1]) return CT_OK;
+  const int32_t zero[2] = {0, 0};
+  HIPCHK(hipMemcpy(scratch + 3 * sizeof(int32_t), zero, sizeof(zero), hipMemcpyHostToDevice));
+  return fail(CT_E_DEVICE, "device-side error %d in a ct_propagate_batch_noalloc call on this stream (wait "
+              "timeout or trail overflow); the slots of that batch are undefined", w[0] ? w[0] : w[1]);
+}
+
+}  // namespace
+
+extern "C" {
+
 int ct_propagate_batch(const ct_job* jobs, int32_t n_jobs, void* stream_v, int32_t* status_dev) {
   if (n_jobs < 0 || (n_jobs > 0 && (!jobs || !status_dev)))
     return fail(CT_E_INVALID, "bad batch arguments");
@@ -1351,56 +1530,23 @@ int ct_propagate_batch(const ct_job* jobs, int32_t n_jobs, void* stream_v, int32
       q = it->second;
     }
   }
-  const bool nodes = use_nodes(jobs, n_jobs);
-  const bool roots = !nodes && use_roots(jobs, n_jobs);
-  if (nodes) {
-    const ct_table* T = jobs[0].table;
-    const size_t need = align256(sizeof(uint64_t) * (size_t)n_jobs * nodes_node_words(T->rows, T->n)) +
-                        align256((size_t)n_jobs * T->nGran);
-    if (q->capNodes < need) {
-      HIPCHK(hipStreamSynchronize(stream));
-      if (q->dNodes) (void)hipFree(q->dNodes);
-      q->dNodes = nullptr;
-      q->capNodes = 0;
-      ALLOCCHK(hipMalloc(&q->dNodes, need));
-      q->capNodes = need;
-    }
+  const BatchPlan p = batch_plan(jobs, n_jobs);
+  // device and pinned scratch, grown before any slot's host state changes:
+  // a failed allocation leaves the slots as they were
+  if (p.nodes && q->capNodes < p.nodesBytes) {
+    HIPCHK(hipStreamSynchronize(stream));
+    if (q->dNodes) (void)hipFree(q->dNodes);
+    q->dNodes = nullptr;
+    q->capNodes = 0;
+    ALLOCCHK(hipMalloc(&q->dNodes, p.nodesBytes));
+    q->capNodes = p.nodesBytes;
   }
-  // root streams: WAVES granules per task, tables with the most support rows
-  // first (their tasks are the longest)
-  std::vector<int32_t>& rootTasks = q->rootTasks;
-  rootTasks.clear();
-  if (roots) {
-    // (rows, granules, job) read once per table, then sorted as plain data
-    std::vector<std::array<int32_t, 3>>& key = q->rootKey;
-    key.resize(n_jobs);
-    size_t nTasks = 0;
-    for (int j = 0; j < n_jobs; ++j) {
-      const ct_table* T = jobs[j].table;
-      key[j] = {-T->rows, -T->nGran, j};
-      nTasks += (size_t)(T->nGran + WAVES - 1) / WAVES;
-    }
-    std::sort(key.begin(), key.end());
-    rootTasks.resize(2 * nTasks);
-    size_t at = 0;
-    for (const auto& k : key)
-      for (int g = 0; g < -k[1]; g += WAVES) {
-        rootTasks[at++] = k[2];
-        rootTasks[at++] = g;
-      }
-  }
-  // staging capacity for the largest prep list (every job), allocated
-  // before any slot's host state changes: a failed allocation leaves the
-  // slots as they were
-  const size_t offAt = align256(sizeof(DevJob) * (size_t)n_jobs);
-  const size_t maxOff = 2 * (size_t)(n_jobs + 1) + (size_t)n_jobs + 2 + rootTasks.size();
-  if (q->capStage < offAt + sizeof(int32_t) * maxOff) {
-    const size_t stageBytes = offAt + sizeof(int32_t) * maxOff;
+  if (q->capStage < p.stageBytes) {
     HIPCHK(hipStreamSynchronize(stream));
     if (q->dStage) (void)hipFree(q->dStage);
     for (int k = 0; k < 2; ++k)
       if (q->pStage[k]) (void)hipHostFree(q->pStage[k]);
-    const size_t cap = std::max(stageBytes, 2 * q->capStage);
+    const size_t cap = std::max(p.stageBytes, 2 * q->capStage);
     q->dStage = nullptr;
     q->pStage[0] = q->pStage[1] = nullptr;
     q->capStage = 0;
@@ -1408,81 +1554,74 @@ int ct_propagate_batch(const ct_job* jobs, int32_t n_jobs, void* stream_v, int32
     for (int k = 0; k < 2; ++k) ALLOCCHK(hipHostMalloc((void**)&q->pStage[k], cap, hipHostMallocDefault));
     q->capStage = cap;
   }
-  // job descriptors (the slots' host mirrors take the jobs' pops and pushes)
   q->hJobs.resize(n_jobs);
-  std::vector<int32_t>& updOff = q->updOff;
-  std::vector<int32_t>& filtOff = q->filtOff;
-  std::vector<int32_t>& prep = q->prep;
-  updOff.assign(n_jobs + 1, 0);
-  filtOff.assign(n_jobs + 1, 0);
-  prep.resize(n_jobs);
-  const int nPrep = batch_build(jobs, n_jobs, status_dev, nodes, q->hJobs.data(), updOff.data(),
-                                filtOff.data(), prep.data());
-  prep.resize(nPrep);
-  // stage to the device (the root tasks start at an even offset: int pairs)
-  const size_t rootBase = (2 * (size_t)(n_jobs + 1) + prep.size() + 2) & ~(size_t)1;
-  const size_t nOff = roots ? rootBase + rootTasks.size() : 2 * (size_t)(n_jobs + 1) + prep.size() + 1;
-  const size_t stageBytes = offAt + sizeof(int32_t) * nOff;
+  q->updOff.assign(n_jobs + 1, 0);
+  q->filtOff.assign(n_jobs + 1, 0);
+  q->prep.resize(n_jobs);
+  q->rootTasks.resize(p.nTaskInts);
+  q->rootKey.resize(p.roots ? n_jobs : 0);
+  // two pinned staging buffers in turn: the copy that last read this one
+  // (two batches ago) has ended
   q->turn ^= 1;
-  // the copy that last read this pinned buffer (two batches ago) has ended
   HIPCHK(hipEventSynchronize(q->staged[q->turn]));
-  char* ps = q->pStage[q->turn];
-  int32_t* pOff = (int32_t*)(ps + offAt);
-  memcpy(ps, q->hJobs.data(), sizeof(DevJob) * n_jobs);
-  memcpy(pOff, updOff.data(), sizeof(int32_t) * (n_jobs + 1));
-  memcpy(pOff + (n_jobs + 1), filtOff.data(), sizeof(int32_t) * (n_jobs + 1));
-  if (!prep.empty()) memcpy(pOff + 2 * (n_jobs + 1), prep.data(), sizeof(int32_t) * prep.size());
-  if (!rootTasks.empty()) memcpy(pOff + rootBase, rootTasks.data(), sizeof(int32_t) * rootTasks.size());
-  HIPCHK(hipMemcpyAsync(q->dStage, ps, stageBytes, hipMemcpyHostToDevice, stream));
-  HIPCHK(hipEventRecord(q->staged[q->turn], stream));
-  DevJob* dJobs = (DevJob*)q->dStage;
-  int32_t* dOff = (int32_t*)(q->dStage + offAt);
-  KArgs a{};
-  a.jobs = dJobs;
-  a.updOff = dOff;
-  a.filtOff = dOff + (n_jobs + 1);
-  a.prepList = dOff + 2 * (n_jobs + 1);
-  a.nJobs = n_jobs;
-  a.nPrep = (int32_t)prep.size();
-  a.nUpd = updOff[n_jobs];
-  a.nFilt = filtOff[n_jobs];
-  a.queue = q->queue;
-  a.hostErr = q->hostErr;
-  if (nodes) {
-    const ct_table* T = jobs[0].table;
-    NodesDesc N{};
-    N.nJobs = n_jobs;
-    N.listCap = nodes_list_cap(T->rows, T->n);
-    const NodesPlan plan = nodes_plan(T);
-    N.groupSize = plan.groupSize;
-    N.tw = plan.tw;
-    N.groups = (n_jobs + N.groupSize - 1) / N.groupSize;
-    N.jobs = dJobs;
-    char* base = (char*)q->dNodes;
-    N.nodeWords = nodes_node_words(T->rows, T->n);
-    N.nodes = (uint64_t*)base;
-    base += align256(sizeof(uint64_t) * (size_t)n_jobs * N.nodeWords);
-    N.nz = (uint8_t*)base;
-    N.rows = T->rows;
-    N.nGran = T->nGran;
-    N.stride = T->stride;
-    N.W = T->W;
-    N.S = T->hTab.S;
-    N.ct0 = T->hTab.ct0;
-    HIPCHK(launch_nodes(a, N, T->n, stream));
-    return CT_OK;
-  }
-  if (roots) {
-    RootDesc R{};
-    R.tasks = dOff + rootBase;
-    R.nTasks = (int32_t)(rootTasks.size() / 2);
-    HIPCHK(launch_roots(a, R, stream));
-    return CT_OK;
-  }
-  const int total = a.nPrep + a.nUpd + a.nFilt;
-  if (total > 0) HIPCHK(launch_propagate(a, std::min(total, propagate_max_grid()), stream));
-  return CT_OK;
+  BatchRes r;
+  r.queue = q->queue;
+  r.hostErr = q->hostErr;
+  r.dStage = q->dStage;
+  r.hStage = q->pStage[q->turn];
+  r.staged = q->staged[q->turn];
+  r.dNodes = q->dNodes;
+  r.hJobs = q->hJobs.data();
+  r.updOff = q->updOff.data();
+  r.filtOff = q->filtOff.data();
+  r.prep = q->prep.data();
+  r.rootTasks = q->rootTasks.data();
+  r.rootKey = q->rootKey.data();
+  return batch_launch(jobs, n_jobs, stream, status_dev, p, r);
 }
+
+int ct_propagate_batch_noalloc(const ct_job* jobs, int32_t n_jobs, void* stream_v, int32_t* status_dev) {
+  if (n_jobs < 0 || (n_jobs > 0 && (!jobs || !status_dev)))
+    return fail(CT_E_INVALID, "bad batch arguments");
+  if (n_jobs == 0) return CT_OK;
+  if (n_jobs > NA_MAX_JOBS)
+    return fail(CT_E_INVALID, "ct_propagate_batch_noalloc: %d jobs, at most %d", n_jobs, NA_MAX_JOBS);
+  for (int j = 0; j < n_jobs; ++j)
+    if (!jobs[j].table) return fail(CT_E_INVALID, "job %d: table is NULL", j);
+  char* scratch = nullptr;
+  size_t scratchBytes = 0;
+  HIPCHK(noalloc_scratch(&scratch, &scratchBytes));
+  const size_t nodesCap = scratchBytes - NA_QUEUE_BYTES - NA_STAGE_BYTES;
+  const BatchPlan p = batch_plan(jobs, n_jobs);
+  if (p.stageBytes > NA_STAGE_BYTES || p.nTaskInts > NA_MAX_TASK_INTS)
+    return fail(CT_E_INVALID, "ct_propagate_batch_noalloc: the batch needs %zu staging bytes, at most %zu",
+                p.stageBytes, NA_STAGE_BYTES);
+  if (p.nodes && p.nodesBytes > nodesCap)
+    return fail(CT_E_INVALID, "ct_propagate_batch_noalloc: the search-node schedule needs %zu scratch bytes, "
+                "at most %zu", p.nodesBytes, nodesCap);
+  hipStream_t stream = (hipStream_t)stream_v;
+  std::lock_guard<std::mutex> lk(g_na.mu);
+  int rc = batch_validate_quiesce(jobs, n_jobs, stream);
+  if (rc) return rc;
+  BatchRes r;
+  r.queue = (int32_t*)scratch;
+  r.dStage = scratch + NA_QUEUE_BYTES;
+  r.hStage = g_na.stage;
+  r.dNodes = scratch + NA_QUEUE_BYTES + NA_STAGE_BYTES;
+  r.hJobs = g_na.jobs;
+  r.updOff = g_na.updOff;
+  r.filtOff = g_na.filtOff;
+  r.prep = g_na.prep;
+  r.rootTasks = g_na.rootTasks;
+  r.rootKey = g_na.rootKey;
+  // the work queue's counters start at zero (an earlier call's error word
+  // is kept for ct_batch_status)
+  HIPCHK(launch_noalloc_reset(r.queue, stream));
+  g_na.used = true;
+  g_na.lastStream = stream;
+  return batch_launch(jobs, n_jobs, stream, status_dev, p, r);
+}
+
 
 }  // extern "C"
 
@@ -1503,7 +1642,7 @@ int root_domains(ct_table* T, uint64_t* out) {
   return CT_OK;
 }
 
-void set_error(const char* msg) { g_err = msg; }
+void set_error(const char* msg) { snprintf(g_err, sizeof(g_err), "%s", msg); }
 
 // Read-only view of a table for the split propagators (ct_split.cpp): the
 // supports, the layout and the root state never change after ct_create.

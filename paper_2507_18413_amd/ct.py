@@ -122,6 +122,7 @@ def lib():
             "ct_slots_free": ([P, I32, I32], C.c_int),
             "ct_slot_stats": ([P, I32, C.POINTER(ct_stats)], C.c_int),
             "ct_propagate_batch": ([P, I32, P, P], C.c_int),
+            "ct_propagate_batch_noalloc": ([P, I32, P, P], C.c_int),
             "ct_batch_status": ([P], C.c_int),
             "ct_set_timing": ([P, I32], C.c_int),
             "ct_get_timing": ([P, C.POINTER(C.c_double), C.POINTER(I64)], C.c_int),
@@ -412,21 +413,23 @@ class Batch:
             a.ct_out = _ptr(j.get("ct_out"))
         self._refs = jobs  # keep tensors alive
 
-    def run(self, status_dev, stream=None):
+    def run(self, status_dev, stream=None, noalloc=False):
         s = None if stream is None else (stream if isinstance(stream, int) else stream.cuda_stream)
-        st = lib().ct_propagate_batch(C.cast(self.arr, C.c_void_p), self.n, s, _ptr(status_dev))
+        fn = lib().ct_propagate_batch_noalloc if noalloc else lib().ct_propagate_batch
+        st = fn(C.cast(self.arr, C.c_void_p), self.n, s, _ptr(status_dev))
         if st < 0:
             raise CTError(st, last_error())
         return st
 
 
-def propagate_batch(jobs, status_dev, stream=None):
+def propagate_batch(jobs, status_dev, stream=None, noalloc=False):
     """jobs: a Batch, or an iterable of dicts with keys table, slot, flags,
     n_pop, n_push, dom_in, dom_out, ct_out (torch tensors or device
     addresses).  status_dev: int32 device tensor (or address) with one entry
-    per job."""
+    per job.  noalloc: call ct_propagate_batch_noalloc (no allocation; the
+    library's static device scratch)."""
     b = jobs if isinstance(jobs, Batch) else Batch(jobs)
-    return b.run(status_dev, stream)
+    return b.run(status_dev, stream, noalloc)
 
 
 class Model:

@@ -40,6 +40,18 @@ int main() {
   EXPECT(ct_propagate_batch(nullptr, -1, nullptr, nullptr) == CT_E_INVALID);
   EXPECT(ct_propagate_batch(nullptr, 0, nullptr, nullptr) == CT_OK);
   EXPECT(ct_propagate_batch(nullptr, 3, nullptr, nullptr) == CT_E_INVALID);
+  EXPECT(ct_propagate_batch_noalloc(nullptr, -1, nullptr, nullptr) == CT_E_INVALID);
+  EXPECT(ct_propagate_batch_noalloc(nullptr, 0, nullptr, nullptr) == CT_OK);
+  EXPECT(ct_propagate_batch_noalloc(nullptr, 3, nullptr, nullptr) == CT_E_INVALID);
+  {
+    // more jobs than the static scratch takes, and a job without a table:
+    // refused before any device work
+    static ct_job jobs[8193];
+    int32_t status = 0;
+    EXPECT(ct_propagate_batch_noalloc(jobs, 8193, nullptr, &status) == CT_E_INVALID);
+    EXPECT(std::strstr(ct_last_error(), "8192") != nullptr);
+    EXPECT(ct_propagate_batch_noalloc(jobs, 1, nullptr, &status) == CT_E_INVALID);
+  }
   EXPECT(ct_layout(nullptr, nullptr, nullptr) == CT_E_INVALID);
   EXPECT(ct_push(nullptr) == CT_E_INVALID);
   EXPECT(ct_pop(nullptr) == CT_E_INVALID);
