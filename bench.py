@@ -381,8 +381,9 @@ def wide_leg(seed, n_calls, cpu, split=True, paper_shape=False):
            "props_per_s": round(props / el, 1),
            "latency_us": {"p50": round(float(np.percentile(lat_us, 50)), 2),
                           "p99": round(float(np.percentile(lat_us, 99)), 2)},
-           "kernel": {"name": "ctk::propagate_kernel", "launches": launches,
-                      "device_us_per_launch": round(kernel_ms * 1e3 / max(launches, 1), 3),
+           "kernel": {"name": "ctk::engine_kernel" if table.resident else "ctk::propagate_kernel",
+                      "calls_timed": launches,
+                      "device_us_per_call": round(kernel_ms * 1e3 / max(launches, 1), 3),
                       "algorithmic_bytes_per_call": round(byts / max(props, 1), 1),
                       "algorithmic_GBps": round(byts / (kernel_ms / 1e3) / 1e9, 2) if kernel_ms > 0 else None,
                       "profiled_hbm_bytes_per_launch": prof.get("hbm_bytes_per_launch") if prof else None,
@@ -826,11 +827,30 @@ def serve_leg(tables_spec, seed, rate, n_requests, n_searches, budget, sample_ch
     start = srv.now() + 0.05
     arrivals = arrivals + start
     nxt = 0
+    drained = set()   # tags of the drain requests (not measured)
+    last_note = time.perf_counter()
     while completed < n_requests:
         now = srv.now()
         while nxt < n_requests and arrivals[nxt] <= now:
             waiting.append(arrivals[nxt])
             nxt += 1
+        if time.perf_counter() - last_note > 5.0:
+            note(f"serving: {completed} of {n_requests} requests done")
+            last_note = time.perf_counter()
+        if nxt == n_requests and not waiting:
+            # every request is issued: a search keeps its slot between its
+            # requests, so under a memory budget the searches still waiting
+            # for a slot need the slot holders to finish; each idle search in
+            # the middle of its life gets one more request, its last (not
+            # measured)
+            for s in [s for s in idle if count[s] > 0]:
+                idle.remove(s)
+                n_pop = 1 if failed[s] and depth[s] > 0 else 0
+                srv.submit(sids[s], remove=None, n_pop=n_pop, push=0, finish=True, dom_out=None, tag=issued)
+                sreq[issued] = (s, True)
+                drained.add(issued)
+                count[s] = 0
+                issued += 1
         while waiting and idle:
             ta = waiting.popleft()
             j = int(rng.integers(0, len(idle)))
@@ -862,6 +882,13 @@ def serve_leg(tables_spec, seed, rate, n_requests, n_searches, budget, sample_ch
         res = srv.poll(wait_us=50 if not waiting else 0)
         for (tg, sid, status, ts, tl, td) in res:
             s, finish = sreq.pop(tg)
+            if tg in drained:
+                # a finishing request releases the slot whatever its status
+                drained.discard(tg)
+                depth[s] = 0
+                failed[s] = False
+                idle.append(s)
+                continue
             t_done.append(td - t_arr.pop(tg))
             t_launch.append(tl)
             if status == 1:
@@ -1167,8 +1194,9 @@ def main():
         stabs = [ct.Table(sp.tuples, sp.lo, sp.dsizes, max_depth=MAX_DEPTH_SERVE) for sp in serve_spec]
         out["serving"] = serve_leg(serve_spec, seed, args.serve_rate, args.serve_requests, 512,
                                    args.serve_budget, 0 if args.no_cpu_baseline else 8, tabs=stabs)
-        note("serving leg: saturation and a memory budget")
+        note("serving leg: saturation")
         sat = serve_leg(serve_spec, seed + 1, 0.0, args.serve_requests // 4, 512, 0, 0, tabs=stabs)
+        note("serving leg: a memory budget of a quarter of the peak slot bytes")
         peak = out["serving"]["peak_slot_bytes"]
         bud = serve_leg(serve_spec, seed + 2, 0.0, args.serve_requests // 8, 512, max(1, peak // 4),
                         0 if args.no_cpu_baseline else 4, tabs=stabs)

@@ -88,8 +88,11 @@ typedef struct ct_table ct_table;
  * the slot's currTable, granule index, stamps, residues and domains in LDS
  * and takes calls from a mailbox in pinned host memory, so a call costs no
  * launch and few round trips to HBM.  Used when that state fits one
- * workgroup's LDS (currTable of up to roughly a million tuples) and D <= 64;
- * AUTO does the same.  Results are identical to the launched schedules.  The
+ * workgroup's LDS (currTable of up to roughly a million tuples), the table
+ * has at most 65,535 support rows and D <= 512; AUTO does the same for
+ * D <= 64 (on wider tables the launched schedules spread filterDomains over
+ * many workgroups and are faster).  Results are identical to the launched
+ * schedules.  The
  * engine writes the state back and exits after 2 ms without a call (the
  * next call starts it again) and before any other operation on the table's
  * device state; one engine runs per process (see ct_quiesce). */

@@ -825,7 +825,7 @@ __device__ void e_filter(Eng& E, bool havePre, ResiduePre pre) {
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
           if (g[u][q] < 0) break;
-          ++cScan;
+          cScan += lane == 0 ? 1 : 0;  // a wave's work, counted once
           const unsigned long long bm =
               __ballot((E.ct[(int64_t)g[u][q] * GW + lane] & y[u][q]) != 0ull);
           if (bm) {

@@ -86,11 +86,12 @@ def test_counters_equal_oracle_counts_on_the_large_table_script(schedule):
     g.close()
 
 
-def test_counters_on_the_wide_scope_table():
+@pytest.mark.parametrize("schedule", [ct.SCHED_AUTO, ct.SCHED_RESIDENT])
+def test_counters_on_the_wide_scope_table(schedule):
     spec = W.wide_table(W.DEFAULT_SEED)
-    say("counters: wide-scope script (200 calls)")
+    say("counters: wide-scope script (200 calls), schedule", schedule)
     script, counts = oracle_script(spec, 200, 6)
-    g = ct.Table(spec.tuples, spec.lo, spec.dsizes)
+    g = ct.Table(spec.tuples, spec.lo, spec.dsizes, schedule=schedule)
     prev = g.stats()
     k = 0
     for kind, payload in script:

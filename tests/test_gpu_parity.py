@@ -191,7 +191,7 @@ def test_large_table_full(schedule):
     assert G.W == 3125
 
 
-@pytest.mark.parametrize("schedule", [ct.SCHED_AUTO, ct.SCHED_SPLIT, ct.SCHED_SOLO])
+@pytest.mark.parametrize("schedule", [ct.SCHED_AUTO, ct.SCHED_SPLIT, ct.SCHED_SOLO, ct.SCHED_RESIDENT])
 def test_wide_scope_vs_oracle(schedule):
     """A wide-scope table (100 variables, domains 64-160, 10,000 tuples:
     11,072 support rows of 157 words, 227 domain words; filterDomains
@@ -200,6 +200,9 @@ def test_wide_scope_vs_oracle(schedule):
     spec = W.wide_table()
     G, Ot = run_plain(spec, 200, W.pick_fraction_removal, 6, schedule=schedule)
     assert G.D == 227 and G.rows == 11072 and G.W == 157
+    # the resident engine takes the 227-word table when asked (its wide
+    # prologue and flat filter); AUTO leaves it to the launched schedules
+    assert G.resident == (schedule == ct.SCHED_RESIDENT)
 
 
 def test_wide_scope_nodes_batch_vs_oracle():
