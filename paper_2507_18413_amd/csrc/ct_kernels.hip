@@ -170,6 +170,16 @@ __device__ __forceinline__ void item_fence(const DevJob& J) {
   else __threadfence();
 }
 
+// Before a job's status is published or its last item is counted: the host
+// reads a synchronous call's outputs (pinned memory, JF_HOST_OUT) as soon as
+// the status changes, so they must be visible first; a batch's statuses and
+// outputs are read after the launch has ended, which makes them visible.  A
+// device-scope fence here costs an L2 write-back and invalidate per job (per
+// search node: thousands per batch), so batch jobs take none.
+__device__ __forceinline__ void status_fence(const DevJob& J) {
+  if (J.flags & JF_HOST_OUT) __threadfence_system();
+}
+
 // largest j with off[j] <= x  (off has n + 1 entries, off[0] = 0)
 __device__ int find_job(const CT_G int32_t* off, int n, int x) {
   int lo = 0, hi = n;  // off[lo] <= x < off[hi]
@@ -268,7 +278,7 @@ __device__ __forceinline__ void do_prep(const KArgs& a, const DevJob& J, Shared&
   apply_pops_pushes(J, sh);
   if (threadIdx.x == 0) {
     if (!(J.flags & JF_PROPAGATE)) {
-      item_fence(J);
+      status_fence(J);
       publish_status(J, ST_OK);
     } else {
       __threadfence();
@@ -728,7 +738,8 @@ __device__ __forceinline__ FilterPre filter_pre(const KArgs& a, const DevJob& J,
 }
 
 __device__ void filter_word(const KArgs& a, const DevJob& J, int q, int noop, int lim,
-                            const CT_G int32_t* idx, unsigned long long* cnt, const FilterPre& f) {
+                            const CT_G int32_t* idx, unsigned long long* cnt, const FilterPre& f,
+                            bool haveCtRes = false, uint64_t ctRes = 0ull) {
   const TabDesc* T = J.tab;
   SlotDesc* slot = J.slot;
   // the slot's arrays, read once (see update_granules)
@@ -747,7 +758,10 @@ __device__ void filter_word(const KArgs& a, const DevJob& J, int q, int noop, in
     const bool present = (din >> lane) & 1ull;
     const int rl = f.rl;
     const int rw0 = f.rw0;
-    const bool hit = present && (s->ct[rw0] & f.sres) != 0ull;
+    // the currTable word at the residue (loaded by the caller with those of
+    // other words, or here)
+    const uint64_t cr = haveCtRes ? ctRes : s->ct[rw0];
+    const bool hit = present && (cr & f.sres) != 0ull;
     unsigned long long miss = __ballot(present && !hit);
     cnt[0] += __popcll(__ballot(present));
     cnt[1] += __popcll(miss);
@@ -928,7 +942,7 @@ __device__ __forceinline__ void do_filter(const KArgs& a, const DevJob& J, int c
   // the last filter item of the job reports OK
   __syncthreads();
   if (threadIdx.x == 0) {
-    item_fence(J);
+    status_fence(J);  // no other item reads this one's outputs
     const int prev = atomicAdd(&s->filtCount, 1);
     if (prev == J.nFilt - 1) {
       s->filtCount = 0;
@@ -1115,7 +1129,7 @@ __device__ __forceinline__ void do_solo(const KArgs& a, const DevJob& J0, Shared
   }
   __syncthreads();
   if (threadIdx.x == 0) {
-    item_fence(J);
+    status_fence(J);
     publish_status(J, st);
   }
 }
@@ -1543,8 +1557,10 @@ __global__ void __launch_bounds__(NodesCfg<TW>::BLOCKT, 4) nodes_update_kernel(K
 // One wave per node, four nodes per workgroup, so the nodes of a batch are
 // resident at once: the stable partition of the root's granule list by the
 // non-zero flags (survivors first) and FAIL (Alg. 1), then filterDomains
-// (Alg. 3) over the node's domain words, the residue loads of FINISH_PRE words
-// in flight together.
+// (Alg. 3) over the node's domain words.  The residue and support-word loads
+// of FINISH_PRE domain words are issued before the partition and the node's
+// currTable words at those residues together after it, so a node's chain of
+// dependent memory rounds does not grow with its domain words.
 constexpr int FINISH_BLOCK = 256;
 constexpr int FINISH_NODES = FINISH_BLOCK / WAVE;
 constexpr int FINISH_PRE = 4;
@@ -1560,6 +1576,13 @@ __global__ void __launch_bounds__(FINISH_BLOCK) nodes_finish_kernel(KArgs a, Nod
   const int st0 = rec->status;
   const int nrows = rec->nrows;
   const bool run = st0 == ST_OK || st0 == ST_FAIL;
+  // the residues and support words of the first FINISH_PRE domain words:
+  // independent of the partition, so their loads run meanwhile (they clamp
+  // every address, so a rejected node's loads are harmless too)
+  const int D = T->D;
+  FilterPre pre[FINISH_PRE];
+#pragma unroll
+  for (int u = 0; u < FINISH_PRE; ++u) pre[u] = filter_pre(a, J, min(u, D - 1));
   int nSurv = 0;
   if (run) {
     const int limit0 = T->limit0, nGran = T->nGran;
@@ -1621,21 +1644,26 @@ __global__ void __launch_bounds__(FINISH_BLOCK) nodes_finish_kernel(KArgs a, Nod
   const int st = run ? (nSurv ? ST_OK : ST_FAIL) : st0;
   if (st == ST_OK) {
     unsigned long long cnt[3] = {0, 0, 0};
-    const int D = T->D;
+    const CT_G uint64_t* ct = s->ct;
     for (int q0 = 0; q0 < D; q0 += FINISH_PRE) {
-      FilterPre pre[FINISH_PRE];
+      if (q0 > 0) {
 #pragma unroll
-      for (int u = 0; u < FINISH_PRE; ++u) pre[u] = filter_pre(a, J, min(q0 + u, D - 1));
+        for (int u = 0; u < FINISH_PRE; ++u) pre[u] = filter_pre(a, J, min(q0 + u, D - 1));
+      }
+      // the node's currTable words at the residues, all in flight together
+      uint64_t cr[FINISH_PRE];
+#pragma unroll
+      for (int u = 0; u < FINISH_PRE; ++u) cr[u] = ct[pre[u].rw0];
 #pragma unroll
       for (int u = 0; u < FINISH_PRE; ++u)
-        if (q0 + u < D) filter_word(a, J, q0 + u, 0, nSurv, s->idx[0], cnt, pre[u]);
+        if (q0 + u < D) filter_word(a, J, q0 + u, 0, nSurv, s->idx[0], cnt, pre[u], true, cr[u]);
     }
     add_filter_stats(s, cnt);
   }
   if (lane == 0) {
     s->status = st;
     s->pad2 = 0;
-    item_fence(J);
+    status_fence(J);
     publish_status(J, st);
   }
 }
