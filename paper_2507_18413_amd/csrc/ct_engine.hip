@@ -979,8 +979,12 @@ __global__ void __launch_bounds__(EBLOCK) engine_kernel(EngDesc D) {
       if (threadIdx.x == 0) {
         const unsigned long long t0 = wall_clock64();
         for (;;) {
-          const int sq = __hip_atomic_load(&cmd->seq, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_SYSTEM);
+          // relaxed polls, one acquire fence once a new call is seen (an
+          // acquire load per poll would invalidate the caches that hold
+          // the table's supports between calls)
+          const int sq = __hip_atomic_load(&cmd->seq, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
           if (sq != st->lastSeq) {
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "");
             st->seq = sq;
             seen = 1;
             break;

@@ -46,9 +46,6 @@ __host__ __device__ __forceinline__ int tile_reps(int tile) { return tile == 8 ?
 __device__ __forceinline__ int lane_id() { return threadIdx.x & (WAVE - 1); }
 __device__ __forceinline__ int wave_id() { return threadIdx.x / WAVE; }
 
-__device__ __forceinline__ int ld_acquire(int32_t* p) {
-  return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-}
 __device__ __forceinline__ void st_release(int32_t* p, int32_t v) {
   __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
 }
@@ -83,11 +80,18 @@ __device__ void raise_error(const KArgs& a, int code) {
 }
 
 // Thread 0 spins until *flag == want; the result is broadcast to the block.
+// The spin reads the flag relaxed and takes one acquire fence once it holds:
+// an acquire load per poll would invalidate the L2 on every iteration (an
+// agent-scope acquire does on this chip), under the feet of the workgroup
+// being waited for.
 __device__ bool block_wait(const KArgs& a, int32_t* flag, int32_t want, Shared& sh) {
   if (threadIdx.x == 0) {
     int ok = 1;
     for (uint32_t it = 0;; ++it) {
-      if (ld_acquire(flag) == want) break;
+      if (ld_relaxed(flag) == want) {
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        break;
+      }
       if (ld_relaxed(&a.queue[3])) { ok = 0; break; }
       if (it > SPIN_LIMIT) { raise_error(a, 1); ok = 0; break; }
       __builtin_amdgcn_s_sleep(1);
