@@ -219,20 +219,38 @@ struct KArgs {
 // persistent workgroup keeps the slot's currTable, granule index, stamps,
 // residues and last domains in LDS and takes calls from a mailbox in
 // coherent pinned host memory; results go back the same way.
+//
+// Both directions use flagged slots: every 8-byte slot holds 32 bits of
+// payload (high half) and the call's sequence number (low half), written by
+// one aligned 64-bit store and read by one aligned 64-bit load, which are
+// single-copy atomic on the host CPU and on the GPU.  A reader takes a
+// message once every slot it needs carries the call's number, so no fence
+// orders the slots against each other and the reader needs no second round
+// trip after it has seen the flag.
 // ---------------------------------------------------------------------------
 constexpr int ENG_OP_PROPAGATE = 1, ENG_OP_STOP = 2;
 
-struct EngCmd {             // written by the host, seq last (release)
-  int32_t seq, op, nPop, nPush;
-  int32_t serialBase, depthAfter, wantCt, wantStats;
-  uint64_t dom[ENG_MAX_D];
+// command slots: op, nPop, nPush, serialBase, depthAfter, wantCt, wantStats,
+// one spare, then each domain word as two slots (low half first)
+enum { EC_OP, EC_NPOP, EC_NPUSH, EC_SERIAL, EC_DEPTH, EC_WANTCT, EC_WANTST, EC_SPARE, EC_DOM };
+constexpr int ENG_CMD_SLOTS = EC_DOM + 2 * ENG_MAX_D;
+
+// result slots: status, call ticks, the slot's 8 counters (two slots each,
+// written on calls that want them), then the domain words (written on OK)
+enum { ER_STATUS, ER_TICKS, ER_STATS, ER_DOM = ER_STATS + 16 };
+constexpr int ENG_RES_SLOTS = ER_DOM + 2 * ENG_MAX_D;
+
+__host__ __device__ inline uint64_t eng_slot(uint32_t payload, uint32_t seq) {
+  return ((uint64_t)payload << 32) | seq;
+}
+
+struct EngCmd {             // written by the host (every slot of a call)
+  uint64_t slot[ENG_CMD_SLOTS];
 };
 
-struct EngRes {             // written by the engine, seq last (release)
-  int32_t seq, status, alive, exitSeq;
-  uint64_t dom[ENG_MAX_D];
-  unsigned long long stats[8];  // the slot's counters after the call
-  unsigned long long callTicks;  // device clock (100 MHz) spent in the call
+struct EngRes {             // written by the engine
+  uint64_t slot[ENG_RES_SLOTS];
+  int32_t alive, exitSeq;        // written at exit (release)
   unsigned long long lifeTicks;  // written at exit: the launch's lifetime (device clock)
 };
 

@@ -25,22 +25,35 @@ namespace {
 constexpr int EBLOCK = 1024;
 constexpr int EWAVES = EBLOCK / WAVE;
 constexpr int E_NG = 4;          // granules per wave per update step
-constexpr int E_ROWS = 4;        // support rows loaded per batch
+constexpr int E_ROWS = 6;        // support rows loaded per batch (even: row ids are read in pairs)
 constexpr int E_LANE_SCAN = 16;  // words each missing lane checks after its residue
+constexpr int E_POP_U = 8;       // granules per wave per step of a pop
+constexpr int E_CMD_U = 8;       // 64-slot chunks of a long command loaded per round trip
 
 struct EngState {
   int32_t op, seq, lastSeq, nPop, nPush, serialBase, depthAfter, wantCt, wantStats, pad3;
   int32_t limit, failed, depth, serial, cur, status, noop, nseg;
   int32_t nrows, badStray, badSub, trailCount, nSurv, devErr, nMiss, nLeft;
   int64_t trailTop, lvTrailTop;
-  int32_t lvLimit, lvFailed, lvSerial, pad2;
+  int64_t trLo;  // trail entries [trLo, trailTop) have their headers in the LDS ring
+  int32_t lvLimit, lvFailed, lvSerial;
+  int32_t lvLo;  // levels [lvLo, depth) have their records and domains in the LDS ring
   int32_t waveSum[EWAVES];
   unsigned long long stat[8];
 };
 
 // Dynamic LDS regions, in this order, each 8-byte aligned.
 enum { R_CT, R_IDX0, R_IDX1, R_STAMP, R_NZ, R_FIRST, R_RES, R_LAST, R_DIN, R_ROWS, R_WVAR, R_VARS, R_VSIZE,
-       R_VDCNT, R_SEGOF, R_SEGEND, R_SEGINC, R_WCNT, R_MSLOT, R_LEFT, R_MFOUND, R_STATE, R_END };
+       R_VDCNT, R_SEGOF, R_SEGEND, R_SEGINC, R_WCNT, R_MSLOT, R_LEFT, R_MFOUND, R_STATE, R_TRH, R_LVR, R_LVD,
+       R_END };
+
+// LDS of one workgroup on gfx950; what the regions above leave of it holds
+// rings that mirror the newest trail headers and level records (a pop then
+// reads its headers, its level's record and its domains from LDS and only
+// the saved words from HBM).
+constexpr size_t E_LDS = 160 * 1024;
+constexpr int E_TRH_MAX = 4096;  // trail headers mirrored (a power of two)
+constexpr int E_LVR_MAX = 64;    // levels mirrored (a power of two)
 
 // Tables of at most this many domain words filter one word per wave (one
 // pass, no barrier); wider ones filter flat over the value slots.
@@ -50,12 +63,14 @@ constexpr int E_NARROW_D = 16;
 // wider domains are filtered in chunks of slots.
 constexpr int E_MISS_CAP = 16384;
 static_assert(ENG_MAX_D * 64 <= 65536, "domain slots fit 16 bits");
+static_assert(E_ROWS % 2 == 0, "a batch starts on a pair of row ids");
+static_assert(E_NG % 2 == 0, "the update takes granules in pairs");
 
 __host__ __device__ inline size_t eng_align(size_t x) { return (x + 7) & ~(size_t)7; }
 
 __host__ __device__ inline int eng_miss_cap(int D) { return D * 64 < E_MISS_CAP ? D * 64 : E_MISS_CAP; }
 
-__host__ __device__ inline void eng_layout(int n, int D, int nGran, int rows, size_t* off) {
+__host__ __device__ inline void eng_layout(int n, int D, int nGran, int rows, size_t* off, int* mirror = nullptr) {
   size_t sz[R_END];
   sz[R_CT] = (size_t)nGran * GW * 8;
   sz[R_IDX0] = sz[R_IDX1] = (size_t)nGran * 2;
@@ -74,7 +89,32 @@ __host__ __device__ inline void eng_layout(int n, int D, int nGran, int rows, si
   sz[R_MFOUND] = (size_t)cap;
   sz[R_STATE] = sizeof(EngState);
   size_t o = 0;
-  for (int r = 0; r < R_END; ++r) {
+  for (int r = 0; r < R_TRH; ++r) {
+    off[r] = o;
+    o += eng_align(sz[r]);
+  }
+  // the rings, each a power of two entries: levels first (up to half of
+  // what is left), then trail headers, at least a call's worth (nGran)
+  const size_t spare = o < E_LDS ? E_LDS - o : 0;
+  const size_t lvBytes = (size_t)D * 8 + sizeof(Level);
+  int lr = E_LVR_MAX;
+  while (lr >= 4 && (size_t)lr * lvBytes > spare / 2) lr >>= 1;
+  if (lr < 4) lr = 0;
+  const size_t left = spare - (size_t)lr * lvBytes;
+  int trh = 0;
+  for (int t = E_TRH_MAX; t >= nGran && t > 0; t >>= 1)
+    if ((size_t)t * sizeof(TrailHdr) <= left) {
+      trh = t;
+      break;
+    }
+  if (mirror) {
+    mirror[0] = trh;
+    mirror[1] = lr;
+  }
+  sz[R_TRH] = (size_t)trh * sizeof(TrailHdr);
+  sz[R_LVR] = (size_t)lr * sizeof(Level);
+  sz[R_LVD] = (size_t)lr * D * 8;
+  for (int r = R_TRH; r < R_END; ++r) {
     off[r] = o;
     o += eng_align(sz[r]);
   }
@@ -98,6 +138,14 @@ __device__ __forceinline__ int e_tid() {
   int t = threadIdx.x;
   asm volatile("" : "+v"(t));
   return t;
+}
+// Flagged mailbox slots: 64-bit loads and stores at system scope (the
+// pinned host buffers are read and written around the GPU's caches).
+__device__ __forceinline__ uint64_t ll_load(const uint64_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+__device__ __forceinline__ void ll_store(uint64_t* p, uint64_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 __device__ __forceinline__ int e_wave() { return __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE); }
 
@@ -143,6 +191,10 @@ struct Eng {
   uint16_t* left;    //   misses the walk after the residue did not resolve
   uint8_t* mFound;   //   a support was found by the granule scans
   int missCap;
+  TrailHdr* trRing;   // mirror of the newest trail headers (trh entries, 0: none)
+  Level* lvRing;      // mirror of the newest level records (lr entries, 0: none)
+  uint64_t* lvDomRing;  //   and their domains (lr x D words)
+  int trh, lr;
   EngState* st;
 };
 
@@ -175,33 +227,58 @@ __device__ void e_pops_pushes(Eng& E) {
     // gets the words of its first entry there (the oldest save holds the
     // words of that level)
     const int dT = st->depth - nPop;
+    const bool lvIn = E.lr > 0 && dT >= st->lvLo;  // level dT's record and domains are in LDS
+    const int lvSlot = dT & (E.lr - 1);
     if (tid == 0) {
-      const Level L = E.levels[dT];
+      const Level L = lvIn ? E.lvRing[lvSlot] : E.levels[dT];
       st->lvTrailTop = L.trailTop;
       st->lvLimit = L.limit;
       st->lvFailed = L.failed;
       st->lvSerial = L.serial;
     }
     for (int g = tid; g < E.nGran; g += EBLOCK) E.first[g] = 0x7fffffff;
-    for (int q = tid; q < E.D; q += EBLOCK) E.last[q] = E.levelDom[(int64_t)dT * E.D + q];
+    for (int q = tid; q < E.D; q += EBLOCK)
+      E.last[q] = lvIn ? E.lvDomRing[(int64_t)lvSlot * E.D + q] : E.levelDom[(int64_t)dT * E.D + q];
     lds_barrier();
-    const int64_t lo = st->lvTrailTop, top = st->trailTop;
-    for (int64_t e = lo + tid; e < top; e += EBLOCK) atomicMin(&E.first[E.trailHdr[e].gran], (int)(e - lo));
+    const int64_t lo = st->lvTrailTop, top = st->trailTop, trLo = E.trh > 0 ? st->trLo : top;
+    const int64_t trMask = E.trh - 1;
+    for (int64_t e = lo + tid; e < top; e += EBLOCK)
+      atomicMin(&E.first[(e >= trLo ? E.trRing[e & trMask] : E.trailHdr[e]).gran], (int)(e - lo));
     lds_barrier();
-    for (int64_t e = lo + e_wave(); e < top; e += EWAVES) {
-      const TrailHdr h = E.trailHdr[e];
-      if (E.first[h.gran] == (int)(e - lo)) {
-        E.ct[(int64_t)h.gran * GW + e_lane()] = E.trailWords[e * GW + e_lane()];
-        if (e_lane() == 0) E.stamp[h.gran] = h.oldStamp;
+    // each granule saved since the level takes back the words of its first
+    // entry: E_POP_U granules per wave per step, every load of a step issued
+    // before any is used (the engine holds currTable in LDS, so a table has
+    // a few hundred granules at most: one or a few steps)
+    for (int g0 = e_wave() * E_POP_U; g0 < E.nGran; g0 += EWAVES * E_POP_U) {
+      int f[E_POP_U];
+      TrailHdr h[E_POP_U];
+      uint64_t w[E_POP_U];
+#pragma unroll
+      for (int u = 0; u < E_POP_U; ++u) {
+        f[u] = g0 + u < E.nGran ? E.first[g0 + u] : 0x7fffffff;  // the same on every lane
+        if (f[u] != 0x7fffffff) {
+          const int64_t e = lo + f[u];
+          h[u] = e >= trLo ? E.trRing[e & trMask] : E.trailHdr[e];
+          w[u] = E.trailWords[e * GW + e_lane()];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < E_POP_U; ++u) {
+        if (f[u] != 0x7fffffff) {
+          E.ct[(int64_t)(g0 + u) * GW + e_lane()] = w[u];
+          if (e_lane() == 0) E.stamp[g0 + u] = h[u].oldStamp;
+        }
       }
     }
     lds_barrier();
     if (tid == 0) {
       st->trailTop = lo;
+      st->trLo = min(st->trLo, lo);
       st->limit = st->lvLimit;
       st->failed = st->lvFailed;
       st->serial = st->lvSerial;
       st->depth = dT;
+      st->lvLo = min(st->lvLo, dT);
     }
     lds_barrier();
   }
@@ -211,7 +288,12 @@ __device__ void e_pops_pushes(Eng& E) {
     const int lane = e_lane();
     for (int k = 0; k < nPush; ++k) {
       const int d = st->depth + k;
-      for (int q = lane; q < E.D; q += WAVE) E.levelDom[(int64_t)d * E.D + q] = E.last[q];
+      const int slotL = d & (E.lr - 1);
+      for (int q = lane; q < E.D; q += WAVE) {
+        const uint64_t w = E.last[q];
+        E.levelDom[(int64_t)d * E.D + q] = w;
+        if (E.lr > 0) E.lvDomRing[(int64_t)slotL * E.D + q] = w;
+      }
       if (lane == 0) {
         Level L;
         L.trailTop = st->trailTop;
@@ -220,11 +302,13 @@ __device__ void e_pops_pushes(Eng& E) {
         L.serial = k == 0 ? st->serial : st->serialBase + k - 1;
         L.pad = 0;
         E.levels[d] = L;
+        if (E.lr > 0) E.lvRing[slotL] = L;
       }
     }
     if (lane == 0) {
       st->depth += nPush;
       st->serial = st->serialBase + nPush - 1;
+      if (E.lr > 0) st->lvLo = max(st->lvLo, st->depth - E.lr);
     }
   }
 }
@@ -400,36 +484,48 @@ __device__ __forceinline__ void e_prologue(Eng& E) {
 
 // ---------------------------------------------------------------------------
 // updateTable (Alg. 2) over the active granules: currTable in LDS, support
-// rows from HBM; first changes of a level are saved on the trail
+// rows from HBM; first changes of a level are saved on the trail.  A wave
+// takes E_NG granules per step as pairs on its two half-waves: each lane
+// owns two adjacent words of its half's granule and loads them with one
+// 16-byte load (a half-wave reads a granule's 512 bytes; one CU moves about
+// twice the bytes per second with 16-byte loads than with 8-byte ones)
 // ---------------------------------------------------------------------------
+__device__ __forceinline__ void e_ld2(__amdgpu_buffer_rsrc_t rs, uint32_t voff, uint32_t soff, uint64_t* w) {
+  const auto v = __builtin_amdgcn_raw_buffer_load_b128(rs, (int)voff, (int)soff, 0);
+  w[0] = (uint64_t)v[0] | ((uint64_t)v[1] << 32);
+  w[1] = (uint64_t)v[2] | ((uint64_t)v[3] << 32);
+}
+
 __device__ void e_update(Eng& E) {
+  constexpr int NP = E_NG / 2;  // granule pairs per wave per step
   EngState* st = E.st;
   const int lane = e_lane();
+  const int half = lane >> 5, hl = lane & 31;  // this lane: words 2hl, 2hl+1 of its half's granule
+  const uint64_t halfMask = half ? 0xffffffff00000000ull : 0x00000000ffffffffull;
   const int limit = st->limit, nseg = st->nseg, nrows = st->nrows, serial = st->serial;
-  const uint32_t laneOff = (uint32_t)lane * 8u;
   const uint16_t* idxCur = st->cur ? E.idx1 : E.idx0;
   const bool trailOn = st->depthAfter > 0;  // levels exist only above depth 0
   const int64_t trailTop = st->trailTop;
   unsigned long long nAct = 0, nTrail = 0;
   for (int base = e_wave() * E_NG; base < limit; base += EWAVES * E_NG) {
-    int pos[E_NG], gs[E_NG], stv[E_NG];
-    bool act[E_NG];
-    uint64_t old[E_NG], m[E_NG], acc[E_NG];
+    int pos[NP], gs[NP];
+    bool act[NP];
+    uint32_t voff[NP];
+    uint64_t m[NP][2], acc[NP][2];
 #pragma unroll
-    for (int u = 0; u < E_NG; ++u) {
-      pos[u] = base + u;
-      act[u] = pos[u] < limit;
-      gs[u] = act[u] ? __builtin_amdgcn_readfirstlane((int)idxCur[pos[u]]) : 0;  // same on every lane
-      old[u] = E.ct[(int64_t)gs[u] * GW + lane];
-      stv[u] = E.stamp[gs[u]];
-      m[u] = ~0ull;
-      acc[u] = 0ull;
-      nAct += act[u] ? 1 : 0;
+    for (int s = 0; s < NP; ++s) {
+      pos[s] = base + 2 * s + half;
+      act[s] = pos[s] < limit;
+      gs[s] = act[s] ? (int)idxCur[pos[s]] : 0;
+      voff[s] = (uint32_t)gs[s] * (GW * 8) + (uint32_t)hl * 16;
+      m[s][0] = m[s][1] = ~0ull;
+      acc[s][0] = acc[s][1] = 0ull;
     }
+    nAct += (unsigned long long)min(E_NG, limit - base);
     int seg = 0;
     int segEnd = nseg > 0 ? E.segEnd[0] : 0;
     for (int k0 = 0; k0 < nrows; k0 += E_ROWS) {
-      uint64_t v[E_ROWS][E_NG];
+      uint64_t v[E_ROWS][NP][2];
       // the batch's row numbers, two per 32-bit LDS word, into scalar
       // registers (the same on every lane)
       uint32_t idw[(E_ROWS + 1) / 2];
@@ -441,9 +537,9 @@ __device__ void e_update(Eng& E) {
         const int k = k0 + j;
         const uint32_t id = (j & 1) ? (idw[j / 2] >> 16) : (idw[j / 2] & 0xFFFFu);
         const int r = k < nrows ? (int)id : 0;  // rows past the end are never used
+        const uint32_t soff = (uint32_t)((int64_t)r * E.stride * 8);
 #pragma unroll
-        for (int u = 0; u < E_NG; ++u)
-          v[j][u] = e_ld(E.Sbuf, laneOff, (uint32_t)(((int64_t)r * E.stride + (int64_t)gs[u] * GW) * 8));
+        for (int s = 0; s < NP; ++s) e_ld2(E.Sbuf, voff[s], soff, v[j][s]);
       }
 #pragma unroll
       for (int j = 0; j < E_ROWS; ++j) {
@@ -452,35 +548,54 @@ __device__ void e_update(Eng& E) {
         while (k >= segEnd) {
           const int inc = E.segInc[seg];
 #pragma unroll
-          for (int u = 0; u < E_NG; ++u) {
-            m[u] &= inc ? ~acc[u] : acc[u];
-            acc[u] = 0ull;
-          }
+          for (int s = 0; s < NP; ++s)
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+              m[s][h] &= inc ? ~acc[s][h] : acc[s][h];
+              acc[s][h] = 0ull;
+            }
           ++seg;
           segEnd = E.segEnd[seg];
         }
 #pragma unroll
-        for (int u = 0; u < E_NG; ++u) acc[u] |= v[j][u];
+        for (int s = 0; s < NP; ++s) {
+          acc[s][0] |= v[j][s][0];
+          acc[s][1] |= v[j][s][1];
+        }
       }
     }
     while (seg < nseg) {  // remaining segments (an empty reset segment gives 0)
       const int inc = E.segInc[seg];
 #pragma unroll
-      for (int u = 0; u < E_NG; ++u) {
-        m[u] &= inc ? ~acc[u] : acc[u];
-        acc[u] = 0ull;
-      }
+      for (int s = 0; s < NP; ++s)
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          m[s][h] &= inc ? ~acc[s][h] : acc[s][h];
+          acc[s][h] = 0ull;
+        }
       ++seg;
     }
-    uint64_t nw[E_NG];
-    bool need[E_NG], changed[E_NG];
+    // currTable and the stamps, read from LDS once the rows are in (fewer
+    // registers live while the row loads are in flight)
+    uint64_t old[NP][2], nw[NP][2];
+    int stv[NP];
+    bool changed[NP], need[NP];
+    int myOff[NP];  // this half's granule's place among the wave's trail entries
     int nNeed = 0;
 #pragma unroll
-    for (int u = 0; u < E_NG; ++u) {
-      nw[u] = old[u] & m[u];
-      changed[u] = act[u] && (__ballot(nw[u] != old[u]) != 0ull);
-      need[u] = changed[u] && trailOn && stv[u] != serial;
-      nNeed += need[u] ? 1 : 0;
+    for (int s = 0; s < NP; ++s) {
+      const int64_t wi = (int64_t)gs[s] * GW + 2 * hl;
+      old[s][0] = E.ct[wi];
+      old[s][1] = E.ct[wi + 1];
+      stv[s] = E.stamp[gs[s]];
+      nw[s][0] = old[s][0] & m[s][0];
+      nw[s][1] = old[s][1] & m[s][1];
+      const uint64_t bc = __ballot(act[s] && (nw[s][0] != old[s][0] || nw[s][1] != old[s][1]));
+      changed[s] = (bc & halfMask) != 0ull;
+      need[s] = changed[s] && trailOn && stv[s] != serial;
+      const uint64_t bn = __ballot(need[s] && hl == 0);  // bits 0 and 32
+      myOff[s] = nNeed + (half && (bn & 1ull) ? 1 : 0);
+      nNeed += __popcll(bn);
     }
     int tb = 0;
     if (nNeed) {
@@ -488,26 +603,31 @@ __device__ void e_update(Eng& E) {
       tb = __shfl(tb, 0);
     }
 #pragma unroll
-    for (int u = 0; u < E_NG; ++u) {
-      if (!act[u]) continue;
-      if (need[u]) {
-        const int64_t tp = trailTop + tb++;
+    for (int s = 0; s < NP; ++s) {
+      if (need[s]) {
+        const int64_t tp = trailTop + tb + myOff[s];
         if (tp < E.trailCap) {
-          E.trailWords[tp * GW + lane] = old[u];
-          if (lane == 0) {
+          E.trailWords[tp * GW + 2 * hl] = old[s][0];
+          E.trailWords[tp * GW + 2 * hl + 1] = old[s][1];
+          if (hl == 0) {
             TrailHdr h;
-            h.gran = gs[u];
-            h.oldStamp = stv[u];
+            h.gran = gs[s];
+            h.oldStamp = stv[s];
             E.trailHdr[tp] = h;
-            E.stamp[gs[u]] = serial;
+            if (E.trh > 0) E.trRing[tp & (E.trh - 1)] = h;
+            E.stamp[gs[s]] = serial;
           }
-        } else if (lane == 0) {
+        } else if (hl == 0) {
           st->devErr = 2;  // capacity is sized so that this cannot happen
         }
       }
-      if (changed[u]) E.ct[(int64_t)gs[u] * GW + lane] = nw[u];
-      const bool nzv = __ballot(nw[u] != 0ull) != 0ull;
-      if (lane == 0) E.nz[pos[u]] = nzv ? 1 : 0;
+      if (changed[s]) {
+        const int64_t wi = (int64_t)gs[s] * GW + 2 * hl;
+        E.ct[wi] = nw[s][0];
+        E.ct[wi + 1] = nw[s][1];
+      }
+      const uint64_t bz = __ballot((nw[s][0] | nw[s][1]) != 0ull);
+      if (act[s] && hl == 0) E.nz[pos[s]] = (bz & halfMask) != 0ull ? 1 : 0;
     }
     nTrail += nNeed;
   }
@@ -551,6 +671,7 @@ __device__ void e_partition(Eng& E) {
       st->limit = nSurv;
       st->trailTop += st->trailCount;
       st->trailCount = 0;
+      if (E.trh > 0) st->trLo = max(st->trLo, st->trailTop - E.trh);
       if (nSurv == 0) {
         st->status = ST_FAIL;
         st->failed = 1;
@@ -883,6 +1004,8 @@ __device__ void e_load(Eng& E, const EngDesc& D) {
     st->depth = s->depth;
     st->serial = s->serial;
     st->trailTop = s->trailTop;
+    st->trLo = s->trailTop;  // the rings start empty
+    st->lvLo = s->depth;
     st->cur = 0;
     st->trailCount = 0;
     st->devErr = 0;
@@ -941,7 +1064,13 @@ __global__ void __launch_bounds__(EBLOCK) engine_kernel(EngDesc D) {
   E.levelDom = D.slot->levelDom;
   E.trailCap = D.slot->trailCap;
   size_t off[R_END + 1];
-  eng_layout(E.n, E.D, E.nGran, E.rows, off);
+  int mirror[2];
+  eng_layout(E.n, E.D, E.nGran, E.rows, off, mirror);
+  E.trh = mirror[0];
+  E.lr = mirror[1];
+  E.trRing = (TrailHdr*)(lds + off[R_TRH]);
+  E.lvRing = (Level*)(lds + off[R_LVR]);
+  E.lvDomRing = (uint64_t*)(lds + off[R_LVD]);
   E.ct = (uint64_t*)(lds + off[R_CT]);
   E.idx0 = (uint16_t*)(lds + off[R_IDX0]);
   E.idx1 = (uint16_t*)(lds + off[R_IDX1]);
@@ -972,67 +1101,81 @@ __global__ void __launch_bounds__(EBLOCK) engine_kernel(EngDesc D) {
   const unsigned long long tLife = wall_clock64();
   e_load(E, D);
   for (;;) {
-    // wave 0 waits for a call (bounded: an idle engine exits), then reads
-    // the whole command, header and domains, in one wave-wide load
+    // wave 0 waits for a call (bounded: an idle engine exits): it polls the
+    // command's first 64 slots with two wave-wide loads in flight and takes
+    // the call once every slot carries the next sequence number; the rest
+    // of a long command follows the same way
     if (threadIdx.x < WAVE) {
-      int seen = 0;
-      if (threadIdx.x == 0) {
-        const unsigned long long t0 = wall_clock64();
+      const int l = e_tid();
+      const uint32_t want = (uint32_t)(st->lastSeq + 1);
+      const int nS = EC_DOM + 2 * E.D;
+      const uint64_t* slots = cmd->slot;
+      const unsigned long long t0 = wall_clock64();
+      bool seen = false;
+      uint64_t v = 0;
+      {
+        uint64_t a = l < nS ? ll_load(slots + l) : (uint64_t)want;
         for (;;) {
-          // relaxed polls, one acquire fence once a new call is seen (an
-          // acquire load per poll would invalidate the caches that hold
-          // the table's supports between calls)
-          const int sq = __hip_atomic_load(&cmd->seq, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-          if (sq != st->lastSeq) {
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "");
-            st->seq = sq;
-            seen = 1;
+          const uint64_t b = l < nS ? ll_load(slots + l) : (uint64_t)want;
+          if (__all((uint32_t)a == want)) {
+            v = a;
+            seen = true;
             break;
           }
           if ((long long)(wall_clock64() - t0) > D.idleTicks) break;
-          __builtin_amdgcn_s_sleep(8);
-        }
-      }
-      seen = __shfl(seen, 0);
-      constexpr int HDR = (int)(offsetof(EngCmd, dom) / 8);  // header words
-      constexpr int CHUNKS = (HDR + ENG_MAX_D) / WAVE;      // whole 64-word chunks of EngCmd
-      static_assert(CHUNKS * WAVE <= HDR + ENG_MAX_D, "chunks within the mailbox");
-      uint64_t w0 = 0;
-      if (seen) {
-        const uint64_t* words = (const uint64_t*)cmd;
-        const int l = e_tid();
-        // the header and the domains, 64 words per wave-wide load; every
-        // load of the needed chunks is issued before the first is used (all
-        // addresses lie inside the mailbox, used or not)
-        if (HDR + E.D <= 2 * WAVE) {
-          const uint64_t a = words[l], b = words[l + WAVE];
-          if (l >= HDR && l - HDR < E.D) E.din[l - HDR] = a;
-          if (l + WAVE - HDR < E.D) E.din[l + WAVE - HDR] = b;
-          w0 = a;
-        } else {
-          uint64_t w[CHUNKS + 1];
-#pragma unroll
-          for (int u = 0; u < CHUNKS; ++u) w[u] = words[l + u * WAVE];
-          // the last, partial chunk
-          w[CHUNKS] = CHUNKS * WAVE + l < HDR + ENG_MAX_D ? words[CHUNKS * WAVE + l] : 0ull;
-#pragma unroll
-          for (int u = 0; u <= CHUNKS; ++u) {
-            const int k = l + u * WAVE - HDR;
-            if (k >= 0 && k < E.D) E.din[k] = w[u];
+          a = l < nS ? ll_load(slots + l) : (uint64_t)want;
+          if (__all((uint32_t)b == want)) {
+            v = b;
+            seen = true;
+            break;
           }
-          w0 = w[0];
+          if ((long long)(wall_clock64() - t0) > D.idleTicks) break;
         }
       }
-      // header words: {seq, op}, {nPop, nPush}, {serialBase, depthAfter}, {wantCt, wantStats}
-      const uint64_t h0 = __shfl(w0, 0), h1 = __shfl(w0, 1), h2 = __shfl(w0, 2), h3 = __shfl(w0, 3);
-      if (threadIdx.x == 0) {
-        st->op = seen ? (int32_t)(h0 >> 32) : 0;
-        st->nPop = (int32_t)h1;
-        st->nPush = (int32_t)(h1 >> 32);
-        st->serialBase = (int32_t)h2;
-        st->depthAfter = (int32_t)(h2 >> 32);
-        st->wantCt = (int32_t)h3;
-        st->wantStats = (int32_t)(h3 >> 32);
+      uint32_t* din32 = (uint32_t*)E.din;
+      if (seen) {
+        if (l >= EC_DOM && l < nS) din32[l - EC_DOM] = (uint32_t)(v >> 32);
+        // the rest, E_CMD_U chunks of 64 slots per round trip
+        for (int c0 = WAVE; c0 < nS && seen; c0 += E_CMD_U * WAVE) {
+          for (;;) {
+            uint64_t w[E_CMD_U];
+            bool ok = true;
+#pragma unroll
+            for (int u = 0; u < E_CMD_U; ++u) {
+              const int i = c0 + u * WAVE + l;
+              w[u] = i < nS ? ll_load(slots + i) : (uint64_t)want;
+              ok = ok && (uint32_t)w[u] == want;
+            }
+            if (__all(ok)) {
+#pragma unroll
+              for (int u = 0; u < E_CMD_U; ++u) {
+                const int i = c0 + u * WAVE + l;
+                if (i < nS) din32[i - EC_DOM] = (uint32_t)(w[u] >> 32);
+              }
+              break;
+            }
+            if ((long long)(wall_clock64() - t0) > D.idleTicks) {
+              seen = false;
+              break;
+            }
+          }
+        }
+      }
+      if (l == 0) {
+        const uint32_t hv = (uint32_t)(v >> 32);
+        st->op = seen ? (int32_t)hv : 0;
+        st->seq = (int32_t)want;
+      }
+      const int32_t h1 = __shfl((int32_t)(v >> 32), EC_NPOP), h2 = __shfl((int32_t)(v >> 32), EC_NPUSH);
+      const int32_t h3 = __shfl((int32_t)(v >> 32), EC_SERIAL), h4 = __shfl((int32_t)(v >> 32), EC_DEPTH);
+      const int32_t h5 = __shfl((int32_t)(v >> 32), EC_WANTCT), h6 = __shfl((int32_t)(v >> 32), EC_WANTST);
+      if (l == 0) {
+        st->nPop = h1;
+        st->nPush = h2;
+        st->serialBase = h3;
+        st->depthAfter = h4;
+        st->wantCt = h5;
+        st->wantStats = h6;
       }
     }
     lds_barrier();
@@ -1088,24 +1231,33 @@ __global__ void __launch_bounds__(EBLOCK) engine_kernel(EngDesc D) {
       }
     }
     lds_barrier();
-    // wave 0 writes every output to host memory, so that its system-scope
-    // fence covers them all before the sequence number is published
+    // wave 0 writes the outputs to host memory: flagged result slots (the
+    // domains and counters first, the status last; the host waits for
+    // every slot it reads), and currTable before them behind a system-scope
+    // release, for the calls that want it
     if (threadIdx.x < WAVE) {
-      if (st->status == ST_OK) {
-        for (int q = threadIdx.x; q < E.D; q += WAVE) res->dom[q] = E.last[q];
-        if (st->wantCt)
-          for (int64_t w = threadIdx.x; w < E.W; w += WAVE) D.ctOut[w] = E.ct[w];
+      const int l = e_tid();
+      const uint32_t sq = (uint32_t)st->seq;
+      const int status = st->devErr ? ST_DEVICE : st->status;
+      uint64_t* rs = res->slot;
+      if (status == ST_OK && st->wantCt) {
+        for (int64_t w = l; w < E.W; w += WAVE) D.ctOut[w] = E.ct[w];
+        __threadfence_system();
       }
-      if (st->wantStats && threadIdx.x < 8) res->stats[threadIdx.x] = st->stat[threadIdx.x];
-      if (threadIdx.x == 0) {
-        res->status = st->devErr ? ST_DEVICE : st->status;
-        res->callTicks = wall_clock64() - tStart;
+      if (status == ST_OK) {
+        const uint32_t* out32 = (const uint32_t*)E.last;
+        for (int i = l; i < 2 * E.D; i += WAVE) ll_store(rs + ER_DOM + i, eng_slot(out32[i], sq));
+      }
+      if (st->wantStats && l < 16) {
+        const unsigned long long c = st->stat[l >> 1];
+        ll_store(rs + ER_STATS + l, eng_slot((uint32_t)(l & 1 ? c >> 32 : c), sq));
+      }
+      if (l == 0) {
+        const unsigned long long ticks = wall_clock64() - tStart;
+        ll_store(rs + ER_TICKS, eng_slot((uint32_t)min(ticks, 0xffffffffull), sq));
+        ll_store(rs + ER_STATUS, eng_slot((uint32_t)status, sq));
         st->lastSeq = st->seq;
       }
-      // system-scope release (it writes back what L2 holds of the outputs
-      // first): the outputs are visible before the sequence number
-      if (threadIdx.x == 0)
-        __hip_atomic_store(&res->seq, st->seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
     }
     __syncthreads();
   }

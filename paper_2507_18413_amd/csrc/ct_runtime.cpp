@@ -207,7 +207,9 @@ struct ct_table {
   EngCmd* pCmd = nullptr;   // coherent pinned mailbox
   EngRes* pRes = nullptr;
   int32_t engSeq = 0;
-  bool engStatsFresh = false;  // pRes->stats is from the last call
+  std::vector<uint64_t> engDom;        // the last call's output domains (D words)
+  unsigned long long engStats[8] = {};  // the slot's counters after the last call
+  bool engStatsFresh = false;  // engStats is from the last call
   unsigned long long engTicks = 0, engCalls = 0;  // timing of engine calls
   // lifetimes of the engine launches started while timing was on
   bool engTimed = false;
@@ -471,12 +473,33 @@ int engine_join(ct_table* T) {
   return CT_OK;
 }
 
+// Writes a call into the mailbox: every command slot, flagged with the
+// call's sequence number, the domain words first and the op last (the
+// engine takes the call once all of them carry the number).
+void engine_post(ct_table* T, int32_t seq, int32_t op, const DevJob* J, const uint64_t* dom_in, bool wantCt,
+                 bool wantStats) {
+  uint64_t* s = T->pCmd->slot;
+  const uint32_t sq = (uint32_t)seq;
+  for (int i = 0; i < 2 * T->D; ++i) {
+    const uint32_t half = dom_in ? (uint32_t)(dom_in[i >> 1] >> (i & 1 ? 32 : 0)) : 0u;
+    __atomic_store_n(&s[EC_DOM + i], eng_slot(half, sq), __ATOMIC_RELAXED);
+  }
+  const uint32_t hdr[EC_DOM] = {(uint32_t)op,
+                                J ? (uint32_t)J->nPop : 0u,
+                                J ? (uint32_t)J->nPush : 0u,
+                                J ? (uint32_t)J->serialBase : 0u,
+                                J ? (uint32_t)J->depthAfter : 0u,
+                                wantCt ? 1u : 0u,
+                                wantStats ? 1u : 0u,
+                                0u};
+  for (int i = EC_DOM - 1; i > 0; --i) __atomic_store_n(&s[i], eng_slot(hdr[i], sq), __ATOMIC_RELAXED);
+  __atomic_store_n(&s[EC_OP], eng_slot(hdr[EC_OP], sq), __ATOMIC_RELEASE);
+}
+
 int engine_stop(ct_table* T) {
   if (!T || !T->engOn) return CT_OK;
-  if (__atomic_load_n(&T->pRes->alive, __ATOMIC_ACQUIRE) != 0) {
-    T->pCmd->op = ENG_OP_STOP;
-    __atomic_store_n(&T->pCmd->seq, ++T->engSeq, __ATOMIC_RELEASE);
-  }
+  if (__atomic_load_n(&T->pRes->alive, __ATOMIC_ACQUIRE) != 0) engine_post(T, ++T->engSeq, ENG_OP_STOP, nullptr,
+                                                                           nullptr, false, false);
   return engine_join(T);
 }
 
@@ -507,7 +530,6 @@ int engine_start(ct_table* T) {
   D.idleTicks = engine_idle_ticks();
   D.startSeq = T->engSeq;
   T->engTimed = T->timing;
-  T->pRes->seq = T->engSeq;
   __atomic_store_n(&T->pRes->alive, 1, __ATOMIC_RELEASE);
   HIPCHK(launch_engine(D, T->engLds, T->engStream));
   T->engOn = true;
@@ -515,30 +537,40 @@ int engine_start(ct_table* T) {
   return CT_OK;
 }
 
+// Waits for a result slot of call `sq` (written at most a few microseconds
+// after its status) and returns its payload; false after two seconds.
+bool engine_slot(const ct_table* T, int i, uint32_t sq, uint32_t* payload) {
+  const uint64_t* p = &T->pRes->slot[i];
+  const auto t0 = std::chrono::steady_clock::now();
+  for (uint32_t spin = 0;; ++spin) {
+    const uint64_t v = __atomic_load_n(p, __ATOMIC_ACQUIRE);
+    if ((uint32_t)v == sq) {
+      *payload = (uint32_t)(v >> 32);
+      return true;
+    }
+    if ((spin & 1023) == 1023 && std::chrono::steady_clock::now() - t0 > std::chrono::seconds(2)) return false;
+  }
+}
+
 // One call through the engine; *status receives the call's status and the
-// outputs are in T->pRes->dom and (wantCt) T->pCt.
+// outputs are in T->engDom, T->engStats (wantStats) and T->pCt (wantCt).
 int engine_call(ct_table* T, const DevJob& J, const uint64_t* dom_in, bool wantCt, bool wantStats, int* status) {
   std::lock_guard<std::mutex> lk(g_engMu);
   int rc;
   if (T->engOn && __atomic_load_n(&T->pRes->alive, __ATOMIC_ACQUIRE) == 0 && (rc = engine_join(T))) return rc;
   if (!T->engOn && (rc = engine_start(T))) return rc;
-  EngCmd* c = T->pCmd;
-  c->op = ENG_OP_PROPAGATE;
-  c->nPop = J.nPop;
-  c->nPush = J.nPush;
-  c->serialBase = J.serialBase;
-  c->depthAfter = J.depthAfter;
-  c->wantCt = wantCt ? 1 : 0;
-  c->wantStats = wantStats ? 1 : 0;
-  memcpy(c->dom, dom_in, sizeof(uint64_t) * T->D);
   const int32_t seq = ++T->engSeq;
-  __atomic_store_n(&c->seq, seq, __ATOMIC_RELEASE);
+  const uint32_t sq = (uint32_t)seq;
+  engine_post(T, seq, ENG_OP_PROPAGATE, &J, dom_in, wantCt, wantStats);
+  const uint64_t* stSlot = &T->pRes->slot[ER_STATUS];
   const auto t0 = std::chrono::steady_clock::now();
+  uint64_t sv = 0;
   for (uint32_t spin = 0;; ++spin) {
-    if (__atomic_load_n(&T->pRes->seq, __ATOMIC_ACQUIRE) == seq) break;
+    if ((uint32_t)(sv = __atomic_load_n(stSlot, __ATOMIC_ACQUIRE)) == sq) break;
     if (__atomic_load_n(&T->pRes->alive, __ATOMIC_ACQUIRE) == 0) {
-      if (__atomic_load_n(&T->pRes->seq, __ATOMIC_ACQUIRE) == seq) break;
-      // the engine went idle before it saw this call: start a new one
+      if ((uint32_t)(sv = __atomic_load_n(stSlot, __ATOMIC_ACQUIRE)) == sq) break;
+      // the engine went idle before it saw this call: start a new one (the
+      // command stays in the mailbox)
       if ((rc = engine_join(T))) return rc;
       T->engSeq = seq - 1;
       if ((rc = engine_start(T))) return rc;
@@ -550,10 +582,32 @@ int engine_call(ct_table* T, const DevJob& J, const uint64_t* dom_in, bool wantC
       return fail(CT_E_DEVICE, "engine did not answer");
     }
   }
-  *status = T->pRes->status;
+  *status = (int32_t)(uint32_t)(sv >> 32);
+  bool whole = true;
+  if (*status == CT_OK) {
+    T->engDom.resize(T->D);
+    for (int i = 0; i < 2 * T->D && whole; i += 2) {
+      uint32_t lo = 0, hi = 0;
+      whole = engine_slot(T, ER_DOM + i, sq, &lo) && engine_slot(T, ER_DOM + i + 1, sq, &hi);
+      T->engDom[i >> 1] = ((uint64_t)hi << 32) | lo;
+    }
+  }
+  if (wantStats) {
+    for (int k = 0; k < 8 && whole; ++k) {
+      uint32_t lo = 0, hi = 0;
+      whole = engine_slot(T, ER_STATS + 2 * k, sq, &lo) && engine_slot(T, ER_STATS + 2 * k + 1, sq, &hi);
+      T->engStats[k] = ((unsigned long long)hi << 32) | lo;
+    }
+  }
+  uint32_t ticks = 0;
+  if (whole && T->timing) whole = engine_slot(T, ER_TICKS, sq, &ticks);
+  if (!whole) {
+    T->poisoned = true;
+    return fail(CT_E_DEVICE, "engine answer incomplete");
+  }
   T->engStatsFresh = wantStats;
   if (T->timing) {
-    T->engTicks += T->pRes->callTicks;
+    T->engTicks += ticks;
     T->engCalls += 1;
   }
   return CT_OK;
@@ -1184,7 +1238,7 @@ int ct_propagate_slot(ct_table* T, int32_t slot, const uint64_t* dom_in, uint64_
   const uint64_t* domRes = T->pDomOut;
   if (slot == 0 && engine_wanted(T)) {
     if ((rc = engine_call(T, J, dom_in, ct_out != nullptr, st != nullptr, &status))) return rc;
-    domRes = T->pRes->dom;
+    domRes = T->engDom.data();
   } else {
     if ((rc = run_single(T, J, dom_in))) return rc;
     status = *T->pStatus;
@@ -1248,7 +1302,7 @@ int ct_slot_stats(ct_table* T, int32_t slot, ct_stats* st) {
   SlotDesc s{};
   if (slot == 0 && T->engOn && T->engStatsFresh && __atomic_load_n(&T->pRes->alive, __ATOMIC_ACQUIRE) != 0) {
     // the engine holds the counters: its snapshot after the last call
-    for (int k = 0; k < 8; ++k) s.stats[k] = T->pRes->stats[k];
+    for (int k = 0; k < 8; ++k) s.stats[k] = T->engStats[k];
   } else {
     if ((rc = quiesce(T))) return rc;
     HIPCHK(hipStreamSynchronize(T->stream));
