@@ -361,15 +361,16 @@ def wide_leg(seed, n_calls, cpu, split=True, paper_shape=False):
     replay(table, script)
     s0 = table.stats()
     table.set_timing(True)
-    lat = []
     t0 = time.perf_counter()
-    props = replay(table, script, lat)
+    props = replay(table, script)
     el = time.perf_counter() - t0
     kernel_ms, launches = table.timing()
     table.set_timing(False)
     s1 = table.stats()
     d = {k: s1[k] - s0[k] for k in s1}
     byts = algorithmic_bytes(d, lay.D, props)
+    lat = []  # latencies from one more replay, outside the timed one
+    replay(table, script, lat)
     lat_us = np.array(lat) * 1e6
     from paper_2507_18413_amd import profiling
     prof = profiling.read_summary(os.path.join(ROOT, "profiles", "propagate_wide_scope.md"))
@@ -431,10 +432,12 @@ def tiny_leg(seed, reps, cpu):
     table = ct.Table(spec.tuples, spec.lo, spec.dsizes)
     for _ in range(3):
         replay(table, script)
-    lat = []
     t0 = time.perf_counter()
-    props = sum(replay(table, script, lat) for _ in range(reps))
+    props = sum(replay(table, script) for _ in range(reps))
     el = time.perf_counter() - t0
+    lat = []  # latencies from as many more replays, outside the timed ones
+    for _ in range(reps):
+        replay(table, script, lat)
     lat_us = np.array(lat) * 1e6
     out = {"workload": "arity 3, domains {0..7}, 200 distinct tuples, 100 calls removing 1-2 values, "
                        "push before every call, pop U{1..depth} every 10 calls",
@@ -1111,12 +1114,11 @@ def main():
     # served by launches whose whole lifetime is measured
     ct.quiesce()
     table.set_timing(True)
-    lat = []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     props = 0
     for _ in range(args.steps):
-        props += replay(table, script, lat)
+        props += replay(table, script)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     kernel_ms, launches = table.timing()
@@ -1126,6 +1128,11 @@ def main():
     d = {k: s1[k] - s0[k] for k in s1}
     elapsed = t1 - t0
     value = props / elapsed
+    # per-call latencies from as many more replays (outside the timed
+    # steps: the timers around every call would be charged to them)
+    lat = []
+    for _ in range(args.steps):
+        replay(table, script, lat)
     lat_us = np.array(lat) * 1e6
     bytes_total = algorithmic_bytes(d, lay.D, props)
     bytes_per_call = bytes_total / max(props, 1)

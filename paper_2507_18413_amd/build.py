@@ -58,6 +58,27 @@ def link_cmd(objs, out):
     return [HIPCC, "-shared", f"--offload-arch={ARCH}", "-o", out, *objs]
 
 
+PYFAST_SRC = os.path.join(CSRC, "ct_pyfast.c")
+
+
+def pyfast_path() -> str:
+    import sysconfig
+    return os.path.join(HERE, "_ctfast" + sysconfig.get_config_var("EXT_SUFFIX"))
+
+
+def build_pyfast(verbose: bool = False) -> str:
+    """The CPython binding of the per-call entry points (host C, gcc)."""
+    import sysconfig
+    out = pyfast_path()
+    tmp = out + ".tmp"
+    cmd = ["gcc", "-O2", "-shared", "-fPIC", "-Wall", "-I", sysconfig.get_paths()["include"], PYFAST_SRC, "-o", tmp]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, out)
+    return out
+
+
 def build(verbose: bool = False) -> str:
     os.makedirs(BUILD, exist_ok=True)
     objs = []
@@ -74,6 +95,7 @@ def build(verbose: bool = False) -> str:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
     os.replace(tmp, LIB)
+    build_pyfast(verbose)
     return LIB
 
 

@@ -27,6 +27,12 @@ KIND_POSITIVE, KIND_NEGATIVE, KIND_SHORT = 0, 1, 2
 STAR = -(1 << 31)  # a cell of a short table: every value of its column
 
 
+try:  # CPython binding of the per-call entry points (built with libct.so)
+    from . import _ctfast as _F
+except ImportError:  # the ctypes path below marshals the same calls
+    _F = None
+
+
 class CTError(RuntimeError):
     def __init__(self, code, msg):
         super().__init__(f"CT error {code}: {msg}")
@@ -158,6 +164,9 @@ def lib():
             f.argtypes = args
             f.restype = res
         _lib = L
+        if _F is not None:
+            addr = lambda f: C.cast(f, C.c_void_p).value  # noqa: E731
+            _F.bind(addr(L.ct_propagate_slot), addr(L.ct_push_slot), addr(L.ct_pop_slot))
         # a resident engine writes its state back and ends before exit
         import atexit
         atexit.register(L.ct_quiesce)
@@ -218,6 +227,7 @@ class Table:
         self._prop = L.ct_propagate_slot
         self._push = L.ct_push_slot
         self._pop = L.ct_pop_slot
+        self._hv = h.value  # the handle as an int, for the CPython binding
 
     @property
     def n_slots(self):
@@ -229,6 +239,7 @@ class Table:
         if getattr(self, "h", None) is not None and self.h.value is not None:
             lib().ct_destroy(self.h)
             self.h = None
+            self._hv = 0
 
     def __del__(self):
         try:
@@ -241,6 +252,16 @@ class Table:
             raise ValueError(f"dom_in has {len(dom_in)} words, the table {self.D}")
         D = self.D
         if not (want_ct or want_stats):
+            if _F is not None:
+                # uint64 arrays go straight to the library; None: marshal below
+                out = np.empty(D, np.uint64)
+                st = _F.propagate(self._hv, slot, dom_in, out, D)
+                if st is not None:
+                    if st == E_DEVICE:
+                        raise CTError(st, last_error())
+                    if st != OK:  # dom_out is written only on OK
+                        out[:] = dom_in
+                    return st, out
             # the common call: one copy in, one out
             self._din[:D] = dom_in
             st = self._prop(self.h, slot, self._din_p, self._dout_p, None, None)
@@ -264,9 +285,13 @@ class Table:
         return tuple(out)
 
     def push(self, slot=0):
+        if _F is not None:
+            return _F.push(self._hv, slot)
         return self._push(self.h, int(slot))
 
     def pop(self, slot=0):
+        if _F is not None:
+            return _F.pop(self._hv, slot)
         return self._pop(self.h, int(slot))
 
     def state(self, slot=0):

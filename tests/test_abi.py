@@ -57,6 +57,27 @@ def test_host_side_errors_without_device(libpath):
     assert L.ct_propagate_batch(None, -1, None, None) == ct.E_INVALID
 
 
+def test_cpython_binding_marshals_to_the_library(libpath):
+    """The CPython binding of the per-call entry points is built beside the
+    library, calls the library's own functions (a null handle gets the
+    library's CT_E_INVALID, no device call) and hands back what is not a
+    uint64 array to the ctypes marshalling (None)."""
+    import numpy as np
+    L = ct.lib()
+    F = ct._F
+    assert F is not None, "the CPython binding is not built"
+    din, dout = np.zeros(5, np.uint64), np.zeros(5, np.uint64)
+    assert F.propagate(0, 0, din, dout, 5) == ct.E_INVALID
+    assert "null" in ct.last_error()
+    assert F.push(0, 0) == ct.E_INVALID and F.pop(0, 0) == ct.E_INVALID
+    assert F.propagate(0, 0, np.zeros(5, np.float64), dout, 5) is None
+    assert F.propagate(0, 0, np.zeros(4, np.uint64), dout, 5) is None
+    assert F.propagate(0, 0, din, np.zeros(5, np.uint64)[::-1], 5) is None  # not contiguous
+    assert F.propagate(0, 0, [0] * 5, dout, 5) is None
+    assert F.propagate(0, 0, din, np.zeros(5, np.uint64).view(np.int64), 5) is None
+    assert L is ct.lib()
+
+
 def test_no_oracle_in_product_path():
     """The package neither imports nor links the oracle."""
     import re
