@@ -49,7 +49,7 @@ constexpr int MAX_D = 1024;        // domain words of a job cached in LDS (the r
 constexpr int NEG_MAX_ROWS = 8192; // negative tables: support rows (their second update pass lists
                                    // the removed values' rows in one LDS chunk)
 constexpr int MAX_GRAN = 8192;     // granules per table (partition done in LDS)
-constexpr int INLINE_WORDS = 64;   // dom_in words carried in kernel arguments
+constexpr int INLINE_WORDS = 256;  // dom_in words carried in kernel arguments
 constexpr int ENG_MAX_D = 512;     // domain words of a table served by the resident engine
 
 // status codes (same values as the public header)

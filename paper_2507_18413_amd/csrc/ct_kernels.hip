@@ -34,6 +34,8 @@ namespace ctk {
 constexpr int NGW = 2;                 // granules per wave per update step (split mode)
 constexpr int NGS = 4;                 // default granules per wave per step (solo mode)
 constexpr int LANE_SCAN = 16;          // words each missing lane checks before the wave scan
+constexpr int FULL_SCAN_GRAN = 4;      // at most this many active granules: misses test every active word
+constexpr int FULL_SCAN_VALS = 4;      //   for this many values per round trip
 constexpr int ROW_UNROLL = 8;          // support rows loaded per batch
 constexpr int ROWS_CHUNK = 8192;       // row-list entries staged in LDS at a time
 constexpr uint32_t SPIN_LIMIT = 1u << 22;
@@ -281,13 +283,10 @@ __device__ void apply_pops_pushes(const DevJob& J, Shared& sh) {
 __device__ __forceinline__ void do_prep(const KArgs& a, const DevJob& J, Shared& sh) {
   apply_pops_pushes(J, sh);
   if (threadIdx.x == 0) {
-    if (!(J.flags & JF_PROPAGATE)) {
-      status_fence(J);
-      publish_status(J, ST_OK);
-    } else {
-      __threadfence();
-      st_release(&J.slot->prepDone, 1);  // consumed (and reset) by the job's last update item
-    }
+    // (the barrier at the end of apply_pops_pushes orders the block's
+    // writes before thread 0's release)
+    if (!(J.flags & JF_PROPAGATE)) publish_status(J, ST_OK);
+    else st_release(&J.slot->prepDone, 1);  // consumed (and reset) by the job's last update item
   }
 }
 
@@ -770,88 +769,135 @@ __device__ void filter_word(const KArgs& a, const DevJob& J, int q, int noop, in
     cnt[0] += __popcll(__ballot(present));
     cnt[1] += __popcll(miss);
     uint64_t unsup = 0;
-    if (miss) {
-      // every missing lane first walks the words after its old residue
-      // (wrapping at the end of the table): a value's supports are spread
-      // over the whole table, so a nearby word usually still holds one
-      const bool mine = (miss >> lane) & 1ull;
-      const int r = rl;
-      const int64_t words = (int64_t)T->nGran * GW;
-      int64_t w = mine ? (int64_t)rw0 : 0;
-      bool found = false;
-#pragma unroll 1
-      for (int step = 0; step < LANE_SCAN; step += 4) {
-        uint64_t x[4];
-        int64_t ww[4];
+    if (miss && lim > 0 && lim <= FULL_SCAN_GRAN) {
+      // few active granules: each missing value tests every active word at
+      // once (FULL_SCAN_VALS values per round trip, one word per lane and
+      // granule); a value with no supported word among them has no support
+      int gg[FULL_SCAN_GRAN];
+      uint64_t c[FULL_SCAN_GRAN];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          ww[j] = w + 1 + step + j;
-          if (ww[j] >= words) ww[j] -= words;
-          const uint64_t y = s->ct[ww[j]] & T->S[(int64_t)r * stride + ww[j]];
-          x[j] = (mine && !found) ? y : 0ull;
-        }
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          if (!found && x[j]) {
-            found = true;
-            s->res[r] = (int)ww[j];
-          }
-        }
-        if (!__ballot(mine && !found)) break;
-      }
-      cnt[2] += __popcll(__ballot(mine));
-      miss = __ballot(mine && !found);
-    }
-    // the values still without a support scan the active granules in index
-    // order together: each step loads 4 currTable granules once and tests
-    // them against the rows of up to 3 values at a time; a value leaves the
-    // scan at its first supported word (its new residue)
-    uint64_t todo = miss;
-    for (int p = 0; p < lim && todo; p += 4) {
-      int gg[4];
-      uint64_t c[4];
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int gv = idx[min(p + j, lim - 1)];
-        gg[j] = (p + j < lim) ? gv : -1;
+      for (int j = 0; j < FULL_SCAN_GRAN; ++j) {
+        const int gv = idx[min(j, lim - 1)];
+        gg[j] = j < lim ? gv : -1;
         const uint64_t cv = s->ct[(int64_t)gv * GW + lane];
-        c[j] = gg[j] >= 0 ? cv : 0ull;
+        c[j] = j < lim ? cv : 0ull;
       }
-      cnt[2] += (unsigned long long)min(4, lim - p) * (unsigned long long)__popcll(todo);
-      uint64_t t = todo;
-      while (t) {
-        int ls[3];
+      uint64_t todo = miss;
+      while (todo) {
+        int ls[FULL_SCAN_VALS];
 #pragma unroll
-        for (int v = 0; v < 3; ++v) {
-          ls[v] = t ? __ffsll((unsigned long long)t) - 1 : -1;
-          t &= t - 1;
+        for (int v = 0; v < FULL_SCAN_VALS; ++v) {
+          ls[v] = todo ? __ffsll((unsigned long long)todo) - 1 : -1;
+          todo &= todo - 1;
         }
-        uint64_t x[3][4];
+        uint64_t x[FULL_SCAN_VALS][FULL_SCAN_GRAN];
 #pragma unroll
-        for (int v = 0; v < 3; ++v) {
+        for (int v = 0; v < FULL_SCAN_VALS; ++v) {
           const CT_G uint64_t* row = T->S + (int64_t)(rowBase + max(ls[v], 0)) * stride;
 #pragma unroll
-          for (int j = 0; j < 4; ++j) {
-            const uint64_t y = c[j] & row[(int64_t)max(gg[j], 0) * GW + lane];
-            x[v][j] = (ls[v] >= 0 && gg[j] >= 0) ? y : 0ull;
-          }
+          for (int j = 0; j < FULL_SCAN_GRAN; ++j) x[v][j] = row[(int64_t)max(gg[j], 0) * GW + lane] & c[j];
         }
 #pragma unroll
-        for (int v = 0; v < 3; ++v) {
+        for (int v = 0; v < FULL_SCAN_VALS; ++v) {
           if (ls[v] < 0) continue;
+          cnt[2] += (unsigned long long)lim;
+          bool found = false;
 #pragma unroll
-          for (int j = 0; j < 4; ++j) {
+          for (int j = 0; j < FULL_SCAN_GRAN; ++j) {
             const unsigned long long bm = __ballot(x[v][j] != 0ull);
             if (bm) {
               if (lane == 0) s->res[rowBase + ls[v]] = gg[j] * GW + (__ffsll(bm) - 1);
-              todo &= ~(1ull << ls[v]);
+              found = true;
               break;
+            }
+          }
+          if (!found) unsup |= 1ull << ls[v];
+        }
+      }
+    } else {
+      if (miss) {
+        // every missing lane first walks the words after its old residue
+        // (wrapping at the end of the table): a value's supports are spread
+        // over the whole table, so a nearby word usually still holds one
+        const bool mine = (miss >> lane) & 1ull;
+        const int r = rl;
+        const int64_t words = (int64_t)T->nGran * GW;
+        int64_t w = mine ? (int64_t)rw0 : 0;
+        bool found = false;
+  #pragma unroll 1
+        for (int step = 0; step < LANE_SCAN; step += 8) {
+          uint64_t x[8];
+          int64_t ww[8];
+  #pragma unroll
+          for (int j = 0; j < 8; ++j) {
+            ww[j] = w + 1 + step + j;
+            if (ww[j] >= words) ww[j] -= words;
+            const uint64_t y = s->ct[ww[j]] & T->S[(int64_t)r * stride + ww[j]];
+            x[j] = (mine && !found) ? y : 0ull;
+          }
+  #pragma unroll
+          for (int j = 0; j < 8; ++j) {
+            if (!found && x[j]) {
+              found = true;
+              s->res[r] = (int)ww[j];
+            }
+          }
+          if (!__ballot(mine && !found)) break;
+        }
+        cnt[2] += __popcll(__ballot(mine));
+        miss = __ballot(mine && !found);
+      }
+      // the values still without a support scan the active granules in index
+      // order together: each step loads 4 currTable granules once and tests
+      // them against the rows of up to 3 values at a time; a value leaves the
+      // scan at its first supported word (its new residue)
+      uint64_t todo = miss;
+      for (int p = 0; p < lim && todo; p += 4) {
+        int gg[4];
+        uint64_t c[4];
+  #pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int gv = idx[min(p + j, lim - 1)];
+          gg[j] = (p + j < lim) ? gv : -1;
+          const uint64_t cv = s->ct[(int64_t)gv * GW + lane];
+          c[j] = gg[j] >= 0 ? cv : 0ull;
+        }
+        cnt[2] += (unsigned long long)min(4, lim - p) * (unsigned long long)__popcll(todo);
+        uint64_t t = todo;
+        while (t) {
+          int ls[3];
+  #pragma unroll
+          for (int v = 0; v < 3; ++v) {
+            ls[v] = t ? __ffsll((unsigned long long)t) - 1 : -1;
+            t &= t - 1;
+          }
+          uint64_t x[3][4];
+  #pragma unroll
+          for (int v = 0; v < 3; ++v) {
+            const CT_G uint64_t* row = T->S + (int64_t)(rowBase + max(ls[v], 0)) * stride;
+  #pragma unroll
+            for (int j = 0; j < 4; ++j) {
+              const uint64_t y = c[j] & row[(int64_t)max(gg[j], 0) * GW + lane];
+              x[v][j] = (ls[v] >= 0 && gg[j] >= 0) ? y : 0ull;
+            }
+          }
+  #pragma unroll
+          for (int v = 0; v < 3; ++v) {
+            if (ls[v] < 0) continue;
+  #pragma unroll
+            for (int j = 0; j < 4; ++j) {
+              const unsigned long long bm = __ballot(x[v][j] != 0ull);
+              if (bm) {
+                if (lane == 0) s->res[rowBase + ls[v]] = gg[j] * GW + (__ffsll(bm) - 1);
+                todo &= ~(1ull << ls[v]);
+                break;
+              }
             }
           }
         }
       }
+      unsup = todo;
     }
-    unsup = todo;
     dout = din & ~unsup;
   }
   if (lane == 0) {
@@ -888,19 +934,22 @@ __device__ __forceinline__ void do_update(const KArgs& a, const DevJob& J, int c
   for (int r = 0; r < reps; ++r)
     update_granules<NGW>(a, J, sh, ((chunk * reps + r) * WAVES + wave_id()) * NGW, false, &s->jobTrail);
 
-  // count finished items; the last one finalizes the job
+  // count finished items; the last one finalizes the job (a job of one
+  // update item finalizes its own writes: no fence, no count)
   __syncthreads();
-  if (threadIdx.x == 0) {
-    item_fence(J);
-    const int prev = atomicAdd(&s->updCount, 1);
-    sh.isLast = prev == J.nUpd - 1;
-    if (sh.isLast) {
-      s->updCount = 0;
-      __threadfence();
+  if (J.nUpd > 1) {
+    if (threadIdx.x == 0) {
+      item_fence(J);
+      const int prev = atomicAdd(&s->updCount, 1);
+      sh.isLast = prev == J.nUpd - 1;
+      if (sh.isLast) {
+        s->updCount = 0;
+        __threadfence();
+      }
     }
+    __syncthreads();
+    if (!sh.isLast) return;
   }
-  __syncthreads();
-  if (!sh.isLast) return;
 
   if (J.nPop > 0) {
     if (threadIdx.x == 0) s->prepDone = 0;  // the prep item also did the pushes
@@ -925,7 +974,10 @@ __device__ __forceinline__ void do_update(const KArgs& a, const DevJob& J, int c
   if (threadIdx.x == 0) {
     s->jobTrail = 0;
     if (st != ST_OK) publish_status(J, st);
-    __threadfence();
+    // finalize_update ends with a barrier: the block's writes are ordered
+    // before this release; a currTable copy in host memory (written by the
+    // update items) is made visible before the filter publishes the status
+    if (J.nUpd == 1 && J.ct_out) status_fence(J);
     st_release(&s->updDone, 1);  // consumed (and reset) by the job's last filter item
   }
 }

@@ -613,13 +613,14 @@ int engine_call(ct_table* T, const DevJob& J, const uint64_t* dom_in, bool wantC
   return CT_OK;
 }
 
-// AUTO takes the engine for tables of at most 64 domain words: on wider
-// tables one workgroup's filterDomains (a gather of one word per checked
-// value) is slower than the launched schedules, which spread it over many
-// workgroups; RESIDENT takes it up to ENG_MAX_D words.
+// AUTO takes the engine for tables of at most ENG_AUTO_D domain words: on
+// wider tables one workgroup's filterDomains (a gather of one word per
+// checked value) is slower than the launched schedules, which spread it over
+// many workgroups; RESIDENT takes it up to ENG_MAX_D words.
+constexpr int ENG_AUTO_D = 64;
 bool engine_wanted(const ct_table* T) {
   return T->engEligible &&
-         ((T->cfg.schedule == CT_SCHED_AUTO && T->D <= INLINE_WORDS) || T->cfg.schedule == CT_SCHED_RESIDENT);
+         ((T->cfg.schedule == CT_SCHED_AUTO && T->D <= ENG_AUTO_D) || T->cfg.schedule == CT_SCHED_RESIDENT);
 }
 
 // Before any other use of a table's device state (from `same`, nullable):
