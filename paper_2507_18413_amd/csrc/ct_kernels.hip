@@ -70,6 +70,7 @@ struct Shared {
   uint32_t rows[ROWS_CHUNK];   // entries [k0, k0 + ROWS_CHUNK) of the job's row list
   uint8_t nz[MAX_GRAN];        // granule non-zero flags of a job run by one workgroup
   uint16_t gidx[MAX_GRAN];     // granule list of a job run by one workgroup
+  unsigned long long fcnt[3];  // a filter item's counters (residue checks, misses, scans)
 };
 
 // Record a device error: the host sees it through hostErr (pinned) and the
@@ -742,14 +743,16 @@ __device__ __forceinline__ FilterPre filter_pre(const KArgs& a, const DevJob& J,
 
 __device__ void filter_word(const KArgs& a, const DevJob& J, int q, int noop, int lim,
                             const CT_G int32_t* idx, unsigned long long* cnt, const FilterPre& f,
-                            bool haveCtRes = false, uint64_t ctRes = 0ull) {
+                            bool haveCtRes = false, uint64_t ctRes = 0ull, CT_G uint64_t* ctArr = nullptr,
+                            CT_G int32_t* resArr = nullptr) {
   const TabDesc* T = J.tab;
   SlotDesc* slot = J.slot;
-  // the slot's arrays, read once (see update_granules)
+  // the slot's arrays, read once (see update_granules), or as the caller
+  // read them
   struct {
     CT_G uint64_t* ct;
     CT_G int32_t* res;
-  } sv{slot->ct, slot->res}, *s = &sv;
+  } sv{ctArr ? ctArr : slot->ct, resArr ? resArr : slot->res}, *s = &sv;
   const int lane = lane_id();
   const VarDesc v = f.v;
   const uint64_t din = f.din;
@@ -987,16 +990,27 @@ __device__ __forceinline__ void do_filter(const KArgs& a, const DevJob& J, int c
   SlotDesc* s = J.slot;
   const int q = chunk * WAVES + wave_id();
   const int qc = min(q, J.tab->D - 1);
-  const FilterPre pre = filter_pre(a, J, qc);  // in flight while the update runs
+  // in flight while the update runs: what filterDomains needs of the input
+  // (filter_pre) and the slot's array addresses, which never change
+  CT_G uint64_t* const sct = s->ct;
+  CT_G int32_t* const sres = s->res;
+  CT_G int32_t* const idx0 = s->idx[0];
+  CT_G int32_t* const idx1 = s->idx[1];
+  const FilterPre pre = filter_pre(a, J, qc);
+  if (threadIdx.x < 3) sh.fcnt[threadIdx.x] = 0ull;
   if (!block_wait(a, &s->updDone, 1, sh)) return;
-  const int jobStatus = s->status;
+  // one round trip: the job's state after the update and, per value, the
+  // currTable word at its residue
+  const int jobStatus = s->status, noop = s->pad2, lim = s->limit, cur = s->cur;
+  const uint64_t cr = sct[pre.rw0];
   unsigned long long cnt[3] = {0, 0, 0};
-  if (q < J.tab->D && jobStatus == ST_OK) {
-    filter_word(a, J, q, s->pad2, s->limit, s->idx[s->cur], cnt, pre);
-  }
-  add_filter_stats(s, cnt);
+  if (q < J.tab->D && jobStatus == ST_OK) filter_word(a, J, q, noop, lim, cur ? idx1 : idx0, cnt, pre, true, cr, sct, sres);
+  // the item's counts, summed in LDS: one set of counter atomics per item
+  if (lane_id() == 0 && (cnt[0] | cnt[1] | cnt[2]))
+    for (int k = 0; k < 3; ++k) atomicAdd(&sh.fcnt[k], cnt[k]);
   // the last filter item of the job reports OK
   __syncthreads();
+  if (threadIdx.x == 0) add_filter_stats(s, sh.fcnt);
   if (threadIdx.x == 0) {
     status_fence(J);  // no other item reads this one's outputs
     const int prev = atomicAdd(&s->filtCount, 1);
