@@ -69,12 +69,20 @@ struct VarDesc {
   int32_t rowStart, dsize, domOff, domWords;
 };
 
+// A domain word's variable and its descriptor, in one record (one load
+// where the variable index and then its descriptor would take two).
+struct WordDesc {
+  VarDesc v;
+  int32_t var, pad0, pad1, pad2;
+};
+
 struct TabDesc {
   int32_t n, rows, D, nGran;
   int64_t W, stride;          // stride = nGran * 64 words per support row
   const CT_G uint64_t* S;          // rows x stride
   const CT_G VarDesc* vars;        // n
   const CT_G int32_t* wordVar;     // D: variable owning each domain word
+  const CT_G WordDesc* words;      // D: the same with the variable's descriptor
   // root state, read-only after creation
   const CT_G uint64_t* ct0;
   const CT_G int32_t* idx0;

@@ -55,6 +55,18 @@ __device__ __forceinline__ int ld_relaxed(int32_t* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// The slot's array addresses (they never change), loaded together: an item
+// that reads them early has them when its first loads from the arrays go.
+struct SlotPtrs {
+  CT_G uint64_t* ct;
+  CT_G int32_t* idx[2];
+  CT_G int32_t* stamp;
+  CT_G int32_t* nzFlag;
+  CT_G uint64_t* trailWords;
+  CT_G TrailHdr* trailHdr;
+  int64_t trailCap;
+};
+
 struct Shared {
   int32_t item, ok, isLast, status, noop, nseg, nrows, limit, serial, depth, bad_stray, bad_sub;
   int64_t trailTop;
@@ -71,7 +83,22 @@ struct Shared {
   uint8_t nz[MAX_GRAN];        // granule non-zero flags of a job run by one workgroup
   uint16_t gidx[MAX_GRAN];     // granule list of a job run by one workgroup
   unsigned long long fcnt[3];  // a filter item's counters (residue checks, misses, scans)
+  int32_t cur;                 // the slot's index buffer in use at the job's start (prologue)
+  SlotPtrs sp;                 // the slot's array addresses (prologue)
 };
+
+__device__ __forceinline__ SlotPtrs slot_ptrs(const SlotDesc* s) {
+  SlotPtrs p;
+  p.ct = s->ct;
+  p.idx[0] = s->idx[0];
+  p.idx[1] = s->idx[1];
+  p.stamp = s->stamp;
+  p.nzFlag = s->nzFlag;
+  p.trailWords = s->trailWords;
+  p.trailHdr = s->trailHdr;
+  p.trailCap = s->trailCap;
+  return p;
+}
 
 // Record a device error: the host sees it through hostErr (pinned) and the
 // other workgroups of the launch stop waiting.
@@ -292,13 +319,15 @@ __device__ __forceinline__ void do_prep(const KArgs& a, const DevJob& J, Shared&
 }
 
 // Inclusive prefix sum over the 64 lanes.
+// DPP moves (VALU, no LDS round trips): shifts within rows of 16 lanes,
+// then the row broadcasts of lanes 15 and 31.
 __device__ __forceinline__ int wave_scan_incl(int v) {
-  const int lane = lane_id();
-#pragma unroll
-  for (int d = 1; d < WAVE; d <<= 1) {
-    const int u = __shfl_up(v, d);
-    if (lane >= d) v += u;
-  }
+  v += __builtin_amdgcn_update_dpp(0, v, 0x111, 0xf, 0xf, false);  // row_shr:1
+  v += __builtin_amdgcn_update_dpp(0, v, 0x112, 0xf, 0xf, false);  // row_shr:2
+  v += __builtin_amdgcn_update_dpp(0, v, 0x114, 0xf, 0xf, false);  // row_shr:4
+  v += __builtin_amdgcn_update_dpp(0, v, 0x118, 0xf, 0xf, false);  // row_shr:8
+  v += __builtin_amdgcn_update_dpp(0, v, 0x142, 0xa, 0xf, false);  // row_bcast:15
+  v += __builtin_amdgcn_update_dpp(0, v, 0x143, 0xc, 0xf, false);  // row_bcast:31
   return v;
 }
 
@@ -329,6 +358,8 @@ __device__ void prologue(const KArgs& a, const DevJob& J, Shared& sh, bool pushH
       sh.status = s->failed ? ST_STATE : ST_OK;
     }
     sh.trailTop = s->trailTop;
+    sh.cur = s->cur;
+    sh.sp = slot_ptrs(s);
     sh.serial = J.nPush > 0 ? J.serialBase + J.nPush - 1 : s->serial;
     if (pushHere) {
       // this job's pushes record the state before it (levels of push_levels)
@@ -355,8 +386,9 @@ __device__ void prologue(const KArgs& a, const DevJob& J, Shared& sh, bool pushH
   __syncthreads();
   for (int q = threadIdx.x; q < D; q += BLOCK) {
     const uint64_t din = job_din(a, J, q);
-    const int i = T->wordVar[q];
-    const VarDesc v = T->vars[i];
+    const WordDesc wd = T->words[q];
+    const int i = wd.var;
+    const VarDesc v = wd.v;
     const int used = v.dsize - 64 * (q - v.domOff);
     if (used < 64 && (din >> used) != 0) sh.bad_stray = 1;
     uint64_t dl = 0;
@@ -429,10 +461,10 @@ __device__ void stage_rows(const DevJob& J, Shared& sh, int k0) {
   const CT_G uint64_t* last = (J.flags & JF_FROM_ROOT) ? T->dom0 : J.slot->lastDom;
   const int k1 = k0 + ROWS_CHUNK;
   for (int q = threadIdx.x; q < T->D; q += BLOCK) {
-    const int i = T->wordVar[q];
-    const int sg = sh.segOf[i];
+    const WordDesc wd = T->words[q];
+    const int sg = sh.segOf[wd.var];
     if (sg < 0) continue;
-    const VarDesc v = T->vars[i];
+    const VarDesc v = wd.v;
     const int inc = sh.segInc[sg];
     int off = sg == 0 ? 0 : sh.segEnd[sg - 1];
     for (int k = v.domOff; k < q && off < k1; ++k) {
@@ -458,7 +490,7 @@ __device__ void stage_rows(const DevJob& J, Shared& sh, int k0) {
 // ---------------------------------------------------------------------------
 template <int NG>
 __device__ void update_granules(const KArgs& a, const DevJob& J, Shared& sh, int p0, bool lds,
-                                int* trailCounter) {
+                                int* trailCounter, const SlotPtrs* sp = nullptr) {
   const TabDesc* T = J.tab;
   SlotDesc* s = J.slot;
   const bool fromRoot = J.flags & JF_FROM_ROOT;
@@ -475,8 +507,11 @@ __device__ void update_granules(const KArgs& a, const DevJob& J, Shared& sh, int
   const int serial = sh.serial;
   const int lane = lane_id();
   const bool scratch = J.flags & JF_SCRATCH;
-  const CT_G uint64_t* srcCt = fromRoot ? T->ct0 : s->ct;
-  const CT_G int32_t* srcIdx = fromRoot ? T->idx0 : s->idx[s->cur];
+  // the slot's arrays as the prologue read them (sp, in LDS), or from the
+  // descriptor
+  const CT_G uint64_t* srcCt = fromRoot ? T->ct0 : sp ? sp->ct : s->ct;
+  const CT_G int32_t* srcIdx = fromRoot ? T->idx0 : sp ? sp->idx[sh.cur] : s->idx[s->cur];
+  const CT_G int32_t* stampArr = sp ? sp->stamp : s->stamp;
   const int64_t trailTop = sh.trailTop;
 
   // Loads below are unconditional, from clamped (always valid) addresses, and
@@ -495,7 +530,7 @@ __device__ void update_granules(const KArgs& a, const DevJob& J, Shared& sh, int
     act[u] = pos[u] < limit && status == ST_OK;
     gs[u] = act[u] ? g[u] : 0;
     const uint64_t o = scratch ? all_tuples_word(T, (int64_t)gs[u] * GW + lane) : srcCt[(int64_t)gs[u] * GW + lane];
-    const int sv = s->stamp[gs[u]];
+    const int sv = stampArr[gs[u]];
     old[u] = act[u] ? o : 0ull;
     stv[u] = (act[u] && trailOn && !noop) ? sv : serial;
     m[u] = ~0ull;
@@ -571,12 +606,13 @@ __device__ void update_granules(const KArgs& a, const DevJob& J, Shared& sh, int
   int tbase = 0;
   // the slot's arrays, read once: the stores below could otherwise force a
   // reload (and a wait) of the descriptor before each of them
-  const int64_t trailCap = s->trailCap;
-  CT_G uint64_t* const sCt = s->ct;
-  CT_G uint64_t* const sTrailWords = s->trailWords;
-  CT_G TrailHdr* const sTrailHdr = s->trailHdr;
-  CT_G int32_t* const sStamp = s->stamp;
-  CT_G int32_t* const sNz = s->nzFlag;
+  const SlotPtrs P = sp ? *sp : slot_ptrs(s);
+  const int64_t trailCap = P.trailCap;
+  CT_G uint64_t* const sCt = P.ct;
+  CT_G uint64_t* const sTrailWords = P.trailWords;
+  CT_G TrailHdr* const sTrailHdr = P.trailHdr;
+  CT_G int32_t* const sStamp = P.stamp;
+  CT_G int32_t* const sNz = P.nzFlag;
   CT_G uint64_t* const ctOut = J.ct_out;
   if (nNeed) {
     if (lane == 0) tbase = atomicAdd(trailCounter, nNeed);
@@ -658,26 +694,29 @@ __device__ int finalize_update(const DevJob& J, Shared& sh, bool ldsFlags, int j
   int st = sh.status;
   if (st == ST_OK && !sh.noop) {
     const bool scratch = J.flags & JF_SCRATCH;  // index = identity
-    const CT_G int32_t* src = fromRoot ? T->idx0 : s->idx[s->cur];
-    const int dstBuf = fromRoot ? 0 : 1 - s->cur;
-    CT_G int32_t* dst = s->idx[dstBuf];
+    // the index buffers and flags as the prologue read them (sh.sp, sh.cur)
+    const CT_G int32_t* src = fromRoot ? T->idx0 : sh.sp.idx[sh.cur];
+    const int dstBuf = fromRoot ? 0 : 1 - sh.cur;
+    CT_G int32_t* dst = sh.sp.idx[dstBuf];
+    const CT_G int32_t* nzf = sh.sp.nzFlag;
     const int per = (limit + BLOCK - 1) / BLOCK;
     const int b = min((int)threadIdx.x * per, limit);
     const int e = min(b + per, limit);
     int cnt = 0;
-    for (int p = b; p < e; ++p) cnt += ldsFlags ? sh.nz[p] : s->nzFlag[p];
+    for (int p = b; p < e; ++p) cnt += ldsFlags ? sh.nz[p] : nzf[p];
     int nSurv = 0;
     int sv = block_scan_excl(cnt, &nSurv, sh);
     int zr = nSurv + (b - sv);
     for (int p = b; p < e; ++p) {
       const int gid = scratch ? p : ldsFlags ? (int)sh.gidx[p] : src[p];
-      const int f = ldsFlags ? sh.nz[p] : s->nzFlag[p];
+      const int f = ldsFlags ? sh.nz[p] : nzf[p];
       if (f) dst[sv++] = gid; else dst[zr++] = gid;
     }
     for (int p = limit + threadIdx.x; p < nGran; p += BLOCK) dst[p] = scratch ? p : src[p];
     if (nSurv == 0 && !negative) st = ST_FAIL;
     if (threadIdx.x == 0) {
       s->cur = dstBuf;
+      sh.cur = dstBuf;  // a second pass over the job (negative tables) reads it
       s->limit = nSurv;
       if (fromRoot) {
         s->depth = 0;
@@ -723,7 +762,7 @@ __device__ __forceinline__ FilterPre filter_pre(const KArgs& a, const DevJob& J,
   const TabDesc* T = J.tab;
   const int lane = lane_id();
   FilterPre f;
-  f.v = T->vars[T->wordVar[q]];
+  f.v = T->words[q].v;
   f.din = job_din(a, J, q);
   f.size = 0;
   for (int k = f.v.domOff; k < f.v.domOff + f.v.domWords; ++k) f.size += __popcll(job_din(a, J, k));
@@ -935,7 +974,7 @@ __device__ __forceinline__ void do_update(const KArgs& a, const DevJob& J, int c
   // time (the item covers WAVES x tile granules)
   const int reps = tile_reps(J.tile);
   for (int r = 0; r < reps; ++r)
-    update_granules<NGW>(a, J, sh, ((chunk * reps + r) * WAVES + wave_id()) * NGW, false, &s->jobTrail);
+    update_granules<NGW>(a, J, sh, ((chunk * reps + r) * WAVES + wave_id()) * NGW, false, &s->jobTrail, &sh.sp);
 
   // count finished items; the last one finalizes the job (a job of one
   // update item finalizes its own writes: no fence, no count)

@@ -186,6 +186,7 @@ struct ct_table {
   uint64_t* dS = nullptr;
   VarDesc* dVars = nullptr;
   int32_t* dWordVar = nullptr;
+  WordDesc* dWords = nullptr;
   int32_t* dLo = nullptr;
   TabDesc hTab{};
   SlotDesc* dRoot = nullptr;
@@ -927,10 +928,20 @@ static int create_impl(ct_table* T, const int32_t* tuples, int64_t t, int32_t n,
   if ((rc = dev_alloc(T, (void**)&T->dS, sizeof(uint64_t) * (size_t)rows * T->stride))) return rc;
   if ((rc = dev_alloc(T, (void**)&T->dVars, sizeof(VarDesc) * n))) return rc;
   if ((rc = dev_alloc(T, (void**)&T->dWordVar, sizeof(int32_t) * D))) return rc;
+  if ((rc = dev_alloc(T, (void**)&T->dWords, sizeof(WordDesc) * D))) return rc;
   if ((rc = dev_alloc(T, (void**)&T->dLo, sizeof(int32_t) * n))) return rc;
   if ((rc = dev_alloc(T, (void**)&T->dTab, sizeof(TabDesc)))) return rc;
   HIPCHK(hipMemcpy(T->dVars, T->vars.data(), sizeof(VarDesc) * n, hipMemcpyHostToDevice));
   HIPCHK(hipMemcpy(T->dWordVar, T->wordVar.data(), sizeof(int32_t) * D, hipMemcpyHostToDevice));
+  {
+    std::vector<WordDesc> words(D);
+    for (int q = 0; q < D; ++q) {
+      words[q] = WordDesc{};
+      words[q].v = T->vars[T->wordVar[q]];
+      words[q].var = T->wordVar[q];
+    }
+    HIPCHK(hipMemcpy(T->dWords, words.data(), sizeof(WordDesc) * D, hipMemcpyHostToDevice));
+  }
   HIPCHK(hipMemcpy(T->dLo, lo, sizeof(int32_t) * n, hipMemcpyHostToDevice));
   HIPCHK(hipMemsetAsync(T->dS, 0, sizeof(uint64_t) * (size_t)rows * T->stride, T->stream));
   if (t > 0) {
@@ -980,6 +991,7 @@ static int create_impl(ct_table* T, const int32_t* tuples, int64_t t, int32_t n,
   tb.S = T->dS;
   tb.vars = T->dVars;
   tb.wordVar = T->dWordVar;
+  tb.words = T->dWords;
   tb.policy = T->cfg.branch_policy;
   tb.tailBits = T->W > 0 ? (int32_t)(t - 64 * (T->W - 1)) : 0;
   tb.kind = T->kind;
