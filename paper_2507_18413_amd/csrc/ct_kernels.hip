@@ -134,17 +134,37 @@ __device__ bool block_wait(const KArgs& a, int32_t* flag, int32_t want, Shared& 
   return ok != 0;
 }
 
+// Workgroup barrier that orders LDS only: global stores still in flight
+// need not complete here (__syncthreads waits for them).
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+// Inclusive prefix sum over the 64 lanes (every lane active), with DPP
+// moves (VALU, no LDS round trips): shifts within rows of 16 lanes, then
+// the row broadcasts of lanes 15 and 31.
+__device__ __forceinline__ int wave_scan_incl(int v) {
+  v += __builtin_amdgcn_update_dpp(0, v, 0x111, 0xf, 0xf, false);  // row_shr:1
+  v += __builtin_amdgcn_update_dpp(0, v, 0x112, 0xf, 0xf, false);  // row_shr:2
+  v += __builtin_amdgcn_update_dpp(0, v, 0x114, 0xf, 0xf, false);  // row_shr:4
+  v += __builtin_amdgcn_update_dpp(0, v, 0x118, 0xf, 0xf, false);  // row_shr:8
+  v += __builtin_amdgcn_update_dpp(0, v, 0x142, 0xa, 0xf, false);  // row_bcast:15
+  v += __builtin_amdgcn_update_dpp(0, v, 0x143, 0xc, 0xf, false);  // row_bcast:31
+  return v;
+}
+
 // Exclusive prefix sum over the block; *total receives the sum.
+// (LDS_ONLY: its barriers order LDS only, so global stores still in flight
+// need not complete there)
+template <bool LDS_ONLY = false>
 __device__ int block_scan_excl(int v, int* total, Shared& sh) {
   const int lane = lane_id(), w = wave_id();
-  int x = v;
-#pragma unroll
-  for (int d = 1; d < WAVE; d <<= 1) {
-    const int y = __shfl_up(x, d);
-    if (lane >= d) x += y;
-  }
+  const int x = wave_scan_incl(v);
   if (lane == WAVE - 1) sh.wsum[w] = x;
-  __syncthreads();
+  if (LDS_ONLY) lds_barrier();
+  else __syncthreads();
   int off = 0, tot = 0;
 #pragma unroll
   for (int k = 0; k < WAVES; ++k) {
@@ -152,7 +172,8 @@ __device__ int block_scan_excl(int v, int* total, Shared& sh) {
     if (k < w) off += s;
     tot += s;
   }
-  __syncthreads();
+  if (LDS_ONLY) lds_barrier();
+  else __syncthreads();
   *total = tot;
   return off + x - v;
 }
@@ -316,19 +337,6 @@ __device__ __forceinline__ void do_prep(const KArgs& a, const DevJob& J, Shared&
     if (!(J.flags & JF_PROPAGATE)) publish_status(J, ST_OK);
     else st_release(&J.slot->prepDone, 1);  // consumed (and reset) by the job's last update item
   }
-}
-
-// Inclusive prefix sum over the 64 lanes.
-// DPP moves (VALU, no LDS round trips): shifts within rows of 16 lanes,
-// then the row broadcasts of lanes 15 and 31.
-__device__ __forceinline__ int wave_scan_incl(int v) {
-  v += __builtin_amdgcn_update_dpp(0, v, 0x111, 0xf, 0xf, false);  // row_shr:1
-  v += __builtin_amdgcn_update_dpp(0, v, 0x112, 0xf, 0xf, false);  // row_shr:2
-  v += __builtin_amdgcn_update_dpp(0, v, 0x114, 0xf, 0xf, false);  // row_shr:4
-  v += __builtin_amdgcn_update_dpp(0, v, 0x118, 0xf, 0xf, false);  // row_shr:8
-  v += __builtin_amdgcn_update_dpp(0, v, 0x142, 0xa, 0xf, false);  // row_bcast:15
-  v += __builtin_amdgcn_update_dpp(0, v, 0x143, 0xc, 0xf, false);  // row_bcast:31
-  return v;
 }
 
 __device__ void stage_rows(const DevJob& J, Shared& sh, int k0);
@@ -705,14 +713,15 @@ __device__ int finalize_update(const DevJob& J, Shared& sh, bool ldsFlags, int j
     int cnt = 0;
     for (int p = b; p < e; ++p) cnt += ldsFlags ? sh.nz[p] : nzf[p];
     int nSurv = 0;
-    int sv = block_scan_excl(cnt, &nSurv, sh);
+    int sv = block_scan_excl<true>(cnt, &nSurv, sh);
     int zr = nSurv + (b - sv);
     for (int p = b; p < e; ++p) {
       const int gid = scratch ? p : ldsFlags ? (int)sh.gidx[p] : src[p];
       const int f = ldsFlags ? sh.nz[p] : nzf[p];
       if (f) dst[sv++] = gid; else dst[zr++] = gid;
     }
-    for (int p = limit + threadIdx.x; p < nGran; p += BLOCK) dst[p] = scratch ? p : src[p];
+    for (int p = limit + threadIdx.x; p < nGran; p += BLOCK)
+      dst[p] = scratch ? p : ldsFlags ? (int)sh.gidx[p] : src[p];
     if (nSurv == 0 && !negative) st = ST_FAIL;
     if (threadIdx.x == 0) {
       s->cur = dstBuf;
@@ -969,29 +978,56 @@ __device__ __forceinline__ void do_update(const KArgs& a, const DevJob& J, int c
   if (J.nPop > 0) {
     if (!block_wait(a, &s->prepDone, 1, sh)) return;
   }
-  prologue(a, J, sh, false);
+  // a job of one update item runs the whole update in this workgroup, as
+  // in solo mode: pushes in the prologue (unless the prep item made them),
+  // granule list, flags and trail count in LDS, no global round trip
+  // between the update and the partition (one call site each of the
+  // prologue and the update: a second would take the kernel arguments'
+  // address)
+  const bool one = J.nUpd == 1;
+  if (one && threadIdx.x == 0) sh.trailCount = 0;
+  prologue(a, J, sh, one && J.nPop == 0 && J.nPush > 0);
+  if (one) {
+    const int span = sh.status == ST_OK ? J.tab->nGran : 0;
+    const CT_G int32_t* src = (J.flags & JF_FROM_ROOT) ? J.tab->idx0 : sh.sp.idx[sh.cur];
+    const bool scratch = J.flags & JF_SCRATCH;
+    for (int p = threadIdx.x; p < span; p += BLOCK) sh.gidx[p] = (uint16_t)(scratch ? p : src[p]);
+    lds_barrier();
+  }
   // the job's tile: each wave takes tile granules of the item, NGW at a
   // time (the item covers WAVES x tile granules)
   const int reps = tile_reps(J.tile);
   for (int r = 0; r < reps; ++r)
-    update_granules<NGW>(a, J, sh, ((chunk * reps + r) * WAVES + wave_id()) * NGW, false, &s->jobTrail, &sh.sp);
-
-  // count finished items; the last one finalizes the job (a job of one
-  // update item finalizes its own writes: no fence, no count)
-  __syncthreads();
-  if (J.nUpd > 1) {
+    update_granules<NGW>(a, J, sh, ((chunk * reps + r) * WAVES + wave_id()) * NGW, one,
+                         one ? &sh.trailCount : &s->jobTrail, &sh.sp);
+  if (one) {
+    lds_barrier();
+    if (J.nPop > 0 && threadIdx.x == 0) s->prepDone = 0;  // the prep item also did the pushes
+    const int st = finalize_update(J, sh, true, sh.trailCount);
     if (threadIdx.x == 0) {
-      item_fence(J);
-      const int prev = atomicAdd(&s->updCount, 1);
-      sh.isLast = prev == J.nUpd - 1;
-      if (sh.isLast) {
-        s->updCount = 0;
-        __threadfence();
-      }
+      if (st != ST_OK) publish_status(J, st);
+      // finalize_update ends with a full barrier: the block's writes are
+      // ordered before this release; a currTable copy in host memory is
+      // made visible before the filter publishes the status
+      if (J.ct_out) status_fence(J);
+      st_release(&s->updDone, 1);  // consumed (and reset) by the job's last filter item
     }
-    __syncthreads();
-    if (!sh.isLast) return;
+    return;
   }
+
+  // count finished items; the last one finalizes the job
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    item_fence(J);
+    const int prev = atomicAdd(&s->updCount, 1);
+    sh.isLast = prev == J.nUpd - 1;
+    if (sh.isLast) {
+      s->updCount = 0;
+      __threadfence();
+    }
+  }
+  __syncthreads();
+  if (!sh.isLast) return;
 
   if (J.nPop > 0) {
     if (threadIdx.x == 0) s->prepDone = 0;  // the prep item also did the pushes
@@ -1017,9 +1053,7 @@ __device__ __forceinline__ void do_update(const KArgs& a, const DevJob& J, int c
     s->jobTrail = 0;
     if (st != ST_OK) publish_status(J, st);
     // finalize_update ends with a barrier: the block's writes are ordered
-    // before this release; a currTable copy in host memory (written by the
-    // update items) is made visible before the filter publishes the status
-    if (J.nUpd == 1 && J.ct_out) status_fence(J);
+    // before this release
     st_release(&s->updDone, 1);  // consumed (and reset) by the job's last filter item
   }
 }
