@@ -1114,23 +1114,27 @@ __global__ void __launch_bounds__(EBLOCK) engine_kernel(EngDesc D) {
       bool seen = false;
       uint64_t v = 0;
       {
-        uint64_t a = l < nS ? ll_load(slots + l) : (uint64_t)want;
+        // every lane loads (lanes past the command re-read its last slot and
+        // count as holding the number): loads under a branch would each be
+        // waited for before the test, one poll in flight at a time
+        const uint64_t* mine = slots + min(l, nS - 1);
+#define E_POLL_LD ll_load(mine)
+#define E_POLL_TEST(x)                                              \
+  if (__all(l >= nS || (uint32_t)(x) == want)) {                    \
+    v = (x);                                                        \
+    seen = true;                                                    \
+    break;                                                          \
+  }                                                                 \
+  if ((long long)(wall_clock64() - t0) > D.idleTicks) break;
+        uint64_t p0 = E_POLL_LD;
         for (;;) {
-          const uint64_t b = l < nS ? ll_load(slots + l) : (uint64_t)want;
-          if (__all((uint32_t)a == want)) {
-            v = a;
-            seen = true;
-            break;
-          }
-          if ((long long)(wall_clock64() - t0) > D.idleTicks) break;
-          a = l < nS ? ll_load(slots + l) : (uint64_t)want;
-          if (__all((uint32_t)b == want)) {
-            v = b;
-            seen = true;
-            break;
-          }
-          if ((long long)(wall_clock64() - t0) > D.idleTicks) break;
+          const uint64_t p1 = E_POLL_LD;
+          E_POLL_TEST(p0)
+          p0 = E_POLL_LD;
+          E_POLL_TEST(p1)
         }
+#undef E_POLL_TEST
+#undef E_POLL_LD
       }
       uint32_t* din32 = (uint32_t*)E.din;
       if (seen) {
@@ -1141,11 +1145,12 @@ __global__ void __launch_bounds__(EBLOCK) engine_kernel(EngDesc D) {
             uint64_t w[E_CMD_U];
             bool ok = true;
 #pragma unroll
-            for (int u = 0; u < E_CMD_U; ++u) {
+            for (int u = 0; u < E_CMD_U; ++u) {  // unconditional loads, as above
               const int i = c0 + u * WAVE + l;
-              w[u] = i < nS ? ll_load(slots + i) : (uint64_t)want;
-              ok = ok && (uint32_t)w[u] == want;
+              w[u] = ll_load(slots + min(i, nS - 1));
             }
+#pragma unroll
+            for (int u = 0; u < E_CMD_U; ++u) ok = ok && (c0 + u * WAVE + l >= nS || (uint32_t)w[u] == want);
             if (__all(ok)) {
 #pragma unroll
               for (int u = 0; u < E_CMD_U; ++u) {
