@@ -62,6 +62,57 @@ def test_long_run_without_state_reads(policy):
         assert (gc == oc).all()
 
 
+def test_deep_levels_past_the_lds_rings():
+    """Pops that reach levels and trail entries older than what the engine
+    mirrors in LDS (64 levels; trail headers up to 4,096 entries, about 83
+    levels of this 49-granule table) take them from HBM: 100 levels pushed,
+    each removing one value, then pops of 37, 41 and 15 levels with calls in
+    between (the second pop reaches a level record older than the ring, the
+    third trail entries older than it too), every output and the final state
+    equal to the oracle's."""
+    spec = W.large_table(t=200_000, d=50, n=5)
+    say("engine: 100 levels, pops across the LDS rings")
+    G, Ot = pair(spec)
+    assert G.resident
+    lay = spec.layout()
+    rng = W.rng_for(4, 602, 0)
+
+    def call(want_ct):
+        dom_in = Ot.domains().copy()
+        cand = [i for i in range(lay.n) if lay.count(dom_in, i) > 1]
+        i = cand[int(rng.integers(0, len(cand)))]
+        vals = lay.values(dom_in, i)
+        lay.clear(dom_in, i, int(vals[int(rng.integers(0, vals.shape[0]))]))
+        if want_ct:
+            gs, gd, gc = G.propagate(dom_in, want_ct=True)
+            os_, od, oc = Ot.propagate(dom_in, want_ct=True)
+        else:
+            gs, gd = G.propagate(dom_in)
+            os_, od = Ot.propagate(dom_in)
+            gc = oc = None
+        assert gs == os_
+        if os_ == O.OK:
+            assert (gd == od).all()
+            if gc is not None:
+                assert (gc == oc).all()
+        return os_
+
+    for level in range(100):
+        assert G.push() == ct.OK and Ot.push() == O.OK
+        assert call(level % 16 == 0) == O.OK, level
+    for k in (37, 41, 15):
+        for _ in range(k):
+            assert G.pop() == ct.OK and Ot.pop() == O.OK
+        for j in range(3):
+            assert G.push() == ct.OK and Ot.push() == O.OK
+            call(j == 2)
+        for _ in range(3):
+            assert G.pop() == ct.OK and Ot.pop() == O.OK
+    gd, gc = G.state()
+    od, oc, of = Ot.state()
+    assert (gd == od).all() and (gc == oc).all()
+
+
 def test_idle_exit_and_restart():
     spec = W.large_table(t=20_000, d=20, n=4)
     say("engine: idle exits between calls")
