@@ -792,7 +792,7 @@ __device__ __forceinline__ FilterPre filter_pre(const KArgs& a, const DevJob& J,
 __device__ void filter_word(const KArgs& a, const DevJob& J, int q, int noop, int lim,
                             const CT_G int32_t* idx, unsigned long long* cnt, const FilterPre& f,
                             bool haveCtRes = false, uint64_t ctRes = 0ull, CT_G uint64_t* ctArr = nullptr,
-                            CT_G int32_t* resArr = nullptr) {
+                            CT_G int32_t* resArr = nullptr, const int* idxHead = nullptr) {
   const TabDesc* T = J.tab;
   SlotDesc* slot = J.slot;
   // the slot's arrays, read once (see update_granules), or as the caller
@@ -828,7 +828,9 @@ __device__ void filter_word(const KArgs& a, const DevJob& J, int q, int noop, in
       uint64_t c[FULL_SCAN_GRAN];
 #pragma unroll
       for (int j = 0; j < FULL_SCAN_GRAN; ++j) {
-        const int gv = idx[min(j, lim - 1)];
+        // the first FULL_SCAN_GRAN entries of the index as the caller read
+        // them, or from memory
+        const int gv = idxHead ? idxHead[j] : idx[min(j, lim - 1)];
         gg[j] = j < lim ? gv : -1;
         const uint64_t cv = s->ct[(int64_t)gv * GW + lane];
         c[j] = j < lim ? cv : 0ull;
@@ -1072,12 +1074,23 @@ __device__ __forceinline__ void do_filter(const KArgs& a, const DevJob& J, int c
   const FilterPre pre = filter_pre(a, J, qc);
   if (threadIdx.x < 3) sh.fcnt[threadIdx.x] = 0ull;
   if (!block_wait(a, &s->updDone, 1, sh)) return;
-  // one round trip: the job's state after the update and, per value, the
-  // currTable word at its residue
+  // one round trip: the job's state after the update, per value the
+  // currTable word at its residue, and the head of both index buffers (the
+  // one in use is known with the state)
   const int jobStatus = s->status, noop = s->pad2, lim = s->limit, cur = s->cur;
   const uint64_t cr = sct[pre.rw0];
+  const int nG = J.tab->nGran;
+  int h0[FULL_SCAN_GRAN], h1[FULL_SCAN_GRAN], head[FULL_SCAN_GRAN];
+#pragma unroll
+  for (int j = 0; j < FULL_SCAN_GRAN; ++j) {
+    h0[j] = idx0[min(j, nG - 1)];
+    h1[j] = idx1[min(j, nG - 1)];
+  }
+#pragma unroll
+  for (int j = 0; j < FULL_SCAN_GRAN; ++j) head[j] = cur ? h1[j] : h0[j];
   unsigned long long cnt[3] = {0, 0, 0};
-  if (q < J.tab->D && jobStatus == ST_OK) filter_word(a, J, q, noop, lim, cur ? idx1 : idx0, cnt, pre, true, cr, sct, sres);
+  if (q < J.tab->D && jobStatus == ST_OK)
+    filter_word(a, J, q, noop, lim, cur ? idx1 : idx0, cnt, pre, true, cr, sct, sres, head);
   // the item's counts, summed in LDS: one set of counter atomics per item
   if (lane_id() == 0 && (cnt[0] | cnt[1] | cnt[2]))
     for (int k = 0; k < 3; ++k) atomicAdd(&sh.fcnt[k], cnt[k]);
