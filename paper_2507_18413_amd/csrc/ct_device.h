@@ -64,6 +64,12 @@ constexpr uint32_t JF_INLINE_DOM = 8u;
 constexpr uint32_t JF_HOST_OUT = 16u;   // status / outputs in host memory: system-scope release
 constexpr uint32_t JF_SOLO = 32u;       // whole job in one workgroup
 constexpr uint32_t JF_SCRATCH = 64u;    // with JF_ROOT | JF_FROM_ROOT: root state recomputed from all tuples
+// A synchronous split job answers through flagged slots in host memory (`ll`:
+// slot 0 the status of a job that does not succeed, slots 2 + 2q and 3 + 2q
+// the halves of domain word q; every slot carries `seq`): no fence, no count
+// of finished items, and the host takes the call once all its domain words
+// carry the number (or the status slot does).
+constexpr uint32_t JF_LL = 128u;
 
 struct VarDesc {
   int32_t rowStart, dsize, domOff, domWords;
@@ -142,7 +148,13 @@ struct DevJob {
   int32_t tile;            // split jobs: granules per wave per update item (2, 4 or 8;
                            // 0 = 2); solo jobs step 4 granules per wave
   const CT_G int32_t* active;  // nullable: the job is skipped when *active == 0
+  uint64_t* ll;             // JF_LL: the result slots (pinned host memory)
+  int32_t seq, llPad;       // JF_LL: the call's number
 };
+
+// The update item's hand-over word of a JF_LL job: the call's number with
+// bit 30 set (never 0 or 1, the values the counted protocol uses).
+__host__ __device__ inline int32_t ll_gen(int32_t seq) { return (seq & 0x3fffffff) | 0x40000000; }
 
 // Granule-major schedule of a batch of search nodes (jobs that all propagate
 // one table from its root state).  Per node: the Alg. 1 prologue's outcome

@@ -210,7 +210,15 @@ __device__ __forceinline__ uint64_t all_tuples_word(const TabDesc* T, int64_t w)
 // Job status for the caller.  Outputs in host memory are published with a
 // system-scope release after a system-scope fence, so a host that sees the
 // status also sees the domain words written before it.
+__device__ __forceinline__ void ll_put(uint64_t* p, uint64_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
 __device__ void publish_status(const DevJob& J, int st) {
+  if (J.flags & JF_LL) {  // a flagged slot: no fence (see JF_LL)
+    ll_put(J.ll, eng_slot((uint32_t)st, (uint32_t)J.seq));
+    return;
+  }
   if (!J.status_out) return;
   if (J.flags & JF_HOST_OUT) {
     __threadfence_system();
@@ -953,10 +961,12 @@ __device__ void filter_word(const KArgs& a, const DevJob& J, int q, int noop, in
     }
     dout = din & ~unsup;
   }
-  if (lane == 0) {
+  if (J.flags & JF_LL) {
+    if (lane < 2) ll_put(J.ll + 2 + 2 * q + lane, eng_slot((uint32_t)(lane ? dout >> 32 : dout), (uint32_t)J.seq));
+  } else if (lane == 0) {
     J.dom_out[q] = dout;
-    slot->lastDom[q] = dout;
   }
+  if (lane == 0) slot->lastDom[q] = dout;
 }
 
 __device__ __forceinline__ void filter_word(const KArgs& a, const DevJob& J, int q, int noop, int lim,
@@ -1012,7 +1022,9 @@ __device__ __forceinline__ void do_update(const KArgs& a, const DevJob& J, int c
       // ordered before this release; a currTable copy in host memory is
       // made visible before the filter publishes the status
       if (J.ct_out) status_fence(J);
-      st_release(&s->updDone, 1);  // consumed (and reset) by the job's last filter item
+      // consumed (and reset) by the job's last filter item, or a flagged
+      // job's number
+      st_release(&s->updDone, (J.flags & JF_LL) ? ll_gen(J.seq) : 1);
     }
     return;
   }
@@ -1056,7 +1068,7 @@ __device__ __forceinline__ void do_update(const KArgs& a, const DevJob& J, int c
     if (st != ST_OK) publish_status(J, st);
     // finalize_update ends with a barrier: the block's writes are ordered
     // before this release
-    st_release(&s->updDone, 1);  // consumed (and reset) by the job's last filter item
+    st_release(&s->updDone, (J.flags & JF_LL) ? ll_gen(J.seq) : 1);
   }
 }
 
@@ -1073,7 +1085,8 @@ __device__ __forceinline__ void do_filter(const KArgs& a, const DevJob& J, int c
   CT_G int32_t* const idx1 = s->idx[1];
   const FilterPre pre = filter_pre(a, J, qc);
   if (threadIdx.x < 3) sh.fcnt[threadIdx.x] = 0ull;
-  if (!block_wait(a, &s->updDone, 1, sh)) return;
+  const bool ll = J.flags & JF_LL;
+  if (!block_wait(a, &s->updDone, ll ? ll_gen(J.seq) : 1, sh)) return;
   // one round trip: the job's state after the update, per value the
   // currTable word at its residue, and the head of both index buffers (the
   // one in use is known with the state)
@@ -1097,6 +1110,7 @@ __device__ __forceinline__ void do_filter(const KArgs& a, const DevJob& J, int c
   // the last filter item of the job reports OK
   __syncthreads();
   if (threadIdx.x == 0) add_filter_stats(s, sh.fcnt);
+  if (ll) return;  // the host counts the domain words itself
   if (threadIdx.x == 0) {
     status_fence(J);  // no other item reads this one's outputs
     const int prev = atomicAdd(&s->filtCount, 1);

@@ -195,6 +195,8 @@ struct ct_table {
   QueueCtx q;
   // pinned staging of the synchronous calls
   uint64_t* pDomOut = nullptr;  // D words
+  uint64_t* pLL = nullptr;      // result slots of flagged synchronous jobs (2 + 2D)
+  int32_t llSeq = 0;
   uint64_t* pDomIn = nullptr;   // D words (used when D > INLINE_WORDS)
   uint64_t* pCt = nullptr;      // W words (lazily)
   int32_t* pStatus = nullptr;
@@ -375,6 +377,8 @@ bool needs_prep(const DevJob& J) {
 // Run one job synchronously on the table's stream.
 int quiesce(ct_table* T, hipStream_t same = nullptr);
 
+uint64_t* pinned_dev64(ct_table* T, uint64_t* host);
+
 int run_single(ct_table* T, DevJob& J, const uint64_t* dom_in_host) {
   int qrc = quiesce(T);
   if (qrc) return qrc;
@@ -385,6 +389,17 @@ int run_single(ct_table* T, DevJob& J, const uint64_t* dom_in_host) {
   job_counts(T, J);
   a.nPrep = needs_prep(J) ? 1 : 0;
   J.flags |= JF_HOST_OUT;
+  // a split propagation answers through flagged slots (no currTable copy:
+  // that one keeps the fenced, counted status)
+  const bool ll = (J.flags & JF_PROPAGATE) && !(J.flags & JF_SOLO) && !J.ct_out && T->pLL;
+  uint32_t sq = 0;
+  if (ll) {
+    J.flags |= JF_LL;
+    J.seq = ++T->llSeq;
+    if (J.seq == 0) J.seq = ++T->llSeq;  // (0 is the slots' initial flag)
+    sq = (uint32_t)J.seq;
+    if (!(J.ll = pinned_dev64(T, T->pLL))) return fail(CT_E_DEVICE, "no device address for the result slots");
+  }
   a.nUpd = J.nUpd;
   a.nFilt = J.nFilt;
   a.queue = T->q.queue;
@@ -408,6 +423,41 @@ int run_single(ct_table* T, DevJob& J, const uint64_t* dom_in_host) {
   a.clock = T->timing ? T->dClock : nullptr;
   HIPCHK(launch_propagate(a, std::min(total, propagate_max_grid()), T->stream));
   T->tailPending = true;
+  if (ll) {
+    // the status slot (a job that does not succeed) or every domain word
+    const uint64_t* sl = T->pLL;
+    const int nS = 2 * T->D;
+    int got = 0;
+    const auto t0 = std::chrono::steady_clock::now();
+    for (uint32_t spin = 0;; ++spin) {
+      const uint64_t v = __atomic_load_n(&sl[0], __ATOMIC_ACQUIRE);
+      if ((uint32_t)v == sq) {
+        *status = (int32_t)(uint32_t)(v >> 32);
+        break;
+      }
+      while (got < nS && (uint32_t)__atomic_load_n(&sl[2 + got], __ATOMIC_ACQUIRE) == sq) ++got;
+      if (got == nS) {
+        for (int q = 0; q < T->D; ++q)
+          T->pDomOut[q] = ((uint64_t)(uint32_t)(sl[3 + 2 * q] >> 32) << 32) | (uint32_t)(sl[2 + 2 * q] >> 32);
+        *status = CT_OK;
+        break;
+      }
+      if ((spin & 1023) == 1023 && std::chrono::steady_clock::now() - t0 > std::chrono::seconds(2)) {
+        hipError_t e = hipStreamSynchronize(T->stream);
+        if (e != hipSuccess) {
+          T->poisoned = true;
+          return fail(CT_E_DEVICE, "kernel failed: %s", hipGetErrorString(e));
+        }
+        T->poisoned = true;
+        return fail(CT_E_DEVICE, "kernel finished without a result (device error %d)", *T->q.hostErr);
+      }
+    }
+    if (*T->q.hostErr) {
+      T->poisoned = true;
+      return fail(CT_E_DEVICE, "device-side error %d (wait timeout or trail overflow)", *T->q.hostErr);
+    }
+    return CT_OK;
+  }
   // The job publishes its status (and its outputs before it) to coherent
   // host memory with a system-scope release: wait for that word instead of
   // the whole kernel.  The kernel's tail finishes on the stream, which
@@ -828,6 +878,7 @@ void ct_destroy(ct_table* T) {
   for (void* p : T->blocks) (void)hipFree(p);
   queue_free(T->q);
   if (T->pDomOut) (void)hipHostFree(T->pDomOut);
+  if (T->pLL) (void)hipHostFree(T->pLL);
   if (T->pDomIn) (void)hipHostFree(T->pDomIn);
   if (T->pCt) (void)hipHostFree(T->pCt);
   if (T->pStatus) (void)hipHostFree(T->pStatus);
@@ -921,6 +972,8 @@ static int create_impl(ct_table* T, const int32_t* tuples, int64_t t, int32_t n,
   // memory without waiting for the end of the kernel
   const unsigned kCoherent = hipHostMallocMapped | hipHostMallocCoherent;
   ALLOCCHK(hipHostMalloc((void**)&T->pDomOut, sizeof(uint64_t) * D, kCoherent));
+  ALLOCCHK(hipHostMalloc((void**)&T->pLL, sizeof(uint64_t) * (2 + 2 * (size_t)D), kCoherent));
+  memset(T->pLL, 0, sizeof(uint64_t) * (2 + 2 * (size_t)D));
   ALLOCCHK(hipHostMalloc((void**)&T->pDomIn, sizeof(uint64_t) * D, kCoherent));
   ALLOCCHK(hipHostMalloc((void**)&T->pStatus, sizeof(int32_t) * 4, kCoherent));
 
