@@ -347,7 +347,8 @@ __device__ __forceinline__ void do_prep(const KArgs& a, const DevJob& J, Shared&
   }
 }
 
-__device__ void stage_rows(const DevJob& J, Shared& sh, int k0);
+__device__ void stage_rows(const DevJob& J, Shared& sh, int k0, const CT_G uint64_t* lastArr = nullptr,
+                           const CT_G WordDesc* wordsArr = nullptr);
 
 // ---------------------------------------------------------------------------
 // prologue of Alg. 1 for one job (every update item recomputes it in LDS)
@@ -359,6 +360,9 @@ __device__ void prologue(const KArgs& a, const DevJob& J, Shared& sh, bool pushH
   const bool root = J.flags & JF_ROOT;
   const bool scratch = J.flags & JF_SCRATCH;
   const int n = T->n, D = T->D;
+  // read before the barriers (a load after one waits its round trip)
+  const int policy = T->policy;
+  const CT_G WordDesc* words = T->words;
   const CT_G uint64_t* last = fromRoot ? T->dom0 : s->lastDom;
   if (threadIdx.x == 0) {
     sh.bad_stray = 0;
@@ -402,7 +406,7 @@ __device__ void prologue(const KArgs& a, const DevJob& J, Shared& sh, bool pushH
   __syncthreads();
   for (int q = threadIdx.x; q < D; q += BLOCK) {
     const uint64_t din = job_din(a, J, q);
-    const WordDesc wd = T->words[q];
+    const WordDesc wd = words[q];
     const int i = wd.var;
     const VarDesc v = wd.v;
     const int used = v.dsize - 64 * (q - v.domOff);
@@ -424,7 +428,6 @@ __device__ void prologue(const KArgs& a, const DevJob& J, Shared& sh, bool pushH
     // wave 0: the segments of s_val in variable order (prefix sums over the
     // variables, 64 at a time)
     const int lane = threadIdx.x;
-    const int policy = T->policy;
     int nseg = 0, nrows = 0;
     for (int i0 = 0; i0 < n; i0 += WAVE) {
       const int i = i0 + lane;
@@ -449,8 +452,8 @@ __device__ void prologue(const KArgs& a, const DevJob& J, Shared& sh, bool pushH
           sh.segOf[i] = -1;
         }
       }
-      nseg += __shfl(segIncl, WAVE - 1);
-      nrows += __shfl(rowsIncl, WAVE - 1);
+      nseg += __builtin_amdgcn_readlane(segIncl, WAVE - 1);
+      nrows += __builtin_amdgcn_readlane(rowsIncl, WAVE - 1);
     }
     if (lane == 0) {
       if (sh.status == ST_OK) {
@@ -464,7 +467,7 @@ __device__ void prologue(const KArgs& a, const DevJob& J, Shared& sh, bool pushH
   }
   __syncthreads();
   if (sh.status != ST_OK || sh.noop) return;
-  stage_rows(J, sh, 0);
+  stage_rows(J, sh, 0, last, words);
   __syncthreads();
 }
 
@@ -472,12 +475,16 @@ __device__ void prologue(const KArgs& a, const DevJob& J, Shared& sh, bool pushH
 // selected rows of every segment, in segment order; word q of variable i
 // contributes the set bits of its Delta word (incremental) or domain word
 // (reset) in ascending order.  Whole block; a barrier must follow.
-__device__ void stage_rows(const DevJob& J, Shared& sh, int k0) {
+// (lastArr, wordsArr: the previous domains and the word records as the
+// caller read their addresses, else read here)
+__device__ void stage_rows(const DevJob& J, Shared& sh, int k0, const CT_G uint64_t* lastArr,
+                           const CT_G WordDesc* wordsArr) {
   const TabDesc* T = J.tab;
-  const CT_G uint64_t* last = (J.flags & JF_FROM_ROOT) ? T->dom0 : J.slot->lastDom;
+  const CT_G uint64_t* last = lastArr ? lastArr : (J.flags & JF_FROM_ROOT) ? T->dom0 : J.slot->lastDom;
+  const CT_G WordDesc* words = wordsArr ? wordsArr : T->words;
   const int k1 = k0 + ROWS_CHUNK;
   for (int q = threadIdx.x; q < T->D; q += BLOCK) {
-    const WordDesc wd = T->words[q];
+    const WordDesc wd = words[q];
     const int sg = sh.segOf[wd.var];
     if (sg < 0) continue;
     const VarDesc v = wd.v;
@@ -1401,7 +1408,7 @@ __global__ void __launch_bounds__(BLOCK) nodes_prep_kernel(KArgs a, NodesDesc N)
     const int c = (in && inc) ? cnt : 0;
     const int incl = wave_scan_incl(c);
     if (i < n) seg[i] = (in && inc) ? ((incTotal + incl - c) | (1 << 30)) : -1;
-    incTotal += __shfl(incl, WAVE - 1);
+    incTotal += __builtin_amdgcn_readlane(incl, WAVE - 1);
   }
   const int incPadded = (incTotal + 3) & ~3;
   int padded = incPadded;
@@ -1418,8 +1425,8 @@ __global__ void __launch_bounds__(BLOCK) nodes_prep_kernel(KArgs a, NodesDesc N)
     const int inclRows = wave_scan_incl(c);
     const int inclPad = wave_scan_incl(4 * groups);
     if (rs) seg[i] = padded + inclPad - 4 * groups;
-    total += __shfl(inclRows, WAVE - 1);
-    padded += __shfl(inclPad, WAVE - 1);
+    total += __builtin_amdgcn_readlane(inclRows, WAVE - 1);
+    padded += __builtin_amdgcn_readlane(inclPad, WAVE - 1);
   }
   if (st == ST_OK && __ballot(emptyReset)) st = ST_FAIL;
   wave_lds_sync();
