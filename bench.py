@@ -365,6 +365,7 @@ def wide_leg(seed, n_calls, cpu, split=True, paper_shape=False):
     props = replay(table, script)
     el = time.perf_counter() - t0
     kernel_ms, launches = table.timing()
+    life_ms, dispatches = table.dispatch_timing() if table.resident_split else (None, None)
     table.set_timing(False)
     s1 = table.stats()
     d = {k: s1[k] - s0[k] for k in s1}
@@ -382,15 +383,28 @@ def wide_leg(seed, n_calls, cpu, split=True, paper_shape=False):
            "props_per_s": round(props / el, 1),
            "latency_us": {"p50": round(float(np.percentile(lat_us, 50)), 2),
                           "p99": round(float(np.percentile(lat_us, 99)), 2)},
-           "kernel": {"name": "ctk::engine_kernel" if table.resident else "ctk::propagate_kernel",
+           "kernel": {"name": "ctk::engine_kernel" if table.resident else
+                      "ctk::split_engine_kernel" if table.resident_split else "ctk::propagate_kernel",
                       "calls_timed": launches,
-                      "device_us_per_call": round(kernel_ms * 1e3 / max(launches, 1), 3),
+                      # the resident split schedule: workgroup 0's time per
+                      # call (receipt to the hand-over to the filters); the
+                      # launched one: each launch's first start to last end
+                      "device_us_per_call" if not table.resident_split else "update_us_per_call":
+                          round(kernel_ms * 1e3 / max(launches, 1), 3),
                       "algorithmic_bytes_per_call": round(byts / max(props, 1), 1),
-                      "algorithmic_GBps": round(byts / (kernel_ms / 1e3) / 1e9, 2) if kernel_ms > 0 else None,
+                      "algorithmic_GBps": round(byts / ((life_ms if table.resident_split else kernel_ms) / 1e3)
+                                                / 1e9, 2) if kernel_ms > 0 else None,
                       "profiled_hbm_bytes_per_launch": prof.get("hbm_bytes_per_launch") if prof else None,
                       "profiled_avg_us": prof.get("avg_us") if prof else None,
                       "counters_per_call": {k: round(v / max(props, 1), 1) for k, v in d.items()}},
+           "schedule": "resident split" if table.resident_split else "resident engine" if table.resident
+           else "launched",
            "split_propagators": split_out}
+    if table.resident_split:
+        # launch lifetimes over the calls they served (the waits for the
+        # host's next call included)
+        out["kernel"]["launches"] = dispatches
+        out["kernel"]["launch_us_per_call"] = round(life_ms * 1e3 / max(launches, 1), 3)
     if cpu:
         from oracle import oracle as O
         for fast in (True, False):

@@ -78,7 +78,15 @@ typedef struct ct_table ct_table;
  * NODES for eligible batches of at least 64 jobs.  A batch whose jobs are all
  * CT_JOB_ROOT on AUTO tables runs as two launches: one wave per (job,
  * granule) streams every support row of its granule once, then one
- * workgroup per job partitions and filters.  Results are identical. */
+ * workgroup per job partitions and filters.  On an AUTO table of more than
+ * 64 and at most 256 domain words whose update is one SPLIT item (at most 8
+ * granules), with variables of at most 31 domain words, plain synchronous
+ * calls on slot 0 (no currTable copy, no counters) go to the resident split
+ * schedule: the SPLIT schedule's update workgroup and its filter workgroups
+ * as one persistent launch that takes calls from a mailbox in pinned host
+ * memory, as the resident engine does (it exits after 2 ms without a call
+ * and before any other operation on the table's device state).  Results are
+ * identical. */
 #define CT_SCHED_AUTO 0
 #define CT_SCHED_SOLO 1
 #define CT_SCHED_SPLIT 2
@@ -113,7 +121,8 @@ typedef struct {
     int32_t n_slots;
     int32_t granules;   /* 64-word groups of currTable tracked by the sparse index */
     int32_t root_failed;/* 1 if the root propagation found no valid tuple */
-    int32_t resident;   /* 1 if synchronous calls on slot 0 use the resident engine */
+    int32_t resident;   /* synchronous calls on slot 0: 1 = the resident engine,
+                           2 = the resident split schedule (AUTO), 0 = launched */
     int32_t kind;       /* CT_KIND_POSITIVE, CT_KIND_SHORT (positive with star cells) or
                            CT_KIND_NEGATIVE */
 } ct_layout_info;
@@ -544,8 +553,9 @@ const char *ct_last_error(void);
  * the hook off.  Returns the previous setting (allocations still to go). */
 int ct_debug_fail_alloc(int32_t nth);
 
-/* Ends the resident engine of any table (CT_SCHED_RESIDENT) after it has
- * written its state back to the device: call before the process exits, or
+/* Ends the resident engine of any table (CT_SCHED_RESIDENT, or the resident
+ * split schedule of an AUTO table) after it has written its state back to
+ * the device: call before the process exits, or
  * before work on the GPU that must not wait up to 2 ms behind an idle engine.
  * Synchronous; CT_OK or CT_E_DEVICE. */
 int ct_quiesce(void);

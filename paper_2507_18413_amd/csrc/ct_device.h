@@ -282,7 +282,19 @@ struct EngDesc {
   uint64_t* ctOut;          // pinned host buffer of W words (calls that want currTable)
   int64_t idleTicks;        // exit after this long without a call (device clock)
   int32_t startSeq, pad;    // the last call seq already answered
+  // resident split schedule only: its control words in device memory
+  // (SE_*, zeroed before each launch) and the filter workgroups
+  int32_t* ctl;
+  int32_t nFilt, pad2;
 };
+
+// Control words of the resident split schedule: the filter workgroups'
+// count of finished calls, the number of the call workgroup 0 has taken
+// (the filters' doorbell: they read the call from the mailbox once it is
+// there), and the word every wait of the launch watches (the launch's error
+// word: -1 once workgroup 0 has stopped, > 0 on a device error).
+enum { SE_DONE = 1, SE_CALL = 2, SE_STOP = 3, SE_CTL_WORDS = 4 };
+constexpr int SE_MAX_VAR_WORDS = 31;  // a filter wave reads its variable's input slots in one load
 
 // Read-only view of a table's immutable parts (host code only): device
 // supports, layout, branch policy and the device root state.

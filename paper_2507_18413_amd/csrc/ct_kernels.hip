@@ -85,6 +85,7 @@ struct Shared {
   unsigned long long fcnt[3];  // a filter item's counters (residue checks, misses, scans)
   int32_t cur;                 // the slot's index buffer in use at the job's start (prologue)
   SlotPtrs sp;                 // the slot's array addresses (prologue)
+  int32_t seOp, seNPop, seNPush, seSerial, seDepth;  // resident split schedule: the call's header
 };
 
 __device__ __forceinline__ SlotPtrs slot_ptrs(const SlotDesc* s) {
@@ -351,9 +352,12 @@ __device__ void stage_rows(const DevJob& J, Shared& sh, int k0, const CT_G uint6
                            const CT_G WordDesc* wordsArr = nullptr);
 
 // ---------------------------------------------------------------------------
-// prologue of Alg. 1 for one job (every update item recomputes it in LDS)
+// prologue of Alg. 1 for one job (every update item recomputes it in LDS).
+// Its barriers order LDS only: what it stores to memory (pushed levels) is
+// read by later calls.  stageGidx: the job's granule list into sh.gidx as
+// well (a job run by one workgroup), loaded with the domain words.
 // ---------------------------------------------------------------------------
-__device__ void prologue(const KArgs& a, const DevJob& J, Shared& sh, bool pushHere) {
+__device__ void prologue(const KArgs& a, const DevJob& J, Shared& sh, bool pushHere, bool stageGidx) {
   const TabDesc* T = J.tab;
   SlotDesc* s = J.slot;
   const bool fromRoot = J.flags & JF_FROM_ROOT;
@@ -362,8 +366,10 @@ __device__ void prologue(const KArgs& a, const DevJob& J, Shared& sh, bool pushH
   const int n = T->n, D = T->D;
   // read before the barriers (a load after one waits its round trip)
   const int policy = T->policy;
+  const int nGran = T->nGran;
   const CT_G WordDesc* words = T->words;
   const CT_G uint64_t* last = fromRoot ? T->dom0 : s->lastDom;
+  const CT_G int32_t* idxRoot = fromRoot ? T->idx0 : nullptr;
   if (threadIdx.x == 0) {
     sh.bad_stray = 0;
     sh.bad_sub = 0;
@@ -403,7 +409,13 @@ __device__ void prologue(const KArgs& a, const DevJob& J, Shared& sh, bool pushH
     sh.size[i] = 0;
     sh.dcnt[i] = 0;
   }
-  __syncthreads();
+  lds_barrier();
+  // the granule list's first BLOCK entries: a load from a clamped address,
+  // in flight with the domain words below
+  const bool scratchIdx = J.flags & JF_SCRATCH;
+  const CT_G int32_t* gsrc = fromRoot ? idxRoot : sh.sp.idx[sh.cur];
+  int g0 = 0;
+  if (stageGidx && !scratchIdx) g0 = gsrc[min((int)threadIdx.x, nGran - 1)];
   for (int q = threadIdx.x; q < D; q += BLOCK) {
     const uint64_t din = job_din(a, J, q);
     const WordDesc wd = words[q];
@@ -423,7 +435,11 @@ __device__ void prologue(const KArgs& a, const DevJob& J, Shared& sh, bool pushH
     atomicAdd(&sh.size[i], __popcll(din));
     atomicAdd(&sh.dcnt[i], __popcll(dl));
   }
-  __syncthreads();
+  if (stageGidx) {
+    if ((int)threadIdx.x < nGran) sh.gidx[threadIdx.x] = (uint16_t)(scratchIdx ? (int)threadIdx.x : g0);
+    for (int p = threadIdx.x + BLOCK; p < nGran; p += BLOCK) sh.gidx[p] = (uint16_t)(scratchIdx ? p : gsrc[p]);
+  }
+  lds_barrier();
   if (threadIdx.x < WAVE) {
     // wave 0: the segments of s_val in variable order (prefix sums over the
     // variables, 64 at a time)
@@ -465,10 +481,10 @@ __device__ void prologue(const KArgs& a, const DevJob& J, Shared& sh, bool pushH
       sh.noop = (nseg == 0) && !fromRoot;
     }
   }
-  __syncthreads();
+  lds_barrier();
   if (sh.status != ST_OK || sh.noop) return;
   stage_rows(J, sh, 0, last, words);
-  __syncthreads();
+  lds_barrier();
 }
 
 // Entries [k0, k0 + ROWS_CHUNK) of the job's row list into sh.rows: the
@@ -512,7 +528,7 @@ __device__ void stage_rows(const DevJob& J, Shared& sh, int k0, const CT_G uint6
 // Granule flags go to LDS (whole job in one workgroup) or to global memory.
 // ---------------------------------------------------------------------------
 template <int NG>
-__device__ void update_granules(const KArgs& a, const DevJob& J, Shared& sh, int p0, bool lds,
+__device__ __forceinline__ void update_granules(const KArgs& a, const DevJob& J, Shared& sh, int p0, bool lds,
                                 int* trailCounter, const SlotPtrs* sp = nullptr) {
   const TabDesc* T = J.tab;
   SlotDesc* s = J.slot;
@@ -782,14 +798,15 @@ struct FilterPre {
   int size, rl, rw0;
 };
 
-__device__ __forceinline__ FilterPre filter_pre(const KArgs& a, const DevJob& J, int q) {
+// (din: the input word q, size: the size of its variable's input domain)
+__device__ __forceinline__ FilterPre filter_pre_of(const DevJob& J, int q, const VarDesc& v, uint64_t din,
+                                                   int size) {
   const TabDesc* T = J.tab;
   const int lane = lane_id();
   FilterPre f;
-  f.v = T->words[q].v;
-  f.din = job_din(a, J, q);
-  f.size = 0;
-  for (int k = f.v.domOff; k < f.v.domOff + f.v.domWords; ++k) f.size += __popcll(job_din(a, J, k));
+  f.v = v;
+  f.din = din;
+  f.size = size;
   const int rowBase = f.v.rowStart + (q - f.v.domOff) * 64;
   // these loads run before the job's input is validated: a lane past the
   // variable's last value (a stray bit) takes the word's first row, and the
@@ -802,6 +819,13 @@ __device__ __forceinline__ FilterPre filter_pre(const KArgs& a, const DevJob& J,
   f.rw0 = min(max(J.slot->res[f.rl], 0), (int)T->stride - 1);
   f.sres = T->S[(int64_t)f.rl * T->stride + f.rw0];
   return f;
+}
+
+__device__ __forceinline__ FilterPre filter_pre(const KArgs& a, const DevJob& J, int q) {
+  const VarDesc v = J.tab->words[q].v;
+  int size = 0;
+  for (int k = v.domOff; k < v.domOff + v.domWords; ++k) size += __popcll(job_din(a, J, k));
+  return filter_pre_of(J, q, v, job_din(a, J, q), size);
 }
 
 __device__ void filter_word(const KArgs& a, const DevJob& J, int q, int noop, int lim,
@@ -1005,14 +1029,7 @@ __device__ __forceinline__ void do_update(const KArgs& a, const DevJob& J, int c
   // address)
   const bool one = J.nUpd == 1;
   if (one && threadIdx.x == 0) sh.trailCount = 0;
-  prologue(a, J, sh, one && J.nPop == 0 && J.nPush > 0);
-  if (one) {
-    const int span = sh.status == ST_OK ? J.tab->nGran : 0;
-    const CT_G int32_t* src = (J.flags & JF_FROM_ROOT) ? J.tab->idx0 : sh.sp.idx[sh.cur];
-    const bool scratch = J.flags & JF_SCRATCH;
-    for (int p = threadIdx.x; p < span; p += BLOCK) sh.gidx[p] = (uint16_t)(scratch ? p : src[p]);
-    lds_barrier();
-  }
+  prologue(a, J, sh, one && J.nPop == 0 && J.nPush > 0, one);
   // the job's tile: each wave takes tile granules of the item, NGW at a
   // time (the item covers WAVES x tile granules)
   const int reps = tile_reps(J.tile);
@@ -1259,17 +1276,12 @@ __device__ __forceinline__ void do_solo(const KArgs& a, const DevJob& J0, Shared
   SlotDesc* s = J.slot;
   const bool pushHere = J.nPop == 0 && J.nPush > 0;
   if (!pushHere) apply_pops_pushes(J, sh);
-  prologue(a, J, sh, pushHere);
+  // (the job's granule list is read once, in the prologue: each update step
+  // is then a single round of independent loads)
+  prologue(a, J, sh, pushHere, true);
   if (threadIdx.x == 0) sh.trailCount = 0;
   const int nGran = J.tab->nGran;
   int span = sh.status == ST_OK ? nGran : 0;
-  {
-    // the job's granule list, read once (each update step is then a single
-    // round of independent loads)
-    const CT_G int32_t* src = (J.flags & JF_FROM_ROOT) ? J.tab->idx0 : s->idx[s->cur];
-    const bool scratch = J.flags & JF_SCRATCH;
-    for (int p = threadIdx.x; p < span; p += BLOCK) sh.gidx[p] = (uint16_t)(scratch ? p : src[p]);
-  }
   __syncthreads();
   int st = ST_OK;
   for (int pass = 0;; ++pass) {
@@ -2069,6 +2081,270 @@ __global__ void __launch_bounds__(BLOCK) propagate_kernel(KArgs a) {
 }
 
 // ---------------------------------------------------------------------------
+// Resident split schedule of slot 0, for synchronous calls on tables whose
+// update is one item: the split schedule's update item and filter items as
+// one persistent launch that takes calls from the resident engine's mailbox
+// (pinned host memory), so a call pays no kernel launch.  Workgroup 0 polls
+// the mailbox and runs each call's pops, pushes, prologue, updateTable and
+// partition, writes the status slot and hands over to the filters with the
+// call's generation in updDone.  Filter workgroup c (filter item c) reads its
+// domain words from the mailbox itself, so its residue loads are in flight
+// during the update; after the hand-over it filters and answers with flagged
+// domain slots, then counts the call in ctl[SE_DONE] behind a release:
+// workgroup 0 waits for that count before the next call reads the slot's
+// domains.  Workgroup 0 alone stops (a stop command, or no call for
+// idleTicks) and sets ctl[SE_STOP], the word every wait of the launch
+// watches, so the filters end too.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint64_t mb_load(const uint64_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
+// Workgroup 0's wave 0: waits for call `want` in the mailbox, copies its
+// input words into ka.inl and its header into sh.se*; sh.seOp is 0 when no
+// call came within idleTicks.  It polls the op slot alone (written last by
+// the host: the lines the host is still writing are not read meanwhile),
+// two loads in flight, then reads the whole command, U chunks of 64 slots
+// per round trip.  Every lane loads (lanes past the command re-read its
+// last slot): a load under a lane condition would be waited for before the
+// test after it.
+__device__ __forceinline__ void se_take_call(const EngDesc& E, KArgs& ka, Shared& sh, uint32_t want, int D) {
+  constexpr int U = 8;
+  const int l = lane_id();
+  const uint64_t* slots = E.cmd->slot;
+  const int nS = EC_DOM + 2 * D;
+  uint32_t* in32 = (uint32_t*)ka.inl;
+  const unsigned long long t0 = wall_clock64();
+  bool seen = false;
+  {
+    uint64_t p0 = mb_load(slots + EC_OP);
+    for (;;) {
+      const uint64_t p1 = mb_load(slots + EC_OP);
+      if (__builtin_amdgcn_readfirstlane((uint32_t)p0) == want) {
+        seen = true;
+        break;
+      }
+      p0 = mb_load(slots + EC_OP);
+      if (__builtin_amdgcn_readfirstlane((uint32_t)p1) == want) {
+        seen = true;
+        break;
+      }
+      if ((long long)(wall_clock64() - t0) > E.idleTicks) break;
+    }
+  }
+  uint32_t hv = 0;
+  for (int c0 = 0; seen && c0 < nS; c0 += U * WAVE) {
+    for (;;) {  // written before the op slot: normally present at once
+      uint64_t w[U];
+      bool ok = true;
+#pragma unroll
+      for (int u = 0; u < U; ++u) w[u] = mb_load(slots + min(c0 + u * WAVE + l, nS - 1));
+#pragma unroll
+      for (int u = 0; u < U; ++u) ok = ok && (uint32_t)w[u] == want;
+      if (__all(ok)) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int i = c0 + u * WAVE + l;
+          if (i >= EC_DOM && i < nS) in32[i - EC_DOM] = (uint32_t)(w[u] >> 32);
+        }
+        if (c0 == 0) hv = (uint32_t)(w[0] >> 32);
+        break;
+      }
+      if ((long long)(wall_clock64() - t0) > E.idleTicks) {
+        seen = false;
+        break;
+      }
+    }
+  }
+  const int h0 = __shfl((int)hv, EC_OP), h1 = __shfl((int)hv, EC_NPOP), h2 = __shfl((int)hv, EC_NPUSH);
+  const int h3 = __shfl((int)hv, EC_SERIAL), h4 = __shfl((int)hv, EC_DEPTH);
+  if (l == 0) {
+    sh.seOp = seen ? h0 : 0;
+    sh.seNPop = h1;
+    sh.seNPush = h2;
+    sh.seSerial = h3;
+    sh.seDepth = h4;
+    // the filters' doorbell: the whole call is in the mailbox (a release: a
+    // relaxed store can wait in this XCD's L2 until the next release, and
+    // polls of one word at system scope from every filter workgroup queue
+    // up at the memory)
+    if (seen && h0 == ENG_OP_PROPAGATE) st_release(&E.ctl[SE_CALL], (int32_t)want);
+  }
+}
+
+// A filter workgroup's input of call `want`.  Wave 0 waits for the doorbell
+// (device memory: the host's lines are read by workgroup 0 alone) while the
+// others wait at the barrier; then each wave reads the input slots of its
+// variable's words (at most SE_MAX_VAR_WORDS, one slot per lane; the lanes
+// past them re-read the last one, so a wave reads one or two lines of host
+// memory) from the mailbox.  Returns false once the launch stops; else the
+// word q and the size of its variable's input.
+__device__ __forceinline__ bool se_filter_input(const EngDesc& E, Shared& sh, const VarDesc& v, int q,
+                                                uint32_t want, uint64_t* din, int* size) {
+  const int l = lane_id();
+  const unsigned long long t0 = wall_clock64();
+  if (wave_id() == 0) {
+    int go = 0;
+    for (;;) {
+      if ((uint32_t)ld_relaxed(&E.ctl[SE_CALL]) == want) {
+        go = 1;
+        break;
+      }
+      // the launch has stopped, or (a bound that is never reached while
+      // workgroup 0 runs) nothing has come for far longer than it waits
+      if (ld_relaxed(&E.ctl[SE_STOP]) != 0 || (long long)(wall_clock64() - t0) > 8 * E.idleTicks) break;
+      __builtin_amdgcn_s_sleep(1);
+    }
+    if (l == 0) sh.ok = go;
+  }
+  lds_barrier();
+  if (!sh.ok) return false;
+  const int nW = 2 * v.domWords;
+  const uint64_t* mine = E.cmd->slot + EC_DOM + 2 * v.domOff + min(l, nW - 1);
+  uint64_t x;
+  for (;;) {  // all there once workgroup 0 rang
+    x = mb_load(mine);
+    if (__all((uint32_t)x == want)) break;
+    if (ld_relaxed(&E.ctl[SE_STOP]) != 0 || (long long)(wall_clock64() - t0) > 8 * E.idleTicks) return false;
+  }
+  const uint32_t p = (uint32_t)(x >> 32);
+  *size = __builtin_amdgcn_readlane(wave_scan_incl(l < nW ? __popc(p) : 0), WAVE - 1);
+  const int k = 2 * (q - v.domOff);
+  const uint32_t lo = (uint32_t)__shfl((int)p, k), hi = (uint32_t)__shfl((int)p, k + 1);
+  *din = ((uint64_t)hi << 32) | lo;
+  return true;
+}
+
+// One call's update on workgroup 0: pops and pushes, prologue, updateTable
+// and partition, then the hand-over to the filters.  Returns the status.
+__device__ __forceinline__ int se_update(const KArgs& a, const DevJob& J, Shared& sh) {
+  SlotDesc* s = J.slot;
+  if (J.nPop > 0) apply_pops_pushes(J, sh);  // the pops, then the pushes
+  if (threadIdx.x == 0) sh.trailCount = 0;
+  prologue(a, J, sh, J.nPop == 0 && J.nPush > 0, true);
+  update_granules<NGW>(a, J, sh, wave_id() * NGW, true, &sh.trailCount, &sh.sp);
+  lds_barrier();
+  const int st = finalize_update(J, sh, true, sh.trailCount);
+  // finalize_update ends with a full barrier: the block's writes are ordered
+  // before this release
+  if (threadIdx.x == 0) st_release(&s->updDone, ll_gen(J.seq));
+  return st;
+}
+
+__global__ void __launch_bounds__(BLOCK) split_engine_kernel(EngDesc E) {
+  __shared__ Shared sh;
+  __shared__ KArgs ka;  // the calls' view of the launched schedule's arguments
+  const CT_G TabDesc* T = E.tab;
+  CT_G SlotDesc* s = E.slot;
+  const int D = T->D;
+  if (threadIdx.x == 0) {
+    ka.jobs = nullptr;
+    ka.nJobs = 1;
+    ka.queue = E.ctl;  // queue[3] = ctl[SE_STOP]: raise_error and block_wait use it
+    ka.hostErr = nullptr;
+    ka.clock = nullptr;
+  }
+  __syncthreads();
+  DevJob J = {};
+  J.tab = T;
+  J.slot = s;
+  J.flags = JF_PROPAGATE | JF_LL | JF_INLINE_DOM;
+  J.nUpd = 1;
+  J.nFilt = E.nFilt;
+  J.ll = E.res->slot + ER_DOM - 2;  // domain word q in slots ER_DOM + 2q, + 1
+  uint32_t last = (uint32_t)E.startSeq;
+  if (blockIdx.x == 0) {
+    const unsigned long long tLife = wall_clock64();
+    for (int served = 0;; ++served) {
+      const uint32_t want = last + 1;
+      if (threadIdx.x < WAVE) se_take_call(E, ka, sh, want, D);
+      lds_barrier();
+      if (sh.seOp != ENG_OP_PROPAGATE) break;
+      // the filters' writes of the previous call (the slot's domains) first
+      if (served > 0 && !block_wait(ka, &E.ctl[SE_DONE], served * E.nFilt, sh)) {
+        if (threadIdx.x == 0) ll_put(&E.res->slot[ER_STATUS], eng_slot((uint32_t)ST_DEVICE, want));
+        last = want;
+        break;
+      }
+      const unsigned long long tStart = wall_clock64();
+      J.nPop = sh.seNPop;
+      J.nPush = sh.seNPush;
+      J.serialBase = sh.seSerial;
+      J.depthAfter = sh.seDepth;
+      J.seq = (int32_t)want;
+      int st = se_update(ka, J, sh);
+      if (threadIdx.x == 0) {
+        if (ld_relaxed(&E.ctl[SE_STOP]) > 0) st = ST_DEVICE;
+        const unsigned long long ticks = wall_clock64() - tStart;
+        ll_put(&E.res->slot[ER_TICKS], eng_slot((uint32_t)min(ticks, 0xffffffffull), want));
+        ll_put(&E.res->slot[ER_STATUS], eng_slot((uint32_t)st, want));
+      }
+      last = want;
+      lds_barrier();
+    }
+    if (threadIdx.x == 0) {
+      atomicCAS(&E.ctl[SE_STOP], 0, -1);
+      E.res->exitSeq = (int32_t)last;
+      E.res->lifeTicks = wall_clock64() - tLife;
+      __threadfence_system();
+      __hip_atomic_store(&E.res->alive, 0, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+    }
+    return;
+  }
+  // filter workgroup: item c, one domain word per wave
+  const int q = (blockIdx.x - 1) * WAVES + wave_id();
+  const int qc = min(q, D - 1);
+  const VarDesc v = T->words[qc].v;
+  CT_G uint64_t* const sct = s->ct;
+  CT_G int32_t* const sres = s->res;
+  CT_G int32_t* const idx0 = s->idx[0];
+  CT_G int32_t* const idx1 = s->idx[1];
+  const int nG = T->nGran;
+  for (;;) {
+    const uint32_t want = last + 1;
+    uint64_t din = 0;
+    int size = 0;
+    const bool go = se_filter_input(E, sh, v, qc, want, &din, &size);
+    if (lane_id() == 0) sh.wsum[wave_id()] = go ? 1 : 0;
+    if (threadIdx.x < 3) sh.fcnt[threadIdx.x] = 0ull;
+    lds_barrier();
+    bool all = true;
+#pragma unroll
+    for (int w = 0; w < WAVES; ++w) all = all && sh.wsum[w] != 0;
+    if (!all) break;
+    J.seq = (int32_t)want;
+    const FilterPre pre = filter_pre_of(J, qc, v, din, size);
+    if (!block_wait(ka, &s->updDone, ll_gen(J.seq), sh)) break;
+    // as do_filter: the state after the update, the currTable word at each
+    // value's residue and the head of both index buffers in one round trip
+    const int jobStatus = s->status, noop = s->pad2, lim = s->limit, cur = s->cur;
+    const uint64_t cr = sct[pre.rw0];
+    int h0[FULL_SCAN_GRAN], h1[FULL_SCAN_GRAN], head[FULL_SCAN_GRAN];
+#pragma unroll
+    for (int j = 0; j < FULL_SCAN_GRAN; ++j) {
+      h0[j] = idx0[min(j, nG - 1)];
+      h1[j] = idx1[min(j, nG - 1)];
+    }
+#pragma unroll
+    for (int j = 0; j < FULL_SCAN_GRAN; ++j) head[j] = cur ? h1[j] : h0[j];
+    unsigned long long cnt[3] = {0, 0, 0};
+    if (q < D && jobStatus == ST_OK)
+      filter_word(ka, J, q, noop, lim, cur ? idx1 : idx0, cnt, pre, true, cr, sct, sres, head);
+    if (lane_id() == 0 && (cnt[0] | cnt[1] | cnt[2]))
+      for (int k = 0; k < 3; ++k) atomicAdd(&sh.fcnt[k], cnt[k]);
+    // every wave's stores of the slot's domains complete at the barrier; the
+    // release makes them visible to workgroup 0 before the call is counted
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      add_filter_stats(s, sh.fcnt);
+      __threadfence();
+      atomicAdd(&E.ctl[SE_DONE], 1);
+    }
+    last = want;
+  }
+}
+
+// ---------------------------------------------------------------------------
 // support bitset builder: one wave per 64 tuples (one word column); for each
 // column of the table every distinct row among the wave's lanes is written
 // once with the ballot of the lanes holding that value (no atomics, each
@@ -2297,6 +2573,11 @@ int propagate_max_grid() {
     perCu = 1;
   cached = cus * perCu;
   return cached;
+}
+
+hipError_t launch_split_engine(const EngDesc& E, int grid, hipStream_t stream) {
+  hipLaunchKernelGGL(split_engine_kernel, dim3(grid), dim3(BLOCK), 0, stream, E);
+  return hipGetLastError();
 }
 
 hipError_t launch_propagate(const KArgs& a, int grid, hipStream_t stream) {

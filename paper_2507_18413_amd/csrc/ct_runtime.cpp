@@ -31,6 +31,7 @@ int propagate_max_grid();
 hipError_t launch_propagate(const KArgs& a, int grid, hipStream_t stream);
 size_t engine_lds_bytes(int n, int D, int nGran, int rows);
 hipError_t launch_engine(const EngDesc& D, size_t lds, hipStream_t stream);
+hipError_t launch_split_engine(const EngDesc& E, int grid, hipStream_t stream);
 int nodes_max_rows();
 int nodes_list_cap(int rows, int n);
 int nodes_node_words(int rows, int n);
@@ -196,7 +197,6 @@ struct ct_table {
   // pinned staging of the synchronous calls
   uint64_t* pDomOut = nullptr;  // D words
   uint64_t* pLL = nullptr;      // result slots of flagged synchronous jobs (2 + 2D)
-  int32_t llSeq = 0;
   uint64_t* pDomIn = nullptr;   // D words (used when D > INLINE_WORDS)
   uint64_t* pCt = nullptr;      // W words (lazily)
   int32_t* pStatus = nullptr;
@@ -209,7 +209,10 @@ struct ct_table {
   hipStream_t engStream = nullptr;
   EngCmd* pCmd = nullptr;   // coherent pinned mailbox
   EngRes* pRes = nullptr;
-  int32_t engSeq = 0;
+  int32_t engSeq = 0;  // call numbers of the mailbox and of flagged launched calls (one sequence)
+  bool engSplit = false;    // the running engine is the resident split schedule
+  int32_t* dCtl = nullptr;  // its control words (SE_CTL_WORDS)
+  int seVarWords = -1;      // largest domain words of one variable (computed once)
   std::vector<uint64_t> engDom;        // the last call's output domains (D words)
   unsigned long long engStats[8] = {};  // the slot's counters after the last call
   bool engStatsFresh = false;  // engStats is from the last call
@@ -395,8 +398,8 @@ int run_single(ct_table* T, DevJob& J, const uint64_t* dom_in_host) {
   uint32_t sq = 0;
   if (ll) {
     J.flags |= JF_LL;
-    J.seq = ++T->llSeq;
-    if (J.seq == 0) J.seq = ++T->llSeq;  // (0 is the slots' initial flag)
+    J.seq = ++T->engSeq;
+    if (J.seq == 0) J.seq = ++T->engSeq;  // (0 is the slots' initial flag)
     sq = (uint32_t)J.seq;
     if (!(J.ll = pinned_dev64(T, T->pLL))) return fail(CT_E_DEVICE, "no device address for the result slots");
   }
@@ -554,6 +557,9 @@ int engine_stop(ct_table* T) {
   return engine_join(T);
 }
 
+bool engine_wanted(const ct_table* T);
+bool split_engine_wanted(ct_table* T);
+
 int engine_start(ct_table* T) {
   if (g_engOwner && g_engOwner != T) {
     int rc = engine_stop(g_engOwner);
@@ -581,8 +587,22 @@ int engine_start(ct_table* T) {
   D.idleTicks = engine_idle_ticks();
   D.startSeq = T->engSeq;
   T->engTimed = T->timing;
+  T->engSplit = !engine_wanted(T) && split_engine_wanted(T);
+  if (T->engSplit) {
+    if (!T->dCtl) {
+      void* p = nullptr;
+      ALLOCCHK(hipMalloc(&p, sizeof(int32_t) * SE_CTL_WORDS));
+      T->blocks.push_back(p);
+      T->dCtl = (int32_t*)p;
+    }
+    // (stream-ordered before the launch; never inside a captured graph)
+    HIPCHK(hipMemsetAsync(T->dCtl, 0, sizeof(int32_t) * SE_CTL_WORDS, T->engStream));
+    D.ctl = T->dCtl;
+    D.nFilt = propagate_items_per_job_filter(T->D);
+  }
   __atomic_store_n(&T->pRes->alive, 1, __ATOMIC_RELEASE);
-  HIPCHK(launch_engine(D, T->engLds, T->engStream));
+  if (T->engSplit) HIPCHK(launch_split_engine(D, 1 + D.nFilt, T->engStream));
+  else HIPCHK(launch_engine(D, T->engLds, T->engStream));
   T->engOn = true;
   g_engOwner = T;
   return CT_OK;
@@ -636,12 +656,23 @@ int engine_call(ct_table* T, const DevJob& J, const uint64_t* dom_in, bool wantC
   *status = (int32_t)(uint32_t)(sv >> 32);
   bool whole = true;
   if (*status == CT_OK) {
-    T->engDom.resize(T->D);
-    for (int i = 0; i < 2 * T->D && whole; i += 2) {
-      uint32_t lo = 0, hi = 0;
-      whole = engine_slot(T, ER_DOM + i, sq, &lo) && engine_slot(T, ER_DOM + i + 1, sq, &hi);
-      T->engDom[i >> 1] = ((uint64_t)hi << 32) | lo;
+    // every domain slot carries the number (in order of arrival: one clock
+    // read per poll round, not per slot)
+    const uint64_t* sl = &T->pRes->slot[ER_DOM];
+    const int nS = 2 * T->D;
+    int got = 0;
+    const auto t1 = std::chrono::steady_clock::now();
+    for (uint32_t spin = 0;; ++spin) {
+      while (got < nS && (uint32_t)__atomic_load_n(&sl[got], __ATOMIC_ACQUIRE) == sq) ++got;
+      if (got == nS) break;
+      if ((spin & 1023) == 1023 && std::chrono::steady_clock::now() - t1 > std::chrono::seconds(2)) {
+        whole = false;
+        break;
+      }
     }
+    T->engDom.resize(T->D);
+    for (int q = 0; q < T->D && whole; ++q)
+      T->engDom[q] = ((uint64_t)(uint32_t)(sl[2 * q + 1] >> 32) << 32) | (uint32_t)(sl[2 * q] >> 32);
   }
   if (wantStats) {
     for (int k = 0; k < 8 && whole; ++k) {
@@ -672,6 +703,25 @@ constexpr int ENG_AUTO_D = 64;
 bool engine_wanted(const ct_table* T) {
   return T->engEligible &&
          ((T->cfg.schedule == CT_SCHED_AUTO && T->D <= ENG_AUTO_D) || T->cfg.schedule == CT_SCHED_RESIDENT);
+}
+
+// AUTO takes the resident split schedule (split_engine_kernel) for the other
+// positive tables whose split update is one item (at most 8 granules) and
+// whose input fits the kernel-argument view (D <= INLINE_WORDS, so at most
+// 64 filter workgroups, all resident at once), with variables of at most
+// SE_MAX_VAR_WORDS domain words: plain synchronous calls on slot 0 then pay
+// no kernel launch.  Calls that want currTable or counters, and the other
+// slots, take the launched schedules.
+bool split_engine_wanted(ct_table* T) {
+  if (T->seVarWords < 0) {
+    int m = 0;
+    for (const VarDesc& v : T->vars) m = std::max(m, (int)v.domWords);
+    T->seVarWords = m;
+  }
+  return T->cfg.schedule == CT_SCHED_AUTO && T->kind == CT_KIND_POSITIVE && !engine_wanted(T) &&
+         !use_solo(T, 1) && propagate_items_per_job_update(T->nGran, 0) == 1 && T->D <= INLINE_WORDS &&
+         T->D <= ENG_MAX_D && T->seVarWords <= SE_MAX_VAR_WORDS &&
+         1 + propagate_items_per_job_filter(T->D) <= propagate_max_grid();
 }
 
 // Before any other use of a table's device state (from `same`, nullable):
@@ -1156,7 +1206,7 @@ int ct_layout(const ct_table* T, ct_layout_info* info, int32_t* dom_off) {
     info->n_slots = (int32_t)T->slots.size();
     info->granules = T->nGran;
     info->root_failed = T->rootFailed;
-    info->resident = engine_wanted(T) ? 1 : 0;
+    info->resident = engine_wanted(T) ? 1 : split_engine_wanted(const_cast<ct_table*>(T)) ? 2 : 0;
     info->kind = T->kind == CT_KIND_NEGATIVE ? CT_KIND_NEGATIVE : T->shortTab ? CT_KIND_SHORT : CT_KIND_POSITIVE;
   }
   if (dom_off) memcpy(dom_off, T->domOff.data(), sizeof(int32_t) * T->n);
@@ -1304,6 +1354,9 @@ int ct_propagate_slot(ct_table* T, int32_t slot, const uint64_t* dom_in, uint64_
   const uint64_t* domRes = T->pDomOut;
   if (slot == 0 && engine_wanted(T)) {
     if ((rc = engine_call(T, J, dom_in, ct_out != nullptr, st != nullptr, &status))) return rc;
+    domRes = T->engDom.data();
+  } else if (slot == 0 && !ct_out && !st && split_engine_wanted(T)) {
+    if ((rc = engine_call(T, J, dom_in, false, false, &status))) return rc;
     domRes = T->engDom.data();
   } else {
     if ((rc = run_single(T, J, dom_in))) return rc;

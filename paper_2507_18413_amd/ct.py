@@ -215,7 +215,11 @@ class Table:
         L.ct_layout(h, C.byref(info), _p(off))
         self.n, self.D, self.W, self.t = info.n_vars, info.D, info.W, info.n_tuples
         self.rows, self.granules, self.root_failed = info.rows, info.granules, bool(info.root_failed)
-        self.resident = bool(info.resident)
+        # synchronous calls on slot 0: the resident engine (one workgroup, its
+        # state in LDS) or the resident split schedule (persistent update and
+        # filter workgroups)
+        self.resident = info.resident == 1
+        self.resident_split = info.resident == 2
         self.kind = int(info.kind)
         self.dom_off = off
         # marshalling buffers of the synchronous calls: fixed addresses, so a

@@ -210,8 +210,10 @@ def test_wide_scope_vs_oracle(schedule):
     G, Ot = run_plain(spec, 200, W.pick_fraction_removal, 6, schedule=schedule)
     assert G.D == 227 and G.rows == 11072 and G.W == 157
     # the resident engine takes the 227-word table when asked (its wide
-    # prologue and flat filter); AUTO leaves it to the launched schedules
+    # prologue and flat filter); AUTO gives its plain calls to the resident
+    # split schedule and the calls that want currTable to the launched one
     assert G.resident == (schedule == ct.SCHED_RESIDENT)
+    assert G.resident_split == (schedule == ct.SCHED_AUTO)
 
 
 def test_wide_scope_nodes_batch_vs_oracle():
