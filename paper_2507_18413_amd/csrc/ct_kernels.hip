@@ -35,7 +35,7 @@ constexpr int NGW = 2;                 // granules per wave per update step (spl
 constexpr int NGS = 4;                 // default granules per wave per step (solo mode)
 constexpr int LANE_SCAN = 16;          // words each missing lane checks before the wave scan
 constexpr int FULL_SCAN_GRAN = 4;      // at most this many active granules: misses test every active word
-constexpr int FULL_SCAN_VALS = 4;      //   for this many values per round trip
+constexpr int FULL_SCAN_VALS = 8;      //   for this many values per round trip
 constexpr int ROW_UNROLL = 8;          // support rows loaded per batch
 constexpr int ROWS_CHUNK = 8192;       // row-list entries staged in LDS at a time
 constexpr uint32_t SPIN_LIMIT = 1u << 22;
@@ -357,19 +357,32 @@ __device__ void stage_rows(const DevJob& J, Shared& sh, int k0, const CT_G uint6
 // read by later calls.  stageGidx: the job's granule list into sh.gidx as
 // well (a job run by one workgroup), loaded with the domain words.
 // ---------------------------------------------------------------------------
-__device__ void prologue(const KArgs& a, const DevJob& J, Shared& sh, bool pushHere, bool stageGidx) {
+__device__ __forceinline__ void prologue(const KArgs& a, const DevJob& J, Shared& sh, bool pushHere, bool stageGidx) {
   const TabDesc* T = J.tab;
   SlotDesc* s = J.slot;
   const bool fromRoot = J.flags & JF_FROM_ROOT;
   const bool root = J.flags & JF_ROOT;
   const bool scratch = J.flags & JF_SCRATCH;
   const int n = T->n, D = T->D;
-  // read before the barriers (a load after one waits its round trip)
+  // read before the first barrier (a load after one waits its round trip):
+  // the table's and slot's addresses, this thread's first domain word with
+  // its record and previous word, and its entry of both index buffers (the
+  // one in use is known after the barrier); addresses are clamped, values
+  // selected afterwards
   const int policy = T->policy;
   const int nGran = T->nGran;
   const CT_G WordDesc* words = T->words;
   const CT_G uint64_t* last = fromRoot ? T->dom0 : s->lastDom;
-  const CT_G int32_t* idxRoot = fromRoot ? T->idx0 : nullptr;
+  const int q0 = min((int)threadIdx.x, D - 1);
+  const uint64_t din0 = job_din(a, J, q0);
+  const WordDesc wd0 = words[q0];
+  const uint64_t ld0 = last[q0];
+  const int p0 = min((int)threadIdx.x, nGran - 1);
+  int ga = 0, gb = 0;
+  if (stageGidx && !scratch) {
+    ga = (fromRoot ? T->idx0 : s->idx[0])[p0];
+    gb = fromRoot ? ga : s->idx[1][p0];
+  }
   if (threadIdx.x == 0) {
     sh.bad_stray = 0;
     sh.bad_sub = 0;
@@ -410,34 +423,54 @@ __device__ void prologue(const KArgs& a, const DevJob& J, Shared& sh, bool pushH
     sh.dcnt[i] = 0;
   }
   lds_barrier();
-  // the granule list's first BLOCK entries: a load from a clamped address,
-  // in flight with the domain words below
-  const bool scratchIdx = J.flags & JF_SCRATCH;
-  const CT_G int32_t* gsrc = fromRoot ? idxRoot : sh.sp.idx[sh.cur];
-  int g0 = 0;
-  if (stageGidx && !scratchIdx) g0 = gsrc[min((int)threadIdx.x, nGran - 1)];
-  for (int q = threadIdx.x; q < D; q += BLOCK) {
-    const uint64_t din = job_din(a, J, q);
-    const WordDesc wd = words[q];
-    const int i = wd.var;
-    const VarDesc v = wd.v;
-    const int used = v.dsize - 64 * (q - v.domOff);
-    if (used < 64 && (din >> used) != 0) sh.bad_stray = 1;
-    uint64_t dl = 0;
-    if (!root) {
-      const uint64_t ld = last[q];
-      if (din & ~ld) sh.bad_sub = 1;
-      dl = ld & ~din;
-      if (pushHere)
-        for (int k = 0; k < J.nPush; ++k) s->levelDom[(int64_t)(sh.depth + k) * D + q] = ld;
+  // one domain word per thread and pass: validation, Delta, |dom| per
+  // variable; the first pass takes the words loaded above, and wider tables
+  // load PRE_PASSES passes at once (one round trip, not one per pass: the
+  // input may be in host memory)
+  constexpr int PRE_PASSES = 4;
+  uint64_t dinK = 0, dlK = 0;  // this thread's word and Delta word (D <= BLOCK)
+  for (int qg = threadIdx.x; qg < D; qg += PRE_PASSES * BLOCK) {
+    uint64_t dv[PRE_PASSES], lv[PRE_PASSES];
+    WordDesc wv[PRE_PASSES];
+#pragma unroll
+    for (int g = 0; g < PRE_PASSES; ++g) {
+      const int q = min(qg + g * BLOCK, D - 1);
+      const bool first = g == 0 && qg == (int)threadIdx.x;
+      if (g > 0 && D <= BLOCK) break;  // (one pass: nothing more to load)
+      dv[g] = first ? din0 : job_din(a, J, q);
+      wv[g] = first ? wd0 : words[q];
+      lv[g] = first ? ld0 : last[q];
     }
-    if (q < MAX_D) sh.din[q] = din;
-    atomicAdd(&sh.size[i], __popcll(din));
-    atomicAdd(&sh.dcnt[i], __popcll(dl));
+#pragma unroll
+    for (int g = 0; g < PRE_PASSES; ++g) {
+      const int q = qg + g * BLOCK;
+      if (q >= D) break;
+      const uint64_t din = dv[g];
+      const int i = wv[g].var;
+      const VarDesc v = wv[g].v;
+      const int used = v.dsize - 64 * (q - v.domOff);
+      if (used < 64 && (din >> used) != 0) sh.bad_stray = 1;
+      uint64_t dl = 0;
+      if (!root) {
+        const uint64_t ld = lv[g];
+        if (din & ~ld) sh.bad_sub = 1;
+        dl = ld & ~din;
+        if (pushHere)
+          for (int k = 0; k < J.nPush; ++k) s->levelDom[(int64_t)(sh.depth + k) * D + q] = ld;
+      }
+      if (q < MAX_D) sh.din[q] = din;
+      if (q == (int)threadIdx.x) {
+        dinK = din;
+        dlK = dl;
+      }
+      atomicAdd(&sh.size[i], __popcll(din));
+      atomicAdd(&sh.dcnt[i], __popcll(dl));
+    }
   }
   if (stageGidx) {
-    if ((int)threadIdx.x < nGran) sh.gidx[threadIdx.x] = (uint16_t)(scratchIdx ? (int)threadIdx.x : g0);
-    for (int p = threadIdx.x + BLOCK; p < nGran; p += BLOCK) sh.gidx[p] = (uint16_t)(scratchIdx ? p : gsrc[p]);
+    if ((int)threadIdx.x < nGran) sh.gidx[threadIdx.x] = (uint16_t)(scratch ? (int)threadIdx.x : sh.cur ? gb : ga);
+    const CT_G int32_t* gsrc = fromRoot ? T->idx0 : sh.sp.idx[sh.cur];
+    for (int p = threadIdx.x + BLOCK; p < nGran; p += BLOCK) sh.gidx[p] = (uint16_t)(scratch ? p : gsrc[p]);
   }
   lds_barrier();
   if (threadIdx.x < WAVE) {
@@ -483,7 +516,25 @@ __device__ void prologue(const KArgs& a, const DevJob& J, Shared& sh, bool pushH
   }
   lds_barrier();
   if (sh.status != ST_OK || sh.noop) return;
-  stage_rows(J, sh, 0, last, words);
+  if (D <= BLOCK && sh.nrows <= ROWS_CHUNK) {
+    // the row list from the words in registers: segments follow variable
+    // order and a variable's words are consecutive, so a word's first entry
+    // is the exclusive prefix sum of the selected bits of the words before it
+    const int q = threadIdx.x;
+    const int sg = q < D ? sh.segOf[wd0.var] : -1;
+    const bool inc = sg >= 0 && sh.segInc[sg];
+    uint64_t bits = sg < 0 ? 0ull : inc ? dlK : dinK;
+    int tot = 0;
+    int off = block_scan_excl<true>(__popcll(bits), &tot, sh);
+    const int base = wd0.v.rowStart + (q - wd0.v.domOff) * 64;
+    while (bits) {
+      const int b = __ffsll((unsigned long long)bits) - 1;
+      bits &= bits - 1;
+      sh.rows[off++] = (uint32_t)(base + b);
+    }
+  } else {
+    stage_rows(J, sh, 0, last, words);
+  }
   lds_barrier();
 }
 
@@ -524,10 +575,11 @@ __device__ void stage_rows(const DevJob& J, Shared& sh, int k0, const CT_G uint6
 }
 
 // ---------------------------------------------------------------------------
-// updateTable (Alg. 2) for NG granules per wave starting at position p0.
-// Granule flags go to LDS (whole job in one workgroup) or to global memory.
+// updateTable (Alg. 2) for NG granules per wave starting at position p0,
+// RU support rows in flight per granule.  Granule flags go to LDS (whole job
+// in one workgroup) or to global memory.
 // ---------------------------------------------------------------------------
-template <int NG>
+template <int NG, int RU = ROW_UNROLL>
 __device__ __forceinline__ void update_granules(const KArgs& a, const DevJob& J, Shared& sh, int p0, bool lds,
                                 int* trailCounter, const SlotPtrs* sp = nullptr) {
   const TabDesc* T = J.tab;
@@ -590,17 +642,17 @@ __device__ __forceinline__ void update_granules(const KArgs& a, const DevJob& J,
     }
     if (nAct == 0) continue;
     const int c1 = min(nrows, c0 + ROWS_CHUNK);
-    for (int k0 = c0; k0 < c1; k0 += ROW_UNROLL) {
-      uint64_t v[ROW_UNROLL][NG];
+    for (int k0 = c0; k0 < c1; k0 += RU) {
+      uint64_t v[RU][NG];
 #pragma unroll
-      for (int j = 0; j < ROW_UNROLL; ++j) {
+      for (int j = 0; j < RU; ++j) {
         const int k = k0 + j;
         const int r = k < c1 ? (int)sh.rows[k - c0] : 0;  // rows past the end are never used
 #pragma unroll
         for (int u = 0; u < NG; ++u) v[j][u] = T->S[(int64_t)r * stride + (int64_t)gs[u] * GW + lane];
       }
 #pragma unroll
-      for (int j = 0; j < ROW_UNROLL; ++j) {
+      for (int j = 0; j < RU; ++j) {
         const int k = k0 + j;
         if (k >= c1) break;
         while (k >= segEnd) {
@@ -1032,10 +1084,15 @@ __device__ __forceinline__ void do_update(const KArgs& a, const DevJob& J, int c
   prologue(a, J, sh, one && J.nPop == 0 && J.nPush > 0, one);
   // the job's tile: each wave takes tile granules of the item, NGW at a
   // time (the item covers WAVES x tile granules)
-  const int reps = tile_reps(J.tile);
-  for (int r = 0; r < reps; ++r)
-    update_granules<NGW>(a, J, sh, ((chunk * reps + r) * WAVES + wave_id()) * NGW, one,
-                         one ? &sh.trailCount : &s->jobTrail, &sh.sp);
+  if (one && J.tab->nGran <= WAVES) {
+    // at most one granule per wave: twice the rows in flight instead
+    update_granules<1, 2 * ROW_UNROLL>(a, J, sh, wave_id(), true, &sh.trailCount, &sh.sp);
+  } else {
+    const int reps = tile_reps(J.tile);
+    for (int r = 0; r < reps; ++r)
+      update_granules<NGW>(a, J, sh, ((chunk * reps + r) * WAVES + wave_id()) * NGW, one,
+                           one ? &sh.trailCount : &s->jobTrail, &sh.sp);
+  }
   if (one) {
     lds_barrier();
     if (J.nPop > 0 && threadIdx.x == 0) s->prepDone = 0;  // the prep item also did the pushes
@@ -2222,7 +2279,10 @@ __device__ __forceinline__ int se_update(const KArgs& a, const DevJob& J, Shared
   if (J.nPop > 0) apply_pops_pushes(J, sh);  // the pops, then the pushes
   if (threadIdx.x == 0) sh.trailCount = 0;
   prologue(a, J, sh, J.nPop == 0 && J.nPush > 0, true);
-  update_granules<NGW>(a, J, sh, wave_id() * NGW, true, &sh.trailCount, &sh.sp);
+  if (J.tab->nGran <= WAVES)  // at most one granule per wave: twice the rows in flight
+    update_granules<1, 2 * ROW_UNROLL>(a, J, sh, wave_id(), true, &sh.trailCount, &sh.sp);
+  else
+    update_granules<NGW>(a, J, sh, wave_id() * NGW, true, &sh.trailCount, &sh.sp);
   lds_barrier();
   const int st = finalize_update(J, sh, true, sh.trailCount);
   // finalize_update ends with a full barrier: the block's writes are ordered
