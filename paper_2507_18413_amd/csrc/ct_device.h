@@ -70,6 +70,10 @@ constexpr uint32_t JF_SCRATCH = 64u;    // with JF_ROOT | JF_FROM_ROOT: root sta
 // of finished items, and the host takes the call once all its domain words
 // carry the number (or the status slot does).
 constexpr uint32_t JF_LL = 128u;
+// The slot's previous domains are read around the L2 (resident split
+// schedule: the filter workgroups on other XCDs write them, and workgroup 0
+// takes no acquire between calls, so its L2 keeps the table and the slot)
+constexpr uint32_t JF_COHLAST = 256u;
 
 struct VarDesc {
   int32_t rowStart, dsize, domOff, domWords;

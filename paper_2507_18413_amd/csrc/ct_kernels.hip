@@ -54,6 +54,11 @@ __device__ __forceinline__ void st_release(int32_t* p, int32_t v) {
 __device__ __forceinline__ int ld_relaxed(int32_t* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
+// A word of the slot's previous domains (JF_COHLAST: read at device scope,
+// around this XCD's L2)
+__device__ __forceinline__ uint64_t ld_last(const CT_G uint64_t* p, bool coh) {
+  return coh ? __hip_atomic_load(const_cast<CT_G uint64_t*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : *p;
+}
 
 // The slot's array addresses (they never change), loaded together: an item
 // that reads them early has them when its first loads from the arrays go.
@@ -260,7 +265,8 @@ __device__ void push_levels(const DevJob& J, SlotDesc* s, int depth0, int64_t tr
                             int failed, int serial0, int D) {
   for (int k = 0; k < J.nPush; ++k) {
     const int d = depth0 + k;
-    for (int q = threadIdx.x; q < D; q += BLOCK) s->levelDom[(int64_t)d * D + q] = s->lastDom[q];
+    for (int q = threadIdx.x; q < D; q += BLOCK)
+      s->levelDom[(int64_t)d * D + q] = ld_last(&s->lastDom[q], J.flags & JF_COHLAST);
     if (threadIdx.x == 0) {
       Level L;
       L.trailTop = trailTop;
@@ -376,7 +382,8 @@ __device__ __forceinline__ void prologue(const KArgs& a, const DevJob& J, Shared
   const int q0 = min((int)threadIdx.x, D - 1);
   const uint64_t din0 = job_din(a, J, q0);
   const WordDesc wd0 = words[q0];
-  const uint64_t ld0 = last[q0];
+  const bool coh = J.flags & JF_COHLAST;
+  const uint64_t ld0 = ld_last(last + q0, coh);
   const int p0 = min((int)threadIdx.x, nGran - 1);
   int ga = 0, gb = 0;
   if (stageGidx && !scratch) {
@@ -439,7 +446,7 @@ __device__ __forceinline__ void prologue(const KArgs& a, const DevJob& J, Shared
       if (g > 0 && D <= BLOCK) break;  // (one pass: nothing more to load)
       dv[g] = first ? din0 : job_din(a, J, q);
       wv[g] = first ? wd0 : words[q];
-      lv[g] = first ? ld0 : last[q];
+      lv[g] = first ? ld0 : ld_last(last + q, coh);
     }
 #pragma unroll
     for (int g = 0; g < PRE_PASSES; ++g) {
@@ -548,6 +555,7 @@ __device__ void stage_rows(const DevJob& J, Shared& sh, int k0, const CT_G uint6
                            const CT_G WordDesc* wordsArr) {
   const TabDesc* T = J.tab;
   const CT_G uint64_t* last = lastArr ? lastArr : (J.flags & JF_FROM_ROOT) ? T->dom0 : J.slot->lastDom;
+  const bool coh = J.flags & JF_COHLAST;
   const CT_G WordDesc* words = wordsArr ? wordsArr : T->words;
   const int k1 = k0 + ROWS_CHUNK;
   for (int q = threadIdx.x; q < T->D; q += BLOCK) {
@@ -559,10 +567,10 @@ __device__ void stage_rows(const DevJob& J, Shared& sh, int k0, const CT_G uint6
     int off = sg == 0 ? 0 : sh.segEnd[sg - 1];
     for (int k = v.domOff; k < q && off < k1; ++k) {
       const uint64_t dk = din_at(J, sh, k);
-      off += __popcll(inc ? (last[k] & ~dk) : dk);
+      off += __popcll(inc ? (ld_last(last + k, coh) & ~dk) : dk);
     }
     const uint64_t dq = din_at(J, sh, q);
-    uint64_t bits = inc ? (last[q] & ~dq) : dq;
+    uint64_t bits = inc ? (ld_last(last + q, coh) & ~dq) : dq;
     if (off >= k1 || off + __popcll(bits) <= k0) continue;
     const int base = v.rowStart + (q - v.domOff) * 64;
     while (bits && off < k1) {
@@ -2272,6 +2280,29 @@ __device__ __forceinline__ bool se_filter_input(const EngDesc& E, Shared& sh, co
   return true;
 }
 
+// Workgroup 0 waits until the filters have counted `want` calls (bounded:
+// false on a device error or when the wait runs out).
+__device__ __forceinline__ bool se_wait_done(const EngDesc& E, int want, Shared& sh) {
+  if (threadIdx.x == 0) {
+    int ok = 1;
+    for (uint32_t it = 0;; ++it) {
+      if (ld_relaxed(&E.ctl[SE_DONE]) == want) break;
+      if (ld_relaxed(&E.ctl[SE_STOP]) > 0) { ok = 0; break; }
+      if (it > SPIN_LIMIT) {
+        atomicExch(&E.ctl[SE_STOP], 1);
+        ok = 0;
+        break;
+      }
+      __builtin_amdgcn_s_sleep(1);
+    }
+    sh.ok = ok;
+  }
+  lds_barrier();
+  const int ok = sh.ok;
+  lds_barrier();
+  return ok != 0;
+}
+
 // One call's update on workgroup 0: pops and pushes, prologue, updateTable
 // and partition, then the hand-over to the filters.  Returns the status.
 __device__ __forceinline__ int se_update(const KArgs& a, const DevJob& J, Shared& sh) {
@@ -2308,7 +2339,7 @@ __global__ void __launch_bounds__(BLOCK) split_engine_kernel(EngDesc E) {
   DevJob J = {};
   J.tab = T;
   J.slot = s;
-  J.flags = JF_PROPAGATE | JF_LL | JF_INLINE_DOM;
+  J.flags = JF_PROPAGATE | JF_LL | JF_INLINE_DOM | JF_COHLAST;
   J.nUpd = 1;
   J.nFilt = E.nFilt;
   J.ll = E.res->slot + ER_DOM - 2;  // domain word q in slots ER_DOM + 2q, + 1
@@ -2320,8 +2351,10 @@ __global__ void __launch_bounds__(BLOCK) split_engine_kernel(EngDesc E) {
       if (threadIdx.x < WAVE) se_take_call(E, ka, sh, want, D);
       lds_barrier();
       if (sh.seOp != ENG_OP_PROPAGATE) break;
-      // the filters' writes of the previous call (the slot's domains) first
-      if (served > 0 && !block_wait(ka, &E.ctl[SE_DONE], served * E.nFilt, sh)) {
+      // the filters' writes of the previous call (the slot's domains) first;
+      // no acquire (it would invalidate this XCD's L2, which holds the table
+      // and the slot between calls): those domains are read at device scope
+      if (served > 0 && !se_wait_done(E, served * E.nFilt, sh)) {
         if (threadIdx.x == 0) ll_put(&E.res->slot[ER_STATUS], eng_slot((uint32_t)ST_DEVICE, want));
         last = want;
         break;
@@ -2351,8 +2384,13 @@ __global__ void __launch_bounds__(BLOCK) split_engine_kernel(EngDesc E) {
     }
     return;
   }
-  // filter workgroup: item c, one domain word per wave
-  const int q = (blockIdx.x - 1) * WAVES + wave_id();
+  // filter workgroup c: the workgroups of XCD 0 (every eighth, in the
+  // dispatch order's round robin) are left to workgroup 0 and end here, so
+  // the filters' acquires never invalidate its L2
+  if (blockIdx.x % 8 == 0) return;
+  const int c = (int)blockIdx.x - 1 - (int)blockIdx.x / 8;
+  if (c >= E.nFilt) return;
+  const int q = c * WAVES + wave_id();
   const int qc = min(q, D - 1);
   const VarDesc v = T->words[qc].v;
   CT_G uint64_t* const sct = s->ct;

@@ -601,7 +601,14 @@ int engine_start(ct_table* T) {
     D.nFilt = propagate_items_per_job_filter(T->D);
   }
   __atomic_store_n(&T->pRes->alive, 1, __ATOMIC_RELEASE);
-  if (T->engSplit) HIPCHK(launch_split_engine(D, 1 + D.nFilt, T->engStream));
+  if (T->engSplit) {
+    // workgroup 0, then the filter workgroups with every eighth workgroup
+    // (XCD 0 in the dispatch round robin) left empty
+    int grid = 1;
+    for (int f = 0; f < D.nFilt; ++grid)
+      if (grid % 8 != 0) ++f;
+    HIPCHK(launch_split_engine(D, grid, T->engStream));
+  }
   else HIPCHK(launch_engine(D, T->engLds, T->engStream));
   T->engOn = true;
   g_engOwner = T;
@@ -721,7 +728,7 @@ bool split_engine_wanted(ct_table* T) {
   return T->cfg.schedule == CT_SCHED_AUTO && T->kind == CT_KIND_POSITIVE && !engine_wanted(T) &&
          !use_solo(T, 1) && propagate_items_per_job_update(T->nGran, 0) == 1 && T->D <= INLINE_WORDS &&
          T->D <= ENG_MAX_D && T->seVarWords <= SE_MAX_VAR_WORDS &&
-         1 + propagate_items_per_job_filter(T->D) <= propagate_max_grid();
+         2 + (8 * propagate_items_per_job_filter(T->D)) / 7 <= propagate_max_grid();
 }
 
 // Before any other use of a table's device state (from `same`, nullable):
