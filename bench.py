@@ -374,7 +374,8 @@ def wide_leg(seed, n_calls, cpu, split=True, paper_shape=False):
     replay(table, script, lat)
     lat_us = np.array(lat) * 1e6
     from paper_2507_18413_amd import profiling
-    prof = profiling.read_summary(os.path.join(ROOT, "profiles", "propagate_wide_scope.md"))
+    prof = profiling.read_summary(os.path.join(ROOT, "profiles", "split_engine_wide_scope.md" if table.resident_split
+                                               else "propagate_wide_scope.md"))
     split_out = split_leg(table, script, 1) if split else None
     shape = ("arity 150, domains U{2..2000}, 15,000 distinct uniform tuples" if paper_shape else
              "arity 100, domains U{64..160}, 10,000 distinct uniform tuples")
@@ -394,7 +395,9 @@ def wide_leg(seed, n_calls, cpu, split=True, paper_shape=False):
                       "algorithmic_bytes_per_call": round(byts / max(props, 1), 1),
                       "algorithmic_GBps": round(byts / ((life_ms if table.resident_split else kernel_ms) / 1e3)
                                                 / 1e9, 2) if kernel_ms > 0 else None,
-                      "profiled_hbm_bytes_per_launch": prof.get("hbm_bytes_per_launch") if prof else None,
+                      "profiled_hbm_bytes_per_launch" if not table.resident_split else "profiled_hbm_bytes_per_call":
+                          (prof.get("hbm_bytes_per_call") if table.resident_split else
+                           prof.get("hbm_bytes_per_launch")) if prof else None,
                       "profiled_avg_us": prof.get("avg_us") if prof else None,
                       "counters_per_call": {k: round(v / max(props, 1), 1) for k, v in d.items()}},
            "schedule": "resident split" if table.resident_split else "resident engine" if table.resident
@@ -458,7 +461,8 @@ def tiny_leg(seed, reps, cpu):
            "calls": props, "props_per_s": round(props / el, 1),
            "latency_us": {"p50": round(float(np.percentile(lat_us, 50)), 2),
                           "p99": round(float(np.percentile(lat_us, 99)), 2)},
-           "schedule": "resident engine" if table.resident else "launched"}
+           "schedule": "resident engine" if table.resident else "resident split" if table.resident_split
+           else "launched"}
     if cpu:
         from oracle import oracle as O
         o = O.OracleTable(spec.tuples, spec.lo, spec.dsizes, fast=True)
@@ -549,7 +553,7 @@ def solver_leg(seed, cpu, n=100, dom=(2, 160), t=10_000):
            "table_seconds": round(prop.seconds, 3),
            "table_props_per_s": round(prop.props / prop.seconds, 1) if prop.seconds > 0 else None,
            "nodes_per_s": round(g.nodes / el, 1), "table_schedule": "resident engine" if table.resident
-           else "launched"}
+           else "resident split" if table.resident_split else "launched"}
     table.close()
     if cpu:
         from oracle import oracle as O

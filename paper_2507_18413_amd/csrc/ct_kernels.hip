@@ -888,10 +888,11 @@ __device__ __forceinline__ FilterPre filter_pre(const KArgs& a, const DevJob& J,
   return filter_pre_of(J, q, v, job_din(a, J, q), size);
 }
 
-__device__ void filter_word(const KArgs& a, const DevJob& J, int q, int noop, int lim,
-                            const CT_G int32_t* idx, unsigned long long* cnt, const FilterPre& f,
+__device__ __forceinline__ void filter_word(const KArgs& a, const DevJob& J, int q, int noop, int lim,
+                                            const CT_G int32_t* idx, unsigned long long* cnt, const FilterPre& f,
                             bool haveCtRes = false, uint64_t ctRes = 0ull, CT_G uint64_t* ctArr = nullptr,
-                            CT_G int32_t* resArr = nullptr, const int* idxHead = nullptr) {
+                            CT_G int32_t* resArr = nullptr, const int* idxHead = nullptr,
+                            const uint64_t* ctHead = nullptr, bool phys = false) {
   const TabDesc* T = J.tab;
   SlotDesc* slot = J.slot;
   // the slot's arrays, read once (see update_granules), or as the caller
@@ -919,14 +920,23 @@ __device__ void filter_word(const KArgs& a, const DevJob& J, int q, int noop, in
     cnt[0] += __popcll(__ballot(present));
     cnt[1] += __popcll(miss);
     uint64_t unsup = 0;
-    if (miss && lim > 0 && lim <= FULL_SCAN_GRAN) {
+    // phys: the caller loaded every granule of a table of at most
+    // FULL_SCAN_GRAN granules into ctHead (physical order; inactive ones are
+    // all zero)
+    if (miss && lim > 0 && (phys || lim <= FULL_SCAN_GRAN)) {
       // few active granules: each missing value tests every active word at
       // once (FULL_SCAN_VALS values per round trip, one word per lane and
       // granule); a value with no supported word among them has no support
       int gg[FULL_SCAN_GRAN];
       uint64_t c[FULL_SCAN_GRAN];
+      const int nG = T->nGran;
 #pragma unroll
       for (int j = 0; j < FULL_SCAN_GRAN; ++j) {
+        if (phys) {
+          gg[j] = j < nG ? j : -1;
+          c[j] = j < nG ? ctHead[j] : 0ull;
+          continue;
+        }
         // the first FULL_SCAN_GRAN entries of the index as the caller read
         // them, or from memory
         const int gv = idxHead ? idxHead[j] : idx[min(j, lim - 1)];
@@ -1190,9 +1200,15 @@ __device__ __forceinline__ void do_filter(const KArgs& a, const DevJob& J, int c
   }
 #pragma unroll
   for (int j = 0; j < FULL_SCAN_GRAN; ++j) head[j] = cur ? h1[j] : h0[j];
+  // a table of at most FULL_SCAN_GRAN granules: all of currTable, in the
+  // same round trip
+  uint64_t cth[FULL_SCAN_GRAN];
+#pragma unroll
+  for (int j = 0; j < FULL_SCAN_GRAN; ++j) cth[j] = sct[(int64_t)min(j, nG - 1) * GW + lane_id()];
   unsigned long long cnt[3] = {0, 0, 0};
   if (q < J.tab->D && jobStatus == ST_OK)
-    filter_word(a, J, q, noop, lim, cur ? idx1 : idx0, cnt, pre, true, cr, sct, sres, head);
+    filter_word(a, J, q, noop, lim, cur ? idx1 : idx0, cnt, pre, true, cr, sct, sres, head, cth,
+                nG <= FULL_SCAN_GRAN);
   // the item's counts, summed in LDS: one set of counter atomics per item
   if (lane_id() == 0 && (cnt[0] | cnt[1] | cnt[2]))
     for (int k = 0; k < 3; ++k) atomicAdd(&sh.fcnt[k], cnt[k]);
@@ -2425,9 +2441,13 @@ __global__ void __launch_bounds__(BLOCK) split_engine_kernel(EngDesc E) {
     }
 #pragma unroll
     for (int j = 0; j < FULL_SCAN_GRAN; ++j) head[j] = cur ? h1[j] : h0[j];
+    uint64_t cth[FULL_SCAN_GRAN];
+#pragma unroll
+    for (int j = 0; j < FULL_SCAN_GRAN; ++j) cth[j] = sct[(int64_t)min(j, nG - 1) * GW + lane_id()];
     unsigned long long cnt[3] = {0, 0, 0};
     if (q < D && jobStatus == ST_OK)
-      filter_word(ka, J, q, noop, lim, cur ? idx1 : idx0, cnt, pre, true, cr, sct, sres, head);
+      filter_word(ka, J, q, noop, lim, cur ? idx1 : idx0, cnt, pre, true, cr, sct, sres, head, cth,
+                  nG <= FULL_SCAN_GRAN);
     if (lane_id() == 0 && (cnt[0] | cnt[1] | cnt[2]))
       for (int k = 0; k < 3; ++k) atomicAdd(&sh.fcnt[k], cnt[k]);
     // every wave's stores of the slot's domains complete at the barrier; the

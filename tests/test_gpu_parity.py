@@ -146,7 +146,8 @@ def test_random_sequences_vs_oracle(chunk):
             same_state(G, Ot, where=f"step {step}")
 
 
-def run_plain(spec, n_calls, picker, family, check_every=1, schedule=ct.SCHED_AUTO):
+def run_plain(spec, n_calls, picker, family, check_every=1, schedule=ct.SCHED_AUTO, ct_every=2,
+              state_after_pops=True):
     G, Ot = pair(spec.tuples, spec.lo, spec.dsizes, schedule=schedule)
     lay = spec.layout()
     same_state(G, Ot, where="root")
@@ -157,10 +158,10 @@ def run_plain(spec, n_calls, picker, family, check_every=1, schedule=ct.SCHED_AU
         dom_in = picker(rng, lay, Ot.domains())
         assert G.push() == ct.OK and Ot.push() == O.OK
         depth += 1
-        # every other call without a currTable copy: synchronous launched
-        # calls then answer through flagged result slots, the others through
-        # the fenced, counted status; the two alternate on one slot
-        want_ct = call % 2 == 0
+        # every ct_every-th call (0: none) with a currTable copy: the others
+        # answer through flagged result slots (launched, or the resident
+        # schedules), these through the fenced, counted status
+        want_ct = ct_every > 0 and call % ct_every == 0
         if want_ct:
             gs, gd, gc = G.propagate(dom_in, want_ct=True)
             os_, od, oc = Ot.propagate(dom_in, want_ct=True)
@@ -175,7 +176,7 @@ def run_plain(spec, n_calls, picker, family, check_every=1, schedule=ct.SCHED_AU
         for _ in range(bt.pops_after(os_ == O.FAIL, depth)):
             assert G.pop() == ct.OK and Ot.pop() == O.OK
             depth -= 1
-            if call % check_every == 0:
+            if state_after_pops and call % check_every == 0:
                 same_state(G, Ot, where=f"after pop at call {call}")
     return G, Ot
 
@@ -214,6 +215,19 @@ def test_wide_scope_vs_oracle(schedule):
     # split schedule and the calls that want currTable to the launched one
     assert G.resident == (schedule == ct.SCHED_RESIDENT)
     assert G.resident_split == (schedule == ct.SCHED_AUTO)
+
+
+def test_wide_scope_resident_split_vs_oracle():
+    """The resident split schedule on its own: 300 plain calls in a row on the
+    wide-scope table (no call stops the persistent launch), backtracking
+    included; every call's status and domains against the oracle, and the
+    slot's state at the end."""
+    say("wide scope: resident split schedule, 300 plain calls")
+    spec = W.wide_table()
+    # (no state reads inside the run: a read ends the persistent launch)
+    G, Ot = run_plain(spec, 300, W.pick_fraction_removal, 7, ct_every=0, state_after_pops=False)
+    assert G.resident_split and not G.resident
+    same_state(G, Ot, where="end")
 
 
 def test_wide_scope_nodes_batch_vs_oracle():
