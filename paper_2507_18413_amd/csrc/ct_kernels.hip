@@ -2166,14 +2166,17 @@ __global__ void __launch_bounds__(BLOCK) propagate_kernel(KArgs a) {
 // update is one item: the split schedule's update item and filter items as
 // one persistent launch that takes calls from the resident engine's mailbox
 // (pinned host memory), so a call pays no kernel launch.  Workgroup 0 polls
-// the mailbox and runs each call's pops, pushes, prologue, updateTable and
-// partition, writes the status slot and hands over to the filters with the
-// call's generation in updDone.  Filter workgroup c (filter item c) reads its
-// domain words from the mailbox itself, so its residue loads are in flight
-// during the update; after the hand-over it filters and answers with flagged
-// domain slots, then counts the call in ctl[SE_DONE] behind a release:
-// workgroup 0 waits for that count before the next call reads the slot's
-// domains.  Workgroup 0 alone stops (a stop command, or no call for
+// the mailbox, rings the doorbell ctl[SE_CALL] once a whole call is there,
+// runs the call's pops, pushes, prologue, updateTable and partition, writes
+// the status slot and hands over to the filters with the call's generation in
+// updDone.  Filter workgroup c (filter item c) waits for the doorbell, reads
+// its domain words from the mailbox itself, so its residue loads are in
+// flight during the update; after the hand-over it filters and answers with
+// flagged domain slots, then counts the call in ctl[SE_DONE] behind a
+// release: workgroup 0 waits for that count before the next call reads the
+// slot's domains.  The other workgroups of XCD 0 stay empty and workgroup 0
+// takes no acquire between calls (JF_COHLAST), so its L2 keeps the table
+// and the slot.  Workgroup 0 alone stops (a stop command, or no call for
 // idleTicks) and sets ctl[SE_STOP], the word every wait of the launch
 // watches, so the filters end too.
 // ---------------------------------------------------------------------------
